@@ -1,0 +1,171 @@
+/* hrc.h - C ABI of the MI355X (gfx950) Holographic Radiance Cascades library.
+ *
+ * The library computes, for a square grid of S = 2^N pixels per side, the
+ * per-pixel fluence F of Eq. 1 as approximated by Holographic Radiance Cascades
+ * (Section 4, Algorithm 1): per-pixel emission and attenuation in, per-pixel
+ * fluence out (the problem statement of Section 3 and the image-in/grid-out
+ * interface of Section 5).  Each quadrant solve builds the interval pyramid
+ * T_0..T_N (traced levels 0..2, then the merge up of Section 4.1, Eq. 18-20),
+ * merges the probe cascades down (Eq. 13-17, R_N = 0), and gathers R_0 at the
+ * probe one pixel ahead (Algorithm 1, Lighting); the four quadrants are summed.
+ * No blur is applied (Eq. 21 is a separate post-process).
+ *
+ * Conventions shared by every entry point
+ *   - Grids are float32 [S][S] row-major: element (r, c) at r*S + c.
+ *   - eps is the emission per unit length (the integrand of Eq. 3), sigma the
+ *     attenuation coefficient sigma_t of Eq. 2.  Preconditions: finite and
+ *     >= 0 (checked only with HRC_FLAG_VALIDATE).
+ *   - Every tensor pointer is a DEVICE pointer on the context's device, owned
+ *     by the caller and 16-byte aligned; outputs are overwritten, never
+ *     accumulated.  Workspace is caller-owned device memory of at least the
+ *     size reported by hrc_workspace_bytes; its contents on entry are ignored.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work is enqueued on it; calls return without synchronising.
+ *   - The forward, backward and batch-launch calls allocate nothing and free
+ *     nothing.  hrc_create and hrc_batch_plan allocate.
+ *   - Argument checks run on the host before any device call, in this order:
+ *     size (HRC_ERR_SHAPE), pointers (HRC_ERR_INVALID_ARG), workspace
+ *     (HRC_ERR_WORKSPACE), context (HRC_ERR_INVALID_ARG).  A failed check
+ *     enqueues nothing.  Launch failures return HRC_ERR_HIP; faults inside
+ *     kernels surface at the caller's next synchronisation.
+ *   - Results are deterministic: every output element has exactly one writer
+ *     and no floating-point atomics are used.
+ *   - A context may be used by one host thread at a time.
+ */
+#ifndef HRC_H
+#define HRC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HRC_OK = 0,
+    HRC_ERR_INVALID_ARG = -1,  /* NULL or misaligned pointer, NULL context, bad count */
+    HRC_ERR_SHAPE = -2,        /* log2_size outside [HRC_MIN_LOG2, HRC_MAX_LOG2] */
+    HRC_ERR_WORKSPACE = -3,    /* workspace smaller than hrc_workspace_bytes */
+    HRC_ERR_HIP = -4,          /* a HIP runtime call or kernel launch failed */
+    HRC_ERR_UNSUPPORTED = -5,  /* unknown flag bits */
+    HRC_ERR_INPUT = -6         /* HRC_FLAG_VALIDATE found a negative or non-finite input */
+} hrc_status;
+
+#define HRC_MIN_LOG2 3
+#define HRC_MAX_LOG2 12
+
+/* Flags.  HRC_FLAG_VALIDATE scans eps and sigma on the device first and
+ * synchronises the stream to report HRC_ERR_INPUT (debug use only). */
+#define HRC_FLAG_VALIDATE 0x1u
+
+typedef struct hrc_context hrc_context;
+
+/* Create a context on HIP device `device`: uploads the cone-angle table of
+ * Eq. 13 (A_m(jj) for m <= HRC_MAX_LOG2) to that device.  *out receives the
+ * context, or NULL on failure. */
+hrc_status hrc_create(int device, hrc_context **out);
+
+/* Destroy a context (NULL-safe).  The caller must have finished all work
+ * enqueued with it. */
+void hrc_destroy(hrc_context *ctx);
+
+/* Static description of a status code (never NULL). */
+const char *hrc_status_string(hrc_status s);
+
+/* Workspace sizes in bytes for a grid of side 2^log2_size: forward needs the
+ * interval pyramid of the four quadrants (Section 4.3.2: (N+3-2^-N) S^2
+ * entries each) plus two cascade levels; backward additionally keeps every
+ * cascade level, their adjoints and the adjoint pyramid.  Either output
+ * pointer may be NULL.  Pure host function. */
+hrc_status hrc_workspace_bytes(int log2_size, unsigned flags,
+                               size_t *forward_bytes, size_t *backward_bytes);
+
+/* Fluence of one scene (Algorithm 1, procedure Lighting, without blur).
+ *   emission, sigma_t : [S][S] inputs
+ *   fluence           : [S][S] output                                       */
+hrc_status hrc_forward(hrc_context *ctx, int log2_size,
+                       const float *emission, const float *sigma_t, float *fluence,
+                       void *workspace, size_t workspace_bytes,
+                       void *stream, unsigned flags);
+
+/* Vector-Jacobian product of hrc_forward: given grad_fluence = dLoss/dF,
+ * writes dLoss/d(emission) and dLoss/d(sigma_t).  The forward intervals and
+ * cascades are recomputed inside the call (nothing is kept between calls);
+ * the reverse runs the merge down from level 0 up, the merge up from level N
+ * down, then the traced levels (the transposes of Eq. 7-8, 14-20 and of the
+ * per-cell integral of Eq. 2-4).                                            */
+hrc_status hrc_backward(hrc_context *ctx, int log2_size,
+                        const float *emission, const float *sigma_t,
+                        const float *grad_fluence,
+                        float *grad_emission, float *grad_sigma_t,
+                        void *workspace, size_t workspace_bytes,
+                        void *stream, unsigned flags);
+
+/* ---- Per-pass timing (profiling) ----------------------------------------- */
+
+/* Pass kinds reported by hrc_profile_solve. */
+typedef enum {
+    HRC_PASS_TRANSPOSE = 0,   /* transposed copies of the inputs for two quadrants */
+    HRC_PASS_SEED = 1,        /* traced levels T_0..T_2 (Section 4.2) */
+    HRC_PASS_MERGE_UP = 2,    /* T_n from T_(n-1) (Eq. 18-20) */
+    HRC_PASS_MERGE_DOWN = 3,  /* R_n from R_(n+1), T_n, T_(n+1) (Eq. 14-17) */
+    HRC_PASS_FRAME_SUM = 4,   /* quadrant gather into F, or gradient sum onto the image */
+    HRC_PASS_GATHER_ADJ = 5,
+    HRC_PASS_MERGE_DOWN_ADJ = 6,
+    HRC_PASS_INTERVAL_ADJ = 7,
+    HRC_PASS_SEED_ADJ = 8
+} hrc_pass_kind;
+
+/* Runs one hrc_forward (grad_fluence == NULL) or one hrc_backward (then
+ * fluence is ignored) exactly as those calls do, with a HIP event recorded on
+ * `stream` around every pass, then synchronises `stream` and reports, per pass
+ * in execution order, its kind, level n (-1 when not per level) and duration
+ * in milliseconds.  At most `max_passes` are reported; *count receives the
+ * number of passes.  Argument checks as for hrc_forward / hrc_backward, plus
+ * HRC_ERR_INVALID_ARG for NULL report arrays. */
+hrc_status hrc_profile_solve(hrc_context *ctx, int log2_size,
+                             const float *emission, const float *sigma_t, float *fluence,
+                             const float *grad_fluence, float *grad_emission,
+                             float *grad_sigma_t, void *workspace, size_t workspace_bytes,
+                             void *stream, float *pass_ms, int *pass_kind, int *pass_level,
+                             int max_passes, int *count);
+
+/* ---- Batched forward + backward over scenes of different sizes ---------- */
+
+/* One scene of a batch.  grad_fluence, grad_emission and grad_sigma_t may all
+ * be NULL (forward only for that scene) or must all be set. */
+typedef struct {
+    int log2_size;
+    const float *emission;
+    const float *sigma_t;
+    float *fluence;
+    const float *grad_fluence;
+    float *grad_emission;
+    float *grad_sigma_t;
+} hrc_scene;
+
+typedef struct hrc_batch hrc_batch;
+
+/* Plan a batch: copies the scene table, sizes and allocates the batch's own
+ * workspace (device memory owned by the batch), picks per-size tile shapes
+ * with the autotuner (timing candidate shapes on `stream`), and captures one
+ * persistent-kernel launch in a HIP graph.  The scene pointers are baked in:
+ * later launches read and write the same buffers.  Synchronises `stream`. */
+hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count,
+                          unsigned flags, void *stream, hrc_batch **out);
+
+/* Run a planned batch on `stream`: one graph launch; results are bitwise equal
+ * to hrc_forward / hrc_backward on each scene. */
+hrc_status hrc_batch_launch(hrc_batch *batch, void *stream);
+
+/* Bytes of device memory the batch owns (workspace and scheduler state). */
+size_t hrc_batch_workspace_bytes(const hrc_batch *batch);
+
+/* Destroy a batch (NULL-safe); frees its device memory and graph. */
+void hrc_batch_destroy(hrc_batch *batch);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HRC_H */

@@ -1,0 +1,97 @@
+"""ctypes declarations of the C ABI in ``include/hrc.h`` (argument marshalling only).
+
+Loading never falls back to anything: if ``libhrc.so`` is missing the import of
+the library raises, and every computation runs in its HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhrc.so")
+
+HRC_OK = 0
+HRC_ERR_INVALID_ARG = -1
+HRC_ERR_SHAPE = -2
+HRC_ERR_WORKSPACE = -3
+HRC_ERR_HIP = -4
+HRC_ERR_UNSUPPORTED = -5
+HRC_ERR_INPUT = -6
+HRC_MIN_LOG2 = 3
+HRC_MAX_LOG2 = 12
+HRC_FLAG_VALIDATE = 0x1
+PASS_NAMES = ["transpose", "seed", "merge_up", "merge_down", "frame_sum", "gather_adj",
+              "merge_down_adj", "interval_adj", "seed_adj"]
+# Kernel symbol of each pass kind (what a profiler shows).
+PASS_KERNELS = ["hrc_transpose", "hrc_seed", "hrc_merge_up", "hrc_merge_down", "hrc_frame_sum",
+                "hrc_gather_adj", "hrc_merge_down_adj", "hrc_interval_adj", "hrc_seed_adj"]
+
+# Every function the header declares, with (restype, argtypes).
+_vp = ctypes.c_void_p
+_sz = ctypes.c_size_t
+
+
+class hrc_scene(ctypes.Structure):
+    _fields_ = [
+        ("log2_size", ctypes.c_int),
+        ("emission", _vp),
+        ("sigma_t", _vp),
+        ("fluence", _vp),
+        ("grad_fluence", _vp),
+        ("grad_emission", _vp),
+        ("grad_sigma_t", _vp),
+    ]
+
+
+SIGNATURES = {
+    "hrc_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp)]),
+    "hrc_destroy": (None, [_vp]),
+    "hrc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "hrc_workspace_bytes": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint,
+                                           ctypes.POINTER(_sz), ctypes.POINTER(_sz)]),
+    "hrc_forward": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _sz, _vp,
+                                   ctypes.c_uint]),
+    "hrc_backward": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
+                                    _vp, ctypes.c_uint]),
+    "hrc_profile_solve": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                         _sz, _vp, ctypes.POINTER(ctypes.c_float),
+                                         ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_int)]),
+    "hrc_batch_plan": (ctypes.c_int, [_vp, ctypes.POINTER(hrc_scene), ctypes.c_int,
+                                      ctypes.c_uint, _vp, ctypes.POINTER(_vp)]),
+    "hrc_batch_launch": (ctypes.c_int, [_vp, _vp]),
+    "hrc_batch_workspace_bytes": (_sz, [_vp]),
+    "hrc_batch_destroy": (None, [_vp]),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load ``libhrc.so`` (built in-tree by ``paper_2505_02041_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2505_02041_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class HRCError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = load().hrc_status_string(status).decode()
+        super().__init__(f"{where}: {msg}")
+        self.status = status
+
+
+def check(status: int, where: str) -> None:
+    if status != HRC_OK:
+        raise HRCError(status, where)

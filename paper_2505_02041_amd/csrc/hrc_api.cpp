@@ -1,0 +1,343 @@
+// Host side of the C ABI: argument checks, workspace layout, context, and the
+// per-level launch sequence of Algorithm 1 (forward) and of its reverse.
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <vector>
+
+#include "../../include/hrc.h"
+#include "hrc_internal.h"
+
+namespace hrc {
+
+Layout make_layout(int N, bool backward) {
+    Layout L;
+    L.N = N;
+    L.S = size_t(1) << N;
+    const size_t SS = L.S * L.S;
+    size_t off = 256;  // first 256 bytes: scratch flag for HRC_FLAG_VALIDATE
+    L.fieldsT = off;
+    off += align256(2 * SS * sizeof(float));
+    for (int n = 0; n <= N; ++n) {
+        L.t_level[n] = off;
+        off += align256(kQuadrants * t_level_entries(N, n) * sizeof(float2));
+    }
+    L.r_count = backward ? N : 2;
+    for (int i = 0; i < L.r_count; ++i) {
+        L.r_level[i] = off;
+        off += align256(kQuadrants * SS * sizeof(float));
+    }
+    if (backward) {
+        for (int n = 0; n <= N; ++n) {
+            L.dt_level[n] = off;
+            off += align256(kQuadrants * t_level_entries(N, n) * sizeof(float2));
+        }
+        for (int i = 0; i < N; ++i) {
+            L.dr_level[i] = off;
+            off += align256(kQuadrants * SS * sizeof(float));
+        }
+        L.dfield = off;
+        off += align256(2 * kQuadrants * SS * sizeof(float));
+    }
+    L.total = off;
+    return L;
+}
+
+// A_m(jj) of Eq. 13 in double precision, rounded once to float.
+static void cone_table(float *out) {
+    for (int m = 0; m <= kMaxLog2; ++m) {
+        const double a = double(1 << m);
+        for (int jj = 0; jj < (1 << m); ++jj) {
+            double hi = atan2(2.0 * (jj + 1) - a, a);
+            double lo = atan2(2.0 * jj - a, a);
+            out[(1 << m) - 1 + jj] = float(hi - lo);
+        }
+    }
+}
+
+static bool aligned16(const void *p) { return p && (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+static hrc_status check_shape(int log2_size) {
+    return (log2_size < HRC_MIN_LOG2 || log2_size > HRC_MAX_LOG2) ? HRC_ERR_SHAPE : HRC_OK;
+}
+
+static int pick_u(const int *U, int kind) { return U ? (U[kind] > 0 ? U[kind] : 1) : 1; }
+
+// The passes of one solve in execution order (Algorithm 1 for the four
+// quadrants at once, then, with gradients, its reverse).  R levels either all
+// kept (R(n) = R_n, needed by the reverse) or alternating in two buffers.
+int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, const int *U,
+                       Phase *out, int max_out) {
+    const int N = w.L.N;
+    int np = 0;
+    auto add = [&](const Phase &p) {
+        if (np < max_out) out[np] = p;
+        ++np;
+    };
+    Phase p;
+    p.kind = PH_TRANSPOSE;
+    p.a.tr = TransposeArgs{b.eps, b.sig, w.epsT(), w.sigT(), N};
+    add(p);
+    p = Phase();
+    p.kind = PH_SEED;
+    p.U = pick_u(U, PH_SEED);
+    p.a.seed = SeedArgs{b.eps, b.sig, w.epsT(), w.sigT(), w.T(0), w.T(1), w.T(2),
+                        t_level_entries(N, 0), t_level_entries(N, 1), t_level_entries(N, 2), N};
+    add(p);
+    for (int n = kTracedLevels; n <= N; ++n) {
+        p = Phase();
+        p.kind = PH_UP;
+        p.U = pick_u(U, PH_UP);
+        p.a.up = UpArgs{w.T(n - 1), w.T(n), t_level_entries(N, n - 1), t_level_entries(N, n), N, n};
+        add(p);
+    }
+    int cur = -1;
+    for (int n = N - 1; n >= 0; --n) {
+        const int o = keep_all_r ? n : ((cur == 0) ? 1 : 0);
+        p = Phase();
+        p.kind = PH_DOWN;
+        p.U = pick_u(U, PH_DOWN);
+        p.a.down = DownArgs{(n + 1 < N) ? w.R(cur) : nullptr, w.T(n), w.T(n + 1), w.R(o),
+                            t_level_entries(N, n), t_level_entries(N, n + 1), N, n};
+        add(p);
+        cur = o;
+    }
+    if (b.F) {
+        p = Phase();
+        p.kind = PH_FRAME_SUM;
+        p.a.fs = FrameSumArgs{w.R(cur), nullptr, b.F, nullptr, N, 1};
+        add(p);
+    }
+    if (b.dF) {
+        p = Phase();
+        p.kind = PH_GATHER_ADJ;
+        p.a.ga = GatherAdjArgs{b.dF, w.dR(0), N};
+        add(p);
+        for (int n = 0; n + 1 < N; ++n) {
+            p = Phase();
+            p.kind = PH_DOWN_ADJ;
+            p.U = pick_u(U, PH_DOWN_ADJ);
+            p.a.da = DownAdjArgs{w.dR(n), w.T(n), w.T(n + 1), w.dR(n + 1), t_level_entries(N, n),
+                                 t_level_entries(N, n + 1), N, n};
+            add(p);
+        }
+        for (int n = N; n >= 0; --n) {
+            p = Phase();
+            p.kind = PH_DT;
+            p.U = pick_u(U, PH_DT);
+            DTArgs d{};
+            d.Tn = w.T(n);
+            d.has_up = (n + 1 <= N && n + 1 >= kTracedLevels) ? 1 : 0;
+            d.dTn1 = d.has_up ? w.dT(n + 1) : nullptr;
+            d.dRn = n < N ? w.dR(n) : nullptr;
+            d.dRm = n >= 1 ? w.dR(n - 1) : nullptr;
+            d.Rn1 = (n + 1 < N) ? w.R(n + 1) : nullptr;
+            d.Rn = n < N ? w.R(n) : nullptr;
+            d.dT = w.dT(n);
+            d.en = t_level_entries(N, n);
+            d.en1 = n + 1 <= N ? t_level_entries(N, n + 1) : 0;
+            d.N = N;
+            d.n = n;
+            p.a.dt = d;
+            add(p);
+        }
+        p = Phase();
+        p.kind = PH_SEED_ADJ;
+        p.U = pick_u(U, PH_SEED_ADJ);
+        p.a.sa = SeedAdjArgs{b.eps, b.sig, w.epsT(), w.sigT(), w.dT(0), w.dT(1), w.dT(2),
+                             t_level_entries(N, 0), t_level_entries(N, 1), t_level_entries(N, 2),
+                             w.dE(), w.dS(), N};
+        add(p);
+        p = Phase();
+        p.kind = PH_FRAME_SUM;
+        p.a.fs = FrameSumArgs{w.dE(), w.dS(), b.dE, b.dS, N, 0};
+        add(p);
+    }
+    return np;
+}
+
+static hrc_status run_phases(const Phase *ph, int np, hipStream_t s) {
+    for (int i = 0; i < np; ++i)
+        if (launch_phase(ph[i], s) != hipSuccess) return HRC_ERR_HIP;
+    return HRC_OK;
+}
+
+static hrc_status validate_inputs(const Ws &w, const float *eps, const float *sig,
+                                  hipStream_t s) {
+    int *flag = reinterpret_cast<int *>(w.base);
+    int host = 0;
+    if (hipMemsetAsync(flag, 0, sizeof(int), s) != hipSuccess) return HRC_ERR_HIP;
+    if (launch_validate(eps, sig, w.L.S * w.L.S, flag, s) != hipSuccess) return HRC_ERR_HIP;
+    if (hipMemcpyAsync(&host, flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return HRC_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return HRC_ERR_HIP;
+    return host ? HRC_ERR_INPUT : HRC_OK;
+}
+
+}  // namespace hrc
+
+using namespace hrc;
+
+extern "C" {
+
+const char *hrc_status_string(hrc_status s) {
+    switch (s) {
+        case HRC_OK: return "HRC_OK";
+        case HRC_ERR_INVALID_ARG: return "HRC_ERR_INVALID_ARG: NULL or misaligned pointer, NULL context or bad count";
+        case HRC_ERR_SHAPE: return "HRC_ERR_SHAPE: log2_size outside [3, 12]";
+        case HRC_ERR_WORKSPACE: return "HRC_ERR_WORKSPACE: workspace smaller than hrc_workspace_bytes";
+        case HRC_ERR_HIP: return "HRC_ERR_HIP: a HIP runtime call or kernel launch failed";
+        case HRC_ERR_UNSUPPORTED: return "HRC_ERR_UNSUPPORTED: unknown flag bits";
+        case HRC_ERR_INPUT: return "HRC_ERR_INPUT: negative or non-finite emission or attenuation";
+    }
+    return "HRC: unknown status";
+}
+
+hrc_status hrc_workspace_bytes(int log2_size, unsigned flags, size_t *forward_bytes,
+                               size_t *backward_bytes) {
+    hrc_status st = check_shape(log2_size);
+    if (st != HRC_OK) return st;
+    if (flags & ~HRC_FLAG_VALIDATE) return HRC_ERR_UNSUPPORTED;
+    if (forward_bytes) *forward_bytes = make_layout(log2_size, false).total;
+    if (backward_bytes) *backward_bytes = make_layout(log2_size, true).total;
+    return HRC_OK;
+}
+
+hrc_status hrc_create(int device, hrc_context **out) {
+    if (!out) return HRC_ERR_INVALID_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return HRC_ERR_HIP;
+    DeviceGuard g(device);
+    if (!g.ok) return HRC_ERR_HIP;
+    std::vector<float> table(kConeTable);
+    cone_table(table.data());
+    if (upload_cone_table(table.data()) != hipSuccess) return HRC_ERR_HIP;
+    hrc_context *ctx = static_cast<hrc_context *>(calloc(1, sizeof(hrc_context)));
+    if (!ctx) return HRC_ERR_HIP;
+    ctx->device = device;
+    hipDeviceProp_t prop;
+    ctx->num_cus = (hipGetDeviceProperties(&prop, device) == hipSuccess) ? prop.multiProcessorCount : 256;
+    *out = ctx;
+    return HRC_OK;
+}
+
+void hrc_destroy(hrc_context *ctx) { free(ctx); }
+
+hrc_status hrc_forward(hrc_context *ctx, int log2_size, const float *emission,
+                       const float *sigma_t, float *fluence, void *workspace,
+                       size_t workspace_bytes, void *stream, unsigned flags) {
+    hrc_status st = check_shape(log2_size);
+    if (st != HRC_OK) return st;
+    if (!aligned16(emission) || !aligned16(sigma_t) || !aligned16(fluence) ||
+        !aligned16(workspace))
+        return HRC_ERR_INVALID_ARG;
+    if (flags & ~HRC_FLAG_VALIDATE) return HRC_ERR_UNSUPPORTED;
+    Layout L = make_layout(log2_size, false);
+    if (workspace_bytes < L.total) return HRC_ERR_WORKSPACE;
+    if (!ctx) return HRC_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return HRC_ERR_HIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Ws w{static_cast<char *>(workspace), L};
+    if (flags & HRC_FLAG_VALIDATE) {
+        st = validate_inputs(w, emission, sigma_t, s);
+        if (st != HRC_OK) return st;
+    }
+    Phase ph[kMaxPhases];
+    SolveBuffers b{emission, sigma_t, fluence, nullptr, nullptr, nullptr};
+    int np = build_solve_phases(w, b, false, nullptr, ph, kMaxPhases);
+    return run_phases(ph, np, s);
+}
+
+hrc_status hrc_backward(hrc_context *ctx, int log2_size, const float *emission,
+                        const float *sigma_t, const float *grad_fluence, float *grad_emission,
+                        float *grad_sigma_t, void *workspace, size_t workspace_bytes,
+                        void *stream, unsigned flags) {
+    hrc_status st = check_shape(log2_size);
+    if (st != HRC_OK) return st;
+    if (!aligned16(emission) || !aligned16(sigma_t) || !aligned16(grad_fluence) ||
+        !aligned16(grad_emission) || !aligned16(grad_sigma_t) || !aligned16(workspace))
+        return HRC_ERR_INVALID_ARG;
+    if (flags & ~HRC_FLAG_VALIDATE) return HRC_ERR_UNSUPPORTED;
+    Layout L = make_layout(log2_size, true);
+    if (workspace_bytes < L.total) return HRC_ERR_WORKSPACE;
+    if (!ctx) return HRC_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return HRC_ERR_HIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Ws w{static_cast<char *>(workspace), L};
+    if (flags & HRC_FLAG_VALIDATE) {
+        st = validate_inputs(w, emission, sigma_t, s);
+        if (st != HRC_OK) return st;
+    }
+    Phase ph[kMaxPhases];
+    SolveBuffers b{emission, sigma_t, nullptr, grad_fluence, grad_emission, grad_sigma_t};
+    int np = build_solve_phases(w, b, true, nullptr, ph, kMaxPhases);
+    return run_phases(ph, np, s);
+}
+
+static int phase_level(const Phase &p) {
+    switch (p.kind) {
+        case PH_UP: return p.a.up.n;
+        case PH_DOWN: return p.a.down.n;
+        case PH_DOWN_ADJ: return p.a.da.n;
+        case PH_DT: return p.a.dt.n;
+        default: return -1;
+    }
+}
+
+hrc_status hrc_profile_solve(hrc_context *ctx, int log2_size, const float *emission,
+                             const float *sigma_t, float *fluence, const float *grad_fluence,
+                             float *grad_emission, float *grad_sigma_t, void *workspace,
+                             size_t workspace_bytes, void *stream, float *pass_ms,
+                             int *pass_kind, int *pass_level, int max_passes, int *count) {
+    hrc_status st = check_shape(log2_size);
+    if (st != HRC_OK) return st;
+    const bool bwd = grad_fluence != nullptr;
+    if (!aligned16(emission) || !aligned16(sigma_t) || !aligned16(workspace))
+        return HRC_ERR_INVALID_ARG;
+    if (bwd ? (!aligned16(grad_emission) || !aligned16(grad_sigma_t)) : !aligned16(fluence))
+        return HRC_ERR_INVALID_ARG;
+    if (!pass_ms || !pass_kind || !pass_level || !count || max_passes < 0)
+        return HRC_ERR_INVALID_ARG;
+    Layout L = make_layout(log2_size, bwd);
+    if (workspace_bytes < L.total) return HRC_ERR_WORKSPACE;
+    if (!ctx) return HRC_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return HRC_ERR_HIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Ws w{static_cast<char *>(workspace), L};
+    Phase ph[kMaxPhases];
+    SolveBuffers b = bwd ? SolveBuffers{emission, sigma_t, nullptr, grad_fluence, grad_emission,
+                                        grad_sigma_t}
+                         : SolveBuffers{emission, sigma_t, fluence, nullptr, nullptr, nullptr};
+    const int np = build_solve_phases(w, b, bwd, nullptr, ph, kMaxPhases);
+    std::vector<hipEvent_t> ev(np + 1, nullptr);
+    st = HRC_OK;
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) st = HRC_ERR_HIP;
+    if (st == HRC_OK && hipEventRecord(ev[0], s) != hipSuccess) st = HRC_ERR_HIP;
+    for (int i = 0; i < np && st == HRC_OK; ++i) {
+        if (launch_phase(ph[i], s) != hipSuccess || hipEventRecord(ev[i + 1], s) != hipSuccess)
+            st = HRC_ERR_HIP;
+    }
+    if (st == HRC_OK && hipEventSynchronize(ev[np]) != hipSuccess) st = HRC_ERR_HIP;
+    for (int i = 0; i < np && st == HRC_OK; ++i) {
+        if (i >= max_passes) break;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) != hipSuccess) st = HRC_ERR_HIP;
+        pass_ms[i] = ms;
+        pass_kind[i] = ph[i].kind;
+        pass_level[i] = phase_level(ph[i]);
+    }
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    *count = np;
+    return st;
+}
+
+}  // extern "C"

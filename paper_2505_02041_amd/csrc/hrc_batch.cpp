@@ -1,0 +1,245 @@
+// Batched forward + backward: many scenes of different power-of-two sizes in one
+// persistent-kernel launch captured in a HIP graph, with tile sizes picked by
+// timing candidates on the device.
+#include <stdint.h>
+#include <stdlib.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/hrc.h"
+#include "hrc_internal.h"
+
+using namespace hrc;
+
+struct hrc_batch {
+    int device = 0;
+    char *dmem = nullptr;          // scene workspaces, then the scheduler tables
+    size_t dmem_bytes = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int target_tiles = 0;          // chosen by the autotuner
+    int grid = 0;
+};
+
+namespace {
+
+struct Plan {
+    std::vector<Phase> phases;     // all scenes, each scene's passes in order
+    std::vector<unsigned> seg_start;
+    std::vector<int> seg_phase;
+    unsigned total_items = 0;
+};
+
+// Elements per thread for a phase so that it splits into at most `target`
+// tiles (tiles of 256*U outputs); fixed-shape phases keep their 32x32 tiles.
+void size_tiles(Phase &p, int target) {
+    if (p.kind == PH_TRANSPOSE || p.kind == PH_FRAME_SUM || p.kind == PH_GATHER_ADJ) return;
+    p.U = 1;
+    unsigned t1 = phase_tiles(p);
+    unsigned U = (t1 + (unsigned)target - 1) / (unsigned)target;
+    p.U = (int)std::max(1u, std::min(U, 64u));
+}
+
+// Interleave the scenes' phase chains: step t holds phase t of every scene
+// that has one, so every phase is queued after the phase it depends on.
+void order_items(Plan &pl, const std::vector<int> &first, const std::vector<int> &count) {
+    pl.seg_start.clear();
+    pl.seg_phase.clear();
+    unsigned pos = 0;
+    int max_count = 0;
+    for (int c : count) max_count = std::max(max_count, c);
+    for (int t = 0; t < max_count; ++t) {
+        for (size_t s = 0; s < first.size(); ++s) {
+            if (t >= count[s]) continue;
+            const int gi = first[s] + t;
+            Phase &p = pl.phases[gi];
+            p.dep = t > 0 ? gi - 1 : -1;
+            p.dep_tiles = t > 0 ? phase_tiles(pl.phases[gi - 1]) : 0;
+            pl.seg_start.push_back(pos);
+            pl.seg_phase.push_back(gi);
+            pos += phase_tiles(p);
+        }
+    }
+    pl.total_items = pos;
+}
+
+void free_batch(hrc_batch *b) {
+    if (!b) return;
+    DeviceGuard g(b->device);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->dmem) (void)hipFree(b->dmem);
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, unsigned flags,
+                          void *stream, hrc_batch **out) {
+    if (!out) return HRC_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!scenes || count <= 0) return HRC_ERR_INVALID_ARG;
+    for (int i = 0; i < count; ++i) {
+        const hrc_scene &sc = scenes[i];
+        if (sc.log2_size < HRC_MIN_LOG2 || sc.log2_size > HRC_MAX_LOG2) return HRC_ERR_SHAPE;
+    }
+    auto ok16 = [](const void *p) { return p && (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
+    for (int i = 0; i < count; ++i) {
+        const hrc_scene &sc = scenes[i];
+        if (!ok16(sc.emission) || !ok16(sc.sigma_t) || !ok16(sc.fluence)) return HRC_ERR_INVALID_ARG;
+        const bool any = sc.grad_fluence || sc.grad_emission || sc.grad_sigma_t;
+        if (any && (!ok16(sc.grad_fluence) || !ok16(sc.grad_emission) || !ok16(sc.grad_sigma_t)))
+            return HRC_ERR_INVALID_ARG;
+    }
+    if (flags != 0) return HRC_ERR_UNSUPPORTED;
+    if (!ctx) return HRC_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return HRC_ERR_HIP;
+    hipStream_t user = static_cast<hipStream_t>(stream);
+    // the autotuner runs the batch on the caller's buffers: let pending work on
+    // them finish first
+    if (hipStreamSynchronize(user) != hipSuccess) return HRC_ERR_HIP;
+
+    hrc_batch *b = new hrc_batch();
+    b->device = ctx->device;
+
+    // ---- device memory: per-scene workspaces, then scheduler tables --------
+    std::vector<Layout> layouts(count);
+    std::vector<size_t> ws_off(count);
+    size_t off = 0;
+    for (int i = 0; i < count; ++i) {
+        const bool bwd = scenes[i].grad_fluence != nullptr;
+        layouts[i] = make_layout(scenes[i].log2_size, bwd);
+        ws_off[i] = off;
+        off += align256(layouts[i].total);
+    }
+    const size_t ws_total = off;
+    const size_t max_phases = (size_t)count * kMaxPhases;
+    const size_t phases_off = ws_total;
+    off += align256(max_phases * sizeof(Phase));
+    const size_t seg_start_off = off;
+    off += align256(max_phases * sizeof(unsigned));
+    const size_t seg_phase_off = off;
+    off += align256(max_phases * sizeof(int));
+    const size_t sched_off = off;  // counter, done[] per phase, error word
+    off += align256((max_phases + 2) * sizeof(unsigned));
+    b->dmem_bytes = off;
+    if (hipMalloc(&b->dmem, b->dmem_bytes) != hipSuccess) {
+        b->dmem = nullptr;
+        free_batch(b);
+        return HRC_ERR_HIP;
+    }
+
+    // ---- phase chains ------------------------------------------------------
+    Plan pl;
+    std::vector<int> first(count), np(count);
+    for (int i = 0; i < count; ++i) {
+        const hrc_scene &sc = scenes[i];
+        Ws w{b->dmem + ws_off[i], layouts[i]};
+        SolveBuffers sb{sc.emission, sc.sigma_t, sc.fluence, sc.grad_fluence, sc.grad_emission,
+                        sc.grad_sigma_t};
+        Phase tmp[kMaxPhases];
+        int n = build_solve_phases(w, sb, sc.grad_fluence != nullptr, nullptr, tmp, kMaxPhases);
+        first[i] = (int)pl.phases.size();
+        np[i] = n;
+        pl.phases.insert(pl.phases.end(), tmp, tmp + n);
+    }
+
+    int per_cu = 0;
+    if (persistent_occupancy(&per_cu) != hipSuccess || per_cu <= 0) per_cu = 1;
+    b->grid = ctx->num_cus * per_cu;
+
+    Phase *d_phases = reinterpret_cast<Phase *>(b->dmem + phases_off);
+    unsigned *d_seg_start = reinterpret_cast<unsigned *>(b->dmem + seg_start_off);
+    int *d_seg_phase = reinterpret_cast<int *>(b->dmem + seg_phase_off);
+    unsigned *d_counter = reinterpret_cast<unsigned *>(b->dmem + sched_off);
+    unsigned *d_done = d_counter + 1;
+
+    hipStream_t cap = nullptr;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+        free_batch(b);
+        return HRC_ERR_HIP;
+    }
+    auto upload = [&](int target) -> bool {
+        for (Phase &p : pl.phases) size_tiles(p, target);
+        order_items(pl, first, np);
+        return hipMemcpyAsync(d_phases, pl.phases.data(), pl.phases.size() * sizeof(Phase),
+                              hipMemcpyHostToDevice, cap) == hipSuccess &&
+               hipMemcpyAsync(d_seg_start, pl.seg_start.data(),
+                              pl.seg_start.size() * sizeof(unsigned), hipMemcpyHostToDevice,
+                              cap) == hipSuccess &&
+               hipMemcpyAsync(d_seg_phase, pl.seg_phase.data(), pl.seg_phase.size() * sizeof(int),
+                              hipMemcpyHostToDevice, cap) == hipSuccess &&
+               hipStreamSynchronize(cap) == hipSuccess;
+    };
+    auto run = [&]() -> bool {
+        return launch_persistent(d_phases, d_seg_start, d_seg_phase, (int)pl.seg_start.size(),
+                                 pl.total_items, d_counter, d_done,
+                                 (unsigned)pl.phases.size(), b->grid, cap) == hipSuccess;
+    };
+
+    // ---- autotune: the largest tile count per phase (hence elements per
+    // tile) that gives the fastest whole-batch launch ---------------------
+    const int candidates[] = {b->grid, 2 * b->grid, 4 * b->grid, 8 * b->grid};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool fine = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    float best_ms = 1e30f;
+    int best = candidates[1];
+    for (int c : candidates) {
+        if (!fine) break;
+        fine = upload(c) && run() && hipStreamSynchronize(cap) == hipSuccess;  // warm-up
+        if (!fine) break;
+        fine = hipEventRecord(e0, cap) == hipSuccess && run() &&
+               hipEventRecord(e1, cap) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+        float ms = 0.f;
+        if (fine && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    if (fine) {
+        // the scheduler's error word (a dependency wait that timed out)
+        unsigned err = 0;
+        fine = hipMemcpy(&err, d_done + pl.phases.size(), sizeof(unsigned),
+                         hipMemcpyDeviceToHost) == hipSuccess && err == 0;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    b->target_tiles = best;
+    if (fine) fine = upload(best);
+
+    // ---- capture one launch in a graph ---------------------------------
+    if (fine) fine = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (fine) {
+        bool launched = run();
+        fine = (hipStreamEndCapture(cap, &b->graph) == hipSuccess) && launched;
+    }
+    if (fine) fine = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess;
+    (void)hipStreamDestroy(cap);
+    if (!fine) {
+        free_batch(b);
+        return HRC_ERR_HIP;
+    }
+    *out = b;
+    return HRC_OK;
+}
+
+hrc_status hrc_batch_launch(hrc_batch *batch, void *stream) {
+    if (!batch || !batch->exec) return HRC_ERR_INVALID_ARG;
+    DeviceGuard g(batch->device);
+    if (!g.ok) return HRC_ERR_HIP;
+    return hipGraphLaunch(batch->exec, static_cast<hipStream_t>(stream)) == hipSuccess
+               ? HRC_OK
+               : HRC_ERR_HIP;
+}
+
+size_t hrc_batch_workspace_bytes(const hrc_batch *batch) {
+    return batch ? batch->dmem_bytes : 0;
+}
+
+void hrc_batch_destroy(hrc_batch *batch) { free_batch(batch); }
+
+}  // extern "C"

@@ -1,0 +1,168 @@
+// Internal declarations shared by the host API, the batch planner and the HIP
+// kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+// Opaque handle of the C ABI.
+struct hrc_context {
+    int device;
+    int num_cus;
+};
+
+namespace hrc {
+
+constexpr int kQuadrants = 4;
+constexpr int kTracedLevels = 3;  // T_0..T_2 are traced directly (Section 4.2)
+constexpr int kMaxLog2 = 12;
+constexpr int kConeTable = (1 << (kMaxLog2 + 1)) - 1;  // sum over m <= 12 of 2^m
+
+// Entries of T_n for one quadrant: (S >> n) columns x (2^n + 1) directions x S rows.
+inline size_t t_level_entries(int N, int n) {
+    size_t S = size_t(1) << N;
+    return (S >> n) * ((size_t(1) << n) + 1) * S;
+}
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Byte offsets of every region inside a forward or backward workspace.
+struct Layout {
+    int N = 0;
+    size_t S = 0;
+    size_t fieldsT = 0;                  // eps^T then sigma^T, [S][S] float each
+    size_t t_level[kMaxLog2 + 2] = {};   // T_n: 4 quadrants x t_level_entries float2
+    size_t r_level[kMaxLog2 + 1] = {};   // R buffers: 4 quadrants x S^2 float each
+    int r_count = 0;                     // 2 (forward ping-pong) or N (keeps every R_n)
+    size_t dt_level[kMaxLog2 + 2] = {};  // backward: adjoint pyramid
+    size_t dr_level[kMaxLog2 + 1] = {};  // backward: adjoint cascades
+    size_t dfield = 0;                   // backward: per-quadrant frame gradients
+    size_t total = 0;
+};
+
+Layout make_layout(int N, bool backward);
+
+struct Ws {
+    char *base;
+    Layout L;
+    float2 *T(int n) const { return reinterpret_cast<float2 *>(base + L.t_level[n]); }
+    float2 *dT(int n) const { return reinterpret_cast<float2 *>(base + L.dt_level[n]); }
+    float *R(int i) const { return reinterpret_cast<float *>(base + L.r_level[i]); }
+    float *dR(int i) const { return reinterpret_cast<float *>(base + L.dr_level[i]); }
+    float *epsT() const { return reinterpret_cast<float *>(base + L.fieldsT); }
+    float *sigT() const { return epsT() + L.S * L.S; }
+    float *dE() const { return reinterpret_cast<float *>(base + L.dfield); }
+    float *dS() const { return dE() + kQuadrants * L.S * L.S; }
+};
+
+// ---- Arguments of each phase (one pass over one level of one scene) -------
+
+struct TransposeArgs { const float *a, *b; float *aT, *bT; int N; };
+struct SeedArgs {
+    const float *eps, *sig, *epsT, *sigT;
+    float2 *T0, *T1, *T2;
+    size_t e0, e1, e2;  // entries per quadrant of each level
+    int N;
+};
+struct UpArgs { const float2 *Tp; float2 *T; size_t ep, e; int N, n; };
+struct DownArgs {
+    const float *Rn1;        // R_{n+1}; unused when n + 1 == N
+    const float2 *Tn, *Tn1;  // T_n, T_{n+1}
+    float *R;                // R_n
+    size_t en, en1;
+    int N, n;
+};
+struct FrameSumArgs { const float *src, *src2; float *out, *out2; int N, off; };
+struct GatherAdjArgs { const float *dF; float *dR0; int N; };
+struct DownAdjArgs {
+    const float *dR;         // dR_n
+    const float2 *Tn, *Tn1;
+    float *dRn1;             // dR_{n+1}
+    size_t en, en1;
+    int N, n;
+};
+struct DTArgs {
+    const float2 *Tn;        // T_n
+    const float2 *dTn1;      // dT_{n+1} (when T_{n+1} is merged up from T_n)
+    const float *dRn;        // dR_n
+    const float *dRm;        // dR_{n-1}
+    const float *Rn1;        // R_{n+1}
+    const float *Rn;         // R_n
+    float2 *dT;              // out: dT_n
+    size_t en, en1;
+    int N, n, has_up;
+};
+struct SeedAdjArgs {
+    const float *eps, *sig, *epsT, *sigT;
+    const float2 *dT0, *dT1, *dT2;
+    size_t e0, e1, e2;
+    float *dE, *dS;          // per-quadrant frame gradients [4][S][S]
+    int N;
+};
+
+enum PhaseKind {
+    PH_TRANSPOSE = 0, PH_SEED, PH_UP, PH_DOWN, PH_FRAME_SUM, PH_GATHER_ADJ,
+    PH_DOWN_ADJ, PH_DT, PH_SEED_ADJ, PH_KIND_COUNT
+};
+
+// One pass.  U = elements per thread of the elementwise phases (a tile covers
+// 256*U consecutive outputs); dep / dep_tiles are used by the batch kernel.
+struct Phase {
+    int kind = 0;
+    int U = 1;
+    int dep = -1;
+    unsigned dep_tiles = 0;
+    union A {
+        TransposeArgs tr;
+        SeedArgs seed;
+        UpArgs up;
+        DownArgs down;
+        FrameSumArgs fs;
+        GatherAdjArgs ga;
+        DownAdjArgs da;
+        DTArgs dt;
+        SeedAdjArgs sa;
+        A() : dt{} {}
+    } a;
+};
+
+// The phase list of one forward (and, with grads, backward) solve, in order.
+// `U` gives elements per thread per phase kind (NULL = 1 everywhere).
+struct SolveBuffers {
+    const float *eps, *sig;
+    float *F;
+    const float *dF;
+    float *dE, *dS;  // all three NULL: forward only
+};
+int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, const int *U,
+                       Phase *out, int max_out);
+
+unsigned phase_tiles(const Phase &p);
+hipError_t upload_cone_table(const float *host_table);
+hipError_t launch_phase(const Phase &p, hipStream_t s);
+hipError_t launch_persistent(const Phase *phases, const unsigned *seg_start,
+                             const int *seg_phase, int nseg, unsigned total_items,
+                             unsigned *counter, unsigned *done, unsigned nphases, int grid,
+                             hipStream_t s);
+hipError_t persistent_occupancy(int *blocks_per_cu);
+hipError_t launch_validate(const float *a, const float *b, size_t n, int *flag,
+                           hipStream_t s);
+
+constexpr int kMaxPhases = 4 * kMaxLog2 + 16;  // passes of one forward + backward solve
+
+// RAII switch to a device for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) return;
+        ok = (prev == dev) || (hipSetDevice(dev) == hipSuccess);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (ok && hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace hrc

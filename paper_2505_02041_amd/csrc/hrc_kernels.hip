@@ -1,0 +1,766 @@
+// HIP kernels (gfx950) of Holographic Radiance Cascades: forward and adjoint.
+//
+// Frames.  Each quadrant solve works in a frame (u, w) whose +u axis faces the
+// quadrant (Section 4: the solve for [-pi/4, pi/4] is rotated four times,
+// Algorithm 1, Lighting).  Quadrant q reads the scene as
+//   q = 0 (+x): E[u][w] = img[w][u]          = imgT[u][w]
+//   q = 1 (-x): E[u][w] = img[w][S-1-u]      = imgT[S-1-u][w]
+//   q = 2 (+y): E[u][w] = img[u][w]
+//   q = 3 (-y): E[u][w] = img[S-1-u][w]
+// so that, with a transposed copy imgT, every quadrant reads whole rows w.
+// Each solve is mirror symmetric in w, so flips stand in for rotations.
+//
+// Storage (per quadrant, y = w fastest so that 64 lanes read 64 consecutive y):
+//   T_n  float2 (L, T)  [S >> n][2^n + 1][S]   index (x*(2^n+1) + k)*S + y
+//   R_n  float          [S >> n][2^n][S]       index ((x << n) | ii)*S + y
+// Probe (n, x, y) sits at the centre of pixel (x*2^n, y).  Outside the grid
+// there is no light: an interval starting off-grid is <0, 1>, an angular
+// fluence off-grid is 0, and R_N = 0 (Section 4.2).
+//
+// Every kernel is elementwise in gather form: one thread owns one output
+// element and reads what it needs, so results do not depend on the launch
+// shape and need no atomics.
+#include "hrc_internal.h"
+
+namespace hrc {
+
+// A_m(jj) of Eq. 13 for m = 0..12 at offset 2^m - 1 (uploaded by the host).
+__constant__ float c_cone[kConeTable];
+
+// Cells crossed by the traced intervals of levels 0..2 (Section 4.2, traced with
+// analytic per-pixel integration, Section 5), for a probe at a pixel centre:
+// offsets (du, dw) from the probe's pixel and chord lengths, in order from the
+// probe.  Derived from the straight segment (1/2,1/2) -> (1/2,1/2) + v_n(k),
+// v_n(k) = (2^n, 2k - 2^n): a diagonal step splits each pixel it crosses at
+// the centre (corner touches have zero length); the slope -1/2 and +1/2 rays of
+// level 2 cross 7 pixels with pieces of sqrt(5)/4 and one of sqrt(5)/2.
+// Stencil id: n = 0 -> k, n = 1 -> 2 + k, n = 2 -> 5 + k.
+constexpr float kH2 = 0.70710678118654752f;  // sqrt(2)/2
+constexpr float kR2 = 1.41421356237309505f;  // sqrt(2)
+constexpr float kQ5 = 0.55901699437494742f;  // sqrt(5)/4
+constexpr float kF5 = 1.11803398874989485f;  // sqrt(5)/2
+constexpr int kMaxCells = 7;
+__constant__ int c_st_len[10] = {2, 2, 3, 3, 3, 5, 7, 5, 7, 5};
+__constant__ signed char c_st_du[10][kMaxCells] = {
+    {0, 1}, {0, 1}, {0, 1, 2}, {0, 1, 2}, {0, 1, 2},
+    {0, 1, 2, 3, 4}, {0, 1, 1, 2, 3, 3, 4}, {0, 1, 2, 3, 4}, {0, 1, 1, 2, 3, 3, 4},
+    {0, 1, 2, 3, 4}};
+__constant__ signed char c_st_dw[10][kMaxCells] = {
+    {0, -1}, {0, 1}, {0, -1, -2}, {0, 0, 0}, {0, 1, 2},
+    {0, -1, -2, -3, -4}, {0, 0, -1, -1, -1, -2, -2}, {0, 0, 0, 0, 0},
+    {0, 0, 1, 1, 1, 2, 2}, {0, 1, 2, 3, 4}};
+__constant__ float c_st_ell[10][kMaxCells] = {
+    {kH2, kH2}, {kH2, kH2}, {kH2, kR2, kH2}, {0.5f, 1.f, 0.5f}, {kH2, kR2, kH2},
+    {kH2, kR2, kR2, kR2, kH2}, {kQ5, kQ5, kQ5, kF5, kQ5, kQ5, kQ5},
+    {0.5f, 1.f, 1.f, 1.f, 0.5f}, {kQ5, kQ5, kQ5, kF5, kQ5, kQ5, kQ5},
+    {kH2, kR2, kR2, kR2, kH2}};
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+
+// Work-tile id for block b of nb: consecutive tiles land on the same XCD (the
+// hardware deals blocks round-robin over 8 XCDs), so neighbouring rows that
+// share input rows share an L2.
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb) {
+    unsigned xcd = b & 7u, local = b >> 3;
+    unsigned q = nb >> 3, r = nb & 7u;
+    return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
+// <L, T> of a chord of length ell through a uniform pixel (Eq. 2-4):
+// T = exp(-tau), L = eps*ell*(1 - exp(-tau))/tau, tau = sig*ell.
+__device__ __forceinline__ float cell_phi(float tau) {
+    return tau < 1e-3f ? 1.0f - tau * (0.5f - tau * (1.0f / 6.0f)) : -expm1f(-tau) / tau;
+}
+
+__device__ __forceinline__ float2 cell_interval(float e, float s, float ell) {
+    float tau = s * ell;
+    return make_float2(e * ell * cell_phi(tau), expf(-tau));
+}
+
+// Eq. 7: near interval first.
+__device__ __forceinline__ float2 merge(float2 n, float2 f) {
+    return make_float2(fmaf(n.y, f.x, n.x), n.y * f.y);
+}
+
+__device__ __forceinline__ const float *frame_src(int q, const float *img, const float *imgT) {
+    return q < 2 ? imgT : img;
+}
+
+__device__ __forceinline__ int frame_row(int q, int u, int S) {
+    return (q & 1) ? S - 1 - u : u;
+}
+
+__device__ __forceinline__ int stencil_id(int n, int k) {
+    return n == 0 ? k : (n == 1 ? 2 + k : 5 + k);
+}
+
+// R_m(column c, cone jj, row y) of one quadrant, 0 outside the grid; R_N = 0.
+__device__ __forceinline__ float r_lookup(const float *Rq, int N, int m, int c, int jj, int y) {
+    const int S = 1 << N;
+    if (m >= N || c >= (S >> m) || y < 0 || y >= S) return 0.f;
+    return Rq[((size_t)((c << m) | jj)) * S + y];
+}
+
+// ---------------------------------------------------------------------------
+// Phase bodies.  Each computes one work tile; a standalone kernel runs one tile
+// per block and the persistent batch kernel runs tiles pulled from its queue,
+// so both paths execute the same code.  Elementwise phases cover 256*U
+// consecutive output elements per tile (U elements per thread, 256 apart).
+// ---------------------------------------------------------------------------
+
+// Transposed copies of the two input fields (for the +-x frames), 32x32 tiles.
+__device__ void body_transpose(const TransposeArgs &a, unsigned tile) {
+    __shared__ float ta[32][33];
+    __shared__ float tb[32][33];
+    const int S = 1 << a.N;
+    const int tiles = (S + 31) >> 5;
+    const int tr = tile / tiles, tc = tile % tiles;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int i = ty; i < 32; i += 8) {
+        int r = tr * 32 + i, c = tc * 32 + tx;
+        if (r < S && c < S) {
+            ta[i][tx] = a.a[(size_t)r * S + c];
+            tb[i][tx] = a.b[(size_t)r * S + c];
+        }
+    }
+    __syncthreads();
+    for (int i = ty; i < 32; i += 8) {
+        int r = tc * 32 + i, c = tr * 32 + tx;  // output row = input column
+        if (r < S && c < S) {
+            a.aT[(size_t)r * S + c] = ta[tx][i];
+            a.bT[(size_t)r * S + c] = tb[tx][i];
+        }
+    }
+    __syncthreads();
+}
+
+// Traced levels T_0, T_1, T_2 (Algorithm 1, first loop).
+__device__ void body_seed(const SeedArgs &a, unsigned tile, int U) {
+    const int N = a.N, S = 1 << N;
+    const unsigned rpq = 19u * (unsigned)S / 4u;  // rows per quadrant: (2 + 1.5 + 1.25) S
+    const size_t total = (size_t)4 * rpq * S;
+    for (int uu = 0; uu < U; ++uu) {
+        const size_t idx = ((size_t)tile * U + uu) * 256 + threadIdx.x;
+        if (idx >= total) return;
+        const int y = (int)(idx & (S - 1));
+        const unsigned row = (unsigned)(idx >> N);
+        const int q = row / rpq;
+        unsigned r = row % rpq;
+        int n, x, k;
+        float2 *out;
+        size_t qoff;
+        if (r < 2u * S) {
+            n = 0; x = r >> 1; k = r & 1; out = a.T0; qoff = a.e0;
+        } else if ((r -= 2u * S) < 3u * S / 2u) {
+            n = 1; x = r / 3; k = r % 3; out = a.T1; qoff = a.e1;
+        } else {
+            r -= 3u * S / 2u;
+            n = 2; x = r / 5; k = r % 5; out = a.T2; qoff = a.e2;
+        }
+        const float *E = frame_src(q, a.eps, a.epsT);
+        const float *G = frame_src(q, a.sig, a.sigT);
+        const int sid = stencil_id(n, k);
+        const int u0 = x << n;
+        float2 acc = make_float2(0.f, 1.f);
+        for (int j = 0; j < c_st_len[sid]; ++j) {
+            int u = u0 + c_st_du[sid][j], w = y + c_st_dw[sid][j];
+            if (u < S && w >= 0 && w < S) {
+                size_t id = (size_t)frame_row(q, u, S) * S + w;
+                acc = merge(acc, cell_interval(E[id], G[id], c_st_ell[sid][j]));
+            }
+        }
+        out[q * qoff + ((size_t)x * ((1 << n) + 1) + k) * S + y] = acc;
+    }
+}
+
+// Merge up: T_n from T_{n-1} (Section 4.1, Eq. 18-20).
+__device__ void body_merge_up(const UpArgs &a, unsigned tile, int U) {
+    const int N = a.N, S = 1 << N, n = a.n;
+    const int h = 1 << (n - 1);
+    const int dirs = 2 * h + 1, pdirs = h + 1;
+    const unsigned rpq = (unsigned)(S >> n) * dirs;
+    const size_t total = (size_t)4 * rpq * S;
+    for (int uu = 0; uu < U; ++uu) {
+        const size_t idx = ((size_t)tile * U + uu) * 256 + threadIdx.x;
+        if (idx >= total) return;
+        const int y = (int)(idx & (S - 1));
+        const unsigned row = (unsigned)(idx >> N);
+        const int q = row / rpq;
+        const unsigned r = row % rpq;
+        const int x = r / dirs, k = r % dirs;
+        const float2 *near = a.Tp + q * a.ep + (size_t)(2 * x) * pdirs * S;
+        const float2 *far = near + (size_t)pdirs * S;
+        float2 res;
+        if ((k & 1) == 0) {
+            // Eq. 18: p -> p + v_{n-1}(k/2) -> p + v_n(k), exact.
+            const int kk = k >> 1, yf = y + 2 * kk - h;
+            float2 f = (yf >= 0 && yf < S) ? far[(size_t)kk * S + yf] : make_float2(0.f, 1.f);
+            res = merge(near[(size_t)kk * S + y], f);
+        } else {
+            // Eq. 19-20: mean of the two bent paths through directions (k+-1)/2.
+            const int ka = (k + 1) >> 1, kb = (k - 1) >> 1;
+            const int ya = y + 2 * ka - h, yb = y + 2 * kb - h;
+            float2 fa = (ya >= 0 && ya < S) ? far[(size_t)kb * S + ya] : make_float2(0.f, 1.f);
+            float2 fb = (yb >= 0 && yb < S) ? far[(size_t)ka * S + yb] : make_float2(0.f, 1.f);
+            float2 p = merge(near[(size_t)ka * S + y], fa);
+            float2 m = merge(near[(size_t)kb * S + y], fb);
+            res = make_float2(0.5f * (p.x + m.x), 0.5f * (p.y + m.y));
+        }
+        a.T[q * a.e + (size_t)r * S + y] = res;
+    }
+}
+
+// Merge down: R_n from R_{n+1}, T_n, T_{n+1} (Eq. 14-17).
+__device__ void body_merge_down(const DownArgs &a, unsigned tile, int U) {
+    const int N = a.N, S = 1 << N, n = a.n;
+    const size_t SS = (size_t)S * S;
+    const size_t total = 4 * SS;
+    const int m = n + 1;
+    for (int uu = 0; uu < U; ++uu) {
+        const size_t idx = ((size_t)tile * U + uu) * 256 + threadIdx.x;
+        if (idx >= total) return;
+        const int y = (int)(idx & (S - 1));
+        const unsigned row = (unsigned)(idx >> N);
+        const int q = row >> N;
+        const unsigned r = row & (S - 1);
+        const int x = r >> n, ii = r & ((1 << n) - 1);
+        const float *Rq = a.Rn1 + q * SS;
+        float acc = 0.f;
+        if (x & 1) {
+            // Eq. 14: trace the half-cone's outer edge to the level n+1 probe.
+            const float2 *Tx = a.Tn + q * a.en + (size_t)x * ((1 << n) + 1) * S;
+            const int c = (x + 1) >> 1;
+#pragma unroll
+            for (int up = 0; up < 2; ++up) {
+                const int e = ii + up, jj = 2 * ii + up;
+                const float A = c_cone[(1 << m) - 1 + jj];
+                float2 t = Tx[(size_t)e * S + y];
+                float rf = r_lookup(Rq, N, m, c, jj, y + 2 * e - (1 << n));
+                acc += fmaf(t.y, rf, A * t.x);
+            }
+        } else {
+            // Eq. 15-17: average the co-located probe with the doubled-edge trace.
+            const int c = x >> 1;
+            const float2 *Tx = a.Tn1 + q * a.en1 + (size_t)c * ((1 << m) + 1) * S;
+#pragma unroll
+            for (int up = 0; up < 2; ++up) {
+                const int e2 = 2 * ii + 2 * up, jj = 2 * ii + up;
+                const float A = c_cone[(1 << m) - 1 + jj];
+                float2 t = Tx[(size_t)e2 * S + y];
+                float r0 = r_lookup(Rq, N, m, c, jj, y);
+                float r1 = r_lookup(Rq, N, m, c + 1, jj, y + 2 * e2 - (1 << m));
+                acc += 0.5f * (r0 + fmaf(t.y, r1, A * t.x));
+            }
+        }
+        a.R[q * SS + (size_t)r * S + y] = acc;
+    }
+}
+
+// out[r][c] = sum over q of src_q[u + off][w], (u, w) the frame coordinates of
+// image pixel (r, c) in quadrant q; rows u + off >= S read as 0.  off = 1 is the
+// gather of Algorithm 1 (R_0 at the probe one pixel ahead); off = 0 sums
+// per-quadrant frame fields back onto the image.  Two fields at once when
+// src2 is set.  32x32 tiles through LDS keep the +-x (transposed) reads
+// coalesced.
+__device__ void body_frame_sum(const FrameSumArgs &a, unsigned tile) {
+    __shared__ float fs_tile[2][32][33];
+    const int N = a.N, S = 1 << N;
+    const size_t SS = (size_t)S * S;
+    const int tiles = (S + 31) >> 5;
+    const int tr = tile / tiles, tc = tile % tiles;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const bool two = a.src2 != nullptr;
+    float acc0[4] = {0.f, 0.f, 0.f, 0.f}, acc1[4] = {0.f, 0.f, 0.f, 0.f};
+    // +-y quadrants: u = r or S-1-r, w = c: rows read directly.
+    for (int q = 2; q < 4; ++q) {
+        for (int i = 0; i < 4; ++i) {
+            int r = tr * 32 + ty + 8 * i, c = tc * 32 + tx;
+            if (r < S && c < S) {
+                int us = frame_row(q, r, S) + a.off;
+                if (us < S) {
+                    acc0[i] += a.src[q * SS + (size_t)us * S + c];
+                    if (two) acc1[i] += a.src2[q * SS + (size_t)us * S + c];
+                }
+            }
+        }
+    }
+    // +-x quadrants: u = c or S-1-c, w = r: read rows u, transpose through LDS.
+    for (int q = 0; q < 2; ++q) {
+        __syncthreads();
+        for (int i = 0; i < 4; ++i) {
+            int cl = ty + 8 * i;
+            int c = tc * 32 + cl, r = tr * 32 + tx;
+            float v0 = 0.f, v1 = 0.f;
+            if (r < S && c < S) {
+                int us = frame_row(q, c, S) + a.off;
+                if (us < S) {
+                    v0 = a.src[q * SS + (size_t)us * S + r];
+                    if (two) v1 = a.src2[q * SS + (size_t)us * S + r];
+                }
+            }
+            fs_tile[0][cl][tx] = v0;
+            fs_tile[1][cl][tx] = v1;
+        }
+        __syncthreads();
+        for (int i = 0; i < 4; ++i) {
+            int rl = ty + 8 * i;
+            acc0[i] += fs_tile[0][tx][rl];
+            acc1[i] += fs_tile[1][tx][rl];
+        }
+    }
+    __syncthreads();
+    for (int i = 0; i < 4; ++i) {
+        int r = tr * 32 + ty + 8 * i, c = tc * 32 + tx;
+        if (r < S && c < S) {
+            a.out[(size_t)r * S + c] = acc0[i];
+            if (two) a.out2[(size_t)r * S + c] = acc1[i];
+        }
+    }
+}
+
+// Transpose of the gather: dR_0[q][x][y] = dF at the image pixel of frame
+// point (x - 1, y), and 0 at x = 0.  Tile = q * tiles^2 + (x tile, y tile).
+__device__ void body_gather_adj(const GatherAdjArgs &a, unsigned tile) {
+    __shared__ float ga_tile[32][33];
+    const int N = a.N, S = 1 << N;
+    const size_t SS = (size_t)S * S;
+    const int tiles = (S + 31) >> 5;
+    const int q = tile / (tiles * tiles);
+    const int t2 = tile % (tiles * tiles);
+    const int tX = t2 / tiles, tY = t2 % tiles;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    if (q >= 2) {
+        for (int i = 0; i < 4; ++i) {
+            int x = tX * 32 + ty + 8 * i, y = tY * 32 + tx;
+            if (x < S && y < S) {
+                float v = 0.f;
+                if (x >= 1) v = a.dF[(size_t)frame_row(q, x - 1, S) * S + y];
+                a.dR0[q * SS + (size_t)x * S + y] = v;
+            }
+        }
+        return;  // uniform over the block: no barrier is skipped by part of it
+    }
+    // +-x: frame (u, w) is image (w, u or S-1-u): read image rows w = y.
+    for (int i = 0; i < 4; ++i) {
+        int yl = ty + 8 * i;
+        int y = tY * 32 + yl, x = tX * 32 + tx;
+        float v = 0.f;
+        if (x < S && y < S && x >= 1) v = a.dF[(size_t)y * S + frame_row(q, x - 1, S)];
+        ga_tile[yl][tx] = v;
+    }
+    __syncthreads();
+    for (int i = 0; i < 4; ++i) {
+        int xl = ty + 8 * i;
+        int x = tX * 32 + xl, y = tY * 32 + tx;
+        if (x < S && y < S) a.dR0[q * SS + (size_t)x * S + y] = ga_tile[tx][xl];
+    }
+    __syncthreads();
+}
+
+// Adjoint of the merge down: dR_{n+1} from dR_n (gather form).  Each R_{n+1}
+// entry (c, jj, y') is read by at most three R_n entries: the odd column 2c-1
+// (far end of Eq. 14), the even column 2c (F^0 of Eq. 16) and the even column
+// 2c-2 (far end of Eq. 17).
+__device__ void body_merge_down_adj(const DownAdjArgs &a, unsigned tile, int U) {
+    const int N = a.N, S = 1 << N, n = a.n, m = n + 1;
+    const size_t SS = (size_t)S * S;
+    for (int uu = 0; uu < U; ++uu) {
+        const size_t idx = ((size_t)tile * U + uu) * 256 + threadIdx.x;
+        if (idx >= 4 * SS) return;
+        const int yp = (int)(idx & (S - 1));
+        const unsigned row = (unsigned)(idx >> N);
+        const int q = row >> N;
+        const unsigned r = row & (S - 1);
+        const int c = r >> m, jj = r & ((1 << m) - 1);
+        const int ii = jj >> 1, up = jj & 1;
+        const float *dRq = a.dR + q * SS;
+        float acc = 0.5f * dRq[((size_t)(((2 * c) << n) | ii)) * S + yp];
+        if (c >= 1) {
+            const int e = ii + up;
+            const int x = 2 * c - 1;
+            const int y = yp - (2 * e - (1 << n));
+            if (y >= 0 && y < S) {
+                float t = a.Tn[q * a.en + ((size_t)x * ((1 << n) + 1) + e) * S + y].y;
+                acc = fmaf(dRq[((size_t)((x << n) | ii)) * S + y], t, acc);
+            }
+            const int e2 = 2 * ii + 2 * up;
+            const int x2 = 2 * c - 2;
+            const int y2 = yp - (2 * e2 - (1 << m));
+            if (y2 >= 0 && y2 < S) {
+                float t = a.Tn1[q * a.en1 + ((size_t)(c - 1) * ((1 << m) + 1) + e2) * S + y2].y;
+                acc = fmaf(0.5f * dRq[((size_t)((x2 << n) | ii)) * S + y2], t, acc);
+            }
+        }
+        a.dRn1[q * SS + (size_t)r * S + yp] = acc;
+    }
+}
+
+// Adjoint of the interval pyramid: dT_n (gather form) from the merge down at
+// levels n and n-1 and from the merge up of T_{n+1}.
+__device__ void body_dT(const DTArgs &a, unsigned tile, int U) {
+    const int N = a.N, S = 1 << N, n = a.n;
+    const size_t SS = (size_t)S * S;
+    const int dirs = (1 << n) + 1;
+    const unsigned rpq = (unsigned)(S >> n) * dirs;
+    const size_t total = (size_t)4 * rpq * S;
+    for (int uu = 0; uu < U; ++uu) {
+        const size_t idx = ((size_t)tile * U + uu) * 256 + threadIdx.x;
+        if (idx >= total) return;
+        const int y = (int)(idx & (S - 1));
+        const unsigned row = (unsigned)(idx >> N);
+        const int q = row / rpq;
+        const unsigned r = row % rpq;
+        const int x = r / dirs, k = r % dirs;
+        float gl = 0.f, gt = 0.f;
+        // (a) merge down at level n, odd x (Eq. 14): T_n(p, k) is the edge of
+        //     cone k (lower half, jj = 2k) and of cone k-1 (upper half, jj = 2k-1).
+        if (n < N && (x & 1)) {
+            const float *dRq = a.dRn + q * SS;
+            const float *Rq = a.Rn1 + q * SS;
+            const int c = (x + 1) >> 1, yf = y + 2 * k - (1 << n);
+            if (k >= 1) {
+                float g = dRq[((size_t)((x << n) | (k - 1))) * S + y];
+                gl = fmaf(g, c_cone[(1 << (n + 1)) - 1 + 2 * k - 1], gl);
+                gt = fmaf(g, r_lookup(Rq, N, n + 1, c, 2 * k - 1, yf), gt);
+            }
+            if (k < (1 << n)) {
+                float g = dRq[((size_t)((x << n) | k)) * S + y];
+                gl = fmaf(g, c_cone[(1 << (n + 1)) - 1 + 2 * k], gl);
+                gt = fmaf(g, r_lookup(Rq, N, n + 1, c, 2 * k, yf), gt);
+            }
+        }
+        // (b) merge down at level n-1, even column 2x (Eq. 17): T_n(p, k), k even,
+        //     is the doubled edge of cone k/2 (jj = k) and of cone k/2-1 (jj = k-1).
+        if (n >= 1 && (k & 1) == 0) {
+            const int nm = n - 1;
+            const float *dRq = a.dRm + q * SS;
+            const float *Rq = a.Rn + q * SS;
+            const int yf = y + 2 * k - (1 << n);
+            const int xm = 2 * x;
+            if (k >= 2) {
+                float g = 0.5f * dRq[((size_t)((xm << nm) | (k / 2 - 1))) * S + y];
+                gl = fmaf(g, c_cone[(1 << n) - 1 + k - 1], gl);
+                gt = fmaf(g, r_lookup(Rq, N, n, x + 1, k - 1, yf), gt);
+            }
+            if (k < (1 << n)) {
+                float g = 0.5f * dRq[((size_t)((xm << nm) | (k / 2))) * S + y];
+                gl = fmaf(g, c_cone[(1 << n) - 1 + k], gl);
+                gt = fmaf(g, r_lookup(Rq, N, n, x + 1, k, yf), gt);
+            }
+        }
+        // (c) merge up of T_{n+1} from T_n (Eq. 18-20), H = 2^n.
+        if (a.has_up) {
+            const int H = 1 << n;
+            const int odirs = 2 * H + 1;
+            const float2 *Tq = a.Tn + q * a.en;
+            const float2 *g0 = a.dTn1 + q * a.en1 + (size_t)(x >> 1) * odirs * S;
+            if ((x & 1) == 0) {
+                // near role: outputs (2k, far k, weight 1), (2k+1, far k+1, 1/2),
+                // (2k-1, far k-1, 1/2), far start at row y + 2k - H
+                const int yf = y + 2 * k - H;
+                const float2 *far = Tq + (size_t)(x + 1) * dirs * S;
+#pragma unroll
+                for (int v = 0; v < 3; ++v) {
+                    const int ko = v == 0 ? 2 * k : (v == 1 ? 2 * k + 1 : 2 * k - 1);
+                    const int kb = v == 0 ? k : (v == 1 ? k + 1 : k - 1);
+                    if (ko < 0 || ko > 2 * H) continue;
+                    const float wgt = v == 0 ? 1.f : 0.5f;
+                    float2 f = (yf >= 0 && yf < S) ? far[(size_t)kb * S + yf]
+                                                   : make_float2(0.f, 1.f);
+                    float2 g = g0[(size_t)ko * S + y];
+                    gl = fmaf(wgt, g.x, gl);
+                    gt = fmaf(wgt, fmaf(g.x, f.x, g.y * f.y), gt);
+                }
+            } else {
+                // far role: outputs (2k, near k), (2k+1, near k+1), (2k-1, near k-1),
+                // each from output row y - (2*ka - H)
+                const float2 *nearp = Tq + (size_t)(x - 1) * dirs * S;
+#pragma unroll
+                for (int v = 0; v < 3; ++v) {
+                    const int ko = v == 0 ? 2 * k : (v == 1 ? 2 * k + 1 : 2 * k - 1);
+                    const int ka = v == 0 ? k : (v == 1 ? k + 1 : k - 1);
+                    if (ko < 0 || ko > 2 * H) continue;
+                    const float wgt = v == 0 ? 1.f : 0.5f;
+                    const int yo = y - (2 * ka - H);
+                    if (yo < 0 || yo >= S) continue;
+                    float tn = nearp[(size_t)ka * S + yo].y;
+                    float2 g = g0[(size_t)ko * S + yo];
+                    gl = fmaf(wgt * g.x, tn, gl);
+                    gt = fmaf(wgt * g.y, tn, gt);
+                }
+            }
+        }
+        a.dT[q * a.en + (size_t)r * S + y] = make_float2(gl, gt);
+    }
+}
+
+// phi'(tau) for phi(tau) = (1 - exp(-tau))/tau: a Taylor series near 0, where
+// the closed form (tau + (1+tau) expm1(-tau))/tau^2 cancels.
+__device__ __forceinline__ float cell_dphi(float tau) {
+    if (tau < 0.25f) {
+        return -0.5f + tau * (1.f / 3.f + tau * (-1.f / 8.f + tau * (1.f / 30.f +
+               tau * (-1.f / 144.f + tau * (1.f / 840.f)))));
+    }
+    return (tau + (1.f + tau) * expm1f(-tau)) / (tau * tau);
+}
+
+// Adjoint of the traced levels: per frame cell, every traced interval that
+// crosses it (gather form), then d/d(eps, sigma) of that cell's interval.  A
+// trace is the fold of cell intervals c_1..c_m (Eq. 7), so with prefix
+// transmittance P_j: dL/dL_j = P_j, dL/dT_j = P_j L(c_j+1..m), dT/dT_j =
+// P_j T(c_j+1..m).
+__device__ void body_seed_adj(const SeedAdjArgs &a, unsigned tile, int U) {
+    const int N = a.N, S = 1 << N;
+    const size_t SS = (size_t)S * S;
+    for (int uu = 0; uu < U; ++uu) {
+        const size_t idx = ((size_t)tile * U + uu) * 256 + threadIdx.x;
+        if (idx >= 4 * SS) return;
+        const int w = (int)(idx & (S - 1));
+        const unsigned row = (unsigned)(idx >> N);
+        const int q = row >> N;
+        const int u = row & (S - 1);
+        const float *E = frame_src(q, a.eps, a.epsT);
+        const float *G = frame_src(q, a.sig, a.sigT);
+        const size_t me = (size_t)frame_row(q, u, S) * S + w;
+        const float e_me = E[me], s_me = G[me];
+        float ae = 0.f, as = 0.f;
+        for (int n = 0; n < kTracedLevels; ++n) {
+            const float2 *dTq = (n == 0 ? a.dT0 : n == 1 ? a.dT1 : a.dT2) +
+                                q * (n == 0 ? a.e0 : n == 1 ? a.e1 : a.e2);
+            const int dirs = (1 << n) + 1;
+            for (int k = 0; k < dirs; ++k) {
+                const int sid = stencil_id(n, k);
+                const int len = c_st_len[sid];
+                for (int j = 0; j < len; ++j) {
+                    const int up = u - c_st_du[sid][j], wp = w - c_st_dw[sid][j];
+                    if (up < 0 || (up & ((1 << n) - 1)) || wp < 0 || wp >= S) continue;
+                    const float2 g = dTq[((size_t)(up >> n) * dirs + k) * S + wp];
+                    float pre = 1.f;
+                    float2 suf = make_float2(0.f, 1.f);
+                    for (int i = 0; i < len; ++i) {
+                        if (i == j) continue;
+                        int uc = up + c_st_du[sid][i], wc = wp + c_st_dw[sid][i];
+                        if (uc >= S || wc < 0 || wc >= S) continue;
+                        size_t id = (size_t)frame_row(q, uc, S) * S + wc;
+                        float2 c = cell_interval(E[id], G[id], c_st_ell[sid][i]);
+                        if (i < j) pre *= c.y;
+                        else suf = merge(suf, c);
+                    }
+                    const float ell = c_st_ell[sid][j];
+                    const float tau = s_me * ell;
+                    const float dl = g.x * pre;
+                    const float dt = pre * fmaf(g.x, suf.x, g.y * suf.y);
+                    ae = fmaf(dl, ell * cell_phi(tau), ae);
+                    as = fmaf(dl, e_me * ell * ell * cell_dphi(tau), as);
+                    as = fmaf(dt, -ell * expf(-tau), as);
+                }
+            }
+        }
+        a.dE[q * SS + (size_t)u * S + w] = ae;
+        a.dS[q * SS + (size_t)u * S + w] = as;
+    }
+}
+
+__device__ __forceinline__ void run_phase(const Phase &p, unsigned tile) {
+    switch (p.kind) {
+        case PH_TRANSPOSE: body_transpose(p.a.tr, tile); break;
+        case PH_SEED: body_seed(p.a.seed, tile, p.U); break;
+        case PH_UP: body_merge_up(p.a.up, tile, p.U); break;
+        case PH_DOWN: body_merge_down(p.a.down, tile, p.U); break;
+        case PH_FRAME_SUM: body_frame_sum(p.a.fs, tile); break;
+        case PH_GATHER_ADJ: body_gather_adj(p.a.ga, tile); break;
+        case PH_DOWN_ADJ: body_merge_down_adj(p.a.da, tile, p.U); break;
+        case PH_DT: body_dT(p.a.dt, tile, p.U); break;
+        case PH_SEED_ADJ: body_seed_adj(p.a.sa, tile, p.U); break;
+        default: break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Standalone kernels: one tile per block, one kernel per pass kind (so that
+// profiles name the pass).
+// ---------------------------------------------------------------------------
+
+#define HRC_ELEMENTWISE_KERNEL(name, body, field)                                  \
+    __global__ __launch_bounds__(256) void name(Phase p) {                         \
+        body(p.a.field, xcd_tile(blockIdx.x, gridDim.x), p.U);                     \
+    }
+HRC_ELEMENTWISE_KERNEL(hrc_seed, body_seed, seed)
+HRC_ELEMENTWISE_KERNEL(hrc_merge_up, body_merge_up, up)
+HRC_ELEMENTWISE_KERNEL(hrc_merge_down, body_merge_down, down)
+HRC_ELEMENTWISE_KERNEL(hrc_merge_down_adj, body_merge_down_adj, da)
+HRC_ELEMENTWISE_KERNEL(hrc_interval_adj, body_dT, dt)
+HRC_ELEMENTWISE_KERNEL(hrc_seed_adj, body_seed_adj, sa)
+#undef HRC_ELEMENTWISE_KERNEL
+
+__global__ __launch_bounds__(256) void hrc_transpose(Phase p) { body_transpose(p.a.tr, blockIdx.x); }
+__global__ __launch_bounds__(256) void hrc_frame_sum(Phase p) { body_frame_sum(p.a.fs, blockIdx.x); }
+__global__ __launch_bounds__(256) void hrc_gather_adj(Phase p) { body_gather_adj(p.a.ga, blockIdx.x); }
+
+// ---------------------------------------------------------------------------
+// Persistent batch kernel.  Work items are (phase, tile) pairs in a global
+// order in which every phase comes after the phase it depends on (the previous
+// phase of the same scene).  Blocks claim items in that order from one counter;
+// before running an item a block waits until every tile of the dependency
+// phase is done.  A block only ever waits on items claimed before its own, by
+// blocks that are already running, so the queue always drains.  Completion is
+// published with an agent-scope release (every wave) and read with an
+// agent-scope acquire, which makes the producer's stores visible across XCDs.
+// ---------------------------------------------------------------------------
+
+constexpr unsigned kMaxSpins = 1u << 24;  // ~2 s of polling at s_sleep(2)
+
+__global__ __launch_bounds__(256) void hrc_persistent(const Phase *__restrict__ phases,
+                                                    const unsigned *__restrict__ seg_start,
+                                                    const int *__restrict__ seg_phase,
+                                                    int nseg, unsigned total_items,
+                                                    unsigned *counter, unsigned *done,
+                                                    unsigned *error) {
+    __shared__ unsigned s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+        __syncthreads();
+        const unsigned item = s_item;
+        __syncthreads();
+        if (item >= total_items) break;
+        // segment containing the item: seg_start is increasing, seg_start[0] = 0
+        int lo = 0, hi = nseg - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (seg_start[mid] <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const int pi = seg_phase[lo];
+        const Phase &p = phases[pi];
+        const unsigned tile = item - seg_start[lo];
+        if (threadIdx.x == 0 && p.dep >= 0) {
+            // Bounded wait: a dependency that never completes (a planning bug)
+            // raises the error word and lets the queue drain instead of hanging.
+            const unsigned need = p.dep_tiles;
+            unsigned spins = 0;
+            while (__hip_atomic_load(&done[p.dep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
+                   need) {
+                if (++spins > kMaxSpins) {
+                    __hip_atomic_store(error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        run_phase(p, tile);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(&done[pi], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Clears the scheduler state (a kernel rather than a memset so that it can be
+// captured in a graph and replayed).
+__global__ void hrc_clear_u32(unsigned *p, unsigned n) {
+    unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// Sets *flag when any element of a or b is negative or not finite.
+__global__ __launch_bounds__(256) void hrc_validate(const float *a, const float *b, size_t n,
+                                                  int *flag) {
+    size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * 256;
+    for (; i < n; i += stride) {
+        float x = a[i], y = b[i];
+        if (!(x >= 0.f && x <= 3.4e38f) || !(y >= 0.f && y <= 3.4e38f)) *flag = 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers and phase builders
+// ---------------------------------------------------------------------------
+
+unsigned phase_tiles(const Phase &p) {
+    auto cdiv = [](size_t a, size_t b) { return (unsigned)((a + b - 1) / b); };
+    const int N = [&] {
+        switch (p.kind) {
+            case PH_TRANSPOSE: return p.a.tr.N;
+            case PH_SEED: return p.a.seed.N;
+            case PH_UP: return p.a.up.N;
+            case PH_DOWN: return p.a.down.N;
+            case PH_FRAME_SUM: return p.a.fs.N;
+            case PH_GATHER_ADJ: return p.a.ga.N;
+            case PH_DOWN_ADJ: return p.a.da.N;
+            case PH_DT: return p.a.dt.N;
+            case PH_SEED_ADJ: return p.a.sa.N;
+        }
+        return 0;
+    }();
+    const size_t S = size_t(1) << N, SS = S * S;
+    const unsigned t32 = (unsigned)((S + 31) / 32);
+    const size_t per = (size_t)256 * (p.U > 0 ? p.U : 1);
+    switch (p.kind) {
+        case PH_TRANSPOSE: return t32 * t32;
+        case PH_FRAME_SUM: return t32 * t32;
+        case PH_GATHER_ADJ: return 4 * t32 * t32;
+        case PH_SEED: return cdiv(4 * (19 * S / 4) * S, per);
+        case PH_UP: return cdiv(4 * t_level_entries(N, p.a.up.n), per);
+        case PH_DT: return cdiv(4 * t_level_entries(N, p.a.dt.n), per);
+        case PH_DOWN:
+        case PH_DOWN_ADJ:
+        case PH_SEED_ADJ: return cdiv(4 * SS, per);
+    }
+    return 0;
+}
+
+hipError_t upload_cone_table(const float *host_table) {
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_cone), host_table, sizeof(float) * kConeTable);
+}
+
+hipError_t launch_phase(const Phase &p, hipStream_t s) {
+    unsigned tiles = phase_tiles(p);
+    if (tiles == 0) return hipSuccess;
+    void (*k)(Phase) = nullptr;
+    switch (p.kind) {
+        case PH_TRANSPOSE: k = hrc_transpose; break;
+        case PH_SEED: k = hrc_seed; break;
+        case PH_UP: k = hrc_merge_up; break;
+        case PH_DOWN: k = hrc_merge_down; break;
+        case PH_FRAME_SUM: k = hrc_frame_sum; break;
+        case PH_GATHER_ADJ: k = hrc_gather_adj; break;
+        case PH_DOWN_ADJ: k = hrc_merge_down_adj; break;
+        case PH_DT: k = hrc_interval_adj; break;
+        case PH_SEED_ADJ: k = hrc_seed_adj; break;
+        default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k, dim3(tiles), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_persistent(const Phase *phases, const unsigned *seg_start,
+                             const int *seg_phase, int nseg, unsigned total_items,
+                             unsigned *counter, unsigned *done, unsigned nphases, int grid,
+                             hipStream_t s) {
+    unsigned n = nphases + 2;  // counter, done[nphases], error word: contiguous
+    hipLaunchKernelGGL(hrc_clear_u32, dim3((n + 255) / 256), dim3(256), 0, s, counter, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(hrc_persistent, dim3(grid), dim3(256), 0, s, phases, seg_start, seg_phase,
+                       nseg, total_items, counter, done, done + nphases);
+    return hipGetLastError();
+}
+
+hipError_t persistent_occupancy(int *blocks_per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, hrc_persistent, 256, 0);
+}
+
+hipError_t launch_validate(const float *a, const float *b, size_t n, int *flag,
+                           hipStream_t s) {
+    unsigned blocks = (unsigned)((n + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(hrc_validate, dim3(blocks), dim3(256), 0, s, a, b, n, flag);
+    return hipGetLastError();
+}
+
+}  // namespace hrc

@@ -1,0 +1,222 @@
+"""Python binding of the C ABI: torch tensors in, device pointers and the
+current HIP stream out.  Marshalling only; every step runs in libhrc.so.
+
+Functions named like the C entry points (``hrc_forward``, ``hrc_backward``,
+``hrc_batch_plan`` ...) take torch tensors; ``fluence`` adds autograd.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib
+from ._lib import check, hrc_scene
+
+
+def _log2_size(t: torch.Tensor) -> int:
+    if t.dim() != 2 or t.shape[0] != t.shape[1]:
+        raise ValueError("expected a square [S, S] tensor")
+    S = t.shape[0]
+    N = S.bit_length() - 1
+    if S != 1 << N:
+        raise ValueError("grid side must be a power of two")
+    return N
+
+
+def _check_field(t: torch.Tensor, name: str) -> None:
+    if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+
+
+def _stream_handle(device: torch.device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def hrc_workspace_bytes(log2_size: int, flags: int = 0) -> Tuple[int, int]:
+    """(forward, backward) workspace bytes; a pure host query."""
+    f = ctypes.c_size_t(0)
+    b = ctypes.c_size_t(0)
+    check(_lib.load().hrc_workspace_bytes(log2_size, flags, ctypes.byref(f), ctypes.byref(b)),
+          "hrc_workspace_bytes")
+    return f.value, b.value
+
+
+class Context:
+    """An ``hrc_context`` on one device plus cached workspaces per grid size."""
+
+    def __init__(self, device: Optional[int] = None):
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        self._ptr = ctypes.c_void_p(0)
+        check(_lib.load().hrc_create(self.device, ctypes.byref(self._ptr)), "hrc_create")
+        self._ws: Dict[Tuple[int, bool], torch.Tensor] = {}
+
+    def __del__(self):
+        ptr = getattr(self, "_ptr", None)
+        if ptr is not None and ptr.value:
+            try:
+                _lib.load().hrc_destroy(ptr)
+            except Exception:
+                pass
+            self._ptr = ctypes.c_void_p(0)
+
+    def workspace(self, N: int, backward: bool) -> torch.Tensor:
+        key = (N, backward)
+        ws = self._ws.get(key)
+        if ws is None:
+            f, b = hrc_workspace_bytes(N)
+            ws = torch.empty(b if backward else f, dtype=torch.uint8,
+                             device=torch.device("cuda", self.device))
+            self._ws[key] = ws
+        return ws
+
+    def release_workspaces(self) -> None:
+        self._ws.clear()
+
+    # -- entry points --------------------------------------------------------
+    def hrc_forward(self, emission: torch.Tensor, sigma_t: torch.Tensor,
+                    out: Optional[torch.Tensor] = None, flags: int = 0) -> torch.Tensor:
+        _check_field(emission, "emission")
+        _check_field(sigma_t, "sigma_t")
+        N = _log2_size(emission)
+        if sigma_t.shape != emission.shape:
+            raise ValueError("emission and sigma_t shapes differ")
+        if out is None:
+            out = torch.empty_like(emission)
+        ws = self.workspace(N, False)
+        check(_lib.load().hrc_forward(self._ptr, N, emission.data_ptr(), sigma_t.data_ptr(),
+                                      out.data_ptr(), ws.data_ptr(), ws.numel(),
+                                      _stream_handle(emission.device), flags), "hrc_forward")
+        return out
+
+    def hrc_backward(self, emission: torch.Tensor, sigma_t: torch.Tensor,
+                     grad_fluence: torch.Tensor, flags: int = 0):
+        for t, n in ((emission, "emission"), (sigma_t, "sigma_t"), (grad_fluence, "grad_fluence")):
+            _check_field(t, n)
+        N = _log2_size(emission)
+        ge = torch.empty_like(emission)
+        gs = torch.empty_like(emission)
+        ws = self.workspace(N, True)
+        check(_lib.load().hrc_backward(self._ptr, N, emission.data_ptr(), sigma_t.data_ptr(),
+                                       grad_fluence.data_ptr(), ge.data_ptr(), gs.data_ptr(),
+                                       ws.data_ptr(), ws.numel(),
+                                       _stream_handle(emission.device), flags), "hrc_backward")
+        return ge, gs
+
+
+    def hrc_profile_solve(self, emission: torch.Tensor, sigma_t: torch.Tensor,
+                          grad_fluence: Optional[torch.Tensor] = None):
+        """One forward (or, with grad_fluence, one backward) with a HIP event
+        around every pass; returns [(pass name, level, milliseconds)]."""
+        _check_field(emission, "emission")
+        _check_field(sigma_t, "sigma_t")
+        N = _log2_size(emission)
+        bwd = grad_fluence is not None
+        ws = self.workspace(N, bwd)
+        F = torch.empty_like(emission)
+        ge = torch.empty_like(emission) if bwd else None
+        gs = torch.empty_like(emission) if bwd else None
+        cap = 128
+        ms = (ctypes.c_float * cap)()
+        kind = (ctypes.c_int * cap)()
+        lvl = (ctypes.c_int * cap)()
+        count = ctypes.c_int(0)
+        check(_lib.load().hrc_profile_solve(
+            self._ptr, N, emission.data_ptr(), sigma_t.data_ptr(), F.data_ptr(),
+            grad_fluence.data_ptr() if bwd else None, ge.data_ptr() if bwd else None,
+            gs.data_ptr() if bwd else None, ws.data_ptr(), ws.numel(),
+            _stream_handle(emission.device), ms, kind, lvl, cap, ctypes.byref(count)),
+            "hrc_profile_solve")
+        return [(_lib.PASS_NAMES[kind[i]], lvl[i], ms[i]) for i in range(min(count.value, cap))]
+
+
+_contexts: Dict[int, Context] = {}
+
+
+def default_context(device: Optional[int] = None) -> Context:
+    if device is None:
+        device = torch.cuda.current_device()
+    ctx = _contexts.get(device)
+    if ctx is None:
+        ctx = Context(device)
+        _contexts[device] = ctx
+    return ctx
+
+
+class HRCFunction(torch.autograd.Function):
+    """F = HRC(emission, sigma_t) with the hand-written adjoint as backward.
+    Nothing but the inputs is saved: the backward recomputes the forward
+    intervals and cascades inside ``hrc_backward``."""
+
+    @staticmethod
+    def forward(ctx, emission, sigma_t):
+        emission = emission.contiguous()
+        sigma_t = sigma_t.contiguous()
+        c = default_context(emission.device.index)
+        F = c.hrc_forward(emission, sigma_t)
+        ctx.save_for_backward(emission, sigma_t)
+        return F
+
+    @staticmethod
+    def backward(ctx, grad_F):
+        emission, sigma_t = ctx.saved_tensors
+        c = default_context(emission.device.index)
+        ge, gs = c.hrc_backward(emission, sigma_t, grad_F.contiguous())
+        return ge, gs
+
+
+def fluence(emission: torch.Tensor, sigma_t: torch.Tensor) -> torch.Tensor:
+    """Per-pixel fluence of a square power-of-two scene (differentiable)."""
+    return HRCFunction.apply(emission, sigma_t)
+
+
+class Batch:
+    """A planned batch (``hrc_batch_plan``): one persistent-kernel graph launch
+    computes every scene's fluence and, where a grad_fluence is given, its
+    gradients.  The tensors passed in are the ones every launch reads/writes."""
+
+    def __init__(self, scenes: Sequence[dict], context: Optional[Context] = None):
+        self.ctx = context or default_context()
+        self.scenes = list(scenes)
+        arr = (hrc_scene * len(self.scenes))()
+        for i, sc in enumerate(self.scenes):
+            e, s, F = sc["emission"], sc["sigma_t"], sc["fluence"]
+            for t, n in ((e, "emission"), (s, "sigma_t"), (F, "fluence")):
+                _check_field(t, n)
+            arr[i].log2_size = _log2_size(e)
+            arr[i].emission = e.data_ptr()
+            arr[i].sigma_t = s.data_ptr()
+            arr[i].fluence = F.data_ptr()
+            if sc.get("grad_fluence") is not None:
+                for n in ("grad_fluence", "grad_emission", "grad_sigma_t"):
+                    _check_field(sc[n], n)
+                arr[i].grad_fluence = sc["grad_fluence"].data_ptr()
+                arr[i].grad_emission = sc["grad_emission"].data_ptr()
+                arr[i].grad_sigma_t = sc["grad_sigma_t"].data_ptr()
+        self._ptr = ctypes.c_void_p(0)
+        dev = self.scenes[0]["emission"].device
+        check(_lib.load().hrc_batch_plan(self.ctx._ptr, arr, len(self.scenes), 0,
+                                         _stream_handle(dev), ctypes.byref(self._ptr)),
+              "hrc_batch_plan")
+        self._device = dev
+
+    def launch(self) -> None:
+        check(_lib.load().hrc_batch_launch(self._ptr, _stream_handle(self._device)),
+              "hrc_batch_launch")
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(_lib.load().hrc_batch_workspace_bytes(self._ptr))
+
+    def __del__(self):
+        ptr = getattr(self, "_ptr", None)
+        if ptr is not None and ptr.value:
+            try:
+                _lib.load().hrc_batch_destroy(ptr)
+            except Exception:
+                pass
+            self._ptr = ctypes.c_void_p(0)

@@ -1,0 +1,126 @@
+"""The C-ABI library on a machine without a GPU: it loads, exports every
+function include/hrc.h declares, and rejects bad arguments on the host before
+any device call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2505_02041_amd import _lib
+from paper_2505_02041_amd._lib import (HRC_ERR_INVALID_ARG, HRC_ERR_SHAPE, HRC_ERR_UNSUPPORTED,
+                                       HRC_ERR_WORKSPACE, HRC_OK)
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hrc.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(_lib.LIB_PATH),
+                                reason="libhrc.so not built (run __graft_entry__.build())")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hrc_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_names():
+    assert declared_functions() == sorted(_lib.SIGNATURES)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    lib = _lib.load()
+    for s in range(-6, 1):
+        assert lib.hrc_status_string(s).decode().startswith("HRC")
+    assert b"unknown" in lib.hrc_status_string(-99)
+
+
+def _ws(N):
+    f = ctypes.c_size_t(0)
+    b = ctypes.c_size_t(0)
+    st = _lib.load().hrc_workspace_bytes(N, 0, ctypes.byref(f), ctypes.byref(b))
+    return st, f.value, b.value
+
+
+@pytest.mark.parametrize("N", [3, 6, 10, 12])
+def test_workspace_sizes_follow_the_memory_analysis(N):
+    """Section 4.3.2: the pyramid holds (N + 3 - 2^-N) S^2 interval entries per
+    quadrant; the forward workspace is four quadrants of it (8 bytes per entry)
+    plus two cascade levels and the transposed inputs, up to alignment."""
+    st, f, b = _ws(N)
+    assert st == HRC_OK
+    S = 1 << N
+    pyramid = 4 * 8 * sum((S >> n) * (2 ** n + 1) * S for n in range(N + 1))
+    assert pyramid == pytest.approx(4 * 8 * (N + 3 - 2.0 ** -N) * S * S)
+    fwd_min = pyramid + 2 * 4 * 4 * S * S + 2 * 4 * S * S
+    assert fwd_min <= f <= fwd_min + 256 * (2 * N + 8)
+    bwd_min = 2 * pyramid + 2 * N * 4 * 4 * S * S + 2 * 4 * S * S + 2 * 4 * 4 * S * S
+    assert bwd_min <= b <= bwd_min + 256 * (4 * N + 10)
+
+
+@pytest.mark.parametrize("N", [0, 2, 13, -1])
+def test_bad_sizes_are_rejected(N):
+    assert _ws(N)[0] == HRC_ERR_SHAPE
+    lib = _lib.load()
+    buf = (ctypes.c_float * 64)()
+    p = ctypes.addressof(buf)
+    assert lib.hrc_forward(None, N, p, p, p, p, 1 << 40, None, 0) == HRC_ERR_SHAPE
+
+
+def test_unknown_flags_are_rejected():
+    lib = _lib.load()
+    f = ctypes.c_size_t(0)
+    assert lib.hrc_workspace_bytes(5, 0x80, ctypes.byref(f), None) == HRC_ERR_UNSUPPORTED
+
+
+def test_argument_checks_run_before_any_device_call():
+    """Host pointers stand in for device pointers: every check below fails
+    before the library touches the (absent) GPU."""
+    lib = _lib.load()
+    buf = (ctypes.c_float * 1024)()
+    p = ctypes.addressof(buf)
+    assert p % 16 == 0
+    st, f, b = _ws(5)
+    # NULL and misaligned pointers
+    assert lib.hrc_forward(None, 5, None, p, p, p, f, None, 0) == HRC_ERR_INVALID_ARG
+    assert lib.hrc_forward(None, 5, p + 4, p, p, p, f, None, 0) == HRC_ERR_INVALID_ARG
+    assert lib.hrc_backward(None, 5, p, p, p, p, None, p, b, None, 0) == HRC_ERR_INVALID_ARG
+    # workspace too small
+    assert lib.hrc_forward(None, 5, p, p, p, p, f - 1, None, 0) == HRC_ERR_WORKSPACE
+    assert lib.hrc_backward(None, 5, p, p, p, p, p, p, b - 1, None, 0) == HRC_ERR_WORKSPACE
+    # forward workspace is not enough for the backward
+    assert lib.hrc_backward(None, 5, p, p, p, p, p, p, f, None, 0) == HRC_ERR_WORKSPACE
+    # everything valid but no context
+    assert lib.hrc_forward(None, 5, p, p, p, p, f, None, 0) == HRC_ERR_INVALID_ARG
+    assert lib.hrc_backward(None, 5, p, p, p, p, p, p, b, None, 0) == HRC_ERR_INVALID_ARG
+    # unknown flags
+    assert lib.hrc_forward(None, 5, p, p, p, p, f, None, 0x10) == HRC_ERR_UNSUPPORTED
+
+
+def test_batch_argument_checks():
+    lib = _lib.load()
+    out = ctypes.c_void_p(0)
+    assert lib.hrc_batch_plan(None, None, 0, 0, None, ctypes.byref(out)) == HRC_ERR_INVALID_ARG
+    assert lib.hrc_batch_plan(None, None, 1, 0, None, None) == HRC_ERR_INVALID_ARG
+    buf = (ctypes.c_float * 64)()
+    p = ctypes.addressof(buf)
+    sc = (_lib.hrc_scene * 1)()
+    sc[0].log2_size = 2
+    sc[0].emission = sc[0].sigma_t = sc[0].fluence = p
+    assert lib.hrc_batch_plan(None, sc, 1, 0, None, ctypes.byref(out)) == HRC_ERR_SHAPE
+    sc[0].log2_size = 5
+    sc[0].grad_fluence = p  # partial gradient set
+    assert lib.hrc_batch_plan(None, sc, 1, 0, None, ctypes.byref(out)) == HRC_ERR_INVALID_ARG
+    sc[0].grad_fluence = None
+    assert lib.hrc_batch_plan(None, sc, 1, 0, None, ctypes.byref(out)) == HRC_ERR_INVALID_ARG
+    assert out.value is None
+    assert lib.hrc_batch_launch(None, None) == HRC_ERR_INVALID_ARG
+    assert lib.hrc_batch_workspace_bytes(None) == 0
+    lib.hrc_batch_destroy(None)
+    lib.hrc_destroy(None)

@@ -1,0 +1,175 @@
+"""GPU parity of the reverse pass (hrc_backward through the C ABI): against the
+oracle's reverse pass element by element, against FP64 central differences of
+the oracle's forward pass, and through torch.autograd."""
+import os
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import hrc as oracle
+from oracle import hrc_vjp
+from scenes import config1, config4
+
+pytestmark = pytest.mark.gpu
+
+from gpu_common import assert_grad_close, log, to_dev  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2505_02041_amd import Context
+    return Context(0)
+
+
+def _random_scene(S, seed):
+    rng = np.random.default_rng(seed)
+    eps = (rng.uniform(0, 3, (S, S)) * (rng.random((S, S)) < 0.3)).astype(np.float32)
+    sig = rng.uniform(0, 1.5, (S, S)).astype(np.float32)
+    dF = rng.normal(size=(S, S)).astype(np.float32)
+    return eps, sig, dF
+
+
+def _bwd(ctx, eps, sig, dF):
+    ge, gs = ctx.hrc_backward(to_dev(eps), to_dev(sig), to_dev(dF))
+    torch.cuda.synchronize()
+    return ge.cpu().numpy(), gs.cpu().numpy()
+
+
+@pytest.mark.parametrize("S", [8, 16, 32, 64, 128])
+def test_backward_matches_oracle_reverse(ctx, S):
+    log(f"backward random S={S}")
+    eps, sig, dF = _random_scene(S, 200 + S)
+    ge, gs = _bwd(ctx, eps, sig, dF)
+    re, rs = hrc_vjp.fluence_vjp(eps, sig, dF)
+    assert_grad_close(ge, re, f"d eps S={S}")
+    assert_grad_close(gs, rs, f"d sigma S={S}")
+
+
+def test_backward_config1(ctx):
+    sc = config1()
+    dF = np.random.default_rng(1).random((64, 64)).astype(np.float32)
+    ge, gs = _bwd(ctx, sc.eps, sc.sigma, dF)
+    re, rs = hrc_vjp.fluence_vjp(sc.eps, sc.sigma, dF)
+    assert_grad_close(ge, re, "d eps 64")
+    assert_grad_close(gs, rs, "d sigma 64")
+
+
+def _mse_target():
+    hidden = config4()
+    return oracle.fluence(hidden.eps, hidden.sigma)
+
+
+def _start_scene():
+    S = 256
+    rng = np.random.default_rng(44)
+    eps = rng.uniform(0.05, 2.0, (S, S)).astype(np.float32) * (rng.random((S, S)) < 0.1)
+    sig = rng.uniform(0.0, 1.0, (S, S)).astype(np.float32)
+    return eps, sig
+
+
+def test_backward_config4_matches_oracle_reverse(ctx):
+    """256x256 differentiable workload: Loss = mean((F - F_target)^2)."""
+    log("backward 256x256 vs oracle reverse")
+    Ft = _mse_target()
+    eps, sig = _start_scene()
+    F = oracle.fluence(eps, sig)
+    dF = (2 * (F - Ft) / F.size).astype(np.float32)
+    ge, gs = _bwd(ctx, eps, sig, dF)
+    re, rs = hrc_vjp.fluence_vjp(eps, sig, dF)
+    assert_grad_close(ge, re, "d eps 256")
+    assert_grad_close(gs, rs, "d sigma 256")
+
+
+_FD = {}
+
+
+def _fd_one(args):
+    field, r, c = args
+    eps, sig, Ft = _FD["eps"], _FD["sig"], _FD["Ft"]
+    x = [eps.astype(np.float64).copy(), sig.astype(np.float64).copy()]
+    h = 1e-4 * max(1.0, abs(x[field][r, c]))
+    x[field][r, c] += h
+    lp = np.mean((oracle.fluence(*x) - Ft) ** 2)
+    x[field][r, c] -= 2 * h
+    lm = np.mean((oracle.fluence(*x) - Ft) ** 2)
+    return (lp - lm) / (2 * h)
+
+
+def test_backward_config4_central_differences(ctx):
+    """dLoss/d eps and dLoss/d sigma from the HIP adjoint against FP64 central
+    differences of the oracle's forward pass at 64 seeded pixels (seed 40)."""
+    log("backward 256x256 vs central differences")
+    Ft = _mse_target()
+    eps, sig = _start_scene()
+    e_t, s_t = to_dev(eps).requires_grad_(), to_dev(sig).requires_grad_()
+    from paper_2505_02041_amd import fluence
+    F = fluence(e_t, s_t)
+    loss = torch.mean((F.double() - torch.from_numpy(Ft).cuda()) ** 2)
+    loss.backward()
+    ge, gs = e_t.grad.cpu().numpy(), s_t.grad.cpu().numpy()
+    pix = np.random.default_rng(40).integers(0, 256, (64, 2))
+    _FD.update(eps=eps, sig=sig, Ft=Ft)
+    jobs = [(f, int(r), int(c)) for r, c in pix for f in (0, 1)]
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        fds = list(ex.map(_fd_one, jobs))
+    gmax_e, gmax_s = np.abs(ge).max(), np.abs(gs).max()
+    for (f, r, c), fd in zip(jobs, fds):
+        g = ge[r, c] if f == 0 else gs[r, c]
+        scale = gmax_e if f == 0 else gmax_s
+        assert abs(g - fd) <= 1e-3 * abs(fd) + 1e-4 * scale, (f, r, c, g, fd)
+
+
+def test_autograd_function_matches_direct_calls(ctx):
+    from paper_2505_02041_amd import fluence
+    eps, sig, dF = _random_scene(64, 7)
+    e_t, s_t = to_dev(eps).requires_grad_(), to_dev(sig).requires_grad_()
+    F = fluence(e_t, s_t)
+    F.backward(to_dev(dF))
+    F2 = ctx.hrc_forward(to_dev(eps), to_dev(sig))
+    ge, gs = ctx.hrc_backward(to_dev(eps), to_dev(sig), to_dev(dF))
+    assert torch.equal(F.detach(), F2)
+    assert torch.equal(e_t.grad, ge) and torch.equal(s_t.grad, gs)
+
+
+def test_backward_signs(ctx):
+    """With dF >= 0 the emission gradient is >= 0 and the attenuation gradient
+    is <= 0 (every term of F grows with emission and shrinks with attenuation)."""
+    sc = config1()
+    dF = np.random.default_rng(3).random((64, 64)).astype(np.float32)
+    ge, gs = _bwd(ctx, sc.eps, sc.sigma, dF)
+    assert (ge >= 0).all() and (gs <= 0).all()
+
+
+def test_backward_is_deterministic(ctx):
+    eps, sig, dF = _random_scene(128, 8)
+    a = _bwd(ctx, eps, sig, dF)
+    b = _bwd(ctx, eps, sig, dF)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_adam_recovers_scene(ctx):
+    """200 Adam steps on softplus-parameterised emission and attenuation from a
+    uniform start (0.1, 0.1) reduce the MSE to the hidden scene's fluence by two
+    orders of magnitude (the fields themselves are not identifiable)."""
+    log("adam 200 steps 256x256")
+    from paper_2505_02041_amd import fluence
+    hidden = config4()
+    with torch.no_grad():
+        Ft = fluence(to_dev(hidden.eps), to_dev(hidden.sigma))
+    inv = float(np.log(np.expm1(0.1)))
+    pe = torch.full((256, 256), inv, device="cuda", requires_grad=True)
+    ps = torch.full((256, 256), inv, device="cuda", requires_grad=True)
+    opt = torch.optim.Adam([pe, ps], lr=0.05)
+    losses = []
+    for _ in range(200):
+        opt.zero_grad()
+        F = fluence(torch.nn.functional.softplus(pe), torch.nn.functional.softplus(ps))
+        loss = torch.mean((F - Ft) ** 2)
+        loss.backward()
+        opt.step()
+        losses.append(float(loss))
+    log(f"adam loss {losses[0]:.4g} -> {losses[-1]:.4g}")
+    assert losses[-1] < 1e-2 * losses[0]

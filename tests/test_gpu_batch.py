@@ -1,0 +1,74 @@
+"""The batched persistent launch: bitwise equal to single-scene calls, replayed
+several times, with mixed sizes and forward-only scenes."""
+import numpy as np
+import pytest
+import torch
+
+from scenes import config5, scene_like_512
+
+pytestmark = pytest.mark.gpu
+
+from gpu_common import log, to_dev  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2505_02041_amd import Context
+    return Context(0)
+
+
+def _make(scenes, with_grad):
+    out = []
+    for i, sc in enumerate(scenes):
+        S = sc.eps.shape[0]
+        d = {"emission": to_dev(sc.eps), "sigma_t": to_dev(sc.sigma),
+             "fluence": torch.full((S, S), float("nan"), device="cuda")}
+        if with_grad(i):
+            rng = np.random.default_rng(900 + i)
+            d["grad_fluence"] = to_dev(rng.normal(size=(S, S)))
+            d["grad_emission"] = torch.full((S, S), float("nan"), device="cuda")
+            d["grad_sigma_t"] = torch.full((S, S), float("nan"), device="cuda")
+        out.append(d)
+    return out
+
+
+def _check_against_single(ctx, items):
+    for i, d in enumerate(items):
+        F = ctx.hrc_forward(d["emission"], d["sigma_t"])
+        assert torch.equal(F, d["fluence"]), f"scene {i} fluence"
+        if "grad_fluence" in d:
+            ge, gs = ctx.hrc_backward(d["emission"], d["sigma_t"], d["grad_fluence"])
+            assert torch.equal(ge, d["grad_emission"]), f"scene {i} d eps"
+            assert torch.equal(gs, d["grad_sigma_t"]), f"scene {i} d sigma"
+
+
+def test_batch_small_mixed_sizes(ctx):
+    from paper_2505_02041_amd import Batch
+    log("batch small mixed")
+    scenes = [scene_like_512(S, 70 + i, 3, 4) for i, S in enumerate([8, 64, 32, 128, 16, 256])]
+    items = _make(scenes, lambda i: i % 2 == 0)
+    b = Batch(items, ctx)
+    for rep in range(3):
+        for d in items:
+            d["fluence"].fill_(float("nan"))
+            if "grad_fluence" in d:
+                d["grad_emission"].fill_(float("nan"))
+                d["grad_sigma_t"].fill_(float("nan"))
+        b.launch()
+        torch.cuda.synchronize()
+        _check_against_single(ctx, items)
+    del b
+
+
+def test_batch_benchmark_workload_subset(ctx):
+    """16 scenes of the 64-scene batch workload (sizes 128..1024), fwd + bwd."""
+    from paper_2505_02041_amd import Batch
+    log("batch 16 scenes of the batch workload")
+    scenes = config5()[:16]
+    items = _make(scenes, lambda i: True)
+    b = Batch(items, ctx)
+    b.launch()
+    torch.cuda.synchronize()
+    _check_against_single(ctx, items)
+    ctx.release_workspaces()
+    del b

@@ -1,0 +1,128 @@
+"""GPU parity of the forward pass (hrc_forward through the C ABI) against the
+FP64 oracle, element by element."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import hrc as oracle
+from scenes import config1, config2, config3
+
+pytestmark = pytest.mark.gpu
+
+from gpu_common import assert_forward_close, log, to_dev  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2505_02041_amd import Context
+    return Context(0)
+
+
+def _random_scene(S, seed, density=0.2, sig_hi=2.0):
+    rng = np.random.default_rng(seed)
+    eps = (rng.uniform(0, 3, (S, S)) * (rng.random((S, S)) < density)).astype(np.float32)
+    sig = rng.uniform(0, sig_hi, (S, S)).astype(np.float32)
+    return eps, sig
+
+
+def _run(ctx, eps, sig):
+    F = ctx.hrc_forward(to_dev(eps), to_dev(sig))
+    torch.cuda.synchronize()
+    return F.cpu().numpy()
+
+
+@pytest.mark.parametrize("S", [8, 16, 32, 64, 128, 256])
+def test_forward_random_scenes(ctx, S):
+    """Several tiles and ragged small grids (S < 256 does not fill a block)."""
+    log(f"forward random S={S}")
+    eps, sig = _random_scene(S, 100 + S)
+    assert_forward_close(_run(ctx, eps, sig), oracle.fluence(eps, sig), f"S={S}")
+
+
+def test_forward_config1_64(ctx):
+    log("forward 64x64 disks3_boxes4")
+    sc = config1()
+    assert_forward_close(_run(ctx, sc.eps, sc.sigma), oracle.fluence(sc.eps, sc.sigma), "64")
+
+
+def test_forward_config2_512(ctx):
+    log("forward 512x512 disks32_boxes64_fog")
+    sc = config2()
+    assert_forward_close(_run(ctx, sc.eps, sc.sigma), oracle.fluence(sc.eps, sc.sigma), "512")
+
+
+def test_forward_config3_1024(ctx):
+    """The full 1024x1024 workload of the benchmark, every pixel."""
+    log("forward 1024x1024 disks128_boxes256_lines32_fog")
+    sc = config3()
+    assert_forward_close(_run(ctx, sc.eps, sc.sigma), oracle.fluence(sc.eps, sc.sigma), "1024")
+
+
+def test_forward_zero_emission_is_exactly_zero(ctx):
+    eps, sig = _random_scene(128, 5)
+    F = _run(ctx, np.zeros_like(eps), sig)
+    assert np.all(F == 0.0)
+
+
+def test_forward_vacuum_and_opaque(ctx):
+    """sigma = 0 everywhere (all transmittances 1) and sigma = 1e4 everywhere
+    (every interval opaque: only the first pixel of each trace counts)."""
+    eps, _ = _random_scene(64, 6, density=0.5)
+    for sig_val in (0.0, 1e4):
+        sig = np.full_like(eps, sig_val)
+        assert_forward_close(_run(ctx, eps, sig), oracle.fluence(eps, sig), f"sig={sig_val}")
+
+
+def test_forward_kirchhoff_at_max_size(ctx):
+    """4096x4096 (largest supported size): eps = B*sigma with sigma = 5 gives
+    F = 2*pi*B wherever every path is optically thick (>= 8 px from the edges),
+    and F <= 2*pi*B everywhere (exact identity of the method)."""
+    log("forward 4096x4096 Kirchhoff")
+    S, B = 4096, 1.7
+    sig = torch.full((S, S), 5.0, device="cuda")
+    F = ctx.hrc_forward(sig * B, sig)
+    torch.cuda.synchronize()
+    inner = F[8:-8, 8:-8]
+    assert torch.allclose(inner, torch.full_like(inner, 2 * math.pi * B), rtol=1e-5, atol=0)
+    assert float(F.max()) <= 2 * math.pi * B * (1 + 1e-5)
+    ctx.release_workspaces()
+
+
+def test_forward_max_size_transpose_symmetry(ctx):
+    """4096x4096: transposing the scene transposes the fluence (the four
+    quadrant solves map onto each other); values agree to FP32 rounding."""
+    log("forward 4096x4096 transpose symmetry")
+    S = 4096
+    g = torch.Generator(device="cuda").manual_seed(3)
+    eps = (torch.rand((S, S), device="cuda", generator=g) < 0.01).float() * 5
+    sig = torch.rand((S, S), device="cuda", generator=g) * 0.2
+    F = ctx.hrc_forward(eps, sig)
+    Ft = ctx.hrc_forward(eps.t().contiguous(), sig.t().contiguous())
+    torch.cuda.synchronize()
+    assert torch.allclose(Ft, F.t(), rtol=1e-5, atol=1e-6 * float(F.max()))
+    ctx.release_workspaces()
+
+
+def test_forward_is_deterministic(ctx):
+    sc = config2()
+    a = _run(ctx, sc.eps, sc.sigma)
+    b = _run(ctx, sc.eps, sc.sigma)
+    assert np.array_equal(a, b)
+
+
+def test_validate_flag_rejects_bad_inputs(ctx):
+    from paper_2505_02041_amd import HRCError
+    from paper_2505_02041_amd._lib import HRC_ERR_INPUT, HRC_FLAG_VALIDATE
+    eps, sig = _random_scene(32, 9)
+    eps[3, 4] = -1.0
+    with pytest.raises(HRCError) as ei:
+        ctx.hrc_forward(to_dev(eps), to_dev(sig), flags=HRC_FLAG_VALIDATE)
+    assert ei.value.status == HRC_ERR_INPUT
+    eps[3, 4] = 1.0
+    sig[0, 0] = float("nan")
+    with pytest.raises(HRCError):
+        ctx.hrc_forward(to_dev(eps), to_dev(sig), flags=HRC_FLAG_VALIDATE)
+    sig[0, 0] = 0.5
+    ctx.hrc_forward(to_dev(eps), to_dev(sig), flags=HRC_FLAG_VALIDATE)
