@@ -151,9 +151,10 @@ def test_backward_is_deterministic(ctx):
 
 
 def test_adam_recovers_scene(ctx):
-    """200 Adam steps on softplus-parameterised emission and attenuation from a
-    uniform start (0.1, 0.1) reduce the MSE to the hidden scene's fluence by two
-    orders of magnitude (the fields themselves are not identifiable)."""
+    """200 Adam steps (lr 0.3) on softplus-parameterised emission and attenuation
+    from a uniform start (0.1, 0.1) reduce the MSE to the hidden scene's fluence
+    by more than 250x (measured 3782 -> 5.96, i.e. 635x; the fields themselves
+    are not identifiable from the fluence alone)."""
     log("adam 200 steps 256x256")
     from paper_2505_02041_amd import fluence
     hidden = config4()
@@ -162,7 +163,7 @@ def test_adam_recovers_scene(ctx):
     inv = float(np.log(np.expm1(0.1)))
     pe = torch.full((256, 256), inv, device="cuda", requires_grad=True)
     ps = torch.full((256, 256), inv, device="cuda", requires_grad=True)
-    opt = torch.optim.Adam([pe, ps], lr=0.05)
+    opt = torch.optim.Adam([pe, ps], lr=0.3)
     losses = []
     for _ in range(200):
         opt.zero_grad()
@@ -170,6 +171,6 @@ def test_adam_recovers_scene(ctx):
         loss = torch.mean((F - Ft) ** 2)
         loss.backward()
         opt.step()
-        losses.append(float(loss))
+        losses.append(loss.item())
     log(f"adam loss {losses[0]:.4g} -> {losses[-1]:.4g}")
-    assert losses[-1] < 1e-2 * losses[0]
+    assert losses[-1] < 4e-3 * losses[0]
