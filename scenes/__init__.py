@@ -69,13 +69,14 @@ def value_noise(rng: np.random.Generator, S: int, octaves: int = 4) -> np.ndarra
 
 def add_box(rng: np.random.Generator, field: np.ndarray, side_lo: int, side_hi: int,
             value) -> None:
-    """Axis-aligned box with integer corners, sides uniform in {side_lo..side_hi}.
+    """Axis-aligned box with integer corners, sides uniform in {side_lo..side_hi}
+    (clipped to the grid side).
 
     ``value`` is a float, or the string ``"u05"`` for per-pixel U[0,5] values.
     """
     S = field.shape[0]
-    h = int(rng.integers(side_lo, side_hi + 1))
-    w = int(rng.integers(side_lo, side_hi + 1))
+    h = min(int(rng.integers(side_lo, side_hi + 1)), S)
+    w = min(int(rng.integers(side_lo, side_hi + 1)), S)
     r0 = int(rng.integers(0, S - h + 1))
     c0 = int(rng.integers(0, S - w + 1))
     if isinstance(value, str):
@@ -99,12 +100,12 @@ def add_line(rng: np.random.Generator, field: np.ndarray, horizontal: bool,
 
 def add_disk(rng: np.random.Generator, field: np.ndarray, r_lo: float, r_hi: float,
              value: float) -> None:
-    """Disk of radius rho ~ U[r_lo, r_hi], centre uniform in [rho, S-rho]^2.
+    """Disk of radius rho ~ U[r_lo, r_hi] (at most S/4), centre uniform in [rho, S-rho]^2.
 
     Pixel (r, c) is covered iff its centre lies within rho of the disk centre.
     """
     S = field.shape[0]
-    rho = float(rng.uniform(r_lo, r_hi))
+    rho = min(float(rng.uniform(r_lo, r_hi)), S / 4.0)
     cx = float(rng.uniform(rho, S - rho))
     cy = float(rng.uniform(rho, S - rho))
     r = np.arange(S) + 0.5
