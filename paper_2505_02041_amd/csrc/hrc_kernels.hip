@@ -610,7 +610,7 @@ __global__ __launch_bounds__(256) void hrc_gather_adj(Phase p) { body_gather_adj
 // agent-scope acquire, which makes the producer's stores visible across XCDs.
 // ---------------------------------------------------------------------------
 
-constexpr unsigned kMaxSpins = 1u << 24;  // ~2 s of polling at s_sleep(2)
+constexpr unsigned kMaxSpins = 1u << 20;  // about a second of polling
 
 __global__ __launch_bounds__(256) void hrc_persistent(const Phase *__restrict__ phases,
                                                     const unsigned *__restrict__ seg_start,
@@ -619,10 +619,22 @@ __global__ __launch_bounds__(256) void hrc_persistent(const Phase *__restrict__ 
                                                     unsigned *counter, unsigned *done,
                                                     unsigned *error) {
     __shared__ unsigned s_item;
+    int finished = -1;  // phase of the item this block completed last (uniform)
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+        // One thread publishes the previous item and claims the next one.  Both
+        // sit in a single thread-0 region at the top of the loop, followed by
+        // a barrier: with the publish at the end of the loop body instead, the
+        // compiler turns the thread-0 path around the back edge into an early
+        // exit of lane 0 from an inner loop, and the other lanes re-enter the
+        // barriers with a stale item forever.
+        if (threadIdx.x == 0) {
+            if (finished >= 0)
+                __hip_atomic_fetch_add(&done[finished], 1u, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            s_item = atomicAdd(counter, 1u);
+        }
         __syncthreads();
-        const unsigned item = s_item;
+        const unsigned item = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (item >= total_items) break;
         // segment containing the item: seg_start is increasing, seg_start[0] = 0
@@ -632,9 +644,9 @@ __global__ __launch_bounds__(256) void hrc_persistent(const Phase *__restrict__ 
             if (seg_start[mid] <= item) lo = mid;
             else hi = mid - 1;
         }
-        const int pi = seg_phase[lo];
+        const int pi = __builtin_amdgcn_readfirstlane(seg_phase[lo]);
         const Phase &p = phases[pi];
-        const unsigned tile = item - seg_start[lo];
+        const unsigned tile = __builtin_amdgcn_readfirstlane(item - seg_start[lo]);
         if (threadIdx.x == 0 && p.dep >= 0) {
             // Bounded wait: a dependency that never completes (a planning bug)
             // raises the error word and lets the queue drain instead of hanging.
@@ -654,8 +666,7 @@ __global__ __launch_bounds__(256) void hrc_persistent(const Phase *__restrict__ 
         run_phase(p, tile);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
-        if (threadIdx.x == 0)
-            __hip_atomic_fetch_add(&done[pi], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        finished = pi;
     }
 }
 
