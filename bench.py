@@ -30,6 +30,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--only-forward", action="store_true",
+                    help="time the forward only (for profiler runs)")
     return ap.parse_args()
 
 
@@ -77,6 +79,15 @@ def main():
     # ---- forward: the metric ------------------------------------------------
     log(f"forward {S}x{S}: {args.warmup} warm-up, {args.steps} timed steps")
     fwd_s = timed(lambda: ctx.hrc_forward(eps, sig, F), args.steps, args.warmup)
+    # ---- a plain device copy of 512 MB: the achievable-bandwidth reference ---
+    nbytes = 512 << 20
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    copy_s = timed(lambda: dst.copy_(src), 10, 2)
+    del src, dst
+    if args.only_forward:
+        print(json.dumps({"ms_per_step": fwd_s * 1e3, "copy_GBps": 2 * nbytes / copy_s / 1e9}))
+        return
     # ---- forward + backward (the backward recomputes the forward) ------------
     log("forward+backward")
     fb_s = timed(lambda: (ctx.hrc_forward(eps, sig, F), ctx.hrc_backward(eps, sig, dF)),
@@ -120,6 +131,7 @@ def main():
         "fwd_model_GBps": step_bytes / fwd_s / 1e9,
         "fwd_model_frac_of_peak": step_bytes / fwd_s / 1e9 / HBM_PEAK_GBPS,
         "fwd_bwd_model_GBps": (step_bytes + backward_bytes(N)) / fb_s / 1e9,
+        "copy_GBps": 2 * nbytes / copy_s / 1e9,
         "roofline": {
             "bound": "hbm",
             "kernel": _lib.PASS_KERNELS[_lib.PASS_NAMES.index(dom)],

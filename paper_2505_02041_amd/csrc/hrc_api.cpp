@@ -77,12 +77,13 @@ int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, cons
         ++np;
     };
     Phase p;
-    p.kind = PH_TRANSPOSE;
-    p.a.tr = TransposeArgs{b.eps, b.sig, w.epsT(), w.sigT(), N};
-    add(p);
+    if (b.dF) {  // the adjoint of the traced levels reads transposed inputs
+        p.kind = PH_TRANSPOSE;
+        p.a.tr = TransposeArgs{b.eps, b.sig, w.epsT(), w.sigT(), N};
+        add(p);
+    }
     p = Phase();
     p.kind = PH_SEED;
-    p.U = pick_u(U, PH_SEED);
     p.a.seed = SeedArgs{b.eps, b.sig, w.epsT(), w.sigT(), w.T(0), w.T(1), w.T(2),
                         t_level_entries(N, 0), t_level_entries(N, 1), t_level_entries(N, 2), N};
     add(p);

@@ -34,7 +34,9 @@ struct Plan {
 // Elements per thread for a phase so that it splits into at most `target`
 // tiles (tiles of 256*U outputs); fixed-shape phases keep their 32x32 tiles.
 void size_tiles(Phase &p, int target) {
-    if (p.kind == PH_TRANSPOSE || p.kind == PH_FRAME_SUM || p.kind == PH_GATHER_ADJ) return;
+    if (p.kind == PH_TRANSPOSE || p.kind == PH_SEED || p.kind == PH_FRAME_SUM ||
+        p.kind == PH_GATHER_ADJ)
+        return;
     p.U = 1;
     unsigned t1 = phase_tiles(p);
     unsigned U = (t1 + (unsigned)target - 1) / (unsigned)target;

@@ -136,43 +136,103 @@ __device__ void body_transpose(const TransposeArgs &a, unsigned tile) {
     __syncthreads();
 }
 
-// Traced levels T_0, T_1, T_2 (Algorithm 1, first loop).
-__device__ void body_seed(const SeedArgs &a, unsigned tile, int U) {
-    const int N = a.N, S = 1 << N;
-    const unsigned rpq = 19u * (unsigned)S / 4u;  // rows per quadrant: (2 + 1.5 + 1.25) S
-    const size_t total = (size_t)4 * rpq * S;
-    for (int uu = 0; uu < U; ++uu) {
-        const size_t idx = ((size_t)tile * U + uu) * 256 + threadIdx.x;
-        if (idx >= total) return;
-        const int y = (int)(idx & (S - 1));
-        const unsigned row = (unsigned)(idx >> N);
-        const int q = row / rpq;
-        unsigned r = row % rpq;
-        int n, x, k;
-        float2 *out;
-        size_t qoff;
-        if (r < 2u * S) {
-            n = 0; x = r >> 1; k = r & 1; out = a.T0; qoff = a.e0;
-        } else if ((r -= 2u * S) < 3u * S / 2u) {
-            n = 1; x = r / 3; k = r % 3; out = a.T1; qoff = a.e1;
-        } else {
-            r -= 3u * S / 2u;
-            n = 2; x = r / 5; k = r % 5; out = a.T2; qoff = a.e2;
-        }
-        const float *E = frame_src(q, a.eps, a.epsT);
-        const float *G = frame_src(q, a.sig, a.sigT);
-        const int sid = stencil_id(n, k);
-        const int u0 = x << n;
+// Traced levels T_0, T_1, T_2 (Algorithm 1, first loop), for all four
+// quadrants from one 32x32 image tile.
+//
+// A chord of length 2a through a uniform pixel is the merge of two chords of
+// length a through it (Eq. 5-6), and every chord of the traced rays is either
+// 1/2 or 1 (axis rays), sqrt(2)/2 or sqrt(2) (diagonals), sqrt(5)/4 or
+// sqrt(5)/2 (slope 1/2).  So each pixel needs only three intervals, for the
+// half lengths 1/2, sqrt(2)/2 and sqrt(5)/4, and every traced ray is a fold of
+// 2^(n+1) half pieces.  The block computes the three intervals of its tile
+// plus a 4-pixel halo once into LDS (out-of-grid pixels are vacuum <0, 1>)
+// and then folds the 4 x 4864 rays whose probes lie in the tile; each wave
+// writes two rows of 32 consecutive y of one direction.
+constexpr int kSeedTile = 32, kSeedHalo = 4;
+constexpr int kSeedSpan = kSeedTile + 2 * kSeedHalo;  // 40
+constexpr int kSeedPitch = kSeedSpan + 1;             // padded row pitch of the LDS tile
+
+// Half pieces of the traced rays: (du, dw) from the probe's pixel and the
+// half-length id (0: 1/2, 1: sqrt(2)/2, 2: sqrt(5)/4), in order from the probe.
+// Stencil id: n = 0 -> k, n = 1 -> 2 + k, n = 2 -> 5 + k; 2^(n+1) pieces each.
+__constant__ signed char c_hp_du[10][8] = {
+    {0, 1}, {0, 1},
+    {0, 1, 1, 2}, {0, 1, 1, 2}, {0, 1, 1, 2},
+    {0, 1, 1, 2, 2, 3, 3, 4}, {0, 1, 1, 2, 2, 3, 3, 4}, {0, 1, 1, 2, 2, 3, 3, 4},
+    {0, 1, 1, 2, 2, 3, 3, 4}, {0, 1, 1, 2, 2, 3, 3, 4}};
+__constant__ signed char c_hp_dw[10][8] = {
+    {0, -1}, {0, 1},
+    {0, -1, -1, -2}, {0, 0, 0, 0}, {0, 1, 1, 2},
+    {0, -1, -1, -2, -2, -3, -3, -4}, {0, 0, -1, -1, -1, -1, -2, -2},
+    {0, 0, 0, 0, 0, 0, 0, 0}, {0, 0, 1, 1, 1, 1, 2, 2}, {0, 1, 1, 2, 2, 3, 3, 4}};
+__constant__ unsigned char c_hp_len[10][8] = {
+    {1, 1}, {1, 1},
+    {1, 1, 1, 1}, {0, 0, 0, 0}, {1, 1, 1, 1},
+    {1, 1, 1, 1, 1, 1, 1, 1}, {2, 2, 2, 2, 2, 2, 2, 2}, {0, 0, 0, 0, 0, 0, 0, 0},
+    {2, 2, 2, 2, 2, 2, 2, 2}, {1, 1, 1, 1, 1, 1, 1, 1}};
+
+// Rays of traced level n of quadrant q whose probes lie in the tile.  Rows
+// (k, xl) run with xl fastest, so the two 32-lane halves of a wave share the
+// direction k and the stencil lookups are wave-uniform.
+template <int n>
+__device__ __forceinline__ void seed_level_rays(const float2 *iv, const SeedArgs &a, int q,
+                                                int r0, int c0) {
+    constexpr int dirs = (1 << n) + 1, cols = kSeedTile >> n, pieces = 2 << n;
+    const int S = 1 << a.N;
+    float2 *out = n == 0 ? a.T0 : n == 1 ? a.T1 : a.T2;
+    const size_t qoff = n == 0 ? a.e0 : n == 1 ? a.e1 : a.e2;
+    // frame of quadrant q: +x (u, w) = (c, r); -x (S-1-c, r); +y (r, c); -y (S-1-r, c)
+    const int u_lo = q == 0 ? c0 : q == 1 ? S - kSeedTile - c0 : q == 2 ? r0 : S - kSeedTile - r0;
+    const int w_lo = q < 2 ? r0 : c0;
+    const int su = q == 0 ? 1 : q == 1 ? -1 : q == 2 ? kSeedPitch : -kSeedPitch;
+    const int sw = q < 2 ? kSeedPitch : 1;
+    for (int it = threadIdx.x; it < dirs * cols * kSeedTile; it += 256) {
+        const int row = it >> 5;
+        const int k = __builtin_amdgcn_readfirstlane(row / cols);
+        const int xl = row % cols;
+        const int u = u_lo + (xl << n), w = w_lo + (it & 31);
+        if (u < 0 || u >= S || w >= S) continue;
+        int lr, lc;
+        if (q < 2) { lr = w - r0; lc = (q == 0 ? u : S - 1 - u) - c0; }
+        else { lc = w - c0; lr = (q == 2 ? u : S - 1 - u) - r0; }
+        const int base = (lr + kSeedHalo) * kSeedPitch + lc + kSeedHalo;
+        const int sid = (n == 0 ? 0 : n == 1 ? 2 : 5) + k;
         float2 acc = make_float2(0.f, 1.f);
-        for (int j = 0; j < c_st_len[sid]; ++j) {
-            int u = u0 + c_st_du[sid][j], w = y + c_st_dw[sid][j];
-            if (u < S && w >= 0 && w < S) {
-                size_t id = (size_t)frame_row(q, u, S) * S + w;
-                acc = merge(acc, cell_interval(E[id], G[id], c_st_ell[sid][j]));
-            }
+#pragma unroll
+        for (int j = 0; j < pieces; ++j) {
+            const int off = c_hp_len[sid][j] * (kSeedSpan * kSeedPitch) + c_hp_du[sid][j] * su +
+                            c_hp_dw[sid][j] * sw;
+            acc = merge(acc, iv[base + off]);
         }
-        out[q * qoff + ((size_t)x * ((1 << n) + 1) + k) * S + y] = acc;
+        out[q * qoff + ((size_t)(u >> n) * dirs + k) * S + w] = acc;
     }
+}
+
+__device__ void body_seed(const SeedArgs &a, unsigned tile) {
+    __shared__ float2 iv[3 * kSeedSpan * kSeedPitch];
+    const int S = 1 << a.N;
+    const int tiles = (S + kSeedTile - 1) / kSeedTile;
+    const int r0 = (int)(tile / tiles) * kSeedTile, c0 = (int)(tile % tiles) * kSeedTile;
+    for (int i = threadIdx.x; i < kSeedSpan * kSeedSpan; i += 256) {
+        const int lr = i / kSeedSpan, lc = i % kSeedSpan;
+        const int r = r0 - kSeedHalo + lr, c = c0 - kSeedHalo + lc;
+        float e = 0.f, g = 0.f;
+        if (r >= 0 && r < S && c >= 0 && c < S) {
+            e = a.eps[(size_t)r * S + c];
+            g = a.sig[(size_t)r * S + c];
+        }
+        const int l = lr * kSeedPitch + lc;
+        iv[l] = cell_interval(e, g, 0.5f);
+        iv[kSeedSpan * kSeedPitch + l] = cell_interval(e, g, kH2);
+        iv[2 * kSeedSpan * kSeedPitch + l] = cell_interval(e, g, kQ5);
+    }
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) {
+        seed_level_rays<0>(iv, a, q, r0, c0);
+        seed_level_rays<1>(iv, a, q, r0, c0);
+        seed_level_rays<2>(iv, a, q, r0, c0);
+    }
+    __syncthreads();
 }
 
 // Merge up: T_n from T_{n-1} (Section 4.1, Eq. 18-20).
@@ -566,7 +626,7 @@ __device__ void body_seed_adj(const SeedAdjArgs &a, unsigned tile, int U) {
 __device__ __forceinline__ void run_phase(const Phase &p, unsigned tile) {
     switch (p.kind) {
         case PH_TRANSPOSE: body_transpose(p.a.tr, tile); break;
-        case PH_SEED: body_seed(p.a.seed, tile, p.U); break;
+        case PH_SEED: body_seed(p.a.seed, tile); break;
         case PH_UP: body_merge_up(p.a.up, tile, p.U); break;
         case PH_DOWN: body_merge_down(p.a.down, tile, p.U); break;
         case PH_FRAME_SUM: body_frame_sum(p.a.fs, tile); break;
@@ -587,7 +647,6 @@ __device__ __forceinline__ void run_phase(const Phase &p, unsigned tile) {
     __global__ __launch_bounds__(256) void name(Phase p) {                         \
         body(p.a.field, xcd_tile(blockIdx.x, gridDim.x), p.U);                     \
     }
-HRC_ELEMENTWISE_KERNEL(hrc_seed, body_seed, seed)
 HRC_ELEMENTWISE_KERNEL(hrc_merge_up, body_merge_up, up)
 HRC_ELEMENTWISE_KERNEL(hrc_merge_down, body_merge_down, down)
 HRC_ELEMENTWISE_KERNEL(hrc_merge_down_adj, body_merge_down_adj, da)
@@ -595,6 +654,7 @@ HRC_ELEMENTWISE_KERNEL(hrc_interval_adj, body_dT, dt)
 HRC_ELEMENTWISE_KERNEL(hrc_seed_adj, body_seed_adj, sa)
 #undef HRC_ELEMENTWISE_KERNEL
 
+__global__ __launch_bounds__(256) void hrc_seed(Phase p) { body_seed(p.a.seed, blockIdx.x); }
 __global__ __launch_bounds__(256) void hrc_transpose(Phase p) { body_transpose(p.a.tr, blockIdx.x); }
 __global__ __launch_bounds__(256) void hrc_frame_sum(Phase p) { body_frame_sum(p.a.fs, blockIdx.x); }
 __global__ __launch_bounds__(256) void hrc_gather_adj(Phase p) { body_gather_adj(p.a.ga, blockIdx.x); }
@@ -715,7 +775,7 @@ unsigned phase_tiles(const Phase &p) {
         case PH_TRANSPOSE: return t32 * t32;
         case PH_FRAME_SUM: return t32 * t32;
         case PH_GATHER_ADJ: return 4 * t32 * t32;
-        case PH_SEED: return cdiv(4 * (19 * S / 4) * S, per);
+        case PH_SEED: return t32 * t32;
         case PH_UP: return cdiv(4 * t_level_entries(N, p.a.up.n), per);
         case PH_DT: return cdiv(4 * t_level_entries(N, p.a.dt.n), per);
         case PH_DOWN:

@@ -26,7 +26,8 @@ def pass_bytes(name: str, N: int, n: int = -1, two_fields: bool = False) -> floa
     if name == "transpose":
         return 16 * SS
     if name == "seed":
-        return q * 8 * SS + q * 8 * (_t(S, 0) + _t(S, 1) + _t(S, 2))
+        # the two fields read once for all four quadrants, T_0..T_2 written
+        return 8 * SS + q * 8 * (_t(S, 0) + _t(S, 1) + _t(S, 2))
     if name == "merge_up":
         return q * 8 * (_t(S, n - 1) + _t(S, n))
     if name == "merge_down":
@@ -58,7 +59,7 @@ def pass_bytes(name: str, N: int, n: int = -1, two_fields: bool = False) -> floa
 
 def forward_passes(N: int):
     """(name, level) of every pass of one forward solve, in order."""
-    out = [("transpose", -1), ("seed", -1)]
+    out = [("seed", -1)]
     out += [("merge_up", n) for n in range(3, N + 1)]
     out += [("merge_down", n) for n in range(N - 1, -1, -1)]
     out += [("frame_sum", -1)]
@@ -71,7 +72,7 @@ def forward_bytes(N: int) -> float:
 
 def backward_bytes(N: int) -> float:
     """hrc_backward: the forward recomputed (without the gather) plus the reverse."""
-    b = forward_bytes(N) - pass_bytes("frame_sum", N)
+    b = forward_bytes(N) - pass_bytes("frame_sum", N) + pass_bytes("transpose", N)
     b += pass_bytes("gather_adj", N)
     b += sum(pass_bytes("merge_down_adj", N, n) for n in range(N - 1))
     b += sum(pass_bytes("interval_adj", N, n) for n in range(N, -1, -1))
