@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Throughput of the HRC hot path on one MI355X.
 
-One step = one full forward solve (transposed inputs, traced levels, merge up,
+One step = one full forward solve (traced levels, merge up,
 merge down, quadrant gather) of the 1024x1024 scene (128 disks, 256 opaque
 boxes, 32 one-pixel sigma-100 lines, value-noise fog), inputs resident in HBM.
 Prints one JSON line: Mpixel/s of fluence (value), plus the forward+backward

@@ -55,8 +55,18 @@ typedef enum {
 #define HRC_MAX_LOG2 12
 
 /* Flags.  HRC_FLAG_VALIDATE scans eps and sigma on the device first and
- * synchronises the stream to report HRC_ERR_INPUT (debug use only). */
+ * synchronises the stream to report HRC_ERR_INPUT (debug use only).
+ * HRC_FLAG_QUADRANTS_{1,2,4} (forward only) choose how many quadrant solves
+ * run side by side, each group reusing one set of pyramid buffers: fewer means
+ * a smaller working set (it can stay in the 256 MB Infinity Cache) but more,
+ * smaller launches.  Without one, the library picks by size.  Results are
+ * bitwise identical for every choice; the workspace size depends on it, so
+ * pass the same flags to hrc_workspace_bytes. */
 #define HRC_FLAG_VALIDATE 0x1u
+#define HRC_FLAG_QUADRANTS_1 0x10u
+#define HRC_FLAG_QUADRANTS_2 0x20u
+#define HRC_FLAG_QUADRANTS_4 0x30u
+#define HRC_FLAG_QUADRANTS_MASK 0x30u
 
 typedef struct hrc_context hrc_context;
 

@@ -21,6 +21,10 @@ HRC_ERR_INPUT = -6
 HRC_MIN_LOG2 = 3
 HRC_MAX_LOG2 = 12
 HRC_FLAG_VALIDATE = 0x1
+HRC_FLAG_QUADRANTS_1 = 0x10
+HRC_FLAG_QUADRANTS_2 = 0x20
+HRC_FLAG_QUADRANTS_4 = 0x30
+HRC_FLAG_QUADRANTS_MASK = 0x30
 PASS_NAMES = ["transpose", "seed", "merge_up", "merge_down", "frame_sum", "gather_adj",
               "merge_down_adj", "interval_adj", "seed_adj"]
 # Kernel symbol of each pass kind (what a profiler shows).

@@ -12,21 +12,28 @@
 
 namespace hrc {
 
-Layout make_layout(int N, bool backward) {
+Layout make_layout(int N, bool backward, int group) {
     Layout L;
     L.N = N;
     L.S = size_t(1) << N;
+    L.group = backward ? kQuadrants : group;
     const size_t SS = L.S * L.S;
     size_t off = 256;  // first 256 bytes: scratch flag for HRC_FLAG_VALIDATE
-    L.fieldsT = off;
-    off += align256(2 * SS * sizeof(float));
+    if (backward) {
+        L.fieldsT = off;
+        off += align256(2 * SS * sizeof(float));
+    }
     for (int n = 0; n <= N; ++n) {
         L.t_level[n] = off;
-        off += align256(kQuadrants * t_level_entries(N, n) * sizeof(float2));
+        off += align256(L.group * t_level_entries(N, n) * sizeof(float2));
     }
     L.r_count = backward ? N : 2;
     for (int i = 0; i < L.r_count; ++i) {
         L.r_level[i] = off;
+        off += align256(L.group * SS * sizeof(float));
+    }
+    if (!backward) {
+        L.r0_all = off;
         off += align256(kQuadrants * SS * sizeof(float));
     }
     if (backward) {
@@ -43,6 +50,16 @@ Layout make_layout(int N, bool backward) {
     }
     L.total = off;
     return L;
+}
+
+// Quadrant group of a forward: from the flags, else the library default.
+static int forward_group(int N, unsigned flags) {
+    switch ((flags & HRC_FLAG_QUADRANTS_MASK) >> 4) {
+        case 1: return 1;
+        case 2: return 2;
+        case 3: return 4;
+        default: return N >= 11 ? 2 : 4;
+    }
 }
 
 // A_m(jj) of Eq. 13 in double precision, rounded once to float.
@@ -82,33 +99,48 @@ int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, cons
         p.a.tr = TransposeArgs{b.eps, b.sig, w.epsT(), w.sigT(), N};
         add(p);
     }
-    p = Phase();
-    p.kind = PH_SEED;
-    p.a.seed = SeedArgs{b.eps, b.sig, w.epsT(), w.sigT(), w.T(0), w.T(1), w.T(2),
-                        t_level_entries(N, 0), t_level_entries(N, 1), t_level_entries(N, 2), N};
-    add(p);
-    for (int n = kTracedLevels; n <= N; ++n) {
-        p = Phase();
-        p.kind = PH_UP;
-        p.U = pick_u(U, PH_UP);
-        p.a.up = UpArgs{w.T(n - 1), w.T(n), t_level_entries(N, n - 1), t_level_entries(N, n), N, n};
-        add(p);
-    }
+    // Algorithm 1 for `group` quadrants at a time; each group reuses the same
+    // pyramid buffers, and the last merge down of a group writes that group's
+    // R_0 (into the per-quadrant R_0 array, or R(0) when every level is kept).
+    const int G = w.L.group;
     int cur = -1;
-    for (int n = N - 1; n >= 0; --n) {
-        const int o = keep_all_r ? n : ((cur == 0) ? 1 : 0);
+    for (int q0 = 0; q0 < kQuadrants; q0 += G) {
         p = Phase();
-        p.kind = PH_DOWN;
-        p.U = pick_u(U, PH_DOWN);
-        p.a.down = DownArgs{(n + 1 < N) ? w.R(cur) : nullptr, w.T(n), w.T(n + 1), w.R(o),
-                            t_level_entries(N, n), t_level_entries(N, n + 1), N, n};
+        p.kind = PH_SEED;
+        p.a.seed = SeedArgs{b.eps, b.sig, w.T(0), w.T(1), w.T(2), t_level_entries(N, 0),
+                            t_level_entries(N, 1), t_level_entries(N, 2), N, q0, G};
         add(p);
-        cur = o;
+        for (int n = kTracedLevels; n <= N; ++n) {
+            p = Phase();
+            p.kind = PH_UP;
+            p.U = pick_u(U, PH_UP);
+            p.a.up = UpArgs{w.T(n - 1), w.T(n), t_level_entries(N, n - 1), t_level_entries(N, n),
+                            N, n, G};
+            add(p);
+        }
+        cur = -1;
+        for (int n = N - 1; n >= 0; --n) {
+            float *dst;
+            int o = n;
+            if (keep_all_r) {
+                dst = w.R(n);
+            } else {
+                o = (cur == 0) ? 1 : 0;
+                dst = n == 0 ? w.R0all() + (size_t)q0 * w.L.S * w.L.S : w.R(o);
+            }
+            p = Phase();
+            p.kind = PH_DOWN;
+            p.U = pick_u(U, PH_DOWN);
+            p.a.down = DownArgs{(n + 1 < N) ? w.R(cur) : nullptr, w.T(n), w.T(n + 1), dst,
+                                t_level_entries(N, n), t_level_entries(N, n + 1), N, n, G};
+            add(p);
+            cur = o;
+        }
     }
     if (b.F) {
         p = Phase();
         p.kind = PH_FRAME_SUM;
-        p.a.fs = FrameSumArgs{w.R(cur), nullptr, b.F, nullptr, N, 1};
+        p.a.fs = FrameSumArgs{keep_all_r ? w.R(0) : w.R0all(), nullptr, b.F, nullptr, N, 1};
         add(p);
     }
     if (b.dF) {
@@ -200,8 +232,9 @@ hrc_status hrc_workspace_bytes(int log2_size, unsigned flags, size_t *forward_by
                                size_t *backward_bytes) {
     hrc_status st = check_shape(log2_size);
     if (st != HRC_OK) return st;
-    if (flags & ~HRC_FLAG_VALIDATE) return HRC_ERR_UNSUPPORTED;
-    if (forward_bytes) *forward_bytes = make_layout(log2_size, false).total;
+    if (flags & ~(HRC_FLAG_VALIDATE | HRC_FLAG_QUADRANTS_MASK)) return HRC_ERR_UNSUPPORTED;
+    if (forward_bytes)
+        *forward_bytes = make_layout(log2_size, false, forward_group(log2_size, flags)).total;
     if (backward_bytes) *backward_bytes = make_layout(log2_size, true).total;
     return HRC_OK;
 }
@@ -236,8 +269,8 @@ hrc_status hrc_forward(hrc_context *ctx, int log2_size, const float *emission,
     if (!aligned16(emission) || !aligned16(sigma_t) || !aligned16(fluence) ||
         !aligned16(workspace))
         return HRC_ERR_INVALID_ARG;
-    if (flags & ~HRC_FLAG_VALIDATE) return HRC_ERR_UNSUPPORTED;
-    Layout L = make_layout(log2_size, false);
+    if (flags & ~(HRC_FLAG_VALIDATE | HRC_FLAG_QUADRANTS_MASK)) return HRC_ERR_UNSUPPORTED;
+    Layout L = make_layout(log2_size, false, forward_group(log2_size, flags));
     if (workspace_bytes < L.total) return HRC_ERR_WORKSPACE;
     if (!ctx) return HRC_ERR_INVALID_ARG;
     DeviceGuard g(ctx->device);
@@ -263,7 +296,7 @@ hrc_status hrc_backward(hrc_context *ctx, int log2_size, const float *emission,
     if (!aligned16(emission) || !aligned16(sigma_t) || !aligned16(grad_fluence) ||
         !aligned16(grad_emission) || !aligned16(grad_sigma_t) || !aligned16(workspace))
         return HRC_ERR_INVALID_ARG;
-    if (flags & ~HRC_FLAG_VALIDATE) return HRC_ERR_UNSUPPORTED;
+    if (flags & ~(HRC_FLAG_VALIDATE | HRC_FLAG_QUADRANTS_MASK)) return HRC_ERR_UNSUPPORTED;
     Layout L = make_layout(log2_size, true);
     if (workspace_bytes < L.total) return HRC_ERR_WORKSPACE;
     if (!ctx) return HRC_ERR_INVALID_ARG;
@@ -305,7 +338,8 @@ hrc_status hrc_profile_solve(hrc_context *ctx, int log2_size, const float *emiss
         return HRC_ERR_INVALID_ARG;
     if (!pass_ms || !pass_kind || !pass_level || !count || max_passes < 0)
         return HRC_ERR_INVALID_ARG;
-    Layout L = make_layout(log2_size, bwd);
+    Layout L = bwd ? make_layout(log2_size, true)
+                   : make_layout(log2_size, false, forward_group(log2_size, 0));
     if (workspace_bytes < L.total) return HRC_ERR_WORKSPACE;
     if (!ctx) return HRC_ERR_INVALID_ARG;
     DeviceGuard g(ctx->device);

@@ -31,17 +31,20 @@ inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 struct Layout {
     int N = 0;
     size_t S = 0;
-    size_t fieldsT = 0;                  // eps^T then sigma^T, [S][S] float each
-    size_t t_level[kMaxLog2 + 2] = {};   // T_n: 4 quadrants x t_level_entries float2
-    size_t r_level[kMaxLog2 + 1] = {};   // R buffers: 4 quadrants x S^2 float each
+    int group = 4;                       // quadrants whose pyramids are live at once
+    size_t fieldsT = 0;                  // backward: eps^T then sigma^T, [S][S] float each
+    size_t t_level[kMaxLog2 + 2] = {};   // T_n: `group` quadrants x t_level_entries float2
+    size_t r_level[kMaxLog2 + 1] = {};   // R buffers: `group` quadrants x S^2 float each
     int r_count = 0;                     // 2 (forward ping-pong) or N (keeps every R_n)
+    size_t r0_all = 0;                   // forward: R_0 of all four quadrants
     size_t dt_level[kMaxLog2 + 2] = {};  // backward: adjoint pyramid
     size_t dr_level[kMaxLog2 + 1] = {};  // backward: adjoint cascades
     size_t dfield = 0;                   // backward: per-quadrant frame gradients
     size_t total = 0;
 };
 
-Layout make_layout(int N, bool backward);
+// Forward: pyramids of `group` quadrants (1, 2 or 4) at a time; backward: all 4.
+Layout make_layout(int N, bool backward, int group = 4);
 
 struct Ws {
     char *base;
@@ -54,24 +57,27 @@ struct Ws {
     float *sigT() const { return epsT() + L.S * L.S; }
     float *dE() const { return reinterpret_cast<float *>(base + L.dfield); }
     float *dS() const { return dE() + kQuadrants * L.S * L.S; }
+    float *R0all() const { return reinterpret_cast<float *>(base + L.r0_all); }
 };
 
 // ---- Arguments of each phase (one pass over one level of one scene) -------
 
 struct TransposeArgs { const float *a, *b; float *aT, *bT; int N; };
+// Forward passes run on a group of nq quadrants q0 .. q0+nq-1 whose buffers
+// start at the pointers given (quadrant q0 first).
 struct SeedArgs {
-    const float *eps, *sig, *epsT, *sigT;
+    const float *eps, *sig;
     float2 *T0, *T1, *T2;
     size_t e0, e1, e2;  // entries per quadrant of each level
-    int N;
+    int N, q0, nq;
 };
-struct UpArgs { const float2 *Tp; float2 *T; size_t ep, e; int N, n; };
+struct UpArgs { const float2 *Tp; float2 *T; size_t ep, e; int N, n, nq; };
 struct DownArgs {
     const float *Rn1;        // R_{n+1}; unused when n + 1 == N
     const float2 *Tn, *Tn1;  // T_n, T_{n+1}
     float *R;                // R_n
     size_t en, en1;
-    int N, n;
+    int N, n, nq;
 };
 struct FrameSumArgs { const float *src, *src2; float *out, *out2; int N, off; };
 struct GatherAdjArgs { const float *dF; float *dR0; int N; };
@@ -149,7 +155,7 @@ hipError_t persistent_occupancy(int *blocks_per_cu);
 hipError_t launch_validate(const float *a, const float *b, size_t n, int *flag,
                            hipStream_t s);
 
-constexpr int kMaxPhases = 4 * kMaxLog2 + 16;  // passes of one forward + backward solve
+constexpr int kMaxPhases = 8 * kMaxLog2 + 16;  // passes of one forward + backward solve
 
 // RAII switch to a device for the duration of a call.
 struct DeviceGuard {

@@ -176,7 +176,7 @@ __constant__ unsigned char c_hp_len[10][8] = {
 // direction k and the stencil lookups are wave-uniform.
 template <int n>
 __device__ __forceinline__ void seed_level_rays(const float2 *iv, const SeedArgs &a, int q,
-                                                int r0, int c0) {
+                                                int slot, int r0, int c0) {
     constexpr int dirs = (1 << n) + 1, cols = kSeedTile >> n, pieces = 2 << n;
     const int S = 1 << a.N;
     float2 *out = n == 0 ? a.T0 : n == 1 ? a.T1 : a.T2;
@@ -204,7 +204,7 @@ __device__ __forceinline__ void seed_level_rays(const float2 *iv, const SeedArgs
                             c_hp_dw[sid][j] * sw;
             acc = merge(acc, iv[base + off]);
         }
-        out[q * qoff + ((size_t)(u >> n) * dirs + k) * S + w] = acc;
+        out[slot * qoff + ((size_t)(u >> n) * dirs + k) * S + w] = acc;
     }
 }
 
@@ -227,12 +227,27 @@ __device__ void body_seed(const SeedArgs &a, unsigned tile) {
         iv[2 * kSeedSpan * kSeedPitch + l] = cell_interval(e, g, kQ5);
     }
     __syncthreads();
-    for (int q = 0; q < 4; ++q) {
-        seed_level_rays<0>(iv, a, q, r0, c0);
-        seed_level_rays<1>(iv, a, q, r0, c0);
-        seed_level_rays<2>(iv, a, q, r0, c0);
+    for (int g = 0; g < a.nq; ++g) {
+        seed_level_rays<0>(iv, a, a.q0 + g, g, r0, c0);
+        seed_level_rays<1>(iv, a, a.q0 + g, g, r0, c0);
+        seed_level_rays<2>(iv, a, a.q0 + g, g, r0, c0);
     }
     __syncthreads();
+}
+
+// Two consecutive y per thread: y is even and every shift is even (except
+// the odd-column shifts 2e - 1 of merge-down level 0, read element-wise), so a
+// pair of intervals is one aligned 16-byte load and a pair of angular
+// fluences one aligned 8-byte load, and both members of a shifted pair are in
+// or out of the grid together.
+__device__ __forceinline__ float4 ld_pair(const float2 *p) {
+    return *reinterpret_cast<const float4 *>(p);
+}
+__device__ __forceinline__ float2 lo(float4 v) { return make_float2(v.x, v.y); }
+__device__ __forceinline__ float2 hi(float4 v) { return make_float2(v.z, v.w); }
+__device__ __forceinline__ float4 pair(float2 a, float2 b) { return make_float4(a.x, a.y, b.x, b.y); }
+__device__ __forceinline__ float4 far_pair(const float2 *row, int yf, int S) {
+    return (yf >= 0 && yf < S) ? ld_pair(row + yf) : make_float4(0.f, 1.f, 0.f, 1.f);
 }
 
 // Merge up: T_n from T_{n-1} (Section 4.1, Eq. 18-20).
@@ -241,53 +256,64 @@ __device__ void body_merge_up(const UpArgs &a, unsigned tile, int U) {
     const int h = 1 << (n - 1);
     const int dirs = 2 * h + 1, pdirs = h + 1;
     const unsigned rpq = (unsigned)(S >> n) * dirs;
-    const size_t total = (size_t)4 * rpq * S;
+    const size_t total = (size_t)a.nq * rpq * (S / 2);
     for (int uu = 0; uu < U; ++uu) {
         const size_t idx = ((size_t)tile * U + uu) * 256 + threadIdx.x;
         if (idx >= total) return;
-        const int y = (int)(idx & (S - 1));
-        const unsigned row = (unsigned)(idx >> N);
+        const int y = (int)(idx & (S / 2 - 1)) * 2;
+        const unsigned row = (unsigned)(idx >> (N - 1));
         const int q = row / rpq;
         const unsigned r = row % rpq;
         const int x = r / dirs, k = r % dirs;
         const float2 *near = a.Tp + q * a.ep + (size_t)(2 * x) * pdirs * S;
         const float2 *far = near + (size_t)pdirs * S;
-        float2 res;
+        float4 res;
         if ((k & 1) == 0) {
             // Eq. 18: p -> p + v_{n-1}(k/2) -> p + v_n(k), exact.
-            const int kk = k >> 1, yf = y + 2 * kk - h;
-            float2 f = (yf >= 0 && yf < S) ? far[(size_t)kk * S + yf] : make_float2(0.f, 1.f);
-            res = merge(near[(size_t)kk * S + y], f);
+            const int kk = k >> 1;
+            const float4 nv = ld_pair(near + (size_t)kk * S + y);
+            const float4 fv = far_pair(far + (size_t)kk * S, y + 2 * kk - h, S);
+            res = pair(merge(lo(nv), lo(fv)), merge(hi(nv), hi(fv)));
         } else {
             // Eq. 19-20: mean of the two bent paths through directions (k+-1)/2.
             const int ka = (k + 1) >> 1, kb = (k - 1) >> 1;
-            const int ya = y + 2 * ka - h, yb = y + 2 * kb - h;
-            float2 fa = (ya >= 0 && ya < S) ? far[(size_t)kb * S + ya] : make_float2(0.f, 1.f);
-            float2 fb = (yb >= 0 && yb < S) ? far[(size_t)ka * S + yb] : make_float2(0.f, 1.f);
-            float2 p = merge(near[(size_t)ka * S + y], fa);
-            float2 m = merge(near[(size_t)kb * S + y], fb);
-            res = make_float2(0.5f * (p.x + m.x), 0.5f * (p.y + m.y));
+            const float4 na = ld_pair(near + (size_t)ka * S + y);
+            const float4 nb = ld_pair(near + (size_t)kb * S + y);
+            const float4 fa = far_pair(far + (size_t)kb * S, y + 2 * ka - h, S);
+            const float4 fb = far_pair(far + (size_t)ka * S, y + 2 * kb - h, S);
+            const float2 p0 = merge(lo(na), lo(fa)), m0 = merge(lo(nb), lo(fb));
+            const float2 p1 = merge(hi(na), hi(fa)), m1 = merge(hi(nb), hi(fb));
+            res = make_float4(0.5f * (p0.x + m0.x), 0.5f * (p0.y + m0.y),
+                              0.5f * (p1.x + m1.x), 0.5f * (p1.y + m1.y));
         }
-        a.T[q * a.e + (size_t)r * S + y] = res;
+        *reinterpret_cast<float4 *>(a.T + q * a.e + (size_t)r * S + y) = res;
     }
+}
+
+// R_m of one quadrant at (c, jj) for the row pair (y, y+1), y even; zero
+// outside the grid, and R_N = 0.
+__device__ __forceinline__ float2 r_pair(const float *Rq, int N, int m, int c, int jj, int y) {
+    const int S = 1 << N;
+    if (m >= N || c >= (S >> m) || y < 0 || y >= S) return make_float2(0.f, 0.f);
+    return *reinterpret_cast<const float2 *>(Rq + ((size_t)((c << m) | jj)) * S + y);
 }
 
 // Merge down: R_n from R_{n+1}, T_n, T_{n+1} (Eq. 14-17).
 __device__ void body_merge_down(const DownArgs &a, unsigned tile, int U) {
     const int N = a.N, S = 1 << N, n = a.n;
     const size_t SS = (size_t)S * S;
-    const size_t total = 4 * SS;
+    const size_t total = (size_t)a.nq * (SS / 2);
     const int m = n + 1;
     for (int uu = 0; uu < U; ++uu) {
         const size_t idx = ((size_t)tile * U + uu) * 256 + threadIdx.x;
         if (idx >= total) return;
-        const int y = (int)(idx & (S - 1));
-        const unsigned row = (unsigned)(idx >> N);
+        const int y = (int)(idx & (S / 2 - 1)) * 2;
+        const unsigned row = (unsigned)(idx >> (N - 1));
         const int q = row >> N;
         const unsigned r = row & (S - 1);
         const int x = r >> n, ii = r & ((1 << n) - 1);
         const float *Rq = a.Rn1 + q * SS;
-        float acc = 0.f;
+        float acc0 = 0.f, acc1 = 0.f;
         if (x & 1) {
             // Eq. 14: trace the half-cone's outer edge to the level n+1 probe.
             const float2 *Tx = a.Tn + q * a.en + (size_t)x * ((1 << n) + 1) * S;
@@ -296,9 +322,13 @@ __device__ void body_merge_down(const DownArgs &a, unsigned tile, int U) {
             for (int up = 0; up < 2; ++up) {
                 const int e = ii + up, jj = 2 * ii + up;
                 const float A = c_cone[(1 << m) - 1 + jj];
-                float2 t = Tx[(size_t)e * S + y];
-                float rf = r_lookup(Rq, N, m, c, jj, y + 2 * e - (1 << n));
-                acc += fmaf(t.y, rf, A * t.x);
+                const float4 t = ld_pair(Tx + (size_t)e * S + y);
+                const int yf = y + 2 * e - (1 << n);  // odd when n = 0
+                const float2 rf = n > 0 ? r_pair(Rq, N, m, c, jj, yf)
+                                        : make_float2(r_lookup(Rq, N, m, c, jj, yf),
+                                                      r_lookup(Rq, N, m, c, jj, yf + 1));
+                acc0 += fmaf(t.y, rf.x, A * t.x);
+                acc1 += fmaf(t.w, rf.y, A * t.z);
             }
         } else {
             // Eq. 15-17: average the co-located probe with the doubled-edge trace.
@@ -308,13 +338,14 @@ __device__ void body_merge_down(const DownArgs &a, unsigned tile, int U) {
             for (int up = 0; up < 2; ++up) {
                 const int e2 = 2 * ii + 2 * up, jj = 2 * ii + up;
                 const float A = c_cone[(1 << m) - 1 + jj];
-                float2 t = Tx[(size_t)e2 * S + y];
-                float r0 = r_lookup(Rq, N, m, c, jj, y);
-                float r1 = r_lookup(Rq, N, m, c + 1, jj, y + 2 * e2 - (1 << m));
-                acc += 0.5f * (r0 + fmaf(t.y, r1, A * t.x));
+                const float4 t = ld_pair(Tx + (size_t)e2 * S + y);
+                const float2 r0 = r_pair(Rq, N, m, c, jj, y);
+                const float2 r1 = r_pair(Rq, N, m, c + 1, jj, y + 2 * e2 - (1 << m));
+                acc0 += 0.5f * (r0.x + fmaf(t.y, r1.x, A * t.x));
+                acc1 += 0.5f * (r0.y + fmaf(t.w, r1.y, A * t.z));
             }
         }
-        a.R[q * SS + (size_t)r * S + y] = acc;
+        *reinterpret_cast<float2 *>(a.R + q * SS + (size_t)r * S + y) = make_float2(acc0, acc1);
     }
 }
 
@@ -776,9 +807,9 @@ unsigned phase_tiles(const Phase &p) {
         case PH_FRAME_SUM: return t32 * t32;
         case PH_GATHER_ADJ: return 4 * t32 * t32;
         case PH_SEED: return t32 * t32;
-        case PH_UP: return cdiv(4 * t_level_entries(N, p.a.up.n), per);
+        case PH_UP: return cdiv((size_t)p.a.up.nq * t_level_entries(N, p.a.up.n) / 2, per);
         case PH_DT: return cdiv(4 * t_level_entries(N, p.a.dt.n), per);
-        case PH_DOWN:
+        case PH_DOWN: return cdiv((size_t)p.a.down.nq * SS / 2, per);
         case PH_DOWN_ADJ:
         case PH_SEED_ADJ: return cdiv(4 * SS, per);
     }

@@ -64,11 +64,12 @@ class Context:
                 pass
             self._ptr = ctypes.c_void_p(0)
 
-    def workspace(self, N: int, backward: bool) -> torch.Tensor:
-        key = (N, backward)
+    def workspace(self, N: int, backward: bool, flags: int = 0) -> torch.Tensor:
+        group = 0 if backward else flags & _lib.HRC_FLAG_QUADRANTS_MASK
+        key = (N, backward, group)
         ws = self._ws.get(key)
         if ws is None:
-            f, b = hrc_workspace_bytes(N)
+            f, b = hrc_workspace_bytes(N, group)
             ws = torch.empty(b if backward else f, dtype=torch.uint8,
                              device=torch.device("cuda", self.device))
             self._ws[key] = ws
@@ -87,7 +88,7 @@ class Context:
             raise ValueError("emission and sigma_t shapes differ")
         if out is None:
             out = torch.empty_like(emission)
-        ws = self.workspace(N, False)
+        ws = self.workspace(N, False, flags)
         check(_lib.load().hrc_forward(self._ptr, N, emission.data_ptr(), sigma_t.data_ptr(),
                                       out.data_ptr(), ws.data_ptr(), ws.numel(),
                                       _stream_handle(emission.device), flags), "hrc_forward")

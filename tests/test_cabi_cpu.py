@@ -41,26 +41,30 @@ def test_status_strings():
     assert b"unknown" in lib.hrc_status_string(-99)
 
 
-def _ws(N):
+def _ws(N, flags=0):
     f = ctypes.c_size_t(0)
     b = ctypes.c_size_t(0)
-    st = _lib.load().hrc_workspace_bytes(N, 0, ctypes.byref(f), ctypes.byref(b))
+    st = _lib.load().hrc_workspace_bytes(N, flags, ctypes.byref(f), ctypes.byref(b))
     return st, f.value, b.value
 
 
 @pytest.mark.parametrize("N", [3, 6, 10, 12])
 def test_workspace_sizes_follow_the_memory_analysis(N):
     """Section 4.3.2: the pyramid holds (N + 3 - 2^-N) S^2 interval entries per
-    quadrant; the forward workspace is four quadrants of it (8 bytes per entry)
-    plus two cascade levels and the transposed inputs, up to alignment."""
-    st, f, b = _ws(N)
-    assert st == HRC_OK
+    quadrant.  A forward keeps the pyramids of G quadrants at once (8 bytes per
+    entry) plus two cascade levels of G quadrants and R_0 of all four; the
+    backward keeps all four pyramids, every cascade level, their adjoints and
+    the transposed inputs, up to alignment."""
     S = 1 << N
-    pyramid = 4 * 8 * sum((S >> n) * (2 ** n + 1) * S for n in range(N + 1))
-    assert pyramid == pytest.approx(4 * 8 * (N + 3 - 2.0 ** -N) * S * S)
-    fwd_min = pyramid + 2 * 4 * 4 * S * S + 2 * 4 * S * S
-    assert fwd_min <= f <= fwd_min + 256 * (2 * N + 8)
-    bwd_min = 2 * pyramid + 2 * N * 4 * 4 * S * S + 2 * 4 * S * S + 2 * 4 * 4 * S * S
+    one = 8 * sum((S >> n) * (2 ** n + 1) * S for n in range(N + 1))
+    assert one == pytest.approx(8 * (N + 3 - 2.0 ** -N) * S * S)
+    for flags, G in ((_lib.HRC_FLAG_QUADRANTS_1, 1), (_lib.HRC_FLAG_QUADRANTS_2, 2),
+                     (_lib.HRC_FLAG_QUADRANTS_4, 4), (0, 2 if N >= 11 else 4)):
+        st, f, b = _ws(N, flags)
+        assert st == HRC_OK
+        fwd_min = G * one + 2 * G * 4 * S * S + 4 * 4 * S * S
+        assert fwd_min <= f <= fwd_min + 256 * (2 * N + 8), (flags, f, fwd_min)
+    bwd_min = 2 * 4 * one + 2 * N * 4 * 4 * S * S + 2 * 4 * S * S + 2 * 4 * 4 * S * S
     assert bwd_min <= b <= bwd_min + 256 * (4 * N + 10)
 
 
@@ -100,7 +104,12 @@ def test_argument_checks_run_before_any_device_call():
     assert lib.hrc_forward(None, 5, p, p, p, p, f, None, 0) == HRC_ERR_INVALID_ARG
     assert lib.hrc_backward(None, 5, p, p, p, p, p, p, b, None, 0) == HRC_ERR_INVALID_ARG
     # unknown flags
-    assert lib.hrc_forward(None, 5, p, p, p, p, f, None, 0x10) == HRC_ERR_UNSUPPORTED
+    assert lib.hrc_forward(None, 5, p, p, p, p, f, None, 0x100) == HRC_ERR_UNSUPPORTED
+    # a quadrant grouping that needs a larger workspace than the one given
+    st1, f4, _ = _ws(5, _lib.HRC_FLAG_QUADRANTS_4)
+    st2, f1, _ = _ws(5, _lib.HRC_FLAG_QUADRANTS_1)
+    assert f1 < f4
+    assert lib.hrc_forward(None, 5, p, p, p, p, f1, None, _lib.HRC_FLAG_QUADRANTS_4) == HRC_ERR_WORKSPACE
 
 
 def test_batch_argument_checks():

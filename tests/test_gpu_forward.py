@@ -126,3 +126,17 @@ def test_validate_flag_rejects_bad_inputs(ctx):
         ctx.hrc_forward(to_dev(eps), to_dev(sig), flags=HRC_FLAG_VALIDATE)
     sig[0, 0] = 0.5
     ctx.hrc_forward(to_dev(eps), to_dev(sig), flags=HRC_FLAG_VALIDATE)
+
+
+@pytest.mark.parametrize("S", [16, 512])
+def test_forward_quadrant_groupings_are_bitwise_equal(ctx, S):
+    """One, two or four quadrant pyramids live at a time: same arithmetic per
+    element, so the fluence is bitwise identical."""
+    from paper_2505_02041_amd import _lib
+    eps, sig = _random_scene(S, 31)
+    e, s = to_dev(eps), to_dev(sig)
+    outs = [ctx.hrc_forward(e, s, flags=f).clone() for f in
+            (_lib.HRC_FLAG_QUADRANTS_1, _lib.HRC_FLAG_QUADRANTS_2, _lib.HRC_FLAG_QUADRANTS_4, 0)]
+    torch.cuda.synchronize()
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
