@@ -19,10 +19,6 @@ Layout make_layout(int N, bool backward, int group) {
     L.group = backward ? kQuadrants : group;
     const size_t SS = L.S * L.S;
     size_t off = 256;  // first 256 bytes: scratch flag for HRC_FLAG_VALIDATE
-    if (backward) {
-        L.fieldsT = off;
-        off += align256(2 * SS * sizeof(float));
-    }
     for (int n = 0; n <= N; ++n) {
         L.t_level[n] = off;
         off += align256(L.group * t_level_entries(N, n) * sizeof(float2));
@@ -45,8 +41,6 @@ Layout make_layout(int N, bool backward, int group) {
             L.dr_level[i] = off;
             off += align256(kQuadrants * SS * sizeof(float));
         }
-        L.dfield = off;
-        off += align256(2 * kQuadrants * SS * sizeof(float));
     }
     L.total = off;
     return L;
@@ -94,11 +88,6 @@ int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, cons
         ++np;
     };
     Phase p;
-    if (b.dF) {  // the adjoint of the traced levels reads transposed inputs
-        p.kind = PH_TRANSPOSE;
-        p.a.tr = TransposeArgs{b.eps, b.sig, w.epsT(), w.sigT(), N};
-        add(p);
-    }
     // Algorithm 1 for `group` quadrants at a time; each group reuses the same
     // pyramid buffers, and the last merge down of a group writes that group's
     // R_0 (into the per-quadrant R_0 array, or R(0) when every level is kept).
@@ -178,14 +167,8 @@ int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, cons
         }
         p = Phase();
         p.kind = PH_SEED_ADJ;
-        p.U = pick_u(U, PH_SEED_ADJ);
-        p.a.sa = SeedAdjArgs{b.eps, b.sig, w.epsT(), w.sigT(), w.dT(0), w.dT(1), w.dT(2),
-                             t_level_entries(N, 0), t_level_entries(N, 1), t_level_entries(N, 2),
-                             w.dE(), w.dS(), N};
-        add(p);
-        p = Phase();
-        p.kind = PH_FRAME_SUM;
-        p.a.fs = FrameSumArgs{w.dE(), w.dS(), b.dE, b.dS, N, 0};
+        p.a.sa = SeedAdjArgs{b.eps, b.sig, w.dT(0), w.dT(1), w.dT(2), t_level_entries(N, 0),
+                             t_level_entries(N, 1), t_level_entries(N, 2), b.dE, b.dS, N};
         add(p);
     }
     return np;

@@ -100,10 +100,10 @@ struct DTArgs {
     int N, n, has_up;
 };
 struct SeedAdjArgs {
-    const float *eps, *sig, *epsT, *sigT;
+    const float *eps, *sig;
     const float2 *dT0, *dT1, *dT2;
     size_t e0, e1, e2;
-    float *dE, *dS;          // per-quadrant frame gradients [4][S][S]
+    float *dE, *dS;          // d eps, d sigma of the image [S][S]
     int N;
 };
 

@@ -450,76 +450,112 @@ __device__ void body_gather_adj(const GatherAdjArgs &a, unsigned tile) {
     __syncthreads();
 }
 
+// Pair loads at a row position y that is even when `even` holds (every shift
+// except those of level 0); otherwise element by element.  Zero (or the vacuum
+// interval) outside the grid.
+__device__ __forceinline__ float2 ld2(const float *row, int y, int S, bool even) {
+    if (even) return (y >= 0 && y < S) ? *reinterpret_cast<const float2 *>(row + y)
+                                       : make_float2(0.f, 0.f);
+    return make_float2((y >= 0 && y < S) ? row[y] : 0.f,
+                       (y + 1 >= 0 && y + 1 < S) ? row[y + 1] : 0.f);
+}
+// Transmittances (the .y of two consecutive intervals) at y, 0 outside.
+__device__ __forceinline__ float2 ld2T(const float2 *row, int y, int S, bool even) {
+    if (even) {
+        if (y < 0 || y >= S) return make_float2(0.f, 0.f);
+        const float4 v = ld_pair(row + y);
+        return make_float2(v.y, v.w);
+    }
+    return make_float2((y >= 0 && y < S) ? row[y].y : 0.f,
+                       (y + 1 >= 0 && y + 1 < S) ? row[y + 1].y : 0.f);
+}
+
 // Adjoint of the merge down: dR_{n+1} from dR_n (gather form).  Each R_{n+1}
 // entry (c, jj, y') is read by at most three R_n entries: the odd column 2c-1
 // (far end of Eq. 14), the even column 2c (F^0 of Eq. 16) and the even column
-// 2c-2 (far end of Eq. 17).
+// 2c-2 (far end of Eq. 17).  Two consecutive y' per thread.
 __device__ void body_merge_down_adj(const DownAdjArgs &a, unsigned tile, int U) {
     const int N = a.N, S = 1 << N, n = a.n, m = n + 1;
     const size_t SS = (size_t)S * S;
     for (int uu = 0; uu < U; ++uu) {
         const size_t idx = ((size_t)tile * U + uu) * 256 + threadIdx.x;
-        if (idx >= 4 * SS) return;
-        const int yp = (int)(idx & (S - 1));
-        const unsigned row = (unsigned)(idx >> N);
+        if (idx >= 2 * SS) return;
+        const int yp = (int)(idx & (S / 2 - 1)) * 2;
+        const unsigned row = (unsigned)(idx >> (N - 1));
         const int q = row >> N;
         const unsigned r = row & (S - 1);
         const int c = r >> m, jj = r & ((1 << m) - 1);
         const int ii = jj >> 1, up = jj & 1;
         const float *dRq = a.dR + q * SS;
-        float acc = 0.5f * dRq[((size_t)(((2 * c) << n) | ii)) * S + yp];
+        const float2 f0 = *reinterpret_cast<const float2 *>(
+            dRq + ((size_t)(((2 * c) << n) | ii)) * S + yp);
+        float acc0 = 0.5f * f0.x, acc1 = 0.5f * f0.y;
         if (c >= 1) {
             const int e = ii + up;
             const int x = 2 * c - 1;
-            const int y = yp - (2 * e - (1 << n));
-            if (y >= 0 && y < S) {
-                float t = a.Tn[q * a.en + ((size_t)x * ((1 << n) + 1) + e) * S + y].y;
-                acc = fmaf(dRq[((size_t)((x << n) | ii)) * S + y], t, acc);
-            }
+            const int y = yp - (2 * e - (1 << n));  // odd when n = 0
+            const float2 g = ld2(dRq + ((size_t)((x << n) | ii)) * S, y, S, n > 0);
+            const float2 t = ld2T(a.Tn + q * a.en + ((size_t)x * ((1 << n) + 1) + e) * S, y, S,
+                                  n > 0);
+            acc0 = fmaf(g.x, t.x, acc0);
+            acc1 = fmaf(g.y, t.y, acc1);
             const int e2 = 2 * ii + 2 * up;
             const int x2 = 2 * c - 2;
             const int y2 = yp - (2 * e2 - (1 << m));
-            if (y2 >= 0 && y2 < S) {
-                float t = a.Tn1[q * a.en1 + ((size_t)(c - 1) * ((1 << m) + 1) + e2) * S + y2].y;
-                acc = fmaf(0.5f * dRq[((size_t)((x2 << n) | ii)) * S + y2], t, acc);
-            }
+            const float2 g2 = ld2(dRq + ((size_t)((x2 << n) | ii)) * S, y2, S, true);
+            const float2 t2 = ld2T(a.Tn1 + q * a.en1 + ((size_t)(c - 1) * ((1 << m) + 1) + e2) * S,
+                                   y2, S, true);
+            acc0 = fmaf(0.5f * g2.x, t2.x, acc0);
+            acc1 = fmaf(0.5f * g2.y, t2.y, acc1);
         }
-        a.dRn1[q * SS + (size_t)r * S + yp] = acc;
+        *reinterpret_cast<float2 *>(a.dRn1 + q * SS + (size_t)r * S + yp) = make_float2(acc0, acc1);
     }
 }
 
 // Adjoint of the interval pyramid: dT_n (gather form) from the merge down at
-// levels n and n-1 and from the merge up of T_{n+1}.
+// levels n and n-1 and from the merge up of T_{n+1}.  Two consecutive y per
+// thread.
 __device__ void body_dT(const DTArgs &a, unsigned tile, int U) {
     const int N = a.N, S = 1 << N, n = a.n;
     const size_t SS = (size_t)S * S;
     const int dirs = (1 << n) + 1;
     const unsigned rpq = (unsigned)(S >> n) * dirs;
-    const size_t total = (size_t)4 * rpq * S;
+    const size_t total = (size_t)4 * rpq * (S / 2);
     for (int uu = 0; uu < U; ++uu) {
         const size_t idx = ((size_t)tile * U + uu) * 256 + threadIdx.x;
         if (idx >= total) return;
-        const int y = (int)(idx & (S - 1));
-        const unsigned row = (unsigned)(idx >> N);
+        const int y = (int)(idx & (S / 2 - 1)) * 2;
+        const unsigned row = (unsigned)(idx >> (N - 1));
         const int q = row / rpq;
         const unsigned r = row % rpq;
         const int x = r / dirs, k = r % dirs;
-        float gl = 0.f, gt = 0.f;
+        float gl0 = 0.f, gt0 = 0.f, gl1 = 0.f, gt1 = 0.f;
         // (a) merge down at level n, odd x (Eq. 14): T_n(p, k) is the edge of
         //     cone k (lower half, jj = 2k) and of cone k-1 (upper half, jj = 2k-1).
         if (n < N && (x & 1)) {
             const float *dRq = a.dRn + q * SS;
             const float *Rq = a.Rn1 + q * SS;
-            const int c = (x + 1) >> 1, yf = y + 2 * k - (1 << n);
+            const int c = (x + 1) >> 1, yf = y + 2 * k - (1 << n);  // odd when n = 0
+            const bool rin = n + 1 < N && c < (S >> (n + 1));
             if (k >= 1) {
-                float g = dRq[((size_t)((x << n) | (k - 1))) * S + y];
-                gl = fmaf(g, c_cone[(1 << (n + 1)) - 1 + 2 * k - 1], gl);
-                gt = fmaf(g, r_lookup(Rq, N, n + 1, c, 2 * k - 1, yf), gt);
+                const float2 g = *reinterpret_cast<const float2 *>(
+                    dRq + ((size_t)((x << n) | (k - 1))) * S + y);
+                const float A = c_cone[(1 << (n + 1)) - 1 + 2 * k - 1];
+                const float2 rv = rin ? ld2(Rq + ((size_t)((c << (n + 1)) | (2 * k - 1))) * S, yf,
+                                            S, n > 0)
+                                      : make_float2(0.f, 0.f);
+                gl0 = fmaf(g.x, A, gl0); gl1 = fmaf(g.y, A, gl1);
+                gt0 = fmaf(g.x, rv.x, gt0); gt1 = fmaf(g.y, rv.y, gt1);
             }
             if (k < (1 << n)) {
-                float g = dRq[((size_t)((x << n) | k)) * S + y];
-                gl = fmaf(g, c_cone[(1 << (n + 1)) - 1 + 2 * k], gl);
-                gt = fmaf(g, r_lookup(Rq, N, n + 1, c, 2 * k, yf), gt);
+                const float2 g = *reinterpret_cast<const float2 *>(
+                    dRq + ((size_t)((x << n) | k)) * S + y);
+                const float A = c_cone[(1 << (n + 1)) - 1 + 2 * k];
+                const float2 rv = rin ? ld2(Rq + ((size_t)((c << (n + 1)) | (2 * k))) * S, yf, S,
+                                            n > 0)
+                                      : make_float2(0.f, 0.f);
+                gl0 = fmaf(g.x, A, gl0); gl1 = fmaf(g.y, A, gl1);
+                gt0 = fmaf(g.x, rv.x, gt0); gt1 = fmaf(g.y, rv.y, gt1);
             }
         }
         // (b) merge down at level n-1, even column 2x (Eq. 17): T_n(p, k), k even,
@@ -530,18 +566,30 @@ __device__ void body_dT(const DTArgs &a, unsigned tile, int U) {
             const float *Rq = a.Rn + q * SS;
             const int yf = y + 2 * k - (1 << n);
             const int xm = 2 * x;
+            const bool rin = n < N && x + 1 < (S >> n);
             if (k >= 2) {
-                float g = 0.5f * dRq[((size_t)((xm << nm) | (k / 2 - 1))) * S + y];
-                gl = fmaf(g, c_cone[(1 << n) - 1 + k - 1], gl);
-                gt = fmaf(g, r_lookup(Rq, N, n, x + 1, k - 1, yf), gt);
+                const float2 g0 = *reinterpret_cast<const float2 *>(
+                    dRq + ((size_t)((xm << nm) | (k / 2 - 1))) * S + y);
+                const float A = c_cone[(1 << n) - 1 + k - 1];
+                const float2 rv = rin ? ld2(Rq + ((size_t)(((x + 1) << n) | (k - 1))) * S, yf, S,
+                                            true)
+                                      : make_float2(0.f, 0.f);
+                const float g0x = 0.5f * g0.x, g0y = 0.5f * g0.y;
+                gl0 = fmaf(g0x, A, gl0); gl1 = fmaf(g0y, A, gl1);
+                gt0 = fmaf(g0x, rv.x, gt0); gt1 = fmaf(g0y, rv.y, gt1);
             }
             if (k < (1 << n)) {
-                float g = 0.5f * dRq[((size_t)((xm << nm) | (k / 2))) * S + y];
-                gl = fmaf(g, c_cone[(1 << n) - 1 + k], gl);
-                gt = fmaf(g, r_lookup(Rq, N, n, x + 1, k, yf), gt);
+                const float2 g0 = *reinterpret_cast<const float2 *>(
+                    dRq + ((size_t)((xm << nm) | (k / 2))) * S + y);
+                const float A = c_cone[(1 << n) - 1 + k];
+                const float2 rv = rin ? ld2(Rq + ((size_t)(((x + 1) << n) | k)) * S, yf, S, true)
+                                      : make_float2(0.f, 0.f);
+                const float g0x = 0.5f * g0.x, g0y = 0.5f * g0.y;
+                gl0 = fmaf(g0x, A, gl0); gl1 = fmaf(g0y, A, gl1);
+                gt0 = fmaf(g0x, rv.x, gt0); gt1 = fmaf(g0y, rv.y, gt1);
             }
         }
-        // (c) merge up of T_{n+1} from T_n (Eq. 18-20), H = 2^n.
+        // (c) merge up of T_{n+1} from T_n (Eq. 18-20), H = 2^n (n >= 2: even shifts).
         if (a.has_up) {
             const int H = 1 << n;
             const int odirs = 2 * H + 1;
@@ -558,11 +606,12 @@ __device__ void body_dT(const DTArgs &a, unsigned tile, int U) {
                     const int kb = v == 0 ? k : (v == 1 ? k + 1 : k - 1);
                     if (ko < 0 || ko > 2 * H) continue;
                     const float wgt = v == 0 ? 1.f : 0.5f;
-                    float2 f = (yf >= 0 && yf < S) ? far[(size_t)kb * S + yf]
-                                                   : make_float2(0.f, 1.f);
-                    float2 g = g0[(size_t)ko * S + y];
-                    gl = fmaf(wgt, g.x, gl);
-                    gt = fmaf(wgt, fmaf(g.x, f.x, g.y * f.y), gt);
+                    const float4 f = far_pair(far + (size_t)kb * S, yf, S);
+                    const float4 g = ld_pair(g0 + (size_t)ko * S + y);
+                    gl0 = fmaf(wgt, g.x, gl0);
+                    gt0 = fmaf(wgt, fmaf(g.x, f.x, g.y * f.y), gt0);
+                    gl1 = fmaf(wgt, g.z, gl1);
+                    gt1 = fmaf(wgt, fmaf(g.z, f.z, g.w * f.w), gt1);
                 }
             } else {
                 // far role: outputs (2k, near k), (2k+1, near k+1), (2k-1, near k-1),
@@ -576,14 +625,17 @@ __device__ void body_dT(const DTArgs &a, unsigned tile, int U) {
                     const float wgt = v == 0 ? 1.f : 0.5f;
                     const int yo = y - (2 * ka - H);
                     if (yo < 0 || yo >= S) continue;
-                    float tn = nearp[(size_t)ka * S + yo].y;
-                    float2 g = g0[(size_t)ko * S + yo];
-                    gl = fmaf(wgt * g.x, tn, gl);
-                    gt = fmaf(wgt * g.y, tn, gt);
+                    const float4 tn = ld_pair(nearp + (size_t)ka * S + yo);
+                    const float4 g = ld_pair(g0 + (size_t)ko * S + yo);
+                    gl0 = fmaf(wgt * g.x, tn.y, gl0);
+                    gt0 = fmaf(wgt * g.y, tn.y, gt0);
+                    gl1 = fmaf(wgt * g.z, tn.w, gl1);
+                    gt1 = fmaf(wgt * g.w, tn.w, gt1);
                 }
             }
         }
-        a.dT[q * a.en + (size_t)r * S + y] = make_float2(gl, gt);
+        *reinterpret_cast<float4 *>(a.dT + q * a.en + (size_t)r * S + y) =
+            make_float4(gl0, gt0, gl1, gt1);
     }
 }
 
@@ -597,60 +649,144 @@ __device__ __forceinline__ float cell_dphi(float tau) {
     return (tau + (1.f + tau) * expm1f(-tau)) / (tau * tau);
 }
 
-// Adjoint of the traced levels: per frame cell, every traced interval that
-// crosses it (gather form), then d/d(eps, sigma) of that cell's interval.  A
-// trace is the fold of cell intervals c_1..c_m (Eq. 7), so with prefix
-// transmittance P_j: dL/dL_j = P_j, dL/dT_j = P_j L(c_j+1..m), dT/dT_j =
-// P_j T(c_j+1..m).
-__device__ void body_seed_adj(const SeedAdjArgs &a, unsigned tile, int U) {
-    const int N = a.N, S = 1 << N;
-    const size_t SS = (size_t)S * S;
-    for (int uu = 0; uu < U; ++uu) {
-        const size_t idx = ((size_t)tile * U + uu) * 256 + threadIdx.x;
-        if (idx >= 4 * SS) return;
-        const int w = (int)(idx & (S - 1));
-        const unsigned row = (unsigned)(idx >> N);
-        const int q = row >> N;
-        const int u = row & (S - 1);
-        const float *E = frame_src(q, a.eps, a.epsT);
-        const float *G = frame_src(q, a.sig, a.sigT);
-        const size_t me = (size_t)frame_row(q, u, S) * S + w;
-        const float e_me = E[me], s_me = G[me];
-        float ae = 0.f, as = 0.f;
-        for (int n = 0; n < kTracedLevels; ++n) {
-            const float2 *dTq = (n == 0 ? a.dT0 : n == 1 ? a.dT1 : a.dT2) +
-                                q * (n == 0 ? a.e0 : n == 1 ? a.e1 : a.e2);
-            const int dirs = (1 << n) + 1;
-            for (int k = 0; k < dirs; ++k) {
-                const int sid = stencil_id(n, k);
-                const int len = c_st_len[sid];
-                for (int j = 0; j < len; ++j) {
-                    const int up = u - c_st_du[sid][j], wp = w - c_st_dw[sid][j];
-                    if (up < 0 || (up & ((1 << n) - 1)) || wp < 0 || wp >= S) continue;
-                    const float2 g = dTq[((size_t)(up >> n) * dirs + k) * S + wp];
-                    float pre = 1.f;
-                    float2 suf = make_float2(0.f, 1.f);
-                    for (int i = 0; i < len; ++i) {
-                        if (i == j) continue;
-                        int uc = up + c_st_du[sid][i], wc = wp + c_st_dw[sid][i];
-                        if (uc >= S || wc < 0 || wc >= S) continue;
-                        size_t id = (size_t)frame_row(q, uc, S) * S + wc;
-                        float2 c = cell_interval(E[id], G[id], c_st_ell[sid][i]);
-                        if (i < j) pre *= c.y;
-                        else suf = merge(suf, c);
-                    }
-                    const float ell = c_st_ell[sid][j];
-                    const float tau = s_me * ell;
-                    const float dl = g.x * pre;
-                    const float dt = pre * fmaf(g.x, suf.x, g.y * suf.y);
-                    ae = fmaf(dl, ell * cell_phi(tau), ae);
-                    as = fmaf(dl, e_me * ell * ell * cell_dphi(tau), as);
-                    as = fmaf(dt, -ell * expf(-tau), as);
-                }
-            }
+// Adjoint of the traced levels, for all four quadrants of one 16x16 image
+// tile, written straight to d eps and d sigma.  Each traced ray is the fold of
+// half pieces c_1..c_m (Eq. 7), so with the prefix transmittance P_j:
+//   dL/dL_j = P_j,  dL/dT_j = P_j L(c_j+1..m),  dT/dT_j = P_j T(c_j+1..m).
+// Per (quadrant, level): phase A takes every ray whose probe lies within 4
+// pixels before the tile (those are the rays that can cross it), folds its
+// pieces forwards and backwards and stores (dLoss/dL_j, dLoss/dT_j) per piece
+// in LDS slots; phase B lets each pixel of the tile sum the slots of the
+// pieces that lie in it, in a fixed order, times d(L_j, T_j)/d(eps, sigma) of
+// its own half-length interval.  The LDS interval tile carries an 8-pixel
+// halo: probes up to 4 pixels off the tile, pieces up to 4 beyond the probe.
+constexpr int kAdjTile = 16, kAdjHalo = 8;
+constexpr int kAdjSpan = kAdjTile + 2 * kAdjHalo;     // 32
+constexpr int kAdjPitch = kAdjSpan + 1;
+constexpr int kAdjProbeRows = kAdjTile + 8;           // probe w offsets -4 .. 19
+constexpr int kAdjSlots = (kAdjTile + 4) / 4 * kAdjProbeRows * 5 * 8;  // level 2: 4800
+
+// LDS index of the frame pixel at offsets (du, dw) from the tile's frame origin.
+__device__ __forceinline__ int adj_lds(int q, int du, int dw) {
+    const int last = kAdjTile - 1 + kAdjHalo;  // 23
+    int lr, lc;
+    if (q == 0) { lr = dw + kAdjHalo; lc = du + kAdjHalo; }
+    else if (q == 1) { lr = dw + kAdjHalo; lc = last - du; }
+    else if (q == 2) { lr = du + kAdjHalo; lc = dw + kAdjHalo; }
+    else { lr = last - du; lc = dw + kAdjHalo; }
+    return lr * kAdjPitch + lc;
+}
+
+template <int n>
+__device__ __forceinline__ void seed_adj_level(const float2 *iv, float2 *slot,
+                                               const SeedAdjArgs &a, int q, int r0, int c0,
+                                               const float (&dl)[3], const float (&ds)[3],
+                                               const float (&dt)[3], float &ae, float &as) {
+    constexpr int dirs = (1 << n) + 1, pieces = 2 << n;
+    constexpr int pcols = (kAdjTile + 4) >> n;
+    constexpr int traces = pcols * kAdjProbeRows * dirs;
+    const int S = 1 << a.N;
+    const int u_lo = q == 0 ? c0 : q == 1 ? S - kAdjTile - c0 : q == 2 ? r0 : S - kAdjTile - r0;
+    const int w_lo = q < 2 ? r0 : c0;
+    const float2 *dTq = (n == 0 ? a.dT0 : n == 1 ? a.dT1 : a.dT2) +
+                        (size_t)q * (n == 0 ? a.e0 : n == 1 ? a.e1 : a.e2);
+    // phase A: per-piece adjoints of every ray that can cross the tile
+    for (int t = threadIdx.x; t < traces; t += 256) {
+        const int k = t % dirs, pr = (t / dirs) % kAdjProbeRows, pc = t / (dirs * kAdjProbeRows);
+        const int du_p = (pc << n) - 4, dw_p = pr - 4;
+        const int pu = u_lo + du_p, pw = w_lo + dw_p;
+        float2 g = make_float2(0.f, 0.f);
+        if (pu >= 0 && pu < S && pw >= 0 && pw < S)
+            g = dTq[((size_t)(pu >> n) * dirs + k) * S + pw];
+        const int sid = (n == 0 ? 0 : n == 1 ? 2 : 5) + k;
+        float2 c[pieces];
+#pragma unroll
+        for (int j = 0; j < pieces; ++j)
+            c[j] = iv[c_hp_len[sid][j] * (kAdjSpan * kAdjPitch) +
+                      adj_lds(q, du_p + c_hp_du[sid][j], dw_p + c_hp_dw[sid][j])];
+        float pre[pieces];
+        float P = 1.f;
+#pragma unroll
+        for (int j = 0; j < pieces; ++j) {
+            pre[j] = P;
+            P *= c[j].y;
         }
-        a.dE[q * SS + (size_t)u * S + w] = ae;
-        a.dS[q * SS + (size_t)u * S + w] = as;
+        float2 suf = make_float2(0.f, 1.f);
+#pragma unroll
+        for (int j = pieces - 1; j >= 0; --j) {
+            slot[t * pieces + j] =
+                make_float2(g.x * pre[j], pre[j] * fmaf(g.x, suf.x, g.y * suf.y));
+            suf = merge(c[j], suf);
+        }
+    }
+    __syncthreads();
+    // phase B: each pixel of the tile sums the pieces that lie in it
+    const int pix = threadIdx.x;
+    const int pu_l = q == 0 ? (pix % kAdjTile) : q == 1 ? kAdjTile - 1 - (pix % kAdjTile)
+                   : q == 2 ? (pix / kAdjTile) : kAdjTile - 1 - (pix / kAdjTile);
+    const int pw_l = q < 2 ? (pix / kAdjTile) : (pix % kAdjTile);
+#pragma unroll
+    for (int k = 0; k < dirs; ++k) {
+        const int sid = (n == 0 ? 0 : n == 1 ? 2 : 5) + k;
+#pragma unroll
+        for (int j = 0; j < pieces; ++j) {
+            const int du_p = pu_l - c_hp_du[sid][j];  // probe offset from the tile origin
+            const int dw_p = pw_l - c_hp_dw[sid][j];
+            if ((du_p + 4) & ((1 << n) - 1)) continue;  // not a probe of level n
+            const int t = (((du_p + 4) >> n) * kAdjProbeRows + dw_p + 4) * dirs + k;
+            const float2 v = slot[t * pieces + j];
+            const int L = c_hp_len[sid][j];
+            ae = fmaf(v.x, dl[L], ae);
+            as = fmaf(v.x, ds[L], fmaf(v.y, dt[L], as));
+        }
+    }
+    __syncthreads();
+}
+
+__device__ void body_seed_adj(const SeedAdjArgs &a, unsigned tile) {
+    __shared__ float2 iv[3 * kAdjSpan * kAdjPitch];
+    __shared__ float2 slot[kAdjSlots];
+    const int S = 1 << a.N;
+    const int tiles = (S + kAdjTile - 1) / kAdjTile;
+    const int r0 = (int)(tile / tiles) * kAdjTile, c0 = (int)(tile % tiles) * kAdjTile;
+    for (int i = threadIdx.x; i < kAdjSpan * kAdjSpan; i += 256) {
+        const int lr = i / kAdjSpan, lc = i % kAdjSpan;
+        const int r = r0 - kAdjHalo + lr, c = c0 - kAdjHalo + lc;
+        float e = 0.f, g = 0.f;
+        if (r >= 0 && r < S && c >= 0 && c < S) {
+            e = a.eps[(size_t)r * S + c];
+            g = a.sig[(size_t)r * S + c];
+        }
+        const int l = lr * kAdjPitch + lc;
+        iv[l] = cell_interval(e, g, 0.5f);
+        iv[kAdjSpan * kAdjPitch + l] = cell_interval(e, g, kH2);
+        iv[2 * kAdjSpan * kAdjPitch + l] = cell_interval(e, g, kQ5);
+    }
+    // this thread's pixel and its derivatives for the three half lengths
+    const int pr = threadIdx.x / kAdjTile, pc = threadIdx.x % kAdjTile;
+    const int r = r0 + pr, c = c0 + pc;
+    const bool inside = r < S && c < S;
+    const float e_me = inside ? a.eps[(size_t)r * S + c] : 0.f;
+    const float s_me = inside ? a.sig[(size_t)r * S + c] : 0.f;
+    const float lens[3] = {0.5f, kH2, kQ5};
+    float dl[3], ds[3], dt[3];
+#pragma unroll
+    for (int L = 0; L < 3; ++L) {
+        const float ell = lens[L], tau = s_me * ell;
+        dl[L] = ell * cell_phi(tau);
+        ds[L] = e_me * ell * ell * cell_dphi(tau);
+        dt[L] = -ell * expf(-tau);
+    }
+    __syncthreads();
+    float ae = 0.f, as = 0.f;
+    for (int q = 0; q < 4; ++q) {
+        seed_adj_level<0>(iv, slot, a, q, r0, c0, dl, ds, dt, ae, as);
+        seed_adj_level<1>(iv, slot, a, q, r0, c0, dl, ds, dt, ae, as);
+        seed_adj_level<2>(iv, slot, a, q, r0, c0, dl, ds, dt, ae, as);
+    }
+    if (inside) {
+        a.dE[(size_t)r * S + c] = ae;
+        a.dS[(size_t)r * S + c] = as;
     }
 }
 
@@ -664,7 +800,7 @@ __device__ __forceinline__ void run_phase(const Phase &p, unsigned tile) {
         case PH_GATHER_ADJ: body_gather_adj(p.a.ga, tile); break;
         case PH_DOWN_ADJ: body_merge_down_adj(p.a.da, tile, p.U); break;
         case PH_DT: body_dT(p.a.dt, tile, p.U); break;
-        case PH_SEED_ADJ: body_seed_adj(p.a.sa, tile, p.U); break;
+        case PH_SEED_ADJ: body_seed_adj(p.a.sa, tile); break;
         default: break;
     }
 }
@@ -682,10 +818,10 @@ HRC_ELEMENTWISE_KERNEL(hrc_merge_up, body_merge_up, up)
 HRC_ELEMENTWISE_KERNEL(hrc_merge_down, body_merge_down, down)
 HRC_ELEMENTWISE_KERNEL(hrc_merge_down_adj, body_merge_down_adj, da)
 HRC_ELEMENTWISE_KERNEL(hrc_interval_adj, body_dT, dt)
-HRC_ELEMENTWISE_KERNEL(hrc_seed_adj, body_seed_adj, sa)
 #undef HRC_ELEMENTWISE_KERNEL
 
 __global__ __launch_bounds__(256) void hrc_seed(Phase p) { body_seed(p.a.seed, blockIdx.x); }
+__global__ __launch_bounds__(256) void hrc_seed_adj(Phase p) { body_seed_adj(p.a.sa, blockIdx.x); }
 __global__ __launch_bounds__(256) void hrc_transpose(Phase p) { body_transpose(p.a.tr, blockIdx.x); }
 __global__ __launch_bounds__(256) void hrc_frame_sum(Phase p) { body_frame_sum(p.a.fs, blockIdx.x); }
 __global__ __launch_bounds__(256) void hrc_gather_adj(Phase p) { body_gather_adj(p.a.ga, blockIdx.x); }
@@ -808,10 +944,13 @@ unsigned phase_tiles(const Phase &p) {
         case PH_GATHER_ADJ: return 4 * t32 * t32;
         case PH_SEED: return t32 * t32;
         case PH_UP: return cdiv((size_t)p.a.up.nq * t_level_entries(N, p.a.up.n) / 2, per);
-        case PH_DT: return cdiv(4 * t_level_entries(N, p.a.dt.n), per);
+        case PH_DT: return cdiv(4 * t_level_entries(N, p.a.dt.n) / 2, per);
         case PH_DOWN: return cdiv((size_t)p.a.down.nq * SS / 2, per);
-        case PH_DOWN_ADJ:
-        case PH_SEED_ADJ: return cdiv(4 * SS, per);
+        case PH_DOWN_ADJ: return cdiv(4 * SS / 2, per);
+        case PH_SEED_ADJ: {
+            const unsigned t16 = (unsigned)((S + 15) / 16);
+            return t16 * t16;
+        }
     }
     return 0;
 }
