@@ -115,15 +115,14 @@ hrc_status hrc_backward(hrc_context *ctx, int log2_size,
 
 /* Pass kinds reported by hrc_profile_solve. */
 typedef enum {
-    HRC_PASS_TRANSPOSE = 0,   /* transposed copies of the inputs for two quadrants */
-    HRC_PASS_SEED = 1,        /* traced levels T_0..T_2 (Section 4.2) */
-    HRC_PASS_MERGE_UP = 2,    /* T_n from T_(n-1) (Eq. 18-20) */
-    HRC_PASS_MERGE_DOWN = 3,  /* R_n from R_(n+1), T_n, T_(n+1) (Eq. 14-17) */
-    HRC_PASS_FRAME_SUM = 4,   /* quadrant gather into F, or gradient sum onto the image */
-    HRC_PASS_GATHER_ADJ = 5,
-    HRC_PASS_MERGE_DOWN_ADJ = 6,
-    HRC_PASS_INTERVAL_ADJ = 7,
-    HRC_PASS_SEED_ADJ = 8
+    HRC_PASS_SEED = 0,        /* traced levels T_0..T_2 (Section 4.2) */
+    HRC_PASS_MERGE_UP = 1,    /* T_n from T_(n-1) (Eq. 18-20) */
+    HRC_PASS_MERGE_DOWN = 2,  /* R_n from R_(n+1), T_n, T_(n+1) (Eq. 14-17) */
+    HRC_PASS_FRAME_SUM = 3,   /* quadrant gather into F (Algorithm 1, Lighting) */
+    HRC_PASS_GATHER_ADJ = 4,  /* adjoint of the gather */
+    HRC_PASS_MERGE_DOWN_ADJ = 5,
+    HRC_PASS_INTERVAL_ADJ = 6,
+    HRC_PASS_SEED_ADJ = 7
 } hrc_pass_kind;
 
 /* Runs one hrc_forward (grad_fluence == NULL) or one hrc_backward (then

@@ -25,10 +25,10 @@ HRC_FLAG_QUADRANTS_1 = 0x10
 HRC_FLAG_QUADRANTS_2 = 0x20
 HRC_FLAG_QUADRANTS_4 = 0x30
 HRC_FLAG_QUADRANTS_MASK = 0x30
-PASS_NAMES = ["transpose", "seed", "merge_up", "merge_down", "frame_sum", "gather_adj",
+PASS_NAMES = ["seed", "merge_up", "merge_down", "frame_sum", "gather_adj",
               "merge_down_adj", "interval_adj", "seed_adj"]
 # Kernel symbol of each pass kind (what a profiler shows).
-PASS_KERNELS = ["hrc_transpose", "hrc_seed", "hrc_merge_up", "hrc_merge_down", "hrc_frame_sum",
+PASS_KERNELS = ["hrc_seed", "hrc_merge_up", "hrc_merge_down", "hrc_frame_sum",
                 "hrc_gather_adj", "hrc_merge_down_adj", "hrc_interval_adj", "hrc_seed_adj"]
 
 # Every function the header declares, with (restype, argtypes).

@@ -28,13 +28,15 @@ struct Plan {
     std::vector<Phase> phases;     // all scenes, each scene's passes in order
     std::vector<unsigned> seg_start;
     std::vector<int> seg_phase;
+    std::vector<int> seg_step;
+    std::vector<unsigned> step_items;
     unsigned total_items = 0;
 };
 
 // Elements per thread for a phase so that it splits into at most `target`
-// tiles (tiles of 256*U outputs); fixed-shape phases keep their 32x32 tiles.
+// tiles (tiles of 256*U outputs); fixed-shape phases keep their own tiles.
 void size_tiles(Phase &p, int target) {
-    if (p.kind == PH_TRANSPOSE || p.kind == PH_SEED || p.kind == PH_FRAME_SUM ||
+    if (p.kind == PH_SEED || p.kind == PH_SEED_ADJ || p.kind == PH_FRAME_SUM ||
         p.kind == PH_GATHER_ADJ)
         return;
     p.U = 1;
@@ -43,25 +45,29 @@ void size_tiles(Phase &p, int target) {
     p.U = (int)std::max(1u, std::min(U, 64u));
 }
 
-// Interleave the scenes' phase chains: step t holds phase t of every scene
-// that has one, so every phase is queued after the phase it depends on.
+// Step t holds phase t of every scene that has one; every phase depends only
+// on the previous phase of its scene, hence only on the previous step.
 void order_items(Plan &pl, const std::vector<int> &first, const std::vector<int> &count) {
     pl.seg_start.clear();
     pl.seg_phase.clear();
+    pl.seg_step.clear();
+    pl.step_items.clear();
     unsigned pos = 0;
     int max_count = 0;
     for (int c : count) max_count = std::max(max_count, c);
     for (int t = 0; t < max_count; ++t) {
+        unsigned in_step = 0;
         for (size_t s = 0; s < first.size(); ++s) {
             if (t >= count[s]) continue;
             const int gi = first[s] + t;
-            Phase &p = pl.phases[gi];
-            p.dep = t > 0 ? gi - 1 : -1;
-            p.dep_tiles = t > 0 ? phase_tiles(pl.phases[gi - 1]) : 0;
+            const unsigned tiles = phase_tiles(pl.phases[gi]);
             pl.seg_start.push_back(pos);
             pl.seg_phase.push_back(gi);
-            pos += phase_tiles(p);
+            pl.seg_step.push_back(t);
+            pos += tiles;
+            in_step += tiles;
         }
+        pl.step_items.push_back(in_step);
     }
     pl.total_items = pos;
 }
@@ -126,8 +132,12 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
     off += align256(max_phases * sizeof(unsigned));
     const size_t seg_phase_off = off;
     off += align256(max_phases * sizeof(int));
-    const size_t sched_off = off;  // counter, done[] per phase, error word
-    off += align256((max_phases + 2) * sizeof(unsigned));
+    const size_t seg_step_off = off;
+    off += align256(max_phases * sizeof(int));
+    const size_t step_items_off = off;
+    off += align256(kMaxPhases * sizeof(unsigned));
+    const size_t sched_off = off;  // counter, done[] per step, error word
+    off += align256((kMaxPhases + 2) * sizeof(unsigned));
     b->dmem_bytes = off;
     if (hipMalloc(&b->dmem, b->dmem_bytes) != hipSuccess) {
         b->dmem = nullptr;
@@ -157,30 +167,33 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
     Phase *d_phases = reinterpret_cast<Phase *>(b->dmem + phases_off);
     unsigned *d_seg_start = reinterpret_cast<unsigned *>(b->dmem + seg_start_off);
     int *d_seg_phase = reinterpret_cast<int *>(b->dmem + seg_phase_off);
-    unsigned *d_counter = reinterpret_cast<unsigned *>(b->dmem + sched_off);
-    unsigned *d_done = d_counter + 1;
+    int *d_seg_step = reinterpret_cast<int *>(b->dmem + seg_step_off);
+    unsigned *d_step_items = reinterpret_cast<unsigned *>(b->dmem + step_items_off);
+    unsigned *d_sched = reinterpret_cast<unsigned *>(b->dmem + sched_off);
 
     hipStream_t cap = nullptr;
     if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
         free_batch(b);
         return HRC_ERR_HIP;
     }
+    BatchTables tables{};
     auto upload = [&](int target) -> bool {
         for (Phase &p : pl.phases) size_tiles(p, target);
         order_items(pl, first, np);
-        return hipMemcpyAsync(d_phases, pl.phases.data(), pl.phases.size() * sizeof(Phase),
-                              hipMemcpyHostToDevice, cap) == hipSuccess &&
-               hipMemcpyAsync(d_seg_start, pl.seg_start.data(),
-                              pl.seg_start.size() * sizeof(unsigned), hipMemcpyHostToDevice,
-                              cap) == hipSuccess &&
-               hipMemcpyAsync(d_seg_phase, pl.seg_phase.data(), pl.seg_phase.size() * sizeof(int),
-                              hipMemcpyHostToDevice, cap) == hipSuccess &&
+        tables = BatchTables{d_phases, d_seg_start, d_seg_phase, d_seg_step, d_step_items,
+                             (int)pl.seg_start.size(), (int)pl.step_items.size(), pl.total_items};
+        auto h2d = [&](void *dst, const void *src, size_t bytes) {
+            return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, cap) == hipSuccess;
+        };
+        return h2d(d_phases, pl.phases.data(), pl.phases.size() * sizeof(Phase)) &&
+               h2d(d_seg_start, pl.seg_start.data(), pl.seg_start.size() * sizeof(unsigned)) &&
+               h2d(d_seg_phase, pl.seg_phase.data(), pl.seg_phase.size() * sizeof(int)) &&
+               h2d(d_seg_step, pl.seg_step.data(), pl.seg_step.size() * sizeof(int)) &&
+               h2d(d_step_items, pl.step_items.data(), pl.step_items.size() * sizeof(unsigned)) &&
                hipStreamSynchronize(cap) == hipSuccess;
     };
     auto run = [&]() -> bool {
-        return launch_persistent(d_phases, d_seg_start, d_seg_phase, (int)pl.seg_start.size(),
-                                 pl.total_items, d_counter, d_done,
-                                 (unsigned)pl.phases.size(), b->grid, cap) == hipSuccess;
+        return launch_persistent(tables, d_sched, b->grid, cap) == hipSuccess;
     };
 
     // ---- autotune: the largest tile count per phase (hence elements per
@@ -205,7 +218,7 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
     if (fine) {
         // the scheduler's error word (a dependency wait that timed out)
         unsigned err = 0;
-        fine = hipMemcpy(&err, d_done + pl.phases.size(), sizeof(unsigned),
+        fine = hipMemcpy(&err, d_sched + 1 + pl.step_items.size(), sizeof(unsigned),
                          hipMemcpyDeviceToHost) == hipSuccess && err == 0;
     }
     if (e0) (void)hipEventDestroy(e0);

@@ -32,14 +32,12 @@ struct Layout {
     int N = 0;
     size_t S = 0;
     int group = 4;                       // quadrants whose pyramids are live at once
-    size_t fieldsT = 0;                  // backward: eps^T then sigma^T, [S][S] float each
     size_t t_level[kMaxLog2 + 2] = {};   // T_n: `group` quadrants x t_level_entries float2
     size_t r_level[kMaxLog2 + 1] = {};   // R buffers: `group` quadrants x S^2 float each
     int r_count = 0;                     // 2 (forward ping-pong) or N (keeps every R_n)
     size_t r0_all = 0;                   // forward: R_0 of all four quadrants
     size_t dt_level[kMaxLog2 + 2] = {};  // backward: adjoint pyramid
     size_t dr_level[kMaxLog2 + 1] = {};  // backward: adjoint cascades
-    size_t dfield = 0;                   // backward: per-quadrant frame gradients
     size_t total = 0;
 };
 
@@ -53,16 +51,11 @@ struct Ws {
     float2 *dT(int n) const { return reinterpret_cast<float2 *>(base + L.dt_level[n]); }
     float *R(int i) const { return reinterpret_cast<float *>(base + L.r_level[i]); }
     float *dR(int i) const { return reinterpret_cast<float *>(base + L.dr_level[i]); }
-    float *epsT() const { return reinterpret_cast<float *>(base + L.fieldsT); }
-    float *sigT() const { return epsT() + L.S * L.S; }
-    float *dE() const { return reinterpret_cast<float *>(base + L.dfield); }
-    float *dS() const { return dE() + kQuadrants * L.S * L.S; }
     float *R0all() const { return reinterpret_cast<float *>(base + L.r0_all); }
 };
 
 // ---- Arguments of each phase (one pass over one level of one scene) -------
 
-struct TransposeArgs { const float *a, *b; float *aT, *bT; int N; };
 // Forward passes run on a group of nq quadrants q0 .. q0+nq-1 whose buffers
 // start at the pointers given (quadrant q0 first).
 struct SeedArgs {
@@ -108,19 +101,16 @@ struct SeedAdjArgs {
 };
 
 enum PhaseKind {
-    PH_TRANSPOSE = 0, PH_SEED, PH_UP, PH_DOWN, PH_FRAME_SUM, PH_GATHER_ADJ,
+    PH_SEED = 0, PH_UP, PH_DOWN, PH_FRAME_SUM, PH_GATHER_ADJ,
     PH_DOWN_ADJ, PH_DT, PH_SEED_ADJ, PH_KIND_COUNT
 };
 
 // One pass.  U = elements per thread of the elementwise phases (a tile covers
-// 256*U consecutive outputs); dep / dep_tiles are used by the batch kernel.
+// 256*U consecutive outputs).
 struct Phase {
     int kind = 0;
     int U = 1;
-    int dep = -1;
-    unsigned dep_tiles = 0;
     union A {
-        TransposeArgs tr;
         SeedArgs seed;
         UpArgs up;
         DownArgs down;
@@ -147,10 +137,20 @@ int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, cons
 unsigned phase_tiles(const Phase &p);
 hipError_t upload_cone_table(const float *host_table);
 hipError_t launch_phase(const Phase &p, hipStream_t s);
-hipError_t launch_persistent(const Phase *phases, const unsigned *seg_start,
-                             const int *seg_phase, int nseg, unsigned total_items,
-                             unsigned *counter, unsigned *done, unsigned nphases, int grid,
-                             hipStream_t s);
+// Device tables of a planned batch: segment i covers the items
+// [seg_start[i], seg_start[i+1]) = the tiles of phase seg_phase[i], in step
+// seg_step[i]; step_items[t] counts the items of step t.
+struct BatchTables {
+    const Phase *phases;
+    const unsigned *seg_start;
+    const int *seg_phase;
+    const int *seg_step;
+    const unsigned *step_items;
+    int nseg, nsteps;
+    unsigned total_items;
+};
+// sched: counter, done[nsteps], error word (cleared by a kernel before the run).
+hipError_t launch_persistent(const BatchTables &t, unsigned *sched, int grid, hipStream_t s);
 hipError_t persistent_occupancy(int *blocks_per_cu);
 hipError_t launch_validate(const float *a, const float *b, size_t n, int *flag,
                            hipStream_t s);

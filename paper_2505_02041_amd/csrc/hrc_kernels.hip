@@ -84,10 +84,6 @@ __device__ __forceinline__ float2 merge(float2 n, float2 f) {
     return make_float2(fmaf(n.y, f.x, n.x), n.y * f.y);
 }
 
-__device__ __forceinline__ const float *frame_src(int q, const float *img, const float *imgT) {
-    return q < 2 ? imgT : img;
-}
-
 __device__ __forceinline__ int frame_row(int q, int u, int S) {
     return (q & 1) ? S - 1 - u : u;
 }
@@ -110,32 +106,6 @@ __device__ __forceinline__ float r_lookup(const float *Rq, int N, int m, int c, 
 // consecutive output elements per tile (U elements per thread, 256 apart).
 // ---------------------------------------------------------------------------
 
-// Transposed copies of the two input fields (for the +-x frames), 32x32 tiles.
-__device__ void body_transpose(const TransposeArgs &a, unsigned tile) {
-    __shared__ float ta[32][33];
-    __shared__ float tb[32][33];
-    const int S = 1 << a.N;
-    const int tiles = (S + 31) >> 5;
-    const int tr = tile / tiles, tc = tile % tiles;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    for (int i = ty; i < 32; i += 8) {
-        int r = tr * 32 + i, c = tc * 32 + tx;
-        if (r < S && c < S) {
-            ta[i][tx] = a.a[(size_t)r * S + c];
-            tb[i][tx] = a.b[(size_t)r * S + c];
-        }
-    }
-    __syncthreads();
-    for (int i = ty; i < 32; i += 8) {
-        int r = tc * 32 + i, c = tr * 32 + tx;  // output row = input column
-        if (r < S && c < S) {
-            a.aT[(size_t)r * S + c] = ta[tx][i];
-            a.bT[(size_t)r * S + c] = tb[tx][i];
-        }
-    }
-    __syncthreads();
-}
-
 // Traced levels T_0, T_1, T_2 (Algorithm 1, first loop), for all four
 // quadrants from one 32x32 image tile.
 //
@@ -155,17 +125,17 @@ constexpr int kSeedPitch = kSeedSpan + 1;             // padded row pitch of the
 // Half pieces of the traced rays: (du, dw) from the probe's pixel and the
 // half-length id (0: 1/2, 1: sqrt(2)/2, 2: sqrt(5)/4), in order from the probe.
 // Stencil id: n = 0 -> k, n = 1 -> 2 + k, n = 2 -> 5 + k; 2^(n+1) pieces each.
-__constant__ signed char c_hp_du[10][8] = {
+constexpr signed char kHpDu[10][8] = {
     {0, 1}, {0, 1},
     {0, 1, 1, 2}, {0, 1, 1, 2}, {0, 1, 1, 2},
     {0, 1, 1, 2, 2, 3, 3, 4}, {0, 1, 1, 2, 2, 3, 3, 4}, {0, 1, 1, 2, 2, 3, 3, 4},
     {0, 1, 1, 2, 2, 3, 3, 4}, {0, 1, 1, 2, 2, 3, 3, 4}};
-__constant__ signed char c_hp_dw[10][8] = {
+constexpr signed char kHpDw[10][8] = {
     {0, -1}, {0, 1},
     {0, -1, -1, -2}, {0, 0, 0, 0}, {0, 1, 1, 2},
     {0, -1, -1, -2, -2, -3, -3, -4}, {0, 0, -1, -1, -1, -1, -2, -2},
     {0, 0, 0, 0, 0, 0, 0, 0}, {0, 0, 1, 1, 1, 1, 2, 2}, {0, 1, 1, 2, 2, 3, 3, 4}};
-__constant__ unsigned char c_hp_len[10][8] = {
+constexpr unsigned char kHpLen[10][8] = {
     {1, 1}, {1, 1},
     {1, 1, 1, 1}, {0, 0, 0, 0}, {1, 1, 1, 1},
     {1, 1, 1, 1, 1, 1, 1, 1}, {2, 2, 2, 2, 2, 2, 2, 2}, {0, 0, 0, 0, 0, 0, 0, 0},
@@ -200,16 +170,18 @@ __device__ __forceinline__ void seed_level_rays(const float2 *iv, const SeedArgs
         float2 acc = make_float2(0.f, 1.f);
 #pragma unroll
         for (int j = 0; j < pieces; ++j) {
-            const int off = c_hp_len[sid][j] * (kSeedSpan * kSeedPitch) + c_hp_du[sid][j] * su +
-                            c_hp_dw[sid][j] * sw;
+            const int off = kHpLen[sid][j] * (kSeedSpan * kSeedPitch) + kHpDu[sid][j] * su +
+                            kHpDw[sid][j] * sw;
             acc = merge(acc, iv[base + off]);
         }
         out[slot * qoff + ((size_t)(u >> n) * dirs + k) * S + w] = acc;
     }
 }
 
-__device__ void body_seed(const SeedArgs &a, unsigned tile) {
-    __shared__ float2 iv[3 * kSeedSpan * kSeedPitch];
+constexpr int kSeedLds = 3 * kSeedSpan * kSeedPitch * 8;
+
+__device__ void body_seed(const SeedArgs &a, unsigned tile, char *lds) {
+    float2 *iv = reinterpret_cast<float2 *>(lds);
     const int S = 1 << a.N;
     const int tiles = (S + kSeedTile - 1) / kSeedTile;
     const int r0 = (int)(tile / tiles) * kSeedTile, c0 = (int)(tile % tiles) * kSeedTile;
@@ -355,8 +327,10 @@ __device__ void body_merge_down(const DownArgs &a, unsigned tile, int U) {
 // per-quadrant frame fields back onto the image.  Two fields at once when
 // src2 is set.  32x32 tiles through LDS keep the +-x (transposed) reads
 // coalesced.
-__device__ void body_frame_sum(const FrameSumArgs &a, unsigned tile) {
-    __shared__ float fs_tile[2][32][33];
+constexpr int kFrameSumLds = 2 * 32 * 33 * 4;
+
+__device__ void body_frame_sum(const FrameSumArgs &a, unsigned tile, char *lds) {
+    float (*fs_tile)[32][33] = reinterpret_cast<float (*)[32][33]>(lds);
     const int N = a.N, S = 1 << N;
     const size_t SS = (size_t)S * S;
     const int tiles = (S + 31) >> 5;
@@ -413,8 +387,10 @@ __device__ void body_frame_sum(const FrameSumArgs &a, unsigned tile) {
 
 // Transpose of the gather: dR_0[q][x][y] = dF at the image pixel of frame
 // point (x - 1, y), and 0 at x = 0.  Tile = q * tiles^2 + (x tile, y tile).
-__device__ void body_gather_adj(const GatherAdjArgs &a, unsigned tile) {
-    __shared__ float ga_tile[32][33];
+constexpr int kGatherAdjLds = 32 * 33 * 4;
+
+__device__ void body_gather_adj(const GatherAdjArgs &a, unsigned tile, char *lds) {
+    float (*ga_tile)[33] = reinterpret_cast<float (*)[33]>(lds);
     const int N = a.N, S = 1 << N;
     const size_t SS = (size_t)S * S;
     const int tiles = (S + 31) >> 5;
@@ -653,99 +629,92 @@ __device__ __forceinline__ float cell_dphi(float tau) {
 // tile, written straight to d eps and d sigma.  Each traced ray is the fold of
 // half pieces c_1..c_m (Eq. 7), so with the prefix transmittance P_j:
 //   dL/dL_j = P_j,  dL/dT_j = P_j L(c_j+1..m),  dT/dT_j = P_j T(c_j+1..m).
-// Per (quadrant, level): phase A takes every ray whose probe lies within 4
-// pixels before the tile (those are the rays that can cross it), folds its
-// pieces forwards and backwards and stores (dLoss/dL_j, dLoss/dT_j) per piece
-// in LDS slots; phase B lets each pixel of the tile sum the slots of the
-// pieces that lie in it, in a fixed order, times d(L_j, T_j)/d(eps, sigma) of
-// its own half-length interval.  The LDS interval tile carries an 8-pixel
-// halo: probes up to 4 pixels off the tile, pieces up to 4 beyond the probe.
-constexpr int kAdjTile = 16, kAdjHalo = 8;
-constexpr int kAdjSpan = kAdjTile + 2 * kAdjHalo;     // 32
+// Pixel p receives piece j of direction k of level n from the probe
+// p - (du_j, dw_j), and that probe exists only when u - du_j is a multiple of
+// 2^n: for each residue of u mod 2^n exactly two of the 2^(n+1) pieces qualify.
+// Each wave therefore takes the 64 pixels of one residue class (in the frame
+// of the quadrant), so every test below is uniform over the wave, refolds the
+// two rays per direction from the interval tile in LDS (pieces relative to the
+// pixel stay within 4 pixels, so the tile needs a 4-pixel halo), and adds
+// dLoss/dL_j d L_j/d(eps, sigma) + dLoss/dT_j d T_j/d(eps, sigma).  The four
+// quadrants' partial sums meet in LDS and are added in a fixed order.
+constexpr int kAdjTile = 16, kAdjHalo = 4;
+constexpr int kAdjSpan = kAdjTile + 2 * kAdjHalo;     // 24
 constexpr int kAdjPitch = kAdjSpan + 1;
-constexpr int kAdjProbeRows = kAdjTile + 8;           // probe w offsets -4 .. 19
-constexpr int kAdjSlots = (kAdjTile + 4) / 4 * kAdjProbeRows * 5 * 8;  // level 2: 4800
 
-// LDS index of the frame pixel at offsets (du, dw) from the tile's frame origin.
-__device__ __forceinline__ int adj_lds(int q, int du, int dw) {
-    const int last = kAdjTile - 1 + kAdjHalo;  // 23
-    int lr, lc;
-    if (q == 0) { lr = dw + kAdjHalo; lc = du + kAdjHalo; }
-    else if (q == 1) { lr = dw + kAdjHalo; lc = last - du; }
-    else if (q == 2) { lr = du + kAdjHalo; lc = dw + kAdjHalo; }
-    else { lr = last - du; lc = dw + kAdjHalo; }
-    return lr * kAdjPitch + lc;
+// Half piece i of the traced ray of level n and direction k covers the pixel
+// at (du, dw) from its probe's pixel: the piece midpoint lies at fraction
+// (i + 1/2)/2^(n+1) of v_n(k) = (2^n, 2k - 2^n) from the probe's centre, so
+// du = floor((2i + 3)/4) and dw = floor((2^(n+1) + (2i+1)(2k - 2^n))/2^(n+2)).
+// The piece length is sqrt(2)/2 on diagonals (k = 0, 2^n), 1/2 on the axis
+// (k = 2^(n-1)) and sqrt(5)/4 otherwise (n = 2, k = 1, 3).
+__device__ __forceinline__ int piece_du(int i) { return (2 * i + 3) >> 2; }
+__device__ __forceinline__ int piece_dw(int n, int k, int i) {
+    return ((2 << n) + (2 * i + 1) * (2 * k - (1 << n))) >> (n + 2);
+}
+__device__ __forceinline__ int piece_len(int n, int k) {
+    return (k == 0 || k == (1 << n)) ? 1 : (2 * k == (1 << n) ? 0 : 2);
 }
 
+// The two pieces of level n that land on a pixel whose frame u has residue
+// rho modulo 2^n (piece j covers u offset (2j + 3) / 4 from its probe).
+__device__ __forceinline__ int adj_piece(int n, int rho, int which) {
+    if (n == 0) return which;
+    if (n == 1) return rho == 0 ? (which ? 3 : 0) : (which ? 2 : 1);
+    return rho == 0 ? (which ? 7 : 0) : 2 * rho - 1 + which;
+}
+
+// Level n's contribution to pixel (u, w): for each direction, the two rays that
+// put a piece on the pixel (their two dLoss/dT loads issued together), each
+// refolded around that piece.  Rays whose probe lies outside the grid add 0.
 template <int n>
-__device__ __forceinline__ void seed_adj_level(const float2 *iv, float2 *slot,
-                                               const SeedAdjArgs &a, int q, int r0, int c0,
-                                               const float (&dl)[3], const float (&ds)[3],
-                                               const float (&dt)[3], float &ae, float &as) {
+__device__ __forceinline__ void seed_adj_level(const SeedAdjArgs &a, int q, int u, int w,
+                                               const float2 *iv, int base, int su, int sw,
+                                               int r, const float *der, float &ae, float &as) {
     constexpr int dirs = (1 << n) + 1, pieces = 2 << n;
-    constexpr int pcols = (kAdjTile + 4) >> n;
-    constexpr int traces = pcols * kAdjProbeRows * dirs;
     const int S = 1 << a.N;
-    const int u_lo = q == 0 ? c0 : q == 1 ? S - kAdjTile - c0 : q == 2 ? r0 : S - kAdjTile - r0;
-    const int w_lo = q < 2 ? r0 : c0;
     const float2 *dTq = (n == 0 ? a.dT0 : n == 1 ? a.dT1 : a.dT2) +
                         (size_t)q * (n == 0 ? a.e0 : n == 1 ? a.e1 : a.e2);
-    // phase A: per-piece adjoints of every ray that can cross the tile
-    for (int t = threadIdx.x; t < traces; t += 256) {
-        const int k = t % dirs, pr = (t / dirs) % kAdjProbeRows, pc = t / (dirs * kAdjProbeRows);
-        const int du_p = (pc << n) - 4, dw_p = pr - 4;
-        const int pu = u_lo + du_p, pw = w_lo + dw_p;
-        float2 g = make_float2(0.f, 0.f);
-        if (pu >= 0 && pu < S && pw >= 0 && pw < S)
-            g = dTq[((size_t)(pu >> n) * dirs + k) * S + pw];
-        const int sid = (n == 0 ? 0 : n == 1 ? 2 : 5) + k;
-        float2 c[pieces];
-#pragma unroll
-        for (int j = 0; j < pieces; ++j)
-            c[j] = iv[c_hp_len[sid][j] * (kAdjSpan * kAdjPitch) +
-                      adj_lds(q, du_p + c_hp_du[sid][j], dw_p + c_hp_dw[sid][j])];
-        float pre[pieces];
-        float P = 1.f;
-#pragma unroll
-        for (int j = 0; j < pieces; ++j) {
-            pre[j] = P;
-            P *= c[j].y;
-        }
-        float2 suf = make_float2(0.f, 1.f);
-#pragma unroll
-        for (int j = pieces - 1; j >= 0; --j) {
-            slot[t * pieces + j] =
-                make_float2(g.x * pre[j], pre[j] * fmaf(g.x, suf.x, g.y * suf.y));
-            suf = merge(c[j], suf);
-        }
-    }
-    __syncthreads();
-    // phase B: each pixel of the tile sums the pieces that lie in it
-    const int pix = threadIdx.x;
-    const int pu_l = q == 0 ? (pix % kAdjTile) : q == 1 ? kAdjTile - 1 - (pix % kAdjTile)
-                   : q == 2 ? (pix / kAdjTile) : kAdjTile - 1 - (pix / kAdjTile);
-    const int pw_l = q < 2 ? (pix / kAdjTile) : (pix % kAdjTile);
-#pragma unroll
+#pragma unroll 1
     for (int k = 0; k < dirs; ++k) {
-        const int sid = (n == 0 ? 0 : n == 1 ? 2 : 5) + k;
+        const int L = piece_len(n, k);
+        const float2 *ivL = iv + L * (kAdjSpan * kAdjPitch) + base;
+        float2 g[2];
 #pragma unroll
-        for (int j = 0; j < pieces; ++j) {
-            const int du_p = pu_l - c_hp_du[sid][j];  // probe offset from the tile origin
-            const int dw_p = pw_l - c_hp_dw[sid][j];
-            if ((du_p + 4) & ((1 << n) - 1)) continue;  // not a probe of level n
-            const int t = (((du_p + 4) >> n) * kAdjProbeRows + dw_p + 4) * dirs + k;
-            const float2 v = slot[t * pieces + j];
-            const int L = c_hp_len[sid][j];
-            ae = fmaf(v.x, dl[L], ae);
-            as = fmaf(v.x, ds[L], fmaf(v.y, dt[L], as));
+        for (int which = 0; which < 2; ++which) {
+            const int j = adj_piece(n, r, which);
+            const int pu = u - piece_du(j), pw = w - piece_dw(n, k, j);
+            const bool ok = pu >= 0 && pw >= 0 && pw < S;
+            const float2 v = dTq[((size_t)(ok ? pu >> n : 0) * dirs + k) * S + (ok ? pw : 0)];
+            g[which] = ok ? v : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int which = 0; which < 2; ++which) {
+            const int j = adj_piece(n, r, which);  // uniform over the wave
+            const int du_j = piece_du(j), dw_j = piece_dw(n, k, j);
+            float pre = 1.f;
+            float2 suf = make_float2(0.f, 1.f);
+#pragma unroll
+            for (int i = pieces - 1; i >= 0; --i) {
+                if (i == j) continue;
+                const float2 c = ivL[(piece_du(i) - du_j) * su + (piece_dw(n, k, i) - dw_j) * sw];
+                if (i > j) suf = merge(c, suf);
+                else pre *= c.y;
+            }
+            const float dl = g[which].x * pre;                               // dLoss/dL_j
+            const float dt = pre * fmaf(g[which].x, suf.x, g[which].y * suf.y);  // dLoss/dT_j
+            ae = fmaf(dl, der[3 * L], ae);
+            as = fmaf(dl, der[3 * L + 1], fmaf(dt, der[3 * L + 2], as));
         }
     }
-    __syncthreads();
 }
 
-__device__ void body_seed_adj(const SeedAdjArgs &a, unsigned tile) {
-    __shared__ float2 iv[3 * kAdjSpan * kAdjPitch];
-    __shared__ float2 slot[kAdjSlots];
+constexpr int kSeedAdjLds = 3 * kAdjSpan * kAdjPitch * 8 + 256 * 9 * 4 + 4 * 256 * 8;
+
+__device__ void body_seed_adj(const SeedAdjArgs &a, unsigned tile, char *lds) {
+    float2 *iv = reinterpret_cast<float2 *>(lds);
+    float *der = reinterpret_cast<float *>(iv + 3 * kAdjSpan * kAdjPitch);  // [256][3 lengths][3]
+    float2 *part = reinterpret_cast<float2 *>(der + 256 * 9);               // [4][256]
     const int S = 1 << a.N;
     const int tiles = (S + kAdjTile - 1) / kAdjTile;
     const int r0 = (int)(tile / tiles) * kAdjTile, c0 = (int)(tile % tiles) * kAdjTile;
@@ -762,45 +731,73 @@ __device__ void body_seed_adj(const SeedAdjArgs &a, unsigned tile) {
         iv[kAdjSpan * kAdjPitch + l] = cell_interval(e, g, kH2);
         iv[2 * kAdjSpan * kAdjPitch + l] = cell_interval(e, g, kQ5);
     }
-    // this thread's pixel and its derivatives for the three half lengths
-    const int pr = threadIdx.x / kAdjTile, pc = threadIdx.x % kAdjTile;
-    const int r = r0 + pr, c = c0 + pc;
-    const bool inside = r < S && c < S;
-    const float e_me = inside ? a.eps[(size_t)r * S + c] : 0.f;
-    const float s_me = inside ? a.sig[(size_t)r * S + c] : 0.f;
-    const float lens[3] = {0.5f, kH2, kQ5};
-    float dl[3], ds[3], dt[3];
+    {
+        // d(L, T)/d(eps, sigma) of this thread's pixel for the three half lengths
+        const int r = r0 + threadIdx.x / kAdjTile, c = c0 + threadIdx.x % kAdjTile;
+        const bool inside = r < S && c < S;
+        const float e_me = inside ? a.eps[(size_t)r * S + c] : 0.f;
+        const float s_me = inside ? a.sig[(size_t)r * S + c] : 0.f;
+        const float lens[3] = {0.5f, kH2, kQ5};
 #pragma unroll
-    for (int L = 0; L < 3; ++L) {
-        const float ell = lens[L], tau = s_me * ell;
-        dl[L] = ell * cell_phi(tau);
-        ds[L] = e_me * ell * ell * cell_dphi(tau);
-        dt[L] = -ell * expf(-tau);
+        for (int L = 0; L < 3; ++L) {
+            const float ell = lens[L], tau = s_me * ell;
+            der[threadIdx.x * 9 + 3 * L] = ell * cell_phi(tau);                 // dL/d eps
+            der[threadIdx.x * 9 + 3 * L + 1] = e_me * ell * ell * cell_dphi(tau);  // dL/d sigma
+            der[threadIdx.x * 9 + 3 * L + 2] = -ell * expf(-tau);               // dT/d sigma
+        }
     }
     __syncthreads();
-    float ae = 0.f, as = 0.f;
+    // wave v takes the frame rows u_l = v, v+4, v+8, v+12 (one residue of u mod 4)
+    const int v = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int u_l = v + 4 * (lane >> 4), w_l = lane & 15;
     for (int q = 0; q < 4; ++q) {
-        seed_adj_level<0>(iv, slot, a, q, r0, c0, dl, ds, dt, ae, as);
-        seed_adj_level<1>(iv, slot, a, q, r0, c0, dl, ds, dt, ae, as);
-        seed_adj_level<2>(iv, slot, a, q, r0, c0, dl, ds, dt, ae, as);
+        const int u_lo = q == 0 ? c0 : q == 1 ? S - kAdjTile - c0 : q == 2 ? r0 : S - kAdjTile - r0;
+        const int w_lo = q < 2 ? r0 : c0;
+        // image pixel (tile-local) of frame pixel (u_l, w_l)
+        int pr, pc;
+        if (q < 2) { pr = w_l; pc = q == 0 ? u_l : kAdjTile - 1 - u_l; }
+        else { pc = w_l; pr = q == 2 ? u_l : kAdjTile - 1 - u_l; }
+        const int u = u_lo + u_l, w = w_lo + w_l;
+        const int base = (pr + kAdjHalo) * kAdjPitch + pc + kAdjHalo;
+        const int su = q == 0 ? 1 : q == 1 ? -1 : q == 2 ? kAdjPitch : -kAdjPitch;
+        const int sw = q < 2 ? kAdjPitch : 1;
+        const int rho = (u_lo + v) & 3;  // u mod 4, uniform over the wave
+        float ae = 0.f, as = 0.f;
+        if (u >= 0 && u < S && w < S) {
+            const float *d = der + (pr * kAdjTile + pc) * 9;
+            seed_adj_level<0>(a, q, u, w, iv, base, su, sw, 0, d, ae, as);
+            seed_adj_level<1>(a, q, u, w, iv, base, su, sw, rho & 1, d, ae, as);
+            seed_adj_level<2>(a, q, u, w, iv, base, su, sw, rho, d, ae, as);
+        }
+        part[q * 256 + pr * kAdjTile + pc] = make_float2(ae, as);
     }
-    if (inside) {
-        a.dE[(size_t)r * S + c] = ae;
-        a.dS[(size_t)r * S + c] = as;
+    __syncthreads();
+    const int r = r0 + threadIdx.x / kAdjTile, c = c0 + threadIdx.x % kAdjTile;
+    if (r < S && c < S) {
+        float2 t = part[threadIdx.x];
+        for (int q = 1; q < 4; ++q) {
+            const float2 o = part[q * 256 + threadIdx.x];
+            t.x += o.x;
+            t.y += o.y;
+        }
+        a.dE[(size_t)r * S + c] = t.x;
+        a.dS[(size_t)r * S + c] = t.y;
     }
+    __syncthreads();
 }
 
-__device__ __forceinline__ void run_phase(const Phase &p, unsigned tile) {
+constexpr int kMaxLds = kSeedAdjLds > kSeedLds ? kSeedAdjLds : kSeedLds;
+
+__device__ __forceinline__ void run_phase(const Phase &p, unsigned tile, char *lds) {
     switch (p.kind) {
-        case PH_TRANSPOSE: body_transpose(p.a.tr, tile); break;
-        case PH_SEED: body_seed(p.a.seed, tile); break;
+        case PH_SEED: body_seed(p.a.seed, tile, lds); break;
         case PH_UP: body_merge_up(p.a.up, tile, p.U); break;
         case PH_DOWN: body_merge_down(p.a.down, tile, p.U); break;
-        case PH_FRAME_SUM: body_frame_sum(p.a.fs, tile); break;
-        case PH_GATHER_ADJ: body_gather_adj(p.a.ga, tile); break;
+        case PH_FRAME_SUM: body_frame_sum(p.a.fs, tile, lds); break;
+        case PH_GATHER_ADJ: body_gather_adj(p.a.ga, tile, lds); break;
         case PH_DOWN_ADJ: body_merge_down_adj(p.a.da, tile, p.U); break;
         case PH_DT: body_dT(p.a.dt, tile, p.U); break;
-        case PH_SEED_ADJ: body_seed_adj(p.a.sa, tile); break;
+        case PH_SEED_ADJ: body_seed_adj(p.a.sa, tile, lds); break;
         default: break;
     }
 }
@@ -820,80 +817,101 @@ HRC_ELEMENTWISE_KERNEL(hrc_merge_down_adj, body_merge_down_adj, da)
 HRC_ELEMENTWISE_KERNEL(hrc_interval_adj, body_dT, dt)
 #undef HRC_ELEMENTWISE_KERNEL
 
-__global__ __launch_bounds__(256) void hrc_seed(Phase p) { body_seed(p.a.seed, blockIdx.x); }
-__global__ __launch_bounds__(256) void hrc_seed_adj(Phase p) { body_seed_adj(p.a.sa, blockIdx.x); }
-__global__ __launch_bounds__(256) void hrc_transpose(Phase p) { body_transpose(p.a.tr, blockIdx.x); }
-__global__ __launch_bounds__(256) void hrc_frame_sum(Phase p) { body_frame_sum(p.a.fs, blockIdx.x); }
-__global__ __launch_bounds__(256) void hrc_gather_adj(Phase p) { body_gather_adj(p.a.ga, blockIdx.x); }
+__global__ __launch_bounds__(256) void hrc_seed(Phase p) {
+    __shared__ __align__(16) char lds[kSeedLds];
+    body_seed(p.a.seed, blockIdx.x, lds);
+}
+__global__ __launch_bounds__(256) void hrc_seed_adj(Phase p) {
+    __shared__ __align__(16) char lds[kSeedAdjLds];
+    body_seed_adj(p.a.sa, blockIdx.x, lds);
+}
+__global__ __launch_bounds__(256) void hrc_frame_sum(Phase p) {
+    __shared__ __align__(16) char lds[kFrameSumLds];
+    body_frame_sum(p.a.fs, blockIdx.x, lds);
+}
+__global__ __launch_bounds__(256) void hrc_gather_adj(Phase p) {
+    __shared__ __align__(16) char lds[kGatherAdjLds];
+    body_gather_adj(p.a.ga, blockIdx.x, lds);
+}
 
 // ---------------------------------------------------------------------------
-// Persistent batch kernel.  Work items are (phase, tile) pairs in a global
-// order in which every phase comes after the phase it depends on (the previous
-// phase of the same scene).  Blocks claim items in that order from one counter;
-// before running an item a block waits until every tile of the dependency
-// phase is done.  A block only ever waits on items claimed before its own, by
-// blocks that are already running, so the queue always drains.  Completion is
-// published with an agent-scope release (every wave) and read with an
-// agent-scope acquire, which makes the producer's stores visible across XCDs.
+// Persistent batch kernel.  Work items are (phase, tile) pairs grouped in
+// steps: step t holds phase t of every scene that has one, so each phase
+// depends only on the step before it.  Blocks claim items in order from one
+// counter.  A block counts the items it finishes in the current step and
+// publishes that count (one agent-scope release, then one atomic add) when it
+// claims its first item of a later step or runs out of items; before its first
+// item of step t it waits until step t-1 is complete (agent-scope acquire).
+// Publishing before waiting means no block ever waits while holding
+// unpublished work, and every item of step t-1 was claimed before any item of
+// step t by a block that is running, so the queue always drains (no grid-wide
+// co-residency is assumed).  Memory ordering costs one release and one acquire
+// per block and step rather than per item.
 // ---------------------------------------------------------------------------
 
 constexpr unsigned kMaxSpins = 1u << 20;  // about a second of polling
 
-__global__ __launch_bounds__(256) void hrc_persistent(const Phase *__restrict__ phases,
-                                                    const unsigned *__restrict__ seg_start,
-                                                    const int *__restrict__ seg_phase,
-                                                    int nseg, unsigned total_items,
-                                                    unsigned *counter, unsigned *done,
-                                                    unsigned *error) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void hrc_persistent(const BatchTables t, unsigned *counter,
+                                                      unsigned *done, unsigned *error) {
+    __shared__ __align__(16) char lds[kMaxLds];
     __shared__ unsigned s_item;
-    int finished = -1;  // phase of the item this block completed last (uniform)
+    int cur_step = -1;
+    unsigned completed = 0;
     for (;;) {
-        // One thread publishes the previous item and claims the next one.  Both
-        // sit in a single thread-0 region at the top of the loop, followed by
-        // a barrier: with the publish at the end of the loop body instead, the
-        // compiler turns the thread-0 path around the back edge into an early
-        // exit of lane 0 from an inner loop, and the other lanes re-enter the
-        // barriers with a stale item forever.
-        if (threadIdx.x == 0) {
-            if (finished >= 0)
-                __hip_atomic_fetch_add(&done[finished], 1u, __ATOMIC_RELEASE,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-            s_item = atomicAdd(counter, 1u);
-        }
+        // claim (one thread), then make the claimed item a scalar for the block
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
         __syncthreads();
         const unsigned item = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
-        if (item >= total_items) break;
-        // segment containing the item: seg_start is increasing, seg_start[0] = 0
-        int lo = 0, hi = nseg - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (seg_start[mid] <= item) lo = mid;
-            else hi = mid - 1;
+        int seg = 0, step = t.nsteps;
+        if (item < t.total_items) {
+            int lo = 0, hi = t.nseg - 1;  // last segment starting at or before the item
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (t.seg_start[mid] <= item) lo = mid;
+                else hi = mid - 1;
+            }
+            seg = lo;
+            step = __builtin_amdgcn_readfirstlane(t.seg_step[lo]);
         }
-        const int pi = __builtin_amdgcn_readfirstlane(seg_phase[lo]);
-        const Phase &p = phases[pi];
-        const unsigned tile = __builtin_amdgcn_readfirstlane(item - seg_start[lo]);
-        if (threadIdx.x == 0 && p.dep >= 0) {
-            // Bounded wait: a dependency that never completes (a planning bug)
-            // raises the error word and lets the queue drain instead of hanging.
-            const unsigned need = p.dep_tiles;
-            unsigned spins = 0;
-            while (__hip_atomic_load(&done[p.dep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
-                   need) {
-                if (++spins > kMaxSpins) {
-                    __hip_atomic_store(error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
+        if (step != cur_step) {
+            if (cur_step >= 0) {
+                // publish this block's items of the step it is leaving
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __syncthreads();
+                if (threadIdx.x == 0)
+                    __hip_atomic_fetch_add(&done[cur_step], completed, __ATOMIC_RELEASE,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                __syncthreads();
+            }
+            cur_step = step;
+            completed = 0;
+            if (step >= t.nsteps) break;
+            if (step > 0) {
+                if (threadIdx.x == 0) {
+                    // Bounded wait: a step that never completes (a planning bug)
+                    // raises the error word and lets the queue drain instead of
+                    // hanging.
+                    const unsigned need = t.step_items[step - 1];
+                    unsigned spins = 0;
+                    while (__hip_atomic_load(&done[step - 1], __ATOMIC_ACQUIRE,
+                                             __HIP_MEMORY_SCOPE_AGENT) < need) {
+                        if (++spins > kMaxSpins) {
+                            __hip_atomic_store(error, 1u, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(2);
+                    }
                 }
-                __builtin_amdgcn_s_sleep(2);
+                __syncthreads();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
         }
-        __syncthreads();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        run_phase(p, tile);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        finished = pi;
+        const int pi = __builtin_amdgcn_readfirstlane(t.seg_phase[seg]);
+        const unsigned tile = __builtin_amdgcn_readfirstlane(item - t.seg_start[seg]);
+        run_phase(t.phases[pi], tile, lds);
+        ++completed;
     }
 }
 
@@ -923,7 +941,6 @@ unsigned phase_tiles(const Phase &p) {
     auto cdiv = [](size_t a, size_t b) { return (unsigned)((a + b - 1) / b); };
     const int N = [&] {
         switch (p.kind) {
-            case PH_TRANSPOSE: return p.a.tr.N;
             case PH_SEED: return p.a.seed.N;
             case PH_UP: return p.a.up.N;
             case PH_DOWN: return p.a.down.N;
@@ -939,7 +956,6 @@ unsigned phase_tiles(const Phase &p) {
     const unsigned t32 = (unsigned)((S + 31) / 32);
     const size_t per = (size_t)256 * (p.U > 0 ? p.U : 1);
     switch (p.kind) {
-        case PH_TRANSPOSE: return t32 * t32;
         case PH_FRAME_SUM: return t32 * t32;
         case PH_GATHER_ADJ: return 4 * t32 * t32;
         case PH_SEED: return t32 * t32;
@@ -964,7 +980,6 @@ hipError_t launch_phase(const Phase &p, hipStream_t s) {
     if (tiles == 0) return hipSuccess;
     void (*k)(Phase) = nullptr;
     switch (p.kind) {
-        case PH_TRANSPOSE: k = hrc_transpose; break;
         case PH_SEED: k = hrc_seed; break;
         case PH_UP: k = hrc_merge_up; break;
         case PH_DOWN: k = hrc_merge_down; break;
@@ -979,16 +994,13 @@ hipError_t launch_phase(const Phase &p, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_persistent(const Phase *phases, const unsigned *seg_start,
-                             const int *seg_phase, int nseg, unsigned total_items,
-                             unsigned *counter, unsigned *done, unsigned nphases, int grid,
-                             hipStream_t s) {
-    unsigned n = nphases + 2;  // counter, done[nphases], error word: contiguous
-    hipLaunchKernelGGL(hrc_clear_u32, dim3((n + 255) / 256), dim3(256), 0, s, counter, n);
+hipError_t launch_persistent(const BatchTables &t, unsigned *sched, int grid, hipStream_t s) {
+    const unsigned n = 2u + (unsigned)t.nsteps;  // counter, done[nsteps], error word
+    hipLaunchKernelGGL(hrc_clear_u32, dim3((n + 255) / 256), dim3(256), 0, s, sched, n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(hrc_persistent, dim3(grid), dim3(256), 0, s, phases, seg_start, seg_phase,
-                       nseg, total_items, counter, done, done + nphases);
+    hipLaunchKernelGGL(hrc_persistent, dim3(grid), dim3(256), 0, s, t, sched, sched + 1,
+                       sched + 1 + t.nsteps);
     return hipGetLastError();
 }
 

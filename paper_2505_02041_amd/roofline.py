@@ -23,8 +23,6 @@ def pass_bytes(name: str, N: int, n: int = -1, two_fields: bool = False) -> floa
     S = 1 << N
     SS = float(S * S)
     q = 4
-    if name == "transpose":
-        return 16 * SS
     if name == "seed":
         # the two fields read once for all four quadrants, T_0..T_2 written
         return 8 * SS + q * 8 * (_t(S, 0) + _t(S, 1) + _t(S, 2))
@@ -53,7 +51,8 @@ def pass_bytes(name: str, N: int, n: int = -1, two_fields: bool = False) -> floa
             b += q * 4 * SS  # even columns of dR_{n-1} and R_n
         return b
     if name == "seed_adj":
-        return q * 8 * SS + q * 8 * (_t(S, 0) + _t(S, 1) + _t(S, 2)) + q * 8 * SS
+        # fields read once, dT_0..dT_2 of the four quadrants read, d eps and d sigma written
+        return 8 * SS + q * 8 * (_t(S, 0) + _t(S, 1) + _t(S, 2)) + 8 * SS
     raise ValueError(name)
 
 
@@ -72,10 +71,9 @@ def forward_bytes(N: int) -> float:
 
 def backward_bytes(N: int) -> float:
     """hrc_backward: the forward recomputed (without the gather) plus the reverse."""
-    b = forward_bytes(N) - pass_bytes("frame_sum", N) + pass_bytes("transpose", N)
+    b = forward_bytes(N) - pass_bytes("frame_sum", N)
     b += pass_bytes("gather_adj", N)
     b += sum(pass_bytes("merge_down_adj", N, n) for n in range(N - 1))
     b += sum(pass_bytes("interval_adj", N, n) for n in range(N, -1, -1))
     b += pass_bytes("seed_adj", N)
-    b += pass_bytes("frame_sum", N, two_fields=True)
     return b
