@@ -32,7 +32,26 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--only-forward", action="store_true",
                     help="time the forward only (for profiler runs)")
+    ap.add_argument("--only-backward", action="store_true",
+                    help="run hrc_backward only, --steps times (for profiler runs)")
     return ap.parse_args()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
+    profile (scaled by the plain-copy calibration), or None when there is no
+    such profile or the kernel source has changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hrc_merge_down_1024_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, rec["source"])
+    if rec["kernel"] != kernel or not os.path.exists(src):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def main():
@@ -76,6 +95,13 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
+    if args.only_backward:
+        for _ in range(args.warmup + args.steps):
+            ctx.hrc_backward(eps, sig, dF)
+        torch.cuda.synchronize()
+        print(json.dumps({"backward_steps": args.steps}))
+        return
+
     # ---- forward: the metric ------------------------------------------------
     log(f"forward {S}x{S}: {args.warmup} warm-up, {args.steps} timed steps")
     fwd_s = timed(lambda: ctx.hrc_forward(eps, sig, F), args.steps, args.warmup)
@@ -109,6 +135,8 @@ def main():
     passes = {k: {"launches_per_step": v[2] // reps, "ms_per_step": v[0] / reps,
                   "GBps": v[1] / (v[0] * 1e-3) / 1e9} for k, v in per.items()}
     step_bytes = forward_bytes(N)
+    kernel_name = _lib.PASS_KERNELS[_lib.PASS_NAMES.index(dom)]
+    traffic = measured_traffic(kernel_name)
 
     out = {
         "metric": "Mpixel/s fluence fwd at 1024^2 (fwd+bwd, ms/frame and HBM roofline alongside)",
@@ -134,12 +162,12 @@ def main():
         "copy_GBps": 2 * nbytes / copy_s / 1e9,
         "roofline": {
             "bound": "hbm",
-            "kernel": _lib.PASS_KERNELS[_lib.PASS_NAMES.index(dom)],
+            "kernel": kernel_name,
             "achieved": achieved,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": None,
+            "traffic": traffic,
             "avg_launch_us": avg_launch_us,
             "algorithmic_bytes_per_launch": bytes_per_launch,
         },
