@@ -208,7 +208,8 @@ def main():
                         "sequential_fwd_bwd_ms": seq_s * 1e3,
                         "sequential_mpixel_per_s": px / seq_s / 1e6,
                         "speedup_vs_sequential": seq_s / batch_s,
-                        "plan_s": plan_s, "workspace_GB": b.workspace_bytes / 1e9}
+                        "plan_s": plan_s, "workspace_GB": b.workspace_bytes / 1e9,
+                        "autotuned": b.describe()}
         del b, items
         ctx.release_workspaces()
 

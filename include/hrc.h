@@ -67,6 +67,10 @@ typedef enum {
 #define HRC_FLAG_QUADRANTS_2 0x20u
 #define HRC_FLAG_QUADRANTS_4 0x30u
 #define HRC_FLAG_QUADRANTS_MASK 0x30u
+/* hrc_batch_plan only: run the persistent kernel variant 0 (full register
+ * budget) or 1 (64 registers) instead of letting the autotuner choose. */
+#define HRC_FLAG_BATCH_FULL 0x100u
+#define HRC_FLAG_BATCH_DENSE 0x200u
 
 typedef struct hrc_context hrc_context;
 
@@ -156,10 +160,13 @@ typedef struct {
 typedef struct hrc_batch hrc_batch;
 
 /* Plan a batch: copies the scene table, sizes and allocates the batch's own
- * workspace (device memory owned by the batch), picks per-size tile shapes
- * with the autotuner (timing candidate shapes on `stream`), and captures one
+ * workspace (device memory owned by the batch), picks the kernel variant, the
+ * tile sizes and the claim chunk with the autotuner (timing each candidate
+ * launch on a stream of its own, on the caller's buffers), and captures one
  * persistent-kernel launch in a HIP graph.  The scene pointers are baked in:
- * later launches read and write the same buffers.  Synchronises `stream`. */
+ * later launches read and write the same buffers.  flags: 0, or one of
+ * HRC_FLAG_BATCH_FULL / HRC_FLAG_BATCH_DENSE (HRC_ERR_UNSUPPORTED otherwise).
+ * Synchronises `stream` first. */
 hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count,
                           unsigned flags, void *stream, hrc_batch **out);
 
@@ -169,6 +176,15 @@ hrc_status hrc_batch_launch(hrc_batch *batch, void *stream);
 
 /* Bytes of device memory the batch owns (workspace and scheduler state). */
 size_t hrc_batch_workspace_bytes(const hrc_batch *batch);
+
+/* What the autotuner chose for a planned batch: the persistent kernel variant
+ * (0: full register budget, one 1024-thread block per CU; 1: 64 registers,
+ * two blocks per CU), the grid in blocks, the target tile count per pass
+ * (each tile 256 threads), and the tiles-groups a block claims at once (a
+ * group is the four tiles a block runs side by side).  Any output pointer may
+ * be NULL.  Pure host function; HRC_ERR_INVALID_ARG for a NULL batch. */
+hrc_status hrc_batch_describe(const hrc_batch *batch, int *variant, int *grid,
+                              int *target_tiles, int *chunk);
 
 /* Destroy a batch (NULL-safe); frees its device memory and graph. */
 void hrc_batch_destroy(hrc_batch *batch);

@@ -25,6 +25,8 @@ HRC_FLAG_QUADRANTS_1 = 0x10
 HRC_FLAG_QUADRANTS_2 = 0x20
 HRC_FLAG_QUADRANTS_4 = 0x30
 HRC_FLAG_QUADRANTS_MASK = 0x30
+HRC_FLAG_BATCH_FULL = 0x100
+HRC_FLAG_BATCH_DENSE = 0x200
 PASS_NAMES = ["seed", "merge_up", "merge_down", "frame_sum", "gather_adj",
               "merge_down_adj", "interval_adj", "seed_adj"]
 # Kernel symbol of each pass kind (what a profiler shows).
@@ -67,6 +69,10 @@ SIGNATURES = {
                                       ctypes.c_uint, _vp, ctypes.POINTER(_vp)]),
     "hrc_batch_launch": (ctypes.c_int, [_vp, _vp]),
     "hrc_batch_workspace_bytes": (_sz, [_vp]),
+    "hrc_batch_describe": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(ctypes.c_int)]),
     "hrc_batch_destroy": (None, [_vp]),
 }
 

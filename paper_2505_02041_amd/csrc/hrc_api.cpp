@@ -97,7 +97,7 @@ int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, cons
         p = Phase();
         p.kind = PH_SEED;
         p.a.seed = SeedArgs{b.eps, b.sig, w.T(0), w.T(1), w.T(2), t_level_entries(N, 0),
-                            t_level_entries(N, 1), t_level_entries(N, 2), N, q0, G};
+                            t_level_entries(N, 1), t_level_entries(N, 2), N, q0, G, 32};
         add(p);
         for (int n = kTracedLevels; n <= N; ++n) {
             p = Phase();

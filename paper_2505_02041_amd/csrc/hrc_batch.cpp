@@ -19,6 +19,8 @@ struct hrc_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int target_tiles = 0;          // chosen by the autotuner
+    unsigned chunk = 1;            // items per claim, chosen by the autotuner
+    int variant = 0;               // persistent kernel variant, chosen by the autotuner
     int grid = 0;
 };
 
@@ -36,6 +38,7 @@ struct Plan {
 // Elements per thread for a phase so that it splits into at most `target`
 // tiles (tiles of 256*U outputs); fixed-shape phases keep their own tiles.
 void size_tiles(Phase &p, int target) {
+    if (p.kind == PH_SEED) p.a.seed.tile = 16;  // the persistent kernel's seed tile
     if (p.kind == PH_SEED || p.kind == PH_SEED_ADJ || p.kind == PH_FRAME_SUM ||
         p.kind == PH_GATHER_ADJ)
         return;
@@ -60,7 +63,10 @@ void order_items(Plan &pl, const std::vector<int> &first, const std::vector<int>
         for (size_t s = 0; s < first.size(); ++s) {
             if (t >= count[s]) continue;
             const int gi = first[s] + t;
-            const unsigned tiles = phase_tiles(pl.phases[gi]);
+            // whole groups of tiles; the bodies store nothing for tiles past
+            // the phase's own count
+            const unsigned tiles =
+                (phase_tiles(pl.phases[gi]) + kBatchQuarters - 1) / kBatchQuarters;
             pl.seg_start.push_back(pos);
             pl.seg_phase.push_back(gi);
             pl.seg_step.push_back(t);
@@ -102,7 +108,9 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
         if (any && (!ok16(sc.grad_fluence) || !ok16(sc.grad_emission) || !ok16(sc.grad_sigma_t)))
             return HRC_ERR_INVALID_ARG;
     }
-    if (flags != 0) return HRC_ERR_UNSUPPORTED;
+    if ((flags & ~(HRC_FLAG_BATCH_FULL | HRC_FLAG_BATCH_DENSE)) ||
+        flags == (HRC_FLAG_BATCH_FULL | HRC_FLAG_BATCH_DENSE))
+        return HRC_ERR_UNSUPPORTED;
     if (!ctx) return HRC_ERR_INVALID_ARG;
     DeviceGuard g(ctx->device);
     if (!g.ok) return HRC_ERR_HIP;
@@ -136,8 +144,8 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
     off += align256(max_phases * sizeof(int));
     const size_t step_items_off = off;
     off += align256(kMaxPhases * sizeof(unsigned));
-    const size_t sched_off = off;  // counter, done[] per step, error word
-    off += align256((kMaxPhases + 2) * sizeof(unsigned));
+    const size_t sched_off = off;  // claim counter, error word, one count per step
+    off += align256(sched_words(kMaxPhases) * sizeof(unsigned));
     b->dmem_bytes = off;
     if (hipMalloc(&b->dmem, b->dmem_bytes) != hipSuccess) {
         b->dmem = nullptr;
@@ -160,9 +168,12 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
         pl.phases.insert(pl.phases.end(), tmp, tmp + n);
     }
 
-    int per_cu = 0;
-    if (persistent_occupancy(&per_cu) != hipSuccess || per_cu <= 0) per_cu = 1;
-    b->grid = ctx->num_cus * per_cu;
+    int grids[kPersistentVariants];  // resident blocks of each kernel variant
+    for (int v = 0; v < kPersistentVariants; ++v) {
+        int per_cu = 0;
+        if (persistent_occupancy(v, &per_cu) != hipSuccess || per_cu <= 0) per_cu = 1;
+        grids[v] = ctx->num_cus * per_cu;
+    }
 
     Phase *d_phases = reinterpret_cast<Phase *>(b->dmem + phases_off);
     unsigned *d_seg_start = reinterpret_cast<unsigned *>(b->dmem + seg_start_off);
@@ -177,11 +188,12 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
         return HRC_ERR_HIP;
     }
     BatchTables tables{};
-    auto upload = [&](int target) -> bool {
+    auto upload = [&](int target, unsigned chunk) -> bool {
         for (Phase &p : pl.phases) size_tiles(p, target);
         order_items(pl, first, np);
         tables = BatchTables{d_phases, d_seg_start, d_seg_phase, d_seg_step, d_step_items,
-                             (int)pl.seg_start.size(), (int)pl.step_items.size(), pl.total_items};
+                             (int)pl.seg_start.size(), (int)pl.step_items.size(), pl.total_items,
+                             chunk};
         auto h2d = [&](void *dst, const void *src, size_t bytes) {
             return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, cap) == hipSuccess;
         };
@@ -192,39 +204,59 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
                h2d(d_step_items, pl.step_items.data(), pl.step_items.size() * sizeof(unsigned)) &&
                hipStreamSynchronize(cap) == hipSuccess;
     };
+    int variant = 0;
     auto run = [&]() -> bool {
-        return launch_persistent(tables, d_sched, b->grid, cap) == hipSuccess;
+        return launch_persistent(tables, d_sched, grids[variant], variant, cap) == hipSuccess;
     };
 
-    // ---- autotune: the largest tile count per phase (hence elements per
-    // tile) that gives the fastest whole-batch launch ---------------------
-    const int candidates[] = {b->grid, 2 * b->grid, 4 * b->grid, 8 * b->grid};
+    // ---- autotune: the kernel variant (registers vs resident blocks), the
+    // tile count per phase (hence elements per tile) as a multiple of the
+    // resident tile slots, and the claim chunk: the fastest whole-batch
+    // launch wins ----------------------------------------------------------
+    const int mults[] = {1, 2, 4};
+    const unsigned chunks[] = {1u, 4u};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     bool fine = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
     float best_ms = 1e30f;
-    int best = candidates[1];
-    for (int c : candidates) {
-        if (!fine) break;
-        fine = upload(c) && run() && hipStreamSynchronize(cap) == hipSuccess;  // warm-up
-        if (!fine) break;
-        fine = hipEventRecord(e0, cap) == hipSuccess && run() &&
-               hipEventRecord(e1, cap) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
-        float ms = 0.f;
-        if (fine && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
-            best_ms = ms;
-            best = c;
+    int best = grids[0] * kBatchQuarters, best_variant = 0;
+    unsigned best_chunk = 1;
+    for (int v = 0; v < kPersistentVariants && fine; ++v) {
+        if ((flags & HRC_FLAG_BATCH_FULL) && v != 0) continue;
+        if ((flags & HRC_FLAG_BATCH_DENSE) && v != 1) continue;
+        variant = v;
+        for (int mult : mults) {
+            const int target = grids[v] * kBatchQuarters * mult;
+            for (unsigned ch : chunks) {
+                if (!fine) break;
+                fine = upload(target, ch) && run() &&
+                       hipStreamSynchronize(cap) == hipSuccess;  // warm-up
+                if (!fine) break;
+                fine = hipEventRecord(e0, cap) == hipSuccess && run() &&
+                       hipEventRecord(e1, cap) == hipSuccess &&
+                       hipEventSynchronize(e1) == hipSuccess;
+                float ms = 0.f;
+                if (fine && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
+                    best_ms = ms;
+                    best = target;
+                    best_chunk = ch;
+                    best_variant = v;
+                }
+            }
         }
     }
     if (fine) {
         // the scheduler's error word (a dependency wait that timed out)
         unsigned err = 0;
-        fine = hipMemcpy(&err, d_sched + 1 + pl.step_items.size(), sizeof(unsigned),
+        fine = hipMemcpy(&err, d_sched + kSchedStride, sizeof(unsigned),
                          hipMemcpyDeviceToHost) == hipSuccess && err == 0;
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     b->target_tiles = best;
-    if (fine) fine = upload(best);
+    b->chunk = best_chunk;
+    b->variant = variant = best_variant;
+    b->grid = grids[variant];
+    if (fine) fine = upload(best, best_chunk);
 
     // ---- capture one launch in a graph ---------------------------------
     if (fine) fine = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
@@ -253,6 +285,16 @@ hrc_status hrc_batch_launch(hrc_batch *batch, void *stream) {
 
 size_t hrc_batch_workspace_bytes(const hrc_batch *batch) {
     return batch ? batch->dmem_bytes : 0;
+}
+
+hrc_status hrc_batch_describe(const hrc_batch *batch, int *variant, int *grid,
+                              int *target_tiles, int *chunk) {
+    if (!batch) return HRC_ERR_INVALID_ARG;
+    if (variant) *variant = batch->variant;
+    if (grid) *grid = batch->grid;
+    if (target_tiles) *target_tiles = batch->target_tiles;
+    if (chunk) *chunk = (int)batch->chunk;
+    return HRC_OK;
 }
 
 void hrc_batch_destroy(hrc_batch *batch) { free_batch(batch); }

@@ -63,6 +63,7 @@ struct SeedArgs {
     float2 *T0, *T1, *T2;
     size_t e0, e1, e2;  // entries per quadrant of each level
     int N, q0, nq;
+    int tile;           // image tile side: 32 standalone, 16 in the persistent kernel
 };
 struct UpArgs { const float2 *Tp; float2 *T; size_t ep, e; int N, n, nq; };
 struct DownArgs {
@@ -140,18 +141,30 @@ hipError_t launch_phase(const Phase &p, hipStream_t s);
 // Device tables of a planned batch: segment i covers the items
 // [seg_start[i], seg_start[i+1]) = the tiles of phase seg_phase[i], in step
 // seg_step[i]; step_items[t] counts the items of step t.
+// The persistent kernel's blocks hold kBatchQuarters 256-thread quarters, each
+// running one tile; work is scheduled in groups of kBatchQuarters consecutive
+// tiles of one phase (phases padded with empty tiles to whole groups).
+constexpr int kBatchQuarters = 4;
 struct BatchTables {
     const Phase *phases;
-    const unsigned *seg_start;
+    const unsigned *seg_start;   // first group of each segment (one phase of one scene)
     const int *seg_phase;
     const int *seg_step;
-    const unsigned *step_items;
+    const unsigned *step_items;  // groups per step
     int nseg, nsteps;
-    unsigned total_items;
+    unsigned total_items;        // groups in all
+    unsigned chunk;              // groups a block claims at once
 };
-// sched: counter, done[nsteps], error word (cleared by a kernel before the run).
-hipError_t launch_persistent(const BatchTables &t, unsigned *sched, int grid, hipStream_t s);
-hipError_t persistent_occupancy(int *blocks_per_cu);
+// Scheduler words, each in a cache line of its own (kSchedStride words apart):
+// the claim counter, the error word, then one completion count per step.
+constexpr unsigned kSchedStride = 32;
+constexpr size_t sched_words(int nsteps) { return (size_t)kSchedStride * (2 + nsteps); }
+// Clears the scheduler words and launches the persistent kernel.
+// variant 0: full register budget; 1: 64 VGPRs (twice the resident blocks).
+constexpr int kPersistentVariants = 2;
+hipError_t launch_persistent(const BatchTables &t, unsigned *sched, int grid, int variant,
+                             hipStream_t s);
+hipError_t persistent_occupancy(int variant, int *blocks_per_cu);
 hipError_t launch_validate(const float *a, const float *b, size_t n, int *flag,
                            hipStream_t s);
 

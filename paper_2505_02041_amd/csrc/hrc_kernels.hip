@@ -118,9 +118,17 @@ __device__ __forceinline__ float r_lookup(const float *Rq, int N, int m, int c, 
 // plus a 4-pixel halo once into LDS (out-of-grid pixels are vacuum <0, 1>)
 // and then folds the 4 x 4864 rays whose probes lie in the tile; each wave
 // writes two rows of 32 consecutive y of one direction.
-constexpr int kSeedTile = 32, kSeedHalo = 4;
-constexpr int kSeedSpan = kSeedTile + 2 * kSeedHalo;  // 40
-constexpr int kSeedPitch = kSeedSpan + 1;             // padded row pitch of the LDS tile
+// Thread index within a 256-thread work tile.  Every pass body is written for
+// 256 threads; the persistent kernel runs several tiles side by side in one
+// block, one per 256-thread quarter.
+__device__ __forceinline__ int ltid() { return (int)(threadIdx.x & 255u); }
+
+constexpr int kSeedHalo = 4;
+template <int TILE> struct SeedTile {
+    static constexpr int span = TILE + 2 * kSeedHalo;  // tile plus halo
+    static constexpr int pitch = span + 1;            // padded LDS row pitch
+    static constexpr int lds = 3 * span * pitch * 8;  // three intervals per pixel
+};
 
 // Half pieces of the traced rays: (du, dw) from the probe's pixel and the
 // half-length id (0: 1/2, 1: sqrt(2)/2, 2: sqrt(5)/4), in order from the probe.
@@ -142,35 +150,37 @@ constexpr unsigned char kHpLen[10][8] = {
     {2, 2, 2, 2, 2, 2, 2, 2}, {1, 1, 1, 1, 1, 1, 1, 1}};
 
 // Rays of traced level n of quadrant q whose probes lie in the tile.  Rows
-// (k, xl) run with xl fastest, so the two 32-lane halves of a wave share the
-// direction k and the stencil lookups are wave-uniform.
-template <int n>
+// (k, xl) run with xl fastest and a wave covers 64/TILE whole rows of one
+// direction k, so the stencil lookups are wave-uniform.
+template <int TILE, int n>
 __device__ __forceinline__ void seed_level_rays(const float2 *iv, const SeedArgs &a, int q,
                                                 int slot, int r0, int c0) {
-    constexpr int dirs = (1 << n) + 1, cols = kSeedTile >> n, pieces = 2 << n;
+    using G = SeedTile<TILE>;
+    constexpr int dirs = (1 << n) + 1, cols = TILE >> n, pieces = 2 << n;
+    constexpr int lg = TILE == 32 ? 5 : 4;
     const int S = 1 << a.N;
     float2 *out = n == 0 ? a.T0 : n == 1 ? a.T1 : a.T2;
     const size_t qoff = n == 0 ? a.e0 : n == 1 ? a.e1 : a.e2;
     // frame of quadrant q: +x (u, w) = (c, r); -x (S-1-c, r); +y (r, c); -y (S-1-r, c)
-    const int u_lo = q == 0 ? c0 : q == 1 ? S - kSeedTile - c0 : q == 2 ? r0 : S - kSeedTile - r0;
+    const int u_lo = q == 0 ? c0 : q == 1 ? S - TILE - c0 : q == 2 ? r0 : S - TILE - r0;
     const int w_lo = q < 2 ? r0 : c0;
-    const int su = q == 0 ? 1 : q == 1 ? -1 : q == 2 ? kSeedPitch : -kSeedPitch;
-    const int sw = q < 2 ? kSeedPitch : 1;
-    for (int it = threadIdx.x; it < dirs * cols * kSeedTile; it += 256) {
-        const int row = it >> 5;
+    const int su = q == 0 ? 1 : q == 1 ? -1 : q == 2 ? G::pitch : -G::pitch;
+    const int sw = q < 2 ? G::pitch : 1;
+    for (int it = ltid(); it < dirs * cols * TILE; it += 256) {
+        const int row = it >> lg;
         const int k = __builtin_amdgcn_readfirstlane(row / cols);
         const int xl = row % cols;
-        const int u = u_lo + (xl << n), w = w_lo + (it & 31);
+        const int u = u_lo + (xl << n), w = w_lo + (it & (TILE - 1));
         if (u < 0 || u >= S || w >= S) continue;
         int lr, lc;
         if (q < 2) { lr = w - r0; lc = (q == 0 ? u : S - 1 - u) - c0; }
         else { lc = w - c0; lr = (q == 2 ? u : S - 1 - u) - r0; }
-        const int base = (lr + kSeedHalo) * kSeedPitch + lc + kSeedHalo;
+        const int base = (lr + kSeedHalo) * G::pitch + lc + kSeedHalo;
         const int sid = (n == 0 ? 0 : n == 1 ? 2 : 5) + k;
         float2 acc = make_float2(0.f, 1.f);
 #pragma unroll
         for (int j = 0; j < pieces; ++j) {
-            const int off = kHpLen[sid][j] * (kSeedSpan * kSeedPitch) + kHpDu[sid][j] * su +
+            const int off = kHpLen[sid][j] * (G::span * G::pitch) + kHpDu[sid][j] * su +
                             kHpDw[sid][j] * sw;
             acc = merge(acc, iv[base + off]);
         }
@@ -178,31 +188,34 @@ __device__ __forceinline__ void seed_level_rays(const float2 *iv, const SeedArgs
     }
 }
 
-constexpr int kSeedLds = 3 * kSeedSpan * kSeedPitch * 8;
-
+// TILE x TILE image pixels per work tile (32 for the standalone kernel, 16
+// inside the persistent kernel, whose one LDS buffer serves every pass); the
+// per-ray arithmetic is the same for both.
+template <int TILE>
 __device__ void body_seed(const SeedArgs &a, unsigned tile, char *lds) {
+    using G = SeedTile<TILE>;
     float2 *iv = reinterpret_cast<float2 *>(lds);
     const int S = 1 << a.N;
-    const int tiles = (S + kSeedTile - 1) / kSeedTile;
-    const int r0 = (int)(tile / tiles) * kSeedTile, c0 = (int)(tile % tiles) * kSeedTile;
-    for (int i = threadIdx.x; i < kSeedSpan * kSeedSpan; i += 256) {
-        const int lr = i / kSeedSpan, lc = i % kSeedSpan;
+    const int tiles = (S + TILE - 1) / TILE;
+    const int r0 = (int)(tile / tiles) * TILE, c0 = (int)(tile % tiles) * TILE;
+    for (int i = ltid(); i < G::span * G::span; i += 256) {
+        const int lr = i / G::span, lc = i % G::span;
         const int r = r0 - kSeedHalo + lr, c = c0 - kSeedHalo + lc;
         float e = 0.f, g = 0.f;
         if (r >= 0 && r < S && c >= 0 && c < S) {
             e = a.eps[(size_t)r * S + c];
             g = a.sig[(size_t)r * S + c];
         }
-        const int l = lr * kSeedPitch + lc;
+        const int l = lr * G::pitch + lc;
         iv[l] = cell_interval(e, g, 0.5f);
-        iv[kSeedSpan * kSeedPitch + l] = cell_interval(e, g, kH2);
-        iv[2 * kSeedSpan * kSeedPitch + l] = cell_interval(e, g, kQ5);
+        iv[G::span * G::pitch + l] = cell_interval(e, g, kH2);
+        iv[2 * G::span * G::pitch + l] = cell_interval(e, g, kQ5);
     }
     __syncthreads();
     for (int g = 0; g < a.nq; ++g) {
-        seed_level_rays<0>(iv, a, a.q0 + g, g, r0, c0);
-        seed_level_rays<1>(iv, a, a.q0 + g, g, r0, c0);
-        seed_level_rays<2>(iv, a, a.q0 + g, g, r0, c0);
+        seed_level_rays<TILE, 0>(iv, a, a.q0 + g, g, r0, c0);
+        seed_level_rays<TILE, 1>(iv, a, a.q0 + g, g, r0, c0);
+        seed_level_rays<TILE, 2>(iv, a, a.q0 + g, g, r0, c0);
     }
     __syncthreads();
 }
@@ -230,7 +243,7 @@ __device__ void body_merge_up(const UpArgs &a, unsigned tile, int U) {
     const unsigned rpq = (unsigned)(S >> n) * dirs;
     const size_t total = (size_t)a.nq * rpq * (S / 2);
     for (int uu = 0; uu < U; ++uu) {
-        const size_t idx = ((size_t)tile * U + uu) * 256 + threadIdx.x;
+        const size_t idx = ((size_t)tile * U + uu) * 256 + ltid();
         if (idx >= total) return;
         const int y = (int)(idx & (S / 2 - 1)) * 2;
         const unsigned row = (unsigned)(idx >> (N - 1));
@@ -277,7 +290,7 @@ __device__ void body_merge_down(const DownArgs &a, unsigned tile, int U) {
     const size_t total = (size_t)a.nq * (SS / 2);
     const int m = n + 1;
     for (int uu = 0; uu < U; ++uu) {
-        const size_t idx = ((size_t)tile * U + uu) * 256 + threadIdx.x;
+        const size_t idx = ((size_t)tile * U + uu) * 256 + ltid();
         if (idx >= total) return;
         const int y = (int)(idx & (S / 2 - 1)) * 2;
         const unsigned row = (unsigned)(idx >> (N - 1));
@@ -335,7 +348,7 @@ __device__ void body_frame_sum(const FrameSumArgs &a, unsigned tile, char *lds) 
     const size_t SS = (size_t)S * S;
     const int tiles = (S + 31) >> 5;
     const int tr = tile / tiles, tc = tile % tiles;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int tx = ltid() & 31, ty = ltid() >> 5;
     const bool two = a.src2 != nullptr;
     float acc0[4] = {0.f, 0.f, 0.f, 0.f}, acc1[4] = {0.f, 0.f, 0.f, 0.f};
     // +-y quadrants: u = r or S-1-r, w = c: rows read directly.
@@ -397,8 +410,10 @@ __device__ void body_gather_adj(const GatherAdjArgs &a, unsigned tile, char *lds
     const int q = tile / (tiles * tiles);
     const int t2 = tile % (tiles * tiles);
     const int tX = t2 / tiles, tY = t2 % tiles;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    if (q >= 2) {
+    const int tx = ltid() & 31, ty = ltid() >> 5;
+    // Every thread reaches both barriers whatever its tile (tiles of other
+    // passes may share the block); tiles past the four quadrants store nothing.
+    if (q == 2 || q == 3) {
         for (int i = 0; i < 4; ++i) {
             int x = tX * 32 + ty + 8 * i, y = tY * 32 + tx;
             if (x < S && y < S) {
@@ -407,21 +422,23 @@ __device__ void body_gather_adj(const GatherAdjArgs &a, unsigned tile, char *lds
                 a.dR0[q * SS + (size_t)x * S + y] = v;
             }
         }
-        return;  // uniform over the block: no barrier is skipped by part of it
-    }
-    // +-x: frame (u, w) is image (w, u or S-1-u): read image rows w = y.
-    for (int i = 0; i < 4; ++i) {
-        int yl = ty + 8 * i;
-        int y = tY * 32 + yl, x = tX * 32 + tx;
-        float v = 0.f;
-        if (x < S && y < S && x >= 1) v = a.dF[(size_t)y * S + frame_row(q, x - 1, S)];
-        ga_tile[yl][tx] = v;
+    } else if (q < 2) {
+        // +-x: frame (u, w) is image (w, u or S-1-u): read image rows w = y.
+        for (int i = 0; i < 4; ++i) {
+            int yl = ty + 8 * i;
+            int y = tY * 32 + yl, x = tX * 32 + tx;
+            float v = 0.f;
+            if (x < S && y < S && x >= 1) v = a.dF[(size_t)y * S + frame_row(q, x - 1, S)];
+            ga_tile[yl][tx] = v;
+        }
     }
     __syncthreads();
-    for (int i = 0; i < 4; ++i) {
-        int xl = ty + 8 * i;
-        int x = tX * 32 + xl, y = tY * 32 + tx;
-        if (x < S && y < S) a.dR0[q * SS + (size_t)x * S + y] = ga_tile[tx][xl];
+    if (q < 2) {
+        for (int i = 0; i < 4; ++i) {
+            int xl = ty + 8 * i;
+            int x = tX * 32 + xl, y = tY * 32 + tx;
+            if (x < S && y < S) a.dR0[q * SS + (size_t)x * S + y] = ga_tile[tx][xl];
+        }
     }
     __syncthreads();
 }
@@ -454,7 +471,7 @@ __device__ void body_merge_down_adj(const DownAdjArgs &a, unsigned tile, int U) 
     const int N = a.N, S = 1 << N, n = a.n, m = n + 1;
     const size_t SS = (size_t)S * S;
     for (int uu = 0; uu < U; ++uu) {
-        const size_t idx = ((size_t)tile * U + uu) * 256 + threadIdx.x;
+        const size_t idx = ((size_t)tile * U + uu) * 256 + ltid();
         if (idx >= 2 * SS) return;
         const int yp = (int)(idx & (S / 2 - 1)) * 2;
         const unsigned row = (unsigned)(idx >> (N - 1));
@@ -498,7 +515,7 @@ __device__ void body_dT(const DTArgs &a, unsigned tile, int U) {
     const unsigned rpq = (unsigned)(S >> n) * dirs;
     const size_t total = (size_t)4 * rpq * (S / 2);
     for (int uu = 0; uu < U; ++uu) {
-        const size_t idx = ((size_t)tile * U + uu) * 256 + threadIdx.x;
+        const size_t idx = ((size_t)tile * U + uu) * 256 + ltid();
         if (idx >= total) return;
         const int y = (int)(idx & (S / 2 - 1)) * 2;
         const unsigned row = (unsigned)(idx >> (N - 1));
@@ -664,13 +681,37 @@ __device__ __forceinline__ int adj_piece(int n, int rho, int which) {
     return rho == 0 ? (which ? 7 : 0) : 2 * rho - 1 + which;
 }
 
+// d(L, T)/d(eps, sigma) of one cell for the three half lengths 1/2, sqrt(2)/2,
+// sqrt(5)/4 (index L), held as named scalars so that a per-direction choice
+// among them stays a register select.
+struct CellDer {
+    float le0, le1, le2;  // dL/d eps
+    float ls0, ls1, ls2;  // dL/d sigma
+    float ts0, ts1, ts2;  // dT/d sigma
+    __device__ __forceinline__ CellDer(float e, float s) {
+        set(e, s, 0.5f, le0, ls0, ts0);
+        set(e, s, kH2, le1, ls1, ts1);
+        set(e, s, kQ5, le2, ls2, ts2);
+    }
+    __device__ __forceinline__ static void set(float e, float s, float ell, float &le,
+                                               float &ls, float &ts) {
+        const float tau = s * ell;
+        le = ell * cell_phi(tau);
+        ls = e * ell * ell * cell_dphi(tau);
+        ts = -ell * expf(-tau);
+    }
+    __device__ __forceinline__ static float pick(int L, float x0, float x1, float x2) {
+        return L == 0 ? x0 : (L == 1 ? x1 : x2);
+    }
+};
+
 // Level n's contribution to pixel (u, w): for each direction, the two rays that
 // put a piece on the pixel (their two dLoss/dT loads issued together), each
 // refolded around that piece.  Rays whose probe lies outside the grid add 0.
 template <int n>
 __device__ __forceinline__ void seed_adj_level(const SeedAdjArgs &a, int q, int u, int w,
                                                const float2 *iv, int base, int su, int sw,
-                                               int r, const float *der, float &ae, float &as) {
+                                               int r, const CellDer &der, float &ae, float &as) {
     constexpr int dirs = (1 << n) + 1, pieces = 2 << n;
     const int S = 1 << a.N;
     const float2 *dTq = (n == 0 ? a.dT0 : n == 1 ? a.dT1 : a.dT2) +
@@ -703,22 +744,22 @@ __device__ __forceinline__ void seed_adj_level(const SeedAdjArgs &a, int q, int 
             }
             const float dl = g[which].x * pre;                               // dLoss/dL_j
             const float dt = pre * fmaf(g[which].x, suf.x, g[which].y * suf.y);  // dLoss/dT_j
-            ae = fmaf(dl, der[3 * L], ae);
-            as = fmaf(dl, der[3 * L + 1], fmaf(dt, der[3 * L + 2], as));
+            ae = fmaf(dl, der.pick(L, der.le0, der.le1, der.le2), ae);
+            as = fmaf(dl, der.pick(L, der.ls0, der.ls1, der.ls2),
+                      fmaf(dt, der.pick(L, der.ts0, der.ts1, der.ts2), as));
         }
     }
 }
 
-constexpr int kSeedAdjLds = 3 * kAdjSpan * kAdjPitch * 8 + 256 * 9 * 4 + 4 * 256 * 8;
+constexpr int kSeedAdjLds = 3 * kAdjSpan * kAdjPitch * 8 + 256 * 8;
 
 __device__ void body_seed_adj(const SeedAdjArgs &a, unsigned tile, char *lds) {
     float2 *iv = reinterpret_cast<float2 *>(lds);
-    float *der = reinterpret_cast<float *>(iv + 3 * kAdjSpan * kAdjPitch);  // [256][3 lengths][3]
-    float2 *part = reinterpret_cast<float2 *>(der + 256 * 9);               // [4][256]
+    float2 *acc = iv + 3 * kAdjSpan * kAdjPitch;  // [256] running (d eps, d sigma) per pixel
     const int S = 1 << a.N;
     const int tiles = (S + kAdjTile - 1) / kAdjTile;
     const int r0 = (int)(tile / tiles) * kAdjTile, c0 = (int)(tile % tiles) * kAdjTile;
-    for (int i = threadIdx.x; i < kAdjSpan * kAdjSpan; i += 256) {
+    for (int i = ltid(); i < kAdjSpan * kAdjSpan; i += 256) {
         const int lr = i / kAdjSpan, lc = i % kAdjSpan;
         const int r = r0 - kAdjHalo + lr, c = c0 - kAdjHalo + lc;
         float e = 0.f, g = 0.f;
@@ -731,24 +772,10 @@ __device__ void body_seed_adj(const SeedAdjArgs &a, unsigned tile, char *lds) {
         iv[kAdjSpan * kAdjPitch + l] = cell_interval(e, g, kH2);
         iv[2 * kAdjSpan * kAdjPitch + l] = cell_interval(e, g, kQ5);
     }
-    {
-        // d(L, T)/d(eps, sigma) of this thread's pixel for the three half lengths
-        const int r = r0 + threadIdx.x / kAdjTile, c = c0 + threadIdx.x % kAdjTile;
-        const bool inside = r < S && c < S;
-        const float e_me = inside ? a.eps[(size_t)r * S + c] : 0.f;
-        const float s_me = inside ? a.sig[(size_t)r * S + c] : 0.f;
-        const float lens[3] = {0.5f, kH2, kQ5};
-#pragma unroll
-        for (int L = 0; L < 3; ++L) {
-            const float ell = lens[L], tau = s_me * ell;
-            der[threadIdx.x * 9 + 3 * L] = ell * cell_phi(tau);                 // dL/d eps
-            der[threadIdx.x * 9 + 3 * L + 1] = e_me * ell * ell * cell_dphi(tau);  // dL/d sigma
-            der[threadIdx.x * 9 + 3 * L + 2] = -ell * expf(-tau);               // dT/d sigma
-        }
-    }
+    acc[ltid()] = make_float2(0.f, 0.f);
     __syncthreads();
     // wave v takes the frame rows u_l = v, v+4, v+8, v+12 (one residue of u mod 4)
-    const int v = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int v = ltid() >> 6, lane = ltid() & 63;
     const int u_l = v + 4 * (lane >> 4), w_l = lane & 15;
     for (int q = 0; q < 4; ++q) {
         const int u_lo = q == 0 ? c0 : q == 1 ? S - kAdjTile - c0 : q == 2 ? r0 : S - kAdjTile - r0;
@@ -764,33 +791,34 @@ __device__ void body_seed_adj(const SeedAdjArgs &a, unsigned tile, char *lds) {
         const int rho = (u_lo + v) & 3;  // u mod 4, uniform over the wave
         float ae = 0.f, as = 0.f;
         if (u >= 0 && u < S && w < S) {
-            const float *d = der + (pr * kAdjTile + pc) * 9;
+            // d(L, T)/d(eps, sigma) of this pixel for the three half lengths
+            const float e_me = a.eps[(size_t)(r0 + pr) * S + c0 + pc];
+            const float s_me = a.sig[(size_t)(r0 + pr) * S + c0 + pc];
+            const CellDer d(e_me, s_me);
             seed_adj_level<0>(a, q, u, w, iv, base, su, sw, 0, d, ae, as);
             seed_adj_level<1>(a, q, u, w, iv, base, su, sw, rho & 1, d, ae, as);
             seed_adj_level<2>(a, q, u, w, iv, base, su, sw, rho, d, ae, as);
         }
-        part[q * 256 + pr * kAdjTile + pc] = make_float2(ae, as);
+        // one writer per pixel and quadrant; quadrants added in order 0..3
+        float2 &t = acc[pr * kAdjTile + pc];
+        t = make_float2(t.x + ae, t.y + as);
+        __syncthreads();
     }
-    __syncthreads();
-    const int r = r0 + threadIdx.x / kAdjTile, c = c0 + threadIdx.x % kAdjTile;
+    const int r = r0 + ltid() / kAdjTile, c = c0 + ltid() % kAdjTile;
     if (r < S && c < S) {
-        float2 t = part[threadIdx.x];
-        for (int q = 1; q < 4; ++q) {
-            const float2 o = part[q * 256 + threadIdx.x];
-            t.x += o.x;
-            t.y += o.y;
-        }
-        a.dE[(size_t)r * S + c] = t.x;
-        a.dS[(size_t)r * S + c] = t.y;
+        a.dE[(size_t)r * S + c] = acc[ltid()].x;
+        a.dS[(size_t)r * S + c] = acc[ltid()].y;
     }
     __syncthreads();
 }
 
-constexpr int kMaxLds = kSeedAdjLds > kSeedLds ? kSeedAdjLds : kSeedLds;
+// The persistent kernel's one LDS buffer: the largest body it runs (the traced
+// levels run there on 16x16 tiles).
+constexpr int kMaxLds = kSeedAdjLds > SeedTile<16>::lds ? kSeedAdjLds : SeedTile<16>::lds;
 
 __device__ __forceinline__ void run_phase(const Phase &p, unsigned tile, char *lds) {
     switch (p.kind) {
-        case PH_SEED: body_seed(p.a.seed, tile, lds); break;
+        case PH_SEED: body_seed<16>(p.a.seed, tile, lds); break;  // planner sets tile 16
         case PH_UP: body_merge_up(p.a.up, tile, p.U); break;
         case PH_DOWN: body_merge_down(p.a.down, tile, p.U); break;
         case PH_FRAME_SUM: body_frame_sum(p.a.fs, tile, lds); break;
@@ -818,8 +846,8 @@ HRC_ELEMENTWISE_KERNEL(hrc_interval_adj, body_dT, dt)
 #undef HRC_ELEMENTWISE_KERNEL
 
 __global__ __launch_bounds__(256) void hrc_seed(Phase p) {
-    __shared__ __align__(16) char lds[kSeedLds];
-    body_seed(p.a.seed, blockIdx.x, lds);
+    __shared__ __align__(16) char lds[SeedTile<32>::lds];
+    body_seed<32>(p.a.seed, blockIdx.x, lds);
 }
 __global__ __launch_bounds__(256) void hrc_seed_adj(Phase p) {
     __shared__ __align__(16) char lds[kSeedAdjLds];
@@ -835,67 +863,86 @@ __global__ __launch_bounds__(256) void hrc_gather_adj(Phase p) {
 }
 
 // ---------------------------------------------------------------------------
-// Persistent batch kernel.  Work items are (phase, tile) pairs grouped in
-// steps: step t holds phase t of every scene that has one, so each phase
-// depends only on the step before it.  Blocks claim items in order from one
-// counter.  A block counts the items it finishes in the current step and
-// publishes that count (one agent-scope release, then one atomic add) when it
-// claims its first item of a later step or runs out of items; before its first
-// item of step t it waits until step t-1 is complete (agent-scope acquire).
-// Publishing before waiting means no block ever waits while holding
-// unpublished work, and every item of step t-1 was claimed before any item of
-// step t by a block that is running, so the queue always drains (no grid-wide
-// co-residency is assumed).  Memory ordering costs one release and one acquire
-// per block and step rather than per item.
+// Persistent batch kernel.  Work items are groups of kBatchQuarters tiles of
+// one phase, run side by side by the block's quarters (so every quarter passes
+// the same barriers), grouped in steps: step t holds phase t of every scene
+// that has one, so each phase depends only on the step before it.  Blocks
+// claim chunks of consecutive items from one counter and run them in order.  A block counts the items it
+// finishes in the current step and publishes that count (one agent-scope
+// release, then one atomic add) when it reaches an item of a later step or
+// runs out of items; before its first item of step t it waits until step t-1
+// is complete (agent-scope acquire).  Thread 0 performs both for the block,
+// between block barriers.  Publishing before waiting means no block
+// ever waits while holding unpublished work, and every item of step t-1 was
+// claimed before any item of step t by a block that is running, so the queue
+// always drains (no grid-wide co-residency is assumed).  Memory ordering costs
+// one release and one acquire per block and step rather than per item, and the
+// counter, the error word and each step's count sit in cache lines of their
+// own.
 // ---------------------------------------------------------------------------
 
 constexpr unsigned kMaxSpins = 1u << 20;  // about a second of polling
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void hrc_persistent(const BatchTables t, unsigned *counter,
-                                                      unsigned *done, unsigned *error) {
-    __shared__ __align__(16) char lds[kMaxLds];
-    __shared__ unsigned s_item;
+__device__ __forceinline__ void persistent_loop(const BatchTables &t, unsigned *sched, char *lds,
+                                                unsigned &s_item) {
+    char *qlds = lds + (threadIdx.x >> 8) * kMaxLds;  // this quarter's LDS
+    unsigned *counter = sched, *error = sched + kSchedStride, *done = sched + 2 * kSchedStride;
     int cur_step = -1;
     unsigned completed = 0;
+    unsigned item = 0, claim_end = 0;  // this block's claimed items [item, claim_end)
+    int seg = 0;
+    unsigned seg_end = 0;              // first item after segment seg
     for (;;) {
-        // claim (one thread), then make the claimed item a scalar for the block
-        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
-        __syncthreads();
-        const unsigned item = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
-        int seg = 0, step = t.nsteps;
+        if (item == claim_end) {
+            // claim the next chunk (one thread), then make it a scalar for the block
+            if (threadIdx.x == 0) s_item = atomicAdd(counter, t.chunk);
+            __syncthreads();
+            item = __builtin_amdgcn_readfirstlane(s_item);
+            claim_end = item + t.chunk;
+            __syncthreads();
+        }
+        int step = t.nsteps;
         if (item < t.total_items) {
-            int lo = 0, hi = t.nseg - 1;  // last segment starting at or before the item
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (t.seg_start[mid] <= item) lo = mid;
-                else hi = mid - 1;
+            if (item >= seg_end || item < t.seg_start[seg]) {
+                int lo = 0, hi = t.nseg - 1;  // last segment starting at or before the item
+                while (lo < hi) {
+                    int mid = (lo + hi + 1) >> 1;
+                    if (t.seg_start[mid] <= item) lo = mid;
+                    else hi = mid - 1;
+                }
+                seg = __builtin_amdgcn_readfirstlane(lo);
+                seg_end = seg + 1 < t.nseg ? t.seg_start[seg + 1] : t.total_items;
             }
-            seg = lo;
-            step = __builtin_amdgcn_readfirstlane(t.seg_step[lo]);
+            step = __builtin_amdgcn_readfirstlane(t.seg_step[seg]);
         }
         if (step != cur_step) {
             if (cur_step >= 0) {
-                // publish this block's items of the step it is leaving
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                // publish this block's items of the step it is leaving: the
+                // block barrier orders every wave's stores before thread 0's
+                // agent-scope release, which then makes them visible to the
+                // other XCDs once for the whole block
                 __syncthreads();
-                if (threadIdx.x == 0)
-                    __hip_atomic_fetch_add(&done[cur_step], completed, __ATOMIC_RELEASE,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                __syncthreads();
+                if (threadIdx.x == 0) {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                    __hip_atomic_fetch_add(&done[(size_t)cur_step * kSchedStride], completed,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
             }
             cur_step = step;
             completed = 0;
             if (step >= t.nsteps) break;
             if (step > 0) {
                 if (threadIdx.x == 0) {
-                    // Bounded wait: a step that never completes (a planning bug)
-                    // raises the error word and lets the queue drain instead of
-                    // hanging.
+                    // Bounded wait on relaxed loads (an acquiring load would
+                    // invalidate the caches on every poll); the acquire fence
+                    // below orders the step's reads after the count is seen.  A
+                    // step that never completes (a planning bug) raises the
+                    // error word and lets the queue drain instead of hanging.
                     const unsigned need = t.step_items[step - 1];
+                    const unsigned *d = &done[(size_t)(step - 1) * kSchedStride];
                     unsigned spins = 0;
-                    while (__hip_atomic_load(&done[step - 1], __ATOMIC_ACQUIRE,
-                                             __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    while (__hip_atomic_load(d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                           need) {
                         if (++spins > kMaxSpins) {
                             __hip_atomic_store(error, 1u, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
@@ -903,16 +950,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void h
                         }
                         __builtin_amdgcn_s_sleep(2);
                     }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 }
-                __syncthreads();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                __syncthreads();  // the other waves read after thread 0's acquire
             }
         }
         const int pi = __builtin_amdgcn_readfirstlane(t.seg_phase[seg]);
-        const unsigned tile = __builtin_amdgcn_readfirstlane(item - t.seg_start[seg]);
-        run_phase(t.phases[pi], tile, lds);
+        const unsigned tile =
+            __builtin_amdgcn_readfirstlane(item - t.seg_start[seg]) * kBatchQuarters +
+            (threadIdx.x >> 8);
+        run_phase(t.phases[pi], tile, qlds);
         ++completed;
+        ++item;
     }
+}
+
+// Two register budgets for the same loop: the full budget (one block per CU)
+// and 64 VGPRs (two blocks per CU, at the cost of some spills in the larger
+// bodies).  The batch planner times both.
+__global__ __launch_bounds__(256 * kBatchQuarters) void hrc_persistent(const BatchTables t,
+                                                                        unsigned *sched) {
+    __shared__ __align__(16) char lds[kBatchQuarters * kMaxLds];
+    __shared__ unsigned s_item;
+    persistent_loop(t, sched, lds, s_item);
+}
+__global__ __launch_bounds__(256 * kBatchQuarters) __attribute__((amdgpu_waves_per_eu(8)))
+void hrc_persistent_dense(const BatchTables t, unsigned *sched) {
+    __shared__ __align__(16) char lds[kBatchQuarters * kMaxLds];
+    __shared__ unsigned s_item;
+    persistent_loop(t, sched, lds, s_item);
 }
 
 // Clears the scheduler state (a kernel rather than a memset so that it can be
@@ -958,7 +1024,10 @@ unsigned phase_tiles(const Phase &p) {
     switch (p.kind) {
         case PH_FRAME_SUM: return t32 * t32;
         case PH_GATHER_ADJ: return 4 * t32 * t32;
-        case PH_SEED: return t32 * t32;
+        case PH_SEED: {
+            const unsigned t = (unsigned)((S + p.a.seed.tile - 1) / p.a.seed.tile);
+            return t * t;
+        }
         case PH_UP: return cdiv((size_t)p.a.up.nq * t_level_entries(N, p.a.up.n) / 2, per);
         case PH_DT: return cdiv(4 * t_level_entries(N, p.a.dt.n) / 2, per);
         case PH_DOWN: return cdiv((size_t)p.a.down.nq * SS / 2, per);
@@ -994,18 +1063,20 @@ hipError_t launch_phase(const Phase &p, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_persistent(const BatchTables &t, unsigned *sched, int grid, hipStream_t s) {
-    const unsigned n = 2u + (unsigned)t.nsteps;  // counter, done[nsteps], error word
+hipError_t launch_persistent(const BatchTables &t, unsigned *sched, int grid, int variant,
+                             hipStream_t s) {
+    const unsigned n = (unsigned)sched_words(t.nsteps);
     hipLaunchKernelGGL(hrc_clear_u32, dim3((n + 255) / 256), dim3(256), 0, s, sched, n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(hrc_persistent, dim3(grid), dim3(256), 0, s, t, sched, sched + 1,
-                       sched + 1 + t.nsteps);
+    hipLaunchKernelGGL(variant ? hrc_persistent_dense : hrc_persistent, dim3(grid),
+                       dim3(256 * kBatchQuarters), 0, s, t, sched);
     return hipGetLastError();
 }
 
-hipError_t persistent_occupancy(int *blocks_per_cu) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, hrc_persistent, 256, 0);
+hipError_t persistent_occupancy(int variant, int *blocks_per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        blocks_per_cu, variant ? hrc_persistent_dense : hrc_persistent, 256 * kBatchQuarters, 0);
 }
 
 hipError_t launch_validate(const float *a, const float *b, size_t n, int *flag,

@@ -180,7 +180,8 @@ class Batch:
     computes every scene's fluence and, where a grad_fluence is given, its
     gradients.  The tensors passed in are the ones every launch reads/writes."""
 
-    def __init__(self, scenes: Sequence[dict], context: Optional[Context] = None):
+    def __init__(self, scenes: Sequence[dict], context: Optional[Context] = None,
+                 flags: int = 0):
         self.ctx = context or default_context()
         self.scenes = list(scenes)
         arr = (hrc_scene * len(self.scenes))()
@@ -200,7 +201,7 @@ class Batch:
                 arr[i].grad_sigma_t = sc["grad_sigma_t"].data_ptr()
         self._ptr = ctypes.c_void_p(0)
         dev = self.scenes[0]["emission"].device
-        check(_lib.load().hrc_batch_plan(self.ctx._ptr, arr, len(self.scenes), 0,
+        check(_lib.load().hrc_batch_plan(self.ctx._ptr, arr, len(self.scenes), flags,
                                          _stream_handle(dev), ctypes.byref(self._ptr)),
               "hrc_batch_plan")
         self._device = dev
@@ -212,6 +213,15 @@ class Batch:
     @property
     def workspace_bytes(self) -> int:
         return int(_lib.load().hrc_batch_workspace_bytes(self._ptr))
+
+    def describe(self) -> dict:
+        """The autotuner's choice (``hrc_batch_describe``)."""
+        v, g, t, c = (ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int())
+        check(_lib.load().hrc_batch_describe(self._ptr, ctypes.byref(v), ctypes.byref(g),
+                                             ctypes.byref(t), ctypes.byref(c)),
+              "hrc_batch_describe")
+        return {"variant": v.value, "grid": g.value, "target_tiles": t.value,
+                "chunk_groups": c.value}
 
     def __del__(self):
         ptr = getattr(self, "_ptr", None)

@@ -42,12 +42,16 @@ def _check_against_single(ctx, items):
             assert torch.equal(gs, d["grad_sigma_t"]), f"scene {i} d sigma"
 
 
-def test_batch_small_mixed_sizes(ctx):
+@pytest.mark.parametrize("flags", [0, 0x100, 0x200], ids=["autotuned", "full", "dense"])
+def test_batch_small_mixed_sizes(ctx, flags):
     from paper_2505_02041_amd import Batch
-    log("batch small mixed")
+    log(f"batch small mixed, flags {flags:#x}")
     scenes = [scene_like_512(S, 70 + i, 3, 4) for i, S in enumerate([8, 64, 32, 128, 16, 256])]
     items = _make(scenes, lambda i: i % 2 == 0)
-    b = Batch(items, ctx)
+    b = Batch(items, ctx, flags=flags)
+    want = {0x100: 0, 0x200: 1}.get(flags)
+    if want is not None:
+        assert b.describe()["variant"] == want
     for rep in range(3):
         for d in items:
             d["fluence"].fill_(float("nan"))
@@ -60,13 +64,14 @@ def test_batch_small_mixed_sizes(ctx):
     del b
 
 
-def test_batch_benchmark_workload_subset(ctx):
+@pytest.mark.parametrize("flags", [0x100, 0x200], ids=["full", "dense"])
+def test_batch_benchmark_workload_subset(ctx, flags):
     """16 scenes of the 64-scene batch workload (sizes 128..1024), fwd + bwd."""
     from paper_2505_02041_amd import Batch
-    log("batch 16 scenes of the batch workload")
+    log(f"batch 16 scenes of the batch workload, flags {flags:#x}")
     scenes = config5()[:16]
     items = _make(scenes, lambda i: True)
-    b = Batch(items, ctx)
+    b = Batch(items, ctx, flags=flags)
     b.launch()
     torch.cuda.synchronize()
     _check_against_single(ctx, items)
