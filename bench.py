@@ -6,7 +6,8 @@ merge down, quadrant gather) of the 1024x1024 scene (128 disks, 256 opaque
 boxes, 32 one-pixel sigma-100 lines, value-noise fog), inputs resident in HBM.
 Prints one JSON line: Mpixel/s of fluence (value), plus the forward+backward
 rate, the batched forward+backward rate against sequential single-scene calls,
-the HBM roofline of the dominant kernel (per-pass HIP events) and the FP64
+the HBM roofline of the dominant kernel (HIP events recorded at each of its
+launches' start and end) and the FP64
 oracle timed on the host.
 """
 from __future__ import annotations
@@ -119,8 +120,9 @@ def main():
     fb_s = timed(lambda: (ctx.hrc_forward(eps, sig, F), ctx.hrc_backward(eps, sig, dF)),
                  max(5, args.steps // 2), 2)
 
-    # ---- per-pass HIP events (same launches, events between passes) ---------
-    log("per-pass event timing")
+    # ---- per-pass kernel durations: the same launches as hrc_forward, each
+    # with HIP events the runtime records at the kernel's own start and end ---
+    log("per-pass kernel timing")
     per = {}
     reps = max(5, args.steps // 2)
     for _ in range(reps):

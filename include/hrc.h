@@ -130,10 +130,11 @@ typedef enum {
 } hrc_pass_kind;
 
 /* Runs one hrc_forward (grad_fluence == NULL) or one hrc_backward (then
- * fluence is ignored) exactly as those calls do, with a HIP event recorded on
- * `stream` around every pass, then synchronises `stream` and reports, per pass
- * in execution order, its kind, level n (-1 when not per level) and duration
- * in milliseconds.  At most `max_passes` are reported; *count receives the
+ * fluence is ignored) with the same kernels and launch shapes, each launched
+ * with a pair of HIP events that the runtime records at that kernel's start
+ * and end on `stream`; then synchronises `stream` and reports, per pass in
+ * execution order, its kind, level n (-1 when not per level) and kernel
+ * duration in milliseconds.  At most `max_passes` are reported; *count receives the
  * number of passes.  Argument checks as for hrc_forward / hrc_backward, plus
  * HRC_ERR_INVALID_ARG for NULL report arrays. */
 hrc_status hrc_profile_solve(hrc_context *ctx, int log2_size,

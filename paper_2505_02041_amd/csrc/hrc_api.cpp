@@ -334,20 +334,20 @@ hrc_status hrc_profile_solve(hrc_context *ctx, int log2_size, const float *emiss
                                         grad_sigma_t}
                          : SolveBuffers{emission, sigma_t, fluence, nullptr, nullptr, nullptr};
     const int np = build_solve_phases(w, b, bwd, nullptr, ph, kMaxPhases);
-    std::vector<hipEvent_t> ev(np + 1, nullptr);
+    // events 2i, 2i+1: start and end of pass i, recorded by the launch itself
+    std::vector<hipEvent_t> ev(2 * np, nullptr);
     st = HRC_OK;
     for (auto &e : ev)
         if (hipEventCreate(&e) != hipSuccess) st = HRC_ERR_HIP;
-    if (st == HRC_OK && hipEventRecord(ev[0], s) != hipSuccess) st = HRC_ERR_HIP;
     for (int i = 0; i < np && st == HRC_OK; ++i) {
-        if (launch_phase(ph[i], s) != hipSuccess || hipEventRecord(ev[i + 1], s) != hipSuccess)
-            st = HRC_ERR_HIP;
+        if (launch_phase(ph[i], s, ev[2 * i], ev[2 * i + 1]) != hipSuccess) st = HRC_ERR_HIP;
     }
-    if (st == HRC_OK && hipEventSynchronize(ev[np]) != hipSuccess) st = HRC_ERR_HIP;
+    if (st == HRC_OK && np > 0 && hipEventSynchronize(ev[2 * np - 1]) != hipSuccess)
+        st = HRC_ERR_HIP;
     for (int i = 0; i < np && st == HRC_OK; ++i) {
         if (i >= max_passes) break;
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) != hipSuccess) st = HRC_ERR_HIP;
+        if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) != hipSuccess) st = HRC_ERR_HIP;
         pass_ms[i] = ms;
         pass_kind[i] = ph[i].kind;
         pass_level[i] = phase_level(ph[i]);

@@ -137,7 +137,10 @@ int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, cons
 
 unsigned phase_tiles(const Phase &p);
 hipError_t upload_cone_table(const float *host_table);
-hipError_t launch_phase(const Phase &p, hipStream_t s);
+// Launches one pass.  With events, they are recorded at the kernel's own start
+// and end (a timed launch: no separate event packets between kernels).
+hipError_t launch_phase(const Phase &p, hipStream_t s, hipEvent_t start = nullptr,
+                        hipEvent_t stop = nullptr);
 // Device tables of a planned batch: segment i covers the items
 // [seg_start[i], seg_start[i+1]) = the tiles of phase seg_phase[i], in step
 // seg_step[i]; step_items[t] counts the items of step t.

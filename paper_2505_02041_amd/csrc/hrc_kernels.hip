@@ -20,6 +20,8 @@
 // Every kernel is elementwise in gather form: one thread owns one output
 // element and reads what it needs, so results do not depend on the launch
 // shape and need no atomics.
+#include <hip/hip_ext.h>
+
 #include "hrc_internal.h"
 
 namespace hrc {
@@ -1044,7 +1046,7 @@ hipError_t upload_cone_table(const float *host_table) {
     return hipMemcpyToSymbol(HIP_SYMBOL(c_cone), host_table, sizeof(float) * kConeTable);
 }
 
-hipError_t launch_phase(const Phase &p, hipStream_t s) {
+hipError_t launch_phase(const Phase &p, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
     unsigned tiles = phase_tiles(p);
     if (tiles == 0) return hipSuccess;
     void (*k)(Phase) = nullptr;
@@ -1059,7 +1061,10 @@ hipError_t launch_phase(const Phase &p, hipStream_t s) {
         case PH_SEED_ADJ: k = hrc_seed_adj; break;
         default: return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL(k, dim3(tiles), dim3(256), 0, s, p);
+    if (start || stop)
+        hipExtLaunchKernelGGL(k, dim3(tiles), dim3(256), 0, s, start, stop, 0, p);
+    else
+        hipLaunchKernelGGL(k, dim3(tiles), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 
