@@ -667,25 +667,24 @@ constexpr int kAdjPitch = kAdjSpan + 1;
 // du = floor((2i + 3)/4) and dw = floor((2^(n+1) + (2i+1)(2k - 2^n))/2^(n+2)).
 // The piece length is sqrt(2)/2 on diagonals (k = 0, 2^n), 1/2 on the axis
 // (k = 2^(n-1)) and sqrt(5)/4 otherwise (n = 2, k = 1, 3).
-__device__ __forceinline__ int piece_du(int i) { return (2 * i + 3) >> 2; }
-__device__ __forceinline__ int piece_dw(int n, int k, int i) {
+__host__ __device__ constexpr int piece_du(int i) { return (2 * i + 3) >> 2; }
+__host__ __device__ constexpr int piece_dw(int n, int k, int i) {
     return ((2 << n) + (2 * i + 1) * (2 * k - (1 << n))) >> (n + 2);
 }
-__device__ __forceinline__ int piece_len(int n, int k) {
+__host__ __device__ constexpr int piece_len(int n, int k) {
     return (k == 0 || k == (1 << n)) ? 1 : (2 * k == (1 << n) ? 0 : 2);
 }
 
 // The two pieces of level n that land on a pixel whose frame u has residue
 // rho modulo 2^n (piece j covers u offset (2j + 3) / 4 from its probe).
-__device__ __forceinline__ int adj_piece(int n, int rho, int which) {
+__host__ __device__ constexpr int adj_piece(int n, int rho, int which) {
     if (n == 0) return which;
     if (n == 1) return rho == 0 ? (which ? 3 : 0) : (which ? 2 : 1);
     return rho == 0 ? (which ? 7 : 0) : 2 * rho - 1 + which;
 }
 
 // d(L, T)/d(eps, sigma) of one cell for the three half lengths 1/2, sqrt(2)/2,
-// sqrt(5)/4 (index L), held as named scalars so that a per-direction choice
-// among them stays a register select.
+// sqrt(5)/4 (index L), held as named scalars.
 struct CellDer {
     float le0, le1, le2;  // dL/d eps
     float ls0, ls1, ls2;  // dL/d sigma
@@ -702,114 +701,203 @@ struct CellDer {
         ls = e * ell * ell * cell_dphi(tau);
         ts = -ell * expf(-tau);
     }
-    __device__ __forceinline__ static float pick(int L, float x0, float x1, float x2) {
-        return L == 0 ? x0 : (L == 1 ? x1 : x2);
-    }
 };
 
-// Level n's contribution to pixel (u, w): for each direction, the two rays that
-// put a piece on the pixel (their two dLoss/dT loads issued together), each
-// refolded around that piece.  Rays whose probe lies outside the grid add 0.
-template <int n>
-__device__ __forceinline__ void seed_adj_level(const SeedAdjArgs &a, int q, int u, int w,
-                                               const float2 *iv, int base, int su, int sw,
-                                               int r, const CellDer &der, float &ae, float &as) {
+// Direction k (uniform over the wave) of level n: its contribution to pixel
+// (u, w), whose frame u has residue rho modulo 2^n, for directions whose half
+// pieces have length index L.  The interval tile in LDS is laid out in the
+// quadrant's frame (u along a row, w across rows), so with n, rho and L known
+// at compile time every piece offset from the pixel is a scalar (ivp points H
+// cells before the pixel in u and in w, so the offsets are non-negative).
+// The two rays that put a piece on the pixel (their dLoss/dT loaded first) are
+// each refolded around that piece.  Rays whose probe lies outside the grid
+// add 0.
+template <int n, int rho, int L>
+__device__ __forceinline__ void seed_adj_dir(int k, const float2 *dTq, int S, int un, int w,
+                                             int lane_idx, const float2 *ivp, float le,
+                                             float ls, float ts, float &ae, float &as) {
     constexpr int dirs = (1 << n) + 1, pieces = 2 << n;
-    const int S = 1 << a.N;
-    const float2 *dTq = (n == 0 ? a.dT0 : n == 1 ? a.dT1 : a.dT2) +
-                        (size_t)q * (n == 0 ? a.e0 : n == 1 ? a.e1 : a.e2);
-#pragma unroll 1
-    for (int k = 0; k < dirs; ++k) {
-        const int L = piece_len(n, k);
-        const float2 *ivL = iv + L * (kAdjSpan * kAdjPitch) + base;
-        float2 g[2];
+    constexpr int P = kAdjPitch, plane = kAdjSpan * kAdjPitch, H = kAdjHalo;
+    float2 g[2];
 #pragma unroll
-        for (int which = 0; which < 2; ++which) {
-            const int j = adj_piece(n, r, which);
-            const int pu = u - piece_du(j), pw = w - piece_dw(n, k, j);
-            const bool ok = pu >= 0 && pw >= 0 && pw < S;
-            const float2 v = dTq[((size_t)(ok ? pu >> n : 0) * dirs + k) * S + (ok ? pw : 0)];
-            g[which] = ok ? v : make_float2(0.f, 0.f);
+    for (int which = 0; which < 2; ++which) {
+        const int j = adj_piece(n, rho, which);
+        // the probe's column (u - du_j) / 2^n is exact: u = rho (mod 2^n)
+        const int cj = (piece_du(j) - (rho & ((1 << n) - 1))) >> n;
+        const int dwj = piece_dw(n, k, j);
+        const int pw = w - dwj;
+        const bool ok = un >= cj && (unsigned)pw < (unsigned)S;
+        // always load (the index stays in the array) and clear the bits of a
+        // discarded value: no branch around the load.  lane_idx = (u >> n)
+        // dirs S + w; the rest is uniform.
+        const unsigned idx = ok ? (unsigned)(lane_idx + (k - cj * dirs) * S - dwj) : 0u;
+        const float2 v = dTq[idx];
+        const unsigned keep = ok ? 0xffffffffu : 0u;
+        g[which] = make_float2(__uint_as_float(__float_as_uint(v.x) & keep),
+                               __uint_as_float(__float_as_uint(v.y) & keep));
+    }
+#pragma unroll
+    for (int which = 0; which < 2; ++which) {
+        const int j = adj_piece(n, rho, which);
+        float pre = 1.f;
+        float2 suf = make_float2(0.f, 1.f);
+#pragma unroll
+        for (int i = pieces - 1; i >= 0; --i) {
+            if (i == j) continue;
+            const float2 c = ivp[L * plane + (H + piece_du(i) - piece_du(j)) +
+                                 (H + piece_dw(n, k, i) - piece_dw(n, k, j)) * P];
+            if (i > j) suf = merge(c, suf);
+            else pre *= c.y;
         }
-#pragma unroll
-        for (int which = 0; which < 2; ++which) {
-            const int j = adj_piece(n, r, which);  // uniform over the wave
-            const int du_j = piece_du(j), dw_j = piece_dw(n, k, j);
-            float pre = 1.f;
-            float2 suf = make_float2(0.f, 1.f);
-#pragma unroll
-            for (int i = pieces - 1; i >= 0; --i) {
-                if (i == j) continue;
-                const float2 c = ivL[(piece_du(i) - du_j) * su + (piece_dw(n, k, i) - dw_j) * sw];
-                if (i > j) suf = merge(c, suf);
-                else pre *= c.y;
-            }
-            const float dl = g[which].x * pre;                               // dLoss/dL_j
-            const float dt = pre * fmaf(g[which].x, suf.x, g[which].y * suf.y);  // dLoss/dT_j
-            ae = fmaf(dl, der.pick(L, der.le0, der.le1, der.le2), ae);
-            as = fmaf(dl, der.pick(L, der.ls0, der.ls1, der.ls2),
-                      fmaf(dt, der.pick(L, der.ts0, der.ts1, der.ts2), as));
-        }
+        const float dl = g[which].x * pre;                                   // dLoss/dL_j
+        const float dt = pre * fmaf(g[which].x, suf.x, g[which].y * suf.y);  // dLoss/dT_j
+        ae = fmaf(dl, le, ae);
+        as = fmaf(dl, ls, fmaf(dt, ts, as));
     }
 }
 
-constexpr int kSeedAdjLds = 3 * kAdjSpan * kAdjPitch * 8 + 256 * 8;
+// Level n: the diagonals k = 0, 2^n (length sqrt(2)/2), the axis k = 2^(n-1)
+// (1/2) and, at n = 2, k = 1, 3 (sqrt(5)/4).
+template <int n, int rho>
+__device__ __forceinline__ void seed_adj_level(const float2 *dTq, int S, int u, int w,
+                                               const float2 *ivp, const CellDer &der,
+                                               float &ae, float &as) {
+    constexpr int dirs = (1 << n) + 1;
+    const int un = u >> n;
+    const int lane_idx = un * dirs * S + w;
+#pragma unroll 1
+    for (int kk = 0; kk < 2; ++kk)
+        seed_adj_dir<n, rho, 1>(kk << n, dTq, S, un, w, lane_idx, ivp, der.le1, der.ls1,
+                                der.ts1, ae, as);
+    if (n >= 1)
+        seed_adj_dir<n, rho, 0>(n >= 1 ? 1 << (n - 1) : 0, dTq, S, un, w, lane_idx, ivp,
+                                der.le0, der.ls0, der.ts0, ae, as);
+    if (n == 2) {
+#pragma unroll 1
+        for (int kk = 1; kk < 4; kk += 2)
+            seed_adj_dir<n, rho, 2>(kk, dTq, S, un, w, lane_idx, ivp, der.le2, der.ls2, der.ts2,
+                                    ae, as);
+    }
+}
 
-__device__ void body_seed_adj(const SeedAdjArgs &a, unsigned tile, char *lds) {
+// All three traced levels for pixels whose frame u is rho modulo 4.
+template <int rho>
+__device__ __forceinline__ void seed_adj_levels(const float2 *dT0, const float2 *dT1,
+                                                const float2 *dT2, int S, int u, int w,
+                                                const float2 *ivp, const CellDer &der,
+                                                float &ae, float &as) {
+    seed_adj_level<0, 0>(dT0, S, u, w, ivp, der, ae, as);
+    seed_adj_level<1, rho & 1>(dT1, S, u, w, ivp, der, ae, as);
+    seed_adj_level<2, rho>(dT2, S, u, w, ivp, der, ae, as);
+}
+
+// per-pixel accumulators, rows padded so that a column of the tile (the
+// lanes of a wave in quadrants 0 and 1) spans distinct banks
+constexpr int kAccPitch = kAdjTile + 1;
+constexpr int kSeedAdjLds = 3 * kAdjSpan * kAdjPitch * 8 + kAdjTile * kAccPitch * 8;
+
+// Image-local (row, column) of the frame-local (ul, wl) of the tile in quadrant
+// q: +x (c, r), -x (S-1-c, r), +y (r, c), -y (S-1-r, c), tile-relative.
+__device__ __forceinline__ void adj_frame_to_image(int q, int ul, int wl, int &rl, int &cl) {
+    if (q < 2) { rl = wl; cl = q == 0 ? ul : kAdjTile - 1 - ul; }
+    else { cl = wl; rl = q == 2 ? ul : kAdjTile - 1 - ul; }
+}
+
+__device__ __forceinline__ void body_seed_adj(const SeedAdjArgs &a, unsigned tile, char *lds) {
+    constexpr int P = kAdjPitch, plane = kAdjSpan * kAdjPitch, H = kAdjHalo;
     float2 *iv = reinterpret_cast<float2 *>(lds);
-    float2 *acc = iv + 3 * kAdjSpan * kAdjPitch;  // [256] running (d eps, d sigma) per pixel
+    float2 *acc = iv + 3 * plane;  // [16][kAccPitch] running (d eps, d sigma) per pixel
     const int S = 1 << a.N;
     const int tiles = (S + kAdjTile - 1) / kAdjTile;
     const int r0 = (int)(tile / tiles) * kAdjTile, c0 = (int)(tile % tiles) * kAdjTile;
+    // the tile and its halo as three half-length intervals per cell, first in
+    // image orientation (the frame of quadrant 0)
     for (int i = ltid(); i < kAdjSpan * kAdjSpan; i += 256) {
         const int lr = i / kAdjSpan, lc = i % kAdjSpan;
-        const int r = r0 - kAdjHalo + lr, c = c0 - kAdjHalo + lc;
+        const int r = r0 - H + lr, c = c0 - H + lc;
         float e = 0.f, g = 0.f;
         if (r >= 0 && r < S && c >= 0 && c < S) {
             e = a.eps[(size_t)r * S + c];
             g = a.sig[(size_t)r * S + c];
         }
-        const int l = lr * kAdjPitch + lc;
+        const int l = lr * P + lc;
         iv[l] = cell_interval(e, g, 0.5f);
-        iv[kAdjSpan * kAdjPitch + l] = cell_interval(e, g, kH2);
-        iv[2 * kAdjSpan * kAdjPitch + l] = cell_interval(e, g, kQ5);
+        iv[plane + l] = cell_interval(e, g, kH2);
+        iv[2 * plane + l] = cell_interval(e, g, kQ5);
     }
-    acc[ltid()] = make_float2(0.f, 0.f);
+    acc[(ltid() / kAdjTile) * kAccPitch + ltid() % kAdjTile] = make_float2(0.f, 0.f);
     __syncthreads();
     // wave v takes the frame rows u_l = v, v+4, v+8, v+12 (one residue of u mod 4)
     const int v = ltid() >> 6, lane = ltid() & 63;
     const int u_l = v + 4 * (lane >> 4), w_l = lane & 15;
+    // this pixel's cell in the frame layout is ivp[H * P + H]: every piece
+    // offset from it is then a non-negative immediate
+    const float2 *ivp = iv + w_l * P + u_l;
+    constexpr int kPer = (3 * kAdjSpan * kAdjSpan + 255) / 256;
     for (int q = 0; q < 4; ++q) {
+        if (q > 0) {
+            // re-lay the tile from quadrant q-1's frame into quadrant q's: read
+            // every destination cell's source into registers, then write
+            float2 tmp[kPer];
+#pragma unroll
+            for (int t = 0; t < kPer; ++t) {
+                const int i = ltid() + 256 * t;
+                if (i < 3 * kAdjSpan * kAdjSpan) {
+                    const int Lh = i / (kAdjSpan * kAdjSpan), rem = i % (kAdjSpan * kAdjSpan);
+                    const int ul = rem % kAdjSpan - H, wl = rem / kAdjSpan - H;
+                    int rl, cl;
+                    adj_frame_to_image(q, ul, wl, rl, cl);
+                    // frame-local of the same cell in quadrant q-1
+                    int ps, pw2;
+                    if (q == 1) { ps = cl; pw2 = rl; }                    // from q = 0
+                    else if (q == 2) { ps = kAdjTile - 1 - cl; pw2 = rl; }  // from q = 1
+                    else { ps = rl; pw2 = cl; }                           // from q = 2
+                    tmp[t] = iv[Lh * plane + (pw2 + H) * P + ps + H];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < kPer; ++t) {
+                const int i = ltid() + 256 * t;
+                if (i < 3 * kAdjSpan * kAdjSpan) {
+                    const int Lh = i / (kAdjSpan * kAdjSpan), rem = i % (kAdjSpan * kAdjSpan);
+                    iv[Lh * plane + (rem / kAdjSpan) * P + rem % kAdjSpan] = tmp[t];
+                }
+            }
+            __syncthreads();
+        }
         const int u_lo = q == 0 ? c0 : q == 1 ? S - kAdjTile - c0 : q == 2 ? r0 : S - kAdjTile - r0;
         const int w_lo = q < 2 ? r0 : c0;
-        // image pixel (tile-local) of frame pixel (u_l, w_l)
-        int pr, pc;
-        if (q < 2) { pr = w_l; pc = q == 0 ? u_l : kAdjTile - 1 - u_l; }
-        else { pc = w_l; pr = q == 2 ? u_l : kAdjTile - 1 - u_l; }
+        int pr, pc;  // image pixel (tile-local) of frame pixel (u_l, w_l)
+        adj_frame_to_image(q, u_l, w_l, pr, pc);
         const int u = u_lo + u_l, w = w_lo + w_l;
-        const int base = (pr + kAdjHalo) * kAdjPitch + pc + kAdjHalo;
-        const int su = q == 0 ? 1 : q == 1 ? -1 : q == 2 ? kAdjPitch : -kAdjPitch;
-        const int sw = q < 2 ? kAdjPitch : 1;
-        const int rho = (u_lo + v) & 3;  // u mod 4, uniform over the wave
         float ae = 0.f, as = 0.f;
         if (u >= 0 && u < S && w < S) {
             // d(L, T)/d(eps, sigma) of this pixel for the three half lengths
-            const float e_me = a.eps[(size_t)(r0 + pr) * S + c0 + pc];
-            const float s_me = a.sig[(size_t)(r0 + pr) * S + c0 + pc];
-            const CellDer d(e_me, s_me);
-            seed_adj_level<0>(a, q, u, w, iv, base, su, sw, 0, d, ae, as);
-            seed_adj_level<1>(a, q, u, w, iv, base, su, sw, rho & 1, d, ae, as);
-            seed_adj_level<2>(a, q, u, w, iv, base, su, sw, rho, d, ae, as);
+            const CellDer d(a.eps[(size_t)(r0 + pr) * S + c0 + pc],
+                            a.sig[(size_t)(r0 + pr) * S + c0 + pc]);
+            const float2 *dT0 = a.dT0 + (size_t)q * a.e0;
+            const float2 *dT1 = a.dT1 + (size_t)q * a.e1;
+            const float2 *dT2 = a.dT2 + (size_t)q * a.e2;
+            // u_lo is a multiple of 4 (tile origins are multiples of 16 and S
+            // of 8), so the residue of u mod 4 is the wave index v
+            switch (v) {
+                case 0: seed_adj_levels<0>(dT0, dT1, dT2, S, u, w, ivp, d, ae, as); break;
+                case 1: seed_adj_levels<1>(dT0, dT1, dT2, S, u, w, ivp, d, ae, as); break;
+                case 2: seed_adj_levels<2>(dT0, dT1, dT2, S, u, w, ivp, d, ae, as); break;
+                default: seed_adj_levels<3>(dT0, dT1, dT2, S, u, w, ivp, d, ae, as); break;
+            }
         }
         // one writer per pixel and quadrant; quadrants added in order 0..3
-        float2 &t = acc[pr * kAdjTile + pc];
+        float2 &t = acc[pr * kAccPitch + pc];
         t = make_float2(t.x + ae, t.y + as);
         __syncthreads();
     }
     const int r = r0 + ltid() / kAdjTile, c = c0 + ltid() % kAdjTile;
     if (r < S && c < S) {
-        a.dE[(size_t)r * S + c] = acc[ltid()].x;
-        a.dS[(size_t)r * S + c] = acc[ltid()].y;
+        const float2 t = acc[(ltid() / kAdjTile) * kAccPitch + ltid() % kAdjTile];
+        a.dE[(size_t)r * S + c] = t.x;
+        a.dS[(size_t)r * S + c] = t.y;
     }
     __syncthreads();
 }
