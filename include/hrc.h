@@ -104,7 +104,8 @@ hrc_status hrc_forward(hrc_context *ctx, int log2_size,
 
 /* Vector-Jacobian product of hrc_forward: given grad_fluence = dLoss/dF,
  * writes dLoss/d(emission) and dLoss/d(sigma_t).  The forward intervals and
- * cascades are recomputed inside the call (nothing is kept between calls);
+ * cascades are recomputed inside the call (nothing is kept between calls; R_0,
+ * which only the gather reads, is not recomputed);
  * the reverse runs the merge down from level 0 up, the merge up from level N
  * down, then the traced levels (the transposes of Eq. 7-8, 14-20 and of the
  * per-cell integral of Eq. 2-4).                                            */

@@ -108,7 +108,10 @@ int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, cons
             add(p);
         }
         cur = -1;
-        for (int n = N - 1; n >= 0; --n) {
+        // R_0 feeds only the gather: a gradient-only solve (no F) stops at R_1,
+        // the last level its reverse reads
+        const int n_last = b.F ? 0 : 1;
+        for (int n = N - 1; n >= n_last; --n) {
             float *dst;
             int o = n;
             if (keep_all_r) {

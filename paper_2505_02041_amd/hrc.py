@@ -110,9 +110,12 @@ class Context:
 
 
     def hrc_profile_solve(self, emission: torch.Tensor, sigma_t: torch.Tensor,
-                          grad_fluence: Optional[torch.Tensor] = None):
-        """One forward (or, with grad_fluence, one backward) with a HIP event
-        around every pass; returns [(pass name, level, milliseconds)]."""
+                          grad_fluence: Optional[torch.Tensor] = None,
+                          return_outputs: bool = False):
+        """One forward (or, with grad_fluence, one backward), each pass timed by
+        HIP events recorded at its kernel's start and end; returns
+        [(pass name, level, milliseconds)], and with return_outputs also the
+        fluence (forward) or (d emission, d sigma_t) (backward)."""
         _check_field(emission, "emission")
         _check_field(sigma_t, "sigma_t")
         N = _log2_size(emission)
@@ -132,7 +135,10 @@ class Context:
             gs.data_ptr() if bwd else None, ws.data_ptr(), ws.numel(),
             _stream_handle(emission.device), ms, kind, lvl, cap, ctypes.byref(count)),
             "hrc_profile_solve")
-        return [(_lib.PASS_NAMES[kind[i]], lvl[i], ms[i]) for i in range(min(count.value, cap))]
+        passes = [(_lib.PASS_NAMES[kind[i]], lvl[i], ms[i]) for i in range(min(count.value, cap))]
+        if return_outputs:
+            return passes, ((ge, gs) if bwd else F)
+        return passes
 
 
 _contexts: Dict[int, Context] = {}

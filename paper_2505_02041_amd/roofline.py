@@ -70,8 +70,9 @@ def forward_bytes(N: int) -> float:
 
 
 def backward_bytes(N: int) -> float:
-    """hrc_backward: the forward recomputed (without the gather) plus the reverse."""
-    b = forward_bytes(N) - pass_bytes("frame_sum", N)
+    """hrc_backward: the forward recomputed (without R_0 and the gather) plus the
+    reverse."""
+    b = forward_bytes(N) - pass_bytes("frame_sum", N) - pass_bytes("merge_down", N, 0)
     b += pass_bytes("gather_adj", N)
     b += sum(pass_bytes("merge_down_adj", N, n) for n in range(N - 1))
     b += sum(pass_bytes("interval_adj", N, n) for n in range(N, -1, -1))
