@@ -11,6 +11,8 @@ Modules
                 merge up (Eq. 18-20), merge down (Eq. 13-17), quadrant gather
                 (Algorithm 1 ``Lighting``).
 ``hrc_vjp``     the hand-written reverse pass of ``hrc`` (vector-Jacobian product).
+``blur``        the cross blur after Algorithm 1 (Eq. 21, opacity rejection) and
+                its adjoint.
 ``bruteforce``  direct many-direction ray march of Eq. 1-3 (C, OpenMP) for the
                 method's approximation error.
 ``closed_forms`` closed-form fluences that pin the brute force.
