@@ -115,6 +115,9 @@ def main():
     if args.only_forward:
         print(json.dumps({"ms_per_step": fwd_s * 1e3, "copy_GBps": 2 * nbytes / copy_s / 1e9}))
         return
+    # ---- the cross blur of Eq. 21 after the gather (HRC_FLAG_BLUR) -----------
+    fwd_blur_s = timed(lambda: ctx.hrc_forward(eps, sig, F, flags=_lib.HRC_FLAG_BLUR),
+                       max(5, args.steps // 2), 2)
     # ---- forward + backward (the backward recomputes the forward) ------------
     log("forward+backward")
     fb_s = timed(lambda: (ctx.hrc_forward(eps, sig, F), ctx.hrc_backward(eps, sig, dF)),
@@ -156,6 +159,8 @@ def main():
         "config": {"workload": "hrc_forward 1024x1024, 1 channel: 128 disks, 256 opaque boxes, "
                                "32 thin sigma-100 lines, value-noise fog (seed 3)",
                    "grid": S, "quadrants": 4, "traced_levels": 3, "parallelism": "single GPU"},
+        "fwd_blur_ms": fwd_blur_s * 1e3,
+        "blur_overhead_us": (fwd_blur_s - fwd_s) * 1e6,
         "fwd_bwd_mpixel_per_s": S * S / fb_s / 1e6,
         "fwd_bwd_ms": fb_s * 1e3,
         "fwd_model_GBps": step_bytes / fwd_s / 1e9,

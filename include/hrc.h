@@ -8,7 +8,7 @@
  * T_0..T_N (traced levels 0..2, then the merge up of Section 4.1, Eq. 18-20),
  * merges the probe cascades down (Eq. 13-17, R_N = 0), and gathers R_0 at the
  * probe one pixel ahead (Algorithm 1, Lighting); the four quadrants are summed.
- * No blur is applied (Eq. 21 is a separate post-process).
+ * The cross blur of Eq. 21 is applied only with HRC_FLAG_BLUR.
  *
  * Conventions shared by every entry point
  *   - Grids are float32 [S][S] row-major: element (r, c) at r*S + c.
@@ -56,6 +56,12 @@ typedef enum {
 
 /* Flags.  HRC_FLAG_VALIDATE scans eps and sigma on the device first and
  * synchronises the stream to report HRC_ERR_INPUT (debug use only).
+ * HRC_FLAG_BLUR (forward and backward) applies the 1-px cross blur of Eq. 21
+ * to the summed fluence: (1/8)[0 1 0; 1 4 1; 0 1 0], ignoring 4-neighbours
+ * outside the grid or whose opacity 1 - exp(-sigma_t) differs from the
+ * pixel's by more than 0.5, and renormalising over the weights kept; the
+ * backward then starts with the blur's transpose (the kept set is piecewise
+ * constant in sigma_t and adds no dLoss/d sigma_t term).
  * HRC_FLAG_QUADRANTS_{1,2,4} (forward only) choose how many quadrant solves
  * run side by side, each group reusing one set of pyramid buffers: fewer means
  * a smaller working set (it can stay in the 256 MB Infinity Cache) but more,
@@ -63,6 +69,7 @@ typedef enum {
  * bitwise identical for every choice; the workspace size depends on it, so
  * pass the same flags to hrc_workspace_bytes. */
 #define HRC_FLAG_VALIDATE 0x1u
+#define HRC_FLAG_BLUR 0x2u
 #define HRC_FLAG_QUADRANTS_1 0x10u
 #define HRC_FLAG_QUADRANTS_2 0x20u
 #define HRC_FLAG_QUADRANTS_4 0x30u
@@ -127,7 +134,9 @@ typedef enum {
     HRC_PASS_GATHER_ADJ = 4,  /* adjoint of the gather */
     HRC_PASS_MERGE_DOWN_ADJ = 5,
     HRC_PASS_INTERVAL_ADJ = 6,
-    HRC_PASS_SEED_ADJ = 7
+    HRC_PASS_SEED_ADJ = 7,
+    HRC_PASS_BLUR = 8,        /* cross blur (Eq. 21) */
+    HRC_PASS_BLUR_ADJ = 9     /* its transpose */
 } hrc_pass_kind;
 
 /* Runs one hrc_forward (grad_fluence == NULL) or one hrc_backward (then

@@ -16,6 +16,10 @@ paper quantifies neither the opacity nor "significantly"; the readings here:
 The kept/ignored choice is piecewise constant in sigma_t, so the adjoint
 carries no dLoss/d sigma_t term from the blur (its derivative is zero almost
 everywhere); dLoss/dF is the transpose of the linear filter.
+
+The choice is an integer outcome decided in floating point; it is taken in
+FP32 (the kernel's precision, the paper fixing none), so that both sides keep
+the same neighbours.  The averaging itself is FP64.
 """
 from __future__ import annotations
 
@@ -26,14 +30,16 @@ NEIGHBOURS = ((-1, 0), (1, 0), (0, -1), (0, 1))
 
 
 def opacity(sigma):
-    """alpha = 1 - exp(-sigma_t) of one unit cell side."""
-    return -np.expm1(-np.asarray(sigma, np.float64))
+    """alpha = 1 - exp(-sigma_t) of one unit cell side, in FP32 (the precision
+    in which the kept neighbours are chosen)."""
+    return -np.expm1(-np.asarray(sigma, np.float32))
 
 
 def kept_neighbours(sigma, threshold: float = DEFAULT_THRESHOLD):
     """keep[i][r][c] for neighbour i of NEIGHBOURS: inside the grid and within
-    ``threshold`` in opacity of pixel (r, c)."""
+    ``threshold`` in opacity of pixel (r, c) (compared in FP32)."""
     a = opacity(sigma)
+    thr = np.float32(threshold)
     S0, S1 = a.shape
     keep = np.zeros((4,) + a.shape, dtype=bool)
     for i, (dr, dc) in enumerate(NEIGHBOURS):
@@ -41,7 +47,7 @@ def kept_neighbours(sigma, threshold: float = DEFAULT_THRESHOLD):
             for c in range(S1):
                 rr, cc = r + dr, c + dc
                 if 0 <= rr < S0 and 0 <= cc < S1:
-                    keep[i, r, c] = abs(a[rr, cc] - a[r, c]) <= threshold
+                    keep[i, r, c] = np.abs(a[rr, cc] - a[r, c]) <= thr
     return keep
 
 

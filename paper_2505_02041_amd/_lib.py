@@ -21,6 +21,7 @@ HRC_ERR_INPUT = -6
 HRC_MIN_LOG2 = 3
 HRC_MAX_LOG2 = 12
 HRC_FLAG_VALIDATE = 0x1
+HRC_FLAG_BLUR = 0x2
 HRC_FLAG_QUADRANTS_1 = 0x10
 HRC_FLAG_QUADRANTS_2 = 0x20
 HRC_FLAG_QUADRANTS_4 = 0x30
@@ -28,10 +29,11 @@ HRC_FLAG_QUADRANTS_MASK = 0x30
 HRC_FLAG_BATCH_FULL = 0x100
 HRC_FLAG_BATCH_DENSE = 0x200
 PASS_NAMES = ["seed", "merge_up", "merge_down", "frame_sum", "gather_adj",
-              "merge_down_adj", "interval_adj", "seed_adj"]
+              "merge_down_adj", "interval_adj", "seed_adj", "blur", "blur_adj"]
 # Kernel symbol of each pass kind (what a profiler shows).
 PASS_KERNELS = ["hrc_seed", "hrc_merge_up", "hrc_merge_down", "hrc_frame_sum",
-                "hrc_gather_adj", "hrc_merge_down_adj", "hrc_interval_adj", "hrc_seed_adj"]
+                "hrc_gather_adj", "hrc_merge_down_adj", "hrc_interval_adj", "hrc_seed_adj",
+                "hrc_blur", "hrc_blur_adj"]
 
 # Every function the header declares, with (restype, argtypes).
 _vp = ctypes.c_void_p

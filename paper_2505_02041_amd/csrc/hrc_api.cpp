@@ -46,6 +46,10 @@ Layout make_layout(int N, bool backward, int group) {
     return L;
 }
 
+// Flags hrc_forward, hrc_backward and hrc_workspace_bytes accept.
+static constexpr unsigned kSolveFlags =
+    HRC_FLAG_VALIDATE | HRC_FLAG_QUADRANTS_MASK | HRC_FLAG_BLUR;
+
 // Quadrant group of a forward: from the flags, else the library default.
 static int forward_group(int N, unsigned flags) {
     switch ((flags & HRC_FLAG_QUADRANTS_MASK) >> 4) {
@@ -130,15 +134,35 @@ int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, cons
         }
     }
     if (b.F) {
+        // with the blur, the gather goes to a buffer that is free by now: a
+        // ping-pong cascade level, or (every level kept) dR_0, which the
+        // reverse writes only later
+        float *gathered = b.blur ? (keep_all_r ? w.dR(0) : w.R(0)) : b.F;
         p = Phase();
         p.kind = PH_FRAME_SUM;
-        p.a.fs = FrameSumArgs{keep_all_r ? w.R(0) : w.R0all(), nullptr, b.F, nullptr, N, 1};
+        p.a.fs = FrameSumArgs{keep_all_r ? w.R(0) : w.R0all(), nullptr, gathered, nullptr, N, 1};
         add(p);
+        if (b.blur) {
+            p = Phase();
+            p.kind = PH_BLUR;
+            p.a.bl = BlurArgs{gathered, b.sig, b.F, N, kBlurThreshold};
+            add(p);
+        }
     }
     if (b.dF) {
+        // with the blur, its transpose first, into R_0's buffer (the reverse
+        // never reads R_0, and the gather above has consumed it)
+        const float *dgathered = b.dF;
+        if (b.blur) {
+            p = Phase();
+            p.kind = PH_BLUR_ADJ;
+            p.a.bl = BlurArgs{b.dF, b.sig, w.R(0), N, kBlurThreshold};
+            add(p);
+            dgathered = w.R(0);
+        }
         p = Phase();
         p.kind = PH_GATHER_ADJ;
-        p.a.ga = GatherAdjArgs{b.dF, w.dR(0), N};
+        p.a.ga = GatherAdjArgs{dgathered, w.dR(0), N};
         add(p);
         for (int n = 0; n + 1 < N; ++n) {
             p = Phase();
@@ -218,7 +242,7 @@ hrc_status hrc_workspace_bytes(int log2_size, unsigned flags, size_t *forward_by
                                size_t *backward_bytes) {
     hrc_status st = check_shape(log2_size);
     if (st != HRC_OK) return st;
-    if (flags & ~(HRC_FLAG_VALIDATE | HRC_FLAG_QUADRANTS_MASK)) return HRC_ERR_UNSUPPORTED;
+    if (flags & ~kSolveFlags) return HRC_ERR_UNSUPPORTED;
     if (forward_bytes)
         *forward_bytes = make_layout(log2_size, false, forward_group(log2_size, flags)).total;
     if (backward_bytes) *backward_bytes = make_layout(log2_size, true).total;
@@ -255,7 +279,7 @@ hrc_status hrc_forward(hrc_context *ctx, int log2_size, const float *emission,
     if (!aligned16(emission) || !aligned16(sigma_t) || !aligned16(fluence) ||
         !aligned16(workspace))
         return HRC_ERR_INVALID_ARG;
-    if (flags & ~(HRC_FLAG_VALIDATE | HRC_FLAG_QUADRANTS_MASK)) return HRC_ERR_UNSUPPORTED;
+    if (flags & ~kSolveFlags) return HRC_ERR_UNSUPPORTED;
     Layout L = make_layout(log2_size, false, forward_group(log2_size, flags));
     if (workspace_bytes < L.total) return HRC_ERR_WORKSPACE;
     if (!ctx) return HRC_ERR_INVALID_ARG;
@@ -268,7 +292,8 @@ hrc_status hrc_forward(hrc_context *ctx, int log2_size, const float *emission,
         if (st != HRC_OK) return st;
     }
     Phase ph[kMaxPhases];
-    SolveBuffers b{emission, sigma_t, fluence, nullptr, nullptr, nullptr};
+    SolveBuffers b{emission, sigma_t, fluence, nullptr, nullptr, nullptr,
+                   (flags & HRC_FLAG_BLUR) ? 1 : 0};
     int np = build_solve_phases(w, b, false, nullptr, ph, kMaxPhases);
     return run_phases(ph, np, s);
 }
@@ -282,7 +307,7 @@ hrc_status hrc_backward(hrc_context *ctx, int log2_size, const float *emission,
     if (!aligned16(emission) || !aligned16(sigma_t) || !aligned16(grad_fluence) ||
         !aligned16(grad_emission) || !aligned16(grad_sigma_t) || !aligned16(workspace))
         return HRC_ERR_INVALID_ARG;
-    if (flags & ~(HRC_FLAG_VALIDATE | HRC_FLAG_QUADRANTS_MASK)) return HRC_ERR_UNSUPPORTED;
+    if (flags & ~kSolveFlags) return HRC_ERR_UNSUPPORTED;
     Layout L = make_layout(log2_size, true);
     if (workspace_bytes < L.total) return HRC_ERR_WORKSPACE;
     if (!ctx) return HRC_ERR_INVALID_ARG;
@@ -295,7 +320,8 @@ hrc_status hrc_backward(hrc_context *ctx, int log2_size, const float *emission,
         if (st != HRC_OK) return st;
     }
     Phase ph[kMaxPhases];
-    SolveBuffers b{emission, sigma_t, nullptr, grad_fluence, grad_emission, grad_sigma_t};
+    SolveBuffers b{emission, sigma_t, nullptr, grad_fluence, grad_emission, grad_sigma_t,
+                   (flags & HRC_FLAG_BLUR) ? 1 : 0};
     int np = build_solve_phases(w, b, true, nullptr, ph, kMaxPhases);
     return run_phases(ph, np, s);
 }

@@ -101,9 +101,20 @@ struct SeedAdjArgs {
     int N;
 };
 
+// Cross blur after the gather (Eq. 21) and its transpose: out = blur(F) with
+// the opacity of each pixel alpha = 1 - exp(-sigma), neighbours further than
+// `thr` in opacity (or outside the grid) ignored and the weights renormalised.
+struct BlurArgs {
+    const float *in;   // F (forward) or dLoss/d(blurred F) (adjoint)
+    const float *sig;
+    float *out;        // blurred F (forward) or dLoss/dF (adjoint)
+    int N;
+    float thr;
+};
+
 enum PhaseKind {
     PH_SEED = 0, PH_UP, PH_DOWN, PH_FRAME_SUM, PH_GATHER_ADJ,
-    PH_DOWN_ADJ, PH_DT, PH_SEED_ADJ, PH_KIND_COUNT
+    PH_DOWN_ADJ, PH_DT, PH_SEED_ADJ, PH_BLUR, PH_BLUR_ADJ, PH_KIND_COUNT
 };
 
 // One pass.  U = elements per thread of the elementwise phases (a tile covers
@@ -120,6 +131,7 @@ struct Phase {
         DownAdjArgs da;
         DTArgs dt;
         SeedAdjArgs sa;
+        BlurArgs bl;
         A() : dt{} {}
     } a;
 };
@@ -131,7 +143,11 @@ struct SolveBuffers {
     float *F;
     const float *dF;
     float *dE, *dS;  // all three NULL: forward only
+    int blur = 0;    // cross blur after the gather (forward) / its transpose first (reverse)
 };
+// Opacity threshold of the cross blur (Eq. 21): |alpha_nb - alpha| above it ignores
+// the neighbour.
+constexpr float kBlurThreshold = 0.5f;
 int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, const int *U,
                        Phase *out, int max_out);
 

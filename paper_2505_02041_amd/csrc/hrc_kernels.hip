@@ -902,6 +902,72 @@ __device__ __forceinline__ void body_seed_adj(const SeedAdjArgs &a, unsigned til
     __syncthreads();
 }
 
+// Cross blur of Eq. 21 on 16x16 pixel tiles: each pixel averages itself
+// (weight 4) with its 4-neighbours inside the grid whose opacity
+// alpha = 1 - exp(-sigma) is within `thr` of its own (weight 1 each), divided
+// by the weights kept, so a neighbour that is ignored renormalises the rest.
+__device__ __forceinline__ float blur_alpha(const float *sig, int S, int r, int c) {
+    return -expm1f(-sig[(size_t)r * S + c]);
+}
+__device__ __forceinline__ bool blur_inside(int S, int r, int c) {
+    return r >= 0 && r < S && c >= 0 && c < S;
+}
+
+__device__ void body_blur(const BlurArgs &a, unsigned tile) {
+    const int S = 1 << a.N;
+    const int tiles = (S + 15) >> 4;
+    const int r = (int)(tile / tiles) * 16 + (ltid() >> 4), c = (int)(tile % tiles) * 16 + (ltid() & 15);
+    if (r >= S || c >= S) return;
+    const float am = blur_alpha(a.sig, S, r, c);
+    float acc = 4.f * a.in[(size_t)r * S + c], wsum = 4.f;
+    const int dr[4] = {-1, 1, 0, 0}, dc[4] = {0, 0, -1, 1};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int rr = r + dr[i], cc = c + dc[i];
+        if (blur_inside(S, rr, cc) && fabsf(blur_alpha(a.sig, S, rr, cc) - am) <= a.thr) {
+            acc += a.in[(size_t)rr * S + cc];
+            wsum += 1.f;
+        }
+    }
+    a.out[(size_t)r * S + c] = acc / wsum;
+}
+
+// Transpose of body_blur (gather form): pixel q receives 4 g_q from itself and
+// g_p from each 4-neighbour p that keeps q, with g_p = dOut_p / (4 + kept_p);
+// kept_p needs the opacities around p, so each pixel reads a radius-2 diamond
+// of sigma.  No dLoss/d sigma term: the kept set is piecewise constant in sigma.
+__device__ __forceinline__ float blur_weight(const BlurArgs &a, int S, int r, int c, float ar) {
+    // 1 / (4 + number of neighbours of (r, c) it keeps)
+    float wsum = 4.f;
+    const int dr[4] = {-1, 1, 0, 0}, dc[4] = {0, 0, -1, 1};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int rr = r + dr[i], cc = c + dc[i];
+        if (blur_inside(S, rr, cc) && fabsf(blur_alpha(a.sig, S, rr, cc) - ar) <= a.thr)
+            wsum += 1.f;
+    }
+    return 1.f / wsum;
+}
+
+__device__ void body_blur_adj(const BlurArgs &a, unsigned tile) {
+    const int S = 1 << a.N;
+    const int tiles = (S + 15) >> 4;
+    const int r = (int)(tile / tiles) * 16 + (ltid() >> 4), c = (int)(tile % tiles) * 16 + (ltid() & 15);
+    if (r >= S || c >= S) return;
+    const float aq = blur_alpha(a.sig, S, r, c);
+    float acc = 4.f * a.in[(size_t)r * S + c] * blur_weight(a, S, r, c, aq);
+    const int dr[4] = {-1, 1, 0, 0}, dc[4] = {0, 0, -1, 1};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int rr = r + dr[i], cc = c + dc[i];
+        if (!blur_inside(S, rr, cc)) continue;
+        const float ap = blur_alpha(a.sig, S, rr, cc);
+        if (fabsf(aq - ap) <= a.thr)
+            acc += a.in[(size_t)rr * S + cc] * blur_weight(a, S, rr, cc, ap);
+    }
+    a.out[(size_t)r * S + c] = acc;
+}
+
 // The persistent kernel's one LDS buffer: the largest body it runs (the traced
 // levels run there on 16x16 tiles).
 constexpr int kMaxLds = kSeedAdjLds > SeedTile<16>::lds ? kSeedAdjLds : SeedTile<16>::lds;
@@ -916,6 +982,8 @@ __device__ __forceinline__ void run_phase(const Phase &p, unsigned tile, char *l
         case PH_DOWN_ADJ: body_merge_down_adj(p.a.da, tile, p.U); break;
         case PH_DT: body_dT(p.a.dt, tile, p.U); break;
         case PH_SEED_ADJ: body_seed_adj(p.a.sa, tile, lds); break;
+        case PH_BLUR: body_blur(p.a.bl, tile); break;
+        case PH_BLUR_ADJ: body_blur_adj(p.a.bl, tile); break;
         default: break;
     }
 }
@@ -942,6 +1010,10 @@ __global__ __launch_bounds__(256) void hrc_seed(Phase p) {
 __global__ __launch_bounds__(256) void hrc_seed_adj(Phase p) {
     __shared__ __align__(16) char lds[kSeedAdjLds];
     body_seed_adj(p.a.sa, blockIdx.x, lds);
+}
+__global__ __launch_bounds__(256) void hrc_blur(Phase p) { body_blur(p.a.bl, blockIdx.x); }
+__global__ __launch_bounds__(256) void hrc_blur_adj(Phase p) {
+    body_blur_adj(p.a.bl, blockIdx.x);
 }
 __global__ __launch_bounds__(256) void hrc_frame_sum(Phase p) {
     __shared__ __align__(16) char lds[kFrameSumLds];
@@ -1105,6 +1177,8 @@ unsigned phase_tiles(const Phase &p) {
             case PH_DOWN_ADJ: return p.a.da.N;
             case PH_DT: return p.a.dt.N;
             case PH_SEED_ADJ: return p.a.sa.N;
+            case PH_BLUR:
+            case PH_BLUR_ADJ: return p.a.bl.N;
         }
         return 0;
     }();
@@ -1122,6 +1196,8 @@ unsigned phase_tiles(const Phase &p) {
         case PH_DT: return cdiv(4 * t_level_entries(N, p.a.dt.n) / 2, per);
         case PH_DOWN: return cdiv((size_t)p.a.down.nq * SS / 2, per);
         case PH_DOWN_ADJ: return cdiv(4 * SS / 2, per);
+        case PH_BLUR:
+        case PH_BLUR_ADJ:
         case PH_SEED_ADJ: {
             const unsigned t16 = (unsigned)((S + 15) / 16);
             return t16 * t16;
@@ -1147,6 +1223,8 @@ hipError_t launch_phase(const Phase &p, hipStream_t s, hipEvent_t start, hipEven
         case PH_DOWN_ADJ: k = hrc_merge_down_adj; break;
         case PH_DT: k = hrc_interval_adj; break;
         case PH_SEED_ADJ: k = hrc_seed_adj; break;
+        case PH_BLUR: k = hrc_blur; break;
+        case PH_BLUR_ADJ: k = hrc_blur_adj; break;
         default: return hipErrorInvalidValue;
     }
     if (start || stop)

@@ -160,11 +160,12 @@ class HRCFunction(torch.autograd.Function):
     intervals and cascades inside ``hrc_backward``."""
 
     @staticmethod
-    def forward(ctx, emission, sigma_t):
+    def forward(ctx, emission, sigma_t, blur=False):
         emission = emission.contiguous()
         sigma_t = sigma_t.contiguous()
         c = default_context(emission.device.index)
-        F = c.hrc_forward(emission, sigma_t)
+        ctx.flags = _lib.HRC_FLAG_BLUR if blur else 0
+        F = c.hrc_forward(emission, sigma_t, flags=ctx.flags)
         ctx.save_for_backward(emission, sigma_t)
         return F
 
@@ -172,13 +173,14 @@ class HRCFunction(torch.autograd.Function):
     def backward(ctx, grad_F):
         emission, sigma_t = ctx.saved_tensors
         c = default_context(emission.device.index)
-        ge, gs = c.hrc_backward(emission, sigma_t, grad_F.contiguous())
-        return ge, gs
+        ge, gs = c.hrc_backward(emission, sigma_t, grad_F.contiguous(), flags=ctx.flags)
+        return ge, gs, None
 
 
-def fluence(emission: torch.Tensor, sigma_t: torch.Tensor) -> torch.Tensor:
-    """Per-pixel fluence of a square power-of-two scene (differentiable)."""
-    return HRCFunction.apply(emission, sigma_t)
+def fluence(emission: torch.Tensor, sigma_t: torch.Tensor, blur: bool = False) -> torch.Tensor:
+    """Per-pixel fluence of a square power-of-two scene (differentiable); with
+    ``blur`` the cross blur of Eq. 21 follows the gather."""
+    return HRCFunction.apply(emission, sigma_t, blur)
 
 
 class Batch:

@@ -62,14 +62,20 @@ def test_opaque_wall_blocks_the_filter():
 
 
 def test_threshold_edge_is_inclusive():
-    """|d alpha| equal to the threshold keeps the neighbour, just above drops it."""
-    a0, a1 = 0.0, 0.5
-    sig = np.array([[-np.log1p(-a0), -np.log1p(-a1)]])
+    """An opacity difference equal to the threshold keeps the neighbour; the
+    next threshold below it drops it (both compared in FP32)."""
+    sig = np.array([[0.0, 0.7]], np.float32)
+    d = np.abs(blur.opacity(sig)[0, 1] - blur.opacity(sig)[0, 0])
     F = np.array([[1.0, 3.0]])
-    got = blur.cross_blur(F, sig, threshold=0.5 + 1e-12)
+    got = blur.cross_blur(F, sig, threshold=float(d))
     assert got[0, 0] == pytest.approx((4 * 1.0 + 3.0) / 5)
-    got = blur.cross_blur(F, sig, threshold=0.5 - 1e-9)
+    got = blur.cross_blur(F, sig, threshold=float(np.nextafter(d, np.float32(0))))
     assert got[0, 0] == pytest.approx(1.0)
+
+
+def test_opacity_is_one_minus_transmittance():
+    sig = np.array([0.0, 0.5, 3.0], np.float32)
+    assert np.allclose(blur.opacity(sig), 1 - np.exp(-sig.astype(np.float64)), rtol=1e-6)
 
 
 @pytest.mark.parametrize("seed", [4, 5])
