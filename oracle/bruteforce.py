@@ -37,6 +37,10 @@ def _load():
         lib.bf_fluence.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
         lib.bf_fluence.restype = ctypes.c_int
+        lib.bf_fluence_env.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_int, dp,
+                                       ctypes.c_int, dp]
+        lib.bf_fluence_env.restype = ctypes.c_int
         lib.bf_radiance.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double]
         lib.bf_radiance.restype = ctypes.c_double
@@ -48,15 +52,21 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def fluence(eps, sigma, M: int = 4096, crop=None) -> np.ndarray:
-    """Brute-force F at pixel centres of the crop (rows r0:r1, cols c0:c1)."""
+def fluence(eps, sigma, M: int = 4096, crop=None, environment=None) -> np.ndarray:
+    """Brute-force F at pixel centres of the crop (rows r0:r1, cols c0:c1);
+    ``environment``: K radiance samples at world angles 2 pi k / K (nearest
+    sample) lighting the grid from outside, or None."""
     lib = _load()
     eps = np.ascontiguousarray(eps, dtype=np.float64)
     sigma = np.ascontiguousarray(sigma, dtype=np.float64)
     S = eps.shape[0]
     r0, r1, c0, c1 = crop if crop is not None else (0, S, 0, S)
     out = np.zeros((r1 - r0, c1 - c0))
-    rc = lib.bf_fluence(S, _ptr(eps), _ptr(sigma), int(M), r0, r1, c0, c1, _ptr(out))
+    env = (np.zeros(1) if environment is None
+           else np.ascontiguousarray(environment, dtype=np.float64))
+    K = 0 if environment is None else len(env)
+    rc = lib.bf_fluence_env(S, _ptr(eps), _ptr(sigma), int(M), r0, r1, c0, c1, _ptr(env), K,
+                            _ptr(out))
     if rc != 0:
         raise ValueError("bad brute-force arguments")
     return out

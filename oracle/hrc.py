@@ -242,7 +242,7 @@ def merge_up(prev, n: int):
     return TL, TT
 
 
-def merge_down(Rnext, Tn, Tn1, n: int):
+def merge_down(Rnext, Tn, Tn1, n: int, env_next=None):
     """R_n from R_{n+1}, T_n and T_{n+1} (Eq. 14-17; Algorithm 1's third loop).
 
     For cone ii of probe (x*2^n, y), the upper (s=+1) and lower (s=-1) halves are
@@ -253,15 +253,19 @@ def merge_down(Rnext, Tn, Tn1, n: int):
     Even x (Eq. 15-17): p is the level n+1 probe in column x/2; with
       e2 = 2ii+1+s, q = p + v_{n+1}(e2) is column x/2+1 at row y + 2*e2 - 2^(n+1):
       F_s = ( R_{n+1}(p, jj) + A*T_{n+1}(p,e2).L + T_{n+1}(p,e2).T * R_{n+1}(q, jj) ) / 2.
-    R_n = F_+ + F_-.  Lookups of R beyond the last column or row are 0; R_N is 0.
+    R_n = F_+ + F_-.  Lookups of R beyond the last column or row are 0, or,
+    with an environment, ``env_next[jj]``: the environment's angular fluence in
+    cone jj of level n+1 (``environment_fluence``).
     """
     TnL, TnT = Tn
     T1L, T1T = Tn1
     S = TnL.shape[-1]
     a = 2 ** n
     X = S // a
-    # pad R_{n+1} with one zero column: column S/2^(n+1) lies beyond the grid
-    Rp = np.concatenate([Rnext, np.zeros((1,) + Rnext.shape[1:])], axis=0)
+    env_next = np.zeros(2 * a) if env_next is None else np.asarray(env_next, np.float64)
+    # pad R_{n+1} with one column beyond the grid (column S/2^(n+1))
+    beyond = np.broadcast_to(env_next[None, :, None], (1,) + Rnext.shape[1:])
+    Rp = np.concatenate([Rnext, beyond], axis=0)
     R = np.zeros((X, a, S))
     for ii in range(a):
         for s in (-1, 1):
@@ -270,11 +274,11 @@ def merge_down(Rnext, Tn, Tn1, n: int):
             A = cone_angle(n + 1, jj)
             # odd x = 1, 3, ...: (x+1)/2 = 1, 2, ...
             e = ii + up
-            far = shifted(Rp[1:, jj], 2 * e - a, 0.0)
+            far = shifted(Rp[1:, jj], 2 * e - a, env_next[jj])
             R[1::2, ii] += merge_r((A * TnL[1::2, e], TnT[1::2, e]), far)
             # even x = 0, 2, ...: x/2 = 0, 1, ...; x/2+1 = 1, 2, ...
             e2 = 2 * ii + 1 + s
-            far2 = shifted(Rp[1:, jj], 2 * e2 - 2 * a, 0.0)
+            far2 = shifted(Rp[1:, jj], 2 * e2 - 2 * a, env_next[jj])
             f1 = merge_r((A * T1L[:, e2], T1T[:, e2]), far2)
             R[0::2, ii] += (Rp[:-1, jj] + f1) / 2
     return R
@@ -294,45 +298,96 @@ def build_pyramid(E, Sg, seed_levels: int = 3):
     return T
 
 
-def cascades_from_pyramid(T):
-    """R_{N-1}..R_0 from a T pyramid, with R_N = 0 (Section 4.2).
-    Returns the list R with R[n] = R_n for n = 0..N-1."""
+def cascades_from_pyramid(T, env=None):
+    """R_{N-1}..R_0 from a T pyramid, with R_N = 0 (Section 4.2), or, with an
+    environment (``env[m]`` = its angular fluence per cone of level m), R_N
+    looked up from it (the footnote to Section 4.2) and so is every lookup
+    outside the grid.  Returns the list R with R[n] = R_n for n = 0..N-1."""
     N = len(T) - 1
     S = T[0][0].shape[-1]
     R = [None] * (N + 1)
     R[N] = np.zeros((1, 2 ** N, S))
+    if env is not None:
+        R[N] += np.asarray(env[N], np.float64)[None, :, None]
     for n in range(N - 1, -1, -1):
-        R[n] = merge_down(R[n + 1], T[n], T[n + 1], n)
+        R[n] = merge_down(R[n + 1], T[n], T[n + 1], n, None if env is None else env[n + 1])
     return R[:N]
 
 
-def gather(R0):
+def gather(R0, env0: float = 0.0):
     """Algorithm 1, Lighting: the quadrant's contribution to pixel [u, w] is
-    R_0([u+1, w], 0); the last column has no probe beyond it and gets 0."""
+    R_0([u+1, w], 0); the last column looks beyond the grid and gets 0, or the
+    environment's fluence over the quadrant, ``env0``."""
     S = R0.shape[-1]
-    Q = np.zeros((S, S))
+    Q = np.full((S, S), float(env0))
     Q[: S - 1] = R0[1:, 0, :]
     return Q
 
 
-def quadrant(E, Sg, seed_levels: int = 3):
-    """One HRC(X, Y) solve plus its gather, in the frame of the quadrant."""
+def quadrant(E, Sg, seed_levels: int = 3, env=None):
+    """One HRC(X, Y) solve plus its gather, in the frame of the quadrant; ``env``
+    as for ``cascades_from_pyramid``."""
     T = build_pyramid(np.asarray(E, np.float64), np.asarray(Sg, np.float64), seed_levels)
-    R = cascades_from_pyramid(T)
-    return gather(R[0])
+    R = cascades_from_pyramid(T, env)
+    return gather(R[0], 0.0 if env is None else float(env[0][0]))
 
 
-def fluence(eps, sigma, seed_levels: int = 3):
+# --------------------------------------------------------------------------
+# Environment (the footnote to Section 4.2): light from beyond the grid
+# --------------------------------------------------------------------------
+
+def frame_to_world(d, du, dw):
+    """World direction (dc, dr) of the frame vector (du, dw) of quadrant d
+    (c: column, increasing +x; r: row, increasing +y), as in ``to_frame``."""
+    if d == "+x":
+        return du, dw
+    if d == "-x":
+        return -du, dw
+    if d == "+y":
+        return dw, du
+    if d == "-y":
+        return dw, -du
+    raise ValueError(d)
+
+
+def environment_radiance(samples, theta: float) -> float:
+    """Radiance of an environment map given as K samples at world angles
+    2 pi k / K (angle from +x towards +y), looked up at the nearest sample."""
+    K = len(samples)
+    k = int(round(theta * K / (2 * math.pi))) % K
+    return float(samples[k])
+
+
+def environment_fluence(samples, d, N: int):
+    """env[m][jj] = A_m(jj) times the environment's radiance in the direction of
+    v_m(jj + 1/2), the cone's centre (the map is looked up in the direction of
+    v_N(i), footnote to Section 4.2), for m = 0..N in the frame of quadrant d."""
+    env = []
+    for m in range(N + 1):
+        a = 2 ** m
+        row = np.zeros(a)
+        for jj in range(a):
+            dc, dr = frame_to_world(d, a, 2 * jj + 1 - a)
+            row[jj] = cone_angle(m, jj) * environment_radiance(samples, math.atan2(dr, dc))
+        env.append(row)
+    return env
+
+
+def fluence(eps, sigma, seed_levels: int = 3, environment=None):
     """Per-pixel fluence F of a square power-of-two scene (Algorithm 1, Lighting):
-    the sum of the four quadrant solves, before any blur."""
+    the sum of the four quadrant solves, before any blur.  ``environment``: K
+    radiance samples of an environment map lighting the grid from outside
+    (``environment_radiance``), or None for no light beyond the grid."""
     eps = np.asarray(eps, dtype=np.float64)
     sigma = np.asarray(sigma, dtype=np.float64)
     if eps.shape != sigma.shape or eps.ndim != 2 or eps.shape[0] != eps.shape[1]:
         raise ValueError("eps and sigma must be equal square 2-D arrays")
     log2_size(eps.shape[0])
+    N = log2_size(eps.shape[0])
     F = np.zeros(eps.shape)
     for d in QUADRANTS:
-        Q = quadrant(to_frame(eps, d), to_frame(sigma, d), seed_levels)
+        env = None if environment is None else environment_fluence(environment, d, N)
+        Q = quadrant(to_frame(eps, d), to_frame(sigma, d), seed_levels, env)
         F += from_frame(Q, d)
     return F
 

@@ -17,7 +17,8 @@ from __future__ import annotations
 import numpy as np
 
 from .hrc import (QUADRANTS, build_pyramid, cascades_from_pyramid, cell_interval,
-                  cone_angle, from_frame, log2_size, probe_offsets, shifted, to_frame)
+                  cone_angle, environment_fluence, from_frame, log2_size, probe_offsets,
+                  shifted, to_frame)
 
 
 def cell_interval_grad(eps, sig, ell):
@@ -49,16 +50,19 @@ def gather_vjp(dQ):
     return dR0
 
 
-def merge_down_vjp(dR, Rnext, Tn, Tn1, n, dRnext, dTn, dTn1):
+def merge_down_vjp(dR, Rnext, Tn, Tn1, n, dRnext, dTn, dTn1, env_next=None):
     """Transpose of ``merge_down`` at level n: accumulate into dR_{n+1}
-    (``dRnext``, padded with the out-of-grid column), dT_n and dT_{n+1}."""
+    (``dRnext``, padded with the out-of-grid column), dT_n and dT_{n+1}.  The
+    out-of-grid values (0, or the environment's ``env_next``) are constants."""
     TnL, TnT = Tn
     T1L, T1T = Tn1
     dTnL, dTnT = dTn
     dT1L, dT1T = dTn1
     S = TnL.shape[-1]
     a = 2 ** n
-    Rp = np.concatenate([Rnext, np.zeros((1,) + Rnext.shape[1:])], axis=0)
+    env_next = np.zeros(2 * a) if env_next is None else np.asarray(env_next, np.float64)
+    beyond = np.broadcast_to(env_next[None, :, None], (1,) + Rnext.shape[1:])
+    Rp = np.concatenate([Rnext, beyond], axis=0)
     for ii in range(a):
         for s in (-1, 1):
             up = 1 if s > 0 else 0
@@ -68,7 +72,7 @@ def merge_down_vjp(dR, Rnext, Tn, Tn1, n, dRnext, dTn, dTn1):
             g = dR[1::2, ii]
             e = ii + up
             sh = 2 * e - a
-            far = shifted(Rp[1:, jj], sh, 0.0)
+            far = shifted(Rp[1:, jj], sh, env_next[jj])
             dTnL[1::2, e] += A * g
             dTnT[1::2, e] += g * far
             dRnext[1:, jj] += unshift(g * TnT[1::2, e], sh)
@@ -76,7 +80,7 @@ def merge_down_vjp(dR, Rnext, Tn, Tn1, n, dRnext, dTn, dTn1):
             g = dR[0::2, ii] / 2
             e2 = 2 * ii + 1 + s
             sh2 = 2 * e2 - 2 * a
-            far2 = shifted(Rp[1:, jj], sh2, 0.0)
+            far2 = shifted(Rp[1:, jj], sh2, env_next[jj])
             dRnext[:-1, jj] += g
             dT1L[:, e2] += A * g
             dT1T[:, e2] += g * far2
@@ -157,21 +161,26 @@ def seed_level_vjp(E, Sg, n, dT, dE, dS):
     dS += dSp[pad:pad + S, pad:pad + S]
 
 
-def quadrant_vjp(E, Sg, dQ, seed_levels=3):
+def quadrant_vjp(E, Sg, dQ, seed_levels=3, env=None):
     """Reverse of one quadrant solve: forward values are recomputed, then the
     merge down is reversed from level 0 upwards, the merge up from level N
-    downwards, and finally the traced levels."""
+    downwards, and finally the traced levels.  ``env`` as for
+    ``cascades_from_pyramid`` (constant: it has no adjoint here)."""
     E = np.asarray(E, np.float64)
     Sg = np.asarray(Sg, np.float64)
     S = E.shape[0]
     N = log2_size(S)
     T = build_pyramid(E, Sg, seed_levels)
-    R = cascades_from_pyramid(T) + [np.zeros((1, 2 ** N, S))]
+    RN = np.zeros((1, 2 ** N, S))
+    if env is not None:
+        RN += np.asarray(env[N], np.float64)[None, :, None]
+    R = cascades_from_pyramid(T, env) + [RN]
     dT = [(np.zeros_like(t[0]), np.zeros_like(t[1])) for t in T]
     dRn = gather_vjp(dQ)
     for n in range(N):
         dRp = np.zeros((R[n + 1].shape[0] + 1,) + R[n + 1].shape[1:])
-        merge_down_vjp(dRn, R[n + 1], T[n], T[n + 1], n, dRp, dT[n], dT[n + 1])
+        merge_down_vjp(dRn, R[n + 1], T[n], T[n + 1], n, dRp, dT[n], dT[n + 1],
+                       None if env is None else env[n + 1])
         dRn = dRp[:-1]
     for n in range(N, seed_levels - 1, -1):
         if n >= 1:
@@ -183,16 +192,19 @@ def quadrant_vjp(E, Sg, dQ, seed_levels=3):
     return dE, dS
 
 
-def fluence_vjp(eps, sigma, dF, seed_levels=3):
-    """(dLoss/d eps, dLoss/d sigma) given dLoss/dF, for ``oracle.hrc.fluence``."""
+def fluence_vjp(eps, sigma, dF, seed_levels=3, environment=None):
+    """(dLoss/d eps, dLoss/d sigma) given dLoss/dF, for ``oracle.hrc.fluence``
+    (with the same ``environment``)."""
     eps = np.asarray(eps, np.float64)
     sigma = np.asarray(sigma, np.float64)
     dF = np.asarray(dF, np.float64)
+    N = log2_size(eps.shape[0])
     dE = np.zeros(eps.shape)
     dS = np.zeros(eps.shape)
     for d in QUADRANTS:
+        env = None if environment is None else environment_fluence(environment, d, N)
         de, ds = quadrant_vjp(to_frame(eps, d), to_frame(sigma, d), to_frame(dF, d),
-                              seed_levels)
+                              seed_levels, env)
         dE += from_frame(de, d)
         dS += from_frame(ds, d)
     return dE, dS
