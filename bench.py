@@ -118,6 +118,10 @@ def main():
     # ---- the cross blur of Eq. 21 after the gather (HRC_FLAG_BLUR) -----------
     fwd_blur_s = timed(lambda: ctx.hrc_forward(eps, sig, F, flags=_lib.HRC_FLAG_BLUR),
                        max(5, args.steps // 2), 2)
+    # ---- with an environment map lighting the grid from outside --------------
+    ctx.set_environment([1.0 + 0.5 * np.sin(2 * np.pi * k / 64) for k in range(64)])
+    fwd_env_s = timed(lambda: ctx.hrc_forward(eps, sig, F), max(5, args.steps // 2), 2)
+    ctx.set_environment(None)
     # ---- forward + backward (the backward recomputes the forward) ------------
     log("forward+backward")
     fb_s = timed(lambda: (ctx.hrc_forward(eps, sig, F), ctx.hrc_backward(eps, sig, dF)),
@@ -161,6 +165,7 @@ def main():
                    "grid": S, "quadrants": 4, "traced_levels": 3, "parallelism": "single GPU"},
         "fwd_blur_ms": fwd_blur_s * 1e3,
         "blur_overhead_us": (fwd_blur_s - fwd_s) * 1e6,
+        "fwd_environment_ms": fwd_env_s * 1e3,
         "fwd_bwd_mpixel_per_s": S * S / fb_s / 1e6,
         "fwd_bwd_ms": fb_s * 1e3,
         "fwd_model_GBps": step_bytes / fwd_s / 1e9,

@@ -90,6 +90,26 @@ hrc_status hrc_create(int device, hrc_context **out);
  * enqueued with it. */
 void hrc_destroy(hrc_context *ctx);
 
+/* Light from beyond the grid (the footnote to Section 4.2): later hrc_forward,
+ * hrc_backward and hrc_profile_solve calls on this context take R_N, and every
+ * angular fluence looked up outside the grid (rows outside [0, S), columns at
+ * or past the far edge, the gather beyond the last column), from an
+ * environment map instead of 0: the map's radiance in the direction of the
+ * cone's centre v_m(jj + 1/2) times the cone's angle A_m(jj).  Outside the
+ * grid is vacuum.
+ *   radiance : host array of `samples` radiances at world angles 2 pi k /
+ *              samples, measured from +x (increasing column) towards +y
+ *              (increasing row); a direction takes the nearest sample (halfway
+ *              between two: the next one counter-clockwise).  Copied.
+ *   samples  : >= 1 to set the map, 0 to remove it (radiance ignored).
+ * A uniform map E in vacuum gives F = 2 pi E everywhere.  The environment is a
+ * constant of the backward (no gradient with respect to it).  Batches run
+ * without it.  Allocates device memory on first use and copies synchronously:
+ * call it when no work of this context is in flight.  Errors:
+ * HRC_ERR_INVALID_ARG (NULL context, samples < 0, NULL radiance with
+ * samples > 0), HRC_ERR_INPUT (a non-finite radiance), HRC_ERR_HIP. */
+hrc_status hrc_set_environment(hrc_context *ctx, const float *radiance, int samples);
+
 /* Static description of a status code (never NULL). */
 const char *hrc_status_string(hrc_status s);
 

@@ -56,11 +56,11 @@ static double march(int S, const double *eps, const double *sig,
 
 /* Environment radiance seen along the outward direction of angle th (from +x,
  * the column axis, towards +y, the row axis): K samples at angles 2 pi k / K,
- * nearest sample. */
+ * nearest sample (halfway: the next one counter-clockwise). */
 static double env_radiance(const double *env, int K, double th) {
     const double two_pi = 6.283185307179586476925286766559;
-    double a = th / two_pi * K;
-    long k = lround(a);
+    double a = th * K / two_pi;
+    long k = (long)floor(a + 0.5);
     k %= K;
     if (k < 0) k += K;
     return env[k];

@@ -352,9 +352,10 @@ def frame_to_world(d, du, dw):
 
 def environment_radiance(samples, theta: float) -> float:
     """Radiance of an environment map given as K samples at world angles
-    2 pi k / K (angle from +x towards +y), looked up at the nearest sample."""
+    2 pi k / K (angle from +x towards +y), looked up at the nearest sample
+    (halfway between two samples: the next one counter-clockwise)."""
     K = len(samples)
-    k = int(round(theta * K / (2 * math.pi))) % K
+    k = math.floor(theta * K / (2 * math.pi) + 0.5) % K
     return float(samples[k])
 
 

@@ -55,6 +55,7 @@ class hrc_scene(ctypes.Structure):
 SIGNATURES = {
     "hrc_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp)]),
     "hrc_destroy": (None, [_vp]),
+    "hrc_set_environment": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int]),
     "hrc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "hrc_workspace_bytes": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint,
                                            ctypes.POINTER(_sz), ctypes.POINTER(_sz)]),

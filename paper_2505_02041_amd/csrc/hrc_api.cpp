@@ -5,6 +5,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <cmath>
 #include <vector>
 
 #include "../../include/hrc.h"
@@ -72,6 +73,35 @@ static void cone_table(float *out) {
     }
 }
 
+// Environment fluence per quadrant and cone (the footnote to Section 4.2): for
+// quadrant q, level m <= HRC_MAX_LOG2 and cone jj, A_m(jj) times the radiance of
+// the map in the world direction of the cone's centre v_m(jj + 1/2), the map
+// being K samples at angles 2 pi k / K from +x (columns) towards +y (rows),
+// nearest sample (halfway: the next one counter-clockwise).  Quadrant frames:
+// +x (u, w) = (c, r), -x (S-1-c, r), +y (r, c), -y (S-1-r, c).
+static void environment_table(const float *radiance, int K, float *out) {
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int q = 0; q < kQuadrants; ++q) {
+        for (int m = 0; m <= kMaxLog2; ++m) {
+            const double a = double(1 << m);
+            for (int jj = 0; jj < (1 << m); ++jj) {
+                const double du = a, dw = 2.0 * jj + 1.0 - a;
+                double dc, dr;
+                switch (q) {
+                    case 0: dc = du; dr = dw; break;
+                    case 1: dc = -du; dr = dw; break;
+                    case 2: dc = dw; dr = du; break;
+                    default: dc = dw; dr = -du; break;
+                }
+                long k = (long)floor(atan2(dr, dc) * K / two_pi + 0.5) % K;
+                if (k < 0) k += K;
+                const double A = atan2(2.0 * (jj + 1) - a, a) - atan2(2.0 * jj - a, a);
+                out[(size_t)q * kConeTable + (1 << m) - 1 + jj] = float(A * radiance[k]);
+            }
+        }
+    }
+}
+
 static bool aligned16(const void *p) { return p && (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 static hrc_status check_shape(int log2_size) {
@@ -128,7 +158,8 @@ int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, cons
             p.kind = PH_DOWN;
             p.U = pick_u(U, PH_DOWN);
             p.a.down = DownArgs{(n + 1 < N) ? w.R(cur) : nullptr, w.T(n), w.T(n + 1), dst,
-                                t_level_entries(N, n), t_level_entries(N, n + 1), N, n, G};
+                                t_level_entries(N, n), t_level_entries(N, n + 1), N, n, G,
+                                b.env, q0};
             add(p);
             cur = o;
         }
@@ -140,7 +171,8 @@ int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, cons
         float *gathered = b.blur ? (keep_all_r ? w.dR(0) : w.R(0)) : b.F;
         p = Phase();
         p.kind = PH_FRAME_SUM;
-        p.a.fs = FrameSumArgs{keep_all_r ? w.R(0) : w.R0all(), nullptr, gathered, nullptr, N, 1};
+        p.a.fs = FrameSumArgs{keep_all_r ? w.R(0) : w.R0all(), nullptr, gathered, nullptr, N, 1,
+                              b.env};
         add(p);
         if (b.blur) {
             p = Phase();
@@ -188,6 +220,7 @@ int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, cons
             d.en = t_level_entries(N, n);
             d.en1 = n + 1 <= N ? t_level_entries(N, n + 1) : 0;
             d.N = N;
+            d.env = b.env;
             d.n = n;
             p.a.dt = d;
             add(p);
@@ -269,7 +302,37 @@ hrc_status hrc_create(int device, hrc_context **out) {
     return HRC_OK;
 }
 
-void hrc_destroy(hrc_context *ctx) { free(ctx); }
+void hrc_destroy(hrc_context *ctx) {
+    if (!ctx) return;
+    if (ctx->env) {
+        DeviceGuard g(ctx->device);
+        (void)hipFree(ctx->env);
+    }
+    free(ctx);
+}
+
+hrc_status hrc_set_environment(hrc_context *ctx, const float *radiance, int samples) {
+    if (!ctx || samples < 0 || (samples > 0 && !radiance)) return HRC_ERR_INVALID_ARG;
+    for (int k = 0; k < samples; ++k)
+        if (!std::isfinite(radiance[k])) return HRC_ERR_INPUT;
+    if (samples == 0) {
+        ctx->has_env = 0;
+        return HRC_OK;
+    }
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return HRC_ERR_HIP;
+    const size_t bytes = sizeof(float) * kQuadrants * kConeTable;
+    if (!ctx->env && hipMalloc(&ctx->env, bytes) != hipSuccess) {
+        ctx->env = nullptr;
+        return HRC_ERR_HIP;
+    }
+    std::vector<float> table((size_t)kQuadrants * kConeTable);
+    environment_table(radiance, samples, table.data());
+    if (hipMemcpy(ctx->env, table.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
+        return HRC_ERR_HIP;
+    ctx->has_env = 1;
+    return HRC_OK;
+}
 
 hrc_status hrc_forward(hrc_context *ctx, int log2_size, const float *emission,
                        const float *sigma_t, float *fluence, void *workspace,
@@ -293,7 +356,7 @@ hrc_status hrc_forward(hrc_context *ctx, int log2_size, const float *emission,
     }
     Phase ph[kMaxPhases];
     SolveBuffers b{emission, sigma_t, fluence, nullptr, nullptr, nullptr,
-                   (flags & HRC_FLAG_BLUR) ? 1 : 0};
+                   (flags & HRC_FLAG_BLUR) ? 1 : 0, ctx->has_env ? ctx->env : nullptr};
     int np = build_solve_phases(w, b, false, nullptr, ph, kMaxPhases);
     return run_phases(ph, np, s);
 }
@@ -321,7 +384,7 @@ hrc_status hrc_backward(hrc_context *ctx, int log2_size, const float *emission,
     }
     Phase ph[kMaxPhases];
     SolveBuffers b{emission, sigma_t, nullptr, grad_fluence, grad_emission, grad_sigma_t,
-                   (flags & HRC_FLAG_BLUR) ? 1 : 0};
+                   (flags & HRC_FLAG_BLUR) ? 1 : 0, ctx->has_env ? ctx->env : nullptr};
     int np = build_solve_phases(w, b, true, nullptr, ph, kMaxPhases);
     return run_phases(ph, np, s);
 }
@@ -359,9 +422,11 @@ hrc_status hrc_profile_solve(hrc_context *ctx, int log2_size, const float *emiss
     hipStream_t s = static_cast<hipStream_t>(stream);
     Ws w{static_cast<char *>(workspace), L};
     Phase ph[kMaxPhases];
+    const float *env = ctx->has_env ? ctx->env : nullptr;
     SolveBuffers b = bwd ? SolveBuffers{emission, sigma_t, nullptr, grad_fluence, grad_emission,
-                                        grad_sigma_t}
-                         : SolveBuffers{emission, sigma_t, fluence, nullptr, nullptr, nullptr};
+                                        grad_sigma_t, 0, env}
+                         : SolveBuffers{emission, sigma_t, fluence, nullptr, nullptr, nullptr,
+                                        0, env};
     const int np = build_solve_phases(w, b, bwd, nullptr, ph, kMaxPhases);
     // events 2i, 2i+1: start and end of pass i, recorded by the launch itself
     std::vector<hipEvent_t> ev(2 * np, nullptr);

@@ -10,6 +10,8 @@
 struct hrc_context {
     int device;
     int num_cus;
+    float *env;    // device [4][kConeTable]: environment fluence per quadrant and cone
+    int has_env;   // set by hrc_set_environment
 };
 
 namespace hrc {
@@ -66,14 +68,24 @@ struct SeedArgs {
     int tile;           // image tile side: 32 standalone, 16 in the persistent kernel
 };
 struct UpArgs { const float2 *Tp; float2 *T; size_t ep, e; int N, n, nq; };
+// env (nullable): the environment's angular fluence per quadrant and cone,
+// [4][kConeTable] with cone jj of level m at (2^m - 1) + jj, read for every
+// angular fluence looked up outside the grid (and for R_N); NULL gives 0.
 struct DownArgs {
     const float *Rn1;        // R_{n+1}; unused when n + 1 == N
     const float2 *Tn, *Tn1;  // T_n, T_{n+1}
     float *R;                // R_n
     size_t en, en1;
     int N, n, nq;
+    const float *env;        // environment table (nullable)
+    int q0;                  // absolute quadrant of the group's first solve
 };
-struct FrameSumArgs { const float *src, *src2; float *out, *out2; int N, off; };
+struct FrameSumArgs {
+    const float *src, *src2;
+    float *out, *out2;
+    int N, off;
+    const float *env;        // off = 1: the gather beyond the last column (nullable)
+};
 struct GatherAdjArgs { const float *dF; float *dR0; int N; };
 struct DownAdjArgs {
     const float *dR;         // dR_n
@@ -92,6 +104,7 @@ struct DTArgs {
     float2 *dT;              // out: dT_n
     size_t en, en1;
     int N, n, has_up;
+    const float *env;        // environment table (nullable), all four quadrants
 };
 struct SeedAdjArgs {
     const float *eps, *sig;
@@ -144,6 +157,7 @@ struct SolveBuffers {
     const float *dF;
     float *dE, *dS;  // all three NULL: forward only
     int blur = 0;    // cross blur after the gather (forward) / its transpose first (reverse)
+    const float *env = nullptr;  // environment table (hrc_context::env) or NULL
 };
 // Opacity threshold of the cross blur (Eq. 21): |alpha_nb - alpha| above it ignores
 // the neighbour.

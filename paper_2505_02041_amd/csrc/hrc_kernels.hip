@@ -95,9 +95,15 @@ __device__ __forceinline__ int stencil_id(int n, int k) {
 }
 
 // R_m(column c, cone jj, row y) of one quadrant, 0 outside the grid; R_N = 0.
-__device__ __forceinline__ float r_lookup(const float *Rq, int N, int m, int c, int jj, int y) {
+// The environment's angular fluence in cone jj of level m (0 without one).
+__device__ __forceinline__ float env_fluence(const float *envq, int m, int jj) {
+    return envq ? envq[(1 << m) - 1 + jj] : 0.f;
+}
+
+__device__ __forceinline__ float r_lookup(const float *Rq, int N, int m, int c, int jj, int y,
+                                          const float *envq) {
     const int S = 1 << N;
-    if (m >= N || c >= (S >> m) || y < 0 || y >= S) return 0.f;
+    if (m >= N || c >= (S >> m) || y < 0 || y >= S) return env_fluence(envq, m, jj);
     return Rq[((size_t)((c << m) | jj)) * S + y];
 }
 
@@ -277,11 +283,15 @@ __device__ void body_merge_up(const UpArgs &a, unsigned tile, int U) {
     }
 }
 
-// R_m of one quadrant at (c, jj) for the row pair (y, y+1), y even; zero
-// outside the grid, and R_N = 0.
-__device__ __forceinline__ float2 r_pair(const float *Rq, int N, int m, int c, int jj, int y) {
+// R_m of one quadrant at (c, jj) for the row pair (y, y+1), y even; outside the
+// grid, and for R_N, the environment's fluence (0 without one).
+__device__ __forceinline__ float2 r_pair(const float *Rq, int N, int m, int c, int jj, int y,
+                                         const float *envq) {
     const int S = 1 << N;
-    if (m >= N || c >= (S >> m) || y < 0 || y >= S) return make_float2(0.f, 0.f);
+    if (m >= N || c >= (S >> m) || y < 0 || y >= S) {
+        const float e = env_fluence(envq, m, jj);
+        return make_float2(e, e);
+    }
     return *reinterpret_cast<const float2 *>(Rq + ((size_t)((c << m) | jj)) * S + y);
 }
 
@@ -300,6 +310,7 @@ __device__ void body_merge_down(const DownArgs &a, unsigned tile, int U) {
         const unsigned r = row & (S - 1);
         const int x = r >> n, ii = r & ((1 << n) - 1);
         const float *Rq = a.Rn1 + q * SS;
+        const float *envq = a.env ? a.env + (size_t)(a.q0 + q) * kConeTable : nullptr;
         float acc0 = 0.f, acc1 = 0.f;
         if (x & 1) {
             // Eq. 14: trace the half-cone's outer edge to the level n+1 probe.
@@ -311,9 +322,9 @@ __device__ void body_merge_down(const DownArgs &a, unsigned tile, int U) {
                 const float A = c_cone[(1 << m) - 1 + jj];
                 const float4 t = ld_pair(Tx + (size_t)e * S + y);
                 const int yf = y + 2 * e - (1 << n);  // odd when n = 0
-                const float2 rf = n > 0 ? r_pair(Rq, N, m, c, jj, yf)
-                                        : make_float2(r_lookup(Rq, N, m, c, jj, yf),
-                                                      r_lookup(Rq, N, m, c, jj, yf + 1));
+                const float2 rf = n > 0 ? r_pair(Rq, N, m, c, jj, yf, envq)
+                                        : make_float2(r_lookup(Rq, N, m, c, jj, yf, envq),
+                                                      r_lookup(Rq, N, m, c, jj, yf + 1, envq));
                 acc0 += fmaf(t.y, rf.x, A * t.x);
                 acc1 += fmaf(t.w, rf.y, A * t.z);
             }
@@ -326,8 +337,8 @@ __device__ void body_merge_down(const DownArgs &a, unsigned tile, int U) {
                 const int e2 = 2 * ii + 2 * up, jj = 2 * ii + up;
                 const float A = c_cone[(1 << m) - 1 + jj];
                 const float4 t = ld_pair(Tx + (size_t)e2 * S + y);
-                const float2 r0 = r_pair(Rq, N, m, c, jj, y);
-                const float2 r1 = r_pair(Rq, N, m, c + 1, jj, y + 2 * e2 - (1 << m));
+                const float2 r0 = r_pair(Rq, N, m, c, jj, y, envq);
+                const float2 r1 = r_pair(Rq, N, m, c + 1, jj, y + 2 * e2 - (1 << m), envq);
                 acc0 += 0.5f * (r0.x + fmaf(t.y, r1.x, A * t.x));
                 acc1 += 0.5f * (r0.y + fmaf(t.w, r1.y, A * t.z));
             }
@@ -337,7 +348,8 @@ __device__ void body_merge_down(const DownArgs &a, unsigned tile, int U) {
 }
 
 // out[r][c] = sum over q of src_q[u + off][w], (u, w) the frame coordinates of
-// image pixel (r, c) in quadrant q; rows u + off >= S read as 0.  off = 1 is the
+// image pixel (r, c) in quadrant q; rows u + off >= S read as 0 (or, with an
+// environment, its fluence over the quadrant's level-0 cone).  off = 1 is the
 // gather of Algorithm 1 (R_0 at the probe one pixel ahead); off = 0 sums
 // per-quadrant frame fields back onto the image.  Two fields at once when
 // src2 is set.  32x32 tiles through LDS keep the +-x (transposed) reads
@@ -362,6 +374,8 @@ __device__ void body_frame_sum(const FrameSumArgs &a, unsigned tile, char *lds) 
                 if (us < S) {
                     acc0[i] += a.src[q * SS + (size_t)us * S + c];
                     if (two) acc1[i] += a.src2[q * SS + (size_t)us * S + c];
+                } else if (a.env) {
+                    acc0[i] += a.env[(size_t)q * kConeTable];  // beyond the grid: level 0, cone 0
                 }
             }
         }
@@ -378,6 +392,8 @@ __device__ void body_frame_sum(const FrameSumArgs &a, unsigned tile, char *lds) 
                 if (us < S) {
                     v0 = a.src[q * SS + (size_t)us * S + r];
                     if (two) v1 = a.src2[q * SS + (size_t)us * S + r];
+                } else if (a.env) {
+                    v0 = a.env[(size_t)q * kConeTable];
                 }
             }
             fs_tile[0][cl][tx] = v0;
@@ -454,6 +470,16 @@ __device__ __forceinline__ float2 ld2(const float *row, int y, int S, bool even)
     return make_float2((y >= 0 && y < S) ? row[y] : 0.f,
                        (y + 1 >= 0 && y + 1 < S) ? row[y + 1] : 0.f);
 }
+// R at (row, y), pair as ld2, when the row lies in the grid (`in`); elements
+// outside it read `fill` (the environment's fluence for the cone, or 0).
+__device__ __forceinline__ float2 ld2_r(bool in, const float *row, int y, int S, bool even,
+                                        float fill) {
+    if (!in) return make_float2(fill, fill);
+    if (even) return (y >= 0 && y < S) ? *reinterpret_cast<const float2 *>(row + y)
+                                       : make_float2(fill, fill);
+    return make_float2((y >= 0 && y < S) ? row[y] : fill,
+                       (y + 1 >= 0 && y + 1 < S) ? row[y + 1] : fill);
+}
 // Transmittances (the .y of two consecutive intervals) at y, 0 outside.
 __device__ __forceinline__ float2 ld2T(const float2 *row, int y, int S, bool even) {
     if (even) {
@@ -525,6 +551,7 @@ __device__ void body_dT(const DTArgs &a, unsigned tile, int U) {
         const unsigned r = row % rpq;
         const int x = r / dirs, k = r % dirs;
         float gl0 = 0.f, gt0 = 0.f, gl1 = 0.f, gt1 = 0.f;
+        const float *envq = a.env ? a.env + (size_t)q * kConeTable : nullptr;
         // (a) merge down at level n, odd x (Eq. 14): T_n(p, k) is the edge of
         //     cone k (lower half, jj = 2k) and of cone k-1 (upper half, jj = 2k-1).
         if (n < N && (x & 1)) {
@@ -536,9 +563,8 @@ __device__ void body_dT(const DTArgs &a, unsigned tile, int U) {
                 const float2 g = *reinterpret_cast<const float2 *>(
                     dRq + ((size_t)((x << n) | (k - 1))) * S + y);
                 const float A = c_cone[(1 << (n + 1)) - 1 + 2 * k - 1];
-                const float2 rv = rin ? ld2(Rq + ((size_t)((c << (n + 1)) | (2 * k - 1))) * S, yf,
-                                            S, n > 0)
-                                      : make_float2(0.f, 0.f);
+                const float2 rv = ld2_r(rin, Rq + ((size_t)((c << (n + 1)) | (2 * k - 1))) * S,
+                                        yf, S, n > 0, env_fluence(envq, n + 1, 2 * k - 1));
                 gl0 = fmaf(g.x, A, gl0); gl1 = fmaf(g.y, A, gl1);
                 gt0 = fmaf(g.x, rv.x, gt0); gt1 = fmaf(g.y, rv.y, gt1);
             }
@@ -546,9 +572,8 @@ __device__ void body_dT(const DTArgs &a, unsigned tile, int U) {
                 const float2 g = *reinterpret_cast<const float2 *>(
                     dRq + ((size_t)((x << n) | k)) * S + y);
                 const float A = c_cone[(1 << (n + 1)) - 1 + 2 * k];
-                const float2 rv = rin ? ld2(Rq + ((size_t)((c << (n + 1)) | (2 * k))) * S, yf, S,
-                                            n > 0)
-                                      : make_float2(0.f, 0.f);
+                const float2 rv = ld2_r(rin, Rq + ((size_t)((c << (n + 1)) | (2 * k))) * S, yf,
+                                        S, n > 0, env_fluence(envq, n + 1, 2 * k));
                 gl0 = fmaf(g.x, A, gl0); gl1 = fmaf(g.y, A, gl1);
                 gt0 = fmaf(g.x, rv.x, gt0); gt1 = fmaf(g.y, rv.y, gt1);
             }
@@ -566,9 +591,8 @@ __device__ void body_dT(const DTArgs &a, unsigned tile, int U) {
                 const float2 g0 = *reinterpret_cast<const float2 *>(
                     dRq + ((size_t)((xm << nm) | (k / 2 - 1))) * S + y);
                 const float A = c_cone[(1 << n) - 1 + k - 1];
-                const float2 rv = rin ? ld2(Rq + ((size_t)(((x + 1) << n) | (k - 1))) * S, yf, S,
-                                            true)
-                                      : make_float2(0.f, 0.f);
+                const float2 rv = ld2_r(rin, Rq + ((size_t)(((x + 1) << n) | (k - 1))) * S, yf,
+                                        S, true, env_fluence(envq, n, k - 1));
                 const float g0x = 0.5f * g0.x, g0y = 0.5f * g0.y;
                 gl0 = fmaf(g0x, A, gl0); gl1 = fmaf(g0y, A, gl1);
                 gt0 = fmaf(g0x, rv.x, gt0); gt1 = fmaf(g0y, rv.y, gt1);
@@ -577,8 +601,8 @@ __device__ void body_dT(const DTArgs &a, unsigned tile, int U) {
                 const float2 g0 = *reinterpret_cast<const float2 *>(
                     dRq + ((size_t)((xm << nm) | (k / 2))) * S + y);
                 const float A = c_cone[(1 << n) - 1 + k];
-                const float2 rv = rin ? ld2(Rq + ((size_t)(((x + 1) << n) | k)) * S, yf, S, true)
-                                      : make_float2(0.f, 0.f);
+                const float2 rv = ld2_r(rin, Rq + ((size_t)(((x + 1) << n) | k)) * S, yf, S,
+                                        true, env_fluence(envq, n, k));
                 const float g0x = 0.5f * g0.x, g0y = 0.5f * g0.y;
                 gl0 = fmaf(g0x, A, gl0); gl1 = fmaf(g0y, A, gl1);
                 gt0 = fmaf(g0x, rv.x, gt0); gt1 = fmaf(g0y, rv.y, gt1);

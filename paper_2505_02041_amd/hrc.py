@@ -64,6 +64,16 @@ class Context:
                 pass
             self._ptr = ctypes.c_void_p(0)
 
+    def set_environment(self, radiance: Optional[Sequence[float]]) -> None:
+        """Light from beyond the grid (``hrc_set_environment``): radiance samples at
+        world angles 2 pi k / K from +x (columns) towards +y (rows), or None."""
+        if radiance is None or len(radiance) == 0:
+            check(_lib.load().hrc_set_environment(self._ptr, None, 0), "hrc_set_environment")
+            return
+        arr = (ctypes.c_float * len(radiance))(*[float(v) for v in radiance])
+        check(_lib.load().hrc_set_environment(self._ptr, arr, len(radiance)),
+              "hrc_set_environment")
+
     def workspace(self, N: int, backward: bool, flags: int = 0) -> torch.Tensor:
         group = 0 if backward else flags & _lib.HRC_FLAG_QUADRANTS_MASK
         key = (N, backward, group)

@@ -138,3 +138,10 @@ def test_batch_argument_checks():
             HRC_ERR_UNSUPPORTED
     lib.hrc_batch_destroy(None)
     lib.hrc_destroy(None)
+
+
+def test_environment_argument_checks():
+    lib = _lib.load()
+    one = (ctypes.c_float * 1)(1.0)
+    assert lib.hrc_set_environment(None, one, 1) == HRC_ERR_INVALID_ARG
+    assert lib.hrc_set_environment(None, None, 0) == HRC_ERR_INVALID_ARG
