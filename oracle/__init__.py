@@ -13,6 +13,8 @@ Modules
 ``hrc_vjp``     the hand-written reverse pass of ``hrc`` (vector-Jacobian product).
 ``blur``        the cross blur after Algorithm 1 (Eq. 21, opacity rejection) and
                 its adjoint.
+``multibounce`` several diffuse bounces (fluence fed back as an in-scattering
+                source, Section 4.2) and their reverse pass.
 ``bruteforce``  direct many-direction ray march of Eq. 1-3 (C, OpenMP) for the
                 method's approximation error.
 ``closed_forms`` closed-form fluences that pin the brute force.
