@@ -122,6 +122,10 @@ def main():
     ctx.set_environment([1.0 + 0.5 * np.sin(2 * np.pi * k / 64) for k in range(64)])
     fwd_env_s = timed(lambda: ctx.hrc_forward(eps, sig, F), max(5, args.steps // 2), 2)
     ctx.set_environment(None)
+    # ---- six diffuse bounces (Section 4.2; Fig. 14 converges after 6) ---------
+    alb = torch.full_like(eps, 0.5)
+    fwd_6b_s = timed(lambda: ctx.hrc_multibounce_forward(eps, sig, alb, 6, out=F),
+                     max(3, args.steps // 10), 1)
     # ---- forward + backward (the backward recomputes the forward) ------------
     log("forward+backward")
     fb_s = timed(lambda: (ctx.hrc_forward(eps, sig, F), ctx.hrc_backward(eps, sig, dF)),
@@ -166,6 +170,7 @@ def main():
         "fwd_blur_ms": fwd_blur_s * 1e3,
         "blur_overhead_us": (fwd_blur_s - fwd_s) * 1e6,
         "fwd_environment_ms": fwd_env_s * 1e3,
+        "fwd_6_bounces_ms": fwd_6b_s * 1e3,
         "fwd_bwd_mpixel_per_s": S * S / fb_s / 1e6,
         "fwd_bwd_ms": fb_s * 1e3,
         "fwd_model_GBps": step_bytes / fwd_s / 1e9,

@@ -143,6 +143,34 @@ hrc_status hrc_backward(hrc_context *ctx, int log2_size,
                         void *workspace, size_t workspace_bytes,
                         void *stream, unsigned flags);
 
+/* ---- Several diffuse bounces ----------------------------------------------- */
+
+/* Multiple diffuse bounces (Section 4.2: the output fluence fed into another
+ * iteration): bounce 0 is hrc_forward of (emission, sigma_t); bounce k > 0 uses
+ * the emission eps_0 + albedo * sigma_t * F_{k-1} / (2 pi), the light that a
+ * pixel scatters isotropically over the plane; the result is F of the last of
+ * `bounces` (1..64) bounces.  albedo is [S][S] like the other fields (a value
+ * in [0, 1) makes the bounces converge).  The context's environment, if any,
+ * lights every bounce.  Flags: HRC_FLAG_VALIDATE (also checks albedo) and
+ * HRC_FLAG_QUADRANTS_*; HRC_FLAG_BLUR is not supported here.  Workspace from
+ * hrc_multibounce_workspace_bytes (it depends on `bounces` for the backward). */
+hrc_status hrc_multibounce_workspace_bytes(int log2_size, int bounces, unsigned flags,
+                                           size_t *forward_bytes, size_t *backward_bytes);
+hrc_status hrc_multibounce_forward(hrc_context *ctx, int log2_size, const float *emission,
+                                   const float *sigma_t, const float *albedo, int bounces,
+                                   float *fluence, void *workspace, size_t workspace_bytes,
+                                   void *stream, unsigned flags);
+
+/* Vector-Jacobian product of hrc_multibounce_forward: dLoss/d(emission),
+ * dLoss/d(sigma_t) (through every bounce's solve and through the sources) and
+ * dLoss/d(albedo).  The bounces are recomputed inside the call and reversed
+ * from the last. */
+hrc_status hrc_multibounce_backward(hrc_context *ctx, int log2_size, const float *emission,
+                                    const float *sigma_t, const float *albedo, int bounces,
+                                    const float *grad_fluence, float *grad_emission,
+                                    float *grad_sigma_t, float *grad_albedo, void *workspace,
+                                    size_t workspace_bytes, void *stream, unsigned flags);
+
 /* ---- Per-pass timing (profiling) ----------------------------------------- */
 
 /* Pass kinds reported by hrc_profile_solve. */

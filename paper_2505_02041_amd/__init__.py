@@ -8,7 +8,9 @@ memory and streams only.
 
     from paper_2505_02041_amd import fluence, Context, Batch
 """
-from .hrc import Batch, Context, HRCFunction, default_context, fluence  # noqa: F401
+from .hrc import (Batch, Context, HRCFunction, MultibounceFunction, default_context,  # noqa: F401
+                  fluence, fluence_multibounce)
 from ._lib import HRCError  # noqa: F401
 
-__all__ = ["fluence", "Context", "Batch", "HRCFunction", "default_context", "HRCError"]
+__all__ = ["fluence", "fluence_multibounce", "Context", "Batch", "HRCFunction",
+           "MultibounceFunction", "default_context", "HRCError"]

@@ -63,6 +63,14 @@ SIGNATURES = {
                                    ctypes.c_uint]),
     "hrc_backward": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
                                     _vp, ctypes.c_uint]),
+    "hrc_multibounce_workspace_bytes": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_uint,
+                                                       ctypes.POINTER(_sz),
+                                                       ctypes.POINTER(_sz)]),
+    "hrc_multibounce_forward": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, ctypes.c_int,
+                                               _vp, _vp, _sz, _vp, ctypes.c_uint]),
+    "hrc_multibounce_backward": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, ctypes.c_int,
+                                                _vp, _vp, _vp, _vp, _vp, _sz, _vp,
+                                                ctypes.c_uint]),
     "hrc_profile_solve": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                          _sz, _vp, ctypes.POINTER(ctypes.c_float),
                                          ctypes.POINTER(ctypes.c_int),

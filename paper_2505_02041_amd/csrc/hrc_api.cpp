@@ -389,6 +389,39 @@ hrc_status hrc_backward(hrc_context *ctx, int log2_size, const float *emission,
     return run_phases(ph, np, s);
 }
 
+// ---- several diffuse bounces ------------------------------------------------
+
+static constexpr int kMaxBounces = 64;
+
+// Workspace of the bounce loop: one solve's workspace, then the source buffer,
+// and for the reverse dLoss/dF of the previous bounce, dLoss/d eps and
+// dLoss/d sigma of one bounce, and the fluence of bounces 0..K-2.
+struct BounceLayout {
+    Layout solve;
+    size_t src = 0, g = 0, dE = 0, dS = 0, saved = 0, field = 0, total = 0;
+};
+
+static BounceLayout bounce_layout(int N, int bounces, bool backward, int group) {
+    BounceLayout M;
+    M.solve = make_layout(N, backward, group);
+    M.field = align256((size_t(1) << (2 * N)) * sizeof(float));
+    size_t off = align256(M.solve.total);
+    M.src = off;
+    off += M.field;
+    if (backward) {
+        M.g = off;
+        off += M.field;
+        M.dE = off;
+        off += M.field;
+        M.dS = off;
+        off += M.field;
+        M.saved = off;
+        off += (size_t)(bounces - 1) * M.field;
+    }
+    M.total = off;
+    return M;
+}
+
 static int phase_level(const Phase &p) {
     switch (p.kind) {
         case PH_UP: return p.a.up.n;
@@ -397,6 +430,127 @@ static int phase_level(const Phase &p) {
         case PH_DT: return p.a.dt.n;
         default: return -1;
     }
+}
+
+hrc_status hrc_multibounce_workspace_bytes(int log2_size, int bounces, unsigned flags,
+                                           size_t *forward_bytes, size_t *backward_bytes) {
+    hrc_status st = check_shape(log2_size);
+    if (st != HRC_OK) return st;
+    if (bounces < 1 || bounces > kMaxBounces) return HRC_ERR_INVALID_ARG;
+    if (flags & ~(HRC_FLAG_VALIDATE | HRC_FLAG_QUADRANTS_MASK)) return HRC_ERR_UNSUPPORTED;
+    if (forward_bytes)
+        *forward_bytes =
+            bounce_layout(log2_size, bounces, false, forward_group(log2_size, flags)).total;
+    if (backward_bytes) *backward_bytes = bounce_layout(log2_size, bounces, true, 4).total;
+    return HRC_OK;
+}
+
+hrc_status hrc_multibounce_forward(hrc_context *ctx, int log2_size, const float *emission,
+                                   const float *sigma_t, const float *albedo, int bounces,
+                                   float *fluence, void *workspace, size_t workspace_bytes,
+                                   void *stream, unsigned flags) {
+    hrc_status st = check_shape(log2_size);
+    if (st != HRC_OK) return st;
+    if (!aligned16(emission) || !aligned16(sigma_t) || !aligned16(albedo) ||
+        !aligned16(fluence) || !aligned16(workspace) || bounces < 1 || bounces > kMaxBounces)
+        return HRC_ERR_INVALID_ARG;
+    if (flags & ~(HRC_FLAG_VALIDATE | HRC_FLAG_QUADRANTS_MASK)) return HRC_ERR_UNSUPPORTED;
+    const BounceLayout M =
+        bounce_layout(log2_size, bounces, false, forward_group(log2_size, flags));
+    if (workspace_bytes < M.total) return HRC_ERR_WORKSPACE;
+    if (!ctx) return HRC_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return HRC_ERR_HIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(workspace);
+    Ws w{base, M.solve};
+    if (flags & HRC_FLAG_VALIDATE) {
+        st = validate_inputs(w, emission, sigma_t, s);
+        if (st == HRC_OK) st = validate_inputs(w, albedo, albedo, s);
+        if (st != HRC_OK) return st;
+    }
+    const size_t SS = M.solve.S * M.solve.S;
+    float *src = reinterpret_cast<float *>(base + M.src);
+    const float *env = ctx->has_env ? ctx->env : nullptr;
+    Phase ph[kMaxPhases];
+    for (int k = 0; k < bounces; ++k) {
+        // bounce k: source eps_0 (k = 0) or eps_0 + a sigma F_{k-1} / (2 pi)
+        if (k > 0 &&
+            launch_scatter_source(emission, sigma_t, albedo, fluence, src, SS, s) != hipSuccess)
+            return HRC_ERR_HIP;
+        SolveBuffers b{k == 0 ? emission : src, sigma_t, fluence, nullptr, nullptr, nullptr,
+                       0, env};
+        const int np = build_solve_phases(w, b, false, nullptr, ph, kMaxPhases);
+        st = run_phases(ph, np, s);
+        if (st != HRC_OK) return st;
+    }
+    return HRC_OK;
+}
+
+hrc_status hrc_multibounce_backward(hrc_context *ctx, int log2_size, const float *emission,
+                                    const float *sigma_t, const float *albedo, int bounces,
+                                    const float *grad_fluence, float *grad_emission,
+                                    float *grad_sigma_t, float *grad_albedo, void *workspace,
+                                    size_t workspace_bytes, void *stream, unsigned flags) {
+    hrc_status st = check_shape(log2_size);
+    if (st != HRC_OK) return st;
+    if (!aligned16(emission) || !aligned16(sigma_t) || !aligned16(albedo) ||
+        !aligned16(grad_fluence) || !aligned16(grad_emission) || !aligned16(grad_sigma_t) ||
+        !aligned16(grad_albedo) || !aligned16(workspace) || bounces < 1 ||
+        bounces > kMaxBounces)
+        return HRC_ERR_INVALID_ARG;
+    if (flags & ~(HRC_FLAG_VALIDATE | HRC_FLAG_QUADRANTS_MASK)) return HRC_ERR_UNSUPPORTED;
+    const BounceLayout M = bounce_layout(log2_size, bounces, true, 4);
+    if (workspace_bytes < M.total) return HRC_ERR_WORKSPACE;
+    if (!ctx) return HRC_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return HRC_ERR_HIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(workspace);
+    Ws w{base, M.solve};
+    if (flags & HRC_FLAG_VALIDATE) {
+        st = validate_inputs(w, emission, sigma_t, s);
+        if (st == HRC_OK) st = validate_inputs(w, albedo, albedo, s);
+        if (st != HRC_OK) return st;
+    }
+    const size_t SS = M.solve.S * M.solve.S;
+    float *src = reinterpret_cast<float *>(base + M.src);
+    float *gbuf = reinterpret_cast<float *>(base + M.g);
+    float *dE = reinterpret_cast<float *>(base + M.dE);
+    float *dS = reinterpret_cast<float *>(base + M.dS);
+    auto saved = [&](int k) { return reinterpret_cast<float *>(base + M.saved + k * M.field); };
+    const float *env = ctx->has_env ? ctx->env : nullptr;
+    Phase ph[kMaxPhases];
+    // the sources of bounces 1..K-1 need F_0..F_{K-2}: recompute and keep them
+    // (every cascade level kept, so the solve fits the reverse's workspace)
+    for (int k = 0; k + 1 < bounces; ++k) {
+        if (k > 0 && launch_scatter_source(emission, sigma_t, albedo, saved(k - 1), src, SS,
+                                           s) != hipSuccess)
+            return HRC_ERR_HIP;
+        SolveBuffers b{k == 0 ? emission : src, sigma_t, saved(k), nullptr, nullptr, nullptr,
+                       0, env};
+        const int np = build_solve_phases(w, b, true, nullptr, ph, kMaxPhases);
+        st = run_phases(ph, np, s);
+        if (st != HRC_OK) return st;
+    }
+    // reverse: bounce K-1 first; each bounce's dLoss/d eps feeds the previous
+    // bounce's dLoss/dF through the source
+    const float *gin = grad_fluence;
+    for (int k = bounces - 1; k >= 0; --k) {
+        if (k > 0 && launch_scatter_source(emission, sigma_t, albedo, saved(k - 1), src, SS,
+                                           s) != hipSuccess)
+            return HRC_ERR_HIP;
+        SolveBuffers b{k == 0 ? emission : src, sigma_t, nullptr, gin, dE, dS, 0, env};
+        const int np = build_solve_phases(w, b, true, nullptr, ph, kMaxPhases);
+        st = run_phases(ph, np, s);
+        if (st != HRC_OK) return st;
+        if (launch_scatter_adj(dE, dS, k > 0 ? saved(k - 1) : nullptr, sigma_t, albedo, gbuf,
+                               grad_emission, grad_sigma_t, grad_albedo, SS,
+                               k == bounces - 1 ? 1 : 0, s) != hipSuccess)
+            return HRC_ERR_HIP;
+        gin = gbuf;
+    }
+    return HRC_OK;
 }
 
 hrc_status hrc_profile_solve(hrc_context *ctx, int log2_size, const float *emission,

@@ -201,6 +201,19 @@ hipError_t persistent_occupancy(int variant, int *blocks_per_cu);
 hipError_t launch_validate(const float *a, const float *b, size_t n, int *flag,
                            hipStream_t s);
 
+// Several diffuse bounces: the next bounce's emission eps_0 + a sigma F / (2 pi)
+// (isotropic in-scattering), and the reverse step of that update given dLoss/d
+// eps_k = dE and the bounce's dLoss/d sigma = dS: d_eps += dE, d_sig += dS +
+// a F_prev dE / (2 pi), d_alb += sigma F_prev dE / (2 pi), g = a sigma dE / (2 pi)
+// (the previous bounce's dLoss/dF).  F_prev NULL: the first bounce (no source
+// term; g untouched, d_alb untouched or, with assign, zero).  assign: overwrite
+// the sums instead of adding.
+hipError_t launch_scatter_source(const float *eps0, const float *sig, const float *alb,
+                                 const float *F, float *out, size_t n, hipStream_t s);
+hipError_t launch_scatter_adj(const float *dE, const float *dS, const float *F_prev,
+                              const float *sig, const float *alb, float *g, float *d_eps,
+                              float *d_sig, float *d_alb, size_t n, int assign, hipStream_t s);
+
 constexpr int kMaxPhases = 8 * kMaxLog2 + 16;  // passes of one forward + backward solve
 
 // RAII switch to a device for the duration of a call.

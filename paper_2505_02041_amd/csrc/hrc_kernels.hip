@@ -1274,6 +1274,60 @@ hipError_t persistent_occupancy(int variant, int *blocks_per_cu) {
         blocks_per_cu, variant ? hrc_persistent_dense : hrc_persistent, 256 * kBatchQuarters, 0);
 }
 
+// Multiple bounces: the in-scattering source of the next bounce and the reverse
+// step of that update (elementwise, grid-stride).
+constexpr float kInvTwoPi = 0.15915494309189533577f;
+
+__global__ __launch_bounds__(256) void hrc_scatter_source(const float *eps0, const float *sig,
+                                                          const float *alb, const float *F,
+                                                          float *out, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+        out[i] = eps0[i] + alb[i] * sig[i] * F[i] * kInvTwoPi;
+}
+
+__global__ __launch_bounds__(256) void hrc_scatter_adj(const float *dE, const float *dS,
+                                                       const float *F_prev, const float *sig,
+                                                       const float *alb, float *g, float *d_eps,
+                                                       float *d_sig, float *d_alb, size_t n,
+                                                       int assign) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * 256) {
+        const float de = dE[i];
+        float ds = dS[i];
+        float da = 0.f;
+        if (F_prev) {
+            const float fp = F_prev[i] * de * kInvTwoPi;
+            ds += alb[i] * fp;
+            da = sig[i] * fp;
+            g[i] = alb[i] * sig[i] * de * kInvTwoPi;
+        }
+        d_eps[i] = assign ? de : d_eps[i] + de;
+        d_sig[i] = assign ? ds : d_sig[i] + ds;
+        if (F_prev) d_alb[i] = assign ? da : d_alb[i] + da;
+        else if (assign) d_alb[i] = 0.f;  // one bounce: no albedo dependence
+    }
+}
+
+static unsigned elementwise_blocks(size_t n) {
+    size_t b = (n + 255) / 256;
+    return (unsigned)(b > 8192 ? 8192 : b);
+}
+
+hipError_t launch_scatter_source(const float *eps0, const float *sig, const float *alb,
+                                 const float *F, float *out, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(hrc_scatter_source, dim3(elementwise_blocks(n)), dim3(256), 0, s, eps0,
+                       sig, alb, F, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_adj(const float *dE, const float *dS, const float *F_prev,
+                              const float *sig, const float *alb, float *g, float *d_eps,
+                              float *d_sig, float *d_alb, size_t n, int assign, hipStream_t s) {
+    hipLaunchKernelGGL(hrc_scatter_adj, dim3(elementwise_blocks(n)), dim3(256), 0, s, dE, dS,
+                       F_prev, sig, alb, g, d_eps, d_sig, d_alb, n, assign);
+    return hipGetLastError();
+}
+
 hipError_t launch_validate(const float *a, const float *b, size_t n, int *flag,
                            hipStream_t s) {
     unsigned blocks = (unsigned)((n + 255) / 256);

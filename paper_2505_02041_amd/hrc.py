@@ -119,6 +119,47 @@ class Context:
         return ge, gs
 
 
+    def _bounce_workspace(self, N: int, bounces: int, backward: bool) -> torch.Tensor:
+        key = ("bounces", N, bounces, backward)
+        ws = self._ws.get(key)
+        if ws is None:
+            f, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
+            check(_lib.load().hrc_multibounce_workspace_bytes(N, bounces, 0, ctypes.byref(f),
+                                                              ctypes.byref(b)),
+                  "hrc_multibounce_workspace_bytes")
+            ws = torch.empty(b.value if backward else f.value, dtype=torch.uint8,
+                             device=torch.device("cuda", self.device))
+            self._ws[key] = ws
+        return ws
+
+    def hrc_multibounce_forward(self, emission: torch.Tensor, sigma_t: torch.Tensor,
+                                albedo: torch.Tensor, bounces: int,
+                                out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        for t, n in ((emission, "emission"), (sigma_t, "sigma_t"), (albedo, "albedo")):
+            _check_field(t, n)
+        N = _log2_size(emission)
+        F = out if out is not None else torch.empty_like(emission)
+        ws = self._bounce_workspace(N, bounces, False)
+        check(_lib.load().hrc_multibounce_forward(
+            self._ptr, N, emission.data_ptr(), sigma_t.data_ptr(), albedo.data_ptr(), bounces,
+            F.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(emission.device), 0),
+            "hrc_multibounce_forward")
+        return F
+
+    def hrc_multibounce_backward(self, emission: torch.Tensor, sigma_t: torch.Tensor,
+                                 albedo: torch.Tensor, bounces: int, grad_fluence: torch.Tensor):
+        for t, n in ((emission, "emission"), (sigma_t, "sigma_t"), (albedo, "albedo"),
+                     (grad_fluence, "grad_fluence")):
+            _check_field(t, n)
+        N = _log2_size(emission)
+        ge, gs, ga = (torch.empty_like(emission) for _ in range(3))
+        ws = self._bounce_workspace(N, bounces, True)
+        check(_lib.load().hrc_multibounce_backward(
+            self._ptr, N, emission.data_ptr(), sigma_t.data_ptr(), albedo.data_ptr(), bounces,
+            grad_fluence.data_ptr(), ge.data_ptr(), gs.data_ptr(), ga.data_ptr(), ws.data_ptr(),
+            ws.numel(), _stream_handle(emission.device), 0), "hrc_multibounce_backward")
+        return ge, gs, ga
+
     def hrc_profile_solve(self, emission: torch.Tensor, sigma_t: torch.Tensor,
                           grad_fluence: Optional[torch.Tensor] = None,
                           return_outputs: bool = False):
@@ -191,6 +232,33 @@ def fluence(emission: torch.Tensor, sigma_t: torch.Tensor, blur: bool = False) -
     """Per-pixel fluence of a square power-of-two scene (differentiable); with
     ``blur`` the cross blur of Eq. 21 follows the gather."""
     return HRCFunction.apply(emission, sigma_t, blur)
+
+
+class MultibounceFunction(torch.autograd.Function):
+    """F after several diffuse bounces (``hrc_multibounce_forward``) with the
+    hand-written reverse (``hrc_multibounce_backward``) as backward."""
+
+    @staticmethod
+    def forward(ctx, emission, sigma_t, albedo, bounces):
+        emission, sigma_t, albedo = (t.contiguous() for t in (emission, sigma_t, albedo))
+        c = default_context(emission.device.index)
+        ctx.bounces = int(bounces)
+        ctx.save_for_backward(emission, sigma_t, albedo)
+        return c.hrc_multibounce_forward(emission, sigma_t, albedo, ctx.bounces)
+
+    @staticmethod
+    def backward(ctx, grad_F):
+        emission, sigma_t, albedo = ctx.saved_tensors
+        c = default_context(emission.device.index)
+        ge, gs, ga = c.hrc_multibounce_backward(emission, sigma_t, albedo, ctx.bounces,
+                                                grad_F.contiguous())
+        return ge, gs, ga, None
+
+
+def fluence_multibounce(emission: torch.Tensor, sigma_t: torch.Tensor, albedo: torch.Tensor,
+                        bounces: int) -> torch.Tensor:
+    """Fluence after ``bounces`` diffuse bounces (differentiable in all three fields)."""
+    return MultibounceFunction.apply(emission, sigma_t, albedo, bounces)
 
 
 class Batch:

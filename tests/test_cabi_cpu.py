@@ -145,3 +145,25 @@ def test_environment_argument_checks():
     one = (ctypes.c_float * 1)(1.0)
     assert lib.hrc_set_environment(None, one, 1) == HRC_ERR_INVALID_ARG
     assert lib.hrc_set_environment(None, None, 0) == HRC_ERR_INVALID_ARG
+
+
+def test_multibounce_argument_checks():
+    lib = _lib.load()
+    f, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.hrc_multibounce_workspace_bytes(5, 0, 0, ctypes.byref(f), None) == HRC_ERR_INVALID_ARG
+    assert lib.hrc_multibounce_workspace_bytes(5, 65, 0, ctypes.byref(f), None) == HRC_ERR_INVALID_ARG
+    assert lib.hrc_multibounce_workspace_bytes(5, 3, 0x2, ctypes.byref(f), None) == HRC_ERR_UNSUPPORTED
+    assert lib.hrc_multibounce_workspace_bytes(5, 3, 0, ctypes.byref(f), ctypes.byref(b)) == 0
+    single_f, single_b = _ws(5, 0)[1:]
+    S2 = 4 * 32 * 32
+    assert f.value >= single_f + S2 and b.value >= single_b + (4 + 2) * S2
+    f3 = f.value
+    assert lib.hrc_multibounce_workspace_bytes(5, 5, 0, ctypes.byref(f), ctypes.byref(b)) == 0
+    assert f.value == f3  # the forward does not keep bounces
+    buf = (ctypes.c_float * 64)()
+    p = ctypes.addressof(buf)
+    assert lib.hrc_multibounce_forward(None, 5, p, p, p, 3, p, p, f3, None, 0) == HRC_ERR_INVALID_ARG
+    assert lib.hrc_multibounce_forward(None, 5, p, p, p, 3, p, p, f3 - 1, None, 0) == HRC_ERR_WORKSPACE
+    assert lib.hrc_multibounce_forward(None, 5, p, p, p, 0, p, p, f3, None, 0) == HRC_ERR_INVALID_ARG
+    assert lib.hrc_multibounce_forward(None, 5, p, p, p, 3, p, p, f3, None, 0x2) == HRC_ERR_UNSUPPORTED
+    assert lib.hrc_multibounce_backward(None, 5, p, p, p, 3, p, p, p, p, p, 1, None, 0) == HRC_ERR_WORKSPACE
