@@ -243,12 +243,16 @@ __device__ __forceinline__ float4 far_pair(const float2 *row, int yf, int S) {
     return (yf >= 0 && yf < S) ? ld_pair(row + yf) : make_float4(0.f, 1.f, 0.f, 1.f);
 }
 
-// Merge up: T_n from T_{n-1} (Section 4.1, Eq. 18-20).
+// Merge up: T_n from T_{n-1} (Section 4.1, Eq. 18-20).  At the top level
+// n = N only the even directions are built: the merge down reads T_N only
+// through its doubled edges (even k, Eq. 15-17), and nothing else reads T_N.
 __device__ void body_merge_up(const UpArgs &a, unsigned tile, int U) {
     const int N = a.N, S = 1 << N, n = a.n;
     const int h = 1 << (n - 1);
     const int dirs = 2 * h + 1, pdirs = h + 1;
-    const unsigned rpq = (unsigned)(S >> n) * dirs;
+    const bool even_only = n == N;
+    const int kdirs = even_only ? pdirs : dirs;  // directions built per column
+    const unsigned rpq = (unsigned)(S >> n) * kdirs;
     const size_t total = (size_t)a.nq * rpq * (S / 2);
     for (int uu = 0; uu < U; ++uu) {
         const size_t idx = ((size_t)tile * U + uu) * 256 + ltid();
@@ -256,8 +260,9 @@ __device__ void body_merge_up(const UpArgs &a, unsigned tile, int U) {
         const int y = (int)(idx & (S / 2 - 1)) * 2;
         const unsigned row = (unsigned)(idx >> (N - 1));
         const int q = row / rpq;
-        const unsigned r = row % rpq;
-        const int x = r / dirs, k = r % dirs;
+        const unsigned rk = row % rpq;
+        const int x = rk / kdirs, k = even_only ? 2 * (rk % kdirs) : rk % kdirs;
+        const unsigned r = (unsigned)x * dirs + k;  // output row (x, k)
         const float2 *near = a.Tp + q * a.ep + (size_t)(2 * x) * pdirs * S;
         const float2 *far = near + (size_t)pdirs * S;
         float4 res;
@@ -1216,7 +1221,12 @@ unsigned phase_tiles(const Phase &p) {
             const unsigned t = (unsigned)((S + p.a.seed.tile - 1) / p.a.seed.tile);
             return t * t;
         }
-        case PH_UP: return cdiv((size_t)p.a.up.nq * t_level_entries(N, p.a.up.n) / 2, per);
+        case PH_UP: {
+            // the top level builds its even directions only
+            const size_t rows = p.a.up.n == N ? (size_t)((1 << (N - 1)) + 1)
+                                              : t_level_entries(N, p.a.up.n) / S;
+            return cdiv((size_t)p.a.up.nq * rows * S / 2, per);
+        }
         case PH_DT: return cdiv(4 * t_level_entries(N, p.a.dt.n) / 2, per);
         case PH_DOWN: return cdiv((size_t)p.a.down.nq * SS / 2, per);
         case PH_DOWN_ADJ: return cdiv(4 * SS / 2, per);

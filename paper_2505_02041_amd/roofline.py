@@ -27,7 +27,10 @@ def pass_bytes(name: str, N: int, n: int = -1, two_fields: bool = False) -> floa
         # the two fields read once for all four quadrants, T_0..T_2 written
         return 8 * SS + q * 8 * (_t(S, 0) + _t(S, 1) + _t(S, 2))
     if name == "merge_up":
-        return q * 8 * (_t(S, n - 1) + _t(S, n))
+        # the top level n = N builds only its even directions (all the merge
+        # down reads): 2^(N-1) + 1 of the 2^N + 1 rows
+        written = _t(S, n) if n < N else float(((1 << (N - 1)) + 1) * S)
+        return q * 8 * (_t(S, n - 1) + written)
     if name == "merge_down":
         # half of T_n (odd columns) and the even directions of T_{n+1}: together
         # X^2 (1 + 2^-n) intervals; R_{n+1} read unless n + 1 = N; R_n written
