@@ -124,8 +124,8 @@ __device__ __forceinline__ float r_lookup(const float *Rq, int N, int m, int c, 
 // half lengths 1/2, sqrt(2)/2 and sqrt(5)/4, and every traced ray is a fold of
 // 2^(n+1) half pieces.  The block computes the three intervals of its tile
 // plus a 4-pixel halo once into LDS (out-of-grid pixels are vacuum <0, 1>)
-// and then folds the 4 x 4864 rays whose probes lie in the tile; each wave
-// writes two rows of 32 consecutive y of one direction.
+// and then folds the 4 x 4864 rays whose probes lie in the tile, each thread
+// every direction of one probe at a time.
 // Thread index within a 256-thread work tile.  Every pass body is written for
 // 256 threads; the persistent kernel runs several tiles side by side in one
 // block, one per 256-thread quarter.
@@ -157,15 +157,17 @@ constexpr unsigned char kHpLen[10][8] = {
     {1, 1, 1, 1, 1, 1, 1, 1}, {2, 2, 2, 2, 2, 2, 2, 2}, {0, 0, 0, 0, 0, 0, 0, 0},
     {2, 2, 2, 2, 2, 2, 2, 2}, {1, 1, 1, 1, 1, 1, 1, 1}};
 
-// Rays of traced level n of quadrant q whose probes lie in the tile.  Rows
-// (k, xl) run with xl fastest and a wave covers 64/TILE whole rows of one
-// direction k, so the stencil lookups are wave-uniform.
+// Rays of traced level n of quadrant q whose probes lie in the tile.  A
+// thread owns one probe (column xl, row w) at a time and folds all its
+// directions (unrolled: the piece offsets are uniform over the wave), so the
+// LDS base and the output address are computed once per probe; lanes run
+// along w, so each direction's stores are contiguous rows.
 template <int TILE, int n>
 __device__ __forceinline__ void seed_level_rays(const float2 *iv, const SeedArgs &a, int q,
                                                 int slot, int r0, int c0) {
     using G = SeedTile<TILE>;
     constexpr int dirs = (1 << n) + 1, cols = TILE >> n, pieces = 2 << n;
-    constexpr int lg = TILE == 32 ? 5 : 4;
+    constexpr int per_pass = 256 / TILE;  // probe columns per pass of the block
     const int S = 1 << a.N;
     float2 *out = n == 0 ? a.T0 : n == 1 ? a.T1 : a.T2;
     const size_t qoff = n == 0 ? a.e0 : n == 1 ? a.e1 : a.e2;
@@ -174,25 +176,28 @@ __device__ __forceinline__ void seed_level_rays(const float2 *iv, const SeedArgs
     const int w_lo = q < 2 ? r0 : c0;
     const int su = q == 0 ? 1 : q == 1 ? -1 : q == 2 ? G::pitch : -G::pitch;
     const int sw = q < 2 ? G::pitch : 1;
-    for (int it = ltid(); it < dirs * cols * TILE; it += 256) {
-        const int row = it >> lg;
-        const int k = __builtin_amdgcn_readfirstlane(row / cols);
-        const int xl = row % cols;
-        const int u = u_lo + (xl << n), w = w_lo + (it & (TILE - 1));
+    const int wl = ltid() % TILE;
+    const int w = w_lo + wl;
+    constexpr int sid0 = n == 0 ? 0 : n == 1 ? 2 : 5;
+    for (int xl = ltid() / TILE; xl < cols; xl += per_pass) {
+        const int u = u_lo + (xl << n);
         if (u < 0 || u >= S || w >= S) continue;
         int lr, lc;
         if (q < 2) { lr = w - r0; lc = (q == 0 ? u : S - 1 - u) - c0; }
         else { lc = w - c0; lr = (q == 2 ? u : S - 1 - u) - r0; }
-        const int base = (lr + kSeedHalo) * G::pitch + lc + kSeedHalo;
-        const int sid = (n == 0 ? 0 : n == 1 ? 2 : 5) + k;
-        float2 acc = make_float2(0.f, 1.f);
+        const float2 *ivp = iv + (lr + kSeedHalo) * G::pitch + lc + kSeedHalo;
+        float2 *o = out + slot * qoff + (size_t)(u >> n) * dirs * S + w;
 #pragma unroll
-        for (int j = 0; j < pieces; ++j) {
-            const int off = kHpLen[sid][j] * (G::span * G::pitch) + kHpDu[sid][j] * su +
-                            kHpDw[sid][j] * sw;
-            acc = merge(acc, iv[base + off]);
+        for (int k = 0; k < dirs; ++k) {
+            float2 acc = make_float2(0.f, 1.f);
+#pragma unroll
+            for (int j = 0; j < pieces; ++j) {
+                const int off = kHpLen[sid0 + k][j] * (G::span * G::pitch) +
+                                kHpDu[sid0 + k][j] * su + kHpDw[sid0 + k][j] * sw;
+                acc = merge(acc, ivp[off]);
+            }
+            o[(size_t)k * S] = acc;
         }
-        out[slot * qoff + ((size_t)(u >> n) * dirs + k) * S + w] = acc;
     }
 }
 
