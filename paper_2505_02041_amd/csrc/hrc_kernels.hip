@@ -873,9 +873,13 @@ __device__ __forceinline__ void body_seed_adj(const SeedAdjArgs &a, unsigned til
             // re-lay the tile from quadrant q-1's frame into quadrant q's: read
             // every destination cell's source into registers, then write
             float2 tmp[kPer];
+            // the per-element indices are recomputed for each quadrant rather
+            // than kept live across the quadrant loop (register pressure)
+            int i0 = ltid();
+            __asm__ volatile("" : "+v"(i0));
 #pragma unroll
             for (int t = 0; t < kPer; ++t) {
-                const int i = ltid() + 256 * t;
+                const int i = i0 + 256 * t;
                 if (i < 3 * kAdjSpan * kAdjSpan) {
                     const int Lh = i / (kAdjSpan * kAdjSpan), rem = i % (kAdjSpan * kAdjSpan);
                     const int ul = rem % kAdjSpan - H, wl = rem / kAdjSpan - H;
@@ -892,7 +896,7 @@ __device__ __forceinline__ void body_seed_adj(const SeedAdjArgs &a, unsigned til
             __syncthreads();
 #pragma unroll
             for (int t = 0; t < kPer; ++t) {
-                const int i = ltid() + 256 * t;
+                const int i = i0 + 256 * t;
                 if (i < 3 * kAdjSpan * kAdjSpan) {
                     const int Lh = i / (kAdjSpan * kAdjSpan), rem = i % (kAdjSpan * kAdjSpan);
                     iv[Lh * plane + (rem / kAdjSpan) * P + rem % kAdjSpan] = tmp[t];
