@@ -174,3 +174,26 @@ def test_adam_recovers_scene(ctx):
         losses.append(loss.item())
     log(f"adam loss {losses[0]:.4g} -> {losses[-1]:.4g}")
     assert losses[-1] < 4e-3 * losses[0]
+
+
+@pytest.mark.parametrize("S", [1024, 4096])
+def test_backward_emission_adjoint_identity_at_full_size(ctx, S):
+    """At the benchmark size and the largest supported size: F is linear in the
+    emission for a fixed attenuation, so the emission gradient is the
+    transpose of the forward map itself and <dF, F(e')> = <d eps, e'> for any
+    probe e' (a property the oracle cannot reach at these sizes)."""
+    log(f"backward adjoint identity S={S}")
+    g = torch.Generator(device="cuda").manual_seed(S)
+    sig = torch.rand((S, S), device="cuda", generator=g) * 0.3
+    sig[S // 4:S // 4 + 16, S // 8:S // 2] = 50.0   # an opaque bar
+    eps = torch.rand((S, S), device="cuda", generator=g) * (
+        torch.rand((S, S), device="cuda", generator=g) < 0.05)
+    probe = torch.rand((S, S), device="cuda", generator=g)
+    dF = torch.randn((S, S), device="cuda", generator=g)
+    ge, _ = ctx.hrc_backward(eps, sig, dF)
+    Fp = ctx.hrc_forward(probe, sig)
+    torch.cuda.synchronize()
+    lhs = float((dF.double() * Fp.double()).sum())
+    rhs = float((ge.double() * probe.double()).sum())
+    assert lhs == pytest.approx(rhs, rel=2e-4), (lhs, rhs)
+    ctx.release_workspaces()
