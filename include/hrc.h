@@ -175,10 +175,13 @@ hrc_status hrc_multibounce_backward(hrc_context *ctx, int log2_size, const float
 
 /* Pass kinds reported by hrc_profile_solve. */
 typedef enum {
-    HRC_PASS_SEED = 0,        /* traced levels T_0..T_2 (Section 4.2) */
+    HRC_PASS_SEED = 0,        /* traced levels T_0..T_2 (Section 4.2); the forward stores T_2 only */
     HRC_PASS_MERGE_UP = 1,    /* T_n from T_(n-1) (Eq. 18-20) */
-    HRC_PASS_MERGE_DOWN = 2,  /* R_n from R_(n+1), T_n, T_(n+1) (Eq. 14-17) */
-    HRC_PASS_FRAME_SUM = 3,   /* quadrant gather into F (Algorithm 1, Lighting) */
+    HRC_PASS_MERGE_DOWN = 2,  /* R_n from R_(n+1), T_n, T_(n+1) (Eq. 14-17), down to level 2
+                                 (forward) or 1 (the reverse's recomputed forward) */
+    HRC_PASS_TAIL = 3,        /* R_1 and R_0 from R_2 with their traced intervals folded on
+                                 chip, the gather and the quadrant sum into F (Eq. 14-17,
+                                 Algorithm 1, Lighting) */
     HRC_PASS_GATHER_ADJ = 4,  /* adjoint of the gather */
     HRC_PASS_MERGE_DOWN_ADJ = 5,
     HRC_PASS_INTERVAL_ADJ = 6,

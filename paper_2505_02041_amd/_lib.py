@@ -28,10 +28,10 @@ HRC_FLAG_QUADRANTS_4 = 0x30
 HRC_FLAG_QUADRANTS_MASK = 0x30
 HRC_FLAG_BATCH_FULL = 0x100
 HRC_FLAG_BATCH_DENSE = 0x200
-PASS_NAMES = ["seed", "merge_up", "merge_down", "frame_sum", "gather_adj",
+PASS_NAMES = ["seed", "merge_up", "merge_down", "tail", "gather_adj",
               "merge_down_adj", "interval_adj", "seed_adj", "blur", "blur_adj"]
 # Kernel symbol of each pass kind (what a profiler shows).
-PASS_KERNELS = ["hrc_seed", "hrc_merge_up", "hrc_merge_down", "hrc_frame_sum",
+PASS_KERNELS = ["hrc_seed", "hrc_merge_up", "hrc_merge_down", "hrc_tail",
                 "hrc_gather_adj", "hrc_merge_down_adj", "hrc_interval_adj", "hrc_seed_adj",
                 "hrc_blur", "hrc_blur_adj"]
 

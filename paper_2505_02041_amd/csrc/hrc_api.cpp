@@ -20,7 +20,8 @@ Layout make_layout(int N, bool backward, int group) {
     L.group = backward ? kQuadrants : group;
     const size_t SS = L.S * L.S;
     size_t off = 256;  // first 256 bytes: scratch flag for HRC_FLAG_VALIDATE
-    for (int n = 0; n <= N; ++n) {
+    // the forward's tail folds T_0 and T_1 itself: only the reverse stores them
+    for (int n = backward ? 0 : kTracedLevels - 1; n <= N; ++n) {
         L.t_level[n] = off;
         off += align256(L.group * t_level_entries(N, n) * sizeof(float2));
     }
@@ -30,8 +31,8 @@ Layout make_layout(int N, bool backward, int group) {
         off += align256(L.group * SS * sizeof(float));
     }
     if (!backward) {
-        L.r0_all = off;
-        off += align256(kQuadrants * SS * sizeof(float));
+        L.aux = off;
+        off += align256(SS * sizeof(float));
     }
     if (backward) {
         for (int n = 0; n <= N; ++n) {
@@ -123,15 +124,30 @@ int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, cons
     };
     Phase p;
     // Algorithm 1 for `group` quadrants at a time; each group reuses the same
-    // pyramid buffers, and the last merge down of a group writes that group's
-    // R_0 (into the per-quadrant R_0 array, or R(0) when every level is kept).
+    // pyramid buffers.  The merge down runs to level 2 (forward: the tail
+    // builds levels 1 and 0 on chip) or, when every level is kept for the
+    // reverse, to level 1, the last one the reverse reads; then the tail adds
+    // the group's quadrants to F.  With the blur, the gather goes first to a
+    // buffer that is free by then: the forward's spare field, or (every level
+    // kept) dR_0, which the reverse writes only later.
     const int G = w.L.group;
-    int cur = -1;
+    float *gathered = b.blur ? (keep_all_r ? w.dR(0) : w.Aux()) : b.F;
     for (int q0 = 0; q0 < kQuadrants; q0 += G) {
         p = Phase();
         p.kind = PH_SEED;
-        p.a.seed = SeedArgs{b.eps, b.sig, w.T(0), w.T(1), w.T(2), t_level_entries(N, 0),
-                            t_level_entries(N, 1), t_level_entries(N, 2), N, q0, G, 32};
+        p.a.seed = SeedArgs{b.eps,
+                            b.sig,
+                            keep_all_r ? w.T(0) : nullptr,
+                            keep_all_r ? w.T(1) : nullptr,
+                            w.T(2),
+                            t_level_entries(N, 0),
+                            t_level_entries(N, 1),
+                            t_level_entries(N, 2),
+                            N,
+                            q0,
+                            G,
+                            32,
+                            keep_all_r ? 0 : kTracedLevels - 1};
         add(p);
         for (int n = kTracedLevels; n <= N; ++n) {
             p = Phase();
@@ -141,49 +157,36 @@ int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, cons
                             N, n, G};
             add(p);
         }
-        cur = -1;
-        // R_0 feeds only the gather: a gradient-only solve (no F) stops at R_1,
-        // the last level its reverse reads
-        const int n_last = b.F ? 0 : 1;
+        int cur = -1;
+        const int n_last = keep_all_r ? 1 : 2;
         for (int n = N - 1; n >= n_last; --n) {
-            float *dst;
-            int o = n;
-            if (keep_all_r) {
-                dst = w.R(n);
-            } else {
-                o = (cur == 0) ? 1 : 0;
-                dst = n == 0 ? w.R0all() + (size_t)q0 * w.L.S * w.L.S : w.R(o);
-            }
+            const int o = keep_all_r ? n : (cur == 0 ? 1 : 0);
             p = Phase();
             p.kind = PH_DOWN;
             p.U = pick_u(U, PH_DOWN);
-            p.a.down = DownArgs{(n + 1 < N) ? w.R(cur) : nullptr, w.T(n), w.T(n + 1), dst,
+            p.a.down = DownArgs{(n + 1 < N) ? w.R(cur) : nullptr, w.T(n), w.T(n + 1), w.R(o),
                                 t_level_entries(N, n), t_level_entries(N, n + 1), N, n, G,
                                 b.env, q0};
             add(p);
             cur = o;
         }
-    }
-    if (b.F) {
-        // with the blur, the gather goes to a buffer that is free by now: a
-        // ping-pong cascade level, or (every level kept) dR_0, which the
-        // reverse writes only later
-        float *gathered = b.blur ? (keep_all_r ? w.dR(0) : w.R(0)) : b.F;
-        p = Phase();
-        p.kind = PH_FRAME_SUM;
-        p.a.fs = FrameSumArgs{keep_all_r ? w.R(0) : w.R0all(), nullptr, gathered, nullptr, N, 1,
-                              b.env};
-        add(p);
-        if (b.blur) {
+        if (b.F) {
             p = Phase();
-            p.kind = PH_BLUR;
-            p.a.bl = BlurArgs{gathered, b.sig, b.F, N, kBlurThreshold};
+            p.kind = PH_TAIL;
+            p.a.tail = TailArgs{b.eps, b.sig, keep_all_r ? w.R(2) : w.R(cur), gathered,
+                                N, q0, G, q0 > 0 ? 1 : 0, b.env, 32};
             add(p);
         }
     }
+    if (b.F && b.blur) {
+        p = Phase();
+        p.kind = PH_BLUR;
+        p.a.bl = BlurArgs{gathered, b.sig, b.F, N, kBlurThreshold};
+        add(p);
+    }
     if (b.dF) {
-        // with the blur, its transpose first, into R_0's buffer (the reverse
-        // never reads R_0, and the gather above has consumed it)
+        // with the blur, its transpose first, into R_0's buffer (neither the
+        // kept forward nor the reverse uses R_0)
         const float *dgathered = b.dF;
         if (b.blur) {
             p = Phase();

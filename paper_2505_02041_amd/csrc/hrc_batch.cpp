@@ -38,8 +38,9 @@ struct Plan {
 // Elements per thread for a phase so that it splits into at most `target`
 // tiles (tiles of 256*U outputs); fixed-shape phases keep their own tiles.
 void size_tiles(Phase &p, int target) {
-    if (p.kind == PH_SEED) p.a.seed.tile = 16;  // the persistent kernel's seed tile
-    if (p.kind == PH_SEED || p.kind == PH_SEED_ADJ || p.kind == PH_FRAME_SUM ||
+    if (p.kind == PH_SEED) p.a.seed.tile = 16;  // the persistent kernel's tiles
+    if (p.kind == PH_TAIL) p.a.tail.tile = 16;
+    if (p.kind == PH_SEED || p.kind == PH_SEED_ADJ || p.kind == PH_TAIL ||
         p.kind == PH_GATHER_ADJ)
         return;
     p.U = 1;

@@ -37,7 +37,7 @@ struct Layout {
     size_t t_level[kMaxLog2 + 2] = {};   // T_n: `group` quadrants x t_level_entries float2
     size_t r_level[kMaxLog2 + 1] = {};   // R buffers: `group` quadrants x S^2 float each
     int r_count = 0;                     // 2 (forward ping-pong) or N (keeps every R_n)
-    size_t r0_all = 0;                   // forward: R_0 of all four quadrants
+    size_t aux = 0;                      // forward: one S^2 field (the gather before the blur)
     size_t dt_level[kMaxLog2 + 2] = {};  // backward: adjoint pyramid
     size_t dr_level[kMaxLog2 + 1] = {};  // backward: adjoint cascades
     size_t total = 0;
@@ -53,7 +53,7 @@ struct Ws {
     float2 *dT(int n) const { return reinterpret_cast<float2 *>(base + L.dt_level[n]); }
     float *R(int i) const { return reinterpret_cast<float *>(base + L.r_level[i]); }
     float *dR(int i) const { return reinterpret_cast<float *>(base + L.dr_level[i]); }
-    float *R0all() const { return reinterpret_cast<float *>(base + L.r0_all); }
+    float *Aux() const { return reinterpret_cast<float *>(base + L.aux); }
 };
 
 // ---- Arguments of each phase (one pass over one level of one scene) -------
@@ -66,6 +66,7 @@ struct SeedArgs {
     size_t e0, e1, e2;  // entries per quadrant of each level
     int N, q0, nq;
     int tile;           // image tile side: 32 standalone, 16 in the persistent kernel
+    int first;          // first level written: 0, or 2 when the tail folds T_0 and T_1 itself
 };
 struct UpArgs { const float2 *Tp; float2 *T; size_t ep, e; int N, n, nq; };
 // env (nullable): the environment's angular fluence per quadrant and cone,
@@ -80,11 +81,16 @@ struct DownArgs {
     const float *env;        // environment table (nullable)
     int q0;                  // absolute quadrant of the group's first solve
 };
-struct FrameSumArgs {
-    const float *src, *src2;
-    float *out, *out2;
-    int N, off;
-    const float *env;        // off = 1: the gather beyond the last column (nullable)
+// The tail of the forward: levels 1 and 0 of the merge down, the gather and
+// the sum over quadrants, from R_2 of the group's quadrants q0 .. q0+nq-1.
+struct TailArgs {
+    const float *eps, *sig;
+    const float *R2;         // R_2, nq quadrants of S^2 floats (quadrant q0 first)
+    float *out;              // F, [S][S]
+    int N, q0, nq;
+    int accumulate;          // add to out (the groups after the first) instead of storing
+    const float *env;        // environment table (nullable)
+    int tile;                // image tile side: 32 standalone, 16 in the persistent kernel
 };
 struct GatherAdjArgs { const float *dF; float *dR0; int N; };
 struct DownAdjArgs {
@@ -126,7 +132,7 @@ struct BlurArgs {
 };
 
 enum PhaseKind {
-    PH_SEED = 0, PH_UP, PH_DOWN, PH_FRAME_SUM, PH_GATHER_ADJ,
+    PH_SEED = 0, PH_UP, PH_DOWN, PH_TAIL, PH_GATHER_ADJ,
     PH_DOWN_ADJ, PH_DT, PH_SEED_ADJ, PH_BLUR, PH_BLUR_ADJ, PH_KIND_COUNT
 };
 
@@ -139,7 +145,7 @@ struct Phase {
         SeedArgs seed;
         UpArgs up;
         DownArgs down;
-        FrameSumArgs fs;
+        TailArgs tail;
         GatherAdjArgs ga;
         DownAdjArgs da;
         DTArgs dt;

@@ -115,7 +115,8 @@ __device__ __forceinline__ float r_lookup(const float *Rq, int N, int m, int c, 
 // ---------------------------------------------------------------------------
 
 // Traced levels T_0, T_1, T_2 (Algorithm 1, first loop), for all four
-// quadrants from one 32x32 image tile.
+// quadrants from one 32x32 image tile (T_2 alone when the forward's tail folds
+// the intervals of T_0 and T_1 itself).
 //
 // A chord of length 2a through a uniform pixel is the merge of two chords of
 // length a through it (Eq. 5-6), and every chord of the traced rays is either
@@ -226,8 +227,8 @@ __device__ void body_seed(const SeedArgs &a, unsigned tile, char *lds) {
     }
     __syncthreads();
     for (int g = 0; g < a.nq; ++g) {
-        seed_level_rays<TILE, 0>(iv, a, a.q0 + g, g, r0, c0);
-        seed_level_rays<TILE, 1>(iv, a, a.q0 + g, g, r0, c0);
+        if (a.first <= 0) seed_level_rays<TILE, 0>(iv, a, a.q0 + g, g, r0, c0);
+        if (a.first <= 1) seed_level_rays<TILE, 1>(iv, a, a.q0 + g, g, r0, c0);
         seed_level_rays<TILE, 2>(iv, a, a.q0 + g, g, r0, c0);
     }
     __syncthreads();
@@ -357,73 +358,178 @@ __device__ void body_merge_down(const DownArgs &a, unsigned tile, int U) {
     }
 }
 
-// out[r][c] = sum over q of src_q[u + off][w], (u, w) the frame coordinates of
-// image pixel (r, c) in quadrant q; rows u + off >= S read as 0 (or, with an
-// environment, its fluence over the quadrant's level-0 cone).  off = 1 is the
-// gather of Algorithm 1 (R_0 at the probe one pixel ahead); off = 0 sums
-// per-quadrant frame fields back onto the image.  Two fields at once when
-// src2 is set.  32x32 tiles through LDS keep the +-x (transposed) reads
-// coalesced.
-constexpr int kFrameSumLds = 2 * 32 * 33 * 4;
+// Tail of the forward, per TILE x TILE image tile and every quadrant of the
+// group: the merge down of levels 1 and 0 (Eq. 14-17), the gather of
+// Algorithm 1 (R_0 at the probe one pixel ahead, cone 0) and the sum of the
+// quadrants' gathers on the image.  For each quadrant, R_1 over the level-1
+// columns and rows the tile's level-0 values read is built from R_2 into LDS,
+// then R_0 one column ahead of every pixel from it.  The intervals these two
+// levels read (both directions of T_0, all of T_1, the even directions of T_2)
+// are folded here from the tile's pixel intervals, as the traced levels are
+// built, instead of being stored and read back: they hold only axis and
+// diagonal half pieces.  Quadrants are summed in order 0..3, and a later group
+// adds to the sum the earlier groups stored.
+template <int TILE> struct TailTile {
+    // T_2 rays run 4 pixels ahead of level-1 probes up to 2 columns past the
+    // tile and +-4 rows around rows up to 2 beyond it
+    static constexpr int halo = 6;
+    static constexpr int span = TILE + 2 * halo;
+    static constexpr int pitch = span + 1;
+    static constexpr int plane = span * pitch;
+    static constexpr int r1cols = TILE / 2 + 1;  // level-1 columns u_lo/2 + 1 .. u_lo/2 + TILE/2 + 1
+    static constexpr int r1rows = TILE + 4;      // rows w_lo - 2 .. w_lo + TILE + 1
+    static constexpr int acc_pitch = TILE + 1;
+    static constexpr int iv_bytes = 2 * plane * 8;
+    static constexpr int r1_bytes = r1cols * 2 * r1rows * 4;
+    static constexpr int lds = iv_bytes + r1_bytes + TILE * acc_pitch * 4;
+};
 
-__device__ void body_frame_sum(const FrameSumArgs &a, unsigned tile, char *lds) {
-    float (*fs_tile)[32][33] = reinterpret_cast<float (*)[32][33]>(lds);
+// Fold of the half pieces of traced ray `sid` (stencil ids as in the traced
+// levels) from the probe's pixel interval at ivp; su / sw step one pixel in u
+// / w, and the two planes hold the axis and the diagonal half pieces.
+template <int sid, int pieces, int plane>
+__device__ __forceinline__ float2 tail_ray(const float2 *ivp, int su, int sw) {
+    float2 acc = make_float2(0.f, 1.f);
+#pragma unroll
+    for (int j = 0; j < pieces; ++j)
+        acc = merge(acc, ivp[kHpLen[sid][j] * plane + kHpDu[sid][j] * su + kHpDw[sid][j] * sw]);
+    return acc;
+}
+
+template <int TILE>
+__device__ void body_tail(const TailArgs &a, unsigned tile, char *lds) {
+    using G = TailTile<TILE>;
+    constexpr int H = G::halo, P = G::pitch, RR = G::r1rows, AP = G::acc_pitch;
+    float2 *iv = reinterpret_cast<float2 *>(lds);
+    float *r1 = reinterpret_cast<float *>(lds + G::iv_bytes);
+    float *acc = reinterpret_cast<float *>(lds + G::iv_bytes + G::r1_bytes);
     const int N = a.N, S = 1 << N;
     const size_t SS = (size_t)S * S;
-    const int tiles = (S + 31) >> 5;
-    const int tr = tile / tiles, tc = tile % tiles;
-    const int tx = ltid() & 31, ty = ltid() >> 5;
-    const bool two = a.src2 != nullptr;
-    float acc0[4] = {0.f, 0.f, 0.f, 0.f}, acc1[4] = {0.f, 0.f, 0.f, 0.f};
-    // +-y quadrants: u = r or S-1-r, w = c: rows read directly.
-    for (int q = 2; q < 4; ++q) {
-        for (int i = 0; i < 4; ++i) {
-            int r = tr * 32 + ty + 8 * i, c = tc * 32 + tx;
-            if (r < S && c < S) {
-                int us = frame_row(q, r, S) + a.off;
-                if (us < S) {
-                    acc0[i] += a.src[q * SS + (size_t)us * S + c];
-                    if (two) acc1[i] += a.src2[q * SS + (size_t)us * S + c];
-                } else if (a.env) {
-                    acc0[i] += a.env[(size_t)q * kConeTable];  // beyond the grid: level 0, cone 0
-                }
-            }
+    const int tiles = (S + TILE - 1) / TILE;
+    const int r0 = (int)(tile / tiles) * TILE, c0 = (int)(tile % tiles) * TILE;
+    for (int i = ltid(); i < G::span * G::span; i += 256) {
+        const int lr = i / G::span, lc = i % G::span;
+        const int r = r0 - H + lr, c = c0 - H + lc;
+        float e = 0.f, g = 0.f;
+        if (r >= 0 && r < S && c >= 0 && c < S) {
+            e = a.eps[(size_t)r * S + c];
+            g = a.sig[(size_t)r * S + c];
         }
+        iv[lr * P + lc] = cell_interval(e, g, 0.5f);
+        iv[G::plane + lr * P + lc] = cell_interval(e, g, kH2);
     }
-    // +-x quadrants: u = c or S-1-c, w = r: read rows u, transpose through LDS.
-    for (int q = 0; q < 2; ++q) {
-        __syncthreads();
-        for (int i = 0; i < 4; ++i) {
-            int cl = ty + 8 * i;
-            int c = tc * 32 + cl, r = tr * 32 + tx;
+    for (int i = ltid(); i < TILE * TILE; i += 256) {
+        const int rl = i / TILE, cl = i % TILE;
+        const int r = r0 + rl, c = c0 + cl;
+        acc[rl * AP + cl] = (a.accumulate && r < S && c < S) ? a.out[(size_t)r * S + c] : 0.f;
+    }
+    for (int g = 0; g < a.nq; ++g) {
+        const int q = a.q0 + g;
+        const float *R2 = a.R2 + g * SS;
+        const float *envq = a.env ? a.env + (size_t)q * kConeTable : nullptr;
+        // frame of quadrant q: +x (u, w) = (c, r); -x (S-1-c, r); +y (r, c); -y (S-1-r, c);
+        // the tile covers u_lo .. u_lo + TILE - 1, w_lo .. w_lo + TILE - 1, and
+        // frame pixel (u, w) sits at LDS index base + (u - u_lo) su + (w - w_lo) sw
+        const int u_lo = q == 0 ? c0 : q == 1 ? S - TILE - c0 : q == 2 ? r0 : S - TILE - r0;
+        const int w_lo = q < 2 ? r0 : c0;
+        const int su = q == 0 ? 1 : q == 1 ? -1 : q == 2 ? P : -P;
+        const int sw = q < 2 ? P : 1;
+        const int base = q == 1 ? H * P + TILE - 1 + H : q == 3 ? (TILE - 1 + H) * P + H : H * P + H;
+        const int c1_lo = u_lo / 2 + 1;  // u_lo is even, so the first level-1 column is odd
+        __syncthreads();  // intervals and sums in place; the previous quadrant's R_1 consumed
+        // R_1 at odd level-1 columns (Eq. 14 at level 1, through T_1)
+        for (int i = ltid(); i < (TILE / 4 + 1) * RR; i += 256) {
+            const int j = 2 * (i / RR), wl = i % RR;
+            const int cp = c1_lo + j, w = w_lo - 2 + wl;
             float v0 = 0.f, v1 = 0.f;
-            if (r < S && c < S) {
-                int us = frame_row(q, c, S) + a.off;
-                if (us < S) {
-                    v0 = a.src[q * SS + (size_t)us * S + r];
-                    if (two) v1 = a.src2[q * SS + (size_t)us * S + r];
-                } else if (a.env) {
-                    v0 = a.env[(size_t)q * kConeTable];
-                }
+            if (cp >= (S >> 1) || w < 0 || w >= S) {
+                v0 = env_fluence(envq, 1, 0);
+                v1 = env_fluence(envq, 1, 1);
+            } else if (cp >= 0) {
+                const float2 *ivp = iv + base + (2 * cp - u_lo) * su + (w - w_lo) * sw;
+                const float2 t0 = tail_ray<2, 4, G::plane>(ivp, su, sw);
+                const float2 t1 = tail_ray<3, 4, G::plane>(ivp, su, sw);
+                const float2 t2 = tail_ray<4, 4, G::plane>(ivp, su, sw);
+                const int c = (cp + 1) >> 1;
+                v0 += fmaf(t0.y, r_lookup(R2, N, 2, c, 0, w - 2, envq), c_cone[3] * t0.x);
+                v0 += fmaf(t1.y, r_lookup(R2, N, 2, c, 1, w, envq), c_cone[4] * t1.x);
+                v1 += fmaf(t1.y, r_lookup(R2, N, 2, c, 2, w, envq), c_cone[5] * t1.x);
+                v1 += fmaf(t2.y, r_lookup(R2, N, 2, c, 3, w + 2, envq), c_cone[6] * t2.x);
             }
-            fs_tile[0][cl][tx] = v0;
-            fs_tile[1][cl][tx] = v1;
+            r1[(2 * j) * RR + wl] = v0;
+            r1[(2 * j + 1) * RR + wl] = v1;
+        }
+        // R_1 at even level-1 columns (Eq. 15-17 at level 1, through the even directions of T_2)
+        for (int i = ltid(); i < (TILE / 4) * RR; i += 256) {
+            const int j = 2 * (i / RR) + 1, wl = i % RR;
+            const int cp = c1_lo + j, w = w_lo - 2 + wl;
+            float v0 = 0.f, v1 = 0.f;
+            if (cp >= (S >> 1) || w < 0 || w >= S) {
+                v0 = env_fluence(envq, 1, 0);
+                v1 = env_fluence(envq, 1, 1);
+            } else if (cp >= 0) {
+                const float2 *ivp = iv + base + (2 * cp - u_lo) * su + (w - w_lo) * sw;
+                const float2 t0 = tail_ray<5, 8, G::plane>(ivp, su, sw);
+                const float2 t2 = tail_ray<7, 8, G::plane>(ivp, su, sw);
+                const float2 t4 = tail_ray<9, 8, G::plane>(ivp, su, sw);
+                const int c = cp >> 1;
+                v0 += 0.5f * (r_lookup(R2, N, 2, c, 0, w, envq) +
+                              fmaf(t0.y, r_lookup(R2, N, 2, c + 1, 0, w - 4, envq), c_cone[3] * t0.x));
+                v0 += 0.5f * (r_lookup(R2, N, 2, c, 1, w, envq) +
+                              fmaf(t2.y, r_lookup(R2, N, 2, c + 1, 1, w, envq), c_cone[4] * t2.x));
+                v1 += 0.5f * (r_lookup(R2, N, 2, c, 2, w, envq) +
+                              fmaf(t2.y, r_lookup(R2, N, 2, c + 1, 2, w, envq), c_cone[5] * t2.x));
+                v1 += 0.5f * (r_lookup(R2, N, 2, c, 3, w, envq) +
+                              fmaf(t4.y, r_lookup(R2, N, 2, c + 1, 3, w + 4, envq), c_cone[6] * t4.x));
+            }
+            r1[(2 * j) * RR + wl] = v0;
+            r1[(2 * j + 1) * RR + wl] = v1;
         }
         __syncthreads();
-        for (int i = 0; i < 4; ++i) {
-            int rl = ty + 8 * i;
-            acc0[i] += fs_tile[0][tx][rl];
-            acc1[i] += fs_tile[1][tx][rl];
+        // R_0 at x = u + 1 for every pixel (u, w) of the tile, added to the sum.
+        // Column slots are ordered even u first, so that each wave holds one
+        // parity of x (64 / TILE slots per wave).
+        for (int i = ltid(); i < TILE * TILE; i += 256) {
+            const int slot = i / TILE, wl = i % TILE;
+            const int ul = slot < TILE / 2 ? 2 * slot : 2 * (slot - TILE / 2) + 1;
+            const int u = u_lo + ul, w = w_lo + wl;
+            if (u < 0 || u >= S || w >= S) continue;
+            const int x = u + 1;
+            float v = 0.f;
+            if (x >= S) {
+                v = env_fluence(envq, 0, 0);  // beyond the grid
+            } else if (x & 1) {
+                // Eq. 14 at level 0: both directions of T_0, R_1 at the next level-1 probe
+                const float2 *ivp = iv + base + (x - u_lo) * su + wl * sw;
+                const float2 t0 = tail_ray<0, 2, G::plane>(ivp, su, sw);
+                const float2 t1 = tail_ray<1, 2, G::plane>(ivp, su, sw);
+                const int j = ((x + 1) >> 1) - c1_lo;
+                v += fmaf(t0.y, r1[(2 * j) * RR + wl + 1], c_cone[1] * t0.x);
+                v += fmaf(t1.y, r1[(2 * j + 1) * RR + wl + 3], c_cone[2] * t1.x);
+            } else {
+                // Eq. 15-17 at level 0: the co-located level-1 probe and the
+                // doubled edges (directions 0 and 2 of T_1)
+                const float2 *ivp = iv + base + (x - u_lo) * su + wl * sw;
+                const float2 t0 = tail_ray<2, 4, G::plane>(ivp, su, sw);
+                const float2 t2 = tail_ray<4, 4, G::plane>(ivp, su, sw);
+                const int j = (x >> 1) - c1_lo;
+                v += 0.5f * (r1[(2 * j) * RR + wl + 2] +
+                             fmaf(t0.y, r1[(2 * j + 2) * RR + wl], c_cone[1] * t0.x));
+                v += 0.5f * (r1[(2 * j + 1) * RR + wl + 2] +
+                             fmaf(t2.y, r1[(2 * j + 3) * RR + wl + 4], c_cone[2] * t2.x));
+            }
+            const int r = q == 0 || q == 1 ? w : q == 2 ? u : S - 1 - u;
+            const int c = q == 0 ? u : q == 1 ? S - 1 - u : w;
+            acc[(r - r0) * AP + (c - c0)] += v;
         }
     }
     __syncthreads();
-    for (int i = 0; i < 4; ++i) {
-        int r = tr * 32 + ty + 8 * i, c = tc * 32 + tx;
-        if (r < S && c < S) {
-            a.out[(size_t)r * S + c] = acc0[i];
-            if (two) a.out2[(size_t)r * S + c] = acc1[i];
-        }
+    for (int i = ltid(); i < TILE * TILE; i += 256) {
+        const int rl = i / TILE, cl = i % TILE;
+        const int r = r0 + rl, c = c0 + cl;
+        if (r < S && c < S) a.out[(size_t)r * S + c] = acc[rl * AP + cl];
     }
+    __syncthreads();
 }
 
 // Transpose of the gather: dR_0[q][x][y] = dF at the image pixel of frame
@@ -1007,15 +1113,16 @@ __device__ void body_blur_adj(const BlurArgs &a, unsigned tile) {
 }
 
 // The persistent kernel's one LDS buffer: the largest body it runs (the traced
-// levels run there on 16x16 tiles).
-constexpr int kMaxLds = kSeedAdjLds > SeedTile<16>::lds ? kSeedAdjLds : SeedTile<16>::lds;
+// levels and the tail run there on 16x16 tiles).
+constexpr int kMaxLds2 = kSeedAdjLds > SeedTile<16>::lds ? kSeedAdjLds : SeedTile<16>::lds;
+constexpr int kMaxLds = kMaxLds2 > TailTile<16>::lds ? kMaxLds2 : TailTile<16>::lds;
 
 __device__ __forceinline__ void run_phase(const Phase &p, unsigned tile, char *lds) {
     switch (p.kind) {
         case PH_SEED: body_seed<16>(p.a.seed, tile, lds); break;  // planner sets tile 16
         case PH_UP: body_merge_up(p.a.up, tile, p.U); break;
         case PH_DOWN: body_merge_down(p.a.down, tile, p.U); break;
-        case PH_FRAME_SUM: body_frame_sum(p.a.fs, tile, lds); break;
+        case PH_TAIL: body_tail<16>(p.a.tail, tile, lds); break;  // planner sets tile 16
         case PH_GATHER_ADJ: body_gather_adj(p.a.ga, tile, lds); break;
         case PH_DOWN_ADJ: body_merge_down_adj(p.a.da, tile, p.U); break;
         case PH_DT: body_dT(p.a.dt, tile, p.U); break;
@@ -1053,9 +1160,9 @@ __global__ __launch_bounds__(256) void hrc_blur(Phase p) { body_blur(p.a.bl, blo
 __global__ __launch_bounds__(256) void hrc_blur_adj(Phase p) {
     body_blur_adj(p.a.bl, blockIdx.x);
 }
-__global__ __launch_bounds__(256) void hrc_frame_sum(Phase p) {
-    __shared__ __align__(16) char lds[kFrameSumLds];
-    body_frame_sum(p.a.fs, blockIdx.x, lds);
+__global__ __launch_bounds__(256) void hrc_tail(Phase p) {
+    __shared__ __align__(16) char lds[TailTile<32>::lds];
+    body_tail<32>(p.a.tail, blockIdx.x, lds);
 }
 __global__ __launch_bounds__(256) void hrc_gather_adj(Phase p) {
     __shared__ __align__(16) char lds[kGatherAdjLds];
@@ -1210,7 +1317,7 @@ unsigned phase_tiles(const Phase &p) {
             case PH_SEED: return p.a.seed.N;
             case PH_UP: return p.a.up.N;
             case PH_DOWN: return p.a.down.N;
-            case PH_FRAME_SUM: return p.a.fs.N;
+            case PH_TAIL: return p.a.tail.N;
             case PH_GATHER_ADJ: return p.a.ga.N;
             case PH_DOWN_ADJ: return p.a.da.N;
             case PH_DT: return p.a.dt.N;
@@ -1224,7 +1331,10 @@ unsigned phase_tiles(const Phase &p) {
     const unsigned t32 = (unsigned)((S + 31) / 32);
     const size_t per = (size_t)256 * (p.U > 0 ? p.U : 1);
     switch (p.kind) {
-        case PH_FRAME_SUM: return t32 * t32;
+        case PH_TAIL: {
+            const unsigned t = (unsigned)((S + p.a.tail.tile - 1) / p.a.tail.tile);
+            return t * t;
+        }
         case PH_GATHER_ADJ: return 4 * t32 * t32;
         case PH_SEED: {
             const unsigned t = (unsigned)((S + p.a.seed.tile - 1) / p.a.seed.tile);
@@ -1261,7 +1371,7 @@ hipError_t launch_phase(const Phase &p, hipStream_t s, hipEvent_t start, hipEven
         case PH_SEED: k = hrc_seed; break;
         case PH_UP: k = hrc_merge_up; break;
         case PH_DOWN: k = hrc_merge_down; break;
-        case PH_FRAME_SUM: k = hrc_frame_sum; break;
+        case PH_TAIL: k = hrc_tail; break;
         case PH_GATHER_ADJ: k = hrc_gather_adj; break;
         case PH_DOWN_ADJ: k = hrc_merge_down_adj; break;
         case PH_DT: k = hrc_interval_adj; break;

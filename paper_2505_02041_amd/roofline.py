@@ -19,12 +19,16 @@ def _t(S: int, n: int) -> float:
     return S * S * (1.0 + 2.0 ** -n)
 
 
-def pass_bytes(name: str, N: int, n: int = -1, two_fields: bool = False) -> float:
+def pass_bytes(name: str, N: int, n: int = -1) -> float:
     S = 1 << N
     SS = float(S * S)
     q = 4
     if name == "seed":
-        # the two fields read once for all four quadrants, T_0..T_2 written
+        # the two fields read once for all four quadrants, T_2 written (the
+        # forward's tail folds T_0 and T_1 itself)
+        return 8 * SS + q * 8 * _t(S, 2)
+    if name == "seed_all":
+        # the reverse's recomputed forward: T_0..T_2 written
         return 8 * SS + q * 8 * (_t(S, 0) + _t(S, 1) + _t(S, 2))
     if name == "merge_up":
         # the top level n = N builds only its even directions (all the merge
@@ -35,9 +39,9 @@ def pass_bytes(name: str, N: int, n: int = -1, two_fields: bool = False) -> floa
         # half of T_n (odd columns) and the even directions of T_{n+1}: together
         # X^2 (1 + 2^-n) intervals; R_{n+1} read unless n + 1 = N; R_n written
         return q * 8 * _t(S, n) + (q * 4 * SS if n + 1 < N else 0.0) + q * 4 * SS
-    if name == "frame_sum":
-        f = 2 if two_fields else 1
-        return f * (q * 4 * SS + 4 * SS)
+    if name == "tail":
+        # the two fields once, R_2 of the four quadrants, F written
+        return 8 * SS + q * 4 * SS + 4 * SS
     if name == "gather_adj":
         return q * 4 * SS + q * 4 * SS
     if name == "merge_down_adj":
@@ -63,8 +67,8 @@ def forward_passes(N: int):
     """(name, level) of every pass of one forward solve, in order."""
     out = [("seed", -1)]
     out += [("merge_up", n) for n in range(3, N + 1)]
-    out += [("merge_down", n) for n in range(N - 1, -1, -1)]
-    out += [("frame_sum", -1)]
+    out += [("merge_down", n) for n in range(N - 1, 1, -1)]
+    out += [("tail", -1)]
     return out
 
 
@@ -73,9 +77,11 @@ def forward_bytes(N: int) -> float:
 
 
 def backward_bytes(N: int) -> float:
-    """hrc_backward: the forward recomputed (without R_0 and the gather) plus the
-    reverse."""
-    b = forward_bytes(N) - pass_bytes("frame_sum", N) - pass_bytes("merge_down", N, 0)
+    """hrc_backward: the forward recomputed down to R_1 (every traced level
+    stored, no gather) plus the reverse."""
+    b = pass_bytes("seed_all", N)
+    b += sum(pass_bytes("merge_up", N, n) for n in range(3, N + 1))
+    b += sum(pass_bytes("merge_down", N, n) for n in range(N - 1, 0, -1))
     b += pass_bytes("gather_adj", N)
     b += sum(pass_bytes("merge_down_adj", N, n) for n in range(N - 1))
     b += sum(pass_bytes("interval_adj", N, n) for n in range(N, -1, -1))

@@ -20,7 +20,7 @@ def ctx():
 
 def _forward_order(N):
     return ([("seed", -1)] + [("merge_up", n) for n in range(3, N + 1)] +
-            [("merge_down", n) for n in range(N - 1, -1, -1)] + [("frame_sum", -1)])
+            [("merge_down", n) for n in range(N - 1, 1, -1)] + [("tail", -1)])
 
 
 @pytest.mark.parametrize("S", [8, 128, 512])
@@ -44,8 +44,8 @@ def test_profile_backward(ctx, S):
     g = to_dev(np.random.default_rng(5).normal(size=(S, S)))
     passes, (ge, gs) = ctx.hrc_profile_solve(e, s, g, return_outputs=True)
     names = [p for p, _, _ in passes]
-    # the recomputed forward (without R_0 and the gather), then the reverse
-    fwd = [(p, n) for p, n in _forward_order(N)][:-2]
+    # the recomputed forward (down to R_1, no gather), then the reverse
+    fwd = _forward_order(N)[:-1] + [("merge_down", 1)]
     assert [(p, n) for p, n, _ in passes[:len(fwd)]] == fwd
     rev = names[len(fwd):]
     assert rev[0] == "gather_adj" and rev[-1] == "seed_adj"
