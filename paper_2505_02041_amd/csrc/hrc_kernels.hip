@@ -72,13 +72,27 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb) {
 
 // <L, T> of a chord of length ell through a uniform pixel (Eq. 2-4):
 // T = exp(-tau), L = eps*ell*(1 - exp(-tau))/tau, tau = sig*ell.
+//
+// exp(-tau) is the hardware base-2 exponential of -tau*log2(e): its relative
+// error grows as tau * 2^-24, about 2e-6 at tau = 25, where T is 1e-11.
+// phi(tau) = (1 - exp(-tau)) / tau is its Taylor polynomial through tau^5
+// below 1/8 (truncation under 1e-9, where the difference would cancel) and
+// the difference times the hardware reciprocal above.
+__device__ __forceinline__ float exp_neg(float tau) {
+    return __builtin_amdgcn_exp2f(tau * -1.44269504088896341f);
+}
+
 __device__ __forceinline__ float cell_phi(float tau) {
-    return tau < 1e-3f ? 1.0f - tau * (0.5f - tau * (1.0f / 6.0f)) : -expm1f(-tau) / tau;
+    const float p =
+        1.0f - tau * (0.5f - tau * (1.0f / 6.0f - tau * (1.0f / 24.0f -
+                                                         tau * (1.0f / 120.0f - tau * (1.0f / 720.0f)))));
+    const float d = (1.0f - exp_neg(tau)) * __builtin_amdgcn_rcpf(tau);
+    return tau < 0.125f ? p : d;
 }
 
 __device__ __forceinline__ float2 cell_interval(float e, float s, float ell) {
     float tau = s * ell;
-    return make_float2(e * ell * cell_phi(tau), expf(-tau));
+    return make_float2(e * ell * cell_phi(tau), exp_neg(tau));
 }
 
 // Eq. 7: near interval first.
@@ -396,37 +410,56 @@ __device__ __forceinline__ float2 tail_ray(const float2 *ivp, int su, int sw) {
     return acc;
 }
 
+// R_2 of one quadrant at the column whose row block starts at `ro` (clamped
+// into the grid by the caller), cone jj, row y: the stored value when the
+// column (cin) and the row lie in the grid, else `fill`.  The load is always
+// in bounds, so the lookup needs no branch.
+__device__ __forceinline__ float r2_at(const float *R2, int ro, int jj, int y, int S, bool cin,
+                                       float fill) {
+    const bool in = cin && (unsigned)y < (unsigned)S;
+    const float v = R2[in ? ro + jj * S + y : 0];
+    return in ? v : fill;
+}
+
 template <int TILE>
 __device__ void body_tail(const TailArgs &a, unsigned tile, char *lds) {
     using G = TailTile<TILE>;
     constexpr int H = G::halo, P = G::pitch, RR = G::r1rows, AP = G::acc_pitch;
+    constexpr int span2 = G::span * G::span;
     float2 *iv = reinterpret_cast<float2 *>(lds);
     float *r1 = reinterpret_cast<float *>(lds + G::iv_bytes);
     float *acc = reinterpret_cast<float *>(lds + G::iv_bytes + G::r1_bytes);
     const int N = a.N, S = 1 << N;
-    const size_t SS = (size_t)S * S;
     const int tiles = (S + TILE - 1) / TILE;
     const int r0 = (int)(tile / tiles) * TILE, c0 = (int)(tile % tiles) * TILE;
-    for (int i = ltid(); i < G::span * G::span; i += 256) {
-        const int lr = i / G::span, lc = i % G::span;
-        const int r = r0 - H + lr, c = c0 - H + lc;
-        float e = 0.f, g = 0.f;
-        if (r >= 0 && r < S && c >= 0 && c < S) {
-            e = a.eps[(size_t)r * S + c];
-            g = a.sig[(size_t)r * S + c];
+#pragma unroll
+    for (int it = 0; it < (span2 + 255) / 256; ++it) {
+        const int i = ltid() + 256 * it;
+        if (i < span2) {
+            const int lr = i / G::span, lc = i % G::span;
+            const int r = r0 - H + lr, c = c0 - H + lc;
+            const bool in = (unsigned)r < (unsigned)S && (unsigned)c < (unsigned)S;
+            const int off = in ? r * S + c : 0;
+            const float e = a.eps[off], g = a.sig[off];
+            iv[lr * P + lc] = cell_interval(in ? e : 0.f, in ? g : 0.f, 0.5f);
+            iv[G::plane + lr * P + lc] = cell_interval(in ? e : 0.f, in ? g : 0.f, kH2);
         }
-        iv[lr * P + lc] = cell_interval(e, g, 0.5f);
-        iv[G::plane + lr * P + lc] = cell_interval(e, g, kH2);
     }
-    for (int i = ltid(); i < TILE * TILE; i += 256) {
+#pragma unroll
+    for (int it = 0; it < TILE * TILE / 256; ++it) {
+        const int i = ltid() + 256 * it;
         const int rl = i / TILE, cl = i % TILE;
         const int r = r0 + rl, c = c0 + cl;
-        acc[rl * AP + cl] = (a.accumulate && r < S && c < S) ? a.out[(size_t)r * S + c] : 0.f;
+        acc[rl * AP + cl] = (a.accumulate && r < S && c < S) ? a.out[r * S + c] : 0.f;
     }
     for (int g = 0; g < a.nq; ++g) {
         const int q = a.q0 + g;
-        const float *R2 = a.R2 + g * SS;
+        const float *R2 = a.R2 + (size_t)g * S * S;
         const float *envq = a.env ? a.env + (size_t)q * kConeTable : nullptr;
+        // angular fluences beyond the grid (uniform over the tile)
+        const float e10 = env_fluence(envq, 1, 0), e11 = env_fluence(envq, 1, 1);
+        const float e20 = env_fluence(envq, 2, 0), e21 = env_fluence(envq, 2, 1);
+        const float e22 = env_fluence(envq, 2, 2), e23 = env_fluence(envq, 2, 3);
         // frame of quadrant q: +x (u, w) = (c, r); -x (S-1-c, r); +y (r, c); -y (S-1-r, c);
         // the tile covers u_lo .. u_lo + TILE - 1, w_lo .. w_lo + TILE - 1, and
         // frame pixel (u, w) sits at LDS index base + (u - u_lo) su + (w - w_lo) sw
@@ -436,51 +469,66 @@ __device__ void body_tail(const TailArgs &a, unsigned tile, char *lds) {
         const int sw = q < 2 ? P : 1;
         const int base = q == 1 ? H * P + TILE - 1 + H : q == 3 ? (TILE - 1 + H) * P + H : H * P + H;
         const int c1_lo = u_lo / 2 + 1;  // u_lo is even, so the first level-1 column is odd
+        const int cmax = S >> 2;          // level-2 columns in the grid
         __syncthreads();  // intervals and sums in place; the previous quadrant's R_1 consumed
         // R_1 at odd level-1 columns (Eq. 14 at level 1, through T_1)
-        for (int i = ltid(); i < (TILE / 4 + 1) * RR; i += 256) {
+        constexpr int n_odd = (TILE / 4 + 1) * RR;
+#pragma unroll
+        for (int it = 0; it < (n_odd + 255) / 256; ++it) {
+            const int i = ltid() + 256 * it;
+            if (i >= n_odd) break;
             const int j = 2 * (i / RR), wl = i % RR;
             const int cp = c1_lo + j, w = w_lo - 2 + wl;
-            float v0 = 0.f, v1 = 0.f;
-            if (cp >= (S >> 1) || w < 0 || w >= S) {
-                v0 = env_fluence(envq, 1, 0);
-                v1 = env_fluence(envq, 1, 1);
-            } else if (cp >= 0) {
+            float v0 = e10, v1 = e11;
+            if (cp < 0) {
+                v0 = v1 = 0.f;
+            } else if (cp < (S >> 1) && (unsigned)w < (unsigned)S) {
                 const float2 *ivp = iv + base + (2 * cp - u_lo) * su + (w - w_lo) * sw;
                 const float2 t0 = tail_ray<2, 4, G::plane>(ivp, su, sw);
                 const float2 t1 = tail_ray<3, 4, G::plane>(ivp, su, sw);
                 const float2 t2 = tail_ray<4, 4, G::plane>(ivp, su, sw);
                 const int c = (cp + 1) >> 1;
-                v0 += fmaf(t0.y, r_lookup(R2, N, 2, c, 0, w - 2, envq), c_cone[3] * t0.x);
-                v0 += fmaf(t1.y, r_lookup(R2, N, 2, c, 1, w, envq), c_cone[4] * t1.x);
-                v1 += fmaf(t1.y, r_lookup(R2, N, 2, c, 2, w, envq), c_cone[5] * t1.x);
-                v1 += fmaf(t2.y, r_lookup(R2, N, 2, c, 3, w + 2, envq), c_cone[6] * t2.x);
+                const bool cin = c < cmax;
+                const int ro = (cin ? c : 0) * 4 * S;
+                v0 = 0.f;
+                v1 = 0.f;
+                v0 += fmaf(t0.y, r2_at(R2, ro, 0, w - 2, S, cin, e20), c_cone[3] * t0.x);
+                v0 += fmaf(t1.y, r2_at(R2, ro, 1, w, S, cin, e21), c_cone[4] * t1.x);
+                v1 += fmaf(t1.y, r2_at(R2, ro, 2, w, S, cin, e22), c_cone[5] * t1.x);
+                v1 += fmaf(t2.y, r2_at(R2, ro, 3, w + 2, S, cin, e23), c_cone[6] * t2.x);
             }
             r1[(2 * j) * RR + wl] = v0;
             r1[(2 * j + 1) * RR + wl] = v1;
         }
         // R_1 at even level-1 columns (Eq. 15-17 at level 1, through the even directions of T_2)
-        for (int i = ltid(); i < (TILE / 4) * RR; i += 256) {
+        constexpr int n_even = (TILE / 4) * RR;
+#pragma unroll
+        for (int it = 0; it < (n_even + 255) / 256; ++it) {
+            const int i = ltid() + 256 * it;
+            if (i >= n_even) break;
             const int j = 2 * (i / RR) + 1, wl = i % RR;
             const int cp = c1_lo + j, w = w_lo - 2 + wl;
-            float v0 = 0.f, v1 = 0.f;
-            if (cp >= (S >> 1) || w < 0 || w >= S) {
-                v0 = env_fluence(envq, 1, 0);
-                v1 = env_fluence(envq, 1, 1);
-            } else if (cp >= 0) {
+            float v0 = e10, v1 = e11;
+            if (cp < 0) {
+                v0 = v1 = 0.f;
+            } else if (cp < (S >> 1) && (unsigned)w < (unsigned)S) {
                 const float2 *ivp = iv + base + (2 * cp - u_lo) * su + (w - w_lo) * sw;
                 const float2 t0 = tail_ray<5, 8, G::plane>(ivp, su, sw);
                 const float2 t2 = tail_ray<7, 8, G::plane>(ivp, su, sw);
                 const float2 t4 = tail_ray<9, 8, G::plane>(ivp, su, sw);
-                const int c = cp >> 1;
-                v0 += 0.5f * (r_lookup(R2, N, 2, c, 0, w, envq) +
-                              fmaf(t0.y, r_lookup(R2, N, 2, c + 1, 0, w - 4, envq), c_cone[3] * t0.x));
-                v0 += 0.5f * (r_lookup(R2, N, 2, c, 1, w, envq) +
-                              fmaf(t2.y, r_lookup(R2, N, 2, c + 1, 1, w, envq), c_cone[4] * t2.x));
-                v1 += 0.5f * (r_lookup(R2, N, 2, c, 2, w, envq) +
-                              fmaf(t2.y, r_lookup(R2, N, 2, c + 1, 2, w, envq), c_cone[5] * t2.x));
-                v1 += 0.5f * (r_lookup(R2, N, 2, c, 3, w, envq) +
-                              fmaf(t4.y, r_lookup(R2, N, 2, c + 1, 3, w + 4, envq), c_cone[6] * t4.x));
+                const int c = cp >> 1;  // < cmax: cp < S / 2
+                const bool cin = c + 1 < cmax;
+                const int ro = c * 4 * S, ro1 = (cin ? c + 1 : 0) * 4 * S;
+                v0 = 0.f;
+                v1 = 0.f;
+                v0 += 0.5f * (r2_at(R2, ro, 0, w, S, true, e20) +
+                              fmaf(t0.y, r2_at(R2, ro1, 0, w - 4, S, cin, e20), c_cone[3] * t0.x));
+                v0 += 0.5f * (r2_at(R2, ro, 1, w, S, true, e21) +
+                              fmaf(t2.y, r2_at(R2, ro1, 1, w, S, cin, e21), c_cone[4] * t2.x));
+                v1 += 0.5f * (r2_at(R2, ro, 2, w, S, true, e22) +
+                              fmaf(t2.y, r2_at(R2, ro1, 2, w, S, cin, e22), c_cone[5] * t2.x));
+                v1 += 0.5f * (r2_at(R2, ro, 3, w, S, true, e23) +
+                              fmaf(t4.y, r2_at(R2, ro1, 3, w + 4, S, cin, e23), c_cone[6] * t4.x));
             }
             r1[(2 * j) * RR + wl] = v0;
             r1[(2 * j + 1) * RR + wl] = v1;
@@ -488,46 +536,48 @@ __device__ void body_tail(const TailArgs &a, unsigned tile, char *lds) {
         __syncthreads();
         // R_0 at x = u + 1 for every pixel (u, w) of the tile, added to the sum.
         // Column slots are ordered even u first, so that each wave holds one
-        // parity of x (64 / TILE slots per wave).
-        for (int i = ltid(); i < TILE * TILE; i += 256) {
-            const int slot = i / TILE, wl = i % TILE;
+        // parity of x (64 / TILE slots per wave); a thread keeps its row.
+        const int wl = ltid() % TILE, w = w_lo + wl;
+        const int slot0 = ltid() / TILE;
+#pragma unroll
+        for (int it = 0; it < TILE * TILE / 256; ++it) {
+            const int slot = slot0 + (256 / TILE) * it;
             const int ul = slot < TILE / 2 ? 2 * slot : 2 * (slot - TILE / 2) + 1;
-            const int u = u_lo + ul, w = w_lo + wl;
+            const int u = u_lo + ul;
             if (u < 0 || u >= S || w >= S) continue;
             const int x = u + 1;
+            const float2 *ivp = iv + base + (x - u_lo) * su + wl * sw;
             float v = 0.f;
             if (x >= S) {
                 v = env_fluence(envq, 0, 0);  // beyond the grid
             } else if (x & 1) {
                 // Eq. 14 at level 0: both directions of T_0, R_1 at the next level-1 probe
-                const float2 *ivp = iv + base + (x - u_lo) * su + wl * sw;
                 const float2 t0 = tail_ray<0, 2, G::plane>(ivp, su, sw);
                 const float2 t1 = tail_ray<1, 2, G::plane>(ivp, su, sw);
-                const int j = ((x + 1) >> 1) - c1_lo;
-                v += fmaf(t0.y, r1[(2 * j) * RR + wl + 1], c_cone[1] * t0.x);
-                v += fmaf(t1.y, r1[(2 * j + 1) * RR + wl + 3], c_cone[2] * t1.x);
+                const float *rj = r1 + (2 * (((x + 1) >> 1) - c1_lo)) * RR + wl;
+                v += fmaf(t0.y, rj[1], c_cone[1] * t0.x);
+                v += fmaf(t1.y, rj[RR + 3], c_cone[2] * t1.x);
             } else {
                 // Eq. 15-17 at level 0: the co-located level-1 probe and the
                 // doubled edges (directions 0 and 2 of T_1)
-                const float2 *ivp = iv + base + (x - u_lo) * su + wl * sw;
                 const float2 t0 = tail_ray<2, 4, G::plane>(ivp, su, sw);
                 const float2 t2 = tail_ray<4, 4, G::plane>(ivp, su, sw);
-                const int j = (x >> 1) - c1_lo;
-                v += 0.5f * (r1[(2 * j) * RR + wl + 2] +
-                             fmaf(t0.y, r1[(2 * j + 2) * RR + wl], c_cone[1] * t0.x));
-                v += 0.5f * (r1[(2 * j + 1) * RR + wl + 2] +
-                             fmaf(t2.y, r1[(2 * j + 3) * RR + wl + 4], c_cone[2] * t2.x));
+                const float *rj = r1 + (2 * ((x >> 1) - c1_lo)) * RR + wl;
+                v += 0.5f * (rj[2] + fmaf(t0.y, rj[2 * RR], c_cone[1] * t0.x));
+                v += 0.5f * (rj[RR + 2] + fmaf(t2.y, rj[3 * RR + 4], c_cone[2] * t2.x));
             }
-            const int r = q == 0 || q == 1 ? w : q == 2 ? u : S - 1 - u;
+            const int r = q < 2 ? w : q == 2 ? u : S - 1 - u;
             const int c = q == 0 ? u : q == 1 ? S - 1 - u : w;
             acc[(r - r0) * AP + (c - c0)] += v;
         }
     }
     __syncthreads();
-    for (int i = ltid(); i < TILE * TILE; i += 256) {
+#pragma unroll
+    for (int it = 0; it < TILE * TILE / 256; ++it) {
+        const int i = ltid() + 256 * it;
         const int rl = i / TILE, cl = i % TILE;
         const int r = r0 + rl, c = c0 + cl;
-        if (r < S && c < S) a.out[(size_t)r * S + c] = acc[rl * AP + cl];
+        if (r < S && c < S) a.out[r * S + c] = acc[rl * AP + cl];
     }
     __syncthreads();
 }
@@ -839,7 +889,7 @@ struct CellDer {
         const float tau = s * ell;
         le = ell * cell_phi(tau);
         ls = e * ell * ell * cell_dphi(tau);
-        ts = -ell * expf(-tau);
+        ts = -ell * exp_neg(tau);
     }
 };
 
