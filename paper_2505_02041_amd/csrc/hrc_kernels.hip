@@ -403,9 +403,9 @@ template <int TILE> struct TailTile {
 // / w, and the two planes hold the axis and the diagonal half pieces.
 template <int sid, int pieces, int plane>
 __device__ __forceinline__ float2 tail_ray(const float2 *ivp, int su, int sw) {
-    float2 acc = make_float2(0.f, 1.f);
+    float2 acc = ivp[kHpLen[sid][0] * plane];  // the first piece lies in the probe's pixel
 #pragma unroll
-    for (int j = 0; j < pieces; ++j)
+    for (int j = 1; j < pieces; ++j)
         acc = merge(acc, ivp[kHpLen[sid][j] * plane + kHpDu[sid][j] * su + kHpDw[sid][j] * sw]);
     return acc;
 }
@@ -417,7 +417,7 @@ __device__ __forceinline__ float2 tail_ray(const float2 *ivp, int su, int sw) {
 __device__ __forceinline__ float r2_at(const float *R2, int ro, int jj, int y, int S, bool cin,
                                        float fill) {
     const bool in = cin && (unsigned)y < (unsigned)S;
-    const float v = R2[in ? ro + jj * S + y : 0];
+    const float v = R2[in ? (unsigned)(ro + jj * S + y) : 0u];
     return in ? v : fill;
 }
 
@@ -490,12 +490,10 @@ __device__ void body_tail(const TailArgs &a, unsigned tile, char *lds) {
                 const int c = (cp + 1) >> 1;
                 const bool cin = c < cmax;
                 const int ro = (cin ? c : 0) * 4 * S;
-                v0 = 0.f;
-                v1 = 0.f;
-                v0 += fmaf(t0.y, r2_at(R2, ro, 0, w - 2, S, cin, e20), c_cone[3] * t0.x);
-                v0 += fmaf(t1.y, r2_at(R2, ro, 1, w, S, cin, e21), c_cone[4] * t1.x);
-                v1 += fmaf(t1.y, r2_at(R2, ro, 2, w, S, cin, e22), c_cone[5] * t1.x);
-                v1 += fmaf(t2.y, r2_at(R2, ro, 3, w + 2, S, cin, e23), c_cone[6] * t2.x);
+                v0 = fmaf(t0.y, r2_at(R2, ro, 0, w - 2, S, cin, e20), c_cone[3] * t0.x) +
+                     fmaf(t1.y, r2_at(R2, ro, 1, w, S, cin, e21), c_cone[4] * t1.x);
+                v1 = fmaf(t1.y, r2_at(R2, ro, 2, w, S, cin, e22), c_cone[5] * t1.x) +
+                     fmaf(t2.y, r2_at(R2, ro, 3, w + 2, S, cin, e23), c_cone[6] * t2.x);
             }
             r1[(2 * j) * RR + wl] = v0;
             r1[(2 * j + 1) * RR + wl] = v1;
@@ -519,56 +517,62 @@ __device__ void body_tail(const TailArgs &a, unsigned tile, char *lds) {
                 const int c = cp >> 1;  // < cmax: cp < S / 2
                 const bool cin = c + 1 < cmax;
                 const int ro = c * 4 * S, ro1 = (cin ? c + 1 : 0) * 4 * S;
-                v0 = 0.f;
-                v1 = 0.f;
-                v0 += 0.5f * (r2_at(R2, ro, 0, w, S, true, e20) +
-                              fmaf(t0.y, r2_at(R2, ro1, 0, w - 4, S, cin, e20), c_cone[3] * t0.x));
-                v0 += 0.5f * (r2_at(R2, ro, 1, w, S, true, e21) +
-                              fmaf(t2.y, r2_at(R2, ro1, 1, w, S, cin, e21), c_cone[4] * t2.x));
-                v1 += 0.5f * (r2_at(R2, ro, 2, w, S, true, e22) +
-                              fmaf(t2.y, r2_at(R2, ro1, 2, w, S, cin, e22), c_cone[5] * t2.x));
-                v1 += 0.5f * (r2_at(R2, ro, 3, w, S, true, e23) +
-                              fmaf(t4.y, r2_at(R2, ro1, 3, w + 4, S, cin, e23), c_cone[6] * t4.x));
+                v0 = 0.5f * (r2_at(R2, ro, 0, w, S, true, e20) +
+                             fmaf(t0.y, r2_at(R2, ro1, 0, w - 4, S, cin, e20), c_cone[3] * t0.x)) +
+                     0.5f * (r2_at(R2, ro, 1, w, S, true, e21) +
+                             fmaf(t2.y, r2_at(R2, ro1, 1, w, S, cin, e21), c_cone[4] * t2.x));
+                v1 = 0.5f * (r2_at(R2, ro, 2, w, S, true, e22) +
+                             fmaf(t2.y, r2_at(R2, ro1, 2, w, S, cin, e22), c_cone[5] * t2.x)) +
+                     0.5f * (r2_at(R2, ro, 3, w, S, true, e23) +
+                             fmaf(t4.y, r2_at(R2, ro1, 3, w + 4, S, cin, e23), c_cone[6] * t4.x));
             }
             r1[(2 * j) * RR + wl] = v0;
             r1[(2 * j + 1) * RR + wl] = v1;
         }
         __syncthreads();
         // R_0 at x = u + 1 for every pixel (u, w) of the tile, added to the sum.
-        // Column slots are ordered even u first, so that each wave holds one
-        // parity of x (64 / TILE slots per wave); a thread keeps its row.
-        const int wl = ltid() % TILE, w = w_lo + wl;
-        const int slot0 = ltid() / TILE;
+        // A thread keeps its row w; its column offsets ul are all even (x
+        // odd) in the first half of the passes and all odd in the second, so
+        // each pass holds one parity of x for the whole block (with a single
+        // pass, for each wave).  Offsets into the intervals and the sum are
+        // linear in ul and wl.
+        constexpr int SP = 256 / TILE, IT = TILE * TILE / 256;
+        const int wl = ltid() % TILE, w = w_lo + wl, slot0 = ltid() / TILE;
+        const int au = q == 0 ? 1 : q == 1 ? -1 : q == 2 ? AP : -AP;
+        const int aw = q < 2 ? AP : 1;
+        const int abase = q == 1 ? TILE - 1 : q == 3 ? (TILE - 1) * AP : 0;
+        const float2 *ivw = iv + base + su + wl * sw;  // pixel (u_lo + 1, w)
+        float *accw = acc + abase + wl * aw;
 #pragma unroll
-        for (int it = 0; it < TILE * TILE / 256; ++it) {
-            const int slot = slot0 + (256 / TILE) * it;
-            const int ul = slot < TILE / 2 ? 2 * slot : 2 * (slot - TILE / 2) + 1;
+        for (int it = 0; it < IT; ++it) {
+            int ul;
+            if constexpr (IT >= 2)
+                ul = 2 * (slot0 + SP * (it % (IT / 2))) + (it >= IT / 2 ? 1 : 0);
+            else
+                ul = slot0 < SP / 2 ? 2 * slot0 : 2 * (slot0 - SP / 2) + 1;
             const int u = u_lo + ul;
             if (u < 0 || u >= S || w >= S) continue;
-            const int x = u + 1;
-            const float2 *ivp = iv + base + (x - u_lo) * su + wl * sw;
-            float v = 0.f;
-            if (x >= S) {
-                v = env_fluence(envq, 0, 0);  // beyond the grid
-            } else if (x & 1) {
-                // Eq. 14 at level 0: both directions of T_0, R_1 at the next level-1 probe
+            const float2 *ivp = ivw + ul * su;  // the probe at x = u + 1
+            float v;
+            if ((ul & 1) == 0) {
+                // x odd, Eq. 14 at level 0: both directions of T_0, R_1 at the
+                // next level-1 probe (column (x + 1) / 2)
                 const float2 t0 = tail_ray<0, 2, G::plane>(ivp, su, sw);
                 const float2 t1 = tail_ray<1, 2, G::plane>(ivp, su, sw);
-                const float *rj = r1 + (2 * (((x + 1) >> 1) - c1_lo)) * RR + wl;
-                v += fmaf(t0.y, rj[1], c_cone[1] * t0.x);
-                v += fmaf(t1.y, rj[RR + 3], c_cone[2] * t1.x);
-            } else {
-                // Eq. 15-17 at level 0: the co-located level-1 probe and the
-                // doubled edges (directions 0 and 2 of T_1)
+                const float *rj = r1 + ul * RR + wl;
+                v = fmaf(t0.y, rj[1], c_cone[1] * t0.x) + fmaf(t1.y, rj[RR + 3], c_cone[2] * t1.x);
+            } else if (u + 1 < S) {
+                // x even, Eq. 15-17 at level 0: the co-located level-1 probe
+                // (column x / 2) and the doubled edges (directions 0 and 2 of T_1)
                 const float2 t0 = tail_ray<2, 4, G::plane>(ivp, su, sw);
                 const float2 t2 = tail_ray<4, 4, G::plane>(ivp, su, sw);
-                const float *rj = r1 + (2 * ((x >> 1) - c1_lo)) * RR + wl;
-                v += 0.5f * (rj[2] + fmaf(t0.y, rj[2 * RR], c_cone[1] * t0.x));
-                v += 0.5f * (rj[RR + 2] + fmaf(t2.y, rj[3 * RR + 4], c_cone[2] * t2.x));
+                const float *rj = r1 + (ul - 1) * RR + wl;
+                v = 0.5f * (rj[2] + fmaf(t0.y, rj[2 * RR], c_cone[1] * t0.x)) +
+                    0.5f * (rj[RR + 2] + fmaf(t2.y, rj[3 * RR + 4], c_cone[2] * t2.x));
+            } else {
+                v = env_fluence(envq, 0, 0);  // x = S: beyond the grid
             }
-            const int r = q < 2 ? w : q == 2 ? u : S - 1 - u;
-            const int c = q == 0 ? u : q == 1 ? S - 1 - u : w;
-            acc[(r - r0) * AP + (c - c0)] += v;
+            accw[ul * au] += v;
         }
     }
     __syncthreads();
