@@ -705,7 +705,10 @@ __device__ void body_merge_down_adj(const DownAdjArgs &a, unsigned tile, int U) 
 
 // Adjoint of the interval pyramid: dT_n (gather form) from the merge down at
 // levels n and n-1 and from the merge up of T_{n+1}.  Two consecutive y per
-// thread.
+// thread.  Every operand is loaded first and the terms are added afterwards,
+// so that a wave waits for memory once rather than once per source: the
+// conditions on x and k are uniform over the wave, absent terms load nothing
+// and add zero, and reads outside the grid take a clamped address and a select.
 __device__ void body_dT(const DTArgs &a, unsigned tile, int U) {
     const int N = a.N, S = 1 << N, n = a.n;
     const size_t SS = (size_t)S * S;
@@ -720,36 +723,36 @@ __device__ void body_dT(const DTArgs &a, unsigned tile, int U) {
         const int q = row / rpq;
         const unsigned r = row % rpq;
         const int x = r / dirs, k = r % dirs;
-        float gl0 = 0.f, gt0 = 0.f, gl1 = 0.f, gt1 = 0.f;
         const float *envq = a.env ? a.env + (size_t)q * kConeTable : nullptr;
         // (a) merge down at level n, odd x (Eq. 14): T_n(p, k) is the edge of
-        //     cone k (lower half, jj = 2k) and of cone k-1 (upper half, jj = 2k-1).
+        //     cone k (lower half, jj = 2k) and of cone k-1 (upper half, jj = 2k-1):
+        //     term i = 0 reads R_n row (x, k-1) and cone 2k-1 of R_{n+1}, i = 1
+        //     row (x, k) and cone 2k.
+        float2 ag[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+        float2 ar[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+        float aA[2] = {0.f, 0.f};
         if (n < N && (x & 1)) {
             const float *dRq = a.dRn + q * SS;
             const float *Rq = a.Rn1 + q * SS;
             const int c = (x + 1) >> 1, yf = y + 2 * k - (1 << n);  // odd when n = 0
             const bool rin = n + 1 < N && c < (S >> (n + 1));
-            if (k >= 1) {
-                const float2 g = *reinterpret_cast<const float2 *>(
-                    dRq + ((size_t)((x << n) | (k - 1))) * S + y);
-                const float A = c_cone[(1 << (n + 1)) - 1 + 2 * k - 1];
-                const float2 rv = ld2_r(rin, Rq + ((size_t)((c << (n + 1)) | (2 * k - 1))) * S,
-                                        yf, S, n > 0, env_fluence(envq, n + 1, 2 * k - 1));
-                gl0 = fmaf(g.x, A, gl0); gl1 = fmaf(g.y, A, gl1);
-                gt0 = fmaf(g.x, rv.x, gt0); gt1 = fmaf(g.y, rv.y, gt1);
-            }
-            if (k < (1 << n)) {
-                const float2 g = *reinterpret_cast<const float2 *>(
-                    dRq + ((size_t)((x << n) | k)) * S + y);
-                const float A = c_cone[(1 << (n + 1)) - 1 + 2 * k];
-                const float2 rv = ld2_r(rin, Rq + ((size_t)((c << (n + 1)) | (2 * k))) * S, yf,
-                                        S, n > 0, env_fluence(envq, n + 1, 2 * k));
-                gl0 = fmaf(g.x, A, gl0); gl1 = fmaf(g.y, A, gl1);
-                gt0 = fmaf(g.x, rv.x, gt0); gt1 = fmaf(g.y, rv.y, gt1);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int ii = k - 1 + i, jj = 2 * k - 1 + i;
+                if (ii < 0 || ii >= (1 << n)) continue;
+                ag[i] = *reinterpret_cast<const float2 *>(dRq + ((size_t)((x << n) | ii)) * S + y);
+                aA[i] = c_cone[(1 << (n + 1)) - 1 + jj];
+                ar[i] = ld2_r(rin, Rq + ((size_t)((c << (n + 1)) | jj)) * S, yf, S, n > 0,
+                              env_fluence(envq, n + 1, jj));
             }
         }
         // (b) merge down at level n-1, even column 2x (Eq. 17): T_n(p, k), k even,
-        //     is the doubled edge of cone k/2 (jj = k) and of cone k/2-1 (jj = k-1).
+        //     is the doubled edge of cone k/2 (jj = k) and of cone k/2-1 (jj = k-1):
+        //     term i = 0 reads dR_{n-1} row (2x, k/2-1) and cone k-1 of R_n at
+        //     column x+1, i = 1 row (2x, k/2) and cone k.
+        float2 bg[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+        float2 br[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+        float bA[2] = {0.f, 0.f};
         if (n >= 1 && (k & 1) == 0) {
             const int nm = n - 1;
             const float *dRq = a.dRm + q * SS;
@@ -757,70 +760,88 @@ __device__ void body_dT(const DTArgs &a, unsigned tile, int U) {
             const int yf = y + 2 * k - (1 << n);
             const int xm = 2 * x;
             const bool rin = n < N && x + 1 < (S >> n);
-            if (k >= 2) {
-                const float2 g0 = *reinterpret_cast<const float2 *>(
-                    dRq + ((size_t)((xm << nm) | (k / 2 - 1))) * S + y);
-                const float A = c_cone[(1 << n) - 1 + k - 1];
-                const float2 rv = ld2_r(rin, Rq + ((size_t)(((x + 1) << n) | (k - 1))) * S, yf,
-                                        S, true, env_fluence(envq, n, k - 1));
-                const float g0x = 0.5f * g0.x, g0y = 0.5f * g0.y;
-                gl0 = fmaf(g0x, A, gl0); gl1 = fmaf(g0y, A, gl1);
-                gt0 = fmaf(g0x, rv.x, gt0); gt1 = fmaf(g0y, rv.y, gt1);
-            }
-            if (k < (1 << n)) {
-                const float2 g0 = *reinterpret_cast<const float2 *>(
-                    dRq + ((size_t)((xm << nm) | (k / 2))) * S + y);
-                const float A = c_cone[(1 << n) - 1 + k];
-                const float2 rv = ld2_r(rin, Rq + ((size_t)(((x + 1) << n) | k)) * S, yf, S,
-                                        true, env_fluence(envq, n, k));
-                const float g0x = 0.5f * g0.x, g0y = 0.5f * g0.y;
-                gl0 = fmaf(g0x, A, gl0); gl1 = fmaf(g0y, A, gl1);
-                gt0 = fmaf(g0x, rv.x, gt0); gt1 = fmaf(g0y, rv.y, gt1);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int jj = k - 1 + i;
+                if (jj < 0 || jj >= (1 << n)) continue;
+                bg[i] = *reinterpret_cast<const float2 *>(
+                    dRq + ((size_t)((xm << nm) | (k / 2 - 1 + i))) * S + y);
+                bA[i] = c_cone[(1 << n) - 1 + jj];
+                br[i] = ld2_r(rin, Rq + ((size_t)(((x + 1) << n) | jj)) * S, yf, S, true,
+                              env_fluence(envq, n, jj));
             }
         }
-        // (c) merge up of T_{n+1} from T_n (Eq. 18-20), H = 2^n (n >= 2: even shifts).
+        // (c) merge up of T_{n+1} from T_n (Eq. 18-20), H = 2^n (n >= 2: even
+        //     shifts).  Outputs ko = 2k (weight 1), 2k+1 and 2k-1 (weight 1/2):
+        //     near role (x even): the far partner kb = k, k+1, k-1 at row y + 2k - H;
+        //     far role (x odd): the near partner ka = k, k+1, k-1, each from
+        //     output row y - (2 ka - H).
+        float4 cg[3], cf[3];
+        float cw[3] = {0.f, 0.f, 0.f};
+        const bool near_role = (x & 1) == 0;
         if (a.has_up) {
             const int H = 1 << n;
             const int odirs = 2 * H + 1;
             const float2 *Tq = a.Tn + q * a.en;
             const float2 *g0 = a.dTn1 + q * a.en1 + (size_t)(x >> 1) * odirs * S;
-            if ((x & 1) == 0) {
-                // near role: outputs (2k, far k, weight 1), (2k+1, far k+1, 1/2),
-                // (2k-1, far k-1, 1/2), far start at row y + 2k - H
-                const int yf = y + 2 * k - H;
-                const float2 *far = Tq + (size_t)(x + 1) * dirs * S;
+            const float2 *part = Tq + (size_t)(near_role ? x + 1 : x - 1) * dirs * S;
 #pragma unroll
-                for (int v = 0; v < 3; ++v) {
-                    const int ko = v == 0 ? 2 * k : (v == 1 ? 2 * k + 1 : 2 * k - 1);
-                    const int kb = v == 0 ? k : (v == 1 ? k + 1 : k - 1);
-                    if (ko < 0 || ko > 2 * H) continue;
-                    const float wgt = v == 0 ? 1.f : 0.5f;
-                    const float4 f = far_pair(far + (size_t)kb * S, yf, S);
-                    const float4 g = ld_pair(g0 + (size_t)ko * S + y);
-                    gl0 = fmaf(wgt, g.x, gl0);
-                    gt0 = fmaf(wgt, fmaf(g.x, f.x, g.y * f.y), gt0);
-                    gl1 = fmaf(wgt, g.z, gl1);
-                    gt1 = fmaf(wgt, fmaf(g.z, f.z, g.w * f.w), gt1);
+            for (int v = 0; v < 3; ++v) {
+                const int ko = v == 0 ? 2 * k : (v == 1 ? 2 * k + 1 : 2 * k - 1);
+                const int kp = v == 0 ? k : (v == 1 ? k + 1 : k - 1);
+                cg[v] = make_float4(0.f, 0.f, 0.f, 0.f);
+                cf[v] = make_float4(0.f, 1.f, 0.f, 1.f);
+                if (ko < 0 || ko > 2 * H) continue;
+                cw[v] = v == 0 ? 1.f : 0.5f;
+                if (near_role) {
+                    cf[v] = far_pair(part + (size_t)kp * S, y + 2 * k - H, S);
+                    cg[v] = ld_pair(g0 + (size_t)ko * S + y);
+                } else {
+                    const int yo = y - (2 * kp - H);
+                    const bool in = (unsigned)yo < (unsigned)S;
+                    const int yc = in ? yo : 0;
+                    const float4 tn = ld_pair(part + (size_t)kp * S + yc);
+                    const float4 g = ld_pair(g0 + (size_t)ko * S + yc);
+                    cf[v] = in ? tn : make_float4(0.f, 0.f, 0.f, 0.f);
+                    cg[v] = in ? g : make_float4(0.f, 0.f, 0.f, 0.f);
                 }
-            } else {
-                // far role: outputs (2k, near k), (2k+1, near k+1), (2k-1, near k-1),
-                // each from output row y - (2*ka - H)
-                const float2 *nearp = Tq + (size_t)(x - 1) * dirs * S;
+            }
+        } else {
 #pragma unroll
-                for (int v = 0; v < 3; ++v) {
-                    const int ko = v == 0 ? 2 * k : (v == 1 ? 2 * k + 1 : 2 * k - 1);
-                    const int ka = v == 0 ? k : (v == 1 ? k + 1 : k - 1);
-                    if (ko < 0 || ko > 2 * H) continue;
-                    const float wgt = v == 0 ? 1.f : 0.5f;
-                    const int yo = y - (2 * ka - H);
-                    if (yo < 0 || yo >= S) continue;
-                    const float4 tn = ld_pair(nearp + (size_t)ka * S + yo);
-                    const float4 g = ld_pair(g0 + (size_t)ko * S + yo);
-                    gl0 = fmaf(wgt * g.x, tn.y, gl0);
-                    gt0 = fmaf(wgt * g.y, tn.y, gt0);
-                    gl1 = fmaf(wgt * g.z, tn.w, gl1);
-                    gt1 = fmaf(wgt * g.w, tn.w, gt1);
-                }
+            for (int v = 0; v < 3; ++v) {
+                cg[v] = make_float4(0.f, 0.f, 0.f, 0.f);
+                cf[v] = make_float4(0.f, 1.f, 0.f, 1.f);
+            }
+        }
+        float gl0 = 0.f, gt0 = 0.f, gl1 = 0.f, gt1 = 0.f;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            gl0 = fmaf(ag[i].x, aA[i], gl0); gl1 = fmaf(ag[i].y, aA[i], gl1);
+            gt0 = fmaf(ag[i].x, ar[i].x, gt0); gt1 = fmaf(ag[i].y, ar[i].y, gt1);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const float g0x = 0.5f * bg[i].x, g0y = 0.5f * bg[i].y;
+            gl0 = fmaf(g0x, bA[i], gl0); gl1 = fmaf(g0y, bA[i], gl1);
+            gt0 = fmaf(g0x, br[i].x, gt0); gt1 = fmaf(g0y, br[i].y, gt1);
+        }
+        if (near_role) {
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                const float4 g = cg[v], f = cf[v];
+                gl0 = fmaf(cw[v], g.x, gl0);
+                gt0 = fmaf(cw[v], fmaf(g.x, f.x, g.y * f.y), gt0);
+                gl1 = fmaf(cw[v], g.z, gl1);
+                gt1 = fmaf(cw[v], fmaf(g.z, f.z, g.w * f.w), gt1);
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                const float4 g = cg[v], tn = cf[v];
+                gl0 = fmaf(cw[v] * g.x, tn.y, gl0);
+                gt0 = fmaf(cw[v] * g.y, tn.y, gt0);
+                gl1 = fmaf(cw[v] * g.z, tn.w, gl1);
+                gt1 = fmaf(cw[v] * g.w, tn.w, gt1);
             }
         }
         *reinterpret_cast<float4 *>(a.dT + q * a.en + (size_t)r * S + y) =
