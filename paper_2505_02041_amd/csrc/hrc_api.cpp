@@ -20,8 +20,9 @@ Layout make_layout(int N, bool backward, int group) {
     L.group = backward ? kQuadrants : group;
     const size_t SS = L.S * L.S;
     size_t off = 256;  // first 256 bytes: scratch flag for HRC_FLAG_VALIDATE
-    // the forward's tail folds T_0 and T_1 itself: only the reverse stores them
-    for (int n = backward ? 0 : kTracedLevels - 1; n <= N; ++n) {
+    // the forward's tail folds T_0 and T_1 itself (only the reverse stores
+    // them), and the merge down builds what it reads of T_N itself
+    for (int n = backward ? 0 : kTracedLevels - 1; n < N; ++n) {
         L.t_level[n] = off;
         off += align256(L.group * t_level_entries(N, n) * sizeof(float2));
     }
@@ -149,7 +150,7 @@ int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, cons
                             32,
                             keep_all_r ? 0 : kTracedLevels - 1};
         add(p);
-        for (int n = kTracedLevels; n <= N; ++n) {
+        for (int n = kTracedLevels; n < N; ++n) {
             p = Phase();
             p.kind = PH_UP;
             p.U = pick_u(U, PH_UP);

@@ -263,16 +263,15 @@ __device__ __forceinline__ float4 far_pair(const float2 *row, int yf, int S) {
     return (yf >= 0 && yf < S) ? ld_pair(row + yf) : make_float4(0.f, 1.f, 0.f, 1.f);
 }
 
-// Merge up: T_n from T_{n-1} (Section 4.1, Eq. 18-20).  At the top level
-// n = N only the even directions are built: the merge down reads T_N only
-// through its doubled edges (even k, Eq. 15-17), and nothing else reads T_N.
+// Merge up: T_n from T_{n-1} (Section 4.1, Eq. 18-20), for n < N.  The top
+// level is never stored: the merge down reads T_N only through the even
+// directions of its one column (the doubled edges of Eq. 15-17), and builds
+// those itself from T_{N-1}.
 __device__ void body_merge_up(const UpArgs &a, unsigned tile, int U) {
     const int N = a.N, S = 1 << N, n = a.n;
     const int h = 1 << (n - 1);
     const int dirs = 2 * h + 1, pdirs = h + 1;
-    const bool even_only = n == N;
-    const int kdirs = even_only ? pdirs : dirs;  // directions built per column
-    const unsigned rpq = (unsigned)(S >> n) * kdirs;
+    const unsigned rpq = (unsigned)(S >> n) * dirs;
     const size_t total = (size_t)a.nq * rpq * (S / 2);
     for (int uu = 0; uu < U; ++uu) {
         const size_t idx = ((size_t)tile * U + uu) * 256 + ltid();
@@ -281,7 +280,7 @@ __device__ void body_merge_up(const UpArgs &a, unsigned tile, int U) {
         const unsigned row = (unsigned)(idx >> (N - 1));
         const int q = row / rpq;
         const unsigned rk = row % rpq;
-        const int x = rk / kdirs, k = even_only ? 2 * (rk % kdirs) : rk % kdirs;
+        const int x = rk / dirs, k = rk % dirs;
         const unsigned r = (unsigned)x * dirs + k;  // output row (x, k)
         const float2 *near = a.Tp + q * a.ep + (size_t)(2 * x) * pdirs * S;
         const float2 *far = near + (size_t)pdirs * S;
@@ -355,13 +354,27 @@ __device__ void body_merge_down(const DownArgs &a, unsigned tile, int U) {
             }
         } else {
             // Eq. 15-17: average the co-located probe with the doubled-edge trace.
+            // At n = N-1 the doubled edge T_N(c, e2) is built here, as the merge
+            // up would (Eq. 18, even direction): T_{N-1}(2c, e2/2) at row y,
+            // then T_{N-1}(2c+1, e2/2) at row y + e2 - 2^n.
             const int c = x >> 1;
+            const bool top = m == N;
             const float2 *Tx = a.Tn1 + q * a.en1 + (size_t)c * ((1 << m) + 1) * S;
+            const float2 *Tnear = a.Tn + q * a.en + (size_t)(2 * c) * ((1 << n) + 1) * S;
+            const float2 *Tfar = Tnear + (size_t)((1 << n) + 1) * S;
 #pragma unroll
             for (int up = 0; up < 2; ++up) {
                 const int e2 = 2 * ii + 2 * up, jj = 2 * ii + up;
                 const float A = c_cone[(1 << m) - 1 + jj];
-                const float4 t = ld_pair(Tx + (size_t)e2 * S + y);
+                float4 t;
+                if (top) {
+                    const int kk = e2 >> 1;
+                    const float4 nv = ld_pair(Tnear + (size_t)kk * S + y);
+                    const float4 fv = far_pair(Tfar + (size_t)kk * S, y + e2 - (1 << n), S);
+                    t = pair(merge(lo(nv), lo(fv)), merge(hi(nv), hi(fv)));
+                } else {
+                    t = ld_pair(Tx + (size_t)e2 * S + y);
+                }
                 const float2 r0 = r_pair(Rq, N, m, c, jj, y, envq);
                 const float2 r1 = r_pair(Rq, N, m, c + 1, jj, y + 2 * e2 - (1 << m), envq);
                 acc0 += 0.5f * (r0.x + fmaf(t.y, r1.x, A * t.x));
@@ -1415,12 +1428,8 @@ unsigned phase_tiles(const Phase &p) {
             const unsigned t = (unsigned)((S + p.a.seed.tile - 1) / p.a.seed.tile);
             return t * t;
         }
-        case PH_UP: {
-            // the top level builds its even directions only
-            const size_t rows = p.a.up.n == N ? (size_t)((1 << (N - 1)) + 1)
-                                              : t_level_entries(N, p.a.up.n) / S;
-            return cdiv((size_t)p.a.up.nq * rows * S / 2, per);
-        }
+        case PH_UP:
+            return cdiv((size_t)p.a.up.nq * t_level_entries(N, p.a.up.n) / 2, per);
         case PH_DT: return cdiv(4 * t_level_entries(N, p.a.dt.n) / 2, per);
         case PH_DOWN: return cdiv((size_t)p.a.down.nq * SS / 2, per);
         case PH_DOWN_ADJ: return cdiv(4 * SS / 2, per);

@@ -31,13 +31,13 @@ def pass_bytes(name: str, N: int, n: int = -1) -> float:
         # the reverse's recomputed forward: T_0..T_2 written
         return 8 * SS + q * 8 * (_t(S, 0) + _t(S, 1) + _t(S, 2))
     if name == "merge_up":
-        # the top level n = N builds only its even directions (all the merge
-        # down reads): 2^(N-1) + 1 of the 2^N + 1 rows
-        written = _t(S, n) if n < N else float(((1 << (N - 1)) + 1) * S)
-        return q * 8 * (_t(S, n - 1) + written)
+        # levels 3 .. N-1 (the top level is built inside the merge down)
+        return q * 8 * (_t(S, n - 1) + _t(S, n))
     if name == "merge_down":
         # half of T_n (odd columns) and the even directions of T_{n+1}: together
-        # X^2 (1 + 2^-n) intervals; R_{n+1} read unless n + 1 = N; R_n written
+        # X^2 (1 + 2^-n) intervals (at n = N-1: all of T_{N-1}, from which the
+        # even directions of T_N are built, the same count); R_{n+1} read
+        # unless n + 1 = N; R_n written
         return q * 8 * _t(S, n) + (q * 4 * SS if n + 1 < N else 0.0) + q * 4 * SS
     if name == "tail":
         # the two fields once, R_2 of the four quadrants, F written
@@ -66,7 +66,7 @@ def pass_bytes(name: str, N: int, n: int = -1) -> float:
 def forward_passes(N: int):
     """(name, level) of every pass of one forward solve, in order."""
     out = [("seed", -1)]
-    out += [("merge_up", n) for n in range(3, N + 1)]
+    out += [("merge_up", n) for n in range(3, N)]
     out += [("merge_down", n) for n in range(N - 1, 1, -1)]
     out += [("tail", -1)]
     return out
@@ -80,7 +80,7 @@ def backward_bytes(N: int) -> float:
     """hrc_backward: the forward recomputed down to R_1 (every traced level
     stored, no gather) plus the reverse."""
     b = pass_bytes("seed_all", N)
-    b += sum(pass_bytes("merge_up", N, n) for n in range(3, N + 1))
+    b += sum(pass_bytes("merge_up", N, n) for n in range(3, N))
     b += sum(pass_bytes("merge_down", N, n) for n in range(N - 1, 0, -1))
     b += pass_bytes("gather_adj", N)
     b += sum(pass_bytes("merge_down_adj", N, n) for n in range(N - 1))

@@ -51,14 +51,16 @@ def _ws(N, flags=0):
 @pytest.mark.parametrize("N", [3, 6, 10, 12])
 def test_workspace_sizes_follow_the_memory_analysis(N):
     """Section 4.3.2: the pyramid holds (N + 3 - 2^-N) S^2 interval entries per
-    quadrant.  A forward keeps the pyramids of G quadrants at once (8 bytes per
-    entry) without T_0 and T_1 (2 S^2 and 1.5 S^2 entries, which its tail folds
-    on chip), two cascade levels of G quadrants and one spare S^2 field; the
-    backward keeps all four pyramids, every cascade level and their adjoints,
-    up to alignment."""
+    quadrant.  No solve stores the top level T_N ((2^N + 1) S entries: the
+    merge down builds the part it reads).  A forward keeps the pyramids of G
+    quadrants at once (8 bytes per entry) without T_0 and T_1 (2 S^2 and 1.5 S^2
+    entries, which its tail folds on chip), two cascade levels of G quadrants
+    and one spare S^2 field; the backward keeps all four pyramids, every
+    cascade level and their adjoints (dT_N included), up to alignment."""
     S = 1 << N
-    one = 8 * sum((S >> n) * (2 ** n + 1) * S for n in range(N + 1))
-    assert one == pytest.approx(8 * (N + 3 - 2.0 ** -N) * S * S)
+    full = 8 * sum((S >> n) * (2 ** n + 1) * S for n in range(N + 1))
+    assert full == pytest.approx(8 * (N + 3 - 2.0 ** -N) * S * S)
+    one = full - 8 * (2 ** N + 1) * S
     fwd_one = one - 8 * (2 + 1.5) * S * S
     for flags, G in ((_lib.HRC_FLAG_QUADRANTS_1, 1), (_lib.HRC_FLAG_QUADRANTS_2, 2),
                      (_lib.HRC_FLAG_QUADRANTS_4, 4), (0, 2 if N >= 11 else 4)):
@@ -66,7 +68,7 @@ def test_workspace_sizes_follow_the_memory_analysis(N):
         assert st == HRC_OK
         fwd_min = G * fwd_one + 2 * G * 4 * S * S + 4 * S * S
         assert fwd_min <= f <= fwd_min + 256 * (2 * N + 8), (flags, f, fwd_min)
-    bwd_min = 2 * 4 * one + 2 * N * 4 * 4 * S * S
+    bwd_min = 4 * one + 4 * full + 2 * N * 4 * 4 * S * S
     assert bwd_min <= b <= bwd_min + 256 * (4 * N + 10)
 
 

@@ -19,7 +19,7 @@ def ctx():
 
 
 def _forward_order(N):
-    return ([("seed", -1)] + [("merge_up", n) for n in range(3, N + 1)] +
+    return ([("seed", -1)] + [("merge_up", n) for n in range(3, N)] +
             [("merge_down", n) for n in range(N - 1, 1, -1)] + [("tail", -1)])
 
 
