@@ -691,27 +691,53 @@ __device__ void body_merge_down_adj(const DownAdjArgs &a, unsigned tile, int U) 
         const int c = r >> m, jj = r & ((1 << m) - 1);
         const int ii = jj >> 1, up = jj & 1;
         const float *dRq = a.dR + q * SS;
+        // Every operand is loaded before any is used (one memory wait per
+        // wave); c >= 1 and n > 0 are uniform over the wave, and rows outside
+        // the grid take a clamped address and a select.
         const float2 f0 = *reinterpret_cast<const float2 *>(
             dRq + ((size_t)(((2 * c) << n) | ii)) * S + yp);
-        float acc0 = 0.5f * f0.x, acc1 = 0.5f * f0.y;
+        float2 g = make_float2(0.f, 0.f), t = make_float2(0.f, 0.f);
+        float2 g2 = make_float2(0.f, 0.f), t2 = make_float2(0.f, 0.f);
         if (c >= 1) {
+            // odd column 2c-1 (far end of Eq. 14) at row y = y' - (2e - 2^n)
             const int e = ii + up;
             const int x = 2 * c - 1;
             const int y = yp - (2 * e - (1 << n));  // odd when n = 0
-            const float2 g = ld2(dRq + ((size_t)((x << n) | ii)) * S, y, S, n > 0);
-            const float2 t = ld2T(a.Tn + q * a.en + ((size_t)x * ((1 << n) + 1) + e) * S, y, S,
-                                  n > 0);
-            acc0 = fmaf(g.x, t.x, acc0);
-            acc1 = fmaf(g.y, t.y, acc1);
+            const float *grow = dRq + ((size_t)((x << n) | ii)) * S;
+            const float2 *trow = a.Tn + q * a.en + ((size_t)x * ((1 << n) + 1) + e) * S;
+            if (n > 0) {
+                const bool in = (unsigned)y < (unsigned)S;
+                const int yc = in ? y : 0;
+                const float2 gv = *reinterpret_cast<const float2 *>(grow + yc);
+                const float4 tv = ld_pair(trow + yc);
+                g = in ? gv : make_float2(0.f, 0.f);
+                t = in ? make_float2(tv.y, tv.w) : make_float2(0.f, 0.f);
+            } else {
+                const bool in0 = (unsigned)y < (unsigned)S, in1 = (unsigned)(y + 1) < (unsigned)S;
+                const int y0 = in0 ? y : 0, y1 = in1 ? y + 1 : 0;
+                const float ga = grow[y0], gb = grow[y1];
+                const float ta = trow[y0].y, tb = trow[y1].y;
+                g = make_float2(in0 ? ga : 0.f, in1 ? gb : 0.f);
+                t = make_float2(in0 ? ta : 0.f, in1 ? tb : 0.f);
+            }
+            // even column 2c-2 (far end of Eq. 17) at row y' - (2 e2 - 2^(n+1))
             const int e2 = 2 * ii + 2 * up;
             const int x2 = 2 * c - 2;
             const int y2 = yp - (2 * e2 - (1 << m));
-            const float2 g2 = ld2(dRq + ((size_t)((x2 << n) | ii)) * S, y2, S, true);
-            const float2 t2 = ld2T(a.Tn1 + q * a.en1 + ((size_t)(c - 1) * ((1 << m) + 1) + e2) * S,
-                                   y2, S, true);
-            acc0 = fmaf(0.5f * g2.x, t2.x, acc0);
-            acc1 = fmaf(0.5f * g2.y, t2.y, acc1);
+            const bool in2 = (unsigned)y2 < (unsigned)S;
+            const int y2c = in2 ? y2 : 0;
+            const float2 g2v = *reinterpret_cast<const float2 *>(
+                dRq + ((size_t)((x2 << n) | ii)) * S + y2c);
+            const float4 t2v =
+                ld_pair(a.Tn1 + q * a.en1 + ((size_t)(c - 1) * ((1 << m) + 1) + e2) * S + y2c);
+            g2 = in2 ? g2v : make_float2(0.f, 0.f);
+            t2 = in2 ? make_float2(t2v.y, t2v.w) : make_float2(0.f, 0.f);
         }
+        float acc0 = 0.5f * f0.x, acc1 = 0.5f * f0.y;
+        acc0 = fmaf(g.x, t.x, acc0);
+        acc1 = fmaf(g.y, t.y, acc1);
+        acc0 = fmaf(0.5f * g2.x, t2.x, acc0);
+        acc1 = fmaf(0.5f * g2.y, t2.y, acc1);
         *reinterpret_cast<float2 *>(a.dRn1 + q * SS + (size_t)r * S + yp) = make_float2(acc0, acc1);
     }
 }
