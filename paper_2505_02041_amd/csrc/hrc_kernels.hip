@@ -3,23 +3,25 @@
 // Frames.  Each quadrant solve works in a frame (u, w) whose +u axis faces the
 // quadrant (Section 4: the solve for [-pi/4, pi/4] is rotated four times,
 // Algorithm 1, Lighting).  Quadrant q reads the scene as
-//   q = 0 (+x): E[u][w] = img[w][u]          = imgT[u][w]
-//   q = 1 (-x): E[u][w] = img[w][S-1-u]      = imgT[S-1-u][w]
+//   q = 0 (+x): E[u][w] = img[w][u]
+//   q = 1 (-x): E[u][w] = img[w][S-1-u]
 //   q = 2 (+y): E[u][w] = img[u][w]
 //   q = 3 (-y): E[u][w] = img[S-1-u][w]
-// so that, with a transposed copy imgT, every quadrant reads whole rows w.
-// Each solve is mirror symmetric in w, so flips stand in for rotations.
+// Each solve is mirror symmetric in w, so flips stand in for rotations.  The
+// passes that read the image (traced levels, tail, their adjoints) stage an
+// image tile in LDS and address it in each quadrant's frame.
 //
 // Storage (per quadrant, y = w fastest so that 64 lanes read 64 consecutive y):
 //   T_n  float2 (L, T)  [S >> n][2^n + 1][S]   index (x*(2^n+1) + k)*S + y
 //   R_n  float          [S >> n][2^n][S]       index ((x << n) | ii)*S + y
 // Probe (n, x, y) sits at the centre of pixel (x*2^n, y).  Outside the grid
-// there is no light: an interval starting off-grid is <0, 1>, an angular
-// fluence off-grid is 0, and R_N = 0 (Section 4.2).
+// there is no light unless an environment map is set: an interval starting
+// off-grid is <0, 1>, an angular fluence off-grid is 0 (or the map's), and
+// R_N = 0 (Section 4.2).
 //
-// Every kernel is elementwise in gather form: one thread owns one output
-// element and reads what it needs, so results do not depend on the launch
-// shape and need no atomics.
+// Every pass is in gather form: each output element has one writer, which
+// reads what it needs, so results do not depend on the launch shape and need
+// no atomics.
 #include <hip/hip_ext.h>
 
 #include "hrc_internal.h"
@@ -29,33 +31,10 @@ namespace hrc {
 // A_m(jj) of Eq. 13 for m = 0..12 at offset 2^m - 1 (uploaded by the host).
 __constant__ float c_cone[kConeTable];
 
-// Cells crossed by the traced intervals of levels 0..2 (Section 4.2, traced with
-// analytic per-pixel integration, Section 5), for a probe at a pixel centre:
-// offsets (du, dw) from the probe's pixel and chord lengths, in order from the
-// probe.  Derived from the straight segment (1/2,1/2) -> (1/2,1/2) + v_n(k),
-// v_n(k) = (2^n, 2k - 2^n): a diagonal step splits each pixel it crosses at
-// the centre (corner touches have zero length); the slope -1/2 and +1/2 rays of
-// level 2 cross 7 pixels with pieces of sqrt(5)/4 and one of sqrt(5)/2.
-// Stencil id: n = 0 -> k, n = 1 -> 2 + k, n = 2 -> 5 + k.
+// Half lengths of the traced rays' pieces (below): every traced chord through
+// a pixel is one or two of these.
 constexpr float kH2 = 0.70710678118654752f;  // sqrt(2)/2
-constexpr float kR2 = 1.41421356237309505f;  // sqrt(2)
 constexpr float kQ5 = 0.55901699437494742f;  // sqrt(5)/4
-constexpr float kF5 = 1.11803398874989485f;  // sqrt(5)/2
-constexpr int kMaxCells = 7;
-__constant__ int c_st_len[10] = {2, 2, 3, 3, 3, 5, 7, 5, 7, 5};
-__constant__ signed char c_st_du[10][kMaxCells] = {
-    {0, 1}, {0, 1}, {0, 1, 2}, {0, 1, 2}, {0, 1, 2},
-    {0, 1, 2, 3, 4}, {0, 1, 1, 2, 3, 3, 4}, {0, 1, 2, 3, 4}, {0, 1, 1, 2, 3, 3, 4},
-    {0, 1, 2, 3, 4}};
-__constant__ signed char c_st_dw[10][kMaxCells] = {
-    {0, -1}, {0, 1}, {0, -1, -2}, {0, 0, 0}, {0, 1, 2},
-    {0, -1, -2, -3, -4}, {0, 0, -1, -1, -1, -2, -2}, {0, 0, 0, 0, 0},
-    {0, 0, 1, 1, 1, 2, 2}, {0, 1, 2, 3, 4}};
-__constant__ float c_st_ell[10][kMaxCells] = {
-    {kH2, kH2}, {kH2, kH2}, {kH2, kR2, kH2}, {0.5f, 1.f, 0.5f}, {kH2, kR2, kH2},
-    {kH2, kR2, kR2, kR2, kH2}, {kQ5, kQ5, kQ5, kF5, kQ5, kQ5, kQ5},
-    {0.5f, 1.f, 1.f, 1.f, 0.5f}, {kQ5, kQ5, kQ5, kF5, kQ5, kQ5, kQ5},
-    {kH2, kR2, kR2, kR2, kH2}};
 
 // ---------------------------------------------------------------------------
 // Device helpers
@@ -104,21 +83,10 @@ __device__ __forceinline__ int frame_row(int q, int u, int S) {
     return (q & 1) ? S - 1 - u : u;
 }
 
-__device__ __forceinline__ int stencil_id(int n, int k) {
-    return n == 0 ? k : (n == 1 ? 2 + k : 5 + k);
-}
-
-// R_m(column c, cone jj, row y) of one quadrant, 0 outside the grid; R_N = 0.
-// The environment's angular fluence in cone jj of level m (0 without one).
+// The environment's angular fluence in cone jj of level m (0 without one):
+// what an angular fluence looked up outside the grid reads, and R_N.
 __device__ __forceinline__ float env_fluence(const float *envq, int m, int jj) {
     return envq ? envq[(1 << m) - 1 + jj] : 0.f;
-}
-
-__device__ __forceinline__ float r_lookup(const float *Rq, int N, int m, int c, int jj, int y,
-                                          const float *envq) {
-    const int S = 1 << N;
-    if (m >= N || c >= (S >> m) || y < 0 || y >= S) return env_fluence(envq, m, jj);
-    return Rq[((size_t)((c << m) | jj)) * S + y];
 }
 
 // ---------------------------------------------------------------------------
@@ -319,7 +287,9 @@ __device__ __forceinline__ float2 r_pair(const float *Rq, int N, int m, int c, i
     return *reinterpret_cast<const float2 *>(Rq + ((size_t)((c << m) | jj)) * S + y);
 }
 
-// Merge down: R_n from R_{n+1}, T_n, T_{n+1} (Eq. 14-17).
+// Merge down: R_n from R_{n+1}, T_n, T_{n+1} (Eq. 14-17), for n >= 1 (levels 1
+// and 0 of the forward are the tail's, and the reverse reads R_1 at the
+// lowest), so every row shift is even and each lookup is a pair.
 __device__ void body_merge_down(const DownArgs &a, unsigned tile, int U) {
     const int N = a.N, S = 1 << N, n = a.n;
     const size_t SS = (size_t)S * S;
@@ -345,10 +315,7 @@ __device__ void body_merge_down(const DownArgs &a, unsigned tile, int U) {
                 const int e = ii + up, jj = 2 * ii + up;
                 const float A = c_cone[(1 << m) - 1 + jj];
                 const float4 t = ld_pair(Tx + (size_t)e * S + y);
-                const int yf = y + 2 * e - (1 << n);  // odd when n = 0
-                const float2 rf = n > 0 ? r_pair(Rq, N, m, c, jj, yf, envq)
-                                        : make_float2(r_lookup(Rq, N, m, c, jj, yf, envq),
-                                                      r_lookup(Rq, N, m, c, jj, yf + 1, envq));
+                const float2 rf = r_pair(Rq, N, m, c, jj, y + 2 * e - (1 << n), envq);
                 acc0 += fmaf(t.y, rf.x, A * t.x);
                 acc1 += fmaf(t.w, rf.y, A * t.z);
             }
@@ -644,17 +611,10 @@ __device__ void body_gather_adj(const GatherAdjArgs &a, unsigned tile, char *lds
     __syncthreads();
 }
 
-// Pair loads at a row position y that is even when `even` holds (every shift
-// except those of level 0); otherwise element by element.  Zero (or the vacuum
-// interval) outside the grid.
-__device__ __forceinline__ float2 ld2(const float *row, int y, int S, bool even) {
-    if (even) return (y >= 0 && y < S) ? *reinterpret_cast<const float2 *>(row + y)
-                                       : make_float2(0.f, 0.f);
-    return make_float2((y >= 0 && y < S) ? row[y] : 0.f,
-                       (y + 1 >= 0 && y + 1 < S) ? row[y + 1] : 0.f);
-}
-// R at (row, y), pair as ld2, when the row lies in the grid (`in`); elements
-// outside it read `fill` (the environment's fluence for the cone, or 0).
+// R at (row, y) and (row, y+1) when the row lies in the grid (`in`); rows y
+// outside [0, S) and every element of a row outside the grid read `fill` (the
+// environment's fluence for the cone, or 0).  With `even` (every shift but
+// those of level 0) y is even and the two form one aligned pair.
 __device__ __forceinline__ float2 ld2_r(bool in, const float *row, int y, int S, bool even,
                                         float fill) {
     if (!in) return make_float2(fill, fill);
@@ -662,16 +622,6 @@ __device__ __forceinline__ float2 ld2_r(bool in, const float *row, int y, int S,
                                        : make_float2(fill, fill);
     return make_float2((y >= 0 && y < S) ? row[y] : fill,
                        (y + 1 >= 0 && y + 1 < S) ? row[y + 1] : fill);
-}
-// Transmittances (the .y of two consecutive intervals) at y, 0 outside.
-__device__ __forceinline__ float2 ld2T(const float2 *row, int y, int S, bool even) {
-    if (even) {
-        if (y < 0 || y >= S) return make_float2(0.f, 0.f);
-        const float4 v = ld_pair(row + y);
-        return make_float2(v.y, v.w);
-    }
-    return make_float2((y >= 0 && y < S) ? row[y].y : 0.f,
-                       (y + 1 >= 0 && y + 1 < S) ? row[y + 1].y : 0.f);
 }
 
 // Adjoint of the merge down: dR_{n+1} from dR_n (gather form).  Each R_{n+1}
