@@ -611,17 +611,23 @@ __device__ void body_gather_adj(const GatherAdjArgs &a, unsigned tile, char *lds
     __syncthreads();
 }
 
-// R at (row, y) and (row, y+1) when the row lies in the grid (`in`); rows y
-// outside [0, S) and every element of a row outside the grid read `fill` (the
-// environment's fluence for the cone, or 0).  With `even` (every shift but
-// those of level 0) y is even and the two form one aligned pair.
+// R at (row, y) and (row, y+1) when the row lies in the grid (`in`, uniform
+// over the wave); rows y outside [0, S) and every element of a row outside the
+// grid read `fill` (the environment's fluence for the cone, or 0).  With
+// `even` (every shift but those of level 0) y is even and the two form one
+// aligned pair.  Rows outside [0, S) load a clamped address and are replaced
+// by a select, so the lookup has no per-lane branch.
 __device__ __forceinline__ float2 ld2_r(bool in, const float *row, int y, int S, bool even,
                                         float fill) {
     if (!in) return make_float2(fill, fill);
-    if (even) return (y >= 0 && y < S) ? *reinterpret_cast<const float2 *>(row + y)
-                                       : make_float2(fill, fill);
-    return make_float2((y >= 0 && y < S) ? row[y] : fill,
-                       (y + 1 >= 0 && y + 1 < S) ? row[y + 1] : fill);
+    if (even) {
+        const bool ok = (unsigned)y < (unsigned)S;
+        const float2 v = *reinterpret_cast<const float2 *>(row + (ok ? y : 0));
+        return ok ? v : make_float2(fill, fill);
+    }
+    const bool ok0 = (unsigned)y < (unsigned)S, ok1 = (unsigned)(y + 1) < (unsigned)S;
+    const float a0 = row[ok0 ? y : 0], a1 = row[ok1 ? y + 1 : 0];
+    return make_float2(ok0 ? a0 : fill, ok1 ? a1 : fill);
 }
 
 // Adjoint of the merge down: dR_{n+1} from dR_n (gather form).  Each R_{n+1}
