@@ -42,7 +42,8 @@ constexpr float kQ5 = 0.55901699437494742f;  // sqrt(5)/4
 
 // Work-tile id for block b of nb: consecutive tiles land on the same XCD (the
 // hardware deals blocks round-robin over 8 XCDs), so neighbouring rows that
-// share input rows share an L2.
+// share input rows, and neighbouring image tiles that share a halo, share an
+// L2 (it cut the traced levels' and the tail's HBM reads of their halos).
 __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb) {
     unsigned xcd = b & 7u, local = b >> 3;
     unsigned q = nb >> 3, r = nb & 7u;
@@ -1220,19 +1221,21 @@ HRC_ELEMENTWISE_KERNEL(hrc_interval_adj, body_dT, dt)
 
 __global__ __launch_bounds__(256) void hrc_seed(Phase p) {
     __shared__ __align__(16) char lds[SeedTile<32>::lds];
-    body_seed<32>(p.a.seed, blockIdx.x, lds);
+    body_seed<32>(p.a.seed, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 __global__ __launch_bounds__(256) void hrc_seed_adj(Phase p) {
     __shared__ __align__(16) char lds[kSeedAdjLds];
-    body_seed_adj(p.a.sa, blockIdx.x, lds);
+    body_seed_adj(p.a.sa, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
-__global__ __launch_bounds__(256) void hrc_blur(Phase p) { body_blur(p.a.bl, blockIdx.x); }
+__global__ __launch_bounds__(256) void hrc_blur(Phase p) {
+    body_blur(p.a.bl, xcd_tile(blockIdx.x, gridDim.x));
+}
 __global__ __launch_bounds__(256) void hrc_blur_adj(Phase p) {
-    body_blur_adj(p.a.bl, blockIdx.x);
+    body_blur_adj(p.a.bl, xcd_tile(blockIdx.x, gridDim.x));
 }
 __global__ __launch_bounds__(256) void hrc_tail(Phase p) {
     __shared__ __align__(16) char lds[TailTile<32>::lds];
-    body_tail<32>(p.a.tail, blockIdx.x, lds);
+    body_tail<32>(p.a.tail, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 __global__ __launch_bounds__(256) void hrc_gather_adj(Phase p) {
     __shared__ __align__(16) char lds[kGatherAdjLds];
