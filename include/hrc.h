@@ -75,9 +75,12 @@ typedef enum {
 #define HRC_FLAG_QUADRANTS_4 0x30u
 #define HRC_FLAG_QUADRANTS_MASK 0x30u
 /* hrc_batch_plan only: run the persistent kernel variant 0 (full register
- * budget) or 1 (64 registers) instead of letting the autotuner choose. */
+ * budget) or 1 (64 registers) instead of letting the autotuner choose;
+ * HRC_FLAG_BATCH_PERSISTENT: run every scene inside the persistent kernel
+ * (none as its own kernels). */
 #define HRC_FLAG_BATCH_FULL 0x100u
 #define HRC_FLAG_BATCH_DENSE 0x200u
+#define HRC_FLAG_BATCH_PERSISTENT 0x400u
 
 typedef struct hrc_context hrc_context;
 
@@ -222,13 +225,17 @@ typedef struct {
 typedef struct hrc_batch hrc_batch;
 
 /* Plan a batch: copies the scene table, sizes and allocates the batch's own
- * workspace (device memory owned by the batch), picks the kernel variant, the
- * tile sizes and the claim chunk with the autotuner (timing each candidate
- * launch on a stream of its own, on the caller's buffers), and captures one
- * persistent-kernel launch in a HIP graph.  The scene pointers are baked in:
- * later launches read and write the same buffers.  flags: 0, or one of
- * HRC_FLAG_BATCH_FULL / HRC_FLAG_BATCH_DENSE (HRC_ERR_UNSUPPORTED otherwise).
- * Synchronises `stream` first. */
+ * workspace (device memory owned by the batch), and captures one batch in a
+ * HIP graph: a persistent kernel that runs the scenes' passes tile by tile,
+ * preceded by the passes of the scenes from a size up as kernels of their own
+ * (a pass of a large scene fills the GPU by itself, and there the persistent
+ * kernel's synchronisation between passes costs more than the launch gaps it
+ * saves).  The autotuner picks that size (possibly none), the kernel variant,
+ * the tile sizes and the claim chunk, timing each candidate batch on a stream
+ * of its own, on the caller's buffers.  The scene pointers are baked in: later
+ * launches read and write the same buffers.  flags: 0, or HRC_FLAG_BATCH_FULL
+ * or HRC_FLAG_BATCH_DENSE, each optionally with HRC_FLAG_BATCH_PERSISTENT
+ * (HRC_ERR_UNSUPPORTED otherwise).  Synchronises `stream` first. */
 hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count,
                           unsigned flags, void *stream, hrc_batch **out);
 
@@ -242,11 +249,12 @@ size_t hrc_batch_workspace_bytes(const hrc_batch *batch);
 /* What the autotuner chose for a planned batch: the persistent kernel variant
  * (0: full register budget, one 1024-thread block per CU; 1: 64 registers,
  * two blocks per CU), the grid in blocks, the target tile count per pass
- * (each tile 256 threads), and the tiles-groups a block claims at once (a
- * group is the four tiles a block runs side by side).  Any output pointer may
- * be NULL.  Pure host function; HRC_ERR_INVALID_ARG for a NULL batch. */
+ * (each tile 256 threads), the tiles-groups a block claims at once (a group
+ * is the four tiles a block runs side by side), and how many scenes run as
+ * kernels of their own.  Any output pointer may be NULL.  Pure host
+ * function; HRC_ERR_INVALID_ARG for a NULL batch. */
 hrc_status hrc_batch_describe(const hrc_batch *batch, int *variant, int *grid,
-                              int *target_tiles, int *chunk);
+                              int *target_tiles, int *chunk, int *direct_scenes);
 
 /* Destroy a batch (NULL-safe); frees its device memory and graph. */
 void hrc_batch_destroy(hrc_batch *batch);

@@ -28,6 +28,7 @@ HRC_FLAG_QUADRANTS_4 = 0x30
 HRC_FLAG_QUADRANTS_MASK = 0x30
 HRC_FLAG_BATCH_FULL = 0x100
 HRC_FLAG_BATCH_DENSE = 0x200
+HRC_FLAG_BATCH_PERSISTENT = 0x400
 PASS_NAMES = ["seed", "merge_up", "merge_down", "tail", "gather_adj",
               "merge_down_adj", "interval_adj", "seed_adj", "blur", "blur_adj"]
 # Kernel symbol of each pass kind (what a profiler shows).
@@ -81,6 +82,7 @@ SIGNATURES = {
     "hrc_batch_launch": (ctypes.c_int, [_vp, _vp]),
     "hrc_batch_workspace_bytes": (_sz, [_vp]),
     "hrc_batch_describe": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(ctypes.c_int),
                                           ctypes.POINTER(ctypes.c_int),
                                           ctypes.POINTER(ctypes.c_int),
                                           ctypes.POINTER(ctypes.c_int)]),

@@ -1,6 +1,11 @@
 // Batched forward + backward: many scenes of different power-of-two sizes in one
-// persistent-kernel launch captured in a HIP graph, with tile sizes picked by
-// timing candidates on the device.
+// HIP graph launch.  The scenes go to one persistent kernel that schedules
+// their passes tile by tile; scenes from a size up (chosen by the autotuner,
+// possibly none) instead run pass by pass as their own kernels in the same
+// graph, where one pass fills the GPU and the persistent kernel's per-pass
+// synchronisation costs more than the launch gaps it saves.  Tile sizes,
+// kernel variant, claim chunk and that size are picked by timing candidates on
+// the device.
 #include <stdint.h>
 #include <stdlib.h>
 
@@ -22,6 +27,7 @@ struct hrc_batch {
     unsigned chunk = 1;            // items per claim, chosen by the autotuner
     int variant = 0;               // persistent kernel variant, chosen by the autotuner
     int grid = 0;
+    int direct = 0;                // scenes run as their own kernels, chosen by the autotuner
 };
 
 namespace {
@@ -109,8 +115,9 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
         if (any && (!ok16(sc.grad_fluence) || !ok16(sc.grad_emission) || !ok16(sc.grad_sigma_t)))
             return HRC_ERR_INVALID_ARG;
     }
-    if ((flags & ~(HRC_FLAG_BATCH_FULL | HRC_FLAG_BATCH_DENSE)) ||
-        flags == (HRC_FLAG_BATCH_FULL | HRC_FLAG_BATCH_DENSE))
+    if ((flags & ~(HRC_FLAG_BATCH_FULL | HRC_FLAG_BATCH_DENSE | HRC_FLAG_BATCH_PERSISTENT)) ||
+        (flags & (HRC_FLAG_BATCH_FULL | HRC_FLAG_BATCH_DENSE)) ==
+            (HRC_FLAG_BATCH_FULL | HRC_FLAG_BATCH_DENSE))
         return HRC_ERR_UNSUPPORTED;
     if (!ctx) return HRC_ERR_INVALID_ARG;
     DeviceGuard g(ctx->device);
@@ -154,20 +161,41 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
         return HRC_ERR_HIP;
     }
 
-    // ---- phase chains ------------------------------------------------------
-    Plan pl;
-    std::vector<int> first(count), np(count);
+    // ---- phase chains: each scene's passes (the persistent kernel's copies get
+    // its own tile sizes; the direct ones keep the standalone kernels')
+    std::vector<std::vector<Phase>> chains(count);
     for (int i = 0; i < count; ++i) {
         const hrc_scene &sc = scenes[i];
         Ws w{b->dmem + ws_off[i], layouts[i]};
         SolveBuffers sb{sc.emission, sc.sigma_t, sc.fluence, sc.grad_fluence, sc.grad_emission,
                         sc.grad_sigma_t};
         Phase tmp[kMaxPhases];
-        int n = build_solve_phases(w, sb, sc.grad_fluence != nullptr, nullptr, tmp, kMaxPhases);
-        first[i] = (int)pl.phases.size();
-        np[i] = n;
-        pl.phases.insert(pl.phases.end(), tmp, tmp + n);
+        const int n = build_solve_phases(w, sb, sc.grad_fluence != nullptr, nullptr, tmp,
+                                         kMaxPhases);
+        chains[i].assign(tmp, tmp + n);
     }
+    // scenes of log2 size >= min_direct run as their own kernels
+    Plan pl;
+    std::vector<int> first, np;
+    std::vector<const Phase *> direct_list;
+    int n_direct = 0;
+    auto split = [&](int min_direct) {
+        pl = Plan();
+        first.clear();
+        np.clear();
+        direct_list.clear();
+        n_direct = 0;
+        for (int i = 0; i < count; ++i) {
+            if (scenes[i].log2_size >= min_direct) {
+                ++n_direct;
+                for (const Phase &p : chains[i]) direct_list.push_back(&p);
+            } else {
+                first.push_back((int)pl.phases.size());
+                np.push_back((int)chains[i].size());
+                pl.phases.insert(pl.phases.end(), chains[i].begin(), chains[i].end());
+            }
+        }
+    };
 
     int grids[kPersistentVariants];  // resident blocks of each kernel variant
     for (int v = 0; v < kPersistentVariants; ++v) {
@@ -190,6 +218,7 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
     }
     BatchTables tables{};
     auto upload = [&](int target, unsigned chunk) -> bool {
+        if (pl.phases.empty()) return true;
         for (Phase &p : pl.phases) size_tiles(p, target);
         order_items(pl, first, np);
         tables = BatchTables{d_phases, d_seg_start, d_seg_phase, d_seg_step, d_step_items,
@@ -206,53 +235,75 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
                hipStreamSynchronize(cap) == hipSuccess;
     };
     int variant = 0;
+    // one batch: the direct scenes' passes in order, then the persistent kernel
     auto run = [&]() -> bool {
+        for (const Phase *p : direct_list)
+            if (launch_phase(*p, cap) != hipSuccess) return false;
+        if (pl.phases.empty()) return true;
         return launch_persistent(tables, d_sched, grids[variant], variant, cap) == hipSuccess;
     };
 
-    // ---- autotune: the kernel variant (registers vs resident blocks), the
-    // tile count per phase (hence elements per tile) as a multiple of the
-    // resident tile slots, and the claim chunk: the fastest whole-batch
-    // launch wins ----------------------------------------------------------
+    // ---- autotune: which sizes run as their own kernels, the persistent
+    // kernel variant (registers vs resident blocks), the tile count per phase
+    // (hence elements per tile) as a multiple of the resident tile slots, and
+    // the claim chunk: the fastest whole-batch launch wins -------------------
+    std::vector<int> min_directs{HRC_MAX_LOG2 + 1};  // none direct
+    if (!(flags & HRC_FLAG_BATCH_PERSISTENT)) {
+        // from 256^2 up: below, a pass does not fill the GPU
+        for (int L = HRC_MAX_LOG2; L >= 8; --L)
+            for (int i = 0; i < count; ++i)
+                if (scenes[i].log2_size == L) {
+                    min_directs.push_back(L);
+                    break;
+                }
+    }
     const int mults[] = {1, 2, 4};
     const unsigned chunks[] = {1u, 4u};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     bool fine = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
     float best_ms = 1e30f;
-    int best = grids[0] * kBatchQuarters, best_variant = 0;
+    int best = grids[0] * kBatchQuarters, best_variant = 0, best_min = HRC_MAX_LOG2 + 1;
     unsigned best_chunk = 1;
-    for (int v = 0; v < kPersistentVariants && fine; ++v) {
-        if ((flags & HRC_FLAG_BATCH_FULL) && v != 0) continue;
-        if ((flags & HRC_FLAG_BATCH_DENSE) && v != 1) continue;
-        variant = v;
-        for (int mult : mults) {
-            const int target = grids[v] * kBatchQuarters * mult;
-            for (unsigned ch : chunks) {
-                if (!fine) break;
-                fine = upload(target, ch) && run() &&
-                       hipStreamSynchronize(cap) == hipSuccess;  // warm-up
-                if (!fine) break;
-                fine = hipEventRecord(e0, cap) == hipSuccess && run() &&
-                       hipEventRecord(e1, cap) == hipSuccess &&
-                       hipEventSynchronize(e1) == hipSuccess;
-                float ms = 0.f;
-                if (fine && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
-                    best_ms = ms;
-                    best = target;
-                    best_chunk = ch;
-                    best_variant = v;
-                }
-            }
+    auto time_one = [&](int min_direct, int v, int target, unsigned ch) {
+        fine = upload(target, ch) && run() && hipStreamSynchronize(cap) == hipSuccess;  // warm-up
+        if (!fine) return;
+        fine = hipEventRecord(e0, cap) == hipSuccess && run() &&
+               hipEventRecord(e1, cap) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+        float ms = 0.f;
+        if (fine && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
+            best_ms = ms;
+            best = target;
+            best_chunk = ch;
+            best_variant = v;
+            best_min = min_direct;
         }
-    }
-    if (fine) {
-        // the scheduler's error word (a dependency wait that timed out)
-        unsigned err = 0;
-        fine = hipMemcpy(&err, d_sched + kSchedStride, sizeof(unsigned),
-                         hipMemcpyDeviceToHost) == hipSuccess && err == 0;
+    };
+    for (int min_direct : min_directs) {
+        if (!fine) break;
+        split(min_direct);
+        if (pl.phases.empty()) {  // every scene direct: nothing to tune
+            time_one(min_direct, 0, grids[0] * kBatchQuarters, 1u);
+            continue;
+        }
+        for (int v = 0; v < kPersistentVariants && fine; ++v) {
+            if ((flags & HRC_FLAG_BATCH_FULL) && v != 0) continue;
+            if ((flags & HRC_FLAG_BATCH_DENSE) && v != 1) continue;
+            variant = v;
+            for (int mult : mults)
+                for (unsigned ch : chunks)
+                    if (fine) time_one(min_direct, v, grids[v] * kBatchQuarters * mult, ch);
+        }
+        if (fine) {
+            // the scheduler's error word (a dependency wait that timed out)
+            unsigned err = 0;
+            fine = hipMemcpy(&err, d_sched + kSchedStride, sizeof(unsigned),
+                             hipMemcpyDeviceToHost) == hipSuccess && err == 0;
+        }
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
+    split(best_min);
+    b->direct = n_direct;
     b->target_tiles = best;
     b->chunk = best_chunk;
     b->variant = variant = best_variant;
@@ -289,8 +340,9 @@ size_t hrc_batch_workspace_bytes(const hrc_batch *batch) {
 }
 
 hrc_status hrc_batch_describe(const hrc_batch *batch, int *variant, int *grid,
-                              int *target_tiles, int *chunk) {
+                              int *target_tiles, int *chunk, int *direct_scenes) {
     if (!batch) return HRC_ERR_INVALID_ARG;
+    if (direct_scenes) *direct_scenes = batch->direct;
     if (variant) *variant = batch->variant;
     if (grid) *grid = batch->grid;
     if (target_tiles) *target_tiles = batch->target_tiles;

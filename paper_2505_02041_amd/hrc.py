@@ -302,12 +302,13 @@ class Batch:
 
     def describe(self) -> dict:
         """The autotuner's choice (``hrc_batch_describe``)."""
-        v, g, t, c = (ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int())
+        v, g, t, c, d = (ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int(),
+                         ctypes.c_int())
         check(_lib.load().hrc_batch_describe(self._ptr, ctypes.byref(v), ctypes.byref(g),
-                                             ctypes.byref(t), ctypes.byref(c)),
+                                             ctypes.byref(t), ctypes.byref(c), ctypes.byref(d)),
               "hrc_batch_describe")
         return {"variant": v.value, "grid": g.value, "target_tiles": t.value,
-                "chunk_groups": c.value}
+                "chunk_groups": c.value, "direct_scenes": d.value}
 
     def __del__(self):
         ptr = getattr(self, "_ptr", None)

@@ -135,9 +135,9 @@ def test_batch_argument_checks():
     assert out.value is None
     assert lib.hrc_batch_launch(None, None) == HRC_ERR_INVALID_ARG
     assert lib.hrc_batch_workspace_bytes(None) == 0
-    assert lib.hrc_batch_describe(None, None, None, None, None) == HRC_ERR_INVALID_ARG
+    assert lib.hrc_batch_describe(None, None, None, None, None, None) == HRC_ERR_INVALID_ARG
     sc[0].grad_fluence = None
-    for bad in (0x1, 0x300, 0x400):  # unknown, or both kernel variants forced
+    for bad in (0x1, 0x300, 0x700, 0x800):  # unknown, or both kernel variants forced
         assert lib.hrc_batch_plan(None, sc, 1, bad, None, ctypes.byref(out)) == \
             HRC_ERR_UNSUPPORTED
     lib.hrc_batch_destroy(None)

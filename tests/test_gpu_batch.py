@@ -1,5 +1,6 @@
-"""The batched persistent launch: bitwise equal to single-scene calls, replayed
-several times, with mixed sizes and forward-only scenes."""
+"""The batched launch (persistent kernel, plus the larger scenes as kernels of
+their own where the autotuner picks that): bitwise equal to single-scene calls,
+replayed several times, with mixed sizes and forward-only scenes."""
 import numpy as np
 import pytest
 import torch
@@ -42,7 +43,8 @@ def _check_against_single(ctx, items):
             assert torch.equal(gs, d["grad_sigma_t"]), f"scene {i} d sigma"
 
 
-@pytest.mark.parametrize("flags", [0, 0x100, 0x200], ids=["autotuned", "full", "dense"])
+@pytest.mark.parametrize("flags", [0, 0x100, 0x200, 0x400],
+                         ids=["autotuned", "full", "dense", "persistent-only"])
 def test_batch_small_mixed_sizes(ctx, flags):
     from paper_2505_02041_amd import Batch
     log(f"batch small mixed, flags {flags:#x}")
@@ -52,6 +54,9 @@ def test_batch_small_mixed_sizes(ctx, flags):
     want = {0x100: 0, 0x200: 1}.get(flags)
     if want is not None:
         assert b.describe()["variant"] == want
+    if flags & 0x400:
+        assert b.describe()["direct_scenes"] == 0
+    log(f"  autotuned: {b.describe()}")
     for rep in range(3):
         for d in items:
             d["fluence"].fill_(float("nan"))
@@ -64,7 +69,8 @@ def test_batch_small_mixed_sizes(ctx, flags):
     del b
 
 
-@pytest.mark.parametrize("flags", [0x100, 0x200], ids=["full", "dense"])
+@pytest.mark.parametrize("flags", [0, 0x500, 0x600],
+                         ids=["autotuned", "full-persistent", "dense-persistent"])
 def test_batch_benchmark_workload_subset(ctx, flags):
     """16 scenes of the 64-scene batch workload (sizes 128..1024), fwd + bwd."""
     from paper_2505_02041_amd import Batch
@@ -72,6 +78,9 @@ def test_batch_benchmark_workload_subset(ctx, flags):
     scenes = config5()[:16]
     items = _make(scenes, lambda i: True)
     b = Batch(items, ctx, flags=flags)
+    log(f"  autotuned: {b.describe()}")
+    if flags & 0x400:
+        assert b.describe()["direct_scenes"] == 0
     b.launch()
     torch.cuda.synchronize()
     _check_against_single(ctx, items)
