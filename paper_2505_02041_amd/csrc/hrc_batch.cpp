@@ -282,7 +282,8 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
         if (!fine) break;
         split(min_direct);
         if (pl.phases.empty()) {  // every scene direct: nothing to tune
-            time_one(min_direct, 0, grids[0] * kBatchQuarters, 1u);
+            const int v = (flags & HRC_FLAG_BATCH_DENSE) ? 1 : 0;
+            time_one(min_direct, v, grids[v] * kBatchQuarters, 1u);
             continue;
         }
         for (int v = 0; v < kPersistentVariants && fine; ++v) {
