@@ -65,7 +65,7 @@ typedef enum {
  * HRC_FLAG_QUADRANTS_{1,2,4} (forward only) choose how many quadrant solves
  * run side by side, each group reusing one set of pyramid buffers: fewer means
  * a smaller working set (it can stay in the 256 MB Infinity Cache) but more,
- * smaller launches.  Without one, the library picks by size.  Results are
+ * smaller launches.  Without one, all four run at once.  Results are
  * bitwise identical for every choice; the workspace size depends on it, so
  * pass the same flags to hrc_workspace_bytes. */
 #define HRC_FLAG_VALIDATE 0x1u

@@ -63,7 +63,7 @@ def test_workspace_sizes_follow_the_memory_analysis(N):
     one = full - 8 * (2 ** N + 1) * S
     fwd_one = one - 8 * (2 + 1.5) * S * S
     for flags, G in ((_lib.HRC_FLAG_QUADRANTS_1, 1), (_lib.HRC_FLAG_QUADRANTS_2, 2),
-                     (_lib.HRC_FLAG_QUADRANTS_4, 4), (0, 2 if N >= 11 else 4)):
+                     (_lib.HRC_FLAG_QUADRANTS_4, 4), (0, 4)):
         st, f, b = _ws(N, flags)
         assert st == HRC_OK
         fwd_min = G * fwd_one + 2 * G * 4 * S * S + 4 * S * S
