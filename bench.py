@@ -115,6 +115,22 @@ def main():
     if args.only_forward:
         print(json.dumps({"ms_per_step": fwd_s * 1e3, "copy_GBps": 2 * nbytes / copy_s / 1e9}))
         return
+    # ---- the method's error: the benchmark scene's fluence against a brute-force
+    # FP64 ray march (4096 directions per pixel) on a 128x128 crop, stored by
+    # tests/golden/make_bruteforce_crop.py ----------------------------------------
+    accuracy = None
+    bf_path = os.path.join(ROOT, "tests", "golden", "bruteforce_1024_crop.npz")
+    if os.path.exists(bf_path):
+        g = np.load(bf_path)
+        r0, r1, c0, c1 = (int(v) for v in g["crop"])
+        ctx.hrc_forward(eps, sig, F)
+        Fc = F[r0:r1, c0:c1].double().cpu().numpy()
+        bf = g["bruteforce"]
+        rms = float(np.sqrt(np.mean((Fc - bf) ** 2)))
+        rms_oracle = float(np.sqrt(np.mean((g["oracle_hrc"] - bf) ** 2)))
+        accuracy = {"rmse_vs_bruteforce": rms, "relative_rmse": rms / float(np.sqrt(np.mean(bf ** 2))),
+                    "oracle_hrc_rmse_vs_bruteforce": rms_oracle,
+                    "crop": [r0, r1, c0, c1], "bruteforce_directions": int(g["directions"])}
     # ---- the cross blur of Eq. 21 after the gather (HRC_FLAG_BLUR) -----------
     fwd_blur_s = timed(lambda: ctx.hrc_forward(eps, sig, F, flags=_lib.HRC_FLAG_BLUR),
                        max(5, args.steps // 2), 2)
@@ -167,6 +183,7 @@ def main():
         "config": {"workload": "hrc_forward 1024x1024, 1 channel: 128 disks, 256 opaque boxes, "
                                "32 thin sigma-100 lines, value-noise fog (seed 3)",
                    "grid": S, "quadrants": 4, "traced_levels": 3, "parallelism": "single GPU"},
+        "accuracy_1024_crop": accuracy,
         "fwd_blur_ms": fwd_blur_s * 1e3,
         "blur_overhead_us": (fwd_blur_s - fwd_s) * 1e6,
         "fwd_environment_ms": fwd_env_s * 1e3,

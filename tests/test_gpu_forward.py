@@ -140,3 +140,27 @@ def test_forward_quadrant_groupings_are_bitwise_equal(ctx, S):
     torch.cuda.synchronize()
     for o in outs[1:]:
         assert torch.equal(o, outs[0])
+
+
+def test_forward_benchmark_scene_error_against_bruteforce(ctx):
+    """The benchmark scene's error report: on the 128x128 crop stored by
+    tests/golden/make_bruteforce_crop.py (a brute-force FP64 ray march of
+    Eq. 1-3 with 4096 directions per pixel, and the FP64 oracle's HRC fluence),
+    the GPU fluence matches the oracle and so carries the method's own
+    approximation error, no more."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "bruteforce_1024_crop.npz")
+    g = np.load(path)
+    r0, r1, c0, c1 = (int(v) for v in g["crop"])
+    sc = config3()
+    F = ctx.hrc_forward(to_dev(sc.eps), to_dev(sc.sigma))
+    torch.cuda.synchronize()
+    Fc = F[r0:r1, c0:c1].cpu().numpy().astype(np.float64)
+    assert_forward_close(Fc, g["oracle_hrc"], "1024 crop vs stored oracle")
+    bf = g["bruteforce"]
+    rms_gpu = float(np.sqrt(np.mean((Fc - bf) ** 2)))
+    rms_oracle = float(np.sqrt(np.mean((g["oracle_hrc"] - bf) ** 2)))
+    log(f"RMSE vs brute force on the crop: GPU {rms_gpu:.5g}, oracle {rms_oracle:.5g}, "
+        f"relative {rms_gpu / float(np.sqrt(np.mean(bf ** 2))):.4f}")
+    assert abs(rms_gpu - rms_oracle) <= 1e-3 * rms_oracle
