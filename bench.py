@@ -131,6 +131,23 @@ def main():
         accuracy = {"rmse_vs_bruteforce": rms, "relative_rmse": rms / float(np.sqrt(np.mean(bf ** 2))),
                     "oracle_hrc_rmse_vs_bruteforce": rms_oracle,
                     "crop": [r0, r1, c0, c1], "bruteforce_directions": int(g["directions"])}
+    # ---- the forward at the other configurations' sizes (64^2, 256^2, 512^2:
+    # the small and differentiable scenes; 2048^2, 4096^2 with the benchmark
+    # scene's generator and feature counts: the method's time does not depend
+    # on the scene) ------------------------------------------------------------
+    from scenes import config1, config2, config4, scene_like_512
+    fwd_by_size = {}
+    for name, cfg in (("64", config1), ("256", config4), ("512", config2),
+                      ("2048", lambda: scene_like_512(2048, 7, 128, 256)),
+                      ("4096", lambda: scene_like_512(4096, 7, 128, 256))):
+        c = cfg()
+        e2 = torch.from_numpy(c.eps).to(dev)
+        s2 = torch.from_numpy(c.sigma).to(dev)
+        F2 = torch.empty_like(e2)
+        t = timed(lambda: ctx.hrc_forward(e2, s2, F2), 20 if c.eps.shape[0] >= 2048 else 50, 3)
+        fwd_by_size[name] = {"ms": t * 1e3, "mpixel_per_s": c.eps.size / t / 1e6}
+        del e2, s2, F2
+    ctx.release_workspaces()
     # ---- the cross blur of Eq. 21 after the gather (HRC_FLAG_BLUR) -----------
     fwd_blur_s = timed(lambda: ctx.hrc_forward(eps, sig, F, flags=_lib.HRC_FLAG_BLUR),
                        max(5, args.steps // 2), 2)
@@ -184,6 +201,7 @@ def main():
                                "32 thin sigma-100 lines, value-noise fog (seed 3)",
                    "grid": S, "quadrants": 4, "traced_levels": 3, "parallelism": "single GPU"},
         "accuracy_1024_crop": accuracy,
+        "fwd_by_size": fwd_by_size,
         "fwd_blur_ms": fwd_blur_s * 1e3,
         "blur_overhead_us": (fwd_blur_s - fwd_s) * 1e6,
         "fwd_environment_ms": fwd_env_s * 1e3,
@@ -264,6 +282,18 @@ def main():
                                "sample": f"{frames} full 1024x1024 forward frames of the same "
                                          f"scene, FP64 NumPy, single thread, {el:.1f} s",
                                "host_cpus": os.cpu_count()}
+        # the oracle on the smaller configurations too (median of 3 frames)
+        from scenes import config1, config2, config4
+        by_size = {}
+        for name, cfg in (("64x64", config1), ("256x256", config4), ("512x512", config2)):
+            c = cfg()
+            ts = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                oracle.fluence(c.eps, c.sigma)
+                ts.append(time.perf_counter() - t0)
+            by_size[name] = sorted(ts)[1] * 1e3
+        out["cpu_baseline"]["ms_per_frame_by_size"] = by_size
     print(json.dumps(out), flush=True)
 
 
