@@ -862,12 +862,14 @@ __device__ __forceinline__ float cell_dphi(float tau) {
 // Pixel p receives piece j of direction k of level n from the probe
 // p - (du_j, dw_j), and that probe exists only when u - du_j is a multiple of
 // 2^n: for each residue of u mod 2^n exactly two of the 2^(n+1) pieces qualify.
-// Each wave therefore takes the 64 pixels of one residue class (in the frame
-// of the quadrant), so every test below is uniform over the wave, refolds the
-// two rays per direction from the interval tile in LDS (pieces relative to the
-// pixel stay within 4 pixels, so the tile needs a 4-pixel halo), and adds
-// dLoss/dL_j d L_j/d(eps, sigma) + dLoss/dT_j d T_j/d(eps, sigma).  The four
-// quadrants' partial sums meet in LDS and are added in a fixed order.
+// Each wave therefore takes 64 pixels of one residue class of the frame u, so
+// every test below is uniform over the wave, and refolds the two rays per
+// direction from the interval tile in LDS (pieces relative to the pixel stay
+// within 4 pixels, so the tile needs a 4-pixel halo).  Piece j adds
+// dLoss/dL_j dL_j/d(eps, sigma) + dLoss/dT_j dT_j/d(eps, sigma), and the cell
+// derivatives depend only on the pixel and the piece's half length, so each
+// pixel sums dLoss/dL_j and dLoss/dT_j per half length over every ray of the
+// four quadrants and applies the cell derivatives once at the end.
 constexpr int kAdjTile = 16, kAdjHalo = 4;
 constexpr int kAdjSpan = kAdjTile + 2 * kAdjHalo;     // 24
 constexpr int kAdjPitch = kAdjSpan + 1;
@@ -914,21 +916,42 @@ struct CellDer {
     }
 };
 
-// Direction k (uniform over the wave) of level n: its contribution to pixel
-// (u, w), whose frame u has residue rho modulo 2^n, for directions whose half
-// pieces have length index L.  The interval tile in LDS is laid out in the
-// quadrant's frame (u along a row, w across rows), so with n, rho and L known
-// at compile time every piece offset from the pixel is a scalar (ivp points H
-// cells before the pixel in u and in w, so the offsets are non-negative).
-// The two rays that put a piece on the pixel (their dLoss/dT loaded first) are
-// each refolded around that piece.  Rays whose probe lies outside the grid
-// add 0.
-template <int n, int rho, int L>
-__device__ __forceinline__ void seed_adj_dir(int k, const float2 *dTq, int S, int un, int w,
-                                             int lane_idx, const float2 *ivp, float le,
-                                             float ls, float ts, float &ae, float &as) {
+// The interval tile stays in image orientation.  The LDS offset of a frame
+// displacement (du, dw) in quadrant Q, from a pointer H rows and H columns
+// before the pixel, follows the frame maps +x (u, w) = (c, r), -x (S-1-c, r),
+// +y (r, c), -y (S-1-r, c).
+template <int Q>
+__host__ __device__ constexpr int adj_lds_off(int du, int dw) {
+    return Q == 0   ? (kAdjHalo + dw) * kAdjPitch + kAdjHalo + du
+           : Q == 1 ? (kAdjHalo + dw) * kAdjPitch + kAdjHalo - du
+           : Q == 2 ? (kAdjHalo + du) * kAdjPitch + kAdjHalo + dw
+                    : (kAdjHalo - du) * kAdjPitch + kAdjHalo + dw;
+}
+
+// dLoss/dL_j and dLoss/dT_j of the pieces on one pixel, summed per half
+// length index (0: 1/2, 1: sqrt(2)/2, 2: sqrt(5)/4).
+struct AdjSums {
+    float dl0 = 0.f, dl1 = 0.f, dl2 = 0.f;
+    float dt0 = 0.f, dt1 = 0.f, dt2 = 0.f;
+    template <int L>
+    __device__ __forceinline__ void add(float dl, float dt) {
+        if (L == 0) { dl0 += dl; dt0 += dt; }
+        else if (L == 1) { dl1 += dl; dt1 += dt; }
+        else { dl2 += dl; dt2 += dt; }
+    }
+};
+
+// Direction k of level n in quadrant Q for a pixel at frame (u, w) whose u has
+// residue rho modulo 2^n.  With all four known at compile time every piece
+// offset in the tile is an immediate.  The two rays that put a piece on the
+// pixel (their dLoss/dT loaded first) are each refolded around that piece.
+// Rays whose probe lies outside the grid add 0.
+template <int Q, int n, int rho, int k>
+__device__ __forceinline__ void seed_adj_dir(const float2 *dTq, int S, int un, int w,
+                                             int lane_idx, const float2 *ivp, AdjSums &sum) {
     constexpr int dirs = (1 << n) + 1, pieces = 2 << n;
-    constexpr int P = kAdjPitch, plane = kAdjSpan * kAdjPitch, H = kAdjHalo;
+    constexpr int L = piece_len(n, k);
+    constexpr int plane = kAdjSpan * kAdjPitch;
     float2 g[2];
 #pragma unroll
     for (int which = 0; which < 2; ++which) {
@@ -955,74 +978,77 @@ __device__ __forceinline__ void seed_adj_dir(int k, const float2 *dTq, int S, in
 #pragma unroll
         for (int i = pieces - 1; i >= 0; --i) {
             if (i == j) continue;
-            const float2 c = ivp[L * plane + (H + piece_du(i) - piece_du(j)) +
-                                 (H + piece_dw(n, k, i) - piece_dw(n, k, j)) * P];
+            const float2 c = ivp[L * plane + adj_lds_off<Q>(piece_du(i) - piece_du(j),
+                                                             piece_dw(n, k, i) - piece_dw(n, k, j))];
             if (i > j) suf = merge(c, suf);
             else pre *= c.y;
         }
-        const float dl = g[which].x * pre;                                   // dLoss/dL_j
-        const float dt = pre * fmaf(g[which].x, suf.x, g[which].y * suf.y);  // dLoss/dT_j
-        ae = fmaf(dl, le, ae);
-        as = fmaf(dl, ls, fmaf(dt, ts, as));
+        sum.add<L>(g[which].x * pre,                                     // dLoss/dL_j
+                   pre * fmaf(g[which].x, suf.x, g[which].y * suf.y));   // dLoss/dT_j
     }
 }
 
-// Level n: the diagonals k = 0, 2^n (length sqrt(2)/2), the axis k = 2^(n-1)
-// (1/2) and, at n = 2, k = 1, 3 (sqrt(5)/4).
-template <int n, int rho>
+// Level n: the diagonals k = 0, 2^n, the axis k = 2^(n-1) and, at n = 2,
+// k = 1, 3.
+template <int Q, int n, int rho>
 __device__ __forceinline__ void seed_adj_level(const float2 *dTq, int S, int u, int w,
-                                               const float2 *ivp, const CellDer &der,
-                                               float &ae, float &as) {
+                                               const float2 *ivp, AdjSums &sum) {
     constexpr int dirs = (1 << n) + 1;
     const int un = u >> n;
     const int lane_idx = un * dirs * S + w;
-#pragma unroll 1
-    for (int kk = 0; kk < 2; ++kk)
-        seed_adj_dir<n, rho, 1>(kk << n, dTq, S, un, w, lane_idx, ivp, der.le1, der.ls1,
-                                der.ts1, ae, as);
-    if (n >= 1)
-        seed_adj_dir<n, rho, 0>(n >= 1 ? 1 << (n - 1) : 0, dTq, S, un, w, lane_idx, ivp,
-                                der.le0, der.ls0, der.ts0, ae, as);
-    if (n == 2) {
-#pragma unroll 1
-        for (int kk = 1; kk < 4; kk += 2)
-            seed_adj_dir<n, rho, 2>(kk, dTq, S, un, w, lane_idx, ivp, der.le2, der.ls2, der.ts2,
-                                    ae, as);
+    seed_adj_dir<Q, n, rho, 0>(dTq, S, un, w, lane_idx, ivp, sum);
+    seed_adj_dir<Q, n, rho, (1 << n)>(dTq, S, un, w, lane_idx, ivp, sum);
+    if constexpr (n >= 1) seed_adj_dir<Q, n, rho, (1 << n) / 2>(dTq, S, un, w, lane_idx, ivp, sum);
+    if constexpr (n == 2) {
+        seed_adj_dir<Q, n, rho, 1>(dTq, S, un, w, lane_idx, ivp, sum);
+        seed_adj_dir<Q, n, rho, 3>(dTq, S, un, w, lane_idx, ivp, sum);
     }
 }
 
-// All three traced levels for pixels whose frame u is rho modulo 4.
-template <int rho>
-__device__ __forceinline__ void seed_adj_levels(const float2 *dT0, const float2 *dT1,
-                                                const float2 *dT2, int S, int u, int w,
-                                                const float2 *ivp, const CellDer &der,
-                                                float &ae, float &as) {
-    seed_adj_level<0, 0>(dT0, S, u, w, ivp, der, ae, as);
-    seed_adj_level<1, rho & 1>(dT1, S, u, w, ivp, der, ae, as);
-    seed_adj_level<2, rho>(dT2, S, u, w, ivp, der, ae, as);
+// All three traced levels of quadrant Q for a pixel whose frame u is rho
+// modulo 4.
+template <int Q, int rho>
+__device__ __forceinline__ void seed_adj_levels(const SeedAdjArgs &a, int u, int w,
+                                                const float2 *ivp, AdjSums &sum) {
+    const int S = 1 << a.N;
+    seed_adj_level<Q, 0, 0>(a.dT0 + (size_t)Q * a.e0, S, u, w, ivp, sum);
+    seed_adj_level<Q, 1, rho & 1>(a.dT1 + (size_t)Q * a.e1, S, u, w, ivp, sum);
+    seed_adj_level<Q, 2, rho>(a.dT2 + (size_t)Q * a.e2, S, u, w, ivp, sum);
 }
 
-// per-pixel accumulators, rows padded so that a column of the tile (the
-// lanes of a wave in quadrants 0 and 1) spans distinct banks
+// Quadrant Q for the pixel at image (r, c) in wave v.  Tile origins are
+// multiples of 16 and S of 8, so the frame u of the wave's pixels is v modulo
+// 4 in quadrants +x and +y and 3 - v in -x and -y.
+template <int Q>
+__device__ __forceinline__ void seed_adj_quadrant(const SeedAdjArgs &a, int v, int r, int c,
+                                                  const float2 *ivp, AdjSums &sum) {
+    const int S = 1 << a.N;
+    const int u = Q == 0 ? c : Q == 1 ? S - 1 - c : Q == 2 ? r : S - 1 - r;
+    const int w = Q < 2 ? r : c;
+    switch ((Q == 0 || Q == 2) ? v : 3 - v) {
+        case 0: seed_adj_levels<Q, 0>(a, u, w, ivp, sum); break;
+        case 1: seed_adj_levels<Q, 1>(a, u, w, ivp, sum); break;
+        case 2: seed_adj_levels<Q, 2>(a, u, w, ivp, sum); break;
+        default: seed_adj_levels<Q, 3>(a, u, w, ivp, sum); break;
+    }
+}
+
+// The quadrants +x and -x and the quadrants +y and -y of a pixel are summed by
+// different threads; the first pair's six sums meet the second's in LDS (over
+// the interval tile, once it is no longer read), rows padded against bank
+// conflicts.
 constexpr int kAccPitch = kAdjTile + 1;
-constexpr int kSeedAdjLds = 3 * kAdjSpan * kAdjPitch * 8 + kAdjTile * kAccPitch * 8;
-
-// Image-local (row, column) of the frame-local (ul, wl) of the tile in quadrant
-// q: +x (c, r), -x (S-1-c, r), +y (r, c), -y (S-1-r, c), tile-relative.
-__device__ __forceinline__ void adj_frame_to_image(int q, int ul, int wl, int &rl, int &cl) {
-    if (q < 2) { rl = wl; cl = q == 0 ? ul : kAdjTile - 1 - ul; }
-    else { cl = wl; rl = q == 2 ? ul : kAdjTile - 1 - ul; }
-}
+constexpr int kAccPlane = kAdjTile * kAccPitch;
+constexpr int kSeedAdjLds = 3 * kAdjSpan * kAdjPitch * 8;
+static_assert(6 * kAccPlane * 4 <= kSeedAdjLds, "partial sums fit over the interval tile");
 
 __device__ __forceinline__ void body_seed_adj(const SeedAdjArgs &a, unsigned tile, char *lds) {
     constexpr int P = kAdjPitch, plane = kAdjSpan * kAdjPitch, H = kAdjHalo;
     float2 *iv = reinterpret_cast<float2 *>(lds);
-    float2 *acc = iv + 3 * plane;  // [16][kAccPitch] running (d eps, d sigma) per pixel
     const int S = 1 << a.N;
     const int tiles = (S + kAdjTile - 1) / kAdjTile;
     const int r0 = (int)(tile / tiles) * kAdjTile, c0 = (int)(tile % tiles) * kAdjTile;
-    // the tile and its halo as three half-length intervals per cell, first in
-    // image orientation (the frame of quadrant 0)
+    // the tile and its halo as three half-length intervals per cell
     for (int i = ltid(); i < kAdjSpan * kAdjSpan; i += 256) {
         const int lr = i / kAdjSpan, lc = i % kAdjSpan;
         const int r = r0 - H + lr, c = c0 - H + lc;
@@ -1036,85 +1062,51 @@ __device__ __forceinline__ void body_seed_adj(const SeedAdjArgs &a, unsigned til
         iv[plane + l] = cell_interval(e, g, kH2);
         iv[2 * plane + l] = cell_interval(e, g, kQ5);
     }
-    acc[(ltid() / kAdjTile) * kAccPitch + ltid() % kAdjTile] = make_float2(0.f, 0.f);
     __syncthreads();
-    // wave v takes the frame rows u_l = v, v+4, v+8, v+12 (one residue of u mod 4)
     const int v = ltid() >> 6, lane = ltid() & 63;
-    const int u_l = v + 4 * (lane >> 4), w_l = lane & 15;
-    // this pixel's cell in the frame layout is ivp[H * P + H]: every piece
-    // offset from it is then a non-negative immediate
-    const float2 *ivp = iv + w_l * P + u_l;
-    constexpr int kPer = (3 * kAdjSpan * kAdjSpan + 255) / 256;
-    for (int q = 0; q < 4; ++q) {
-        if (q > 0) {
-            // re-lay the tile from quadrant q-1's frame into quadrant q's: read
-            // every destination cell's source into registers, then write
-            float2 tmp[kPer];
-            // the per-element indices are recomputed for each quadrant rather
-            // than kept live across the quadrant loop (register pressure)
-            int i0 = ltid();
-            __asm__ volatile("" : "+v"(i0));
-#pragma unroll
-            for (int t = 0; t < kPer; ++t) {
-                const int i = i0 + 256 * t;
-                if (i < 3 * kAdjSpan * kAdjSpan) {
-                    const int Lh = i / (kAdjSpan * kAdjSpan), rem = i % (kAdjSpan * kAdjSpan);
-                    const int ul = rem % kAdjSpan - H, wl = rem / kAdjSpan - H;
-                    int rl, cl;
-                    adj_frame_to_image(q, ul, wl, rl, cl);
-                    // frame-local of the same cell in quadrant q-1
-                    int ps, pw2;
-                    if (q == 1) { ps = cl; pw2 = rl; }                    // from q = 0
-                    else if (q == 2) { ps = kAdjTile - 1 - cl; pw2 = rl; }  // from q = 1
-                    else { ps = rl; pw2 = cl; }                           // from q = 2
-                    tmp[t] = iv[Lh * plane + (pw2 + H) * P + ps + H];
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int t = 0; t < kPer; ++t) {
-                const int i = i0 + 256 * t;
-                if (i < 3 * kAdjSpan * kAdjSpan) {
-                    const int Lh = i / (kAdjSpan * kAdjSpan), rem = i % (kAdjSpan * kAdjSpan);
-                    iv[Lh * plane + (rem / kAdjSpan) * P + rem % kAdjSpan] = tmp[t];
-                }
-            }
-            __syncthreads();
-        }
-        const int u_lo = q == 0 ? c0 : q == 1 ? S - kAdjTile - c0 : q == 2 ? r0 : S - kAdjTile - r0;
-        const int w_lo = q < 2 ? r0 : c0;
-        int pr, pc;  // image pixel (tile-local) of frame pixel (u_l, w_l)
-        adj_frame_to_image(q, u_l, w_l, pr, pc);
-        const int u = u_lo + u_l, w = w_lo + w_l;
-        float ae = 0.f, as = 0.f;
-        if (u >= 0 && u < S && w < S) {
-            // d(L, T)/d(eps, sigma) of this pixel for the three half lengths
-            const CellDer d(a.eps[(size_t)(r0 + pr) * S + c0 + pc],
-                            a.sig[(size_t)(r0 + pr) * S + c0 + pc]);
-            const float2 *dT0 = a.dT0 + (size_t)q * a.e0;
-            const float2 *dT1 = a.dT1 + (size_t)q * a.e1;
-            const float2 *dT2 = a.dT2 + (size_t)q * a.e2;
-            // u_lo is a multiple of 4 (tile origins are multiples of 16 and S
-            // of 8), so the residue of u mod 4 is the wave index v
-            switch (v) {
-                case 0: seed_adj_levels<0>(dT0, dT1, dT2, S, u, w, ivp, d, ae, as); break;
-                case 1: seed_adj_levels<1>(dT0, dT1, dT2, S, u, w, ivp, d, ae, as); break;
-                case 2: seed_adj_levels<2>(dT0, dT1, dT2, S, u, w, ivp, d, ae, as); break;
-                default: seed_adj_levels<3>(dT0, dT1, dT2, S, u, w, ivp, d, ae, as); break;
-            }
-        }
-        // one writer per pixel and quadrant; quadrants added in order 0..3
-        float2 &t = acc[pr * kAccPitch + pc];
-        t = make_float2(t.x + ae, t.y + as);
-        __syncthreads();
+    const int i4 = v + 4 * (lane >> 4), i16 = lane & 15;
+    // quadrants +x and -x (frame u along the row): wave v takes the tile
+    // columns v, v+4, v+8, v+12, pixel (i16, i4)
+    AdjSums sa;
+    if (r0 + i16 < S && c0 + i4 < S) {
+        const float2 *ivp = iv + i16 * P + i4;  // the pixel's cell is ivp[H * P + H]
+        seed_adj_quadrant<0>(a, v, r0 + i16, c0 + i4, ivp, sa);
+        seed_adj_quadrant<1>(a, v, r0 + i16, c0 + i4, ivp, sa);
     }
-    const int r = r0 + ltid() / kAdjTile, c = c0 + ltid() % kAdjTile;
-    if (r < S && c < S) {
-        const float2 t = acc[(ltid() / kAdjTile) * kAccPitch + ltid() % kAdjTile];
-        a.dE[(size_t)r * S + c] = t.x;
-        a.dS[(size_t)r * S + c] = t.y;
+    // quadrants +y and -y (frame u down the column): wave v takes the tile
+    // rows v, v+4, v+8, v+12, pixel (i4, i16)
+    const int r = r0 + i4, c = c0 + i16;
+    const bool in = r < S && c < S;
+    AdjSums sb;
+    if (in) {
+        const float2 *ivp = iv + i4 * P + i16;
+        seed_adj_quadrant<2>(a, v, r, c, ivp, sb);
+        seed_adj_quadrant<3>(a, v, r, c, ivp, sb);
     }
     __syncthreads();
+    float *x = reinterpret_cast<float *>(lds);  // [6][16][kAccPitch]
+    const int la = i16 * kAccPitch + i4;
+    x[la] = sa.dl0;
+    x[kAccPlane + la] = sa.dl1;
+    x[2 * kAccPlane + la] = sa.dl2;
+    x[3 * kAccPlane + la] = sa.dt0;
+    x[4 * kAccPlane + la] = sa.dt1;
+    x[5 * kAccPlane + la] = sa.dt2;
+    __syncthreads();
+    if (in) {
+        // each pixel adds the two pairs of quadrants and applies its cell
+        // derivatives
+        const int lb = i4 * kAccPitch + i16;
+        const float dl0 = x[lb] + sb.dl0, dl1 = x[kAccPlane + lb] + sb.dl1;
+        const float dl2 = x[2 * kAccPlane + lb] + sb.dl2, dt0 = x[3 * kAccPlane + lb] + sb.dt0;
+        const float dt1 = x[4 * kAccPlane + lb] + sb.dt1, dt2 = x[5 * kAccPlane + lb] + sb.dt2;
+        const CellDer d(a.eps[(size_t)r * S + c], a.sig[(size_t)r * S + c]);
+        a.dE[(size_t)r * S + c] = fmaf(dl2, d.le2, fmaf(dl1, d.le1, dl0 * d.le0));
+        a.dS[(size_t)r * S + c] =
+            fmaf(dt2, d.ts2, fmaf(dl2, d.ls2, fmaf(dt1, d.ts1, fmaf(dl1, d.ls1,
+                 fmaf(dt0, d.ts0, dl0 * d.ls0)))));
+    }
+    __syncthreads();  // the persistent kernel reuses the LDS for its next tile
 }
 
 // Cross blur of Eq. 21 on 16x16 pixel tiles: each pixel averages itself
