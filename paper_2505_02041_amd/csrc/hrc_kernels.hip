@@ -941,14 +941,25 @@ struct AdjSums {
     }
 };
 
+// dLoss/dT of one quadrant's traced level as a buffer resource: a lane whose
+// probe lies outside the grid reads at an offset past the end, which the
+// hardware bounds check returns as zero, so the load needs neither a clamped
+// address nor a select afterwards.
+constexpr unsigned kBufferWord3 = 0x00020000u;  // raw 32-bit data, bounds checked
+constexpr unsigned kOutside = 0x80000000u;      // beyond every level's byte count
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t dT_resource(const float2 *p, size_t entries) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float2 *>(p), (short)0,
+                                             (int)(entries * sizeof(float2)), (int)kBufferWord3);
+}
+
 // Direction k of level n in quadrant Q for a pixel at frame (u, w) whose u has
 // residue rho modulo 2^n.  With all four known at compile time every piece
 // offset in the tile is an immediate.  The two rays that put a piece on the
 // pixel (their dLoss/dT loaded first) are each refolded around that piece.
 // Rays whose probe lies outside the grid add 0.
 template <int Q, int n, int rho, int k>
-__device__ __forceinline__ void seed_adj_dir(const float2 *dTq, int S, int un, int w,
-                                             int lane_idx, const float2 *ivp, AdjSums &sum) {
+__device__ __forceinline__ void seed_adj_dir(__amdgpu_buffer_rsrc_t dTq, int S, int un, int w,
+                                             int lane_off, const float2 *ivp, AdjSums &sum) {
     constexpr int dirs = (1 << n) + 1, pieces = 2 << n;
     constexpr int L = piece_len(n, k);
     constexpr int plane = kAdjSpan * kAdjPitch;
@@ -961,14 +972,11 @@ __device__ __forceinline__ void seed_adj_dir(const float2 *dTq, int S, int un, i
         const int dwj = piece_dw(n, k, j);
         const int pw = w - dwj;
         const bool ok = un >= cj && (unsigned)pw < (unsigned)S;
-        // always load (the index stays in the array) and clear the bits of a
-        // discarded value: no branch around the load.  lane_idx = (u >> n)
-        // dirs S + w; the rest is uniform.
-        const unsigned idx = ok ? (unsigned)(lane_idx + (k - cj * dirs) * S - dwj) : 0u;
-        const float2 v = dTq[idx];
-        const unsigned keep = ok ? 0xffffffffu : 0u;
-        g[which] = make_float2(__uint_as_float(__float_as_uint(v.x) & keep),
-                               __uint_as_float(__float_as_uint(v.y) & keep));
+        // lane_off = ((u >> n) dirs S + w) * 8; the rest is uniform
+        const unsigned off =
+            ok ? (unsigned)(lane_off + ((k - cj * dirs) * S - dwj) * (int)sizeof(float2)) : kOutside;
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(dTq, off, 0, 0);
+        g[which] = make_float2(__uint_as_float(v[0]), __uint_as_float(v[1]));
     }
 #pragma unroll
     for (int which = 0; which < 2; ++which) {
@@ -991,17 +999,17 @@ __device__ __forceinline__ void seed_adj_dir(const float2 *dTq, int S, int un, i
 // Level n: the diagonals k = 0, 2^n, the axis k = 2^(n-1) and, at n = 2,
 // k = 1, 3.
 template <int Q, int n, int rho>
-__device__ __forceinline__ void seed_adj_level(const float2 *dTq, int S, int u, int w,
+__device__ __forceinline__ void seed_adj_level(__amdgpu_buffer_rsrc_t dTq, int S, int u, int w,
                                                const float2 *ivp, AdjSums &sum) {
     constexpr int dirs = (1 << n) + 1;
     const int un = u >> n;
-    const int lane_idx = un * dirs * S + w;
-    seed_adj_dir<Q, n, rho, 0>(dTq, S, un, w, lane_idx, ivp, sum);
-    seed_adj_dir<Q, n, rho, (1 << n)>(dTq, S, un, w, lane_idx, ivp, sum);
-    if constexpr (n >= 1) seed_adj_dir<Q, n, rho, (1 << n) / 2>(dTq, S, un, w, lane_idx, ivp, sum);
+    const int lane_off = (un * dirs * S + w) * (int)sizeof(float2);
+    seed_adj_dir<Q, n, rho, 0>(dTq, S, un, w, lane_off, ivp, sum);
+    seed_adj_dir<Q, n, rho, (1 << n)>(dTq, S, un, w, lane_off, ivp, sum);
+    if constexpr (n >= 1) seed_adj_dir<Q, n, rho, (1 << n) / 2>(dTq, S, un, w, lane_off, ivp, sum);
     if constexpr (n == 2) {
-        seed_adj_dir<Q, n, rho, 1>(dTq, S, un, w, lane_idx, ivp, sum);
-        seed_adj_dir<Q, n, rho, 3>(dTq, S, un, w, lane_idx, ivp, sum);
+        seed_adj_dir<Q, n, rho, 1>(dTq, S, un, w, lane_off, ivp, sum);
+        seed_adj_dir<Q, n, rho, 3>(dTq, S, un, w, lane_off, ivp, sum);
     }
 }
 
@@ -1011,9 +1019,9 @@ template <int Q, int rho>
 __device__ __forceinline__ void seed_adj_levels(const SeedAdjArgs &a, int u, int w,
                                                 const float2 *ivp, AdjSums &sum) {
     const int S = 1 << a.N;
-    seed_adj_level<Q, 0, 0>(a.dT0 + (size_t)Q * a.e0, S, u, w, ivp, sum);
-    seed_adj_level<Q, 1, rho & 1>(a.dT1 + (size_t)Q * a.e1, S, u, w, ivp, sum);
-    seed_adj_level<Q, 2, rho>(a.dT2 + (size_t)Q * a.e2, S, u, w, ivp, sum);
+    seed_adj_level<Q, 0, 0>(dT_resource(a.dT0 + (size_t)Q * a.e0, a.e0), S, u, w, ivp, sum);
+    seed_adj_level<Q, 1, rho & 1>(dT_resource(a.dT1 + (size_t)Q * a.e1, a.e1), S, u, w, ivp, sum);
+    seed_adj_level<Q, 2, rho>(dT_resource(a.dT2 + (size_t)Q * a.e2, a.e2), S, u, w, ivp, sum);
 }
 
 // Quadrant Q for the pixel at image (r, c) in wave v.  Tile origins are
