@@ -155,6 +155,16 @@ def main():
     ctx.set_environment([1.0 + 0.5 * np.sin(2 * np.pi * k / 64) for k in range(64)])
     fwd_env_s = timed(lambda: ctx.hrc_forward(eps, sig, F), max(5, args.steps // 2), 2)
     ctx.set_environment(None)
+    # ---- the paper's 16-bit interval storage (Section 5; HRC_FLAG_HALF_INTERVALS):
+    # a separate, reduced-precision line, never the metric -----------------------
+    Fh = torch.empty_like(eps)
+    fwd_half_s = timed(lambda: ctx.hrc_forward(eps, sig, Fh, flags=_lib.HRC_FLAG_HALF_INTERVALS),
+                       args.steps, 3)
+    ctx.hrc_forward(eps, sig, F)
+    big = F.abs() > 1e-3 * F.abs().max()
+    half_dev = float(((Fh - F).abs() / F.abs().clamp_min(1e-30))[big].max())
+    del Fh
+    ctx.release_workspaces()
     # ---- six diffuse bounces (Section 4.2; Fig. 14 converges after 6) ---------
     alb = torch.full_like(eps, 0.5)
     fwd_6b_s = timed(lambda: ctx.hrc_multibounce_forward(eps, sig, alb, 6, out=F),
@@ -206,6 +216,12 @@ def main():
         "blur_overhead_us": (fwd_blur_s - fwd_s) * 1e6,
         "fwd_environment_ms": fwd_env_s * 1e3,
         "fwd_6_bounces_ms": fwd_6b_s * 1e3,
+        "fwd_half_intervals": {
+            "ms": fwd_half_s * 1e3, "mpixel_per_s": S * S / fwd_half_s / 1e6,
+            "model_GBps": forward_bytes(N, 4) / fwd_half_s / 1e9,
+            "max_rel_dev_vs_f32": half_dev,
+            "bound": N * 2.0 ** -11,
+            "note": "intervals stored as 16-bit halves (Section 5); reduced precision, not the metric"},
         "fwd_bwd_mpixel_per_s": S * S / fb_s / 1e6,
         "fwd_bwd_ms": fb_s * 1e3,
         "fwd_model_GBps": step_bytes / fwd_s / 1e9,

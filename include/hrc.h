@@ -47,7 +47,7 @@ typedef enum {
     HRC_ERR_SHAPE = -2,        /* log2_size outside [HRC_MIN_LOG2, HRC_MAX_LOG2] */
     HRC_ERR_WORKSPACE = -3,    /* workspace smaller than hrc_workspace_bytes */
     HRC_ERR_HIP = -4,          /* a HIP runtime call or kernel launch failed */
-    HRC_ERR_UNSUPPORTED = -5,  /* unknown flag bits */
+    HRC_ERR_UNSUPPORTED = -5,  /* unknown flag bits, or a flag the call does not take */
     HRC_ERR_INPUT = -6         /* HRC_FLAG_VALIDATE found a negative or non-finite input */
 } hrc_status;
 
@@ -70,6 +70,16 @@ typedef enum {
  * pass the same flags to hrc_workspace_bytes. */
 #define HRC_FLAG_VALIDATE 0x1u
 #define HRC_FLAG_BLUR 0x2u
+/* HRC_FLAG_HALF_INTERVALS (hrc_forward and hrc_workspace_bytes only): the
+ * interval pyramid is stored as IEEE half floats, L and T in 16 bits each, as
+ * the paper stores it (Section 5), which halves its traffic; every value is
+ * still computed in FP32 and rounded to nearest once when stored.  Each
+ * stored level adds a relative rounding of at most 2^-11 to what depends on
+ * it, so the fluence stays within a relative N * 2^-11 of the FP32 result
+ * (about 5e-3 at S = 1024) instead of 1e-4.  L above 65504 (the half
+ * range) becomes infinite: the caller keeps the radiance along any ray below
+ * it.  hrc_backward, the bounce calls and the batch reject the flag. */
+#define HRC_FLAG_HALF_INTERVALS 0x4u
 #define HRC_FLAG_QUADRANTS_1 0x10u
 #define HRC_FLAG_QUADRANTS_2 0x20u
 #define HRC_FLAG_QUADRANTS_4 0x30u
@@ -120,7 +130,9 @@ const char *hrc_status_string(hrc_status s);
  * interval pyramid of the four quadrants (Section 4.3.2: (N+3-2^-N) S^2
  * entries each) plus two cascade levels; backward additionally keeps every
  * cascade level, their adjoints and the adjoint pyramid.  Either output
- * pointer may be NULL.  Pure host function. */
+ * pointer may be NULL.  Pure host function.  The forward size depends on
+ * HRC_FLAG_QUADRANTS_* and HRC_FLAG_HALF_INTERVALS; the backward size on
+ * neither. */
 hrc_status hrc_workspace_bytes(int log2_size, unsigned flags,
                                size_t *forward_bytes, size_t *backward_bytes);
 

@@ -13,7 +13,7 @@
 
 namespace hrc {
 
-Layout make_layout(int N, bool backward, int group) {
+Layout make_layout(int N, bool backward, int group, bool half) {
     Layout L;
     L.N = N;
     L.S = size_t(1) << N;
@@ -22,9 +22,10 @@ Layout make_layout(int N, bool backward, int group) {
     size_t off = 256;  // first 256 bytes: scratch flag for HRC_FLAG_VALIDATE
     // the forward's tail folds T_0 and T_1 itself (only the reverse stores
     // them), and the merge down builds what it reads of T_N itself
+    const size_t iv_bytes = (half && !backward) ? 2 * sizeof(uint16_t) : sizeof(float2);
     for (int n = backward ? 0 : kTracedLevels - 1; n < N; ++n) {
         L.t_level[n] = off;
-        off += align256(L.group * t_level_entries(N, n) * sizeof(float2));
+        off += align256(L.group * t_level_entries(N, n) * iv_bytes);
     }
     L.r_count = backward ? N : 2;
     for (int i = 0; i < L.r_count; ++i) {
@@ -49,9 +50,11 @@ Layout make_layout(int N, bool backward, int group) {
     return L;
 }
 
-// Flags hrc_forward, hrc_backward and hrc_workspace_bytes accept.
+// Flags hrc_backward accepts; hrc_forward and hrc_workspace_bytes also take
+// HRC_FLAG_HALF_INTERVALS.
 static constexpr unsigned kSolveFlags =
     HRC_FLAG_VALIDATE | HRC_FLAG_QUADRANTS_MASK | HRC_FLAG_BLUR;
+static constexpr unsigned kForwardFlags = kSolveFlags | HRC_FLAG_HALF_INTERVALS;
 
 // Quadrant group of a forward: from the flags, else all four at once.
 static int forward_group(int N, unsigned flags) {
@@ -148,14 +151,15 @@ int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, cons
                             q0,
                             G,
                             32,
-                            keep_all_r ? 0 : kTracedLevels - 1};
+                            keep_all_r ? 0 : kTracedLevels - 1,
+                            b.half};
         add(p);
         for (int n = kTracedLevels; n < N; ++n) {
             p = Phase();
             p.kind = PH_UP;
             p.U = pick_u(U, PH_UP);
             p.a.up = UpArgs{w.T(n - 1), w.T(n), t_level_entries(N, n - 1), t_level_entries(N, n),
-                            N, n, G};
+                            N, n, G, b.half};
             add(p);
         }
         int cur = -1;
@@ -167,7 +171,7 @@ int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, cons
             p.U = pick_u(U, PH_DOWN);
             p.a.down = DownArgs{(n + 1 < N) ? w.R(cur) : nullptr, w.T(n), w.T(n + 1), w.R(o),
                                 t_level_entries(N, n), t_level_entries(N, n + 1), N, n, G,
-                                b.env, q0};
+                                b.env, q0, b.half};
             add(p);
             cur = o;
         }
@@ -269,7 +273,7 @@ const char *hrc_status_string(hrc_status s) {
         case HRC_ERR_SHAPE: return "HRC_ERR_SHAPE: log2_size outside [3, 12]";
         case HRC_ERR_WORKSPACE: return "HRC_ERR_WORKSPACE: workspace smaller than hrc_workspace_bytes";
         case HRC_ERR_HIP: return "HRC_ERR_HIP: a HIP runtime call or kernel launch failed";
-        case HRC_ERR_UNSUPPORTED: return "HRC_ERR_UNSUPPORTED: unknown flag bits";
+        case HRC_ERR_UNSUPPORTED: return "HRC_ERR_UNSUPPORTED: unknown flag bits, or a flag this call does not take";
         case HRC_ERR_INPUT: return "HRC_ERR_INPUT: negative or non-finite emission or attenuation";
     }
     return "HRC: unknown status";
@@ -279,9 +283,11 @@ hrc_status hrc_workspace_bytes(int log2_size, unsigned flags, size_t *forward_by
                                size_t *backward_bytes) {
     hrc_status st = check_shape(log2_size);
     if (st != HRC_OK) return st;
-    if (flags & ~kSolveFlags) return HRC_ERR_UNSUPPORTED;
+    if (flags & ~kForwardFlags) return HRC_ERR_UNSUPPORTED;
     if (forward_bytes)
-        *forward_bytes = make_layout(log2_size, false, forward_group(log2_size, flags)).total;
+        *forward_bytes = make_layout(log2_size, false, forward_group(log2_size, flags),
+                                     (flags & HRC_FLAG_HALF_INTERVALS) != 0)
+                             .total;
     if (backward_bytes) *backward_bytes = make_layout(log2_size, true).total;
     return HRC_OK;
 }
@@ -346,8 +352,9 @@ hrc_status hrc_forward(hrc_context *ctx, int log2_size, const float *emission,
     if (!aligned16(emission) || !aligned16(sigma_t) || !aligned16(fluence) ||
         !aligned16(workspace))
         return HRC_ERR_INVALID_ARG;
-    if (flags & ~kSolveFlags) return HRC_ERR_UNSUPPORTED;
-    Layout L = make_layout(log2_size, false, forward_group(log2_size, flags));
+    if (flags & ~kForwardFlags) return HRC_ERR_UNSUPPORTED;
+    const bool half = (flags & HRC_FLAG_HALF_INTERVALS) != 0;
+    Layout L = make_layout(log2_size, false, forward_group(log2_size, flags), half);
     if (workspace_bytes < L.total) return HRC_ERR_WORKSPACE;
     if (!ctx) return HRC_ERR_INVALID_ARG;
     DeviceGuard g(ctx->device);
@@ -360,7 +367,8 @@ hrc_status hrc_forward(hrc_context *ctx, int log2_size, const float *emission,
     }
     Phase ph[kMaxPhases];
     SolveBuffers b{emission, sigma_t, fluence, nullptr, nullptr, nullptr,
-                   (flags & HRC_FLAG_BLUR) ? 1 : 0, ctx->has_env ? ctx->env : nullptr};
+                   (flags & HRC_FLAG_BLUR) ? 1 : 0, ctx->has_env ? ctx->env : nullptr,
+                   half ? 1 : 0};
     int np = build_solve_phases(w, b, false, nullptr, ph, kMaxPhases);
     return run_phases(ph, np, s);
 }

@@ -44,7 +44,8 @@ struct Layout {
 };
 
 // Forward: pyramids of `group` quadrants (1, 2 or 4) at a time; backward: all 4.
-Layout make_layout(int N, bool backward, int group = 4);
+// half: the forward's interval levels as 16-bit (L, T) pairs (4 bytes an entry)
+Layout make_layout(int N, bool backward, int group = 4, bool half = false);
 
 struct Ws {
     char *base;
@@ -67,8 +68,11 @@ struct SeedArgs {
     int N, q0, nq;
     int tile;           // image tile side: 32 standalone, 16 in the persistent kernel
     int first;          // first level written: 0, or 2 when the tail folds T_0 and T_1 itself
+    int half;           // T levels stored as 16-bit (L, T) pairs (HRC_FLAG_HALF_INTERVALS)
 };
-struct UpArgs { const float2 *Tp; float2 *T; size_t ep, e; int N, n, nq; };
+// half: both levels stored as 16-bit (L, T) pairs (the pointers then address
+// pairs of halves; the entry counts are unchanged)
+struct UpArgs { const float2 *Tp; float2 *T; size_t ep, e; int N, n, nq; int half; };
 // env (nullable): the environment's angular fluence per quadrant and cone,
 // [4][kConeTable] with cone jj of level m at (2^m - 1) + jj, read for every
 // angular fluence looked up outside the grid (and for R_N); NULL gives 0.
@@ -80,6 +84,7 @@ struct DownArgs {
     int N, n, nq;
     const float *env;        // environment table (nullable)
     int q0;                  // absolute quadrant of the group's first solve
+    int half;                // T levels stored as 16-bit (L, T) pairs
 };
 // The tail of the forward: levels 1 and 0 of the merge down, the gather and
 // the sum over quadrants, from R_2 of the group's quadrants q0 .. q0+nq-1.
@@ -164,6 +169,7 @@ struct SolveBuffers {
     float *dE, *dS;  // all three NULL: forward only
     int blur = 0;    // cross blur after the gather (forward) / its transpose first (reverse)
     const float *env = nullptr;  // environment table (hrc_context::env) or NULL
+    int half = 0;    // forward only: interval levels stored as 16-bit pairs
 };
 // Opacity threshold of the cross blur (Eq. 21): |alpha_nb - alpha| above it ignores
 // the neighbour.

@@ -97,6 +97,50 @@ __device__ __forceinline__ float env_fluence(const float *envq, int m, int jj) {
 // consecutive output elements per tile (U elements per thread, 256 apart).
 // ---------------------------------------------------------------------------
 
+// Two consecutive y per thread: y is even and every shift is even (except
+// the odd-column shifts 2e - 1 of merge-down level 0, read element-wise), so a
+// pair of intervals is one aligned 16-byte load and a pair of angular
+// fluences one aligned 8-byte load, and both members of a shifted pair are in
+// or out of the grid together.
+__device__ __forceinline__ float4 ld_pair(const float2 *p) {
+    return *reinterpret_cast<const float4 *>(p);
+}
+__device__ __forceinline__ float2 lo(float4 v) { return make_float2(v.x, v.y); }
+__device__ __forceinline__ float2 hi(float4 v) { return make_float2(v.z, v.w); }
+__device__ __forceinline__ float4 pair(float2 a, float2 b) { return make_float4(a.x, a.y, b.x, b.y); }
+__device__ __forceinline__ void st_pair(float2 *p, float4 v) { *reinterpret_cast<float4 *>(p) = v; }
+__device__ __forceinline__ void st_iv(float2 *p, float2 v) { *p = v; }
+
+// The 16-bit interval storage of Section 5 (HRC_FLAG_HALF_INTERVALS, forward
+// only): an interval is a pair of IEEE half floats (L, T), computed in FP32 and
+// rounded to nearest even once when it is stored; a pair of intervals is one
+// 8-byte load.
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld_pair(const half2_t *p) {
+    const half4_t v = *reinterpret_cast<const half4_t *>(p);
+    return make_float4((float)v.x, (float)v.y, (float)v.z, (float)v.w);
+}
+__device__ __forceinline__ void st_pair(half2_t *p, float4 v) {
+    half4_t h;
+    h.x = (_Float16)v.x;
+    h.y = (_Float16)v.y;
+    h.z = (_Float16)v.z;
+    h.w = (_Float16)v.w;
+    *reinterpret_cast<half4_t *>(p) = h;
+}
+__device__ __forceinline__ void st_iv(half2_t *p, float2 v) {
+    half2_t h;
+    h.x = (_Float16)v.x;
+    h.y = (_Float16)v.y;
+    *p = h;
+}
+
+template <typename TS>
+__device__ __forceinline__ float4 far_pair(const TS *row, int yf, int S) {
+    return (yf >= 0 && yf < S) ? ld_pair(row + yf) : make_float4(0.f, 1.f, 0.f, 1.f);
+}
+
 // Traced levels T_0, T_1, T_2 (Algorithm 1, first loop), for all four
 // quadrants from one 32x32 image tile (T_2 alone when the forward's tail folds
 // the intervals of T_0 and T_1 itself).
@@ -146,14 +190,14 @@ constexpr unsigned char kHpLen[10][8] = {
 // directions (unrolled: the piece offsets are uniform over the wave), so the
 // LDS base and the output address are computed once per probe; lanes run
 // along w, so each direction's stores are contiguous rows.
-template <int TILE, int n>
+template <int TILE, int n, typename TS>
 __device__ __forceinline__ void seed_level_rays(const float2 *iv, const SeedArgs &a, int q,
                                                 int slot, int r0, int c0) {
     using G = SeedTile<TILE>;
     constexpr int dirs = (1 << n) + 1, cols = TILE >> n, pieces = 2 << n;
     constexpr int per_pass = 256 / TILE;  // probe columns per pass of the block
     const int S = 1 << a.N;
-    float2 *out = n == 0 ? a.T0 : n == 1 ? a.T1 : a.T2;
+    TS *out = reinterpret_cast<TS *>(n == 0 ? a.T0 : n == 1 ? a.T1 : a.T2);
     const size_t qoff = n == 0 ? a.e0 : n == 1 ? a.e1 : a.e2;
     // frame of quadrant q: +x (u, w) = (c, r); -x (S-1-c, r); +y (r, c); -y (S-1-r, c)
     const int u_lo = q == 0 ? c0 : q == 1 ? S - TILE - c0 : q == 2 ? r0 : S - TILE - r0;
@@ -170,7 +214,7 @@ __device__ __forceinline__ void seed_level_rays(const float2 *iv, const SeedArgs
         if (q < 2) { lr = w - r0; lc = (q == 0 ? u : S - 1 - u) - c0; }
         else { lc = w - c0; lr = (q == 2 ? u : S - 1 - u) - r0; }
         const float2 *ivp = iv + (lr + kSeedHalo) * G::pitch + lc + kSeedHalo;
-        float2 *o = out + slot * qoff + (size_t)(u >> n) * dirs * S + w;
+        TS *o = out + slot * qoff + (size_t)(u >> n) * dirs * S + w;
 #pragma unroll
         for (int k = 0; k < dirs; ++k) {
             float2 acc = make_float2(0.f, 1.f);
@@ -180,7 +224,7 @@ __device__ __forceinline__ void seed_level_rays(const float2 *iv, const SeedArgs
                                 kHpDu[sid0 + k][j] * su + kHpDw[sid0 + k][j] * sw;
                 acc = merge(acc, ivp[off]);
             }
-            o[(size_t)k * S] = acc;
+            st_iv(o + (size_t)k * S, acc);
         }
     }
 }
@@ -188,7 +232,7 @@ __device__ __forceinline__ void seed_level_rays(const float2 *iv, const SeedArgs
 // TILE x TILE image pixels per work tile (32 for the standalone kernel, 16
 // inside the persistent kernel, whose one LDS buffer serves every pass); the
 // per-ray arithmetic is the same for both.
-template <int TILE>
+template <int TILE, typename TS>
 __device__ void body_seed(const SeedArgs &a, unsigned tile, char *lds) {
     using G = SeedTile<TILE>;
     float2 *iv = reinterpret_cast<float2 *>(lds);
@@ -210,32 +254,18 @@ __device__ void body_seed(const SeedArgs &a, unsigned tile, char *lds) {
     }
     __syncthreads();
     for (int g = 0; g < a.nq; ++g) {
-        if (a.first <= 0) seed_level_rays<TILE, 0>(iv, a, a.q0 + g, g, r0, c0);
-        if (a.first <= 1) seed_level_rays<TILE, 1>(iv, a, a.q0 + g, g, r0, c0);
-        seed_level_rays<TILE, 2>(iv, a, a.q0 + g, g, r0, c0);
+        if (a.first <= 0) seed_level_rays<TILE, 0, TS>(iv, a, a.q0 + g, g, r0, c0);
+        if (a.first <= 1) seed_level_rays<TILE, 1, TS>(iv, a, a.q0 + g, g, r0, c0);
+        seed_level_rays<TILE, 2, TS>(iv, a, a.q0 + g, g, r0, c0);
     }
     __syncthreads();
-}
-
-// Two consecutive y per thread: y is even and every shift is even (except
-// the odd-column shifts 2e - 1 of merge-down level 0, read element-wise), so a
-// pair of intervals is one aligned 16-byte load and a pair of angular
-// fluences one aligned 8-byte load, and both members of a shifted pair are in
-// or out of the grid together.
-__device__ __forceinline__ float4 ld_pair(const float2 *p) {
-    return *reinterpret_cast<const float4 *>(p);
-}
-__device__ __forceinline__ float2 lo(float4 v) { return make_float2(v.x, v.y); }
-__device__ __forceinline__ float2 hi(float4 v) { return make_float2(v.z, v.w); }
-__device__ __forceinline__ float4 pair(float2 a, float2 b) { return make_float4(a.x, a.y, b.x, b.y); }
-__device__ __forceinline__ float4 far_pair(const float2 *row, int yf, int S) {
-    return (yf >= 0 && yf < S) ? ld_pair(row + yf) : make_float4(0.f, 1.f, 0.f, 1.f);
 }
 
 // Merge up: T_n from T_{n-1} (Section 4.1, Eq. 18-20), for n < N.  The top
 // level is never stored: the merge down reads T_N only through the even
 // directions of its one column (the doubled edges of Eq. 15-17), and builds
 // those itself from T_{N-1}.
+template <typename TS>
 __device__ void body_merge_up(const UpArgs &a, unsigned tile, int U) {
     const int N = a.N, S = 1 << N, n = a.n;
     const int h = 1 << (n - 1);
@@ -251,8 +281,8 @@ __device__ void body_merge_up(const UpArgs &a, unsigned tile, int U) {
         const unsigned rk = row % rpq;
         const int x = rk / dirs, k = rk % dirs;
         const unsigned r = (unsigned)x * dirs + k;  // output row (x, k)
-        const float2 *near = a.Tp + q * a.ep + (size_t)(2 * x) * pdirs * S;
-        const float2 *far = near + (size_t)pdirs * S;
+        const TS *near = reinterpret_cast<const TS *>(a.Tp) + q * a.ep + (size_t)(2 * x) * pdirs * S;
+        const TS *far = near + (size_t)pdirs * S;
         float4 res;
         if ((k & 1) == 0) {
             // Eq. 18: p -> p + v_{n-1}(k/2) -> p + v_n(k), exact.
@@ -272,7 +302,7 @@ __device__ void body_merge_up(const UpArgs &a, unsigned tile, int U) {
             res = make_float4(0.5f * (p0.x + m0.x), 0.5f * (p0.y + m0.y),
                               0.5f * (p1.x + m1.x), 0.5f * (p1.y + m1.y));
         }
-        *reinterpret_cast<float4 *>(a.T + q * a.e + (size_t)r * S + y) = res;
+        st_pair(reinterpret_cast<TS *>(a.T) + q * a.e + (size_t)r * S + y, res);
     }
 }
 
@@ -291,6 +321,7 @@ __device__ __forceinline__ float2 r_pair(const float *Rq, int N, int m, int c, i
 // Merge down: R_n from R_{n+1}, T_n, T_{n+1} (Eq. 14-17), for n >= 1 (levels 1
 // and 0 of the forward are the tail's, and the reverse reads R_1 at the
 // lowest), so every row shift is even and each lookup is a pair.
+template <typename TS>
 __device__ void body_merge_down(const DownArgs &a, unsigned tile, int U) {
     const int N = a.N, S = 1 << N, n = a.n;
     const size_t SS = (size_t)S * S;
@@ -309,7 +340,7 @@ __device__ void body_merge_down(const DownArgs &a, unsigned tile, int U) {
         float acc0 = 0.f, acc1 = 0.f;
         if (x & 1) {
             // Eq. 14: trace the half-cone's outer edge to the level n+1 probe.
-            const float2 *Tx = a.Tn + q * a.en + (size_t)x * ((1 << n) + 1) * S;
+            const TS *Tx = reinterpret_cast<const TS *>(a.Tn) + q * a.en + (size_t)x * ((1 << n) + 1) * S;
             const int c = (x + 1) >> 1;
 #pragma unroll
             for (int up = 0; up < 2; ++up) {
@@ -327,9 +358,9 @@ __device__ void body_merge_down(const DownArgs &a, unsigned tile, int U) {
             // then T_{N-1}(2c+1, e2/2) at row y + e2 - 2^n.
             const int c = x >> 1;
             const bool top = m == N;
-            const float2 *Tx = a.Tn1 + q * a.en1 + (size_t)c * ((1 << m) + 1) * S;
-            const float2 *Tnear = a.Tn + q * a.en + (size_t)(2 * c) * ((1 << n) + 1) * S;
-            const float2 *Tfar = Tnear + (size_t)((1 << n) + 1) * S;
+            const TS *Tx = reinterpret_cast<const TS *>(a.Tn1) + q * a.en1 + (size_t)c * ((1 << m) + 1) * S;
+            const TS *Tnear = reinterpret_cast<const TS *>(a.Tn) + q * a.en + (size_t)(2 * c) * ((1 << n) + 1) * S;
+            const TS *Tfar = Tnear + (size_t)((1 << n) + 1) * S;
 #pragma unroll
             for (int up = 0; up < 2; ++up) {
                 const int e2 = 2 * ii + 2 * up, jj = 2 * ii + up;
@@ -1190,9 +1221,9 @@ constexpr int kMaxLds = kMaxLds2 > TailTile<16>::lds ? kMaxLds2 : TailTile<16>::
 
 __device__ __forceinline__ void run_phase(const Phase &p, unsigned tile, char *lds) {
     switch (p.kind) {
-        case PH_SEED: body_seed<16>(p.a.seed, tile, lds); break;  // planner sets tile 16
-        case PH_UP: body_merge_up(p.a.up, tile, p.U); break;
-        case PH_DOWN: body_merge_down(p.a.down, tile, p.U); break;
+        case PH_SEED: body_seed<16, float2>(p.a.seed, tile, lds); break;  // planner sets tile 16
+        case PH_UP: body_merge_up<float2>(p.a.up, tile, p.U); break;
+        case PH_DOWN: body_merge_down<float2>(p.a.down, tile, p.U); break;
         case PH_TAIL: body_tail<16>(p.a.tail, tile, lds); break;  // planner sets tile 16
         case PH_GATHER_ADJ: body_gather_adj(p.a.ga, tile, lds); break;
         case PH_DOWN_ADJ: body_merge_down_adj(p.a.da, tile, p.U); break;
@@ -1213,15 +1244,21 @@ __device__ __forceinline__ void run_phase(const Phase &p, unsigned tile, char *l
     __global__ __launch_bounds__(256) void name(Phase p) {                         \
         body(p.a.field, xcd_tile(blockIdx.x, gridDim.x), p.U);                     \
     }
-HRC_ELEMENTWISE_KERNEL(hrc_merge_up, body_merge_up, up)
-HRC_ELEMENTWISE_KERNEL(hrc_merge_down, body_merge_down, down)
+HRC_ELEMENTWISE_KERNEL(hrc_merge_up, body_merge_up<float2>, up)
+HRC_ELEMENTWISE_KERNEL(hrc_merge_down, body_merge_down<float2>, down)
+HRC_ELEMENTWISE_KERNEL(hrc_merge_up_f16, body_merge_up<half2_t>, up)
+HRC_ELEMENTWISE_KERNEL(hrc_merge_down_f16, body_merge_down<half2_t>, down)
 HRC_ELEMENTWISE_KERNEL(hrc_merge_down_adj, body_merge_down_adj, da)
 HRC_ELEMENTWISE_KERNEL(hrc_interval_adj, body_dT, dt)
 #undef HRC_ELEMENTWISE_KERNEL
 
 __global__ __launch_bounds__(256) void hrc_seed(Phase p) {
     __shared__ __align__(16) char lds[SeedTile<32>::lds];
-    body_seed<32>(p.a.seed, xcd_tile(blockIdx.x, gridDim.x), lds);
+    body_seed<32, float2>(p.a.seed, xcd_tile(blockIdx.x, gridDim.x), lds);
+}
+__global__ __launch_bounds__(256) void hrc_seed_f16(Phase p) {
+    __shared__ __align__(16) char lds[SeedTile<32>::lds];
+    body_seed<32, half2_t>(p.a.seed, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 __global__ __launch_bounds__(256) void hrc_seed_adj(Phase p) {
     __shared__ __align__(16) char lds[kSeedAdjLds];
@@ -1437,9 +1474,9 @@ hipError_t launch_phase(const Phase &p, hipStream_t s, hipEvent_t start, hipEven
     if (tiles == 0) return hipSuccess;
     void (*k)(Phase) = nullptr;
     switch (p.kind) {
-        case PH_SEED: k = hrc_seed; break;
-        case PH_UP: k = hrc_merge_up; break;
-        case PH_DOWN: k = hrc_merge_down; break;
+        case PH_SEED: k = p.a.seed.half ? hrc_seed_f16 : hrc_seed; break;
+        case PH_UP: k = p.a.up.half ? hrc_merge_up_f16 : hrc_merge_up; break;
+        case PH_DOWN: k = p.a.down.half ? hrc_merge_down_f16 : hrc_merge_down; break;
         case PH_TAIL: k = hrc_tail; break;
         case PH_GATHER_ADJ: k = hrc_gather_adj; break;
         case PH_DOWN_ADJ: k = hrc_merge_down_adj; break;

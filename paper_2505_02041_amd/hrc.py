@@ -75,11 +75,14 @@ class Context:
               "hrc_set_environment")
 
     def workspace(self, N: int, backward: bool, flags: int = 0) -> torch.Tensor:
-        group = 0 if backward else flags & _lib.HRC_FLAG_QUADRANTS_MASK
-        key = (N, backward, group)
+        # the forward's size depends on the quadrant grouping and the interval
+        # storage, the backward's on neither
+        sized = 0 if backward else flags & (_lib.HRC_FLAG_QUADRANTS_MASK |
+                                            _lib.HRC_FLAG_HALF_INTERVALS)
+        key = (N, backward, sized)
         ws = self._ws.get(key)
         if ws is None:
-            f, b = hrc_workspace_bytes(N, group)
+            f, b = hrc_workspace_bytes(N, sized)
             ws = torch.empty(b if backward else f, dtype=torch.uint8,
                              device=torch.device("cuda", self.device))
             self._ws[key] = ws

@@ -8,7 +8,8 @@ outputs sharing an input row) are not counted: they are what the kernels must
 keep on chip to reach the roofline.
 
 Counts per quadrant follow Section 4.3: T_n has X^2 (1 + 2^-n) entries, R_n has
-X^2, with X = S = 2^N.
+X^2, with X = S = 2^N.  ``iv`` is the bytes of a stored interval: 8 in FP32, 4
+with the 16-bit storage of the forward's ``HRC_FLAG_HALF_INTERVALS``.
 """
 from __future__ import annotations
 
@@ -19,26 +20,26 @@ def _t(S: int, n: int) -> float:
     return S * S * (1.0 + 2.0 ** -n)
 
 
-def pass_bytes(name: str, N: int, n: int = -1) -> float:
+def pass_bytes(name: str, N: int, n: int = -1, iv: int = 8) -> float:
     S = 1 << N
     SS = float(S * S)
     q = 4
     if name == "seed":
         # the two fields read once for all four quadrants, T_2 written (the
         # forward's tail folds T_0 and T_1 itself)
-        return 8 * SS + q * 8 * _t(S, 2)
+        return 8 * SS + q * iv * _t(S, 2)
     if name == "seed_all":
         # the reverse's recomputed forward: T_0..T_2 written
         return 8 * SS + q * 8 * (_t(S, 0) + _t(S, 1) + _t(S, 2))
     if name == "merge_up":
         # levels 3 .. N-1 (the top level is built inside the merge down)
-        return q * 8 * (_t(S, n - 1) + _t(S, n))
+        return q * iv * (_t(S, n - 1) + _t(S, n))
     if name == "merge_down":
         # half of T_n (odd columns) and the even directions of T_{n+1}: together
         # X^2 (1 + 2^-n) intervals (at n = N-1: all of T_{N-1}, from which the
         # even directions of T_N are built, the same count); R_{n+1} read
         # unless n + 1 = N; R_n written
-        return q * 8 * _t(S, n) + (q * 4 * SS if n + 1 < N else 0.0) + q * 4 * SS
+        return q * iv * _t(S, n) + (q * 4 * SS if n + 1 < N else 0.0) + q * 4 * SS
     if name == "tail":
         # the two fields once, R_2 of the four quadrants, F written
         return 8 * SS + q * 4 * SS + 4 * SS
@@ -72,8 +73,8 @@ def forward_passes(N: int):
     return out
 
 
-def forward_bytes(N: int) -> float:
-    return sum(pass_bytes(k, N, n) for k, n in forward_passes(N))
+def forward_bytes(N: int, iv: int = 8) -> float:
+    return sum(pass_bytes(k, N, n, iv) for k, n in forward_passes(N))
 
 
 def backward_bytes(N: int) -> float:

@@ -27,6 +27,31 @@ def assert_forward_close(F_gpu, F_ref, what=""):
                              f"gpu {F_gpu[i]!r} ref {F_ref[i]!r}")
 
 
+# Forward tolerance with the 16-bit interval storage (HRC_FLAG_HALF_INTERVALS):
+# each of the at most N - 2 stored levels on a path adds a relative rounding of
+# at most 2^-11 to non-negative sums and products, so N * 2^-11 componentwise
+# (plus FP32's 1e-4), with a floor for values in the half's subnormal range
+# (absolute 2^-25 each).  tests/test_oracle_half_storage.py checks the bound on
+# the oracle's steps rounded at the same points.
+HALF_RTOL_PER_LEVEL = 2.0 ** -11
+HALF_FLOOR = 1e-6
+
+
+def assert_half_close(F_gpu, F_ref, N, what=""):
+    F_gpu = np.asarray(F_gpu, dtype=np.float64)
+    F_ref = np.asarray(F_ref, dtype=np.float64)
+    assert F_gpu.shape == F_ref.shape
+    rtol = N * HALF_RTOL_PER_LEVEL + FWD_RTOL
+    bound = rtol * np.abs(F_ref) + HALF_FLOOR * np.abs(F_ref).max()
+    err = np.abs(F_gpu - F_ref)
+    bad = err > bound
+    if bad.any():
+        i = np.unravel_index(np.argmax(err / np.maximum(bound, 1e-300)), err.shape)
+        raise AssertionError(f"{what}: {bad.sum()} of {bad.size} outside the 16-bit storage "
+                             f"bound; worst at {i}: gpu {F_gpu[i]!r} ref {F_ref[i]!r}")
+    return float(np.max(err / np.maximum(np.abs(F_ref), 1e-300) * (np.abs(F_ref) > 1e-3 * np.abs(F_ref).max())))
+
+
 # Gradient tolerance: the reverse pass sums signed terms (the loss residual), so
 # the bound is relative to the largest gradient, plus a relative check on the
 # entries that carry most of the gradient.
