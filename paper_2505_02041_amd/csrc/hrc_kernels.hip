@@ -141,6 +141,40 @@ __device__ __forceinline__ float4 far_pair(const TS *row, int yf, int S) {
     return (yf >= 0 && yf < S) ? ld_pair(row + yf) : make_float4(0.f, 1.f, 0.f, 1.f);
 }
 
+// Four consecutive 16-bit intervals (two pairs) at y, y a multiple of 4: one
+// 16-byte load.
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ void ld_quad(const half2_t *p, float4 &a, float4 &b) {
+    const half8_t v = *reinterpret_cast<const half8_t *>(p);
+    a = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+    b = make_float4((float)v[4], (float)v[5], (float)v[6], (float)v[7]);
+}
+__device__ __forceinline__ void st_quad(half2_t *p, float4 a, float4 b) {
+    half8_t h;
+    h[0] = (_Float16)a.x; h[1] = (_Float16)a.y; h[2] = (_Float16)a.z; h[3] = (_Float16)a.w;
+    h[4] = (_Float16)b.x; h[5] = (_Float16)b.y; h[6] = (_Float16)b.z; h[7] = (_Float16)b.w;
+    *reinterpret_cast<half8_t *>(p) = h;
+}
+__device__ __forceinline__ void st_quad(float2 *, float4, float4) {}  // not used with FP32
+
+// The same at a shifted row position yf (even): one 16-byte load when yf is a
+// multiple of 4 (it is, or is not, for the whole wave: threads start at
+// multiples of 4 and the shift is uniform), else two 8-byte pair loads; rows
+// outside [0, S) read <0, 1> (S and aligned yf are multiples of 4, so an
+// aligned quad is wholly in or out).
+__device__ __forceinline__ void far_quad(const half2_t *row, int yf, int S, float4 &a, float4 &b) {
+    if ((yf & 3) == 0) {
+        if (yf >= 0 && yf < S) {
+            ld_quad(row + yf, a, b);
+        } else {
+            a = b = make_float4(0.f, 1.f, 0.f, 1.f);
+        }
+    } else {
+        a = far_pair(row, yf, S);
+        b = far_pair(row, yf + 2, S);
+    }
+}
+
 // Traced levels T_0, T_1, T_2 (Algorithm 1, first loop), for all four
 // quadrants from one 32x32 image tile (T_2 alone when the forward's tail folds
 // the intervals of T_0 and T_1 itself).
@@ -261,48 +295,90 @@ __device__ void body_seed(const SeedArgs &a, unsigned tile, char *lds) {
     __syncthreads();
 }
 
+// Pairs of consecutive y per thread in the merges: one with FP32 intervals
+// (a pair is a 16-byte load), two with 16-bit ones (so that a thread still
+// has 16 bytes of each row in flight).
+template <typename TS> constexpr int merge_pairs() { return sizeof(TS) == 4 ? 2 : 1; }
+
 // Merge up: T_n from T_{n-1} (Section 4.1, Eq. 18-20), for n < N.  The top
 // level is never stored: the merge down reads T_N only through the even
 // directions of its one column (the doubled edges of Eq. 15-17), and builds
 // those itself from T_{N-1}.
 template <typename TS>
 __device__ void body_merge_up(const UpArgs &a, unsigned tile, int U) {
+    constexpr int P = merge_pairs<TS>();
     const int N = a.N, S = 1 << N, n = a.n;
     const int h = 1 << (n - 1);
     const int dirs = 2 * h + 1, pdirs = h + 1;
     const unsigned rpq = (unsigned)(S >> n) * dirs;
-    const size_t total = (size_t)a.nq * rpq * (S / 2);
+    const size_t total = (size_t)a.nq * rpq * (S / (2 * P));
     for (int uu = 0; uu < U; ++uu) {
         const size_t idx = ((size_t)tile * U + uu) * 256 + ltid();
         if (idx >= total) return;
-        const int y = (int)(idx & (S / 2 - 1)) * 2;
-        const unsigned row = (unsigned)(idx >> (N - 1));
+        const int y0 = (int)(idx & (S / (2 * P) - 1)) * 2 * P;
+        const unsigned row = (unsigned)(idx >> (N - (P == 2 ? 2 : 1)));
         const int q = row / rpq;
         const unsigned rk = row % rpq;
         const int x = rk / dirs, k = rk % dirs;
         const unsigned r = (unsigned)x * dirs + k;  // output row (x, k)
         const TS *near = reinterpret_cast<const TS *>(a.Tp) + q * a.ep + (size_t)(2 * x) * pdirs * S;
         const TS *far = near + (size_t)pdirs * S;
-        float4 res;
-        if ((k & 1) == 0) {
-            // Eq. 18: p -> p + v_{n-1}(k/2) -> p + v_n(k), exact.
-            const int kk = k >> 1;
-            const float4 nv = ld_pair(near + (size_t)kk * S + y);
-            const float4 fv = far_pair(far + (size_t)kk * S, y + 2 * kk - h, S);
-            res = pair(merge(lo(nv), lo(fv)), merge(hi(nv), hi(fv)));
+        float4 res[P];
+        if constexpr (P == 2) {
+            // 16-bit intervals: each row read as one quad (two pairs) per thread
+            if ((k & 1) == 0) {
+                const int kk = k >> 1;
+                float4 nv[2], fv[2];
+                ld_quad(near + (size_t)kk * S + y0, nv[0], nv[1]);
+                far_quad(far + (size_t)kk * S, y0 + 2 * kk - h, S, fv[0], fv[1]);
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    res[j] = pair(merge(lo(nv[j]), lo(fv[j])), merge(hi(nv[j]), hi(fv[j])));
+            } else {
+                const int ka = (k + 1) >> 1, kb = (k - 1) >> 1;
+                float4 na[2], nb[2], fa[2], fb[2];
+                ld_quad(near + (size_t)ka * S + y0, na[0], na[1]);
+                ld_quad(near + (size_t)kb * S + y0, nb[0], nb[1]);
+                far_quad(far + (size_t)kb * S, y0 + 2 * ka - h, S, fa[0], fa[1]);
+                far_quad(far + (size_t)ka * S, y0 + 2 * kb - h, S, fb[0], fb[1]);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const float2 p0 = merge(lo(na[j]), lo(fa[j])), m0 = merge(lo(nb[j]), lo(fb[j]));
+                    const float2 p1 = merge(hi(na[j]), hi(fa[j])), m1 = merge(hi(nb[j]), hi(fb[j]));
+                    res[j] = make_float4(0.5f * (p0.x + m0.x), 0.5f * (p0.y + m0.y),
+                                         0.5f * (p1.x + m1.x), 0.5f * (p1.y + m1.y));
+                }
+            }
         } else {
-            // Eq. 19-20: mean of the two bent paths through directions (k+-1)/2.
-            const int ka = (k + 1) >> 1, kb = (k - 1) >> 1;
-            const float4 na = ld_pair(near + (size_t)ka * S + y);
-            const float4 nb = ld_pair(near + (size_t)kb * S + y);
-            const float4 fa = far_pair(far + (size_t)kb * S, y + 2 * ka - h, S);
-            const float4 fb = far_pair(far + (size_t)ka * S, y + 2 * kb - h, S);
-            const float2 p0 = merge(lo(na), lo(fa)), m0 = merge(lo(nb), lo(fb));
-            const float2 p1 = merge(hi(na), hi(fa)), m1 = merge(hi(nb), hi(fb));
-            res = make_float4(0.5f * (p0.x + m0.x), 0.5f * (p0.y + m0.y),
-                              0.5f * (p1.x + m1.x), 0.5f * (p1.y + m1.y));
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const int y = y0 + 2 * j;
+            if ((k & 1) == 0) {
+                // Eq. 18: p -> p + v_{n-1}(k/2) -> p + v_n(k), exact.
+                const int kk = k >> 1;
+                const float4 nv = ld_pair(near + (size_t)kk * S + y);
+                const float4 fv = far_pair(far + (size_t)kk * S, y + 2 * kk - h, S);
+                res[j] = pair(merge(lo(nv), lo(fv)), merge(hi(nv), hi(fv)));
+            } else {
+                // Eq. 19-20: mean of the two bent paths through directions (k+-1)/2.
+                const int ka = (k + 1) >> 1, kb = (k - 1) >> 1;
+                const float4 na = ld_pair(near + (size_t)ka * S + y);
+                const float4 nb = ld_pair(near + (size_t)kb * S + y);
+                const float4 fa = far_pair(far + (size_t)kb * S, y + 2 * ka - h, S);
+                const float4 fb = far_pair(far + (size_t)ka * S, y + 2 * kb - h, S);
+                const float2 p0 = merge(lo(na), lo(fa)), m0 = merge(lo(nb), lo(fb));
+                const float2 p1 = merge(hi(na), hi(fa)), m1 = merge(hi(nb), hi(fb));
+                res[j] = make_float4(0.5f * (p0.x + m0.x), 0.5f * (p0.y + m0.y),
+                                     0.5f * (p1.x + m1.x), 0.5f * (p1.y + m1.y));
+            }
         }
-        st_pair(reinterpret_cast<TS *>(a.T) + q * a.e + (size_t)r * S + y, res);
+        }
+        TS *out = reinterpret_cast<TS *>(a.T) + q * a.e + (size_t)r * S + y0;
+        if constexpr (P == 2) {
+            st_quad(out, res[0], res[1]);
+        } else {
+            st_pair(out, res[0]);
+        }
     }
 }
 
@@ -318,38 +394,78 @@ __device__ __forceinline__ float2 r_pair(const float *Rq, int N, int m, int c, i
     return *reinterpret_cast<const float2 *>(Rq + ((size_t)((c << m) | jj)) * S + y);
 }
 
+// The same for rows y .. y+3 (y even): one 16-byte load when y is a multiple of
+// 4 (uniform over the wave, as in far_quad) and the four lie in the grid, else
+// two pair lookups.
+__device__ __forceinline__ void r_quad(const float *Rq, int N, int m, int c, int jj, int y,
+                                       const float *envq, float2 &a, float2 &b) {
+    const int S = 1 << N;
+    if ((y & 3) == 0 && m < N && c < (S >> m) && y >= 0 && y < S) {
+        const float4 v = *reinterpret_cast<const float4 *>(Rq + ((size_t)((c << m) | jj)) * S + y);
+        a = make_float2(v.x, v.y);
+        b = make_float2(v.z, v.w);
+    } else {
+        a = r_pair(Rq, N, m, c, jj, y, envq);
+        b = r_pair(Rq, N, m, c, jj, y + 2, envq);
+    }
+}
+
 // Merge down: R_n from R_{n+1}, T_n, T_{n+1} (Eq. 14-17), for n >= 1 (levels 1
 // and 0 of the forward are the tail's, and the reverse reads R_1 at the
 // lowest), so every row shift is even and each lookup is a pair.
 template <typename TS>
 __device__ void body_merge_down(const DownArgs &a, unsigned tile, int U) {
+    constexpr int P = merge_pairs<TS>();
     const int N = a.N, S = 1 << N, n = a.n;
     const size_t SS = (size_t)S * S;
-    const size_t total = (size_t)a.nq * (SS / 2);
+    const size_t total = (size_t)a.nq * (SS / (2 * P));
     const int m = n + 1;
     for (int uu = 0; uu < U; ++uu) {
         const size_t idx = ((size_t)tile * U + uu) * 256 + ltid();
         if (idx >= total) return;
-        const int y = (int)(idx & (S / 2 - 1)) * 2;
-        const unsigned row = (unsigned)(idx >> (N - 1));
+        const int y0 = (int)(idx & (S / (2 * P) - 1)) * 2 * P;
+        const unsigned row = (unsigned)(idx >> (N - (P == 2 ? 2 : 1)));
         const int q = row >> N;
         const unsigned r = row & (S - 1);
         const int x = r >> n, ii = r & ((1 << n) - 1);
         const float *Rq = a.Rn1 + q * SS;
         const float *envq = a.env ? a.env + (size_t)(a.q0 + q) * kConeTable : nullptr;
-        float acc0 = 0.f, acc1 = 0.f;
+        float acc0[P], acc1[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) acc0[j] = acc1[j] = 0.f;
         if (x & 1) {
             // Eq. 14: trace the half-cone's outer edge to the level n+1 probe.
             const TS *Tx = reinterpret_cast<const TS *>(a.Tn) + q * a.en + (size_t)x * ((1 << n) + 1) * S;
             const int c = (x + 1) >> 1;
+            if constexpr (P == 2) {
 #pragma unroll
-            for (int up = 0; up < 2; ++up) {
-                const int e = ii + up, jj = 2 * ii + up;
-                const float A = c_cone[(1 << m) - 1 + jj];
-                const float4 t = ld_pair(Tx + (size_t)e * S + y);
-                const float2 rf = r_pair(Rq, N, m, c, jj, y + 2 * e - (1 << n), envq);
-                acc0 += fmaf(t.y, rf.x, A * t.x);
-                acc1 += fmaf(t.w, rf.y, A * t.z);
+                for (int up = 0; up < 2; ++up) {
+                    const int e = ii + up, jj = 2 * ii + up;
+                    const float A = c_cone[(1 << m) - 1 + jj];
+                    float4 t[2];
+                    float2 rf[2];
+                    ld_quad(Tx + (size_t)e * S + y0, t[0], t[1]);
+                    r_quad(Rq, N, m, c, jj, y0 + 2 * e - (1 << n), envq, rf[0], rf[1]);
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        acc0[j] += fmaf(t[j].y, rf[j].x, A * t[j].x);
+                        acc1[j] += fmaf(t[j].w, rf[j].y, A * t[j].z);
+                    }
+                }
+            } else {
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                const int y = y0 + 2 * j;
+#pragma unroll
+                for (int up = 0; up < 2; ++up) {
+                    const int e = ii + up, jj = 2 * ii + up;
+                    const float A = c_cone[(1 << m) - 1 + jj];
+                    const float4 t = ld_pair(Tx + (size_t)e * S + y);
+                    const float2 rf = r_pair(Rq, N, m, c, jj, y + 2 * e - (1 << n), envq);
+                    acc0[j] += fmaf(t.y, rf.x, A * t.x);
+                    acc1[j] += fmaf(t.w, rf.y, A * t.z);
+                }
+            }
             }
         } else {
             // Eq. 15-17: average the co-located probe with the doubled-edge trace.
@@ -361,26 +477,63 @@ __device__ void body_merge_down(const DownArgs &a, unsigned tile, int U) {
             const TS *Tx = reinterpret_cast<const TS *>(a.Tn1) + q * a.en1 + (size_t)c * ((1 << m) + 1) * S;
             const TS *Tnear = reinterpret_cast<const TS *>(a.Tn) + q * a.en + (size_t)(2 * c) * ((1 << n) + 1) * S;
             const TS *Tfar = Tnear + (size_t)((1 << n) + 1) * S;
+            if constexpr (P == 2) {
 #pragma unroll
-            for (int up = 0; up < 2; ++up) {
-                const int e2 = 2 * ii + 2 * up, jj = 2 * ii + up;
-                const float A = c_cone[(1 << m) - 1 + jj];
-                float4 t;
-                if (top) {
-                    const int kk = e2 >> 1;
-                    const float4 nv = ld_pair(Tnear + (size_t)kk * S + y);
-                    const float4 fv = far_pair(Tfar + (size_t)kk * S, y + e2 - (1 << n), S);
-                    t = pair(merge(lo(nv), lo(fv)), merge(hi(nv), hi(fv)));
-                } else {
-                    t = ld_pair(Tx + (size_t)e2 * S + y);
+                for (int up = 0; up < 2; ++up) {
+                    const int e2 = 2 * ii + 2 * up, jj = 2 * ii + up;
+                    const float A = c_cone[(1 << m) - 1 + jj];
+                    float4 t[2];
+                    if (top) {
+                        const int kk = e2 >> 1;
+                        float4 nv[2], fv[2];
+                        ld_quad(Tnear + (size_t)kk * S + y0, nv[0], nv[1]);
+                        far_quad(Tfar + (size_t)kk * S, y0 + e2 - (1 << n), S, fv[0], fv[1]);
+#pragma unroll
+                        for (int j = 0; j < 2; ++j)
+                            t[j] = pair(merge(lo(nv[j]), lo(fv[j])), merge(hi(nv[j]), hi(fv[j])));
+                    } else {
+                        ld_quad(Tx + (size_t)e2 * S + y0, t[0], t[1]);
+                    }
+                    float2 r0[2], r1[2];
+                    r_quad(Rq, N, m, c, jj, y0, envq, r0[0], r0[1]);
+                    r_quad(Rq, N, m, c + 1, jj, y0 + 2 * e2 - (1 << m), envq, r1[0], r1[1]);
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        acc0[j] += 0.5f * (r0[j].x + fmaf(t[j].y, r1[j].x, A * t[j].x));
+                        acc1[j] += 0.5f * (r0[j].y + fmaf(t[j].w, r1[j].y, A * t[j].z));
+                    }
                 }
-                const float2 r0 = r_pair(Rq, N, m, c, jj, y, envq);
-                const float2 r1 = r_pair(Rq, N, m, c + 1, jj, y + 2 * e2 - (1 << m), envq);
-                acc0 += 0.5f * (r0.x + fmaf(t.y, r1.x, A * t.x));
-                acc1 += 0.5f * (r0.y + fmaf(t.w, r1.y, A * t.z));
+            } else {
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                const int y = y0 + 2 * j;
+#pragma unroll
+                for (int up = 0; up < 2; ++up) {
+                    const int e2 = 2 * ii + 2 * up, jj = 2 * ii + up;
+                    const float A = c_cone[(1 << m) - 1 + jj];
+                    float4 t;
+                    if (top) {
+                        const int kk = e2 >> 1;
+                        const float4 nv = ld_pair(Tnear + (size_t)kk * S + y);
+                        const float4 fv = far_pair(Tfar + (size_t)kk * S, y + e2 - (1 << n), S);
+                        t = pair(merge(lo(nv), lo(fv)), merge(hi(nv), hi(fv)));
+                    } else {
+                        t = ld_pair(Tx + (size_t)e2 * S + y);
+                    }
+                    const float2 r0 = r_pair(Rq, N, m, c, jj, y, envq);
+                    const float2 r1 = r_pair(Rq, N, m, c + 1, jj, y + 2 * e2 - (1 << m), envq);
+                    acc0[j] += 0.5f * (r0.x + fmaf(t.y, r1.x, A * t.x));
+                    acc1[j] += 0.5f * (r0.y + fmaf(t.w, r1.y, A * t.z));
+                }
+            }
             }
         }
-        *reinterpret_cast<float2 *>(a.R + q * SS + (size_t)r * S + y) = make_float2(acc0, acc1);
+        float *out = a.R + q * SS + (size_t)r * S + y0;
+        if constexpr (P == 2) {
+            *reinterpret_cast<float4 *>(out) = make_float4(acc0[0], acc1[0], acc0[1], acc1[1]);
+        } else {
+            *reinterpret_cast<float2 *>(out) = make_float2(acc0[0], acc1[0]);
+        }
     }
 }
 
@@ -1450,10 +1603,10 @@ unsigned phase_tiles(const Phase &p) {
             const unsigned t = (unsigned)((S + p.a.seed.tile - 1) / p.a.seed.tile);
             return t * t;
         }
-        case PH_UP:
-            return cdiv((size_t)p.a.up.nq * t_level_entries(N, p.a.up.n) / 2, per);
+        case PH_UP:  // pairs of y per thread: one, two with 16-bit intervals
+            return cdiv((size_t)p.a.up.nq * t_level_entries(N, p.a.up.n) / (p.a.up.half ? 4 : 2), per);
         case PH_DT: return cdiv(4 * t_level_entries(N, p.a.dt.n) / 2, per);
-        case PH_DOWN: return cdiv((size_t)p.a.down.nq * SS / 2, per);
+        case PH_DOWN: return cdiv((size_t)p.a.down.nq * SS / (p.a.down.half ? 4 : 2), per);
         case PH_DOWN_ADJ: return cdiv(4 * SS / 2, per);
         case PH_BLUR:
         case PH_BLUR_ADJ:
