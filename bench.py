@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--only-forward", action="store_true",
                     help="time the forward only (for profiler runs)")
+    ap.add_argument("--half-intervals", action="store_true",
+                    help="with --only-forward: the 16-bit interval storage (for profiling)")
     ap.add_argument("--only-backward", action="store_true",
                     help="run hrc_backward only, --steps times (for profiler runs)")
     return ap.parse_args()
@@ -105,7 +107,8 @@ def main():
 
     # ---- forward: the metric ------------------------------------------------
     log(f"forward {S}x{S}: {args.warmup} warm-up, {args.steps} timed steps")
-    fwd_s = timed(lambda: ctx.hrc_forward(eps, sig, F), args.steps, args.warmup)
+    fwd_flags = _lib.HRC_FLAG_HALF_INTERVALS if (args.half_intervals and args.only_forward) else 0
+    fwd_s = timed(lambda: ctx.hrc_forward(eps, sig, F, flags=fwd_flags), args.steps, args.warmup)
     # ---- a plain device copy of 512 MB: the achievable-bandwidth reference ---
     nbytes = 512 << 20
     src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
