@@ -14,6 +14,8 @@
 // Storage (per quadrant, y = w fastest so that 64 lanes read 64 consecutive y):
 //   T_n  float2 (L, T)  [S >> n][2^n + 1][S]   index (x*(2^n+1) + k)*S + y
 //   R_n  float          [S >> n][2^n][S]       index ((x << n) | ii)*S + y
+// (T_n as a pair of IEEE halves instead, same index, in the forward with the
+// 16-bit storage of Section 5.)
 // Probe (n, x, y) sits at the centre of pixel (x*2^n, y).  Outside the grid
 // there is no light unless an environment map is set: an interval starting
 // off-grid is <0, 1>, an angular fluence off-grid is 0 (or the map's), and
