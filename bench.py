@@ -281,7 +281,16 @@ def main():
                         "speedup_vs_sequential": seq_s / batch_s,
                         "plan_s": plan_s, "workspace_GB": b.workspace_bytes / 1e9,
                         "autotuned": b.describe()}
-        del b, items
+        del b
+        # every scene inside the one persistent kernel (HRC_FLAG_BATCH_PERSISTENT):
+        # the launch shape the planner's split is measured against
+        log("batch with every scene in the persistent kernel")
+        bp = Batch(items, ctx, flags=_lib.HRC_FLAG_BATCH_PERSISTENT)
+        bp_s = timed(bp.launch, bsteps, 1)
+        out["batch"]["persistent_only"] = {"fwd_bwd_ms": bp_s * 1e3,
+                                           "speedup_vs_sequential": seq_s / bp_s,
+                                           "autotuned": bp.describe()}
+        del bp, items
         ctx.release_workspaces()
 
     # ---- the oracle on the host (reported baseline) ---------------------------
