@@ -22,10 +22,12 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
  *     device work is enqueued on it; calls return without synchronising.
  *   - The forward, backward and batch-launch calls allocate nothing and free
- *     nothing.  hrc_create and hrc_batch_plan allocate.
+ *     nothing.  hrc_create, hrc_set_environment (its first map) and
+ *     hrc_batch_plan allocate.
  *   - Argument checks run on the host before any device call, in this order:
- *     size (HRC_ERR_SHAPE), pointers (HRC_ERR_INVALID_ARG), workspace
- *     (HRC_ERR_WORKSPACE), context (HRC_ERR_INVALID_ARG).  A failed check
+ *     size (HRC_ERR_SHAPE), pointers (HRC_ERR_INVALID_ARG), flags
+ *     (HRC_ERR_UNSUPPORTED), workspace (HRC_ERR_WORKSPACE), context
+ *     (HRC_ERR_INVALID_ARG).  A failed check
  *     enqueues nothing.  Launch failures return HRC_ERR_HIP; faults inside
  *     kernels surface at the caller's next synchronisation.
  *   - Results are deterministic: every output element has exactly one writer
