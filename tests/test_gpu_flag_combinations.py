@@ -1,4 +1,4 @@
-"""Every combination of the forward's options on small ragged grids, each
+"""Every combination of the forward's options (and of the reverse's) on small ragged grids, each
 against the FP64 oracle: quadrant grouping, cross blur, environment light and
 16-bit interval storage (tolerances from tests/gpu_common.py)."""
 import itertools
@@ -56,4 +56,25 @@ def test_forward_option_combinations(ctx, S):
             assert_half_close(got, want, N, what)
         else:
             assert_forward_close(got, want, what)
+    ctx.set_environment(None)
+
+
+@pytest.mark.parametrize("S", [8, 32])
+def test_backward_option_combinations(ctx, S):
+    """The reverse with the blur's transpose and with environment light, alone
+    and together, against the oracle's reverse pass."""
+    from gpu_common import assert_grad_close
+    from oracle import hrc_vjp
+    eps, sig = _scene(S, 700 + S)
+    dF = np.random.default_rng(S).normal(size=(S, S)).astype(np.float32)
+    for blur, env in itertools.product((0, BLUR), (False, True)):
+        what = f"S={S} blur={bool(blur)} env={env}"
+        log(f"backward {what}")
+        ctx.set_environment(ENV if env else None)
+        ge, gs = ctx.hrc_backward(to_dev(eps), to_dev(sig), to_dev(dF), flags=blur)
+        torch.cuda.synchronize()
+        dG = oracle_blur.cross_blur_vjp(dF, sig) if blur else dF
+        re, rs = hrc_vjp.fluence_vjp(eps, sig, dG, environment=np.asarray(ENV) if env else None)
+        assert_grad_close(ge.cpu().numpy(), re, f"d eps {what}")
+        assert_grad_close(gs.cpu().numpy(), rs, f"d sigma {what}")
     ctx.set_environment(None)
