@@ -55,30 +55,129 @@ void size_tiles(Phase &p, int target) {
     p.U = (int)std::max(1u, std::min(U, 64u));
 }
 
-// Step t holds phase t of every scene that has one; every phase depends only
-// on the previous phase of its scene, hence only on the previous step.
-void order_items(Plan &pl, const std::vector<int> &first, const std::vector<int> &count) {
+// The buffers a pass reads and writes (device base pointers: every level of a
+// workspace and every field of a scene is its own buffer).  Pointers a pass
+// carries but does not read at its level are left out.
+void phase_access(const Phase &p, std::vector<const void *> &rd, std::vector<const void *> &wr) {
+    rd.clear();
+    wr.clear();
+    auto r = [&](const void *q) { if (q) rd.push_back(q); };
+    auto w = [&](const void *q) { if (q) wr.push_back(q); };
+    switch (p.kind) {
+        case PH_SEED: {
+            const SeedArgs &a = p.a.seed;
+            r(a.eps); r(a.sig);
+            if (a.first <= 0) w(a.T0);
+            if (a.first <= 1) w(a.T1);
+            w(a.T2);
+            break;
+        }
+        case PH_UP: r(p.a.up.Tp); w(p.a.up.T); break;
+        case PH_DOWN: {
+            const DownArgs &a = p.a.down;
+            if (a.n + 1 < a.N) { r(a.Rn1); r(a.Tn1); }
+            r(a.Tn);
+            w(a.R);
+            break;
+        }
+        case PH_TAIL: {
+            const TailArgs &a = p.a.tail;
+            r(a.eps); r(a.sig); r(a.R2);
+            if (a.accumulate) r(a.out);
+            w(a.out);
+            break;
+        }
+        case PH_GATHER_ADJ: r(p.a.ga.dF); w(p.a.ga.dR0); break;
+        case PH_DOWN_ADJ: {
+            const DownAdjArgs &a = p.a.da;
+            r(a.dR); r(a.Tn); r(a.Tn1);
+            w(a.dRn1);
+            break;
+        }
+        case PH_DT: {
+            const DTArgs &a = p.a.dt;
+            if (a.has_up) { r(a.Tn); r(a.dTn1); }
+            if (a.n < a.N) { r(a.dRn); r(a.Rn); }
+            if (a.n >= 1) r(a.dRm);
+            if (a.n + 1 < a.N) r(a.Rn1);
+            w(a.dT);
+            break;
+        }
+        case PH_SEED_ADJ: {
+            const SeedAdjArgs &a = p.a.sa;
+            r(a.eps); r(a.sig); r(a.dT0); r(a.dT1); r(a.dT2);
+            w(a.dE); w(a.dS);
+            break;
+        }
+        case PH_BLUR:
+        case PH_BLUR_ADJ: r(p.a.bl.in); r(p.a.bl.sig); w(p.a.bl.out); break;
+        default: break;
+    }
+}
+
+// Step of each pass of one scene's chain: one past the latest earlier pass it
+// depends on (it reads what that pass wrote, or writes what that pass read or
+// wrote), so independent passes (the reverse's merge-down adjoint beside the
+// recomputed merge up and merge down) share a step.
+std::vector<int> chain_steps(const std::vector<Phase> &chain) {
+    std::vector<int> step(chain.size(), 0);
+    std::vector<std::pair<const void *, int>> last_w, last_r;  // buffer, latest step
+    auto find = [](std::vector<std::pair<const void *, int>> &v, const void *q) -> int * {
+        for (auto &e : v)
+            if (e.first == q) return &e.second;
+        return nullptr;
+    };
+    std::vector<const void *> rd, wr;
+    for (size_t i = 0; i < chain.size(); ++i) {
+        phase_access(chain[i], rd, wr);
+        int s = 0;
+        for (const void *q : rd)
+            if (int *t = find(last_w, q)) s = std::max(s, *t + 1);
+        for (const void *q : wr) {
+            if (int *t = find(last_w, q)) s = std::max(s, *t + 1);
+            if (int *t = find(last_r, q)) s = std::max(s, *t + 1);
+        }
+        step[i] = s;
+        for (const void *q : rd) {
+            if (int *t = find(last_r, q)) *t = std::max(*t, s);
+            else last_r.push_back({q, s});
+        }
+        for (const void *q : wr) {
+            if (int *t = find(last_w, q)) *t = std::max(*t, s);
+            else last_w.push_back({q, s});
+        }
+    }
+    return step;
+}
+
+// Items in step order: step t holds, for every scene, its passes of step t
+// (chain_steps), so every pass depends only on passes of earlier steps.
+void order_items(Plan &pl, const std::vector<int> &first, const std::vector<int> &count,
+                 const std::vector<std::vector<int>> &steps) {
     pl.seg_start.clear();
     pl.seg_phase.clear();
     pl.seg_step.clear();
     pl.step_items.clear();
     unsigned pos = 0;
-    int max_count = 0;
-    for (int c : count) max_count = std::max(max_count, c);
-    for (int t = 0; t < max_count; ++t) {
+    int max_step = -1;
+    for (const auto &st : steps)
+        for (int t : st) max_step = std::max(max_step, t);
+    for (int t = 0; t <= max_step; ++t) {
         unsigned in_step = 0;
         for (size_t s = 0; s < first.size(); ++s) {
-            if (t >= count[s]) continue;
-            const int gi = first[s] + t;
-            // whole groups of tiles; the bodies store nothing for tiles past
-            // the phase's own count
-            const unsigned tiles =
-                (phase_tiles(pl.phases[gi]) + kBatchQuarters - 1) / kBatchQuarters;
-            pl.seg_start.push_back(pos);
-            pl.seg_phase.push_back(gi);
-            pl.seg_step.push_back(t);
-            pos += tiles;
-            in_step += tiles;
+            for (int j = 0; j < count[s]; ++j) {
+                if (steps[s][j] != t) continue;
+                const int gi = first[s] + j;
+                // whole groups of tiles; the bodies store nothing for tiles
+                // past the phase's own count
+                const unsigned tiles =
+                    (phase_tiles(pl.phases[gi]) + kBatchQuarters - 1) / kBatchQuarters;
+                pl.seg_start.push_back(pos);
+                pl.seg_phase.push_back(gi);
+                pl.seg_step.push_back(t);
+                pos += tiles;
+                in_step += tiles;
+            }
         }
         pl.step_items.push_back(in_step);
     }
@@ -174,15 +273,19 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
                                          kMaxPhases);
         chains[i].assign(tmp, tmp + n);
     }
+    std::vector<std::vector<int>> steps(count);
+    for (int i = 0; i < count; ++i) steps[i] = chain_steps(chains[i]);
     // scenes of log2 size >= min_direct run as their own kernels
     Plan pl;
     std::vector<int> first, np;
+    std::vector<std::vector<int>> psteps;  // steps of the persistent kernel's scenes
     std::vector<const Phase *> direct_list;
     int n_direct = 0;
     auto split = [&](int min_direct) {
         pl = Plan();
         first.clear();
         np.clear();
+        psteps.clear();
         direct_list.clear();
         n_direct = 0;
         for (int i = 0; i < count; ++i) {
@@ -192,6 +295,7 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
             } else {
                 first.push_back((int)pl.phases.size());
                 np.push_back((int)chains[i].size());
+                psteps.push_back(steps[i]);
                 pl.phases.insert(pl.phases.end(), chains[i].begin(), chains[i].end());
             }
         }
@@ -220,7 +324,7 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
     auto upload = [&](int target, unsigned chunk) -> bool {
         if (pl.phases.empty()) return true;
         for (Phase &p : pl.phases) size_tiles(p, target);
-        order_items(pl, first, np);
+        order_items(pl, first, np, psteps);
         tables = BatchTables{d_phases, d_seg_start, d_seg_phase, d_seg_step, d_step_items,
                              (int)pl.seg_start.size(), (int)pl.step_items.size(), pl.total_items,
                              chunk};
