@@ -241,7 +241,8 @@ typedef struct hrc_batch hrc_batch;
 /* Plan a batch: copies the scene table, sizes and allocates the batch's own
  * workspace (device memory owned by the batch), and captures one batch in a
  * HIP graph: a persistent kernel that runs the scenes' passes tile by tile,
- * preceded by the passes of the scenes from a size up as kernels of their own
+ * in steps ordered by what each pass reads and writes (a scene's independent
+ * passes share a step), preceded by the passes of the scenes from a size up as kernels of their own
  * (a pass of a large scene fills the GPU by itself, and there the persistent
  * kernel's synchronisation between passes costs more than the launch gaps it
  * saves).  The autotuner picks that size (possibly none), the kernel variant,
@@ -254,7 +255,8 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count,
                           unsigned flags, void *stream, hrc_batch **out);
 
 /* Run a planned batch on `stream`: one graph launch; results are bitwise equal
- * to hrc_forward / hrc_backward on each scene. */
+ * to hrc_forward / hrc_backward on each scene (on a context without an
+ * environment map: batches run without one). */
 hrc_status hrc_batch_launch(hrc_batch *batch, void *stream);
 
 /* Bytes of device memory the batch owns (workspace and scheduler state). */
