@@ -10,7 +10,7 @@ import torch
 from oracle import blur as oracle_blur
 from oracle import hrc as oracle
 from oracle import hrc_vjp
-from scenes import config3, scene_like_512
+from scenes import config2, config3, scene_like_512
 
 pytestmark = pytest.mark.gpu
 
@@ -36,6 +36,10 @@ def _scenes():
     out = [("random8", *_random_scene(8, 11)), ("random64", *_random_scene(64, 12))]
     sc = scene_like_512(128, 13, 6, 10)
     out.append(("boxes128", sc.eps, sc.sigma))
+    sc = scene_like_512(256, 14, 12, 20)
+    out.append(("boxes256", sc.eps, sc.sigma))
+    sc = config2()
+    out.append(("config512", sc.eps, sc.sigma))
     return out
 
 
@@ -62,7 +66,8 @@ def test_unblurred_forward_unchanged_by_the_flag_bit(ctx):
     assert_forward_close(b.cpu().numpy(), want, "blur of the GPU's own fluence")
 
 
-@pytest.mark.parametrize("case", [0, 1, 2], ids=["random8", "random64", "boxes128"])
+@pytest.mark.parametrize("case", [0, 1, 2, 3, 4],
+                         ids=["random8", "random64", "boxes128", "boxes256", "config512"])
 def test_blurred_backward_matches_oracle(ctx, case):
     name, eps, sig = _scenes()[case]
     log(f"blurred backward {name}")

@@ -9,7 +9,7 @@ import torch
 
 from oracle import hrc as oracle
 from oracle import hrc_vjp
-from scenes import scene_like_512
+from scenes import config2, scene_like_512
 
 pytestmark = pytest.mark.gpu
 
@@ -60,11 +60,21 @@ def test_environment_forward_matches_oracle(ctx, S, K):
     assert_forward_close(F.cpu().numpy(), want, f"environment S={S}")
 
 
-@pytest.mark.parametrize("S", [8, 64])
+@pytest.mark.parametrize("S", [8, 64, 256, 512])
 def test_environment_backward_matches_oracle(ctx, S):
+    """Up to the 512x512 configuration's scene (opaque boxes and fog), whose
+    upper levels (N = 9) read the map through every off-grid lookup of the
+    merge-down and interval adjoints."""
     log(f"environment backward S={S}")
-    eps, sig = _random_scene(S, 40 + S)
-    env = _env(12, 7 + S)
+    if S == 512:
+        sc = config2()
+        eps, sig = sc.eps, sc.sigma
+    elif S == 256:
+        sc = scene_like_512(S, 41, 12, 20)
+        eps, sig = sc.eps, sc.sigma
+    else:
+        eps, sig = _random_scene(S, 40 + S)
+    env = _env(12 if S < 256 else 64, 7 + S)
     dF = np.random.default_rng(S).normal(size=(S, S)).astype(np.float32)
     ctx.set_environment(env)
     ge, gs = ctx.hrc_backward(to_dev(eps), to_dev(sig), to_dev(dF))

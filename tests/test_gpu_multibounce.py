@@ -44,7 +44,7 @@ def test_multibounce_forward_matches_oracle(ctx, S, K):
                          f"bounces S={S} K={K}")
 
 
-@pytest.mark.parametrize("S,K", [(8, 1), (16, 3), (64, 2)])
+@pytest.mark.parametrize("S,K", [(8, 1), (16, 3), (64, 2), (256, 3)])
 def test_multibounce_backward_matches_oracle(ctx, S, K):
     log(f"multibounce backward S={S} K={K}")
     eps, sig, alb = _scene(S, 100 + S + K)
