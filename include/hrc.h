@@ -50,7 +50,8 @@ typedef enum {
     HRC_ERR_WORKSPACE = -3,    /* workspace smaller than hrc_workspace_bytes */
     HRC_ERR_HIP = -4,          /* a HIP runtime call or kernel launch failed */
     HRC_ERR_UNSUPPORTED = -5,  /* unknown flag bits, or a flag the call does not take */
-    HRC_ERR_INPUT = -6         /* HRC_FLAG_VALIDATE found a negative or non-finite input */
+    HRC_ERR_INPUT = -6,        /* HRC_FLAG_VALIDATE found a negative or non-finite input */
+    HRC_ERR_TIMEOUT = -7       /* a batch's dependency wait gave up (hrc_batch_status) */
 } hrc_status;
 
 #define HRC_MIN_LOG2 3
@@ -240,26 +241,52 @@ typedef struct hrc_batch hrc_batch;
 
 /* Plan a batch: copies the scene table, sizes and allocates the batch's own
  * workspace (device memory owned by the batch), and captures one batch in a
- * HIP graph: a persistent kernel that runs the scenes' passes tile by tile,
- * in steps ordered by what each pass reads and writes (a scene's independent
- * passes share a step), preceded by the passes of the scenes from a size up as kernels of their own
- * (a pass of a large scene fills the GPU by itself, and there the persistent
- * kernel's synchronisation between passes costs more than the launch gaps it
- * saves).  The autotuner picks that size (possibly none), the kernel variant,
- * the tile sizes and the claim chunk, timing each candidate batch on a stream
- * of its own, on the caller's buffers.  The scene pointers are baked in: later
- * launches read and write the same buffers.  flags: 0, or HRC_FLAG_BATCH_FULL
- * or HRC_FLAG_BATCH_DENSE, each optionally with HRC_FLAG_BATCH_PERSISTENT
- * (HRC_ERR_UNSUPPORTED otherwise).  Synchronises `stream` first. */
+ * HIP graph.  The scenes run in one persistent kernel that works through one
+ * queue of passes per XCD (accelerator complex die) of the device, each scene
+ * pinned to one queue and the queues balanced by work: every block serves the
+ * queue of the XCD it runs on, so a queue's passes exchange data through that
+ * XCD's L2.  A queue runs its passes tile by tile in steps ordered by what each
+ * pass reads and writes (a scene's independent passes share a step); the
+ * scenes of a queue share a few workspace slots, the scenes of one slot
+ * running one after another.  Optionally the scenes from a size up run first,
+ * pass by pass, as kernels of their own in the same graph (a pass of a large
+ * scene fills the GPU by itself).  The autotuner picks that size (possibly
+ * none), the queue layout (per XCD, or one queue for the whole device whose
+ * steps then synchronise through an L2 write-back), the slots per queue, the
+ * kernel variant, the tile sizes and the claim chunk, timing each candidate
+ * batch on a stream of its own, on the caller's buffers.  The scene pointers are
+ * baked in: later launches read and write the same buffers; no scene's
+ * outputs may overlap another scene's inputs or outputs.  flags: 0, or
+ * HRC_FLAG_BATCH_FULL or HRC_FLAG_BATCH_DENSE, each optionally with
+ * HRC_FLAG_BATCH_PERSISTENT (HRC_ERR_UNSUPPORTED otherwise).  Synchronises
+ * `stream` first.  HRC_ERR_TIMEOUT if a dependency wait gave up while timing
+ * the candidates. */
 hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count,
                           unsigned flags, void *stream, hrc_batch **out);
 
 /* Run a planned batch on `stream`: one graph launch; results are bitwise equal
  * to hrc_forward / hrc_backward on each scene (on a context without an
- * environment map: batches run without one). */
+ * environment map: batches run without one).  Does not wait for the launch:
+ * hrc_batch_status reports whether it completed every pass. */
 hrc_status hrc_batch_launch(hrc_batch *batch, void *stream);
 
-/* Bytes of device memory the batch owns (workspace and scheduler state). */
+/* Synchronises `stream`, then reports HRC_ERR_TIMEOUT if, in a launch of this
+ * batch since the previous hrc_batch_status call, a dependency wait of the
+ * persistent kernel gave up (no progress for about a second) or a queue was
+ * left unfinished: that launch's results are incomplete (every kernel still
+ * ran to its end).  Clears the report.  HRC_OK otherwise; HRC_ERR_INVALID_ARG
+ * for a NULL batch, HRC_ERR_HIP if a HIP call failed. */
+hrc_status hrc_batch_status(hrc_batch *batch, void *stream);
+
+/* Failure testing: with spins > 0, every dependency wait of later launches
+ * waits for one group more than its step holds (a count never reached) and
+ * gives up after `spins` polls, so the wait's error path runs and
+ * hrc_batch_status reports HRC_ERR_TIMEOUT while every kernel still exits;
+ * spins = 0 restores normal waits.  Copies synchronously: call it when no
+ * launch of the batch is in flight. */
+hrc_status hrc_batch_debug_waits(hrc_batch *batch, unsigned spins);
+
+/* Bytes of device memory the batch owns (workspace, scheduler tables and state). */
 size_t hrc_batch_workspace_bytes(const hrc_batch *batch);
 
 /* What the autotuner chose for a planned batch: the persistent kernel variant
@@ -271,6 +298,23 @@ size_t hrc_batch_workspace_bytes(const hrc_batch *batch);
  * function; HRC_ERR_INVALID_ARG for a NULL batch. */
 hrc_status hrc_batch_describe(const hrc_batch *batch, int *variant, int *grid,
                               int *target_tiles, int *chunk, int *direct_scenes);
+
+/* The queue layout the autotuner chose: the persistent kernel's queues, 1 if
+ * each serves one XCD (0: one queue for the whole device), and the workspace
+ * slots per queue (0: one per scene).  Any output pointer may be NULL.  Pure
+ * host function; HRC_ERR_INVALID_ARG for a NULL batch. */
+hrc_status hrc_batch_queues(const hrc_batch *batch, int *queues, int *xcd_local, int *slots);
+
+/* Every candidate the autotuner timed, in the order timed: *count receives
+ * their number; for the first min(max, count), desc[7 i .. 7 i + 6] receives
+ * (log2 size from which scenes ran as kernels of their own, 0 for none;
+ * queues; 1 if one queue per XCD; workspace slots per queue, 0 for one per
+ * scene; kernel variant; target tiles per pass; claim chunk) and ms[i] the
+ * whole batch's time in milliseconds.  Pure host function;
+ * HRC_ERR_INVALID_ARG for a NULL batch or count, a negative max, or NULL
+ * arrays with max > 0. */
+hrc_status hrc_batch_candidates(const hrc_batch *batch, int max, int *count, int *desc,
+                                float *ms);
 
 /* Destroy a batch (NULL-safe); frees its device memory and graph. */
 void hrc_batch_destroy(hrc_batch *batch);

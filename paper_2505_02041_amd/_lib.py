@@ -18,6 +18,7 @@ HRC_ERR_WORKSPACE = -3
 HRC_ERR_HIP = -4
 HRC_ERR_UNSUPPORTED = -5
 HRC_ERR_INPUT = -6
+HRC_ERR_TIMEOUT = -7
 HRC_MIN_LOG2 = 3
 HRC_MAX_LOG2 = 12
 HRC_FLAG_VALIDATE = 0x1
@@ -87,6 +88,14 @@ SIGNATURES = {
                                           ctypes.POINTER(ctypes.c_int),
                                           ctypes.POINTER(ctypes.c_int),
                                           ctypes.POINTER(ctypes.c_int)]),
+    "hrc_batch_status": (ctypes.c_int, [_vp, _vp]),
+    "hrc_batch_debug_waits": (ctypes.c_int, [_vp, ctypes.c_uint]),
+    "hrc_batch_queues": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_int)]),
+    "hrc_batch_candidates": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                            ctypes.POINTER(ctypes.c_int),
+                                            ctypes.POINTER(ctypes.c_float)]),
     "hrc_batch_destroy": (None, [_vp]),
 }
 

@@ -275,6 +275,7 @@ const char *hrc_status_string(hrc_status s) {
         case HRC_ERR_HIP: return "HRC_ERR_HIP: a HIP runtime call or kernel launch failed";
         case HRC_ERR_UNSUPPORTED: return "HRC_ERR_UNSUPPORTED: unknown flag bits, or a flag this call does not take";
         case HRC_ERR_INPUT: return "HRC_ERR_INPUT: negative or non-finite emission or attenuation";
+        case HRC_ERR_TIMEOUT: return "HRC_ERR_TIMEOUT: a dependency wait of the batch gave up; that launch's results are incomplete";
     }
     return "HRC: unknown status";
 }

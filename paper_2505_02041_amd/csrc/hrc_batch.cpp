@@ -1,15 +1,16 @@
 // Batched forward + backward: many scenes of different power-of-two sizes in one
 // HIP graph launch.  The scenes go to one persistent kernel that schedules
-// their passes tile by tile; scenes from a size up (chosen by the autotuner,
-// possibly none) instead run pass by pass as their own kernels in the same
-// graph, where one pass fills the GPU and the persistent kernel's per-pass
-// synchronisation costs more than the launch gaps it saves.  Tile sizes,
-// kernel variant, claim chunk and that size are picked by timing candidates on
-// the device.
+// their passes tile by tile, one queue per XCD, each scene pinned to one
+// queue; scenes from a size up (chosen by the autotuner, possibly none) can
+// instead run pass by pass as their own kernels in the same graph, ahead of
+// the persistent kernel.  The queues' scene lists, how many scenes of a queue
+// share a workspace slot, the tile sizes, kernel variant and claim chunk are
+// picked by timing candidates on the device.
 #include <stdint.h>
 #include <stdlib.h>
 
 #include <algorithm>
+#include <numeric>
 #include <vector>
 
 #include "../../include/hrc.h"
@@ -19,8 +20,11 @@ using namespace hrc;
 
 struct hrc_batch {
     int device = 0;
-    char *dmem = nullptr;          // scene workspaces, then the scheduler tables
+    char *dmem = nullptr;          // the scenes' workspaces
     size_t dmem_bytes = 0;
+    char *tmem = nullptr;          // scheduler tables and words
+    size_t tmem_bytes = 0;
+    unsigned *sched = nullptr;     // scheduler words inside tmem
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int target_tiles = 0;          // chosen by the autotuner
@@ -28,18 +32,17 @@ struct hrc_batch {
     int variant = 0;               // persistent kernel variant, chosen by the autotuner
     int grid = 0;
     int direct = 0;                // scenes run as their own kernels, chosen by the autotuner
+    int queues = 0;                // queues of the persistent kernel
+    int xcd_local = 0;             // one queue per XCD
+    int slots = 0;                 // workspace slots per queue (0: one per scene)
+    std::vector<int> cand_desc;    // every timed candidate: kCandFields ints each
+    std::vector<float> cand_ms;    // and its time
 };
+
+// Fields of a timed candidate as hrc_batch_candidates reports them.
+constexpr int kCandFields = 7;
 
 namespace {
-
-struct Plan {
-    std::vector<Phase> phases;     // all scenes, each scene's passes in order
-    std::vector<unsigned> seg_start;
-    std::vector<int> seg_phase;
-    std::vector<int> seg_step;
-    std::vector<unsigned> step_items;
-    unsigned total_items = 0;
-};
 
 // Elements per thread for a phase so that it splits into at most `target`
 // tiles (tiles of 256*U outputs); fixed-shape phases keep their own tiles.
@@ -150,38 +153,163 @@ std::vector<int> chain_steps(const std::vector<Phase> &chain) {
     return step;
 }
 
-// Items in step order: step t holds, for every scene, its passes of step t
-// (chain_steps), so every pass depends only on passes of earlier steps.
-void order_items(Plan &pl, const std::vector<int> &first, const std::vector<int> &count,
-                 const std::vector<std::vector<int>> &steps) {
-    pl.seg_start.clear();
-    pl.seg_phase.clear();
-    pl.seg_step.clear();
-    pl.step_items.clear();
-    unsigned pos = 0;
-    int max_step = -1;
-    for (const auto &st : steps)
-        for (int t : st) max_step = std::max(max_step, t);
-    for (int t = 0; t <= max_step; ++t) {
-        unsigned in_step = 0;
-        for (size_t s = 0; s < first.size(); ++s) {
-            for (int j = 0; j < count[s]; ++j) {
-                if (steps[s][j] != t) continue;
-                const int gi = first[s] + j;
-                // whole groups of tiles; the bodies store nothing for tiles
-                // past the phase's own count
-                const unsigned tiles =
-                    (phase_tiles(pl.phases[gi]) + kBatchQuarters - 1) / kBatchQuarters;
-                pl.seg_start.push_back(pos);
-                pl.seg_phase.push_back(gi);
-                pl.seg_step.push_back(t);
-                pos += tiles;
-                in_step += tiles;
-            }
+// One arrangement of the batch: which scenes run as their own kernels, how the
+// others are spread over queues and workspace slots, and the resulting tables.
+struct Arrangement {
+    int min_direct = HRC_MAX_LOG2 + 1;  // scenes of this log2 size and up run direct
+    int nqueues = 1;
+    int slots = 0;                      // workspace slots per queue; 0 = one per scene
+    int target = 0;                     // tiles per phase
+    std::vector<Phase> direct;          // direct scenes' passes in order
+    std::vector<Phase> phases;          // the persistent kernel's passes
+    std::vector<unsigned> seg_start;
+    std::vector<int> seg_phase, seg_step;
+    std::vector<unsigned> step_items;
+    int q_seg[kMaxQueues + 1] = {};
+    int q_step[kMaxQueues + 1] = {};
+    unsigned q_items[kMaxQueues] = {};
+    int n_direct = 0;
+    size_t ws_bytes = 0;                // workspace the arrangement needs
+};
+
+// Relative amount of work of a scene: its pixels times its passes.
+double scene_cost(const hrc_scene &sc) {
+    const double S = double(1 << sc.log2_size);
+    return S * S * (sc.grad_fluence ? 2.0 : 1.0) * (sc.log2_size + 2);
+}
+
+// Lays out the workspaces at `base` and builds the tables of an arrangement
+// (with a null base: only the workspace size, ws_bytes).
+// The direct scenes run one after another, so they share one workspace; the
+// persistent kernel runs after them, so its slots reuse the same memory.  A
+// queue's scenes (largest first, greedily balanced over the queues by cost)
+// go round-robin to its slots; the scenes of one slot run one after another
+// (a scene's first step follows the previous one's last), scenes of different
+// slots side by side, and within a scene independent passes share a step.
+// Step t of a queue holds, for every scene of the queue in order, its passes
+// of step t.
+void arrange(Arrangement &ar, const hrc_scene *scenes, int count, char *base) {
+    ar.direct.clear();
+    ar.phases.clear();
+    ar.seg_start.clear();
+    ar.seg_phase.clear();
+    ar.seg_step.clear();
+    ar.step_items.clear();
+    ar.n_direct = 0;
+    std::vector<Layout> lay(count);
+    for (int i = 0; i < count; ++i)
+        lay[i] = make_layout(scenes[i].log2_size, scenes[i].grad_fluence != nullptr);
+    auto solve = [&](int i, char *ws, bool persistent, std::vector<Phase> &out) {
+        const hrc_scene &sc = scenes[i];
+        SolveBuffers sb{sc.emission, sc.sigma_t, sc.fluence, sc.grad_fluence, sc.grad_emission,
+                        sc.grad_sigma_t};
+        Phase tmp[kMaxPhases];
+        const int n = build_solve_phases(Ws{ws, lay[i]}, sb, sc.grad_fluence != nullptr, nullptr,
+                                         tmp, kMaxPhases);
+        out.assign(tmp, tmp + n);
+        if (persistent)
+            for (Phase &p : out) size_tiles(p, ar.target);
+    };
+    // direct scenes, in the caller's order, in one shared workspace
+    size_t direct_bytes = 0;
+    std::vector<int> pers, direct;
+    for (int i = 0; i < count; ++i) {
+        if (scenes[i].log2_size >= ar.min_direct) {
+            direct.push_back(i);
+            direct_bytes = std::max(direct_bytes, align256(lay[i].total));
+        } else {
+            pers.push_back(i);
         }
-        pl.step_items.push_back(in_step);
     }
-    pl.total_items = pos;
+    ar.n_direct = (int)direct.size();
+    // persistent scenes: largest first, each to the least-loaded queue
+    std::stable_sort(pers.begin(), pers.end(), [&](int a, int b) {
+        return scene_cost(scenes[a]) > scene_cost(scenes[b]);
+    });
+    const int nq = ar.nqueues;
+    std::vector<std::vector<int>> queue(nq);
+    std::vector<double> load(nq, 0.0);
+    for (int i : pers) {
+        const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        queue[q].push_back(i);
+        load[q] += scene_cost(scenes[i]);
+    }
+    // slots: sized to the largest scene they hold, laid out queue by queue
+    size_t off = 0;
+    std::vector<int> slot_of(count, -1);
+    std::vector<size_t> slot_base;
+    for (int q = 0; q < nq; ++q) {
+        const int n = (int)queue[q].size();
+        if (n == 0) continue;
+        const int k = ar.slots > 0 ? std::min(ar.slots, n) : n;
+        std::vector<size_t> size(k, 0);
+        for (int j = 0; j < n; ++j)
+            size[j % k] = std::max(size[j % k], align256(lay[queue[q][j]].total));
+        for (int j = 0; j < n; ++j) slot_of[queue[q][j]] = (int)slot_base.size() + j % k;
+        for (int s = 0; s < k; ++s) {
+            slot_base.push_back(off);
+            off += size[s];
+        }
+    }
+    ar.ws_bytes = std::max(direct_bytes, off);
+    if (!base) return;  // sizes only
+    std::vector<Phase> chain;
+    for (int i : direct) {
+        solve(i, base, false, chain);
+        ar.direct.insert(ar.direct.end(), chain.begin(), chain.end());
+    }
+    // per queue: each scene's steps, offset past the previous scene of its slot
+    int total_steps = 0, seg = 0;
+    for (int q = 0; q < nq; ++q) {
+        ar.q_seg[q] = seg;
+        ar.q_step[q] = total_steps;
+        const int n = (int)queue[q].size();
+        std::vector<std::vector<Phase>> chains(n);
+        std::vector<std::vector<int>> steps(n);
+        std::vector<int> first(n);
+        std::vector<int> slot_next(slot_base.size(), 0);  // first free step of each slot
+        int nsteps = 0;
+        for (int j = 0; j < n; ++j) {
+            const int i = queue[q][j];
+            solve(i, base + slot_base[slot_of[i]], true, chains[j]);
+            steps[j] = chain_steps(chains[j]);
+            const int o = slot_next[slot_of[i]];
+            int last = o;
+            for (int &t : steps[j]) {
+                t += o;
+                last = std::max(last, t);
+            }
+            slot_next[slot_of[i]] = last + 1;
+            nsteps = std::max(nsteps, last + 1);
+            first[j] = (int)ar.phases.size();
+            ar.phases.insert(ar.phases.end(), chains[j].begin(), chains[j].end());
+        }
+        unsigned pos = 0;
+        for (int t = 0; t < nsteps; ++t) {
+            unsigned in_step = 0;
+            for (int j = 0; j < n; ++j) {
+                for (size_t k = 0; k < chains[j].size(); ++k) {
+                    if (steps[j][k] != t) continue;
+                    const int gi = first[j] + (int)k;
+                    // whole groups of tiles; the bodies store nothing for tiles
+                    // past the phase's own count
+                    const unsigned groups =
+                        (phase_tiles(ar.phases[gi]) + kBatchQuarters - 1) / kBatchQuarters;
+                    ar.seg_start.push_back(pos);
+                    ar.seg_phase.push_back(gi);
+                    ar.seg_step.push_back(t);
+                    pos += groups;
+                    in_step += groups;
+                    ++seg;
+                }
+            }
+            ar.step_items.push_back(in_step);
+        }
+        ar.q_items[q] = pos;
+        total_steps += nsteps;
+    }
+    ar.q_seg[nq] = seg;
+    ar.q_step[nq] = total_steps;
 }
 
 void free_batch(hrc_batch *b) {
@@ -190,7 +318,28 @@ void free_batch(hrc_batch *b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->dmem) (void)hipFree(b->dmem);
+    if (b->tmem) (void)hipFree(b->tmem);
     delete b;
+}
+
+// Queues the persistent kernel can use on this device with `grid` blocks: the
+// number of XCDs if every XCD runs at least one block of the grid (probed),
+// else 0.
+int probe_xcds(int grid, unsigned *dbuf, hipStream_t s) {
+    if (launch_xcd_probe(dbuf, grid, s) != hipSuccess) return 0;
+    std::vector<unsigned> h(grid);
+    if (hipMemcpyAsync(h.data(), dbuf, grid * sizeof(unsigned), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return 0;
+    unsigned hi = 0;
+    for (unsigned x : h) hi = std::max(hi, x);
+    if (hi >= (unsigned)kMaxQueues) return 0;
+    std::vector<int> per(hi + 1, 0);
+    for (unsigned x : h) ++per[x];
+    for (int c : per)
+        if (c == 0) return 0;
+    return (int)hi + 1;
 }
 
 }  // namespace
@@ -229,19 +378,12 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
     hrc_batch *b = new hrc_batch();
     b->device = ctx->device;
 
-    // ---- device memory: per-scene workspaces, then scheduler tables --------
-    std::vector<Layout> layouts(count);
-    std::vector<size_t> ws_off(count);
-    size_t off = 0;
-    for (int i = 0; i < count; ++i) {
-        const bool bwd = scenes[i].grad_fluence != nullptr;
-        layouts[i] = make_layout(scenes[i].log2_size, bwd);
-        ws_off[i] = off;
-        off += align256(layouts[i].total);
-    }
-    const size_t ws_total = off;
+    // ---- device memory: scheduler tables (sized for the most phases and
+    // steps any arrangement can have), then the workspace of the arrangement
+    // that needs the most (every persistent scene in a slot of its own) ------
     const size_t max_phases = (size_t)count * kMaxPhases;
-    const size_t phases_off = ws_total;
+    size_t off = 0;
+    const size_t phases_off = off;
     off += align256(max_phases * sizeof(Phase));
     const size_t seg_start_off = off;
     off += align256(max_phases * sizeof(unsigned));
@@ -250,107 +392,107 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
     const size_t seg_step_off = off;
     off += align256(max_phases * sizeof(int));
     const size_t step_items_off = off;
-    off += align256(kMaxPhases * sizeof(unsigned));
-    const size_t sched_off = off;  // claim counter, error word, one count per step
-    off += align256(sched_words(kMaxPhases) * sizeof(unsigned));
-    b->dmem_bytes = off;
-    if (hipMalloc(&b->dmem, b->dmem_bytes) != hipSuccess) {
+    off += align256(max_phases * sizeof(unsigned));
+    const size_t sched_off = off;
+    off += align256(sched_words(kMaxQueues, (int)max_phases) * sizeof(unsigned));
+    constexpr int kMaxProbe = 1 << 14;  // blocks of a probed grid
+    const size_t probe_off = off;
+    off += align256(kMaxProbe * sizeof(unsigned));
+    b->tmem_bytes = off;
+    size_t ws_max = 0;
+    for (int i = 0; i < count; ++i)
+        ws_max += align256(make_layout(scenes[i].log2_size, scenes[i].grad_fluence != nullptr).total);
+    if (hipMalloc(&b->tmem, b->tmem_bytes) != hipSuccess) {
+        b->tmem = nullptr;
+        free_batch(b);
+        return HRC_ERR_HIP;
+    }
+    if (hipMalloc(&b->dmem, ws_max) != hipSuccess) {
         b->dmem = nullptr;
         free_batch(b);
         return HRC_ERR_HIP;
     }
-
-    // ---- phase chains: each scene's passes (the persistent kernel's copies get
-    // its own tile sizes; the direct ones keep the standalone kernels')
-    std::vector<std::vector<Phase>> chains(count);
-    for (int i = 0; i < count; ++i) {
-        const hrc_scene &sc = scenes[i];
-        Ws w{b->dmem + ws_off[i], layouts[i]};
-        SolveBuffers sb{sc.emission, sc.sigma_t, sc.fluence, sc.grad_fluence, sc.grad_emission,
-                        sc.grad_sigma_t};
-        Phase tmp[kMaxPhases];
-        const int n = build_solve_phases(w, sb, sc.grad_fluence != nullptr, nullptr, tmp,
-                                         kMaxPhases);
-        chains[i].assign(tmp, tmp + n);
+    b->dmem_bytes = ws_max;
+    Phase *d_phases = reinterpret_cast<Phase *>(b->tmem + phases_off);
+    unsigned *d_seg_start = reinterpret_cast<unsigned *>(b->tmem + seg_start_off);
+    int *d_seg_phase = reinterpret_cast<int *>(b->tmem + seg_phase_off);
+    int *d_seg_step = reinterpret_cast<int *>(b->tmem + seg_step_off);
+    unsigned *d_step_items = reinterpret_cast<unsigned *>(b->tmem + step_items_off);
+    b->sched = reinterpret_cast<unsigned *>(b->tmem + sched_off);
+    // error word and wait configuration start at zero (outside any graph)
+    if (hipMemset(b->sched, 0, (size_t)kSchedExit * kSchedStride * sizeof(unsigned)) !=
+        hipSuccess) {
+        free_batch(b);
+        return HRC_ERR_HIP;
     }
-    std::vector<std::vector<int>> steps(count);
-    for (int i = 0; i < count; ++i) steps[i] = chain_steps(chains[i]);
-    // scenes of log2 size >= min_direct run as their own kernels
-    Plan pl;
-    std::vector<int> first, np;
-    std::vector<std::vector<int>> psteps;  // steps of the persistent kernel's scenes
-    std::vector<const Phase *> direct_list;
-    int n_direct = 0;
-    auto split = [&](int min_direct) {
-        pl = Plan();
-        first.clear();
-        np.clear();
-        psteps.clear();
-        direct_list.clear();
-        n_direct = 0;
-        for (int i = 0; i < count; ++i) {
-            if (scenes[i].log2_size >= min_direct) {
-                ++n_direct;
-                for (const Phase &p : chains[i]) direct_list.push_back(&p);
-            } else {
-                first.push_back((int)pl.phases.size());
-                np.push_back((int)chains[i].size());
-                psteps.push_back(steps[i]);
-                pl.phases.insert(pl.phases.end(), chains[i].begin(), chains[i].end());
-            }
-        }
-    };
-
-    int grids[kPersistentVariants];  // resident blocks of each kernel variant
-    for (int v = 0; v < kPersistentVariants; ++v) {
-        int per_cu = 0;
-        if (persistent_occupancy(v, &per_cu) != hipSuccess || per_cu <= 0) per_cu = 1;
-        grids[v] = ctx->num_cus * per_cu;
-    }
-
-    Phase *d_phases = reinterpret_cast<Phase *>(b->dmem + phases_off);
-    unsigned *d_seg_start = reinterpret_cast<unsigned *>(b->dmem + seg_start_off);
-    int *d_seg_phase = reinterpret_cast<int *>(b->dmem + seg_phase_off);
-    int *d_seg_step = reinterpret_cast<int *>(b->dmem + seg_step_off);
-    unsigned *d_step_items = reinterpret_cast<unsigned *>(b->dmem + step_items_off);
-    unsigned *d_sched = reinterpret_cast<unsigned *>(b->dmem + sched_off);
 
     hipStream_t cap = nullptr;
     if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
         free_batch(b);
         return HRC_ERR_HIP;
     }
+
+    // resident blocks of each kernel variant, and the XCDs their grids reach
+    int grids[kPersistentVariants], xcds[kPersistentVariants];
+    for (int v = 0; v < kPersistentVariants; ++v) {
+        int per_cu = 0;
+        if (persistent_occupancy(v, &per_cu) != hipSuccess || per_cu <= 0) per_cu = 1;
+        grids[v] = ctx->num_cus * per_cu;
+        xcds[v] = grids[v] <= kMaxProbe
+                      ? probe_xcds(grids[v], reinterpret_cast<unsigned *>(b->tmem + probe_off), cap)
+                      : 0;
+    }
+
+    Arrangement ar;
     BatchTables tables{};
-    auto upload = [&](int target, unsigned chunk) -> bool {
-        if (pl.phases.empty()) return true;
-        for (Phase &p : pl.phases) size_tiles(p, target);
-        order_items(pl, first, np, psteps);
-        tables = BatchTables{d_phases, d_seg_start, d_seg_phase, d_seg_step, d_step_items,
-                             (int)pl.seg_start.size(), (int)pl.step_items.size(), pl.total_items,
-                             chunk};
+    int variant = 0;
+    unsigned chunk = 1;
+    bool xcd_local = false;
+    auto upload = [&]() -> bool {
+        tables = BatchTables{};
+        tables.phases = d_phases;
+        tables.seg_start = d_seg_start;
+        tables.seg_phase = d_seg_phase;
+        tables.seg_step = d_seg_step;
+        tables.step_items = d_step_items;
+        tables.nqueues = ar.nqueues;
+        tables.xcd_local = xcd_local ? 1 : 0;
+        for (int q = 0; q <= ar.nqueues; ++q) {
+            tables.q_seg[q] = ar.q_seg[q];
+            tables.q_step[q] = ar.q_step[q];
+        }
+        for (int q = 0; q < ar.nqueues; ++q) tables.q_items[q] = ar.q_items[q];
+        tables.chunk = chunk;
+        if (ar.phases.empty()) return true;
         auto h2d = [&](void *dst, const void *src, size_t bytes) {
             return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, cap) == hipSuccess;
         };
-        return h2d(d_phases, pl.phases.data(), pl.phases.size() * sizeof(Phase)) &&
-               h2d(d_seg_start, pl.seg_start.data(), pl.seg_start.size() * sizeof(unsigned)) &&
-               h2d(d_seg_phase, pl.seg_phase.data(), pl.seg_phase.size() * sizeof(int)) &&
-               h2d(d_seg_step, pl.seg_step.data(), pl.seg_step.size() * sizeof(int)) &&
-               h2d(d_step_items, pl.step_items.data(), pl.step_items.size() * sizeof(unsigned)) &&
+        return h2d(d_phases, ar.phases.data(), ar.phases.size() * sizeof(Phase)) &&
+               h2d(d_seg_start, ar.seg_start.data(), ar.seg_start.size() * sizeof(unsigned)) &&
+               h2d(d_seg_phase, ar.seg_phase.data(), ar.seg_phase.size() * sizeof(int)) &&
+               h2d(d_seg_step, ar.seg_step.data(), ar.seg_step.size() * sizeof(int)) &&
+               h2d(d_step_items, ar.step_items.data(), ar.step_items.size() * sizeof(unsigned)) &&
                hipStreamSynchronize(cap) == hipSuccess;
     };
-    int variant = 0;
     // one batch: the direct scenes' passes in order, then the persistent kernel
     auto run = [&]() -> bool {
-        for (const Phase *p : direct_list)
-            if (launch_phase(*p, cap) != hipSuccess) return false;
-        if (pl.phases.empty()) return true;
-        return launch_persistent(tables, d_sched, grids[variant], variant, cap) == hipSuccess;
+        for (const Phase &p : ar.direct)
+            if (launch_phase(p, cap) != hipSuccess) return false;
+        if (ar.phases.empty()) return true;
+        return launch_persistent(tables, b->sched, grids[variant], variant, cap) == hipSuccess;
     };
 
-    // ---- autotune: which sizes run as their own kernels, the persistent
-    // kernel variant (registers vs resident blocks), the tile count per phase
-    // (hence elements per tile) as a multiple of the resident tile slots, and
-    // the claim chunk: the fastest whole-batch launch wins -------------------
+    // ---- autotune.  A candidate is a split (which sizes run direct), a queue
+    // layout (one queue per XCD, or one queue over the whole device), the
+    // workspace slots per queue, the kernel variant, the tile count per phase
+    // (a multiple of the resident tile slots per queue) and the claim chunk.
+    // Stage 1 times every split, queue layout, slot count and variant at one
+    // setting of the rest; stage 2 sweeps the rest for the winner.  The fastest
+    // whole-batch launch wins. ------------------------------------------------
+    struct Cand {
+        int min_direct, xcd, slots, variant, mult;
+        unsigned chunk;
+    };
     std::vector<int> min_directs{HRC_MAX_LOG2 + 1};  // none direct
     if (!(flags & HRC_FLAG_BATCH_PERSISTENT)) {
         // from 256^2 up: below, a pass does not fill the GPU
@@ -361,59 +503,116 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
                     break;
                 }
     }
-    const int mults[] = {1, 2, 4};
-    const unsigned chunks[] = {1u, 4u};
+    std::vector<int> variants;
+    for (int v = 0; v < kPersistentVariants; ++v) {
+        if ((flags & HRC_FLAG_BATCH_FULL) && v != 0) continue;
+        if ((flags & HRC_FLAG_BATCH_DENSE) && v != 1) continue;
+        variants.push_back(v);
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     bool fine = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    bool timed_out = false;
     float best_ms = 1e30f;
-    int best = grids[0] * kBatchQuarters, best_variant = 0, best_min = HRC_MAX_LOG2 + 1;
-    unsigned best_chunk = 1;
-    auto time_one = [&](int min_direct, int v, int target, unsigned ch) {
-        fine = upload(target, ch) && run() && hipStreamSynchronize(cap) == hipSuccess;  // warm-up
+    Cand best{HRC_MAX_LOG2 + 1, 0, 0, variants[0], 1, 1u};
+    auto set_up = [&](const Cand &c) -> bool {
+        variant = c.variant;
+        chunk = c.chunk;
+        xcd_local = c.xcd > 0;
+        ar = Arrangement();
+        ar.min_direct = c.min_direct;
+        ar.nqueues = xcd_local ? c.xcd : 1;
+        ar.slots = c.slots;
+        ar.target = std::max(1, grids[variant] / ar.nqueues) * kBatchQuarters * c.mult;
+        arrange(ar, scenes, count, b->dmem);
+        return ar.ws_bytes <= b->dmem_bytes && upload();
+    };
+    auto time_one = [&](const Cand &c) {
+        if (!fine) return;
+        fine = set_up(c) && run() && hipStreamSynchronize(cap) == hipSuccess;  // warm-up
         if (!fine) return;
         fine = hipEventRecord(e0, cap) == hipSuccess && run() &&
                hipEventRecord(e1, cap) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
         float ms = 0.f;
-        if (fine && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
+        if (!fine || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            fine = false;
+            return;
+        }
+        // the scheduler's error word (a dependency wait that gave up)
+        unsigned err = 0;
+        fine = hipMemcpy(&err, b->sched + kSchedError * kSchedStride, sizeof(unsigned),
+                         hipMemcpyDeviceToHost) == hipSuccess;
+        if (fine && err) {
+            timed_out = true;
+            fine = false;
+            return;
+        }
+        const int desc[kCandFields] = {c.min_direct <= HRC_MAX_LOG2 ? c.min_direct : 0,
+                                       ar.nqueues, xcd_local ? 1 : 0, c.slots, c.variant,
+                                       ar.target, (int)c.chunk};
+        b->cand_desc.insert(b->cand_desc.end(), desc, desc + kCandFields);
+        b->cand_ms.push_back(ms);
+        if (ms < best_ms) {
             best_ms = ms;
-            best = target;
-            best_chunk = ch;
-            best_variant = v;
-            best_min = min_direct;
+            best = c;
         }
     };
-    for (int min_direct : min_directs) {
-        if (!fine) break;
-        split(min_direct);
-        if (pl.phases.empty()) {  // every scene direct: nothing to tune
-            const int v = (flags & HRC_FLAG_BATCH_DENSE) ? 1 : 0;
-            time_one(min_direct, v, grids[v] * kBatchQuarters, 1u);
+    const int xcd_opts[] = {xcds[0] > 1 && xcds[1] > 1 ? xcds[0] : 0, 0};
+    for (int md : min_directs) {
+        bool all_direct = true;
+        for (int i = 0; i < count; ++i) all_direct = all_direct && scenes[i].log2_size >= md;
+        if (all_direct) {  // nothing for the persistent kernel: one timing
+            time_one(Cand{md, 0, 0, variants[0], 2, 1u});
             continue;
         }
-        for (int v = 0; v < kPersistentVariants && fine; ++v) {
-            if ((flags & HRC_FLAG_BATCH_FULL) && v != 0) continue;
-            if ((flags & HRC_FLAG_BATCH_DENSE) && v != 1) continue;
-            variant = v;
-            for (int mult : mults)
-                for (unsigned ch : chunks)
-                    if (fine) time_one(min_direct, v, grids[v] * kBatchQuarters * mult, ch);
-        }
-        if (fine) {
-            // the scheduler's error word (a dependency wait that timed out)
-            unsigned err = 0;
-            fine = hipMemcpy(&err, d_sched + kSchedStride, sizeof(unsigned),
-                             hipMemcpyDeviceToHost) == hipSuccess && err == 0;
+        for (int xo = 0; xo < 2; ++xo) {
+            if (xo == 1 && xcd_opts[0] == 0) continue;  // the single queue is tried once
+            const int xc = xcd_opts[xo];
+            for (int slots : {1, 2, 0})
+                for (int v : variants) time_one(Cand{md, xc, slots, v, 2, 1u});
         }
     }
+    const Cand stage1 = best;
+    bool stage1_direct = true;
+    for (int i = 0; i < count; ++i)
+        stage1_direct = stage1_direct && scenes[i].log2_size >= stage1.min_direct;
+    if (!stage1_direct)
+        for (int mult : {1, 2, 4})
+            for (unsigned ch : {1u, 4u})
+                if (!(mult == stage1.mult && ch == stage1.chunk))
+                    time_one(Cand{stage1.min_direct, stage1.xcd, stage1.slots, stage1.variant, mult,
+                                  ch});
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    split(best_min);
-    b->direct = n_direct;
-    b->target_tiles = best;
-    b->chunk = best_chunk;
-    b->variant = variant = best_variant;
-    b->grid = grids[variant];
-    if (fine) fine = upload(best, best_chunk);
+
+    // ---- the winner: its own (smaller) workspace, tables, and the graph ----
+    if (fine) {
+        ar = Arrangement();
+        ar.min_direct = best.min_direct;
+        ar.nqueues = best.xcd > 0 ? best.xcd : 1;
+        ar.slots = best.slots;
+        ar.target = std::max(1, grids[best.variant] / ar.nqueues) * kBatchQuarters * best.mult;
+        arrange(ar, scenes, count, nullptr);  // sizes only
+        if (ar.ws_bytes < b->dmem_bytes) {
+            (void)hipFree(b->dmem);
+            b->dmem = nullptr;
+            b->dmem_bytes = 0;
+            if (hipMalloc(&b->dmem, std::max<size_t>(ar.ws_bytes, 256)) != hipSuccess) {
+                b->dmem = nullptr;
+                fine = false;
+            } else {
+                b->dmem_bytes = std::max<size_t>(ar.ws_bytes, 256);
+            }
+        }
+    }
+    if (fine) fine = set_up(best);
+    b->direct = ar.n_direct;
+    b->target_tiles = ar.target;
+    b->chunk = best.chunk;
+    b->variant = best.variant;
+    b->grid = grids[best.variant];
+    b->queues = ar.nqueues;
+    b->xcd_local = best.xcd > 0 ? 1 : 0;
+    b->slots = best.slots;
 
     // ---- capture one launch in a graph ---------------------------------
     if (fine) fine = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
@@ -425,7 +624,7 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
     (void)hipStreamDestroy(cap);
     if (!fine) {
         free_batch(b);
-        return HRC_ERR_HIP;
+        return timed_out ? HRC_ERR_TIMEOUT : HRC_ERR_HIP;
     }
     *out = b;
     return HRC_OK;
@@ -440,8 +639,35 @@ hrc_status hrc_batch_launch(hrc_batch *batch, void *stream) {
                : HRC_ERR_HIP;
 }
 
+hrc_status hrc_batch_status(hrc_batch *batch, void *stream) {
+    if (!batch || !batch->sched) return HRC_ERR_INVALID_ARG;
+    DeviceGuard g(batch->device);
+    if (!g.ok) return HRC_ERR_HIP;
+    if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return HRC_ERR_HIP;
+    unsigned err = 0;
+    unsigned *word = batch->sched + kSchedError * kSchedStride;
+    if (hipMemcpy(&err, word, sizeof(unsigned), hipMemcpyDeviceToHost) != hipSuccess)
+        return HRC_ERR_HIP;
+    if (!err) return HRC_OK;
+    const unsigned zero = 0;
+    if (hipMemcpy(word, &zero, sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess)
+        return HRC_ERR_HIP;
+    return HRC_ERR_TIMEOUT;
+}
+
+hrc_status hrc_batch_debug_waits(hrc_batch *batch, unsigned spins) {
+    if (!batch || !batch->sched) return HRC_ERR_INVALID_ARG;
+    DeviceGuard g(batch->device);
+    if (!g.ok) return HRC_ERR_HIP;
+    const unsigned cfg[2] = {spins, spins ? 1u : 0u};
+    return hipMemcpy(batch->sched + kSchedConfig * kSchedStride, cfg, sizeof(cfg),
+                     hipMemcpyHostToDevice) == hipSuccess
+               ? HRC_OK
+               : HRC_ERR_HIP;
+}
+
 size_t hrc_batch_workspace_bytes(const hrc_batch *batch) {
-    return batch ? batch->dmem_bytes : 0;
+    return batch ? batch->dmem_bytes + batch->tmem_bytes : 0;
 }
 
 hrc_status hrc_batch_describe(const hrc_batch *batch, int *variant, int *grid,
@@ -452,6 +678,26 @@ hrc_status hrc_batch_describe(const hrc_batch *batch, int *variant, int *grid,
     if (grid) *grid = batch->grid;
     if (target_tiles) *target_tiles = batch->target_tiles;
     if (chunk) *chunk = (int)batch->chunk;
+    return HRC_OK;
+}
+
+hrc_status hrc_batch_queues(const hrc_batch *batch, int *queues, int *xcd_local, int *slots) {
+    if (!batch) return HRC_ERR_INVALID_ARG;
+    if (queues) *queues = batch->queues;
+    if (xcd_local) *xcd_local = batch->xcd_local;
+    if (slots) *slots = batch->slots;
+    return HRC_OK;
+}
+
+hrc_status hrc_batch_candidates(const hrc_batch *batch, int max, int *count, int *desc,
+                                float *ms) {
+    if (!batch || !count || max < 0 || (max > 0 && (!desc || !ms))) return HRC_ERR_INVALID_ARG;
+    const int n = (int)batch->cand_ms.size();
+    *count = n;
+    for (int i = 0; i < n && i < max; ++i) {
+        for (int f = 0; f < kCandFields; ++f) desc[i * kCandFields + f] = batch->cand_desc[i * kCandFields + f];
+        ms[i] = batch->cand_ms[i];
+    }
     return HRC_OK;
 }
 

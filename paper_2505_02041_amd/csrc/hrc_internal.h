@@ -183,33 +183,55 @@ hipError_t upload_cone_table(const float *host_table);
 // and end (a timed launch: no separate event packets between kernels).
 hipError_t launch_phase(const Phase &p, hipStream_t s, hipEvent_t start = nullptr,
                         hipEvent_t stop = nullptr);
-// Device tables of a planned batch: segment i covers the items
-// [seg_start[i], seg_start[i+1]) = the tiles of phase seg_phase[i], in step
-// seg_step[i]; step_items[t] counts the items of step t.
+// Device tables of a planned batch.  The work is split over `nqueues` queues;
+// with `xcd_local` each queue belongs to one XCD (accelerator complex die) and
+// is served only by the blocks running there, which then see each other's
+// stores in that XCD's L2 without writing the L2 back.  Queue q holds the
+// segments [q_seg[q], q_seg[q+1]) and the steps [q_step[q], q_step[q+1]);
+// segment i covers the queue's items [seg_start[i], seg_start[i+1]) (the last
+// one up to q_items[q]) = the tiles of phase seg_phase[i], in step seg_step[i]
+// (counted from the queue's first step); step_items[q_step[q] + t] counts the
+// items of step t of queue q.
 // The persistent kernel's blocks hold kBatchQuarters 256-thread quarters, each
 // running one tile; work is scheduled in groups of kBatchQuarters consecutive
 // tiles of one phase (phases padded with empty tiles to whole groups).
 constexpr int kBatchQuarters = 4;
+constexpr int kMaxQueues = 16;
 struct BatchTables {
     const Phase *phases;
-    const unsigned *seg_start;   // first group of each segment (one phase of one scene)
+    const unsigned *seg_start;   // first group of each segment, counted within its queue
     const int *seg_phase;
     const int *seg_step;
     const unsigned *step_items;  // groups per step
-    int nseg, nsteps;
-    unsigned total_items;        // groups in all
+    int nqueues;
+    int xcd_local;               // queue q is served by the blocks of XCD q
+    int q_seg[kMaxQueues + 1];
+    int q_step[kMaxQueues + 1];
+    unsigned q_items[kMaxQueues];
     unsigned chunk;              // groups a block claims at once
 };
 // Scheduler words, each in a cache line of its own (kSchedStride words apart):
-// the claim counter, the error word, then one completion count per step.
+// line 0 the error word (bits: 1 a dependency wait gave up, 2 a queue was left
+// unfinished), line 1 the wait configuration (word 0: polls before a wait gives
+// up, 0 for the default; word 1: groups added to what every wait needs, for
+// failure tests), line 2 the count of blocks that have finished, then one claim
+// counter per queue, then one completion count per step of each queue.  A
+// launch clears everything from line 2 on; the error word and the
+// configuration persist across launches.
 constexpr unsigned kSchedStride = 32;
-constexpr size_t sched_words(int nsteps) { return (size_t)kSchedStride * (2 + nsteps); }
-// Clears the scheduler words and launches the persistent kernel.
+constexpr unsigned kSchedError = 0, kSchedConfig = 1, kSchedExit = 2, kSchedClaim = 3;
+constexpr size_t sched_words(int nqueues, int total_steps) {
+    return (size_t)kSchedStride * (kSchedClaim + nqueues + total_steps);
+}
+// Clears the per-launch scheduler words and launches the persistent kernel.
 // variant 0: full register budget; 1: 64 VGPRs (twice the resident blocks).
 constexpr int kPersistentVariants = 2;
 hipError_t launch_persistent(const BatchTables &t, unsigned *sched, int grid, int variant,
                              hipStream_t s);
 hipError_t persistent_occupancy(int variant, int *blocks_per_cu);
+// Writes the XCD of every block of a `grid` x (256 * kBatchQuarters) launch to
+// out[block] (the queue a block of the persistent kernel would serve).
+hipError_t launch_xcd_probe(unsigned *out, int grid, hipStream_t s);
 hipError_t launch_validate(const float *a, const float *b, size_t n, int *flag,
                            hipStream_t s);
 

@@ -191,8 +191,9 @@ __device__ __forceinline__ void far_quad(const half2_t *row, int yf, int S, floa
 // and then folds the 4 x 4864 rays whose probes lie in the tile, each thread
 // every direction of one probe at a time.
 // Thread index within a 256-thread work tile.  Every pass body is written for
-// 256 threads; the persistent kernel runs several tiles side by side in one
-// block, one per 256-thread quarter.
+// 256 threads and takes this index as its `tid` argument; the persistent
+// kernel runs several tiles side by side in one block, one per 256-thread
+// quarter, and passes each body an opaque copy (see run_phase).
 __device__ __forceinline__ int ltid() { return (int)(threadIdx.x & 255u); }
 
 constexpr int kSeedHalo = 4;
@@ -228,7 +229,7 @@ constexpr unsigned char kHpLen[10][8] = {
 // along w, so each direction's stores are contiguous rows.
 template <int TILE, int n, typename TS>
 __device__ __forceinline__ void seed_level_rays(const float2 *iv, const SeedArgs &a, int q,
-                                                int slot, int r0, int c0) {
+                                                int slot, int r0, int c0, int tid) {
     using G = SeedTile<TILE>;
     constexpr int dirs = (1 << n) + 1, cols = TILE >> n, pieces = 2 << n;
     constexpr int per_pass = 256 / TILE;  // probe columns per pass of the block
@@ -240,10 +241,10 @@ __device__ __forceinline__ void seed_level_rays(const float2 *iv, const SeedArgs
     const int w_lo = q < 2 ? r0 : c0;
     const int su = q == 0 ? 1 : q == 1 ? -1 : q == 2 ? G::pitch : -G::pitch;
     const int sw = q < 2 ? G::pitch : 1;
-    const int wl = ltid() % TILE;
+    const int wl = tid % TILE;
     const int w = w_lo + wl;
     constexpr int sid0 = n == 0 ? 0 : n == 1 ? 2 : 5;
-    for (int xl = ltid() / TILE; xl < cols; xl += per_pass) {
+    for (int xl = tid / TILE; xl < cols; xl += per_pass) {
         const int u = u_lo + (xl << n);
         if (u < 0 || u >= S || w >= S) continue;
         int lr, lc;
@@ -269,13 +270,13 @@ __device__ __forceinline__ void seed_level_rays(const float2 *iv, const SeedArgs
 // inside the persistent kernel, whose one LDS buffer serves every pass); the
 // per-ray arithmetic is the same for both.
 template <int TILE, typename TS>
-__device__ void body_seed(const SeedArgs &a, unsigned tile, char *lds) {
+__device__ void body_seed(const SeedArgs &a, unsigned tile, char *lds, int tid) {
     using G = SeedTile<TILE>;
     float2 *iv = reinterpret_cast<float2 *>(lds);
     const int S = 1 << a.N;
     const int tiles = (S + TILE - 1) / TILE;
     const int r0 = (int)(tile / tiles) * TILE, c0 = (int)(tile % tiles) * TILE;
-    for (int i = ltid(); i < G::span * G::span; i += 256) {
+    for (int i = tid; i < G::span * G::span; i += 256) {
         const int lr = i / G::span, lc = i % G::span;
         const int r = r0 - kSeedHalo + lr, c = c0 - kSeedHalo + lc;
         float e = 0.f, g = 0.f;
@@ -290,9 +291,9 @@ __device__ void body_seed(const SeedArgs &a, unsigned tile, char *lds) {
     }
     __syncthreads();
     for (int g = 0; g < a.nq; ++g) {
-        if (a.first <= 0) seed_level_rays<TILE, 0, TS>(iv, a, a.q0 + g, g, r0, c0);
-        if (a.first <= 1) seed_level_rays<TILE, 1, TS>(iv, a, a.q0 + g, g, r0, c0);
-        seed_level_rays<TILE, 2, TS>(iv, a, a.q0 + g, g, r0, c0);
+        if (a.first <= 0) seed_level_rays<TILE, 0, TS>(iv, a, a.q0 + g, g, r0, c0, tid);
+        if (a.first <= 1) seed_level_rays<TILE, 1, TS>(iv, a, a.q0 + g, g, r0, c0, tid);
+        seed_level_rays<TILE, 2, TS>(iv, a, a.q0 + g, g, r0, c0, tid);
     }
     __syncthreads();
 }
@@ -307,7 +308,7 @@ template <typename TS> constexpr int merge_pairs() { return sizeof(TS) == 4 ? 2 
 // directions of its one column (the doubled edges of Eq. 15-17), and builds
 // those itself from T_{N-1}.
 template <typename TS>
-__device__ void body_merge_up(const UpArgs &a, unsigned tile, int U) {
+__device__ void body_merge_up(const UpArgs &a, unsigned tile, int U, int tid) {
     constexpr int P = merge_pairs<TS>();
     const int N = a.N, S = 1 << N, n = a.n;
     const int h = 1 << (n - 1);
@@ -315,7 +316,7 @@ __device__ void body_merge_up(const UpArgs &a, unsigned tile, int U) {
     const unsigned rpq = (unsigned)(S >> n) * dirs;
     const size_t total = (size_t)a.nq * rpq * (S / (2 * P));
     for (int uu = 0; uu < U; ++uu) {
-        const size_t idx = ((size_t)tile * U + uu) * 256 + ltid();
+        const size_t idx = ((size_t)tile * U + uu) * 256 + tid;
         if (idx >= total) return;
         const int y0 = (int)(idx & (S / (2 * P) - 1)) * 2 * P;
         const unsigned row = (unsigned)(idx >> (N - (P == 2 ? 2 : 1)));
@@ -416,14 +417,14 @@ __device__ __forceinline__ void r_quad(const float *Rq, int N, int m, int c, int
 // and 0 of the forward are the tail's, and the reverse reads R_1 at the
 // lowest), so every row shift is even and each lookup is a pair.
 template <typename TS>
-__device__ void body_merge_down(const DownArgs &a, unsigned tile, int U) {
+__device__ void body_merge_down(const DownArgs &a, unsigned tile, int U, int tid) {
     constexpr int P = merge_pairs<TS>();
     const int N = a.N, S = 1 << N, n = a.n;
     const size_t SS = (size_t)S * S;
     const size_t total = (size_t)a.nq * (SS / (2 * P));
     const int m = n + 1;
     for (int uu = 0; uu < U; ++uu) {
-        const size_t idx = ((size_t)tile * U + uu) * 256 + ltid();
+        const size_t idx = ((size_t)tile * U + uu) * 256 + tid;
         if (idx >= total) return;
         const int y0 = (int)(idx & (S / (2 * P) - 1)) * 2 * P;
         const unsigned row = (unsigned)(idx >> (N - (P == 2 ? 2 : 1)));
@@ -589,7 +590,7 @@ __device__ __forceinline__ float r2_at(const float *R2, int ro, int jj, int y, i
 }
 
 template <int TILE>
-__device__ void body_tail(const TailArgs &a, unsigned tile, char *lds) {
+__device__ void body_tail(const TailArgs &a, unsigned tile, char *lds, int tid) {
     using G = TailTile<TILE>;
     constexpr int H = G::halo, P = G::pitch, RR = G::r1rows, AP = G::acc_pitch;
     constexpr int span2 = G::span * G::span;
@@ -601,7 +602,7 @@ __device__ void body_tail(const TailArgs &a, unsigned tile, char *lds) {
     const int r0 = (int)(tile / tiles) * TILE, c0 = (int)(tile % tiles) * TILE;
 #pragma unroll
     for (int it = 0; it < (span2 + 255) / 256; ++it) {
-        const int i = ltid() + 256 * it;
+        const int i = tid + 256 * it;
         if (i < span2) {
             const int lr = i / G::span, lc = i % G::span;
             const int r = r0 - H + lr, c = c0 - H + lc;
@@ -614,7 +615,7 @@ __device__ void body_tail(const TailArgs &a, unsigned tile, char *lds) {
     }
 #pragma unroll
     for (int it = 0; it < TILE * TILE / 256; ++it) {
-        const int i = ltid() + 256 * it;
+        const int i = tid + 256 * it;
         const int rl = i / TILE, cl = i % TILE;
         const int r = r0 + rl, c = c0 + cl;
         acc[rl * AP + cl] = (a.accumulate && r < S && c < S) ? a.out[r * S + c] : 0.f;
@@ -642,7 +643,7 @@ __device__ void body_tail(const TailArgs &a, unsigned tile, char *lds) {
         constexpr int n_odd = (TILE / 4 + 1) * RR;
 #pragma unroll
         for (int it = 0; it < (n_odd + 255) / 256; ++it) {
-            const int i = ltid() + 256 * it;
+            const int i = tid + 256 * it;
             if (i >= n_odd) break;
             const int j = 2 * (i / RR), wl = i % RR;
             const int cp = c1_lo + j, w = w_lo - 2 + wl;
@@ -669,7 +670,7 @@ __device__ void body_tail(const TailArgs &a, unsigned tile, char *lds) {
         constexpr int n_even = (TILE / 4) * RR;
 #pragma unroll
         for (int it = 0; it < (n_even + 255) / 256; ++it) {
-            const int i = ltid() + 256 * it;
+            const int i = tid + 256 * it;
             if (i >= n_even) break;
             const int j = 2 * (i / RR) + 1, wl = i % RR;
             const int cp = c1_lo + j, w = w_lo - 2 + wl;
@@ -704,7 +705,7 @@ __device__ void body_tail(const TailArgs &a, unsigned tile, char *lds) {
         // pass, for each wave).  Offsets into the intervals and the sum are
         // linear in ul and wl.
         constexpr int SP = 256 / TILE, IT = TILE * TILE / 256;
-        const int wl = ltid() % TILE, w = w_lo + wl, slot0 = ltid() / TILE;
+        const int wl = tid % TILE, w = w_lo + wl, slot0 = tid / TILE;
         const int au = q == 0 ? 1 : q == 1 ? -1 : q == 2 ? AP : -AP;
         const int aw = q < 2 ? AP : 1;
         const int abase = q == 1 ? TILE - 1 : q == 3 ? (TILE - 1) * AP : 0;
@@ -745,7 +746,7 @@ __device__ void body_tail(const TailArgs &a, unsigned tile, char *lds) {
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < TILE * TILE / 256; ++it) {
-        const int i = ltid() + 256 * it;
+        const int i = tid + 256 * it;
         const int rl = i / TILE, cl = i % TILE;
         const int r = r0 + rl, c = c0 + cl;
         if (r < S && c < S) a.out[r * S + c] = acc[rl * AP + cl];
@@ -757,7 +758,7 @@ __device__ void body_tail(const TailArgs &a, unsigned tile, char *lds) {
 // point (x - 1, y), and 0 at x = 0.  Tile = q * tiles^2 + (x tile, y tile).
 constexpr int kGatherAdjLds = 32 * 33 * 4;
 
-__device__ void body_gather_adj(const GatherAdjArgs &a, unsigned tile, char *lds) {
+__device__ void body_gather_adj(const GatherAdjArgs &a, unsigned tile, char *lds, int tid) {
     float (*ga_tile)[33] = reinterpret_cast<float (*)[33]>(lds);
     const int N = a.N, S = 1 << N;
     const size_t SS = (size_t)S * S;
@@ -765,7 +766,7 @@ __device__ void body_gather_adj(const GatherAdjArgs &a, unsigned tile, char *lds
     const int q = tile / (tiles * tiles);
     const int t2 = tile % (tiles * tiles);
     const int tX = t2 / tiles, tY = t2 % tiles;
-    const int tx = ltid() & 31, ty = ltid() >> 5;
+    const int tx = tid & 31, ty = tid >> 5;
     // Every thread reaches both barriers whatever its tile (tiles of other
     // passes may share the block); tiles past the four quadrants store nothing.
     if (q == 2 || q == 3) {
@@ -821,11 +822,11 @@ __device__ __forceinline__ float2 ld2_r(bool in, const float *row, int y, int S,
 // entry (c, jj, y') is read by at most three R_n entries: the odd column 2c-1
 // (far end of Eq. 14), the even column 2c (F^0 of Eq. 16) and the even column
 // 2c-2 (far end of Eq. 17).  Two consecutive y' per thread.
-__device__ void body_merge_down_adj(const DownAdjArgs &a, unsigned tile, int U) {
+__device__ void body_merge_down_adj(const DownAdjArgs &a, unsigned tile, int U, int tid) {
     const int N = a.N, S = 1 << N, n = a.n, m = n + 1;
     const size_t SS = (size_t)S * S;
     for (int uu = 0; uu < U; ++uu) {
-        const size_t idx = ((size_t)tile * U + uu) * 256 + ltid();
+        const size_t idx = ((size_t)tile * U + uu) * 256 + tid;
         if (idx >= 2 * SS) return;
         const int yp = (int)(idx & (S / 2 - 1)) * 2;
         const unsigned row = (unsigned)(idx >> (N - 1));
@@ -891,14 +892,14 @@ __device__ void body_merge_down_adj(const DownAdjArgs &a, unsigned tile, int U) 
 // so that a wave waits for memory once rather than once per source: the
 // conditions on x and k are uniform over the wave, absent terms load nothing
 // and add zero, and reads outside the grid take a clamped address and a select.
-__device__ void body_dT(const DTArgs &a, unsigned tile, int U) {
+__device__ void body_dT(const DTArgs &a, unsigned tile, int U, int tid) {
     const int N = a.N, S = 1 << N, n = a.n;
     const size_t SS = (size_t)S * S;
     const int dirs = (1 << n) + 1;
     const unsigned rpq = (unsigned)(S >> n) * dirs;
     const size_t total = (size_t)4 * rpq * (S / 2);
     for (int uu = 0; uu < U; ++uu) {
-        const size_t idx = ((size_t)tile * U + uu) * 256 + ltid();
+        const size_t idx = ((size_t)tile * U + uu) * 256 + tid;
         if (idx >= total) return;
         const int y = (int)(idx & (S / 2 - 1)) * 2;
         const unsigned row = (unsigned)(idx >> (N - 1));
@@ -1236,14 +1237,14 @@ constexpr int kAccPlane = kAdjTile * kAccPitch;
 constexpr int kSeedAdjLds = 3 * kAdjSpan * kAdjPitch * 8;
 static_assert(6 * kAccPlane * 4 <= kSeedAdjLds, "partial sums fit over the interval tile");
 
-__device__ __forceinline__ void body_seed_adj(const SeedAdjArgs &a, unsigned tile, char *lds) {
+__device__ __forceinline__ void body_seed_adj(const SeedAdjArgs &a, unsigned tile, char *lds, int tid) {
     constexpr int P = kAdjPitch, plane = kAdjSpan * kAdjPitch, H = kAdjHalo;
     float2 *iv = reinterpret_cast<float2 *>(lds);
     const int S = 1 << a.N;
     const int tiles = (S + kAdjTile - 1) / kAdjTile;
     const int r0 = (int)(tile / tiles) * kAdjTile, c0 = (int)(tile % tiles) * kAdjTile;
     // the tile and its halo as three half-length intervals per cell
-    for (int i = ltid(); i < kAdjSpan * kAdjSpan; i += 256) {
+    for (int i = tid; i < kAdjSpan * kAdjSpan; i += 256) {
         const int lr = i / kAdjSpan, lc = i % kAdjSpan;
         const int r = r0 - H + lr, c = c0 - H + lc;
         float e = 0.f, g = 0.f;
@@ -1257,7 +1258,7 @@ __device__ __forceinline__ void body_seed_adj(const SeedAdjArgs &a, unsigned til
         iv[2 * plane + l] = cell_interval(e, g, kQ5);
     }
     __syncthreads();
-    const int v = ltid() >> 6, lane = ltid() & 63;
+    const int v = tid >> 6, lane = tid & 63;
     const int i4 = v + 4 * (lane >> 4), i16 = lane & 15;
     // quadrants +x and -x (frame u along the row): wave v takes the tile
     // columns v, v+4, v+8, v+12, pixel (i16, i4)
@@ -1314,10 +1315,10 @@ __device__ __forceinline__ bool blur_inside(int S, int r, int c) {
     return r >= 0 && r < S && c >= 0 && c < S;
 }
 
-__device__ void body_blur(const BlurArgs &a, unsigned tile) {
+__device__ void body_blur(const BlurArgs &a, unsigned tile, int tid) {
     const int S = 1 << a.N;
     const int tiles = (S + 15) >> 4;
-    const int r = (int)(tile / tiles) * 16 + (ltid() >> 4), c = (int)(tile % tiles) * 16 + (ltid() & 15);
+    const int r = (int)(tile / tiles) * 16 + (tid >> 4), c = (int)(tile % tiles) * 16 + (tid & 15);
     if (r >= S || c >= S) return;
     const float am = blur_alpha(a.sig, S, r, c);
     float acc = 4.f * a.in[(size_t)r * S + c], wsum = 4.f;
@@ -1350,10 +1351,10 @@ __device__ __forceinline__ float blur_weight(const BlurArgs &a, int S, int r, in
     return 1.f / wsum;
 }
 
-__device__ void body_blur_adj(const BlurArgs &a, unsigned tile) {
+__device__ void body_blur_adj(const BlurArgs &a, unsigned tile, int tid) {
     const int S = 1 << a.N;
     const int tiles = (S + 15) >> 4;
-    const int r = (int)(tile / tiles) * 16 + (ltid() >> 4), c = (int)(tile % tiles) * 16 + (ltid() & 15);
+    const int r = (int)(tile / tiles) * 16 + (tid >> 4), c = (int)(tile % tiles) * 16 + (tid & 15);
     if (r >= S || c >= S) return;
     const float aq = blur_alpha(a.sig, S, r, c);
     float acc = 4.f * a.in[(size_t)r * S + c] * blur_weight(a, S, r, c, aq);
@@ -1374,18 +1375,29 @@ __device__ void body_blur_adj(const BlurArgs &a, unsigned tile) {
 constexpr int kMaxLds2 = kSeedAdjLds > SeedTile<16>::lds ? kSeedAdjLds : SeedTile<16>::lds;
 constexpr int kMaxLds = kMaxLds2 > TailTile<16>::lds ? kMaxLds2 : TailTile<16>::lds;
 
+// One tile of the persistent kernel.  The thread index reaches the body as a
+// value the compiler cannot see through, created afresh for every tile: were
+// it threadIdx.x itself, the values every inlined body derives from it would
+// be hoisted out of the persistent loop and stay live across all of the other
+// bodies (125 instead of 87 VGPRs; 212 instead of 44 bytes of spills in the
+// 64-VGPR variant).  Its range is restated so that index arithmetic stays
+// 32-bit.
 __device__ __forceinline__ void run_phase(const Phase &p, unsigned tile, char *lds) {
+    unsigned t = threadIdx.x & 255u;
+    asm volatile("" : "+v"(t));
+    __builtin_assume(t < 256u);
+    const int tid = (int)t;
     switch (p.kind) {
-        case PH_SEED: body_seed<16, float2>(p.a.seed, tile, lds); break;  // planner sets tile 16
-        case PH_UP: body_merge_up<float2>(p.a.up, tile, p.U); break;
-        case PH_DOWN: body_merge_down<float2>(p.a.down, tile, p.U); break;
-        case PH_TAIL: body_tail<16>(p.a.tail, tile, lds); break;  // planner sets tile 16
-        case PH_GATHER_ADJ: body_gather_adj(p.a.ga, tile, lds); break;
-        case PH_DOWN_ADJ: body_merge_down_adj(p.a.da, tile, p.U); break;
-        case PH_DT: body_dT(p.a.dt, tile, p.U); break;
-        case PH_SEED_ADJ: body_seed_adj(p.a.sa, tile, lds); break;
-        case PH_BLUR: body_blur(p.a.bl, tile); break;
-        case PH_BLUR_ADJ: body_blur_adj(p.a.bl, tile); break;
+        case PH_SEED: body_seed<16, float2>(p.a.seed, tile, lds, tid); break;  // planner sets tile 16
+        case PH_UP: body_merge_up<float2>(p.a.up, tile, p.U, tid); break;
+        case PH_DOWN: body_merge_down<float2>(p.a.down, tile, p.U, tid); break;
+        case PH_TAIL: body_tail<16>(p.a.tail, tile, lds, tid); break;  // planner sets tile 16
+        case PH_GATHER_ADJ: body_gather_adj(p.a.ga, tile, lds, tid); break;
+        case PH_DOWN_ADJ: body_merge_down_adj(p.a.da, tile, p.U, tid); break;
+        case PH_DT: body_dT(p.a.dt, tile, p.U, tid); break;
+        case PH_SEED_ADJ: body_seed_adj(p.a.sa, tile, lds, tid); break;
+        case PH_BLUR: body_blur(p.a.bl, tile, tid); break;
+        case PH_BLUR_ADJ: body_blur_adj(p.a.bl, tile, tid); break;
         default: break;
     }
 }
@@ -1397,7 +1409,7 @@ __device__ __forceinline__ void run_phase(const Phase &p, unsigned tile, char *l
 
 #define HRC_ELEMENTWISE_KERNEL(name, body, field)                                  \
     __global__ __launch_bounds__(256) void name(Phase p) {                         \
-        body(p.a.field, xcd_tile(blockIdx.x, gridDim.x), p.U);                     \
+        body(p.a.field, xcd_tile(blockIdx.x, gridDim.x), p.U, ltid());             \
     }
 HRC_ELEMENTWISE_KERNEL(hrc_merge_up, body_merge_up<float2>, up)
 HRC_ELEMENTWISE_KERNEL(hrc_merge_down, body_merge_down<float2>, down)
@@ -1409,131 +1421,186 @@ HRC_ELEMENTWISE_KERNEL(hrc_interval_adj, body_dT, dt)
 
 __global__ __launch_bounds__(256) void hrc_seed(Phase p) {
     __shared__ __align__(16) char lds[SeedTile<32>::lds];
-    body_seed<32, float2>(p.a.seed, xcd_tile(blockIdx.x, gridDim.x), lds);
+    body_seed<32, float2>(p.a.seed, xcd_tile(blockIdx.x, gridDim.x), lds, ltid());
 }
 __global__ __launch_bounds__(256) void hrc_seed_f16(Phase p) {
     __shared__ __align__(16) char lds[SeedTile<32>::lds];
-    body_seed<32, half2_t>(p.a.seed, xcd_tile(blockIdx.x, gridDim.x), lds);
+    body_seed<32, half2_t>(p.a.seed, xcd_tile(blockIdx.x, gridDim.x), lds, ltid());
 }
 __global__ __launch_bounds__(256) void hrc_seed_adj(Phase p) {
     __shared__ __align__(16) char lds[kSeedAdjLds];
-    body_seed_adj(p.a.sa, xcd_tile(blockIdx.x, gridDim.x), lds);
+    body_seed_adj(p.a.sa, xcd_tile(blockIdx.x, gridDim.x), lds, ltid());
 }
 __global__ __launch_bounds__(256) void hrc_blur(Phase p) {
-    body_blur(p.a.bl, xcd_tile(blockIdx.x, gridDim.x));
+    body_blur(p.a.bl, xcd_tile(blockIdx.x, gridDim.x), ltid());
 }
 __global__ __launch_bounds__(256) void hrc_blur_adj(Phase p) {
-    body_blur_adj(p.a.bl, xcd_tile(blockIdx.x, gridDim.x));
+    body_blur_adj(p.a.bl, xcd_tile(blockIdx.x, gridDim.x), ltid());
 }
 __global__ __launch_bounds__(256) void hrc_tail(Phase p) {
     __shared__ __align__(16) char lds[TailTile<32>::lds];
-    body_tail<32>(p.a.tail, xcd_tile(blockIdx.x, gridDim.x), lds);
+    body_tail<32>(p.a.tail, xcd_tile(blockIdx.x, gridDim.x), lds, ltid());
 }
 __global__ __launch_bounds__(256) void hrc_gather_adj(Phase p) {
     __shared__ __align__(16) char lds[kGatherAdjLds];
-    body_gather_adj(p.a.ga, blockIdx.x, lds);
+    body_gather_adj(p.a.ga, blockIdx.x, lds, ltid());
 }
 
 // ---------------------------------------------------------------------------
 // Persistent batch kernel.  Work items are groups of kBatchQuarters tiles of
 // one phase, run side by side by the block's quarters (so every quarter passes
-// the same barriers), grouped in steps: step t holds phase t of every scene
-// that has one, so each phase depends only on the step before it.  Blocks
-// claim chunks of consecutive items from one counter and run them in order.  A block counts the items it
-// finishes in the current step and publishes that count (one agent-scope
-// release, then one atomic add) when it reaches an item of a later step or
-// runs out of items; before its first item of step t it waits until step t-1
-// is complete (agent-scope acquire).  Thread 0 performs both for the block,
-// between block barriers.  Publishing before waiting means no block
-// ever waits while holding unpublished work, and every item of step t-1 was
-// claimed before any item of step t by a block that is running, so the queue
-// always drains (no grid-wide co-residency is assumed).  Memory ordering costs
-// one release and one acquire per block and step rather than per item, and the
-// counter, the error word and each step's count sit in cache lines of their
-// own.
+// the same barriers), in queues of steps: a queue's step t depends only on its
+// steps before t.  Blocks claim chunks of consecutive items from their queue's
+// counter and run them in order.  A block counts the items it finishes in the
+// current step and publishes that count (one atomic add) when it reaches an
+// item of a later step or runs out of items; before its first item of step t
+// it waits until step t-1 of its queue is complete.  Thread 0 performs both
+// for the block, between block barriers.  Publishing before waiting means no
+// block ever waits while holding unpublished work, and every item of step t-1
+// was claimed before any item of step t by a block that is running, so the
+// queue always drains (no grid-wide co-residency is assumed).
+//
+// Visibility.  With one queue per XCD (xcd_local) every block of a queue runs
+// on the XCD whose L2 holds what the queue's passes write (vector L1 caches
+// write through to it): a publisher waits until its block's stores are
+// complete, and a waiter invalidates its L1 after seeing the count, so the
+// queue's scenes never write the L2 back mid-kernel.  With a single queue over
+// all XCDs a publisher makes the block's stores visible to every XCD with one
+// agent-scope release (an L2 write-back) per block and step.
 // ---------------------------------------------------------------------------
 
 constexpr unsigned kMaxSpins = 1u << 20;  // about a second of polling
 
+// The XCD (accelerator complex die) this wave runs on.
+__device__ __forceinline__ unsigned xcc_id() {
+    unsigned v;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+    return v & 0xfu;
+}
+
+__device__ __forceinline__ unsigned *sched_line(unsigned *sched, unsigned line) {
+    return sched + (size_t)line * kSchedStride;
+}
+
 __device__ __forceinline__ void persistent_loop(const BatchTables &t, unsigned *sched, char *lds,
                                                 unsigned &s_item) {
-    char *qlds = lds + (threadIdx.x >> 8) * kMaxLds;  // this quarter's LDS
-    unsigned *counter = sched, *error = sched + kSchedStride, *done = sched + 2 * kSchedStride;
-    int cur_step = -1;
-    unsigned completed = 0;
-    unsigned item = 0, claim_end = 0;  // this block's claimed items [item, claim_end)
-    int seg = 0;
-    unsigned seg_end = 0;              // first item after segment seg
-    for (;;) {
-        if (item == claim_end) {
-            // claim the next chunk (one thread), then make it a scalar for the block
-            if (threadIdx.x == 0) s_item = atomicAdd(counter, t.chunk);
-            __syncthreads();
-            item = __builtin_amdgcn_readfirstlane(s_item);
-            claim_end = item + t.chunk;
-            __syncthreads();
-        }
-        int step = t.nsteps;
-        if (item < t.total_items) {
-            if (item >= seg_end || item < t.seg_start[seg]) {
-                int lo = 0, hi = t.nseg - 1;  // last segment starting at or before the item
-                while (lo < hi) {
-                    int mid = (lo + hi + 1) >> 1;
-                    if (t.seg_start[mid] <= item) lo = mid;
-                    else hi = mid - 1;
-                }
-                seg = __builtin_amdgcn_readfirstlane(lo);
-                seg_end = seg + 1 < t.nseg ? t.seg_start[seg + 1] : t.total_items;
-            }
-            step = __builtin_amdgcn_readfirstlane(t.seg_step[seg]);
-        }
-        if (step != cur_step) {
-            if (cur_step >= 0) {
-                // publish this block's items of the step it is leaving: the
-                // block barrier orders every wave's stores before thread 0's
-                // agent-scope release, which then makes them visible to the
-                // other XCDs once for the whole block
+    // this quarter's LDS (the quarter is uniform over each wave)
+    const unsigned quarter = __builtin_amdgcn_readfirstlane(threadIdx.x >> 8);
+    char *qlds = lds + quarter * kMaxLds;
+    unsigned *error = sched_line(sched, kSchedError);
+    const int q = t.xcd_local ? (int)xcc_id() : 0;
+    if (q < t.nqueues) {
+        unsigned *counter = sched_line(sched, kSchedClaim + q);
+        unsigned *done = sched_line(sched, kSchedClaim + t.nqueues + t.q_step[q]);
+        const unsigned *step_items = t.step_items + t.q_step[q];
+        const int nsteps = t.q_step[q + 1] - t.q_step[q];
+        const int seg_lo = t.q_seg[q], seg_hi = t.q_seg[q + 1];
+        const unsigned total = t.q_items[q];
+        int cur_step = -1;
+        unsigned completed = 0;
+        unsigned item = 0, claim_end = 0;  // this block's claimed items [item, claim_end)
+        int seg = seg_lo;
+        unsigned seg_end = 0;              // first item after segment seg
+        for (;;) {
+            if (item == claim_end) {
+                // claim the next chunk (one thread), then make it a scalar for the block
+                if (threadIdx.x == 0) s_item = atomicAdd(counter, t.chunk);
                 __syncthreads();
-                if (threadIdx.x == 0) {
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                    __hip_atomic_fetch_add(&done[(size_t)cur_step * kSchedStride], completed,
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                item = __builtin_amdgcn_readfirstlane(s_item);
+                claim_end = item + t.chunk;
+                __syncthreads();
+            }
+            int step = nsteps;
+            if (item < total) {
+                if (item >= seg_end || item < t.seg_start[seg]) {
+                    int lo = seg_lo, hi = seg_hi - 1;  // last segment starting at or before the item
+                    while (lo < hi) {
+                        int mid = (lo + hi + 1) >> 1;
+                        if (t.seg_start[mid] <= item) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    seg = __builtin_amdgcn_readfirstlane(lo);
+                    seg_end = seg + 1 < seg_hi ? t.seg_start[seg + 1] : total;
+                }
+                step = __builtin_amdgcn_readfirstlane(t.seg_step[seg]);
+            }
+            if (step != cur_step) {
+                if (cur_step >= 0) {
+                    // publish this block's items of the step it is leaving
+                    if (t.xcd_local) {
+                        // every wave's stores have reached the XCD's L2 before
+                        // the barrier, and so before thread 0's count (the
+                        // memory clobber keeps the compiler from moving stores
+                        // past the wait)
+                        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                        __syncthreads();
+                    } else {
+                        // the block barrier orders every wave's stores before
+                        // thread 0's agent-scope release, which then makes them
+                        // visible to the other XCDs once for the whole block
+                        __syncthreads();
+                        if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                    }
+                    if (threadIdx.x == 0)
+                        __hip_atomic_fetch_add(&done[(size_t)cur_step * kSchedStride], completed,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                cur_step = step;
+                completed = 0;
+                if (step >= nsteps) break;
+                if (step > 0) {
+                    if (threadIdx.x == 0) {
+                        // Bounded wait on relaxed loads (an acquiring load would
+                        // invalidate the caches on every poll); the acquire fence
+                        // below orders the step's reads after the count is seen.
+                        // A step that never completes (a planning bug, or the
+                        // failure test's unreachable count) raises the error word
+                        // and lets the queue drain instead of hanging.
+                        const unsigned *cfg = sched_line(sched, kSchedConfig);
+                        const unsigned limit = cfg[0] ? cfg[0] : kMaxSpins;
+                        const unsigned need = step_items[step - 1] + cfg[1];
+                        const unsigned *d = &done[(size_t)(step - 1) * kSchedStride];
+                        unsigned spins = 0;
+                        while (__hip_atomic_load(d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                               need) {
+                            if (++spins > limit) {
+                                __hip_atomic_fetch_or(error, 1u, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(2);
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    }
+                    __syncthreads();  // the other waves read after thread 0's acquire
                 }
             }
-            cur_step = step;
-            completed = 0;
-            if (step >= t.nsteps) break;
-            if (step > 0) {
-                if (threadIdx.x == 0) {
-                    // Bounded wait on relaxed loads (an acquiring load would
-                    // invalidate the caches on every poll); the acquire fence
-                    // below orders the step's reads after the count is seen.  A
-                    // step that never completes (a planning bug) raises the
-                    // error word and lets the queue drain instead of hanging.
-                    const unsigned need = t.step_items[step - 1];
-                    const unsigned *d = &done[(size_t)(step - 1) * kSchedStride];
-                    unsigned spins = 0;
-                    while (__hip_atomic_load(d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                           need) {
-                        if (++spins > kMaxSpins) {
-                            __hip_atomic_store(error, 1u, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(2);
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                }
-                __syncthreads();  // the other waves read after thread 0's acquire
+            const int pi = __builtin_amdgcn_readfirstlane(t.seg_phase[seg]);
+            const unsigned tile =
+                __builtin_amdgcn_readfirstlane(item - t.seg_start[seg]) * kBatchQuarters + quarter;
+            run_phase(t.phases[pi], tile, qlds);
+            ++completed;
+            ++item;
+        }
+    }
+    // The last block to finish checks that every queue completed its last step
+    // (a queue whose XCD ran no block of the grid would not have).
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned before = __hip_atomic_fetch_add(sched_line(sched, kSchedExit), 1u,
+                                                       __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (before + 1 == gridDim.x) {
+            for (int qq = 0; qq < t.nqueues; ++qq) {
+                const int ns = t.q_step[qq + 1] - t.q_step[qq];
+                if (ns == 0) continue;
+                const int last = t.q_step[qq + 1] - 1;
+                const unsigned got = __hip_atomic_load(
+                    sched_line(sched, kSchedClaim + t.nqueues + last), __ATOMIC_RELAXED,
+                    __HIP_MEMORY_SCOPE_AGENT);
+                if (got < t.step_items[last])
+                    __hip_atomic_fetch_or(error, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        const int pi = __builtin_amdgcn_readfirstlane(t.seg_phase[seg]);
-        const unsigned tile =
-            __builtin_amdgcn_readfirstlane(item - t.seg_start[seg]) * kBatchQuarters +
-            (threadIdx.x >> 8);
-        run_phase(t.phases[pi], tile, qlds);
-        ++completed;
-        ++item;
     }
 }
 
@@ -1553,11 +1620,16 @@ void hrc_persistent_dense(const BatchTables t, unsigned *sched) {
     persistent_loop(t, sched, lds, s_item);
 }
 
-// Clears the scheduler state (a kernel rather than a memset so that it can be
-// captured in a graph and replayed).
-__global__ void hrc_clear_u32(unsigned *p, unsigned n) {
-    unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+// Clears words [from, n) of the scheduler state (a kernel rather than a memset
+// so that it can be captured in a graph and replayed).
+__global__ void hrc_clear_u32(unsigned *p, unsigned from, unsigned n) {
+    unsigned i = from + blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0u;
+}
+
+// The XCD of every block (thread 0 writes it), for the planner to map queues.
+__global__ __launch_bounds__(256 * kBatchQuarters) void hrc_xcd_probe(unsigned *out) {
+    if (threadIdx.x == 0) out[blockIdx.x] = xcc_id();
 }
 
 // Sets *flag when any element of a or b is negative or not finite.
@@ -1650,12 +1722,19 @@ hipError_t launch_phase(const Phase &p, hipStream_t s, hipEvent_t start, hipEven
 
 hipError_t launch_persistent(const BatchTables &t, unsigned *sched, int grid, int variant,
                              hipStream_t s) {
-    const unsigned n = (unsigned)sched_words(t.nsteps);
-    hipLaunchKernelGGL(hrc_clear_u32, dim3((n + 255) / 256), dim3(256), 0, s, sched, n);
+    const unsigned from = kSchedExit * kSchedStride;
+    const unsigned n = (unsigned)sched_words(t.nqueues, t.q_step[t.nqueues]);
+    hipLaunchKernelGGL(hrc_clear_u32, dim3((n - from + 255) / 256), dim3(256), 0, s, sched, from,
+                       n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(variant ? hrc_persistent_dense : hrc_persistent, dim3(grid),
                        dim3(256 * kBatchQuarters), 0, s, t, sched);
+    return hipGetLastError();
+}
+
+hipError_t launch_xcd_probe(unsigned *out, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(hrc_xcd_probe, dim3(grid), dim3(256 * kBatchQuarters), 0, s, out);
     return hipGetLastError();
 }
 

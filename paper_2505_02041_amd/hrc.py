@@ -299,6 +299,18 @@ class Batch:
         check(_lib.load().hrc_batch_launch(self._ptr, _stream_handle(self._device)),
               "hrc_batch_launch")
 
+    def status(self) -> None:
+        """Wait for the launches so far and raise (``HRC_ERR_TIMEOUT``) if one of
+        them left a pass incomplete (``hrc_batch_status``)."""
+        check(_lib.load().hrc_batch_status(self._ptr, _stream_handle(self._device)),
+              "hrc_batch_status")
+
+    def debug_waits(self, spins: int) -> None:
+        """Failure testing (``hrc_batch_debug_waits``): with spins > 0 every
+        dependency wait of later launches gives up after that many polls."""
+        torch.cuda.synchronize(self._device)
+        check(_lib.load().hrc_batch_debug_waits(self._ptr, int(spins)), "hrc_batch_debug_waits")
+
     @property
     def workspace_bytes(self) -> int:
         return int(_lib.load().hrc_batch_workspace_bytes(self._ptr))
@@ -310,8 +322,26 @@ class Batch:
         check(_lib.load().hrc_batch_describe(self._ptr, ctypes.byref(v), ctypes.byref(g),
                                              ctypes.byref(t), ctypes.byref(c), ctypes.byref(d)),
               "hrc_batch_describe")
+        nq, xl, sl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(_lib.load().hrc_batch_queues(self._ptr, ctypes.byref(nq), ctypes.byref(xl),
+                                           ctypes.byref(sl)), "hrc_batch_queues")
         return {"variant": v.value, "grid": g.value, "target_tiles": t.value,
-                "chunk_groups": c.value, "direct_scenes": d.value}
+                "chunk_groups": c.value, "direct_scenes": d.value, "queues": nq.value,
+                "xcd_local": xl.value, "slots_per_queue": sl.value}
+
+    def candidates(self) -> List[dict]:
+        """Every candidate the autotuner timed (``hrc_batch_candidates``)."""
+        n = ctypes.c_int(0)
+        check(_lib.load().hrc_batch_candidates(self._ptr, 0, ctypes.byref(n), None, None),
+              "hrc_batch_candidates")
+        cap = n.value
+        desc = (ctypes.c_int * (7 * max(cap, 1)))()
+        ms = (ctypes.c_float * max(cap, 1))()
+        check(_lib.load().hrc_batch_candidates(self._ptr, cap, ctypes.byref(n), desc, ms),
+              "hrc_batch_candidates")
+        keys = ("direct_from_log2", "queues", "xcd_local", "slots_per_queue", "variant",
+                "target_tiles", "chunk_groups")
+        return [dict(zip(keys, desc[7 * i:7 * i + 7]), ms=ms[i]) for i in range(cap)]
 
     def __del__(self):
         ptr = getattr(self, "_ptr", None)

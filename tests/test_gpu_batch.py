@@ -1,15 +1,23 @@
-"""The batched launch (persistent kernel, plus the larger scenes as kernels of
-their own where the autotuner picks that): bitwise equal to single-scene calls,
-replayed several times, with mixed sizes and forward-only scenes."""
+"""The batched launch (persistent kernel with one queue per XCD, plus the
+larger scenes as kernels of their own where the autotuner picks that): bitwise
+equal to single-scene calls, replayed several times, with mixed sizes and
+forward-only scenes; the whole 64-scene batch workload against the single-scene
+calls and, for its scenes up to 256^2 and two of 512^2, against the oracle; and
+the failure path of the dependency waits, forced from the host."""
+import os
+from concurrent.futures import ProcessPoolExecutor
+
 import numpy as np
 import pytest
 import torch
 
+from oracle import hrc as oracle
+from oracle import hrc_vjp
 from scenes import config5, scene_like_512
 
 pytestmark = pytest.mark.gpu
 
-from gpu_common import log, to_dev  # noqa: E402
+from gpu_common import assert_forward_close, assert_grad_close, log, to_dev  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -64,7 +72,7 @@ def test_batch_small_mixed_sizes(ctx, flags):
                 d["grad_emission"].fill_(float("nan"))
                 d["grad_sigma_t"].fill_(float("nan"))
         b.launch()
-        torch.cuda.synchronize()
+        b.status()
         _check_against_single(ctx, items)
     del b
 
@@ -82,7 +90,81 @@ def test_batch_benchmark_workload_subset(ctx, flags):
     if flags & 0x400:
         assert b.describe()["direct_scenes"] == 0
     b.launch()
-    torch.cuda.synchronize()
+    b.status()
     _check_against_single(ctx, items)
     ctx.release_workspaces()
+    del b
+
+
+def _oracle_one(args):
+    eps, sig, dF = args
+    F = oracle.fluence(eps, sig)
+    ge, gs = hrc_vjp.fluence_vjp(eps, sig, dF)
+    return F, ge, gs
+
+
+@pytest.mark.parametrize("flags", [0, 0x400], ids=["autotuned", "persistent-only"])
+def test_batch_workload_64_scenes(ctx, flags):
+    """The 64-scene batch workload (sizes drawn from 128^2..1024^2, forward and
+    backward for every scene): every scene bitwise equal to its single-scene
+    calls, the scheduler's status clean after two launches, and the batch's
+    own outputs for the scenes up to 256^2 and two of the 512^2 scenes against
+    the oracle's forward and reverse passes."""
+    from paper_2505_02041_amd import Batch
+    log(f"batch: the 64-scene workload, flags {flags:#x}")
+    scenes = config5()
+    assert len(scenes) == 64
+    items = _make(scenes, lambda i: True)
+    b = Batch(items, ctx, flags=flags)
+    d = b.describe()
+    log(f"  autotuned: {d}")
+    if flags & 0x400:
+        assert d["direct_scenes"] == 0
+    for _ in range(2):
+        b.launch()
+    b.status()
+    small = [i for i, sc in enumerate(scenes) if sc.eps.shape[0] <= 256]
+    small += [i for i, sc in enumerate(scenes) if sc.eps.shape[0] == 512][:2]
+    got = {i: (items[i]["fluence"].cpu().numpy(), items[i]["grad_emission"].cpu().numpy(),
+               items[i]["grad_sigma_t"].cpu().numpy()) for i in small}
+    _check_against_single(ctx, items)
+    ctx.release_workspaces()
+    del b
+    log(f"  oracle on {len(small)} scenes")
+    jobs = [(scenes[i].eps, scenes[i].sigma, items[i]["grad_fluence"].cpu().numpy())
+            for i in small]
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        refs = list(ex.map(_oracle_one, jobs))
+    for i, (F, ge, gs) in zip(small, refs):
+        S = scenes[i].eps.shape[0]
+        assert_forward_close(got[i][0], F, f"batch scene {i} ({S}^2) fluence")
+        assert_grad_close(got[i][1], ge, f"batch scene {i} ({S}^2) d eps")
+        assert_grad_close(got[i][2], gs, f"batch scene {i} ({S}^2) d sigma")
+
+
+def test_batch_wait_failure_is_reported(ctx):
+    """A dependency wait that gives up is reported by hrc_batch_status, forced
+    from the host: every wait asks for one group more than its step holds and
+    gives up after a few polls, so every kernel still runs to its end.  With
+    normal waits restored the next launch is clean and bitwise correct."""
+    from paper_2505_02041_amd import Batch
+    from paper_2505_02041_amd._lib import HRC_ERR_TIMEOUT, HRCError
+    log("batch: forced wait failure")
+    scenes = [scene_like_512(S, 90 + i, 3, 4) for i, S in enumerate([32, 64, 128, 64])]
+    items = _make(scenes, lambda i: i != 1)
+    b = Batch(items, ctx, flags=0x400)
+    b.status()
+    b.debug_waits(16)
+    b.launch()
+    with pytest.raises(HRCError) as e:
+        b.status()
+    assert e.value.status == HRC_ERR_TIMEOUT
+    b.status()  # the report was cleared
+    b.debug_waits(0)
+    for d in items:
+        d["fluence"].fill_(float("nan"))
+    b.launch()
+    b.status()
+    _check_against_single(ctx, items)
     del b
