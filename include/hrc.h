@@ -87,8 +87,9 @@ typedef enum {
 #define HRC_FLAG_QUADRANTS_2 0x20u
 #define HRC_FLAG_QUADRANTS_4 0x30u
 #define HRC_FLAG_QUADRANTS_MASK 0x30u
-/* hrc_batch_plan only: run the persistent kernel variant 0 (full register
- * budget) or 1 (64 registers) instead of letting the autotuner choose;
+/* hrc_batch_plan only: run a persistent kernel variant with the full register
+ * budget (HRC_FLAG_BATCH_FULL) or with 64 registers (HRC_FLAG_BATCH_DENSE)
+ * instead of letting the autotuner choose between them;
  * HRC_FLAG_BATCH_PERSISTENT: run every scene inside the persistent kernel
  * (none as its own kernels). */
 #define HRC_FLAG_BATCH_FULL 0x100u
@@ -290,12 +291,13 @@ hrc_status hrc_batch_debug_waits(hrc_batch *batch, unsigned spins);
 size_t hrc_batch_workspace_bytes(const hrc_batch *batch);
 
 /* What the autotuner chose for a planned batch: the persistent kernel variant
- * (0: full register budget, one 1024-thread block per CU; 1: 64 registers,
- * two blocks per CU), the grid in blocks, the target tile count per pass
- * (each tile 256 threads), the tiles-groups a block claims at once (a group
- * is the four tiles a block runs side by side), and how many scenes run as
- * kernels of their own.  Any output pointer may be NULL.  Pure host
- * function; HRC_ERR_INVALID_ARG for a NULL batch. */
+ * (0: 1024-thread blocks, four tiles side by side, full register budget; 1:
+ * the same with 64 registers, twice the resident blocks; 2, 3: 256-thread
+ * blocks, one tile each, full budget or 64 registers), the grid in blocks, the
+ * target tile count per pass (each tile 256 threads), the tile groups a block
+ * claims at once (a group is the tiles a block runs side by side), and how
+ * many scenes run as kernels of their own.  Any output pointer may be NULL.
+ * Pure host function; HRC_ERR_INVALID_ARG for a NULL batch. */
 hrc_status hrc_batch_describe(const hrc_batch *batch, int *variant, int *grid,
                               int *target_tiles, int *chunk, int *direct_scenes);
 

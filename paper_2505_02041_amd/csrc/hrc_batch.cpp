@@ -160,6 +160,7 @@ struct Arrangement {
     int nqueues = 1;
     int slots = 0;                      // workspace slots per queue; 0 = one per scene
     int target = 0;                     // tiles per phase
+    int quarters = kMaxQuarters;        // tiles per group (per block of the kernel variant)
     std::vector<Phase> direct;          // direct scenes' passes in order
     std::vector<Phase> phases;          // the persistent kernel's passes
     std::vector<unsigned> seg_start;
@@ -294,7 +295,7 @@ void arrange(Arrangement &ar, const hrc_scene *scenes, int count, char *base) {
                     // whole groups of tiles; the bodies store nothing for tiles
                     // past the phase's own count
                     const unsigned groups =
-                        (phase_tiles(ar.phases[gi]) + kBatchQuarters - 1) / kBatchQuarters;
+                        (phase_tiles(ar.phases[gi]) + ar.quarters - 1) / ar.quarters;
                     ar.seg_start.push_back(pos);
                     ar.seg_phase.push_back(gi);
                     ar.seg_step.push_back(t);
@@ -325,8 +326,8 @@ void free_batch(hrc_batch *b) {
 // Queues the persistent kernel can use on this device with `grid` blocks: the
 // number of XCDs if every XCD runs at least one block of the grid (probed),
 // else 0.
-int probe_xcds(int grid, unsigned *dbuf, hipStream_t s) {
-    if (launch_xcd_probe(dbuf, grid, s) != hipSuccess) return 0;
+int probe_xcds(int grid, int variant, unsigned *dbuf, hipStream_t s) {
+    if (launch_xcd_probe(dbuf, grid, variant, s) != hipSuccess) return 0;
     std::vector<unsigned> h(grid);
     if (hipMemcpyAsync(h.data(), dbuf, grid * sizeof(unsigned), hipMemcpyDeviceToHost, s) !=
             hipSuccess ||
@@ -439,7 +440,8 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
         if (persistent_occupancy(v, &per_cu) != hipSuccess || per_cu <= 0) per_cu = 1;
         grids[v] = ctx->num_cus * per_cu;
         xcds[v] = grids[v] <= kMaxProbe
-                      ? probe_xcds(grids[v], reinterpret_cast<unsigned *>(b->tmem + probe_off), cap)
+                      ? probe_xcds(grids[v], v, reinterpret_cast<unsigned *>(b->tmem + probe_off),
+                                   cap)
                       : 0;
     }
 
@@ -505,8 +507,9 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
     }
     std::vector<int> variants;
     for (int v = 0; v < kPersistentVariants; ++v) {
-        if ((flags & HRC_FLAG_BATCH_FULL) && v != 0) continue;
-        if ((flags & HRC_FLAG_BATCH_DENSE) && v != 1) continue;
+        // variants 0, 2: full register budget; 1, 3: 64 VGPRs
+        if ((flags & HRC_FLAG_BATCH_FULL) && v % 2 != 0) continue;
+        if ((flags & HRC_FLAG_BATCH_DENSE) && v % 2 != 1) continue;
         variants.push_back(v);
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -522,7 +525,8 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
         ar.min_direct = c.min_direct;
         ar.nqueues = xcd_local ? c.xcd : 1;
         ar.slots = c.slots;
-        ar.target = std::max(1, grids[variant] / ar.nqueues) * kBatchQuarters * c.mult;
+        ar.quarters = persistent_quarters(variant);
+        ar.target = std::max(1, grids[variant] / ar.nqueues) * ar.quarters * c.mult;
         arrange(ar, scenes, count, b->dmem);
         return ar.ws_bytes <= b->dmem_bytes && upload();
     };
@@ -556,7 +560,11 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
             best = c;
         }
     };
-    const int xcd_opts[] = {xcds[0] > 1 && xcds[1] > 1 ? xcds[0] : 0, 0};
+    // per-XCD queues when every variant's grid reaches the same XCDs
+    int xcd_q = xcds[0];
+    for (int v = 1; v < kPersistentVariants; ++v)
+        if (xcds[v] != xcd_q) xcd_q = 0;
+    const int xcd_opts[] = {xcd_q > 1 ? xcd_q : 0, 0};
     for (int md : min_directs) {
         bool all_direct = true;
         for (int i = 0; i < count; ++i) all_direct = all_direct && scenes[i].log2_size >= md;
@@ -590,7 +598,8 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
         ar.min_direct = best.min_direct;
         ar.nqueues = best.xcd > 0 ? best.xcd : 1;
         ar.slots = best.slots;
-        ar.target = std::max(1, grids[best.variant] / ar.nqueues) * kBatchQuarters * best.mult;
+        ar.quarters = persistent_quarters(best.variant);
+        ar.target = std::max(1, grids[best.variant] / ar.nqueues) * ar.quarters * best.mult;
         arrange(ar, scenes, count, nullptr);  // sizes only
         if (ar.ws_bytes < b->dmem_bytes) {
             (void)hipFree(b->dmem);

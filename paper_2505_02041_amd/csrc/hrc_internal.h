@@ -192,10 +192,11 @@ hipError_t launch_phase(const Phase &p, hipStream_t s, hipEvent_t start = nullpt
 // one up to q_items[q]) = the tiles of phase seg_phase[i], in step seg_step[i]
 // (counted from the queue's first step); step_items[q_step[q] + t] counts the
 // items of step t of queue q.
-// The persistent kernel's blocks hold kBatchQuarters 256-thread quarters, each
-// running one tile; work is scheduled in groups of kBatchQuarters consecutive
-// tiles of one phase (phases padded with empty tiles to whole groups).
-constexpr int kBatchQuarters = 4;
+// The persistent kernel's blocks hold one or four 256-thread quarters
+// (persistent_quarters(variant)), each running one tile; work is scheduled in
+// groups of that many consecutive tiles of one phase (phases padded with empty
+// tiles to whole groups).
+constexpr int kMaxQuarters = 4;
 constexpr int kMaxQueues = 16;
 struct BatchTables {
     const Phase *phases;
@@ -224,14 +225,17 @@ constexpr size_t sched_words(int nqueues, int total_steps) {
     return (size_t)kSchedStride * (kSchedClaim + nqueues + total_steps);
 }
 // Clears the per-launch scheduler words and launches the persistent kernel.
-// variant 0: full register budget; 1: 64 VGPRs (twice the resident blocks).
-constexpr int kPersistentVariants = 2;
+// Variants: 0 and 1 run 1024-thread blocks (four tiles side by side) with the
+// full register budget or with 64 VGPRs (twice the resident blocks); 2 and 3
+// run 256-thread blocks (one tile), likewise.
+constexpr int kPersistentVariants = 4;
+constexpr int persistent_quarters(int variant) { return variant < 2 ? 4 : 1; }
 hipError_t launch_persistent(const BatchTables &t, unsigned *sched, int grid, int variant,
                              hipStream_t s);
 hipError_t persistent_occupancy(int variant, int *blocks_per_cu);
-// Writes the XCD of every block of a `grid` x (256 * kBatchQuarters) launch to
-// out[block] (the queue a block of the persistent kernel would serve).
-hipError_t launch_xcd_probe(unsigned *out, int grid, hipStream_t s);
+// Writes the XCD of every block of a `grid`-block launch of `variant`'s block
+// size to out[block] (the queue a block of the persistent kernel would serve).
+hipError_t launch_xcd_probe(unsigned *out, int grid, int variant, hipStream_t s);
 hipError_t launch_validate(const float *a, const float *b, size_t n, int *flag,
                            hipStream_t s);
 

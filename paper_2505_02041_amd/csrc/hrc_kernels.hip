@@ -1447,9 +1447,9 @@ __global__ __launch_bounds__(256) void hrc_gather_adj(Phase p) {
 }
 
 // ---------------------------------------------------------------------------
-// Persistent batch kernel.  Work items are groups of kBatchQuarters tiles of
-// one phase, run side by side by the block's quarters (so every quarter passes
-// the same barriers), in queues of steps: a queue's step t depends only on its
+// Persistent batch kernel.  Work items are groups of Q tiles of one phase
+// (Q = 1 or 4 256-thread quarters per block), run side by side by the block's
+// quarters (so every quarter passes the same barriers), in queues of steps: a queue's step t depends only on its
 // steps before t.  Blocks claim chunks of consecutive items from their queue's
 // counter and run them in order.  A block counts the items it finishes in the
 // current step and publishes that count (one atomic add) when it reaches an
@@ -1482,10 +1482,11 @@ __device__ __forceinline__ unsigned *sched_line(unsigned *sched, unsigned line) 
     return sched + (size_t)line * kSchedStride;
 }
 
+template <int Q>
 __device__ __forceinline__ void persistent_loop(const BatchTables &t, unsigned *sched, char *lds,
                                                 unsigned &s_item) {
     // this quarter's LDS (the quarter is uniform over each wave)
-    const unsigned quarter = __builtin_amdgcn_readfirstlane(threadIdx.x >> 8);
+    const unsigned quarter = Q == 1 ? 0u : __builtin_amdgcn_readfirstlane(threadIdx.x >> 8);
     char *qlds = lds + quarter * kMaxLds;
     unsigned *error = sched_line(sched, kSchedError);
     const int q = t.xcd_local ? (int)xcc_id() : 0;
@@ -1577,7 +1578,7 @@ __device__ __forceinline__ void persistent_loop(const BatchTables &t, unsigned *
             }
             const int pi = __builtin_amdgcn_readfirstlane(t.seg_phase[seg]);
             const unsigned tile =
-                __builtin_amdgcn_readfirstlane(item - t.seg_start[seg]) * kBatchQuarters + quarter;
+                __builtin_amdgcn_readfirstlane(item - t.seg_start[seg]) * Q + quarter;
             run_phase(t.phases[pi], tile, qlds);
             ++completed;
             ++item;
@@ -1604,20 +1605,41 @@ __device__ __forceinline__ void persistent_loop(const BatchTables &t, unsigned *
     }
 }
 
-// Two register budgets for the same loop: the full budget (one block per CU)
-// and 64 VGPRs (two blocks per CU, at the cost of some spills in the larger
-// bodies).  The batch planner times both.
-__global__ __launch_bounds__(256 * kBatchQuarters) void hrc_persistent(const BatchTables t,
-                                                                        unsigned *sched) {
-    __shared__ __align__(16) char lds[kBatchQuarters * kMaxLds];
+// Two block sizes (four tiles side by side, or one) and two register budgets
+// for the same loop: the full budget, or 64 VGPRs (eight waves per SIMD, at
+// the cost of some spills in the larger bodies).  The batch planner times all
+// four.
+__global__ __launch_bounds__(1024) void hrc_persistent(const BatchTables t, unsigned *sched) {
+    __shared__ __align__(16) char lds[4 * kMaxLds];
     __shared__ unsigned s_item;
-    persistent_loop(t, sched, lds, s_item);
+    persistent_loop<4>(t, sched, lds, s_item);
 }
-__global__ __launch_bounds__(256 * kBatchQuarters) __attribute__((amdgpu_waves_per_eu(8)))
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
 void hrc_persistent_dense(const BatchTables t, unsigned *sched) {
-    __shared__ __align__(16) char lds[kBatchQuarters * kMaxLds];
+    __shared__ __align__(16) char lds[4 * kMaxLds];
     __shared__ unsigned s_item;
-    persistent_loop(t, sched, lds, s_item);
+    persistent_loop<4>(t, sched, lds, s_item);
+}
+__global__ __launch_bounds__(256) void hrc_persistent_1(const BatchTables t, unsigned *sched) {
+    __shared__ __align__(16) char lds[kMaxLds];
+    __shared__ unsigned s_item;
+    persistent_loop<1>(t, sched, lds, s_item);
+}
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+void hrc_persistent_1_dense(const BatchTables t, unsigned *sched) {
+    __shared__ __align__(16) char lds[kMaxLds];
+    __shared__ unsigned s_item;
+    persistent_loop<1>(t, sched, lds, s_item);
+}
+
+typedef void (*PersistentKernel)(const BatchTables, unsigned *);
+static PersistentKernel persistent_kernel(int variant) {
+    switch (variant) {
+        case 0: return hrc_persistent;
+        case 1: return hrc_persistent_dense;
+        case 2: return hrc_persistent_1;
+        default: return hrc_persistent_1_dense;
+    }
 }
 
 // Clears words [from, n) of the scheduler state (a kernel rather than a memset
@@ -1628,7 +1650,7 @@ __global__ void hrc_clear_u32(unsigned *p, unsigned from, unsigned n) {
 }
 
 // The XCD of every block (thread 0 writes it), for the planner to map queues.
-__global__ __launch_bounds__(256 * kBatchQuarters) void hrc_xcd_probe(unsigned *out) {
+__global__ __launch_bounds__(1024) void hrc_xcd_probe(unsigned *out) {
     if (threadIdx.x == 0) out[blockIdx.x] = xcc_id();
 }
 
@@ -1728,19 +1750,20 @@ hipError_t launch_persistent(const BatchTables &t, unsigned *sched, int grid, in
                        n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(variant ? hrc_persistent_dense : hrc_persistent, dim3(grid),
-                       dim3(256 * kBatchQuarters), 0, s, t, sched);
+    hipLaunchKernelGGL(persistent_kernel(variant), dim3(grid),
+                       dim3(256 * persistent_quarters(variant)), 0, s, t, sched);
     return hipGetLastError();
 }
 
-hipError_t launch_xcd_probe(unsigned *out, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(hrc_xcd_probe, dim3(grid), dim3(256 * kBatchQuarters), 0, s, out);
+hipError_t launch_xcd_probe(unsigned *out, int grid, int variant, hipStream_t s) {
+    hipLaunchKernelGGL(hrc_xcd_probe, dim3(grid), dim3(256 * persistent_quarters(variant)), 0, s,
+                       out);
     return hipGetLastError();
 }
 
 hipError_t persistent_occupancy(int variant, int *blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        blocks_per_cu, variant ? hrc_persistent_dense : hrc_persistent, 256 * kBatchQuarters, 0);
+        blocks_per_cu, persistent_kernel(variant), 256 * persistent_quarters(variant), 0);
 }
 
 // Multiple bounces: the in-scattering source of the next bounce and the reverse
