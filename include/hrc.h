@@ -51,7 +51,8 @@ typedef enum {
     HRC_ERR_HIP = -4,          /* a HIP runtime call or kernel launch failed */
     HRC_ERR_UNSUPPORTED = -5,  /* unknown flag bits, or a flag the call does not take */
     HRC_ERR_INPUT = -6,        /* HRC_FLAG_VALIDATE found a negative or non-finite input */
-    HRC_ERR_TIMEOUT = -7       /* a batch's dependency wait gave up (hrc_batch_status) */
+    HRC_ERR_TIMEOUT = -7,      /* a batch's dependency wait gave up (hrc_batch_status) */
+    HRC_ERR_TOO_LARGE = -8     /* grid larger than hrc_forward_static takes */
 } hrc_status;
 
 #define HRC_MIN_LOG2 3
@@ -147,6 +148,24 @@ hrc_status hrc_forward(hrc_context *ctx, int log2_size,
                        const float *emission, const float *sigma_t, float *fluence,
                        void *workspace, size_t workspace_bytes,
                        void *stream, unsigned flags);
+
+/* hrc_forward without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the same passes, launch shapes and results, bitwise,
+ * as hrc_forward with the same flags, using instead a scratch array of
+ * 69 MiB (72,351,744 bytes) that the library holds in every device it runs on
+ * until the process ends (its address is looked up by hrc_create).  Takes
+ * grids up to 2^9 per side (log2_size <= 9); larger ones return
+ * HRC_ERR_TOO_LARGE before any device call.  Allocates, frees and
+ * synchronises nothing; flags as hrc_forward except HRC_FLAG_VALIDATE
+ * (HRC_ERR_UNSUPPORTED: it synchronises).  Every call on one device shares that
+ * device's scratch, and what a call leaves there is overwritten by the next
+ * (nothing in it needs clearing: every pass writes what it later reads), so
+ * calls that overlap on one device race: run them on one stream, or one at a
+ * time. */
+hrc_status hrc_forward_static(hrc_context *ctx, int log2_size,
+                              const float *emission, const float *sigma_t, float *fluence,
+                              void *stream, unsigned flags);
 
 /* Vector-Jacobian product of hrc_forward: given grad_fluence = dLoss/dF,
  * writes dLoss/d(emission) and dLoss/d(sigma_t).  The forward intervals and

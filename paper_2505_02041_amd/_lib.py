@@ -19,6 +19,7 @@ HRC_ERR_HIP = -4
 HRC_ERR_UNSUPPORTED = -5
 HRC_ERR_INPUT = -6
 HRC_ERR_TIMEOUT = -7
+HRC_ERR_TOO_LARGE = -8
 HRC_MIN_LOG2 = 3
 HRC_MAX_LOG2 = 12
 HRC_FLAG_VALIDATE = 0x1
@@ -64,6 +65,8 @@ SIGNATURES = {
                                            ctypes.POINTER(_sz), ctypes.POINTER(_sz)]),
     "hrc_forward": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _sz, _vp,
                                    ctypes.c_uint]),
+    "hrc_forward_static": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp,
+                                          ctypes.c_uint]),
     "hrc_backward": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
                                     _vp, ctypes.c_uint]),
     "hrc_multibounce_workspace_bytes": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_uint,

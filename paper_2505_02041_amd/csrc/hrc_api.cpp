@@ -107,6 +107,15 @@ static void environment_table(const float *radiance, int K, float *out) {
     }
 }
 
+// Scratch of hrc_forward_static: the FP32 forward workspace of the largest
+// grid it takes (2^9 per side, all four quadrants at once: 72,319,232 bytes),
+// in device memory every device the library runs on holds until the process
+// ends.  Host code never passes the array's name to a kernel or a copy: it
+// uses the device address hrc_create looked up (hrc_context::scratch).
+constexpr int kStaticMaxLog2 = 9;
+constexpr size_t kStaticScratchBytes = size_t(69) << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
 static bool aligned16(const void *p) { return p && (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 static hrc_status check_shape(int log2_size) {
@@ -276,6 +285,7 @@ const char *hrc_status_string(hrc_status s) {
         case HRC_ERR_UNSUPPORTED: return "HRC_ERR_UNSUPPORTED: unknown flag bits, or a flag this call does not take";
         case HRC_ERR_INPUT: return "HRC_ERR_INPUT: negative or non-finite emission or attenuation";
         case HRC_ERR_TIMEOUT: return "HRC_ERR_TIMEOUT: a dependency wait of the batch gave up; that launch's results are incomplete";
+        case HRC_ERR_TOO_LARGE: return "HRC_ERR_TOO_LARGE: grid larger than hrc_forward_static's scratch holds (log2_size <= 9)";
     }
     return "HRC: unknown status";
 }
@@ -304,9 +314,14 @@ hrc_status hrc_create(int device, hrc_context **out) {
     std::vector<float> table(kConeTable);
     cone_table(table.data());
     if (upload_cone_table(table.data()) != hipSuccess) return HRC_ERR_HIP;
+    // the device address of hrc_forward_static's scratch on this device (each
+    // device holds its own copy of the array)
+    void *scr = nullptr;
+    if (hipGetSymbolAddress(&scr, HIP_SYMBOL(scratch)) != hipSuccess || !scr) return HRC_ERR_HIP;
     hrc_context *ctx = static_cast<hrc_context *>(calloc(1, sizeof(hrc_context)));
     if (!ctx) return HRC_ERR_HIP;
     ctx->device = device;
+    ctx->scratch = static_cast<char *>(scr);
     hipDeviceProp_t prop;
     ctx->num_cus = (hipGetDeviceProperties(&prop, device) == hipSuccess) ? prop.multiProcessorCount : 256;
     *out = ctx;
@@ -372,6 +387,31 @@ hrc_status hrc_forward(hrc_context *ctx, int log2_size, const float *emission,
                    half ? 1 : 0};
     int np = build_solve_phases(w, b, false, nullptr, ph, kMaxPhases);
     return run_phases(ph, np, s);
+}
+
+hrc_status hrc_forward_static(hrc_context *ctx, int log2_size, const float *emission,
+                              const float *sigma_t, float *fluence, void *stream,
+                              unsigned flags) {
+    hrc_status st = check_shape(log2_size);
+    if (st != HRC_OK) return st;
+    if (!aligned16(emission) || !aligned16(sigma_t) || !aligned16(fluence))
+        return HRC_ERR_INVALID_ARG;
+    if (flags & ~(kForwardFlags & ~HRC_FLAG_VALIDATE)) return HRC_ERR_UNSUPPORTED;
+    if (log2_size > kStaticMaxLog2) return HRC_ERR_TOO_LARGE;
+    const bool half = (flags & HRC_FLAG_HALF_INTERVALS) != 0;
+    Layout L = make_layout(log2_size, false, forward_group(log2_size, flags), half);
+    if (L.total > kStaticScratchBytes) return HRC_ERR_TOO_LARGE;
+    if (!ctx || !ctx->scratch) return HRC_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return HRC_ERR_HIP;
+    // the same passes and launch shapes as hrc_forward, on the scratch
+    Ws w{ctx->scratch, L};
+    Phase ph[kMaxPhases];
+    SolveBuffers b{emission, sigma_t, fluence, nullptr, nullptr, nullptr,
+                   (flags & HRC_FLAG_BLUR) ? 1 : 0, ctx->has_env ? ctx->env : nullptr,
+                   half ? 1 : 0};
+    int np = build_solve_phases(w, b, false, nullptr, ph, kMaxPhases);
+    return run_phases(ph, np, static_cast<hipStream_t>(stream));
 }
 
 hrc_status hrc_backward(hrc_context *ctx, int log2_size, const float *emission,

@@ -12,6 +12,7 @@ struct hrc_context {
     int num_cus;
     float *env;    // device [4][kConeTable]: environment fluence per quadrant and cone
     int has_env;   // set by hrc_set_environment
+    char *scratch; // device address of hrc_forward_static's scratch on this device
 };
 
 namespace hrc {

@@ -107,6 +107,21 @@ class Context:
                                       _stream_handle(emission.device), flags), "hrc_forward")
         return out
 
+    def hrc_forward_static(self, emission: torch.Tensor, sigma_t: torch.Tensor,
+                           out: torch.Tensor, flags: int = 0) -> torch.Tensor:
+        """``hrc_forward_static``: the forward on the library's own device scratch
+        (no workspace; grids up to 512^2), writing into the caller's ``out``."""
+        for t, n in ((emission, "emission"), (sigma_t, "sigma_t"), (out, "out")):
+            _check_field(t, n)
+        N = _log2_size(emission)
+        if sigma_t.shape != emission.shape or out.shape != emission.shape:
+            raise ValueError("emission, sigma_t and out shapes differ")
+        check(_lib.load().hrc_forward_static(self._ptr, N, emission.data_ptr(),
+                                             sigma_t.data_ptr(), out.data_ptr(),
+                                             _stream_handle(emission.device), flags),
+              "hrc_forward_static")
+        return out
+
     def hrc_backward(self, emission: torch.Tensor, sigma_t: torch.Tensor,
                      grad_fluence: torch.Tensor, flags: int = 0):
         for t, n in ((emission, "emission"), (sigma_t, "sigma_t"), (grad_fluence, "grad_fluence")):
