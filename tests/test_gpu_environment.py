@@ -44,7 +44,7 @@ def test_uniform_environment_in_vacuum(ctx, S):
     assert np.allclose(F, 2 * math.pi * 1.5, rtol=2e-6, atol=0)
 
 
-@pytest.mark.parametrize("S,K", [(8, 4), (64, 16), (128, 61)])
+@pytest.mark.parametrize("S,K", [(8, 4), (16, 2), (64, 16), (128, 61)])
 def test_environment_forward_matches_oracle(ctx, S, K):
     log(f"environment forward S={S} K={K}")
     if S == 128:

@@ -120,3 +120,43 @@ def test_environment_gradient_central_differences():
             fa = (hrc.fluence(a["eps"], a["sig"], environment=env) * dF).sum()
             fb = (hrc.fluence(b["eps"], b["sig"], environment=env) * dF).sum()
             assert grad[r, c] == pytest.approx((fa - fb) / (2 * h), rel=1e-6, abs=1e-8)
+
+
+def test_halfway_directions_take_the_next_sample_counter_clockwise():
+    """The tie-break of reading R15, fixed by hand: a direction exactly halfway
+    between two samples of the map takes the next sample counter-clockwise
+    (towards increasing angle).  Two samples [E0 at 0, E1 at pi]: the +y axis
+    (pi/2) lies halfway and takes E1, the -y axis (-pi/2, i.e. 3 pi/2) takes E0
+    (round half to even would give E0 and E0).  Four samples at 0, pi/2, pi,
+    3 pi/2: pi/4 -> the one at pi/2, 3 pi/4 -> pi, -3 pi/4 -> 3 pi/2,
+    -pi/4 -> 0."""
+    two = [10.0, 20.0]
+    assert hrc.environment_radiance(two, math.pi / 2) == 20.0
+    assert hrc.environment_radiance(two, -math.pi / 2) == 10.0
+    four = [1.0, 2.0, 3.0, 4.0]
+    assert hrc.environment_radiance(four, math.pi / 4) == 2.0
+    assert hrc.environment_radiance(four, 3 * math.pi / 4) == 3.0
+    assert hrc.environment_radiance(four, -3 * math.pi / 4) == 4.0
+    assert hrc.environment_radiance(four, -math.pi / 4) == 1.0
+    # away from a tie the nearest sample wins on either side
+    assert hrc.environment_radiance(two, math.pi / 2 - 1e-9) == 10.0
+    assert hrc.environment_radiance(two, math.pi / 2 + 1e-9) == 20.0
+
+
+def test_halfway_cone_reaches_the_gather_beyond_the_last_column():
+    """The level-0 cone of the +y quadrant is centred on the +y axis, halfway
+    between the two samples of [E0, E1]: its environment fluence is
+    A_0(0) E1 = (pi/2) E1 (Eq. 13: A_0(0) = atan(1) - atan(-1)), and the -y
+    quadrant's is (pi/2) E0.  The gather reads that fluence beyond the grid, so
+    in the last frame column of the +y solve (the image's bottom row) the
+    quadrant contributes exactly (pi/2) E1."""
+    E0, E1 = 1.0, 3.0
+    N = 3
+    S = 1 << N
+    env_py = hrc.environment_fluence([E0, E1], "+y", N)
+    env_my = hrc.environment_fluence([E0, E1], "-y", N)
+    assert env_py[0][0] == pytest.approx(math.pi / 2 * E1, rel=1e-15)
+    assert env_my[0][0] == pytest.approx(math.pi / 2 * E0, rel=1e-15)
+    z = np.zeros((S, S))
+    Q = hrc.quadrant(z, z, env=env_py)
+    assert np.allclose(Q[S - 1, :], math.pi / 2 * E1, rtol=1e-14, atol=0)
