@@ -171,6 +171,9 @@ struct Arrangement {
     unsigned q_items[kMaxQueues] = {};
     int n_direct = 0;
     size_t ws_bytes = 0;                // workspace the arrangement needs
+    std::vector<int> phase_scene;       // scene of each persistent pass
+    std::vector<int> scene_slot;        // workspace slot of each scene (-1: direct)
+    std::vector<size_t> slot_base;      // byte offset of each slot in the workspace
 };
 
 // Relative amount of work of a scene: its pixels times its passes.
@@ -192,6 +195,7 @@ double scene_cost(const hrc_scene &sc) {
 void arrange(Arrangement &ar, const hrc_scene *scenes, int count, char *base) {
     ar.direct.clear();
     ar.phases.clear();
+    ar.phase_scene.clear();
     ar.seg_start.clear();
     ar.seg_phase.clear();
     ar.seg_step.clear();
@@ -253,6 +257,8 @@ void arrange(Arrangement &ar, const hrc_scene *scenes, int count, char *base) {
         }
     }
     ar.ws_bytes = std::max(direct_bytes, off);
+    ar.scene_slot = slot_of;
+    ar.slot_base = slot_base;
     if (!base) return;  // sizes only
     std::vector<Phase> chain;
     for (int i : direct) {
@@ -284,6 +290,7 @@ void arrange(Arrangement &ar, const hrc_scene *scenes, int count, char *base) {
             nsteps = std::max(nsteps, last + 1);
             first[j] = (int)ar.phases.size();
             ar.phases.insert(ar.phases.end(), chains[j].begin(), chains[j].end());
+            ar.phase_scene.insert(ar.phase_scene.end(), chains[j].size(), i);
         }
         unsigned pos = 0;
         for (int t = 0; t < nsteps; ++t) {
