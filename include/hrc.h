@@ -181,6 +181,37 @@ hrc_status hrc_backward(hrc_context *ctx, int log2_size,
                         void *workspace, size_t workspace_bytes,
                         void *stream, unsigned flags);
 
+/* ---- Three radiance channels (RGB) over one medium ------------------------ */
+
+/* The channels of a colour scene see the same medium (Section 3: channels are
+ * independent; Section 5 stores radiance as a 3-vector), so one RGB solve
+ * shares every transmittance between them: an interval is (L_r, L_g, L_b, T),
+ * 16 bytes, where three one-channel solves move 3 x 8.  Each channel's
+ * fluence equals hrc_forward on that channel's emission, bitwise.
+ *   emission : [3][S][S] planes (channel c at c * S * S)
+ *   sigma_t  : [S][S], shared by the channels
+ *   fluence  : [3][S][S] planes, overwritten
+ * Flags: HRC_FLAG_VALIDATE, HRC_FLAG_BLUR (each plane blurred as by
+ * hrc_forward); the context's environment map is not applied (RGB calls run
+ * without one).  Workspace from hrc_workspace_bytes_rgb.  Argument checks as
+ * for hrc_forward. */
+hrc_status hrc_workspace_bytes_rgb(int log2_size, unsigned flags, size_t *forward_bytes,
+                                   size_t *backward_bytes);
+hrc_status hrc_forward_rgb(hrc_context *ctx, int log2_size, const float *emission,
+                           const float *sigma_t, float *fluence, void *workspace,
+                           size_t workspace_bytes, void *stream, unsigned flags);
+
+/* Vector-Jacobian product of hrc_forward_rgb: given grad_fluence ([3][S][S]),
+ * writes grad_emission ([3][S][S]) and grad_sigma_t ([S][S], the sum over the
+ * channels, in channel order).  Runs the one-channel reverse of hrc_backward
+ * per channel over the shared medium, so grad_emission's plane c equals
+ * hrc_backward's d emission for channel c bitwise.  Flags and checks as for
+ * hrc_forward_rgb. */
+hrc_status hrc_backward_rgb(hrc_context *ctx, int log2_size, const float *emission,
+                            const float *sigma_t, const float *grad_fluence,
+                            float *grad_emission, float *grad_sigma_t, void *workspace,
+                            size_t workspace_bytes, void *stream, unsigned flags);
+
 /* ---- Several diffuse bounces ----------------------------------------------- */
 
 /* Multiple diffuse bounces (Section 4.2: the output fluence fed into another

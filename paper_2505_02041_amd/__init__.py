@@ -8,9 +8,9 @@ memory and streams only.
 
     from paper_2505_02041_amd import fluence, Context, Batch
 """
-from .hrc import (Batch, Context, HRCFunction, MultibounceFunction, default_context,  # noqa: F401
-                  fluence, fluence_multibounce)
+from .hrc import (Batch, Context, HRCFunction, MultibounceFunction, RGBFunction,  # noqa: F401
+                  default_context, fluence, fluence_multibounce, fluence_rgb)
 from ._lib import HRCError  # noqa: F401
 
-__all__ = ["fluence", "fluence_multibounce", "Context", "Batch", "HRCFunction",
-           "MultibounceFunction", "default_context", "HRCError"]
+__all__ = ["fluence", "fluence_multibounce", "fluence_rgb", "Context", "Batch", "HRCFunction",
+           "MultibounceFunction", "RGBFunction", "default_context", "HRCError"]

@@ -13,16 +13,20 @@
 
 namespace hrc {
 
-Layout make_layout(int N, bool backward, int group, bool half) {
+Layout make_layout(int N, bool backward, int group, bool half, bool rgb) {
     Layout L;
     L.N = N;
     L.S = size_t(1) << N;
     L.group = backward ? kQuadrants : group;
     const size_t SS = L.S * L.S;
+    const size_t planes = (rgb && !backward) ? 3 : 1;
     size_t off = 256;  // first 256 bytes: scratch flag for HRC_FLAG_VALIDATE
     // the forward's tail folds T_0 and T_1 itself (only the reverse stores
     // them), and the merge down builds what it reads of T_N itself
-    const size_t iv_bytes = (half && !backward) ? 2 * sizeof(uint16_t) : sizeof(float2);
+    const size_t iv_bytes = backward ? sizeof(float2)
+                            : rgb    ? sizeof(float4)
+                            : half   ? 2 * sizeof(uint16_t)
+                                     : sizeof(float2);
     for (int n = backward ? 0 : kTracedLevels - 1; n < N; ++n) {
         L.t_level[n] = off;
         off += align256(L.group * t_level_entries(N, n) * iv_bytes);
@@ -30,11 +34,11 @@ Layout make_layout(int N, bool backward, int group, bool half) {
     L.r_count = backward ? N : 2;
     for (int i = 0; i < L.r_count; ++i) {
         L.r_level[i] = off;
-        off += align256(L.group * SS * sizeof(float));
+        off += align256(planes * L.group * SS * sizeof(float));
     }
     if (!backward) {
         L.aux = off;
-        off += align256(SS * sizeof(float));
+        off += align256(planes * SS * sizeof(float));
     }
     if (backward) {
         for (int n = 0; n <= N; ++n) {
@@ -251,6 +255,54 @@ int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, cons
     return np;
 }
 
+int build_rgb_forward_phases(const Ws &w, const SolveBuffers &b, Phase *out, int max_out) {
+    const int N = w.L.N;
+    const size_t SS = w.L.S * w.L.S;
+    int np = 0;
+    auto add = [&](const Phase &p) {
+        if (np < max_out) out[np] = p;
+        ++np;
+    };
+    Phase p;
+    float *gathered = b.blur ? w.Aux() : b.F;
+    p.kind = PH_SEED_RGB;
+    p.a.seed = SeedArgs{b.eps, b.sig, nullptr, nullptr, w.T(2), t_level_entries(N, 0),
+                        t_level_entries(N, 1), t_level_entries(N, 2), N, 0, kQuadrants, 16,
+                        kTracedLevels - 1, 0};
+    add(p);
+    for (int n = kTracedLevels; n < N; ++n) {
+        p = Phase();
+        p.kind = PH_UP_RGB;
+        p.a.up = UpArgs{w.T(n - 1), w.T(n), t_level_entries(N, n - 1), t_level_entries(N, n), N, n,
+                        kQuadrants, 0};
+        add(p);
+    }
+    int cur = -1;
+    for (int n = N - 1; n >= 2; --n) {
+        const int o = cur == 0 ? 1 : 0;
+        p = Phase();
+        p.kind = PH_DOWN_RGB;
+        p.a.down = DownArgs{(n + 1 < N) ? w.R(cur) : nullptr, w.T(n), w.T(n + 1), w.R(o),
+                            t_level_entries(N, n), t_level_entries(N, n + 1), N, n, kQuadrants,
+                            nullptr, 0, 0};
+        add(p);
+        cur = o;
+    }
+    p = Phase();
+    p.kind = PH_TAIL_RGB;
+    p.a.tail = TailArgs{b.eps, b.sig, w.R(cur), gathered, N, 0, kQuadrants, 0, nullptr, 16};
+    add(p);
+    if (b.blur) {
+        for (int c = 0; c < 3; ++c) {
+            p = Phase();
+            p.kind = PH_BLUR;
+            p.a.bl = BlurArgs{gathered + c * SS, b.sig, b.F + c * SS, N, kBlurThreshold};
+            add(p);
+        }
+    }
+    return np;
+}
+
 static hrc_status run_phases(const Phase *ph, int np, hipStream_t s) {
     for (int i = 0; i < np; ++i)
         if (launch_phase(ph[i], s) != hipSuccess) return HRC_ERR_HIP;
@@ -440,6 +492,97 @@ hrc_status hrc_backward(hrc_context *ctx, int log2_size, const float *emission,
                    (flags & HRC_FLAG_BLUR) ? 1 : 0, ctx->has_env ? ctx->env : nullptr};
     int np = build_solve_phases(w, b, true, nullptr, ph, kMaxPhases);
     return run_phases(ph, np, s);
+}
+
+// ---- three radiance channels (RGB) over one medium ---------------------------
+
+static constexpr unsigned kRgbFlags = HRC_FLAG_VALIDATE | HRC_FLAG_BLUR;
+
+// The RGB reverse: the one-channel reverse's workspace, then two fields for
+// the second and third channels' dLoss/d sigma.
+static size_t rgb_backward_bytes(int N) {
+    const size_t SS = size_t(1) << (2 * N);
+    return align256(make_layout(N, true).total) + 2 * align256(SS * sizeof(float));
+}
+
+hrc_status hrc_workspace_bytes_rgb(int log2_size, unsigned flags, size_t *forward_bytes,
+                                   size_t *backward_bytes) {
+    hrc_status st = check_shape(log2_size);
+    if (st != HRC_OK) return st;
+    if (flags & ~kRgbFlags) return HRC_ERR_UNSUPPORTED;
+    if (forward_bytes) *forward_bytes = make_layout(log2_size, false, 4, false, true).total;
+    if (backward_bytes) *backward_bytes = rgb_backward_bytes(log2_size);
+    return HRC_OK;
+}
+
+hrc_status hrc_forward_rgb(hrc_context *ctx, int log2_size, const float *emission,
+                           const float *sigma_t, float *fluence, void *workspace,
+                           size_t workspace_bytes, void *stream, unsigned flags) {
+    hrc_status st = check_shape(log2_size);
+    if (st != HRC_OK) return st;
+    if (!aligned16(emission) || !aligned16(sigma_t) || !aligned16(fluence) ||
+        !aligned16(workspace))
+        return HRC_ERR_INVALID_ARG;
+    if (flags & ~kRgbFlags) return HRC_ERR_UNSUPPORTED;
+    Layout L = make_layout(log2_size, false, 4, false, true);
+    if (workspace_bytes < L.total) return HRC_ERR_WORKSPACE;
+    if (!ctx) return HRC_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return HRC_ERR_HIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Ws w{static_cast<char *>(workspace), L};
+    if (flags & HRC_FLAG_VALIDATE) {
+        const size_t SS = L.S * L.S;
+        st = validate_inputs(w, emission, emission + SS, s);
+        if (st == HRC_OK) st = validate_inputs(w, emission + 2 * SS, sigma_t, s);
+        if (st != HRC_OK) return st;
+    }
+    Phase ph[kMaxPhases];
+    SolveBuffers b{emission, sigma_t, fluence, nullptr, nullptr, nullptr,
+                   (flags & HRC_FLAG_BLUR) ? 1 : 0, nullptr, 0};
+    int np = build_rgb_forward_phases(w, b, ph, kMaxPhases);
+    return run_phases(ph, np, s);
+}
+
+hrc_status hrc_backward_rgb(hrc_context *ctx, int log2_size, const float *emission,
+                            const float *sigma_t, const float *grad_fluence,
+                            float *grad_emission, float *grad_sigma_t, void *workspace,
+                            size_t workspace_bytes, void *stream, unsigned flags) {
+    hrc_status st = check_shape(log2_size);
+    if (st != HRC_OK) return st;
+    if (!aligned16(emission) || !aligned16(sigma_t) || !aligned16(grad_fluence) ||
+        !aligned16(grad_emission) || !aligned16(grad_sigma_t) || !aligned16(workspace))
+        return HRC_ERR_INVALID_ARG;
+    if (flags & ~kRgbFlags) return HRC_ERR_UNSUPPORTED;
+    if (workspace_bytes < rgb_backward_bytes(log2_size)) return HRC_ERR_WORKSPACE;
+    if (!ctx) return HRC_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return HRC_ERR_HIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Layout L = make_layout(log2_size, true);
+    const size_t SS = L.S * L.S;
+    char *base = static_cast<char *>(workspace);
+    Ws w{base, L};
+    float *dS1 = reinterpret_cast<float *>(base + align256(L.total));
+    float *dS2 = reinterpret_cast<float *>(base + align256(L.total) + align256(SS * sizeof(float)));
+    if (flags & HRC_FLAG_VALIDATE) {
+        st = validate_inputs(w, emission, emission + SS, s);
+        if (st == HRC_OK) st = validate_inputs(w, emission + 2 * SS, sigma_t, s);
+        if (st != HRC_OK) return st;
+    }
+    // each channel's reverse over the shared medium (the channels' fluences are
+    // independent solves), then dLoss/d sigma summed over the channels
+    float *dS[3] = {grad_sigma_t, dS1, dS2};
+    Phase ph[kMaxPhases];
+    for (int c = 0; c < 3; ++c) {
+        SolveBuffers b{emission + c * SS, sigma_t, nullptr, grad_fluence + c * SS,
+                       grad_emission + c * SS, dS[c], (flags & HRC_FLAG_BLUR) ? 1 : 0, nullptr};
+        const int np = build_solve_phases(w, b, true, nullptr, ph, kMaxPhases);
+        st = run_phases(ph, np, s);
+        if (st != HRC_OK) return st;
+    }
+    return launch_add3(grad_sigma_t, dS1, dS2, grad_sigma_t, SS, s) == hipSuccess ? HRC_OK
+                                                                                 : HRC_ERR_HIP;
 }
 
 // ---- several diffuse bounces ------------------------------------------------

@@ -45,8 +45,10 @@ struct Layout {
 };
 
 // Forward: pyramids of `group` quadrants (1, 2 or 4) at a time; backward: all 4.
-// half: the forward's interval levels as 16-bit (L, T) pairs (4 bytes an entry)
-Layout make_layout(int N, bool backward, int group = 4, bool half = false);
+// half: the forward's interval levels as 16-bit (L, T) pairs (4 bytes an entry).
+// rgb (forward only): intervals (L_r, L_g, L_b, T) of 16 bytes, and the R
+// levels and the spare field as three planes each.
+Layout make_layout(int N, bool backward, int group = 4, bool half = false, bool rgb = false);
 
 struct Ws {
     char *base;
@@ -139,7 +141,9 @@ struct BlurArgs {
 
 enum PhaseKind {
     PH_SEED = 0, PH_UP, PH_DOWN, PH_TAIL, PH_GATHER_ADJ,
-    PH_DOWN_ADJ, PH_DT, PH_SEED_ADJ, PH_BLUR, PH_BLUR_ADJ, PH_KIND_COUNT
+    PH_DOWN_ADJ, PH_DT, PH_SEED_ADJ, PH_BLUR, PH_BLUR_ADJ,
+    // the RGB forward (three radiance channels over one medium)
+    PH_SEED_RGB, PH_UP_RGB, PH_DOWN_RGB, PH_TAIL_RGB, PH_KIND_COUNT
 };
 
 // One pass.  U = elements per thread of the elementwise phases (a tile covers
@@ -177,6 +181,9 @@ struct SolveBuffers {
 constexpr float kBlurThreshold = 0.5f;
 int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, const int *U,
                        Phase *out, int max_out);
+// The passes of one RGB forward (all four quadrants at once): eps is [3][S][S],
+// F is [3][S][S]; with blur, each plane is blurred by the one-channel pass.
+int build_rgb_forward_phases(const Ws &w, const SolveBuffers &b, Phase *out, int max_out);
 
 unsigned phase_tiles(const Phase &p);
 hipError_t upload_cone_table(const float *host_table);
@@ -239,6 +246,8 @@ hipError_t persistent_occupancy(int variant, int *blocks_per_cu);
 hipError_t launch_xcd_probe(unsigned *out, int grid, int variant, hipStream_t s);
 hipError_t launch_validate(const float *a, const float *b, size_t n, int *flag,
                            hipStream_t s);
+hipError_t launch_add3(const float *a, const float *b, const float *c, float *out, size_t n,
+                       hipStream_t s);
 
 // Several diffuse bounces: the next bounce's emission eps_0 + a sigma F / (2 pi)
 // (isotropic in-scattering), and the reverse step of that update given dLoss/d

@@ -82,6 +82,21 @@ __device__ __forceinline__ float2 merge(float2 n, float2 f) {
     return make_float2(fmaf(n.y, f.x, n.x), n.y * f.y);
 }
 
+// Three radiance channels over one medium (RGB): (L_r, L_g, L_b, T), each
+// channel merged exactly as the one-channel interval.
+__device__ __forceinline__ float4 merge(float4 n, float4 f) {
+    return make_float4(fmaf(n.w, f.x, n.x), fmaf(n.w, f.y, n.y), fmaf(n.w, f.z, n.z), n.w * f.w);
+}
+
+// The RGB pixel interval: the one-channel expression per channel, with the
+// attenuation's phi and exp(-tau) shared.
+__device__ __forceinline__ float4 cell_interval_rgb(float e0, float e1, float e2, float s,
+                                                    float ell) {
+    const float tau = s * ell;
+    const float phi = cell_phi(tau);
+    return make_float4(e0 * ell * phi, e1 * ell * phi, e2 * ell * phi, exp_neg(tau));
+}
+
 __device__ __forceinline__ int frame_row(int q, int u, int S) {
     return (q & 1) ? S - 1 - u : u;
 }
@@ -112,6 +127,12 @@ __device__ __forceinline__ float2 hi(float4 v) { return make_float2(v.z, v.w); }
 __device__ __forceinline__ float4 pair(float2 a, float2 b) { return make_float4(a.x, a.y, b.x, b.y); }
 __device__ __forceinline__ void st_pair(float2 *p, float4 v) { *reinterpret_cast<float4 *>(p) = v; }
 __device__ __forceinline__ void st_iv(float2 *p, float2 v) { *p = v; }
+__device__ __forceinline__ void st_iv(float4 *p, float4 v) { *p = v; }
+template <typename I> __device__ __forceinline__ I empty_interval();
+template <> __device__ __forceinline__ float2 empty_interval<float2>() { return make_float2(0.f, 1.f); }
+template <> __device__ __forceinline__ float4 empty_interval<float4>() {
+    return make_float4(0.f, 0.f, 0.f, 1.f);
+}
 
 // The 16-bit interval storage of Section 5 (HRC_FLAG_HALF_INTERVALS, forward
 // only): an interval is a pair of IEEE half floats (L, T), computed in FP32 and
@@ -227,8 +248,8 @@ constexpr unsigned char kHpLen[10][8] = {
 // directions (unrolled: the piece offsets are uniform over the wave), so the
 // LDS base and the output address are computed once per probe; lanes run
 // along w, so each direction's stores are contiguous rows.
-template <int TILE, int n, typename TS>
-__device__ __forceinline__ void seed_level_rays(const float2 *iv, const SeedArgs &a, int q,
+template <int TILE, int n, typename TS, typename I = float2>
+__device__ __forceinline__ void seed_level_rays(const I *iv, const SeedArgs &a, int q,
                                                 int slot, int r0, int c0, int tid) {
     using G = SeedTile<TILE>;
     constexpr int dirs = (1 << n) + 1, cols = TILE >> n, pieces = 2 << n;
@@ -250,11 +271,11 @@ __device__ __forceinline__ void seed_level_rays(const float2 *iv, const SeedArgs
         int lr, lc;
         if (q < 2) { lr = w - r0; lc = (q == 0 ? u : S - 1 - u) - c0; }
         else { lc = w - c0; lr = (q == 2 ? u : S - 1 - u) - r0; }
-        const float2 *ivp = iv + (lr + kSeedHalo) * G::pitch + lc + kSeedHalo;
+        const I *ivp = iv + (lr + kSeedHalo) * G::pitch + lc + kSeedHalo;
         TS *o = out + slot * qoff + (size_t)(u >> n) * dirs * S + w;
 #pragma unroll
         for (int k = 0; k < dirs; ++k) {
-            float2 acc = make_float2(0.f, 1.f);
+            I acc = empty_interval<I>();
 #pragma unroll
             for (int j = 0; j < pieces; ++j) {
                 const int off = kHpLen[sid0 + k][j] * (G::span * G::pitch) +
@@ -569,9 +590,9 @@ template <int TILE> struct TailTile {
 // Fold of the half pieces of traced ray `sid` (stencil ids as in the traced
 // levels) from the probe's pixel interval at ivp; su / sw step one pixel in u
 // / w, and the two planes hold the axis and the diagonal half pieces.
-template <int sid, int pieces, int plane>
-__device__ __forceinline__ float2 tail_ray(const float2 *ivp, int su, int sw) {
-    float2 acc = ivp[kHpLen[sid][0] * plane];  // the first piece lies in the probe's pixel
+template <int sid, int pieces, int plane, typename I>
+__device__ __forceinline__ I tail_ray(const I *ivp, int su, int sw) {
+    I acc = ivp[kHpLen[sid][0] * plane];  // the first piece lies in the probe's pixel
 #pragma unroll
     for (int j = 1; j < pieces; ++j)
         acc = merge(acc, ivp[kHpLen[sid][j] * plane + kHpDu[sid][j] * su + kHpDw[sid][j] * sw]);
@@ -1370,6 +1391,373 @@ __device__ void body_blur_adj(const BlurArgs &a, unsigned tile, int tid) {
     a.out[(size_t)r * S + c] = acc;
 }
 
+// ---------------------------------------------------------------------------
+// Three radiance channels over one attenuation (RGB).  The channels see the
+// same medium (Section 3: they are independent; Section 5 stores radiance as a
+// 3-vector), so they share every transmittance: an interval is one float4
+// (L_r, L_g, L_b, T), 16 bytes where three one-channel solves would move 24,
+// and a cascade level is three planes of floats (plane c at c * nq * S^2).
+// Every channel's arithmetic is that of the one-channel bodies, in the same
+// order, so each channel's fluence equals the one-channel forward's bitwise.
+// The forward only: 16x16 image tiles (a 32x32 tile of RGB intervals would
+// not leave LDS for two blocks per CU), all four quadrants at once, no
+// environment map.
+// ---------------------------------------------------------------------------
+
+template <int TILE> struct SeedTileRgb {
+    static constexpr int span = TILE + 2 * kSeedHalo;
+    static constexpr int pitch = span + 1;
+    static constexpr int lds = 3 * span * pitch * 16;
+};
+
+// Traced level T_2 of every quadrant (the tail folds T_0 and T_1 itself).
+template <int TILE>
+__device__ void body_seed_rgb(const SeedArgs &a, unsigned tile, char *lds, int tid) {
+    using G = SeedTileRgb<TILE>;
+    float4 *iv = reinterpret_cast<float4 *>(lds);
+    const int S = 1 << a.N;
+    const size_t SS = (size_t)S * S;
+    const int tiles = (S + TILE - 1) / TILE;
+    const int r0 = (int)(tile / tiles) * TILE, c0 = (int)(tile % tiles) * TILE;
+    for (int i = tid; i < G::span * G::span; i += 256) {
+        const int lr = i / G::span, lc = i % G::span;
+        const int r = r0 - kSeedHalo + lr, c = c0 - kSeedHalo + lc;
+        float e0 = 0.f, e1 = 0.f, e2 = 0.f, g = 0.f;
+        if (r >= 0 && r < S && c >= 0 && c < S) {
+            const size_t o = (size_t)r * S + c;
+            e0 = a.eps[o];
+            e1 = a.eps[SS + o];
+            e2 = a.eps[2 * SS + o];
+            g = a.sig[o];
+        }
+        const int l = lr * G::pitch + lc;
+        iv[l] = cell_interval_rgb(e0, e1, e2, g, 0.5f);
+        iv[G::span * G::pitch + l] = cell_interval_rgb(e0, e1, e2, g, kH2);
+        iv[2 * G::span * G::pitch + l] = cell_interval_rgb(e0, e1, e2, g, kQ5);
+    }
+    __syncthreads();
+    for (int g = 0; g < a.nq; ++g) seed_level_rays<TILE, 2, float4, float4>(iv, a, a.q0 + g, g, r0, c0, tid);
+    __syncthreads();
+}
+
+// Two consecutive RGB intervals of a row at y (even), or <0, 1> both when the
+// row position lies outside the grid (y and S even: both in or both out).
+__device__ __forceinline__ void far_pair_rgb(const float4 *row, int yf, int S, float4 &a,
+                                             float4 &b) {
+    if (yf >= 0 && yf < S) {
+        a = row[yf];
+        b = row[yf + 1];
+    } else {
+        a = b = empty_interval<float4>();
+    }
+}
+
+__device__ __forceinline__ float4 mean4(float4 p, float4 m) {
+    return make_float4(0.5f * (p.x + m.x), 0.5f * (p.y + m.y), 0.5f * (p.z + m.z),
+                       0.5f * (p.w + m.w));
+}
+
+// Merge up (Eq. 18-20) of RGB intervals, two consecutive y per thread.
+__device__ void body_merge_up_rgb(const UpArgs &a, unsigned tile, int U, int tid) {
+    const int N = a.N, S = 1 << N, n = a.n;
+    const int h = 1 << (n - 1);
+    const int dirs = 2 * h + 1, pdirs = h + 1;
+    const unsigned rpq = (unsigned)(S >> n) * dirs;
+    const size_t total = (size_t)a.nq * rpq * (S / 2);
+    for (int uu = 0; uu < U; ++uu) {
+        const size_t idx = ((size_t)tile * U + uu) * 256 + tid;
+        if (idx >= total) return;
+        const int y = (int)(idx & (S / 2 - 1)) * 2;
+        const unsigned row = (unsigned)(idx >> (N - 1));
+        const int q = row / rpq;
+        const unsigned rk = row % rpq;
+        const int x = rk / dirs, k = rk % dirs;
+        const unsigned r = (unsigned)x * dirs + k;
+        const float4 *near =
+            reinterpret_cast<const float4 *>(a.Tp) + q * a.ep + (size_t)(2 * x) * pdirs * S;
+        const float4 *far = near + (size_t)pdirs * S;
+        float4 o0, o1;
+        if ((k & 1) == 0) {
+            const int kk = k >> 1;
+            const float4 n0 = near[(size_t)kk * S + y], n1 = near[(size_t)kk * S + y + 1];
+            float4 f0, f1;
+            far_pair_rgb(far + (size_t)kk * S, y + 2 * kk - h, S, f0, f1);
+            o0 = merge(n0, f0);
+            o1 = merge(n1, f1);
+        } else {
+            const int ka = (k + 1) >> 1, kb = (k - 1) >> 1;
+            const float4 na0 = near[(size_t)ka * S + y], na1 = near[(size_t)ka * S + y + 1];
+            const float4 nb0 = near[(size_t)kb * S + y], nb1 = near[(size_t)kb * S + y + 1];
+            float4 fa0, fa1, fb0, fb1;
+            far_pair_rgb(far + (size_t)kb * S, y + 2 * ka - h, S, fa0, fa1);
+            far_pair_rgb(far + (size_t)ka * S, y + 2 * kb - h, S, fb0, fb1);
+            o0 = mean4(merge(na0, fa0), merge(nb0, fb0));
+            o1 = mean4(merge(na1, fa1), merge(nb1, fb1));
+        }
+        float4 *out = reinterpret_cast<float4 *>(a.T) + q * a.e + (size_t)r * S + y;
+        out[0] = o0;
+        out[1] = o1;
+    }
+}
+
+// R_m of one quadrant's channel plane at (c, jj) for rows y, y+1 (y even);
+// 0 outside the grid and for R_N.
+__device__ __forceinline__ float2 r_pair0(const float *Rq, int N, int m, int c, int jj, int y) {
+    const int S = 1 << N;
+    if (m >= N || c >= (S >> m) || y < 0 || y >= S) return make_float2(0.f, 0.f);
+    return *reinterpret_cast<const float2 *>(Rq + ((size_t)((c << m) | jj)) * S + y);
+}
+
+__device__ __forceinline__ float chan(float4 v, int c) { return c == 0 ? v.x : c == 1 ? v.y : v.z; }
+
+// Merge down (Eq. 14-17) of RGB intervals into three planes, n >= 1, two
+// consecutive y per thread.
+__device__ void body_merge_down_rgb(const DownArgs &a, unsigned tile, int U, int tid) {
+    const int N = a.N, S = 1 << N, n = a.n;
+    const size_t SS = (size_t)S * S;
+    const size_t plane = (size_t)a.nq * SS;
+    const size_t total = (size_t)a.nq * (SS / 2);
+    const int m = n + 1;
+    for (int uu = 0; uu < U; ++uu) {
+        const size_t idx = ((size_t)tile * U + uu) * 256 + tid;
+        if (idx >= total) return;
+        const int y = (int)(idx & (S / 2 - 1)) * 2;
+        const unsigned row = (unsigned)(idx >> (N - 1));
+        const int q = row >> N;
+        const unsigned r = row & (S - 1);
+        const int x = r >> n, ii = r & ((1 << n) - 1);
+        float acc0[3] = {0.f, 0.f, 0.f}, acc1[3] = {0.f, 0.f, 0.f};
+        if (x & 1) {
+            // Eq. 14
+            const float4 *Tx = reinterpret_cast<const float4 *>(a.Tn) + q * a.en +
+                               (size_t)x * ((1 << n) + 1) * S;
+            const int c = (x + 1) >> 1;
+#pragma unroll
+            for (int up = 0; up < 2; ++up) {
+                const int e = ii + up, jj = 2 * ii + up;
+                const float A = c_cone[(1 << m) - 1 + jj];
+                const float4 t0 = Tx[(size_t)e * S + y], t1 = Tx[(size_t)e * S + y + 1];
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    const float2 rf = r_pair0(a.Rn1 + ch * plane + q * SS, N, m, c, jj,
+                                              y + 2 * e - (1 << n));
+                    acc0[ch] += fmaf(t0.w, rf.x, A * chan(t0, ch));
+                    acc1[ch] += fmaf(t1.w, rf.y, A * chan(t1, ch));
+                }
+            }
+        } else {
+            // Eq. 15-17, with T_N built here at n = N-1 (Eq. 18, even direction)
+            const int c = x >> 1;
+            const bool top = m == N;
+            const float4 *Tx = reinterpret_cast<const float4 *>(a.Tn1) + q * a.en1 +
+                               (size_t)c * ((1 << m) + 1) * S;
+            const float4 *Tnear = reinterpret_cast<const float4 *>(a.Tn) + q * a.en +
+                                  (size_t)(2 * c) * ((1 << n) + 1) * S;
+            const float4 *Tfar = Tnear + (size_t)((1 << n) + 1) * S;
+#pragma unroll
+            for (int up = 0; up < 2; ++up) {
+                const int e2 = 2 * ii + 2 * up, jj = 2 * ii + up;
+                const float A = c_cone[(1 << m) - 1 + jj];
+                float4 t0, t1;
+                if (top) {
+                    const int kk = e2 >> 1;
+                    const float4 n0 = Tnear[(size_t)kk * S + y], n1 = Tnear[(size_t)kk * S + y + 1];
+                    float4 f0, f1;
+                    far_pair_rgb(Tfar + (size_t)kk * S, y + e2 - (1 << n), S, f0, f1);
+                    t0 = merge(n0, f0);
+                    t1 = merge(n1, f1);
+                } else {
+                    t0 = Tx[(size_t)e2 * S + y];
+                    t1 = Tx[(size_t)e2 * S + y + 1];
+                }
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    const float *Rq = a.Rn1 + ch * plane + q * SS;
+                    const float2 ra = r_pair0(Rq, N, m, c, jj, y);
+                    const float2 rb = r_pair0(Rq, N, m, c + 1, jj, y + 2 * e2 - (1 << m));
+                    acc0[ch] += 0.5f * (ra.x + fmaf(t0.w, rb.x, A * chan(t0, ch)));
+                    acc1[ch] += 0.5f * (ra.y + fmaf(t1.w, rb.y, A * chan(t1, ch)));
+                }
+            }
+        }
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch)
+            *reinterpret_cast<float2 *>(a.R + ch * plane + q * SS + (size_t)r * S + y) =
+                make_float2(acc0[ch], acc1[ch]);
+    }
+}
+
+// Tail of the RGB forward: levels 1 and 0 of the merge down, the gather and
+// the sum of the four quadrants, as the one-channel tail, per channel.
+template <int TILE> struct TailTileRgb {
+    using T1 = TailTile<TILE>;
+    static constexpr int plane = T1::plane;
+    static constexpr int iv_bytes = 2 * plane * 16;
+    static constexpr int r1_plane = T1::r1cols * 2 * T1::r1rows;  // floats per channel
+    static constexpr int acc_plane = TILE * T1::acc_pitch;       // floats per channel
+    static constexpr int lds = iv_bytes + 3 * r1_plane * 4 + 3 * acc_plane * 4;
+};
+
+__device__ __forceinline__ float r2_at3(const float *R2, int ro, int jj, int y, int S, bool cin) {
+    const bool in = cin && (unsigned)y < (unsigned)S;
+    const float v = R2[in ? (unsigned)(ro + jj * S + y) : 0u];
+    return in ? v : 0.f;
+}
+
+template <int TILE>
+__device__ void body_tail_rgb(const TailArgs &a, unsigned tile, char *lds, int tid) {
+    using G1 = TailTile<TILE>;
+    using G = TailTileRgb<TILE>;
+    constexpr int H = G1::halo, P = G1::pitch, RR = G1::r1rows, AP = G1::acc_pitch;
+    constexpr int span2 = G1::span * G1::span;
+    constexpr int R1P = G::r1_plane, ACP = G::acc_plane;
+    float4 *iv = reinterpret_cast<float4 *>(lds);
+    float *r1 = reinterpret_cast<float *>(lds + G::iv_bytes);
+    float *acc = reinterpret_cast<float *>(lds + G::iv_bytes + 3 * R1P * 4);
+    const int N = a.N, S = 1 << N;
+    const size_t SS = (size_t)S * S;
+    const int tiles = (S + TILE - 1) / TILE;
+    const int r0 = (int)(tile / tiles) * TILE, c0 = (int)(tile % tiles) * TILE;
+    for (int i = tid; i < span2; i += 256) {
+        const int lr = i / G1::span, lc = i % G1::span;
+        const int r = r0 - H + lr, c = c0 - H + lc;
+        const bool in = (unsigned)r < (unsigned)S && (unsigned)c < (unsigned)S;
+        const size_t off = in ? (size_t)r * S + c : 0;
+        const float e0 = in ? a.eps[off] : 0.f, e1 = in ? a.eps[SS + off] : 0.f;
+        const float e2 = in ? a.eps[2 * SS + off] : 0.f, g = in ? a.sig[off] : 0.f;
+        iv[lr * P + lc] = cell_interval_rgb(e0, e1, e2, g, 0.5f);
+        iv[G::plane + lr * P + lc] = cell_interval_rgb(e0, e1, e2, g, kH2);
+    }
+    for (int i = tid; i < 3 * ACP; i += 256) acc[i] = 0.f;
+    const size_t R2plane = (size_t)a.nq * SS;
+    for (int g = 0; g < a.nq; ++g) {
+        const int q = a.q0 + g;
+        const float *R2 = a.R2 + (size_t)g * SS;
+        const int u_lo = q == 0 ? c0 : q == 1 ? S - TILE - c0 : q == 2 ? r0 : S - TILE - r0;
+        const int w_lo = q < 2 ? r0 : c0;
+        const int su = q == 0 ? 1 : q == 1 ? -1 : q == 2 ? P : -P;
+        const int sw = q < 2 ? P : 1;
+        const int base = q == 1 ? H * P + TILE - 1 + H : q == 3 ? (TILE - 1 + H) * P + H : H * P + H;
+        const int c1_lo = u_lo / 2 + 1;
+        const int cmax = S >> 2;
+        __syncthreads();
+        // R_1 at odd level-1 columns (Eq. 14 at level 1)
+        constexpr int n_odd = (TILE / 4 + 1) * RR;
+        for (int i = tid; i < n_odd; i += 256) {
+            const int j = 2 * (i / RR), wl = i % RR;
+            const int cp = c1_lo + j, w = w_lo - 2 + wl;
+            float v0[3] = {0.f, 0.f, 0.f}, v1[3] = {0.f, 0.f, 0.f};
+            if (cp >= 0 && cp < (S >> 1) && (unsigned)w < (unsigned)S) {
+                const float4 *ivp = iv + base + (2 * cp - u_lo) * su + (w - w_lo) * sw;
+                const float4 t0 = tail_ray<2, 4, G::plane>(ivp, su, sw);
+                const float4 t1 = tail_ray<3, 4, G::plane>(ivp, su, sw);
+                const float4 t2 = tail_ray<4, 4, G::plane>(ivp, su, sw);
+                const int c = (cp + 1) >> 1;
+                const bool cin = c < cmax;
+                const int ro = (cin ? c : 0) * 4 * S;
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    const float *R2c = R2 + ch * R2plane;
+                    v0[ch] = fmaf(t0.w, r2_at3(R2c, ro, 0, w - 2, S, cin), c_cone[3] * chan(t0, ch)) +
+                             fmaf(t1.w, r2_at3(R2c, ro, 1, w, S, cin), c_cone[4] * chan(t1, ch));
+                    v1[ch] = fmaf(t1.w, r2_at3(R2c, ro, 2, w, S, cin), c_cone[5] * chan(t1, ch)) +
+                             fmaf(t2.w, r2_at3(R2c, ro, 3, w + 2, S, cin), c_cone[6] * chan(t2, ch));
+                }
+            }
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                r1[ch * R1P + (2 * j) * RR + wl] = v0[ch];
+                r1[ch * R1P + (2 * j + 1) * RR + wl] = v1[ch];
+            }
+        }
+        // R_1 at even level-1 columns (Eq. 15-17 at level 1)
+        constexpr int n_even = (TILE / 4) * RR;
+        for (int i = tid; i < n_even; i += 256) {
+            const int j = 2 * (i / RR) + 1, wl = i % RR;
+            const int cp = c1_lo + j, w = w_lo - 2 + wl;
+            float v0[3] = {0.f, 0.f, 0.f}, v1[3] = {0.f, 0.f, 0.f};
+            if (cp >= 0 && cp < (S >> 1) && (unsigned)w < (unsigned)S) {
+                const float4 *ivp = iv + base + (2 * cp - u_lo) * su + (w - w_lo) * sw;
+                const float4 t0 = tail_ray<5, 8, G::plane>(ivp, su, sw);
+                const float4 t2 = tail_ray<7, 8, G::plane>(ivp, su, sw);
+                const float4 t4 = tail_ray<9, 8, G::plane>(ivp, su, sw);
+                const int c = cp >> 1;
+                const bool cin = c + 1 < cmax;
+                const int ro = c * 4 * S, ro1 = (cin ? c + 1 : 0) * 4 * S;
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    const float *R2c = R2 + ch * R2plane;
+                    v0[ch] = 0.5f * (r2_at3(R2c, ro, 0, w, S, true) +
+                                     fmaf(t0.w, r2_at3(R2c, ro1, 0, w - 4, S, cin), c_cone[3] * chan(t0, ch))) +
+                             0.5f * (r2_at3(R2c, ro, 1, w, S, true) +
+                                     fmaf(t2.w, r2_at3(R2c, ro1, 1, w, S, cin), c_cone[4] * chan(t2, ch)));
+                    v1[ch] = 0.5f * (r2_at3(R2c, ro, 2, w, S, true) +
+                                     fmaf(t2.w, r2_at3(R2c, ro1, 2, w, S, cin), c_cone[5] * chan(t2, ch))) +
+                             0.5f * (r2_at3(R2c, ro, 3, w, S, true) +
+                                     fmaf(t4.w, r2_at3(R2c, ro1, 3, w + 4, S, cin), c_cone[6] * chan(t4, ch)));
+                }
+            }
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                r1[ch * R1P + (2 * j) * RR + wl] = v0[ch];
+                r1[ch * R1P + (2 * j + 1) * RR + wl] = v1[ch];
+            }
+        }
+        __syncthreads();
+        // R_0 at x = u + 1 for every pixel (u, w) of the tile, added to the sums
+        constexpr int SP = 256 / TILE, IT = TILE * TILE / 256;
+        const int wl = tid % TILE, w = w_lo + wl, slot0 = tid / TILE;
+        const int au = q == 0 ? 1 : q == 1 ? -1 : q == 2 ? AP : -AP;
+        const int aw = q < 2 ? AP : 1;
+        const int abase = q == 1 ? TILE - 1 : q == 3 ? (TILE - 1) * AP : 0;
+        const float4 *ivw = iv + base + su + wl * sw;
+        float *accw = acc + abase + wl * aw;
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            int ul;
+            if constexpr (IT >= 2)
+                ul = 2 * (slot0 + SP * (it % (IT / 2))) + (it >= IT / 2 ? 1 : 0);
+            else
+                ul = slot0 < SP / 2 ? 2 * slot0 : 2 * (slot0 - SP / 2) + 1;
+            const int u = u_lo + ul;
+            if (u < 0 || u >= S || w >= S) continue;
+            const float4 *ivp = ivw + ul * su;
+            float v[3] = {0.f, 0.f, 0.f};
+            if ((ul & 1) == 0) {
+                const float4 t0 = tail_ray<0, 2, G::plane>(ivp, su, sw);
+                const float4 t1 = tail_ray<1, 2, G::plane>(ivp, su, sw);
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    const float *rj = r1 + ch * R1P + ul * RR + wl;
+                    v[ch] = fmaf(t0.w, rj[1], c_cone[1] * chan(t0, ch)) +
+                            fmaf(t1.w, rj[RR + 3], c_cone[2] * chan(t1, ch));
+                }
+            } else if (u + 1 < S) {
+                const float4 t0 = tail_ray<2, 4, G::plane>(ivp, su, sw);
+                const float4 t2 = tail_ray<4, 4, G::plane>(ivp, su, sw);
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    const float *rj = r1 + ch * R1P + (ul - 1) * RR + wl;
+                    v[ch] = 0.5f * (rj[2] + fmaf(t0.w, rj[2 * RR], c_cone[1] * chan(t0, ch))) +
+                            0.5f * (rj[RR + 2] + fmaf(t2.w, rj[3 * RR + 4], c_cone[2] * chan(t2, ch)));
+                }
+            }
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) accw[ch * ACP + ul * au] += v[ch];
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < TILE * TILE; i += 256) {
+        const int rl = i / TILE, cl = i % TILE;
+        const int r = r0 + rl, c = c0 + cl;
+        if (r < S && c < S) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) a.out[ch * SS + (size_t)r * S + c] = acc[ch * ACP + rl * AP + cl];
+        }
+    }
+    __syncthreads();
+}
+
 // The persistent kernel's one LDS buffer: the largest body it runs (the traced
 // levels and the tail run there on 16x16 tiles).
 constexpr int kMaxLds2 = kSeedAdjLds > SeedTile<16>::lds ? kSeedAdjLds : SeedTile<16>::lds;
@@ -1440,6 +1828,20 @@ __global__ __launch_bounds__(256) void hrc_blur_adj(Phase p) {
 __global__ __launch_bounds__(256) void hrc_tail(Phase p) {
     __shared__ __align__(16) char lds[TailTile<32>::lds];
     body_tail<32>(p.a.tail, xcd_tile(blockIdx.x, gridDim.x), lds, ltid());
+}
+__global__ __launch_bounds__(256) void hrc_seed_rgb(Phase p) {
+    __shared__ __align__(16) char lds[SeedTileRgb<16>::lds];
+    body_seed_rgb<16>(p.a.seed, xcd_tile(blockIdx.x, gridDim.x), lds, ltid());
+}
+__global__ __launch_bounds__(256) void hrc_merge_up_rgb(Phase p) {
+    body_merge_up_rgb(p.a.up, xcd_tile(blockIdx.x, gridDim.x), p.U, ltid());
+}
+__global__ __launch_bounds__(256) void hrc_merge_down_rgb(Phase p) {
+    body_merge_down_rgb(p.a.down, xcd_tile(blockIdx.x, gridDim.x), p.U, ltid());
+}
+__global__ __launch_bounds__(256) void hrc_tail_rgb(Phase p) {
+    __shared__ __align__(16) char lds[TailTileRgb<16>::lds];
+    body_tail_rgb<16>(p.a.tail, xcd_tile(blockIdx.x, gridDim.x), lds, ltid());
 }
 __global__ __launch_bounds__(256) void hrc_gather_adj(Phase p) {
     __shared__ __align__(16) char lds[kGatherAdjLds];
@@ -1683,6 +2085,10 @@ unsigned phase_tiles(const Phase &p) {
             case PH_SEED_ADJ: return p.a.sa.N;
             case PH_BLUR:
             case PH_BLUR_ADJ: return p.a.bl.N;
+            case PH_SEED_RGB: return p.a.seed.N;
+            case PH_UP_RGB: return p.a.up.N;
+            case PH_DOWN_RGB: return p.a.down.N;
+            case PH_TAIL_RGB: return p.a.tail.N;
         }
         return 0;
     }();
@@ -1706,10 +2112,14 @@ unsigned phase_tiles(const Phase &p) {
         case PH_DOWN_ADJ: return cdiv(4 * SS / 2, per);
         case PH_BLUR:
         case PH_BLUR_ADJ:
-        case PH_SEED_ADJ: {
+        case PH_SEED_ADJ:
+        case PH_SEED_RGB:
+        case PH_TAIL_RGB: {
             const unsigned t16 = (unsigned)((S + 15) / 16);
             return t16 * t16;
         }
+        case PH_UP_RGB: return cdiv((size_t)p.a.up.nq * t_level_entries(N, p.a.up.n) / 2, per);
+        case PH_DOWN_RGB: return cdiv((size_t)p.a.down.nq * SS / 2, per);
     }
     return 0;
 }
@@ -1733,6 +2143,10 @@ hipError_t launch_phase(const Phase &p, hipStream_t s, hipEvent_t start, hipEven
         case PH_SEED_ADJ: k = hrc_seed_adj; break;
         case PH_BLUR: k = hrc_blur; break;
         case PH_BLUR_ADJ: k = hrc_blur_adj; break;
+        case PH_SEED_RGB: k = hrc_seed_rgb; break;
+        case PH_UP_RGB: k = hrc_merge_up_rgb; break;
+        case PH_DOWN_RGB: k = hrc_merge_down_rgb; break;
+        case PH_TAIL_RGB: k = hrc_tail_rgb; break;
         default: return hipErrorInvalidValue;
     }
     if (start || stop)
@@ -1800,6 +2214,14 @@ __global__ __launch_bounds__(256) void hrc_scatter_adj(const float *dE, const fl
     }
 }
 
+// out = (a + b) + c elementwise (out may be a): the RGB reverse's sum of the
+// three channels' dLoss/d sigma, in channel order.
+__global__ __launch_bounds__(256) void hrc_add3(const float *a, const float *b, const float *c,
+                                                float *out, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+        out[i] = (a[i] + b[i]) + c[i];
+}
+
 static unsigned elementwise_blocks(size_t n) {
     size_t b = (n + 255) / 256;
     return (unsigned)(b > 8192 ? 8192 : b);
@@ -1817,6 +2239,12 @@ hipError_t launch_scatter_adj(const float *dE, const float *dS, const float *F_p
                               float *d_sig, float *d_alb, size_t n, int assign, hipStream_t s) {
     hipLaunchKernelGGL(hrc_scatter_adj, dim3(elementwise_blocks(n)), dim3(256), 0, s, dE, dS,
                        F_prev, sig, alb, g, d_eps, d_sig, d_alb, n, assign);
+    return hipGetLastError();
+}
+
+hipError_t launch_add3(const float *a, const float *b, const float *c, float *out, size_t n,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(hrc_add3, dim3(elementwise_blocks(n)), dim3(256), 0, s, a, b, c, out, n);
     return hipGetLastError();
 }
 

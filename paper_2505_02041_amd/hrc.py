@@ -137,6 +137,63 @@ class Context:
         return ge, gs
 
 
+    # -- three radiance channels over one medium ----------------------------
+    def _rgb_workspace(self, N: int, backward: bool) -> torch.Tensor:
+        key = ("rgb", N, backward)
+        ws = self._ws.get(key)
+        if ws is None:
+            f, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
+            check(_lib.load().hrc_workspace_bytes_rgb(N, 0, ctypes.byref(f), ctypes.byref(b)),
+                  "hrc_workspace_bytes_rgb")
+            ws = torch.empty(b.value if backward else f.value, dtype=torch.uint8,
+                             device=torch.device("cuda", self.device))
+            self._ws[key] = ws
+        return ws
+
+    @staticmethod
+    def _rgb_shapes(emission: torch.Tensor, sigma_t: torch.Tensor) -> int:
+        if emission.dim() != 3 or emission.shape[0] != 3:
+            raise ValueError("emission must be a [3, S, S] tensor")
+        N = _log2_size(sigma_t)
+        if tuple(emission.shape[1:]) != tuple(sigma_t.shape):
+            raise ValueError("emission planes and sigma_t shapes differ")
+        return N
+
+    def hrc_forward_rgb(self, emission: torch.Tensor, sigma_t: torch.Tensor,
+                        out: Optional[torch.Tensor] = None, flags: int = 0) -> torch.Tensor:
+        """Fluence of the three channels of emission [3, S, S] over one sigma_t [S, S]."""
+        _check_field(emission, "emission")
+        _check_field(sigma_t, "sigma_t")
+        N = self._rgb_shapes(emission, sigma_t)
+        if out is None:
+            out = torch.empty_like(emission)
+        _check_field(out, "out")
+        if out.shape != emission.shape:
+            raise ValueError("out must have emission's shape")
+        ws = self._rgb_workspace(N, False)
+        check(_lib.load().hrc_forward_rgb(self._ptr, N, emission.data_ptr(), sigma_t.data_ptr(),
+                                          out.data_ptr(), ws.data_ptr(), ws.numel(),
+                                          _stream_handle(emission.device), flags),
+              "hrc_forward_rgb")
+        return out
+
+    def hrc_backward_rgb(self, emission: torch.Tensor, sigma_t: torch.Tensor,
+                         grad_fluence: torch.Tensor, flags: int = 0):
+        for t, n in ((emission, "emission"), (sigma_t, "sigma_t"), (grad_fluence, "grad_fluence")):
+            _check_field(t, n)
+        N = self._rgb_shapes(emission, sigma_t)
+        if grad_fluence.shape != emission.shape:
+            raise ValueError("grad_fluence must have emission's shape")
+        ge = torch.empty_like(emission)
+        gs = torch.empty_like(sigma_t)
+        ws = self._rgb_workspace(N, True)
+        check(_lib.load().hrc_backward_rgb(self._ptr, N, emission.data_ptr(), sigma_t.data_ptr(),
+                                           grad_fluence.data_ptr(), ge.data_ptr(), gs.data_ptr(),
+                                           ws.data_ptr(), ws.numel(),
+                                           _stream_handle(emission.device), flags),
+              "hrc_backward_rgb")
+        return ge, gs
+
     def _bounce_workspace(self, N: int, bounces: int, backward: bool) -> torch.Tensor:
         key = ("bounces", N, bounces, backward)
         ws = self._ws.get(key)
@@ -250,6 +307,33 @@ def fluence(emission: torch.Tensor, sigma_t: torch.Tensor, blur: bool = False) -
     """Per-pixel fluence of a square power-of-two scene (differentiable); with
     ``blur`` the cross blur of Eq. 21 follows the gather."""
     return HRCFunction.apply(emission, sigma_t, blur)
+
+
+class RGBFunction(torch.autograd.Function):
+    """F[3, S, S] = HRC of three emission channels over one sigma_t, with the
+    hand-written reverse (``hrc_backward_rgb``) as backward."""
+
+    @staticmethod
+    def forward(ctx, emission, sigma_t, blur=False):
+        emission = emission.contiguous()
+        sigma_t = sigma_t.contiguous()
+        c = default_context(emission.device.index)
+        ctx.flags = _lib.HRC_FLAG_BLUR if blur else 0
+        ctx.save_for_backward(emission, sigma_t)
+        return c.hrc_forward_rgb(emission, sigma_t, flags=ctx.flags)
+
+    @staticmethod
+    def backward(ctx, grad_F):
+        emission, sigma_t = ctx.saved_tensors
+        c = default_context(emission.device.index)
+        ge, gs = c.hrc_backward_rgb(emission, sigma_t, grad_F.contiguous(), flags=ctx.flags)
+        return ge, gs, None
+
+
+def fluence_rgb(emission: torch.Tensor, sigma_t: torch.Tensor, blur: bool = False) -> torch.Tensor:
+    """Fluence [3, S, S] of three emission channels [3, S, S] over one attenuation
+    sigma_t [S, S] (differentiable in both)."""
+    return RGBFunction.apply(emission, sigma_t, blur)
 
 
 class MultibounceFunction(torch.autograd.Function):

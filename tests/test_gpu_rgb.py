@@ -1,0 +1,116 @@
+"""GPU parity of the RGB solve (hrc_forward_rgb / hrc_backward_rgb: three
+emission channels over one attenuation, sharing every transmittance) through
+the C ABI: each channel bitwise equal to the one-channel calls, against three
+oracle solves up to the 1024x1024 benchmark scene, and through autograd."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import blur as oracle_blur
+from oracle import hrc as oracle
+from oracle import hrc_vjp
+from scenes import config3, scene_like_512
+
+pytestmark = pytest.mark.gpu
+
+from gpu_common import assert_forward_close, assert_grad_close, log, to_dev  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2505_02041_amd import Context
+    return Context(0)
+
+
+def _rgb_scene(S, seed):
+    """Three emission channels over one attenuation: the channels are the
+    scene's emission, a second seeded scene's emission, and their mix."""
+    if S >= 128:
+        a = scene_like_512(S, seed, max(2, S // 32), max(4, S // 16))
+        b = scene_like_512(S, seed + 1, max(2, S // 32), 2)
+        eps = np.stack([a.eps, b.eps, 0.5 * a.eps + 0.25 * b.eps]).astype(np.float32)
+        return eps, a.sigma
+    rng = np.random.default_rng(seed)
+    eps = (rng.uniform(0, 3, (3, S, S)) * (rng.random((3, S, S)) < 0.3)).astype(np.float32)
+    sig = rng.uniform(0, 1.5, (S, S)).astype(np.float32)
+    return eps, sig
+
+
+@pytest.mark.parametrize("S", [8, 16, 64, 256])
+@pytest.mark.parametrize("flags", [0, 0x2], ids=["plain", "blur"])
+def test_rgb_forward_equals_one_channel_calls(ctx, S, flags):
+    log(f"rgb forward S={S} flags {flags:#x}")
+    eps, sig = _rgb_scene(S, 10 + S)
+    e, s = to_dev(eps), to_dev(sig)
+    F = ctx.hrc_forward_rgb(e, s, flags=flags)
+    for c in range(3):
+        assert torch.equal(F[c], ctx.hrc_forward(e[c].contiguous(), s, flags=flags)), c
+
+
+@pytest.mark.parametrize("S", [8, 64, 256])
+def test_rgb_forward_matches_oracle(ctx, S):
+    log(f"rgb forward vs oracle S={S}")
+    eps, sig = _rgb_scene(S, 20 + S)
+    F = ctx.hrc_forward_rgb(to_dev(eps), to_dev(sig)).cpu().numpy()
+    for c in range(3):
+        assert_forward_close(F[c], oracle.fluence(eps[c], sig), f"rgb channel {c} S={S}")
+
+
+def test_rgb_forward_benchmark_scene_matches_oracle(ctx):
+    """The 1024x1024 benchmark scene's attenuation with three emission channels
+    (its own emission, a shifted copy, a scaled copy) against three oracle
+    solves."""
+    log("rgb forward 1024 vs oracle")
+    sc = config3()
+    eps = np.stack([sc.eps, np.roll(sc.eps, 37, axis=1), 0.3 * sc.eps]).astype(np.float32)
+    F = ctx.hrc_forward_rgb(to_dev(eps), to_dev(sc.sigma)).cpu().numpy()
+    for c in range(3):
+        assert_forward_close(F[c], oracle.fluence(eps[c], sc.sigma), f"rgb 1024 channel {c}")
+    ctx.release_workspaces()
+
+
+@pytest.mark.parametrize("S,flags", [(8, 0), (64, 0), (256, 0), (64, 0x2)])
+def test_rgb_backward(ctx, S, flags):
+    """d emission per channel bitwise equal to the one-channel reverse, d sigma
+    the channels' sum in channel order, both against the oracle's reverse."""
+    log(f"rgb backward S={S} flags {flags:#x}")
+    eps, sig = _rgb_scene(S, 30 + S)
+    dF = np.random.default_rng(S).normal(size=(3, S, S)).astype(np.float32)
+    e, s, g = to_dev(eps), to_dev(sig), to_dev(dF)
+    ge, gs = ctx.hrc_backward_rgb(e, s, g, flags=flags)
+    parts = [ctx.hrc_backward(e[c].contiguous(), s, g[c].contiguous(), flags=flags)
+             for c in range(3)]
+    for c in range(3):
+        assert torch.equal(ge[c], parts[c][0]), c
+    assert torch.equal(gs, (parts[0][1] + parts[1][1]) + parts[2][1])
+    ge, gs = ge.cpu().numpy(), gs.cpu().numpy()
+    rs = np.zeros((S, S))
+    for c in range(3):
+        d = dF[c] if not flags else oracle_blur.cross_blur_vjp(dF[c], sig)
+        re, rsc = hrc_vjp.fluence_vjp(eps[c], sig, d)
+        assert_grad_close(ge[c], re, f"rgb d eps channel {c} S={S}")
+        rs += rsc
+    assert_grad_close(gs, rs, f"rgb d sigma S={S}")
+
+
+def test_rgb_autograd(ctx):
+    from paper_2505_02041_amd import fluence_rgb
+    eps, sig = _rgb_scene(32, 40)
+    e = to_dev(eps).requires_grad_(True)
+    s = to_dev(sig).requires_grad_(True)
+    F = fluence_rgb(e, s)
+    g = torch.randn_like(F)
+    F.backward(g)
+    ge, gs = ctx.hrc_backward_rgb(to_dev(eps), to_dev(sig), g)
+    assert torch.equal(e.grad, ge) and torch.equal(s.grad, gs)
+    assert torch.equal(F.detach(), ctx.hrc_forward_rgb(to_dev(eps), to_dev(sig)))
+
+
+def test_rgb_rejects_bad_arguments(ctx):
+    from paper_2505_02041_amd._lib import HRCError
+    z = torch.zeros((3, 16, 16), device="cuda")
+    s = torch.zeros((16, 16), device="cuda")
+    with pytest.raises(HRCError):
+        ctx.hrc_forward_rgb(z, s, flags=0x4)  # no 16-bit storage for RGB
+    with pytest.raises(ValueError):
+        ctx.hrc_forward_rgb(z[:2].contiguous(), s)
