@@ -57,6 +57,64 @@ def measured_traffic(kernel: str):
     return rec["traffic_bytes_per_launch"]
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (as lscpu reports it), from /proc/cpuinfo."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def adam_recovery(ctx, steps: int = 200, lr: float = 0.3, every: int = 10) -> dict:
+    """The 256x256 differentiable workload: Adam on softplus-parameterised
+    emission and attenuation from a uniform start (0.1, 0.1), loss = MSE between
+    the fluence and the hidden scene's; the loss curve and the fields' RMSEs
+    against the hidden scene (the fields are not identifiable from the fluence
+    alone, so the loss is what falls)."""
+    import numpy as np
+    import torch
+    from paper_2505_02041_amd import fluence
+    from scenes import config4
+    hidden = config4()
+    dev = torch.device("cuda", 0)
+    he = torch.from_numpy(hidden.eps).to(dev)
+    hs = torch.from_numpy(hidden.sigma).to(dev)
+    with torch.no_grad():
+        Ft = fluence(he, hs)
+    inv = float(np.log(np.expm1(0.1)))
+    pe = torch.full(he.shape, inv, device=dev, requires_grad=True)
+    ps = torch.full(he.shape, inv, device=dev, requires_grad=True)
+    opt = torch.optim.Adam([pe, ps], lr=lr)
+    curve = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        opt.zero_grad()
+        loss = torch.mean((fluence(torch.nn.functional.softplus(pe),
+                                   torch.nn.functional.softplus(ps)) - Ft) ** 2)
+        loss.backward()
+        opt.step()
+        if i % every == 0 or i == steps - 1:
+            curve.append([i, float(loss.detach())])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    with torch.no_grad():
+        e = torch.nn.functional.softplus(pe)
+        sg = torch.nn.functional.softplus(ps)
+        rmse_e = float(torch.sqrt(torch.mean((e - he) ** 2)))
+        rmse_s = float(torch.sqrt(torch.mean((sg - hs) ** 2)))
+        e0 = float(torch.sqrt(torch.mean((0.1 - he) ** 2)))
+        s0 = float(torch.sqrt(torch.mean((0.1 - hs) ** 2)))
+    return {"steps": steps, "lr": lr, "loss_curve": curve,
+            "loss_ratio_first_to_last": curve[0][1] / curve[-1][1],
+            "rmse_emission": rmse_e, "rmse_emission_at_start": e0,
+            "rmse_sigma_t": rmse_s, "rmse_sigma_t_at_start": s0,
+            "ms_per_step": el / steps * 1e3}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -69,8 +127,8 @@ def main():
     from paper_2505_02041_amd import Batch, Context
     from paper_2505_02041_amd import _lib
     from paper_2505_02041_amd.roofline import (HBM_PEAK_GBPS, backward_bytes, forward_bytes,
-                                               pass_bytes)
-    from scenes import config3, config5
+                                               forward_bytes_rgb, pass_bytes)
+    from scenes import config2, config3, config5
 
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
@@ -172,6 +230,26 @@ def main():
     alb = torch.full_like(eps, 0.5)
     fwd_6b_s = timed(lambda: ctx.hrc_multibounce_forward(eps, sig, alb, 6, out=F),
                      max(3, args.steps // 10), 1)
+    # ---- three radiance channels over the benchmark scene's medium in one call
+    # (hrc_forward_rgb: the channels share every transmittance) beside three
+    # one-channel calls ------------------------------------------------------------
+    eps3 = torch.stack([eps, torch.roll(eps, 37, 1), 0.3 * eps]).contiguous()
+    F3 = torch.empty_like(eps3)
+    rgb_s = timed(lambda: ctx.hrc_forward_rgb(eps3, sig, F3), args.steps, 3)
+    del eps3, F3
+    ctx.release_workspaces()
+    # ---- the allocation-free forward (hrc_forward_static: the library's own
+    # device scratch) beside hrc_forward at 512^2, its largest grid -------------
+    c2 = config2()
+    e2 = torch.from_numpy(c2.eps).to(dev)
+    s2 = torch.from_numpy(c2.sigma).to(dev)
+    F2 = torch.empty_like(e2)
+    static_s = timed(lambda: ctx.hrc_forward_static(e2, s2, F2), 50, 3)
+    plain512_s = timed(lambda: ctx.hrc_forward(e2, s2, F2), 50, 3)
+    del e2, s2, F2
+    # ---- the 256^2 differentiable workload: 200 Adam steps -------------------
+    log("adam 200 steps at 256x256")
+    adam = adam_recovery(ctx)
     # ---- forward + backward (the backward recomputes the forward) ------------
     log("forward+backward")
     fb_s = timed(lambda: (ctx.hrc_forward(eps, sig, F), ctx.hrc_backward(eps, sig, dF)),
@@ -225,6 +303,18 @@ def main():
             "max_rel_dev_vs_f32": half_dev,
             "bound": N * 2.0 ** -11,
             "note": "intervals stored as 16-bit halves (Section 5); reduced precision, not the metric"},
+        "fwd_rgb": {"ms": rgb_s * 1e3, "ms_per_channel": rgb_s * 1e3 / 3,
+                    "mpixel_per_s": S * S / rgb_s / 1e6,
+                    "model_bytes_per_channel": forward_bytes_rgb(N) / 3,
+                    "one_channel_model_bytes": step_bytes,
+                    "model_GBps": forward_bytes_rgb(N) / rgb_s / 1e9,
+                    "speedup_vs_three_calls": 3 * fwd_s / rgb_s,
+                    "note": "three emission channels over the 1024x1024 scene's attenuation in "
+                            "one hrc_forward_rgb call (16-byte intervals, transmittance shared)"},
+        "fwd_static_512": {"ms": static_s * 1e3, "hrc_forward_ms": plain512_s * 1e3,
+                           "note": "hrc_forward_static (no workspace argument, static device "
+                                   "scratch) and hrc_forward on the 512x512 scene"},
+        "adam_256": adam,
         "fwd_bwd_mpixel_per_s": S * S / fb_s / 1e6,
         "fwd_bwd_ms": fb_s * 1e3,
         "fwd_model_GBps": step_bytes / fwd_s / 1e9,
@@ -267,6 +357,7 @@ def main():
         log(f"batch planned in {plan_s:.1f} s; timing")
         bsteps = max(3, args.steps // 10)
         batch_s = timed(b.launch, bsteps, 1)
+        b.status()
 
         def sequential():
             for it in items:
@@ -280,15 +371,18 @@ def main():
                         "sequential_mpixel_per_s": px / seq_s / 1e6,
                         "speedup_vs_sequential": seq_s / batch_s,
                         "plan_s": plan_s, "workspace_GB": b.workspace_bytes / 1e9,
-                        "autotuned": b.describe()}
+                        "autotuned": b.describe(),
+                        "candidates_fastest": sorted(b.candidates(), key=lambda c: c["ms"])[:8]}
         del b
         # every scene inside the one persistent kernel (HRC_FLAG_BATCH_PERSISTENT):
         # the launch shape the planner's split is measured against
         log("batch with every scene in the persistent kernel")
         bp = Batch(items, ctx, flags=_lib.HRC_FLAG_BATCH_PERSISTENT)
         bp_s = timed(bp.launch, bsteps, 1)
+        bp.status()
         out["batch"]["persistent_only"] = {"fwd_bwd_ms": bp_s * 1e3,
                                            "speedup_vs_sequential": seq_s / bp_s,
+                                           "workspace_GB": bp.workspace_bytes / 1e9,
                                            "autotuned": bp.describe()}
         del bp, items
         ctx.release_workspaces()
@@ -306,7 +400,7 @@ def main():
                 break
         el = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": frames * S * S / el / 1e6, "unit": "Mpixel/s",
-                               "cores": 1, "kind": "oracle",
+                               "cores": 1, "kind": "oracle", "cpu_model": cpu_model(),
                                "sample": f"{frames} full 1024x1024 forward frames of the same "
                                          f"scene, FP64 NumPy, single thread, {el:.1f} s",
                                "host_cpus": os.cpu_count()}

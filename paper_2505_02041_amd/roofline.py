@@ -88,3 +88,18 @@ def backward_bytes(N: int) -> float:
     b += sum(pass_bytes("interval_adj", N, n) for n in range(N, -1, -1))
     b += pass_bytes("seed_adj", N)
     return b
+
+
+def forward_bytes_rgb(N: int) -> float:
+    """hrc_forward_rgb: three emission planes and sigma read (16 bytes a pixel),
+    intervals (L_r, L_g, L_b, T) of 16 bytes, cascade levels and fluence as
+    three planes (12 bytes an entry)."""
+    S = 1 << N
+    SS = float(S * S)
+    q = 4
+    b = 16 * SS + q * 16 * _t(S, 2)
+    b += sum(q * 16 * (_t(S, n - 1) + _t(S, n)) for n in range(3, N))
+    for n in range(N - 1, 1, -1):
+        b += q * 16 * _t(S, n) + (q * 12 * SS if n + 1 < N else 0.0) + q * 12 * SS
+    b += 16 * SS + q * 12 * SS + 12 * SS
+    return b
