@@ -192,9 +192,13 @@ hrc_status hrc_backward(hrc_context *ctx, int log2_size,
  *   sigma_t  : [S][S], shared by the channels
  *   fluence  : [3][S][S] planes, overwritten
  * Flags: HRC_FLAG_VALIDATE, HRC_FLAG_BLUR (each plane blurred as by
- * hrc_forward); the context's environment map is not applied (RGB calls run
- * without one).  Workspace from hrc_workspace_bytes_rgb.  Argument checks as
- * for hrc_forward. */
+ * hrc_forward), and for the forward HRC_FLAG_HALF_INTERVALS: the paper's own
+ * storage (Section 5), the interval as four IEEE halves (8 bytes), computed
+ * in FP32 and rounded once when stored, each channel then within the relative
+ * N * 2^-11 of the FP32 result that hrc_forward's flag states.  The context's
+ * environment map is not applied (RGB calls run without one).  Workspace from
+ * hrc_workspace_bytes_rgb (pass the same flags).  Argument checks as for
+ * hrc_forward. */
 hrc_status hrc_workspace_bytes_rgb(int log2_size, unsigned flags, size_t *forward_bytes,
                                    size_t *backward_bytes);
 hrc_status hrc_forward_rgb(hrc_context *ctx, int log2_size, const float *emission,

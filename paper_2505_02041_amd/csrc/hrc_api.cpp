@@ -24,7 +24,7 @@ Layout make_layout(int N, bool backward, int group, bool half, bool rgb) {
     // the forward's tail folds T_0 and T_1 itself (only the reverse stores
     // them), and the merge down builds what it reads of T_N itself
     const size_t iv_bytes = backward ? sizeof(float2)
-                            : rgb    ? sizeof(float4)
+                            : rgb    ? (half ? 4 * sizeof(uint16_t) : sizeof(float4))
                             : half   ? 2 * sizeof(uint16_t)
                                      : sizeof(float2);
     for (int n = backward ? 0 : kTracedLevels - 1; n < N; ++n) {
@@ -268,13 +268,13 @@ int build_rgb_forward_phases(const Ws &w, const SolveBuffers &b, Phase *out, int
     p.kind = PH_SEED_RGB;
     p.a.seed = SeedArgs{b.eps, b.sig, nullptr, nullptr, w.T(2), t_level_entries(N, 0),
                         t_level_entries(N, 1), t_level_entries(N, 2), N, 0, kQuadrants, 16,
-                        kTracedLevels - 1, 0};
+                        kTracedLevels - 1, b.half};
     add(p);
     for (int n = kTracedLevels; n < N; ++n) {
         p = Phase();
         p.kind = PH_UP_RGB;
         p.a.up = UpArgs{w.T(n - 1), w.T(n), t_level_entries(N, n - 1), t_level_entries(N, n), N, n,
-                        kQuadrants, 0};
+                        kQuadrants, b.half};
         add(p);
     }
     int cur = -1;
@@ -284,7 +284,7 @@ int build_rgb_forward_phases(const Ws &w, const SolveBuffers &b, Phase *out, int
         p.kind = PH_DOWN_RGB;
         p.a.down = DownArgs{(n + 1 < N) ? w.R(cur) : nullptr, w.T(n), w.T(n + 1), w.R(o),
                             t_level_entries(N, n), t_level_entries(N, n + 1), N, n, kQuadrants,
-                            nullptr, 0, 0};
+                            nullptr, 0, b.half};
         add(p);
         cur = o;
     }
@@ -497,6 +497,7 @@ hrc_status hrc_backward(hrc_context *ctx, int log2_size, const float *emission,
 // ---- three radiance channels (RGB) over one medium ---------------------------
 
 static constexpr unsigned kRgbFlags = HRC_FLAG_VALIDATE | HRC_FLAG_BLUR;
+static constexpr unsigned kRgbForwardFlags = kRgbFlags | HRC_FLAG_HALF_INTERVALS;
 
 // The RGB reverse: the one-channel reverse's workspace, then two fields for
 // the second and third channels' dLoss/d sigma.
@@ -509,8 +510,10 @@ hrc_status hrc_workspace_bytes_rgb(int log2_size, unsigned flags, size_t *forwar
                                    size_t *backward_bytes) {
     hrc_status st = check_shape(log2_size);
     if (st != HRC_OK) return st;
-    if (flags & ~kRgbFlags) return HRC_ERR_UNSUPPORTED;
-    if (forward_bytes) *forward_bytes = make_layout(log2_size, false, 4, false, true).total;
+    if (flags & ~kRgbForwardFlags) return HRC_ERR_UNSUPPORTED;
+    if (forward_bytes)
+        *forward_bytes =
+            make_layout(log2_size, false, 4, (flags & HRC_FLAG_HALF_INTERVALS) != 0, true).total;
     if (backward_bytes) *backward_bytes = rgb_backward_bytes(log2_size);
     return HRC_OK;
 }
@@ -523,8 +526,9 @@ hrc_status hrc_forward_rgb(hrc_context *ctx, int log2_size, const float *emissio
     if (!aligned16(emission) || !aligned16(sigma_t) || !aligned16(fluence) ||
         !aligned16(workspace))
         return HRC_ERR_INVALID_ARG;
-    if (flags & ~kRgbFlags) return HRC_ERR_UNSUPPORTED;
-    Layout L = make_layout(log2_size, false, 4, false, true);
+    if (flags & ~kRgbForwardFlags) return HRC_ERR_UNSUPPORTED;
+    const bool half = (flags & HRC_FLAG_HALF_INTERVALS) != 0;
+    Layout L = make_layout(log2_size, false, 4, half, true);
     if (workspace_bytes < L.total) return HRC_ERR_WORKSPACE;
     if (!ctx) return HRC_ERR_INVALID_ARG;
     DeviceGuard g(ctx->device);
@@ -539,7 +543,7 @@ hrc_status hrc_forward_rgb(hrc_context *ctx, int log2_size, const float *emissio
     }
     Phase ph[kMaxPhases];
     SolveBuffers b{emission, sigma_t, fluence, nullptr, nullptr, nullptr,
-                   (flags & HRC_FLAG_BLUR) ? 1 : 0, nullptr, 0};
+                   (flags & HRC_FLAG_BLUR) ? 1 : 0, nullptr, half ? 1 : 0};
     int np = build_rgb_forward_phases(w, b, ph, kMaxPhases);
     return run_phases(ph, np, s);
 }

@@ -140,22 +140,32 @@ template <> __device__ __forceinline__ float4 empty_interval<float4>() {
 // 8-byte load.
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+
+// An FP32 value rounded to half.  The value is first pinned in a register, so
+// that the compiler cannot fuse the arithmetic that produced it with the
+// narrowing (a mixed-precision FMA that rounds the exact result to half once,
+// e.g. v_fma_mixlo_f16): the stored half is always the FP32 result rounded to
+// nearest even, whatever the code around it.
+__device__ __forceinline__ _Float16 to_half(float v) {
+    asm volatile("" : "+v"(v));
+    return (_Float16)v;
+}
 __device__ __forceinline__ float4 ld_pair(const half2_t *p) {
     const half4_t v = *reinterpret_cast<const half4_t *>(p);
     return make_float4((float)v.x, (float)v.y, (float)v.z, (float)v.w);
 }
 __device__ __forceinline__ void st_pair(half2_t *p, float4 v) {
     half4_t h;
-    h.x = (_Float16)v.x;
-    h.y = (_Float16)v.y;
-    h.z = (_Float16)v.z;
-    h.w = (_Float16)v.w;
+    h.x = to_half(v.x);
+    h.y = to_half(v.y);
+    h.z = to_half(v.z);
+    h.w = to_half(v.w);
     *reinterpret_cast<half4_t *>(p) = h;
 }
 __device__ __forceinline__ void st_iv(half2_t *p, float2 v) {
     half2_t h;
-    h.x = (_Float16)v.x;
-    h.y = (_Float16)v.y;
+    h.x = to_half(v.x);
+    h.y = to_half(v.y);
     *p = h;
 }
 
@@ -174,11 +184,27 @@ __device__ __forceinline__ void ld_quad(const half2_t *p, float4 &a, float4 &b) 
 }
 __device__ __forceinline__ void st_quad(half2_t *p, float4 a, float4 b) {
     half8_t h;
-    h[0] = (_Float16)a.x; h[1] = (_Float16)a.y; h[2] = (_Float16)a.z; h[3] = (_Float16)a.w;
-    h[4] = (_Float16)b.x; h[5] = (_Float16)b.y; h[6] = (_Float16)b.z; h[7] = (_Float16)b.w;
+    h[0] = to_half(a.x); h[1] = to_half(a.y); h[2] = to_half(a.z); h[3] = to_half(a.w);
+    h[4] = to_half(b.x); h[5] = to_half(b.y); h[6] = to_half(b.z); h[7] = to_half(b.w);
     *reinterpret_cast<half8_t *>(p) = h;
 }
 __device__ __forceinline__ void st_quad(float2 *, float4, float4) {}  // not used with FP32
+
+// One RGB interval (L_r, L_g, L_b, T): FP32, or four IEEE halves (the 16-bit
+// storage, rounded to nearest even once when stored).
+__device__ __forceinline__ float4 ld4(const float4 *p) { return *p; }
+__device__ __forceinline__ float4 ld4(const half4_t *p) {
+    const half4_t v = *p;
+    return make_float4((float)v.x, (float)v.y, (float)v.z, (float)v.w);
+}
+__device__ __forceinline__ void st_iv(half4_t *p, float4 v) {
+    half4_t h;
+    h.x = to_half(v.x);
+    h.y = to_half(v.y);
+    h.z = to_half(v.z);
+    h.w = to_half(v.w);
+    *p = h;
+}
 
 // The same at a shifted row position yf (even): one 16-byte load when yf is a
 // multiple of 4 (it is, or is not, for the whole wave: threads start at
@@ -1401,7 +1427,9 @@ __device__ void body_blur_adj(const BlurArgs &a, unsigned tile, int tid) {
 // order, so each channel's fluence equals the one-channel forward's bitwise.
 // The forward only: 16x16 image tiles (a 32x32 tile of RGB intervals would
 // not leave LDS for two blocks per CU), all four quadrants at once, no
-// environment map.
+// environment map.  With the 16-bit storage (the paper's: radiance and
+// transmittance as halves) an interval is four halves, 8 bytes, computed in
+// FP32 and rounded once when stored.
 // ---------------------------------------------------------------------------
 
 template <int TILE> struct SeedTileRgb {
@@ -1411,7 +1439,7 @@ template <int TILE> struct SeedTileRgb {
 };
 
 // Traced level T_2 of every quadrant (the tail folds T_0 and T_1 itself).
-template <int TILE>
+template <int TILE, typename TS>
 __device__ void body_seed_rgb(const SeedArgs &a, unsigned tile, char *lds, int tid) {
     using G = SeedTileRgb<TILE>;
     float4 *iv = reinterpret_cast<float4 *>(lds);
@@ -1436,17 +1464,17 @@ __device__ void body_seed_rgb(const SeedArgs &a, unsigned tile, char *lds, int t
         iv[2 * G::span * G::pitch + l] = cell_interval_rgb(e0, e1, e2, g, kQ5);
     }
     __syncthreads();
-    for (int g = 0; g < a.nq; ++g) seed_level_rays<TILE, 2, float4, float4>(iv, a, a.q0 + g, g, r0, c0, tid);
+    for (int g = 0; g < a.nq; ++g) seed_level_rays<TILE, 2, TS, float4>(iv, a, a.q0 + g, g, r0, c0, tid);
     __syncthreads();
 }
 
 // Two consecutive RGB intervals of a row at y (even), or <0, 1> both when the
 // row position lies outside the grid (y and S even: both in or both out).
-__device__ __forceinline__ void far_pair_rgb(const float4 *row, int yf, int S, float4 &a,
-                                             float4 &b) {
+template <typename TS>
+__device__ __forceinline__ void far_pair_rgb(const TS *row, int yf, int S, float4 &a, float4 &b) {
     if (yf >= 0 && yf < S) {
-        a = row[yf];
-        b = row[yf + 1];
+        a = ld4(row + yf);
+        b = ld4(row + yf + 1);
     } else {
         a = b = empty_interval<float4>();
     }
@@ -1458,6 +1486,7 @@ __device__ __forceinline__ float4 mean4(float4 p, float4 m) {
 }
 
 // Merge up (Eq. 18-20) of RGB intervals, two consecutive y per thread.
+template <typename TS>
 __device__ void body_merge_up_rgb(const UpArgs &a, unsigned tile, int U, int tid) {
     const int N = a.N, S = 1 << N, n = a.n;
     const int h = 1 << (n - 1);
@@ -1473,30 +1502,30 @@ __device__ void body_merge_up_rgb(const UpArgs &a, unsigned tile, int U, int tid
         const unsigned rk = row % rpq;
         const int x = rk / dirs, k = rk % dirs;
         const unsigned r = (unsigned)x * dirs + k;
-        const float4 *near =
-            reinterpret_cast<const float4 *>(a.Tp) + q * a.ep + (size_t)(2 * x) * pdirs * S;
-        const float4 *far = near + (size_t)pdirs * S;
+        const TS *near =
+            reinterpret_cast<const TS *>(a.Tp) + q * a.ep + (size_t)(2 * x) * pdirs * S;
+        const TS *far = near + (size_t)pdirs * S;
         float4 o0, o1;
         if ((k & 1) == 0) {
             const int kk = k >> 1;
-            const float4 n0 = near[(size_t)kk * S + y], n1 = near[(size_t)kk * S + y + 1];
+            const float4 n0 = ld4(near + (size_t)kk * S + y), n1 = ld4(near + (size_t)kk * S + y + 1);
             float4 f0, f1;
             far_pair_rgb(far + (size_t)kk * S, y + 2 * kk - h, S, f0, f1);
             o0 = merge(n0, f0);
             o1 = merge(n1, f1);
         } else {
             const int ka = (k + 1) >> 1, kb = (k - 1) >> 1;
-            const float4 na0 = near[(size_t)ka * S + y], na1 = near[(size_t)ka * S + y + 1];
-            const float4 nb0 = near[(size_t)kb * S + y], nb1 = near[(size_t)kb * S + y + 1];
+            const float4 na0 = ld4(near + (size_t)ka * S + y), na1 = ld4(near + (size_t)ka * S + y + 1);
+            const float4 nb0 = ld4(near + (size_t)kb * S + y), nb1 = ld4(near + (size_t)kb * S + y + 1);
             float4 fa0, fa1, fb0, fb1;
             far_pair_rgb(far + (size_t)kb * S, y + 2 * ka - h, S, fa0, fa1);
             far_pair_rgb(far + (size_t)ka * S, y + 2 * kb - h, S, fb0, fb1);
             o0 = mean4(merge(na0, fa0), merge(nb0, fb0));
             o1 = mean4(merge(na1, fa1), merge(nb1, fb1));
         }
-        float4 *out = reinterpret_cast<float4 *>(a.T) + q * a.e + (size_t)r * S + y;
-        out[0] = o0;
-        out[1] = o1;
+        TS *out = reinterpret_cast<TS *>(a.T) + q * a.e + (size_t)r * S + y;
+        st_iv(out, o0);
+        st_iv(out + 1, o1);
     }
 }
 
@@ -1512,6 +1541,7 @@ __device__ __forceinline__ float chan(float4 v, int c) { return c == 0 ? v.x : c
 
 // Merge down (Eq. 14-17) of RGB intervals into three planes, n >= 1, two
 // consecutive y per thread.
+template <typename TS>
 __device__ void body_merge_down_rgb(const DownArgs &a, unsigned tile, int U, int tid) {
     const int N = a.N, S = 1 << N, n = a.n;
     const size_t SS = (size_t)S * S;
@@ -1529,14 +1559,14 @@ __device__ void body_merge_down_rgb(const DownArgs &a, unsigned tile, int U, int
         float acc0[3] = {0.f, 0.f, 0.f}, acc1[3] = {0.f, 0.f, 0.f};
         if (x & 1) {
             // Eq. 14
-            const float4 *Tx = reinterpret_cast<const float4 *>(a.Tn) + q * a.en +
-                               (size_t)x * ((1 << n) + 1) * S;
+            const TS *Tx = reinterpret_cast<const TS *>(a.Tn) + q * a.en +
+                           (size_t)x * ((1 << n) + 1) * S;
             const int c = (x + 1) >> 1;
 #pragma unroll
             for (int up = 0; up < 2; ++up) {
                 const int e = ii + up, jj = 2 * ii + up;
                 const float A = c_cone[(1 << m) - 1 + jj];
-                const float4 t0 = Tx[(size_t)e * S + y], t1 = Tx[(size_t)e * S + y + 1];
+                const float4 t0 = ld4(Tx + (size_t)e * S + y), t1 = ld4(Tx + (size_t)e * S + y + 1);
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch) {
                     const float2 rf = r_pair0(a.Rn1 + ch * plane + q * SS, N, m, c, jj,
@@ -1549,11 +1579,11 @@ __device__ void body_merge_down_rgb(const DownArgs &a, unsigned tile, int U, int
             // Eq. 15-17, with T_N built here at n = N-1 (Eq. 18, even direction)
             const int c = x >> 1;
             const bool top = m == N;
-            const float4 *Tx = reinterpret_cast<const float4 *>(a.Tn1) + q * a.en1 +
-                               (size_t)c * ((1 << m) + 1) * S;
-            const float4 *Tnear = reinterpret_cast<const float4 *>(a.Tn) + q * a.en +
-                                  (size_t)(2 * c) * ((1 << n) + 1) * S;
-            const float4 *Tfar = Tnear + (size_t)((1 << n) + 1) * S;
+            const TS *Tx = reinterpret_cast<const TS *>(a.Tn1) + q * a.en1 +
+                           (size_t)c * ((1 << m) + 1) * S;
+            const TS *Tnear = reinterpret_cast<const TS *>(a.Tn) + q * a.en +
+                              (size_t)(2 * c) * ((1 << n) + 1) * S;
+            const TS *Tfar = Tnear + (size_t)((1 << n) + 1) * S;
 #pragma unroll
             for (int up = 0; up < 2; ++up) {
                 const int e2 = 2 * ii + 2 * up, jj = 2 * ii + up;
@@ -1561,14 +1591,14 @@ __device__ void body_merge_down_rgb(const DownArgs &a, unsigned tile, int U, int
                 float4 t0, t1;
                 if (top) {
                     const int kk = e2 >> 1;
-                    const float4 n0 = Tnear[(size_t)kk * S + y], n1 = Tnear[(size_t)kk * S + y + 1];
+                    const float4 n0 = ld4(Tnear + (size_t)kk * S + y), n1 = ld4(Tnear + (size_t)kk * S + y + 1);
                     float4 f0, f1;
                     far_pair_rgb(Tfar + (size_t)kk * S, y + e2 - (1 << n), S, f0, f1);
                     t0 = merge(n0, f0);
                     t1 = merge(n1, f1);
                 } else {
-                    t0 = Tx[(size_t)e2 * S + y];
-                    t1 = Tx[(size_t)e2 * S + y + 1];
+                    t0 = ld4(Tx + (size_t)e2 * S + y);
+                    t1 = ld4(Tx + (size_t)e2 * S + y + 1);
                 }
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch) {
@@ -1831,13 +1861,23 @@ __global__ __launch_bounds__(256) void hrc_tail(Phase p) {
 }
 __global__ __launch_bounds__(256) void hrc_seed_rgb(Phase p) {
     __shared__ __align__(16) char lds[SeedTileRgb<16>::lds];
-    body_seed_rgb<16>(p.a.seed, xcd_tile(blockIdx.x, gridDim.x), lds, ltid());
+    body_seed_rgb<16, float4>(p.a.seed, xcd_tile(blockIdx.x, gridDim.x), lds, ltid());
+}
+__global__ __launch_bounds__(256) void hrc_seed_rgb_f16(Phase p) {
+    __shared__ __align__(16) char lds[SeedTileRgb<16>::lds];
+    body_seed_rgb<16, half4_t>(p.a.seed, xcd_tile(blockIdx.x, gridDim.x), lds, ltid());
 }
 __global__ __launch_bounds__(256) void hrc_merge_up_rgb(Phase p) {
-    body_merge_up_rgb(p.a.up, xcd_tile(blockIdx.x, gridDim.x), p.U, ltid());
+    body_merge_up_rgb<float4>(p.a.up, xcd_tile(blockIdx.x, gridDim.x), p.U, ltid());
+}
+__global__ __launch_bounds__(256) void hrc_merge_up_rgb_f16(Phase p) {
+    body_merge_up_rgb<half4_t>(p.a.up, xcd_tile(blockIdx.x, gridDim.x), p.U, ltid());
 }
 __global__ __launch_bounds__(256) void hrc_merge_down_rgb(Phase p) {
-    body_merge_down_rgb(p.a.down, xcd_tile(blockIdx.x, gridDim.x), p.U, ltid());
+    body_merge_down_rgb<float4>(p.a.down, xcd_tile(blockIdx.x, gridDim.x), p.U, ltid());
+}
+__global__ __launch_bounds__(256) void hrc_merge_down_rgb_f16(Phase p) {
+    body_merge_down_rgb<half4_t>(p.a.down, xcd_tile(blockIdx.x, gridDim.x), p.U, ltid());
 }
 __global__ __launch_bounds__(256) void hrc_tail_rgb(Phase p) {
     __shared__ __align__(16) char lds[TailTileRgb<16>::lds];
@@ -2143,9 +2183,9 @@ hipError_t launch_phase(const Phase &p, hipStream_t s, hipEvent_t start, hipEven
         case PH_SEED_ADJ: k = hrc_seed_adj; break;
         case PH_BLUR: k = hrc_blur; break;
         case PH_BLUR_ADJ: k = hrc_blur_adj; break;
-        case PH_SEED_RGB: k = hrc_seed_rgb; break;
-        case PH_UP_RGB: k = hrc_merge_up_rgb; break;
-        case PH_DOWN_RGB: k = hrc_merge_down_rgb; break;
+        case PH_SEED_RGB: k = p.a.seed.half ? hrc_seed_rgb_f16 : hrc_seed_rgb; break;
+        case PH_UP_RGB: k = p.a.up.half ? hrc_merge_up_rgb_f16 : hrc_merge_up_rgb; break;
+        case PH_DOWN_RGB: k = p.a.down.half ? hrc_merge_down_rgb_f16 : hrc_merge_down_rgb; break;
         case PH_TAIL_RGB: k = hrc_tail_rgb; break;
         default: return hipErrorInvalidValue;
     }

@@ -138,12 +138,13 @@ class Context:
 
 
     # -- three radiance channels over one medium ----------------------------
-    def _rgb_workspace(self, N: int, backward: bool) -> torch.Tensor:
-        key = ("rgb", N, backward)
+    def _rgb_workspace(self, N: int, backward: bool, flags: int = 0) -> torch.Tensor:
+        half = 0 if backward else flags & _lib.HRC_FLAG_HALF_INTERVALS
+        key = ("rgb", N, backward, half)
         ws = self._ws.get(key)
         if ws is None:
             f, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
-            check(_lib.load().hrc_workspace_bytes_rgb(N, 0, ctypes.byref(f), ctypes.byref(b)),
+            check(_lib.load().hrc_workspace_bytes_rgb(N, half, ctypes.byref(f), ctypes.byref(b)),
                   "hrc_workspace_bytes_rgb")
             ws = torch.empty(b.value if backward else f.value, dtype=torch.uint8,
                              device=torch.device("cuda", self.device))
@@ -170,7 +171,7 @@ class Context:
         _check_field(out, "out")
         if out.shape != emission.shape:
             raise ValueError("out must have emission's shape")
-        ws = self._rgb_workspace(N, False)
+        ws = self._rgb_workspace(N, False, flags)
         check(_lib.load().hrc_forward_rgb(self._ptr, N, emission.data_ptr(), sigma_t.data_ptr(),
                                           out.data_ptr(), ws.data_ptr(), ws.numel(),
                                           _stream_handle(emission.device), flags),

@@ -13,7 +13,8 @@ from scenes import config3, scene_like_512
 
 pytestmark = pytest.mark.gpu
 
-from gpu_common import assert_forward_close, assert_grad_close, log, to_dev  # noqa: E402
+from gpu_common import (assert_forward_close, assert_grad_close, assert_half_close, log,  # noqa: E402
+                        to_dev)
 
 
 @pytest.fixture(scope="module")
@@ -106,11 +107,39 @@ def test_rgb_autograd(ctx):
     assert torch.equal(F.detach(), ctx.hrc_forward_rgb(to_dev(eps), to_dev(sig)))
 
 
+@pytest.mark.parametrize("S", [8, 64, 256])
+def test_rgb_half_storage(ctx, S):
+    """The paper's storage (16-bit RGB intervals): each channel bitwise equal to
+    the one-channel 16-bit forward (the same values rounded at the same points)
+    and within the derived bound N 2^-11 of the oracle."""
+    log(f"rgb 16-bit forward S={S}")
+    eps, sig = _rgb_scene(S, 50 + S)
+    e, s = to_dev(eps), to_dev(sig)
+    F = ctx.hrc_forward_rgb(e, s, flags=0x4)
+    N = S.bit_length() - 1
+    for c in range(3):
+        assert torch.equal(F[c], ctx.hrc_forward(e[c].contiguous(), s, flags=0x4)), c
+        assert_half_close(F[c].cpu().numpy(), oracle.fluence(eps[c], sig), N,
+                          f"rgb 16-bit channel {c} S={S}")
+
+
+def test_rgb_half_storage_benchmark_scene(ctx):
+    log("rgb 16-bit forward 1024 vs oracle")
+    sc = config3()
+    eps = np.stack([sc.eps, np.roll(sc.eps, 37, axis=1), 0.3 * sc.eps]).astype(np.float32)
+    F = ctx.hrc_forward_rgb(to_dev(eps), to_dev(sc.sigma), flags=0x4).cpu().numpy()
+    for c in range(3):
+        assert_half_close(F[c], oracle.fluence(eps[c], sc.sigma), 10, f"rgb 16-bit 1024 ch {c}")
+    ctx.release_workspaces()
+
+
 def test_rgb_rejects_bad_arguments(ctx):
     from paper_2505_02041_amd._lib import HRCError
     z = torch.zeros((3, 16, 16), device="cuda")
     s = torch.zeros((16, 16), device="cuda")
     with pytest.raises(HRCError):
-        ctx.hrc_forward_rgb(z, s, flags=0x4)  # no 16-bit storage for RGB
+        ctx.hrc_forward_rgb(z, s, flags=0x10)  # no quadrant grouping for RGB
+    with pytest.raises(HRCError):
+        ctx.hrc_backward_rgb(z, s, z, flags=0x4)  # the reverse stays FP32
     with pytest.raises(ValueError):
         ctx.hrc_forward_rgb(z[:2].contiguous(), s)
