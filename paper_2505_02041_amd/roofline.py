@@ -90,16 +90,16 @@ def backward_bytes(N: int) -> float:
     return b
 
 
-def forward_bytes_rgb(N: int) -> float:
+def forward_bytes_rgb(N: int, iv: int = 16) -> float:
     """hrc_forward_rgb: three emission planes and sigma read (16 bytes a pixel),
-    intervals (L_r, L_g, L_b, T) of 16 bytes, cascade levels and fluence as
-    three planes (12 bytes an entry)."""
+    intervals (L_r, L_g, L_b, T) of ``iv`` bytes (16 in FP32, 8 with the 16-bit
+    storage), cascade levels and fluence as three planes (12 bytes an entry)."""
     S = 1 << N
     SS = float(S * S)
     q = 4
-    b = 16 * SS + q * 16 * _t(S, 2)
-    b += sum(q * 16 * (_t(S, n - 1) + _t(S, n)) for n in range(3, N))
+    b = 16 * SS + q * iv * _t(S, 2)
+    b += sum(q * iv * (_t(S, n - 1) + _t(S, n)) for n in range(3, N))
     for n in range(N - 1, 1, -1):
-        b += q * 16 * _t(S, n) + (q * 12 * SS if n + 1 < N else 0.0) + q * 12 * SS
+        b += q * iv * _t(S, n) + (q * 12 * SS if n + 1 < N else 0.0) + q * 12 * SS
     b += 16 * SS + q * 12 * SS + 12 * SS
     return b
