@@ -31,6 +31,17 @@ def _check_field(t: torch.Tensor, name: str) -> None:
         raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
 
 
+def _check_like(ref: torch.Tensor, **fields: torch.Tensor) -> None:
+    """Every field a contiguous float32 tensor of ref's shape on ref's device (a
+    tensor of the wrong size would make the kernels read or write out of
+    bounds)."""
+    for name, t in fields.items():
+        _check_field(t, name)
+        if t.shape != ref.shape or t.device != ref.device:
+            raise ValueError(f"{name} must have shape {tuple(ref.shape)} on {ref.device}, "
+                             f"got {tuple(t.shape)} on {t.device}")
+
+
 def _stream_handle(device: torch.device) -> ctypes.c_void_p:
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
@@ -45,7 +56,9 @@ def hrc_workspace_bytes(log2_size: int, flags: int = 0) -> Tuple[int, int]:
 
 
 class Context:
-    """An ``hrc_context`` on one device plus cached workspaces per grid size."""
+    """An ``hrc_context`` on one device plus cached workspaces per grid size and
+    stream (calls on different streams never share a workspace).  Like the C
+    context, it is meant for one host thread at a time."""
 
     def __init__(self, device: Optional[int] = None):
         if device is None:
@@ -74,12 +87,21 @@ class Context:
         check(_lib.load().hrc_set_environment(self._ptr, arr, len(radiance)),
               "hrc_set_environment")
 
+    def _check_device(self, t: torch.Tensor) -> None:
+        if t.device.index != self.device:
+            raise ValueError(f"tensors must be on cuda:{self.device} (the context's device)")
+
+    def _stream_key(self) -> int:
+        # cached workspaces are per stream: calls on different streams never
+        # share one (calls on one stream run in order)
+        return torch.cuda.current_stream(self.device).cuda_stream
+
     def workspace(self, N: int, backward: bool, flags: int = 0) -> torch.Tensor:
         # the forward's size depends on the quadrant grouping and the interval
         # storage, the backward's on neither
         sized = 0 if backward else flags & (_lib.HRC_FLAG_QUADRANTS_MASK |
                                             _lib.HRC_FLAG_HALF_INTERVALS)
-        key = (N, backward, sized)
+        key = (N, backward, sized, self._stream_key())
         ws = self._ws.get(key)
         if ws is None:
             f, b = hrc_workspace_bytes(N, sized)
@@ -95,12 +117,11 @@ class Context:
     def hrc_forward(self, emission: torch.Tensor, sigma_t: torch.Tensor,
                     out: Optional[torch.Tensor] = None, flags: int = 0) -> torch.Tensor:
         _check_field(emission, "emission")
-        _check_field(sigma_t, "sigma_t")
+        self._check_device(emission)
         N = _log2_size(emission)
-        if sigma_t.shape != emission.shape:
-            raise ValueError("emission and sigma_t shapes differ")
         if out is None:
             out = torch.empty_like(emission)
+        _check_like(emission, sigma_t=sigma_t, out=out)
         ws = self.workspace(N, False, flags)
         check(_lib.load().hrc_forward(self._ptr, N, emission.data_ptr(), sigma_t.data_ptr(),
                                       out.data_ptr(), ws.data_ptr(), ws.numel(),
@@ -111,11 +132,10 @@ class Context:
                            out: torch.Tensor, flags: int = 0) -> torch.Tensor:
         """``hrc_forward_static``: the forward on the library's own device scratch
         (no workspace; grids up to 512^2), writing into the caller's ``out``."""
-        for t, n in ((emission, "emission"), (sigma_t, "sigma_t"), (out, "out")):
-            _check_field(t, n)
+        _check_field(emission, "emission")
+        self._check_device(emission)
         N = _log2_size(emission)
-        if sigma_t.shape != emission.shape or out.shape != emission.shape:
-            raise ValueError("emission, sigma_t and out shapes differ")
+        _check_like(emission, sigma_t=sigma_t, out=out)
         check(_lib.load().hrc_forward_static(self._ptr, N, emission.data_ptr(),
                                              sigma_t.data_ptr(), out.data_ptr(),
                                              _stream_handle(emission.device), flags),
@@ -124,9 +144,10 @@ class Context:
 
     def hrc_backward(self, emission: torch.Tensor, sigma_t: torch.Tensor,
                      grad_fluence: torch.Tensor, flags: int = 0):
-        for t, n in ((emission, "emission"), (sigma_t, "sigma_t"), (grad_fluence, "grad_fluence")):
-            _check_field(t, n)
+        _check_field(emission, "emission")
+        self._check_device(emission)
         N = _log2_size(emission)
+        _check_like(emission, sigma_t=sigma_t, grad_fluence=grad_fluence)
         ge = torch.empty_like(emission)
         gs = torch.empty_like(emission)
         ws = self.workspace(N, True)
@@ -140,7 +161,7 @@ class Context:
     # -- three radiance channels over one medium ----------------------------
     def _rgb_workspace(self, N: int, backward: bool, flags: int = 0) -> torch.Tensor:
         half = 0 if backward else flags & _lib.HRC_FLAG_HALF_INTERVALS
-        key = ("rgb", N, backward, half)
+        key = ("rgb", N, backward, half, self._stream_key())
         ws = self._ws.get(key)
         if ws is None:
             f, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
@@ -151,13 +172,13 @@ class Context:
             self._ws[key] = ws
         return ws
 
-    @staticmethod
-    def _rgb_shapes(emission: torch.Tensor, sigma_t: torch.Tensor) -> int:
+    def _rgb_shapes(self, emission: torch.Tensor, sigma_t: torch.Tensor) -> int:
         if emission.dim() != 3 or emission.shape[0] != 3:
             raise ValueError("emission must be a [3, S, S] tensor")
+        self._check_device(emission)
         N = _log2_size(sigma_t)
-        if tuple(emission.shape[1:]) != tuple(sigma_t.shape):
-            raise ValueError("emission planes and sigma_t shapes differ")
+        if tuple(emission.shape[1:]) != tuple(sigma_t.shape) or sigma_t.device != emission.device:
+            raise ValueError("emission planes and sigma_t shapes or devices differ")
         return N
 
     def hrc_forward_rgb(self, emission: torch.Tensor, sigma_t: torch.Tensor,
@@ -168,9 +189,7 @@ class Context:
         N = self._rgb_shapes(emission, sigma_t)
         if out is None:
             out = torch.empty_like(emission)
-        _check_field(out, "out")
-        if out.shape != emission.shape:
-            raise ValueError("out must have emission's shape")
+        _check_like(emission, out=out)
         ws = self._rgb_workspace(N, False, flags)
         check(_lib.load().hrc_forward_rgb(self._ptr, N, emission.data_ptr(), sigma_t.data_ptr(),
                                           out.data_ptr(), ws.data_ptr(), ws.numel(),
@@ -183,8 +202,7 @@ class Context:
         for t, n in ((emission, "emission"), (sigma_t, "sigma_t"), (grad_fluence, "grad_fluence")):
             _check_field(t, n)
         N = self._rgb_shapes(emission, sigma_t)
-        if grad_fluence.shape != emission.shape:
-            raise ValueError("grad_fluence must have emission's shape")
+        _check_like(emission, grad_fluence=grad_fluence)
         ge = torch.empty_like(emission)
         gs = torch.empty_like(sigma_t)
         ws = self._rgb_workspace(N, True)
@@ -196,7 +214,7 @@ class Context:
         return ge, gs
 
     def _bounce_workspace(self, N: int, bounces: int, backward: bool) -> torch.Tensor:
-        key = ("bounces", N, bounces, backward)
+        key = ("bounces", N, bounces, backward, self._stream_key())
         ws = self._ws.get(key)
         if ws is None:
             f, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
@@ -211,10 +229,11 @@ class Context:
     def hrc_multibounce_forward(self, emission: torch.Tensor, sigma_t: torch.Tensor,
                                 albedo: torch.Tensor, bounces: int,
                                 out: Optional[torch.Tensor] = None) -> torch.Tensor:
-        for t, n in ((emission, "emission"), (sigma_t, "sigma_t"), (albedo, "albedo")):
-            _check_field(t, n)
+        _check_field(emission, "emission")
+        self._check_device(emission)
         N = _log2_size(emission)
         F = out if out is not None else torch.empty_like(emission)
+        _check_like(emission, sigma_t=sigma_t, albedo=albedo, out=F)
         ws = self._bounce_workspace(N, bounces, False)
         check(_lib.load().hrc_multibounce_forward(
             self._ptr, N, emission.data_ptr(), sigma_t.data_ptr(), albedo.data_ptr(), bounces,
@@ -224,10 +243,10 @@ class Context:
 
     def hrc_multibounce_backward(self, emission: torch.Tensor, sigma_t: torch.Tensor,
                                  albedo: torch.Tensor, bounces: int, grad_fluence: torch.Tensor):
-        for t, n in ((emission, "emission"), (sigma_t, "sigma_t"), (albedo, "albedo"),
-                     (grad_fluence, "grad_fluence")):
-            _check_field(t, n)
+        _check_field(emission, "emission")
+        self._check_device(emission)
         N = _log2_size(emission)
+        _check_like(emission, sigma_t=sigma_t, albedo=albedo, grad_fluence=grad_fluence)
         ge, gs, ga = (torch.empty_like(emission) for _ in range(3))
         ws = self._bounce_workspace(N, bounces, True)
         check(_lib.load().hrc_multibounce_backward(
@@ -244,8 +263,11 @@ class Context:
         [(pass name, level, milliseconds)], and with return_outputs also the
         fluence (forward) or (d emission, d sigma_t) (backward)."""
         _check_field(emission, "emission")
-        _check_field(sigma_t, "sigma_t")
+        self._check_device(emission)
         N = _log2_size(emission)
+        _check_like(emission, sigma_t=sigma_t)
+        if grad_fluence is not None:
+            _check_like(emission, grad_fluence=grad_fluence)
         bwd = grad_fluence is not None
         ws = self.workspace(N, bwd)
         F = torch.empty_like(emission)
@@ -376,15 +398,15 @@ class Batch:
         arr = (hrc_scene * len(self.scenes))()
         for i, sc in enumerate(self.scenes):
             e, s, F = sc["emission"], sc["sigma_t"], sc["fluence"]
-            for t, n in ((e, "emission"), (s, "sigma_t"), (F, "fluence")):
-                _check_field(t, n)
+            _check_field(e, "emission")
+            _check_like(e, sigma_t=s, fluence=F)
             arr[i].log2_size = _log2_size(e)
             arr[i].emission = e.data_ptr()
             arr[i].sigma_t = s.data_ptr()
             arr[i].fluence = F.data_ptr()
             if sc.get("grad_fluence") is not None:
-                for n in ("grad_fluence", "grad_emission", "grad_sigma_t"):
-                    _check_field(sc[n], n)
+                _check_like(e, **{n: sc[n] for n in ("grad_fluence", "grad_emission",
+                                                     "grad_sigma_t")})
                 arr[i].grad_fluence = sc["grad_fluence"].data_ptr()
                 arr[i].grad_emission = sc["grad_emission"].data_ptr()
                 arr[i].grad_sigma_t = sc["grad_sigma_t"].data_ptr()
