@@ -256,6 +256,11 @@ def main():
     log("forward+backward")
     fb_s = timed(lambda: (ctx.hrc_forward(eps, sig, F), ctx.hrc_backward(eps, sig, dF)),
                  max(5, args.steps // 2), 2)
+    H = _lib.HRC_FLAG_HALF_INTERVALS
+    fb_half_s = timed(lambda: (ctx.hrc_forward(eps, sig, F, flags=H),
+                               ctx.hrc_backward(eps, sig, dF, flags=H)),
+                      max(5, args.steps // 2), 2)
+    ctx.release_workspaces()
 
     # ---- per-pass kernel durations: the same launches as hrc_forward, each
     # with HIP events the runtime records at the kernel's own start and end ---
@@ -322,6 +327,10 @@ def main():
                            "note": "hrc_forward_static (no workspace argument, static device "
                                    "scratch) and hrc_forward on the 512x512 scene"},
         "adam_256": adam,
+        "fwd_bwd_half_intervals": {"ms": fb_half_s * 1e3, "mpixel_per_s": S * S / fb_half_s / 1e6,
+                                   "note": "forward and backward with 16-bit intervals (the "
+                                           "reverse's adjoints stay FP32); reduced precision, "
+                                           "not the metric"},
         "fwd_bwd_mpixel_per_s": S * S / fb_s / 1e6,
         "fwd_bwd_ms": fb_s * 1e3,
         "fwd_model_GBps": step_bytes / fwd_s / 1e9,

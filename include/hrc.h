@@ -74,15 +74,20 @@ typedef enum {
  * pass the same flags to hrc_workspace_bytes. */
 #define HRC_FLAG_VALIDATE 0x1u
 #define HRC_FLAG_BLUR 0x2u
-/* HRC_FLAG_HALF_INTERVALS (hrc_forward and hrc_workspace_bytes only): the
- * interval pyramid is stored as IEEE half floats, L and T in 16 bits each, as
- * the paper stores it (Section 5), which halves its traffic; every value is
- * still computed in FP32 and rounded to nearest once when stored.  Each
- * stored level adds a relative rounding of at most 2^-11 to what depends on
- * it, so the fluence stays within a relative N * 2^-11 of the FP32 result
- * (about 5e-3 at S = 1024) instead of 1e-4.  L above 65504 (the half
- * range) becomes infinite: the caller keeps the radiance along any ray below
- * it.  hrc_backward, the bounce calls and the batch reject the flag. */
+/* HRC_FLAG_HALF_INTERVALS (hrc_forward, hrc_backward, hrc_forward_static,
+ * hrc_forward_rgb and the workspace queries): the interval pyramid is stored
+ * as IEEE half floats, L and T in 16 bits each, as the paper stores it
+ * (Section 5), which halves its traffic; every value is still computed in
+ * FP32 and rounded to nearest once when stored.  Each stored level adds a
+ * relative rounding of at most 2^-11 to what depends on it, so the fluence
+ * stays within a relative N * 2^-11 of the FP32 result (about 5e-3 at
+ * S = 1024) instead of 1e-4.  In hrc_backward the recomputed forward stores
+ * its pyramid so while every adjoint stays FP32: every term of a gradient is a
+ * term of the fluence with one factor differentiated (all of one sign for
+ * emission, and for sigma_t), so each gradient element stays within
+ * N * 2^-11 times the same gradient taken with abs(grad_fluence).  L above
+ * 65504 (the half range) becomes infinite: the caller keeps the radiance
+ * along any ray below it.  The bounce calls and the batch reject the flag. */
 #define HRC_FLAG_HALF_INTERVALS 0x4u
 #define HRC_FLAG_QUADRANTS_1 0x10u
 #define HRC_FLAG_QUADRANTS_2 0x20u
@@ -136,8 +141,8 @@ const char *hrc_status_string(hrc_status s);
  * entries each) plus two cascade levels; backward additionally keeps every
  * cascade level, their adjoints and the adjoint pyramid.  Either output
  * pointer may be NULL.  Pure host function.  The forward size depends on
- * HRC_FLAG_QUADRANTS_* and HRC_FLAG_HALF_INTERVALS; the backward size on
- * neither. */
+ * HRC_FLAG_QUADRANTS_* and HRC_FLAG_HALF_INTERVALS, the backward size on
+ * HRC_FLAG_HALF_INTERVALS only. */
 hrc_status hrc_workspace_bytes(int log2_size, unsigned flags,
                                size_t *forward_bytes, size_t *backward_bytes);
 

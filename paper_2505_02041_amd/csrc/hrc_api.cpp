@@ -23,7 +23,7 @@ Layout make_layout(int N, bool backward, int group, bool half, bool rgb) {
     size_t off = 256;  // first 256 bytes: scratch flag for HRC_FLAG_VALIDATE
     // the forward's tail folds T_0 and T_1 itself (only the reverse stores
     // them), and the merge down builds what it reads of T_N itself
-    const size_t iv_bytes = backward ? sizeof(float2)
+    const size_t iv_bytes = backward ? (half ? 2 * sizeof(uint16_t) : sizeof(float2))
                             : rgb    ? (half ? 4 * sizeof(uint16_t) : sizeof(float4))
                             : half   ? 2 * sizeof(uint16_t)
                                      : sizeof(float2);
@@ -54,8 +54,8 @@ Layout make_layout(int N, bool backward, int group, bool half, bool rgb) {
     return L;
 }
 
-// Flags hrc_backward accepts; hrc_forward and hrc_workspace_bytes also take
-// HRC_FLAG_HALF_INTERVALS.
+// Flags hrc_forward, hrc_backward and hrc_workspace_bytes accept; the bounce
+// calls and the profile take those of kSolveFlags.
 static constexpr unsigned kSolveFlags =
     HRC_FLAG_VALIDATE | HRC_FLAG_QUADRANTS_MASK | HRC_FLAG_BLUR;
 static constexpr unsigned kForwardFlags = kSolveFlags | HRC_FLAG_HALF_INTERVALS;
@@ -222,7 +222,7 @@ int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, cons
             p.kind = PH_DOWN_ADJ;
             p.U = pick_u(U, PH_DOWN_ADJ);
             p.a.da = DownAdjArgs{w.dR(n), w.T(n), w.T(n + 1), w.dR(n + 1), t_level_entries(N, n),
-                                 t_level_entries(N, n + 1), N, n};
+                                 t_level_entries(N, n + 1), N, n, b.half};
             add(p);
         }
         for (int n = N; n >= 0; --n) {
@@ -243,6 +243,7 @@ int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, cons
             d.N = N;
             d.env = b.env;
             d.n = n;
+            d.half = b.half;
             p.a.dt = d;
             add(p);
         }
@@ -351,7 +352,9 @@ hrc_status hrc_workspace_bytes(int log2_size, unsigned flags, size_t *forward_by
         *forward_bytes = make_layout(log2_size, false, forward_group(log2_size, flags),
                                      (flags & HRC_FLAG_HALF_INTERVALS) != 0)
                              .total;
-    if (backward_bytes) *backward_bytes = make_layout(log2_size, true).total;
+    if (backward_bytes)
+        *backward_bytes =
+            make_layout(log2_size, true, 4, (flags & HRC_FLAG_HALF_INTERVALS) != 0).total;
     return HRC_OK;
 }
 
@@ -475,8 +478,9 @@ hrc_status hrc_backward(hrc_context *ctx, int log2_size, const float *emission,
     if (!aligned16(emission) || !aligned16(sigma_t) || !aligned16(grad_fluence) ||
         !aligned16(grad_emission) || !aligned16(grad_sigma_t) || !aligned16(workspace))
         return HRC_ERR_INVALID_ARG;
-    if (flags & ~kSolveFlags) return HRC_ERR_UNSUPPORTED;
-    Layout L = make_layout(log2_size, true);
+    if (flags & ~kForwardFlags) return HRC_ERR_UNSUPPORTED;
+    const bool half = (flags & HRC_FLAG_HALF_INTERVALS) != 0;
+    Layout L = make_layout(log2_size, true, 4, half);
     if (workspace_bytes < L.total) return HRC_ERR_WORKSPACE;
     if (!ctx) return HRC_ERR_INVALID_ARG;
     DeviceGuard g(ctx->device);
@@ -489,7 +493,8 @@ hrc_status hrc_backward(hrc_context *ctx, int log2_size, const float *emission,
     }
     Phase ph[kMaxPhases];
     SolveBuffers b{emission, sigma_t, nullptr, grad_fluence, grad_emission, grad_sigma_t,
-                   (flags & HRC_FLAG_BLUR) ? 1 : 0, ctx->has_env ? ctx->env : nullptr};
+                   (flags & HRC_FLAG_BLUR) ? 1 : 0, ctx->has_env ? ctx->env : nullptr,
+                   half ? 1 : 0};
     int np = build_solve_phases(w, b, true, nullptr, ph, kMaxPhases);
     return run_phases(ph, np, s);
 }

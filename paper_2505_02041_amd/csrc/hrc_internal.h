@@ -107,6 +107,7 @@ struct DownAdjArgs {
     float *dRn1;             // dR_{n+1}
     size_t en, en1;
     int N, n;
+    int half;                // T levels stored as 16-bit (L, T) pairs
 };
 struct DTArgs {
     const float2 *Tn;        // T_n
@@ -119,6 +120,7 @@ struct DTArgs {
     size_t en, en1;
     int N, n, has_up;
     const float *env;        // environment table (nullable), all four quadrants
+    int half;                // T levels stored as 16-bit (L, T) pairs (dT stays FP32)
 };
 struct SeedAdjArgs {
     const float *eps, *sig;
@@ -174,7 +176,7 @@ struct SolveBuffers {
     float *dE, *dS;  // all three NULL: forward only
     int blur = 0;    // cross blur after the gather (forward) / its transpose first (reverse)
     const float *env = nullptr;  // environment table (hrc_context::env) or NULL
-    int half = 0;    // forward only: interval levels stored as 16-bit pairs
+    int half = 0;    // interval levels stored as 16-bit pairs (the reverse's adjoints stay FP32)
 };
 // Opacity threshold of the cross blur (Eq. 21): |alpha_nb - alpha| above it ignores
 // the neighbour.

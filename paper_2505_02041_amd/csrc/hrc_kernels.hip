@@ -169,6 +169,10 @@ __device__ __forceinline__ void st_iv(half2_t *p, float2 v) {
     *p = h;
 }
 
+// The transmittance of one stored interval, FP32 or 16-bit.
+__device__ __forceinline__ float iv_t(const float2 *p) { return p->y; }
+__device__ __forceinline__ float iv_t(const half2_t *p) { return (float)(*p).y; }
+
 template <typename TS>
 __device__ __forceinline__ float4 far_pair(const TS *row, int yf, int S) {
     return (yf >= 0 && yf < S) ? ld_pair(row + yf) : make_float4(0.f, 1.f, 0.f, 1.f);
@@ -869,6 +873,7 @@ __device__ __forceinline__ float2 ld2_r(bool in, const float *row, int y, int S,
 // entry (c, jj, y') is read by at most three R_n entries: the odd column 2c-1
 // (far end of Eq. 14), the even column 2c (F^0 of Eq. 16) and the even column
 // 2c-2 (far end of Eq. 17).  Two consecutive y' per thread.
+template <typename TS>
 __device__ void body_merge_down_adj(const DownAdjArgs &a, unsigned tile, int U, int tid) {
     const int N = a.N, S = 1 << N, n = a.n, m = n + 1;
     const size_t SS = (size_t)S * S;
@@ -895,7 +900,8 @@ __device__ void body_merge_down_adj(const DownAdjArgs &a, unsigned tile, int U, 
             const int x = 2 * c - 1;
             const int y = yp - (2 * e - (1 << n));  // odd when n = 0
             const float *grow = dRq + ((size_t)((x << n) | ii)) * S;
-            const float2 *trow = a.Tn + q * a.en + ((size_t)x * ((1 << n) + 1) + e) * S;
+            const TS *trow = reinterpret_cast<const TS *>(a.Tn) + q * a.en +
+                             ((size_t)x * ((1 << n) + 1) + e) * S;
             if (n > 0) {
                 const bool in = (unsigned)y < (unsigned)S;
                 const int yc = in ? y : 0;
@@ -907,7 +913,7 @@ __device__ void body_merge_down_adj(const DownAdjArgs &a, unsigned tile, int U, 
                 const bool in0 = (unsigned)y < (unsigned)S, in1 = (unsigned)(y + 1) < (unsigned)S;
                 const int y0 = in0 ? y : 0, y1 = in1 ? y + 1 : 0;
                 const float ga = grow[y0], gb = grow[y1];
-                const float ta = trow[y0].y, tb = trow[y1].y;
+                const float ta = iv_t(trow + y0), tb = iv_t(trow + y1);
                 g = make_float2(in0 ? ga : 0.f, in1 ? gb : 0.f);
                 t = make_float2(in0 ? ta : 0.f, in1 ? tb : 0.f);
             }
@@ -919,8 +925,8 @@ __device__ void body_merge_down_adj(const DownAdjArgs &a, unsigned tile, int U, 
             const int y2c = in2 ? y2 : 0;
             const float2 g2v = *reinterpret_cast<const float2 *>(
                 dRq + ((size_t)((x2 << n) | ii)) * S + y2c);
-            const float4 t2v =
-                ld_pair(a.Tn1 + q * a.en1 + ((size_t)(c - 1) * ((1 << m) + 1) + e2) * S + y2c);
+            const float4 t2v = ld_pair(reinterpret_cast<const TS *>(a.Tn1) + q * a.en1 +
+                                       ((size_t)(c - 1) * ((1 << m) + 1) + e2) * S + y2c);
             g2 = in2 ? g2v : make_float2(0.f, 0.f);
             t2 = in2 ? make_float2(t2v.y, t2v.w) : make_float2(0.f, 0.f);
         }
@@ -939,6 +945,7 @@ __device__ void body_merge_down_adj(const DownAdjArgs &a, unsigned tile, int U, 
 // so that a wave waits for memory once rather than once per source: the
 // conditions on x and k are uniform over the wave, absent terms load nothing
 // and add zero, and reads outside the grid take a clamped address and a select.
+template <typename TS>
 __device__ void body_dT(const DTArgs &a, unsigned tile, int U, int tid) {
     const int N = a.N, S = 1 << N, n = a.n;
     const size_t SS = (size_t)S * S;
@@ -1012,9 +1019,9 @@ __device__ void body_dT(const DTArgs &a, unsigned tile, int U, int tid) {
         if (a.has_up) {
             const int H = 1 << n;
             const int odirs = 2 * H + 1;
-            const float2 *Tq = a.Tn + q * a.en;
+            const TS *Tq = reinterpret_cast<const TS *>(a.Tn) + q * a.en;
             const float2 *g0 = a.dTn1 + q * a.en1 + (size_t)(x >> 1) * odirs * S;
-            const float2 *part = Tq + (size_t)(near_role ? x + 1 : x - 1) * dirs * S;
+            const TS *part = Tq + (size_t)(near_role ? x + 1 : x - 1) * dirs * S;
 #pragma unroll
             for (int v = 0; v < 3; ++v) {
                 const int ko = v == 0 ? 2 * k : (v == 1 ? 2 * k + 1 : 2 * k - 1);
@@ -1811,8 +1818,8 @@ __device__ __forceinline__ void run_phase(const Phase &p, unsigned tile, char *l
         case PH_DOWN: body_merge_down<float2>(p.a.down, tile, p.U, tid); break;
         case PH_TAIL: body_tail<16>(p.a.tail, tile, lds, tid); break;  // planner sets tile 16
         case PH_GATHER_ADJ: body_gather_adj(p.a.ga, tile, lds, tid); break;
-        case PH_DOWN_ADJ: body_merge_down_adj(p.a.da, tile, p.U, tid); break;
-        case PH_DT: body_dT(p.a.dt, tile, p.U, tid); break;
+        case PH_DOWN_ADJ: body_merge_down_adj<float2>(p.a.da, tile, p.U, tid); break;
+        case PH_DT: body_dT<float2>(p.a.dt, tile, p.U, tid); break;
         case PH_SEED_ADJ: body_seed_adj(p.a.sa, tile, lds, tid); break;
         case PH_BLUR: body_blur(p.a.bl, tile, tid); break;
         case PH_BLUR_ADJ: body_blur_adj(p.a.bl, tile, tid); break;
@@ -1833,8 +1840,10 @@ HRC_ELEMENTWISE_KERNEL(hrc_merge_up, body_merge_up<float2>, up)
 HRC_ELEMENTWISE_KERNEL(hrc_merge_down, body_merge_down<float2>, down)
 HRC_ELEMENTWISE_KERNEL(hrc_merge_up_f16, body_merge_up<half2_t>, up)
 HRC_ELEMENTWISE_KERNEL(hrc_merge_down_f16, body_merge_down<half2_t>, down)
-HRC_ELEMENTWISE_KERNEL(hrc_merge_down_adj, body_merge_down_adj, da)
-HRC_ELEMENTWISE_KERNEL(hrc_interval_adj, body_dT, dt)
+HRC_ELEMENTWISE_KERNEL(hrc_merge_down_adj, body_merge_down_adj<float2>, da)
+HRC_ELEMENTWISE_KERNEL(hrc_interval_adj, body_dT<float2>, dt)
+HRC_ELEMENTWISE_KERNEL(hrc_merge_down_adj_f16, body_merge_down_adj<half2_t>, da)
+HRC_ELEMENTWISE_KERNEL(hrc_interval_adj_f16, body_dT<half2_t>, dt)
 #undef HRC_ELEMENTWISE_KERNEL
 
 __global__ __launch_bounds__(256) void hrc_seed(Phase p) {
@@ -2178,8 +2187,8 @@ hipError_t launch_phase(const Phase &p, hipStream_t s, hipEvent_t start, hipEven
         case PH_DOWN: k = p.a.down.half ? hrc_merge_down_f16 : hrc_merge_down; break;
         case PH_TAIL: k = hrc_tail; break;
         case PH_GATHER_ADJ: k = hrc_gather_adj; break;
-        case PH_DOWN_ADJ: k = hrc_merge_down_adj; break;
-        case PH_DT: k = hrc_interval_adj; break;
+        case PH_DOWN_ADJ: k = p.a.da.half ? hrc_merge_down_adj_f16 : hrc_merge_down_adj; break;
+        case PH_DT: k = p.a.dt.half ? hrc_interval_adj_f16 : hrc_interval_adj; break;
         case PH_SEED_ADJ: k = hrc_seed_adj; break;
         case PH_BLUR: k = hrc_blur; break;
         case PH_BLUR_ADJ: k = hrc_blur_adj; break;

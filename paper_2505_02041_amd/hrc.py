@@ -99,8 +99,8 @@ class Context:
     def workspace(self, N: int, backward: bool, flags: int = 0) -> torch.Tensor:
         # the forward's size depends on the quadrant grouping and the interval
         # storage, the backward's on neither
-        sized = 0 if backward else flags & (_lib.HRC_FLAG_QUADRANTS_MASK |
-                                            _lib.HRC_FLAG_HALF_INTERVALS)
+        sized = flags & (_lib.HRC_FLAG_HALF_INTERVALS if backward else
+                         (_lib.HRC_FLAG_QUADRANTS_MASK | _lib.HRC_FLAG_HALF_INTERVALS))
         key = (N, backward, sized, self._stream_key())
         ws = self._ws.get(key)
         if ws is None:
@@ -150,7 +150,7 @@ class Context:
         _check_like(emission, sigma_t=sigma_t, grad_fluence=grad_fluence)
         ge = torch.empty_like(emission)
         gs = torch.empty_like(emission)
-        ws = self.workspace(N, True)
+        ws = self.workspace(N, True, flags)
         check(_lib.load().hrc_backward(self._ptr, N, emission.data_ptr(), sigma_t.data_ptr(),
                                        grad_fluence.data_ptr(), ge.data_ptr(), gs.data_ptr(),
                                        ws.data_ptr(), ws.numel(),

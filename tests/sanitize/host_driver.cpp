@@ -27,10 +27,9 @@ static char *fake(size_t i) {
 }
 
 // The regions of a layout lie inside it, 256-byte aligned, and do not overlap.
-static void check_layout(const Layout &L, bool backward) {
+static void check_layout(const Layout &L, bool backward, int iv = 8) {
     std::vector<std::pair<size_t, size_t>> reg;
     const size_t SS = L.S * L.S;
-    const int iv = 8;  // the FP32 layouts
     for (int n = backward ? 0 : kTracedLevels - 1; n < L.N; ++n)
         reg.push_back({L.t_level[n], L.group * t_level_entries(L.N, n) * iv});
     for (int i = 0; i < L.r_count; ++i) reg.push_back({L.r_level[i], L.group * SS * 4});
@@ -162,8 +161,12 @@ int main() {
     CHECK(hrc_forward(nctx, 5, fp, fp, fp, ws, 1u << 30, nullptr, 0x8000u) == HRC_ERR_UNSUPPORTED);
     CHECK(hrc_forward(nctx, 5, fp, fp, fp, ws, 16, nullptr, 0) == HRC_ERR_WORKSPACE);
     CHECK(hrc_forward(nctx, 5, fp, fp, fp, ws, 1u << 30, nullptr, 0) == HRC_ERR_INVALID_ARG);
+    CHECK(hrc_backward(nctx, 5, fp, fp, fp, fp, fp, ws, 1u << 30, nullptr, 0x8000u) ==
+          HRC_ERR_UNSUPPORTED);
     CHECK(hrc_backward(nctx, 5, fp, fp, fp, fp, fp, ws, 1u << 30, nullptr,
-                       HRC_FLAG_HALF_INTERVALS) == HRC_ERR_UNSUPPORTED);
+                       HRC_FLAG_HALF_INTERVALS) == HRC_ERR_INVALID_ARG);  // no context
+    for (int N = HRC_MIN_LOG2; N <= HRC_MAX_LOG2; ++N)
+        check_layout(make_layout(N, true, 4, true), true, 4);  // the 16-bit reverse
     CHECK(hrc_backward(nctx, 5, fp, fp, fp, fp, fp, ws, 16, nullptr, 0) == HRC_ERR_WORKSPACE);
     CHECK(hrc_forward_static(nctx, 10, fp, fp, fp, nullptr, 0) == HRC_ERR_TOO_LARGE);
     CHECK(hrc_forward_static(nctx, 9, fp, fp, fp, nullptr, HRC_FLAG_VALIDATE) ==

@@ -75,32 +75,36 @@ def test_workspace_sizes_follow_the_memory_analysis(N):
 @pytest.mark.parametrize("N", [3, 6, 10, 12])
 def test_half_interval_workspace(N):
     """With HRC_FLAG_HALF_INTERVALS the forward stores the same interval
-    entries in 4 bytes instead of 8 (the 16-bit pairs of Section 5); the
-    cascade levels and the spare field stay FP32, and the backward's size does
-    not change."""
+    entries in 4 bytes instead of 8 (the 16-bit pairs of Section 5), and so
+    does the backward's recomputed forward; the cascade levels, the spare field
+    and every adjoint stay FP32."""
     S = 1 << N
-    one = sum((S >> n) * (2 ** n + 1) * S for n in range(N + 1)) - (2 ** N + 1) * S
+    full = sum((S >> n) * (2 ** n + 1) * S for n in range(N + 1))
+    one = full - (2 ** N + 1) * S
     fwd_entries = one - (2 + 1.5) * S * S
     for group_flag, G in ((_lib.HRC_FLAG_QUADRANTS_1, 1), (0, 4)):
         st, f, b = _ws(N, group_flag | _lib.HRC_FLAG_HALF_INTERVALS)
         assert st == HRC_OK
         fwd_min = G * 4 * fwd_entries + 2 * G * 4 * S * S + 4 * S * S
         assert fwd_min <= f <= fwd_min + 256 * (2 * N + 8), (group_flag, f, fwd_min)
-        assert b == _ws(N, group_flag)[2]
+        bwd_min = 4 * 4 * one + 4 * 8 * full + 2 * N * 4 * 4 * S * S
+        assert bwd_min <= b <= bwd_min + 256 * (4 * N + 10), (b, bwd_min)
+        assert b < _ws(N, group_flag)[2]
 
 
-def test_half_intervals_only_for_the_forward():
-    """The backward, the bounce calls and the batch reject the 16-bit storage
-    flag before touching the device; the forward takes it and then needs only
-    the smaller workspace."""
+def test_half_intervals_where_taken():
+    """The bounce calls and the batch reject the 16-bit storage flag before
+    touching the device; the forward and the backward take it and then need
+    only the smaller workspaces."""
     lib = _lib.load()
     buf = (ctypes.c_float * 1024)()
     p = ctypes.addressof(buf)
     H = _lib.HRC_FLAG_HALF_INTERVALS
     st, f, b = _ws(5)
-    _, fh, _ = _ws(5, H)
-    assert fh < f
-    assert lib.hrc_backward(None, 5, p, p, p, p, p, p, b, None, H) == HRC_ERR_UNSUPPORTED
+    _, fh, bh = _ws(5, H)
+    assert fh < f and bh < b
+    assert lib.hrc_backward(None, 5, p, p, p, p, p, p, bh - 1, None, H) == HRC_ERR_WORKSPACE
+    assert lib.hrc_backward(None, 5, p, p, p, p, p, p, bh, None, H) == HRC_ERR_INVALID_ARG
     assert lib.hrc_forward(None, 5, p, p, p, p, fh - 1, None, H) == HRC_ERR_WORKSPACE
     assert lib.hrc_forward(None, 5, p, p, p, p, fh, None, H) == HRC_ERR_INVALID_ARG  # no context
     fb = ctypes.c_size_t(0)

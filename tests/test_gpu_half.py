@@ -1,7 +1,8 @@
-"""The forward with 16-bit interval storage (HRC_FLAG_HALF_INTERVALS, the
-storage of Section 5) against the FP64 oracle, within the bound derived from
+"""The 16-bit interval storage (HRC_FLAG_HALF_INTERVALS, the storage of
+Section 5) against the FP64 oracle: the forward within the bound derived from
 the arithmetic (tests/gpu_common.py, pinned on the oracle's own steps in
-tests/test_oracle_half_storage.py)."""
+tests/test_oracle_half_storage.py), and the reverse with its recomputed
+forward stored so, within the bound on each gradient term."""
 import numpy as np
 import pytest
 import torch
@@ -89,13 +90,55 @@ def test_half_with_environment_and_blur(ctx):
     assert_half_close(_run(ctx, eps, sig, HALF | 0x2), _run(ctx, eps, sig, 0x2), 6, "blur")
 
 
-def test_half_rejected_by_the_backward(ctx):
-    eps, sig = _random_scene(32, 5)
-    with pytest.raises(RuntimeError, match="UNSUPPORTED"):
-        ctx.hrc_backward(to_dev(eps), to_dev(sig), to_dev(np.ones_like(eps)), flags=HALF)
-
-
 def test_fp32_path_unchanged_by_the_option(ctx):
     """The FP32 forward still meets its 1e-4 bar on the same scene."""
     eps, sig = _random_scene(64, 12)
     assert_forward_close(_run(ctx, eps, sig, 0), oracle.fluence(eps, sig), "fp32")
+
+
+# ---- the reverse with the 16-bit storage ------------------------------------
+
+def _assert_half_grad(g16, g_ref, g_abs, N, what):
+    """Each gradient element within N 2^-11 times the same gradient taken with
+    abs(dLoss/dF) (every term of a gradient is a fluence term with one factor
+    differentiated: one sign per field, and at most N roundings on its path),
+    plus the FP32 reverse's own tolerance."""
+    g16 = np.asarray(g16, np.float64)
+    err = np.abs(g16 - g_ref)
+    bound = N * 2.0 ** -11 * np.abs(g_abs) + 1e-4 * np.abs(g_ref).max()
+    bad = err > bound
+    if bad.any():
+        i = np.unravel_index(np.argmax(err / np.maximum(bound, 1e-300)), err.shape)
+        raise AssertionError(f"{what}: {bad.sum()} of {bad.size} outside the 16-bit reverse "
+                             f"bound; worst at {i}: gpu {g16[i]!r} ref {g_ref[i]!r} "
+                             f"abs-gradient {g_abs[i]!r}")
+
+
+@pytest.mark.parametrize("case", ["random8", "random64", "config1", "random256", "config3"])
+def test_half_backward_within_derived_bound(ctx, case):
+    """hrc_backward with HRC_FLAG_HALF_INTERVALS against the oracle's FP64
+    reverse pass, up to the 1024x1024 benchmark scene."""
+    from oracle import hrc_vjp
+    log(f"16-bit reverse {case}")
+    if case == "config1":
+        sc = config1()
+        eps, sig = sc.eps, sc.sigma
+    elif case == "config3":
+        sc = config3()
+        eps, sig = sc.eps, sc.sigma
+    else:
+        S = int(case[len("random"):])
+        eps, sig = _random_scene(S, 70 + S)
+    S = eps.shape[0]
+    N = S.bit_length() - 1
+    dF = np.random.default_rng(S + 1).normal(size=(S, S)).astype(np.float32)
+    ge, gs = ctx.hrc_backward(to_dev(eps), to_dev(sig), to_dev(dF), flags=HALF)
+    torch.cuda.synchronize()
+    re, rs = hrc_vjp.fluence_vjp(eps, sig, dF)
+    ae, as_ = hrc_vjp.fluence_vjp(eps, sig, np.abs(dF))
+    _assert_half_grad(ge.cpu().numpy(), re, ae, N, f"d eps {case}")
+    _assert_half_grad(gs.cpu().numpy(), rs, as_, N, f"d sigma {case}")
+    # the storage does round (the check is not vacuous)
+    ge32, _ = ctx.hrc_backward(to_dev(eps), to_dev(sig), to_dev(dF))
+    assert not torch.equal(ge, ge32) or S <= 8
+    ctx.release_workspaces()
