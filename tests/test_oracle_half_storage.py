@@ -77,3 +77,61 @@ def test_model_without_rounding_is_the_oracle(monkeypatch):
     monkeypatch.setattr(sys.modules[__name__], "_q16", lambda a: np.asarray(a, np.float64))
     sc = config1()
     assert np.array_equal(_fluence_half(sc.eps, sc.sigma), O.fluence(sc.eps, sc.sigma))
+
+
+def _pyramid_half_reverse(E, Sg, seed_levels=3):
+    """The reverse's recomputed pyramid as the kernels store it with 16-bit
+    intervals: T_0 .. T_(N-1) rounded to half (traced levels rounded once,
+    each merged level computed from the rounded one below and rounded), T_N
+    built from the rounded T_(N-1) and never stored."""
+    S = E.shape[0]
+    N = O.log2_size(S)
+    T = []
+    for n in range(N + 1):
+        t = O.seed_level(E, Sg, n) if n < seed_levels else O.merge_up(T[n - 1], n)
+        T.append(tuple(_q16(a) for a in t) if n < N else t)
+    return T
+
+
+@pytest.mark.parametrize("which", ["64 disks3_boxes4", "128 like-512"])
+def test_half_reverse_within_the_derived_bound(which, monkeypatch):
+    """The reverse with the 16-bit pyramid stays within N 2^-11 times the
+    gradient of abs(dLoss/dF), element by element, on the oracle's own steps:
+    every gradient term is a fluence term with one factor differentiated, the
+    terms of d eps are all >= 0 and those of d sigma all <= 0, and a term
+    passes through at most N rounded values."""
+    from oracle import hrc_vjp
+    sc = config1() if which.startswith("64") else scene_like_512(128, 12, 4, 8)
+    S = sc.eps.shape[0]
+    N = O.log2_size(S)
+    dF = np.random.default_rng(S).normal(size=(S, S))
+    ge, gs = hrc_vjp.fluence_vjp(sc.eps, sc.sigma, dF)
+    ae, as_ = hrc_vjp.fluence_vjp(sc.eps, sc.sigma, np.abs(dF))
+    assert (ae >= 0).all() and (as_ <= 0).all()  # one sign per field
+    monkeypatch.setattr(hrc_vjp, "build_pyramid", _pyramid_half_reverse)
+    he, hs = hrc_vjp.fluence_vjp(sc.eps, sc.sigma, dF)
+    for g16, g, ga, name in ((he, ge, ae, "d eps"), (hs, gs, as_, "d sigma")):
+        err = np.abs(g16 - g)
+        # Below 2^-14 half is subnormal: a stored value keeps an absolute
+        # precision of 2^-24 there, not a relative one, and a term whose
+        # factors underflow is lost whole.  Those terms are tiny beside the
+        # largest gradient, hence the absolute term (the same the GPU tests
+        # carry); where the gradient is not tiny the relative bound alone holds.
+        bound = N * HALF_RTOL_PER_LEVEL * np.abs(ga) + 1e-4 * np.abs(ga).max()
+        assert (err <= bound).all(), (name, float(np.max(err / bound)))
+        big = np.abs(ga) >= 1e-3 * np.abs(ga).max()
+        rel = err[big] / (N * HALF_RTOL_PER_LEVEL * np.abs(ga[big]))
+        assert rel.max() <= 1.0, (name, float(rel.max()))
+        # the storage does perturb the gradient (the check is not vacuous)
+        assert rel.max() > 1e-3, (name, float(rel.max()))
+
+
+def test_half_reverse_model_without_rounding_is_the_oracle(monkeypatch):
+    from oracle import hrc_vjp
+    sc = config1()
+    dF = np.random.default_rng(3).normal(size=sc.eps.shape)
+    want = hrc_vjp.fluence_vjp(sc.eps, sc.sigma, dF)
+    monkeypatch.setattr(sys.modules[__name__], "_q16", lambda a: np.asarray(a, np.float64))
+    monkeypatch.setattr(hrc_vjp, "build_pyramid", _pyramid_half_reverse)
+    got = hrc_vjp.fluence_vjp(sc.eps, sc.sigma, dF)
+    assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
