@@ -260,6 +260,18 @@ def main():
     fb_half_s = timed(lambda: (ctx.hrc_forward(eps, sig, F, flags=H),
                                ctx.hrc_backward(eps, sig, dF, flags=H)),
                       max(5, args.steps // 2), 2)
+    # the forward keeps what the reverse reads in a reserve space, the
+    # backward reads it instead of recomputing it
+    K, R = _lib.HRC_FLAG_KEEP_PYRAMID, _lib.HRC_FLAG_REUSE_PYRAMID
+    log("forward (kept) + backward (reused)")
+    res = ctx.reserve(N)
+    fb_kept_s = timed(lambda: (ctx.hrc_forward(eps, sig, F, flags=K, reserve=res),
+                               ctx.hrc_backward(eps, sig, dF, flags=R, reserve=res)),
+                      max(5, args.steps // 2), 2)
+    fwd_kept_s = timed(lambda: ctx.hrc_forward(eps, sig, F, flags=K, reserve=res),
+                       max(5, args.steps // 2), 2)
+    reserve_bytes = res.numel()
+    del res
     ctx.release_workspaces()
 
     # ---- per-pass kernel durations: the same launches as hrc_forward, each
@@ -333,6 +345,12 @@ def main():
                                            "not the metric"},
         "fwd_bwd_mpixel_per_s": S * S / fb_s / 1e6,
         "fwd_bwd_ms": fb_s * 1e3,
+        "fwd_bwd_kept": {"ms": fb_kept_s * 1e3, "mpixel_per_s": S * S / fb_kept_s / 1e6,
+                         "forward_ms": fwd_kept_s * 1e3, "reserve_GB": reserve_bytes / 1e9,
+                         "note": "hrc_forward keeping the pyramid and cascade levels in a reserve "
+                                 "space (HRC_FLAG_KEEP_PYRAMID), hrc_backward reading them "
+                                 "(HRC_FLAG_REUSE_PYRAMID) instead of recomputing them; results "
+                                 "bitwise those of fwd_bwd_ms's plain calls"},
         "fwd_model_GBps": step_bytes / fwd_s / 1e9,
         "fwd_model_frac_of_peak": step_bytes / fwd_s / 1e9 / HBM_PEAK_GBPS,
         "fwd_bwd_model_GBps": (step_bytes + backward_bytes(N)) / fb_s / 1e9,
@@ -380,12 +398,28 @@ def main():
                 ctx.hrc_forward(it["emission"], it["sigma_t"], it["fluence"])
                 ctx.hrc_backward(it["emission"], it["sigma_t"], it["grad_fluence"])
         seq_s = timed(sequential, bsteps, 1)
+        reserves = {}
+
+        def sequential_kept():
+            K, R = _lib.HRC_FLAG_KEEP_PYRAMID, _lib.HRC_FLAG_REUSE_PYRAMID
+            for it in items:
+                n_ = it["emission"].shape[0].bit_length() - 1
+                if n_ not in reserves:
+                    reserves[n_] = ctx.reserve(n_)
+                ctx.hrc_forward(it["emission"], it["sigma_t"], it["fluence"], flags=K,
+                                reserve=reserves[n_])
+                ctx.hrc_backward(it["emission"], it["sigma_t"], it["grad_fluence"], flags=R,
+                                 reserve=reserves[n_])
+        seq_kept_s = timed(sequential_kept, bsteps, 1)
+        reserves.clear()
         out["batch"] = {"scenes": len(items), "megapixels": px / 1e6,
                         "fwd_bwd_ms": batch_s * 1e3,
                         "fwd_bwd_mpixel_per_s": px / batch_s / 1e6,
                         "sequential_fwd_bwd_ms": seq_s * 1e3,
                         "sequential_mpixel_per_s": px / seq_s / 1e6,
                         "speedup_vs_sequential": seq_s / batch_s,
+                        "sequential_kept_fwd_bwd_ms": seq_kept_s * 1e3,
+                        "speedup_vs_sequential_kept": seq_kept_s / batch_s,
                         "plan_s": plan_s, "workspace_GB": b.workspace_bytes / 1e9,
                         "autotuned": b.describe(),
                         "candidates_fastest": sorted(b.candidates(), key=lambda c: c["ms"])[:8]}
@@ -398,6 +432,7 @@ def main():
         bp.status()
         out["batch"]["persistent_only"] = {"fwd_bwd_ms": bp_s * 1e3,
                                            "speedup_vs_sequential": seq_s / bp_s,
+                                           "speedup_vs_sequential_kept": seq_kept_s / bp_s,
                                            "workspace_GB": bp.workspace_bytes / 1e9,
                                            "autotuned": bp.describe()}
         del bp, items

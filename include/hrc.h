@@ -89,6 +89,27 @@ typedef enum {
  * 65504 (the half range) becomes infinite: the caller keeps the radiance
  * along any ray below it.  The bounce calls and the batch reject the flag. */
 #define HRC_FLAG_HALF_INTERVALS 0x4u
+/* HRC_FLAG_KEEP_PYRAMID (hrc_forward, and the workspace query) and
+ * HRC_FLAG_REUSE_PYRAMID (hrc_backward): a reserve space between a forward
+ * and its reverse.  The reverse reads the interval pyramid T_0 .. T_(N-1) of
+ * the four quadrants and the cascade levels R_1 .. R_(N-1); hrc_backward
+ * alone recomputes them from emission and sigma_t.  With KEEP the forward
+ * computes them as the backward would and leaves them in its workspace, which
+ * must then be the backward's size (hrc_workspace_bytes with KEEP returns it
+ * as forward_bytes); the fluence is bitwise that of a plain forward.  With
+ * REUSE the backward skips the recomputation and reads them from its
+ * workspace, which must be that kept forward's workspace, for the same
+ * log2_size, emission, sigma_t, environment map and HRC_FLAG_BLUR /
+ * HRC_FLAG_HALF_INTERVALS bits, unwritten since by anything but backwards
+ * that reuse it (a backward leaves them intact, so one kept forward serves
+ * several reverses).  The gradients are then bitwise those of a plain
+ * hrc_backward.  The library cannot check the pairing: a workspace that does
+ * not hold a matching kept forward gives wrong gradients (every access stays
+ * inside the workspace).  KEEP runs the four quadrants at once
+ * (HRC_FLAG_QUADRANTS_1 or _2 with it: HRC_ERR_UNSUPPORTED); the other calls
+ * reject both flags. */
+#define HRC_FLAG_KEEP_PYRAMID 0x8u
+#define HRC_FLAG_REUSE_PYRAMID 0x40u
 #define HRC_FLAG_QUADRANTS_1 0x10u
 #define HRC_FLAG_QUADRANTS_2 0x20u
 #define HRC_FLAG_QUADRANTS_4 0x30u
@@ -141,8 +162,9 @@ const char *hrc_status_string(hrc_status s);
  * entries each) plus two cascade levels; backward additionally keeps every
  * cascade level, their adjoints and the adjoint pyramid.  Either output
  * pointer may be NULL.  Pure host function.  The forward size depends on
- * HRC_FLAG_QUADRANTS_* and HRC_FLAG_HALF_INTERVALS, the backward size on
- * HRC_FLAG_HALF_INTERVALS only. */
+ * HRC_FLAG_QUADRANTS_* and HRC_FLAG_HALF_INTERVALS (with HRC_FLAG_KEEP_PYRAMID
+ * it is the backward size), the backward size on HRC_FLAG_HALF_INTERVALS
+ * only. */
 hrc_status hrc_workspace_bytes(int log2_size, unsigned flags,
                                size_t *forward_bytes, size_t *backward_bytes);
 

@@ -25,6 +25,8 @@ HRC_MAX_LOG2 = 12
 HRC_FLAG_VALIDATE = 0x1
 HRC_FLAG_BLUR = 0x2
 HRC_FLAG_HALF_INTERVALS = 0x4
+HRC_FLAG_KEEP_PYRAMID = 0x8
+HRC_FLAG_REUSE_PYRAMID = 0x40
 HRC_FLAG_QUADRANTS_1 = 0x10
 HRC_FLAG_QUADRANTS_2 = 0x20
 HRC_FLAG_QUADRANTS_4 = 0x30

@@ -59,6 +59,16 @@ Layout make_layout(int N, bool backward, int group, bool half, bool rgb) {
 static constexpr unsigned kSolveFlags =
     HRC_FLAG_VALIDATE | HRC_FLAG_QUADRANTS_MASK | HRC_FLAG_BLUR;
 static constexpr unsigned kForwardFlags = kSolveFlags | HRC_FLAG_HALF_INTERVALS;
+// hrc_forward and the workspace query also take HRC_FLAG_KEEP_PYRAMID,
+// hrc_backward HRC_FLAG_REUSE_PYRAMID.
+static constexpr unsigned kKeepFlags = kForwardFlags | HRC_FLAG_KEEP_PYRAMID;
+static constexpr unsigned kReuseFlags = kForwardFlags | HRC_FLAG_REUSE_PYRAMID;
+
+// HRC_FLAG_KEEP_PYRAMID computes all four quadrants at once.
+static bool keep_group_ok(unsigned flags) {
+    const unsigned g = flags & HRC_FLAG_QUADRANTS_MASK;
+    return !(flags & HRC_FLAG_KEEP_PYRAMID) || g == 0 || g == HRC_FLAG_QUADRANTS_4;
+}
 
 // Quadrant group of a forward: from the flags, else all four at once.
 static int forward_group(int N, unsigned flags) {
@@ -132,7 +142,7 @@ static int pick_u(const int *U, int kind) { return U ? (U[kind] > 0 ? U[kind] : 
 // quadrants at once, then, with gradients, its reverse).  R levels either all
 // kept (R(n) = R_n, needed by the reverse) or alternating in two buffers.
 int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, const int *U,
-                       Phase *out, int max_out) {
+                       Phase *out, int max_out, bool recompute) {
     const int N = w.L.N;
     int np = 0;
     auto add = [&](const Phase &p) {
@@ -149,7 +159,7 @@ int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, cons
     // kept) dR_0, which the reverse writes only later.
     const int G = w.L.group;
     float *gathered = b.blur ? (keep_all_r ? w.dR(0) : w.Aux()) : b.F;
-    for (int q0 = 0; q0 < kQuadrants; q0 += G) {
+    for (int q0 = 0; recompute && q0 < kQuadrants; q0 += G) {
         p = Phase();
         p.kind = PH_SEED;
         p.a.seed = SeedArgs{b.eps,
@@ -196,7 +206,7 @@ int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, cons
             add(p);
         }
     }
-    if (b.F && b.blur) {
+    if (recompute && b.F && b.blur) {
         p = Phase();
         p.kind = PH_BLUR;
         p.a.bl = BlurArgs{gathered, b.sig, b.F, N, kBlurThreshold};
@@ -347,9 +357,11 @@ hrc_status hrc_workspace_bytes(int log2_size, unsigned flags, size_t *forward_by
                                size_t *backward_bytes) {
     hrc_status st = check_shape(log2_size);
     if (st != HRC_OK) return st;
-    if (flags & ~kForwardFlags) return HRC_ERR_UNSUPPORTED;
+    if ((flags & ~(kKeepFlags | HRC_FLAG_REUSE_PYRAMID)) || !keep_group_ok(flags))
+        return HRC_ERR_UNSUPPORTED;
+    const bool keep = (flags & HRC_FLAG_KEEP_PYRAMID) != 0;
     if (forward_bytes)
-        *forward_bytes = make_layout(log2_size, false, forward_group(log2_size, flags),
+        *forward_bytes = make_layout(log2_size, keep, forward_group(log2_size, flags),
                                      (flags & HRC_FLAG_HALF_INTERVALS) != 0)
                              .total;
     if (backward_bytes)
@@ -423,9 +435,11 @@ hrc_status hrc_forward(hrc_context *ctx, int log2_size, const float *emission,
     if (!aligned16(emission) || !aligned16(sigma_t) || !aligned16(fluence) ||
         !aligned16(workspace))
         return HRC_ERR_INVALID_ARG;
-    if (flags & ~kForwardFlags) return HRC_ERR_UNSUPPORTED;
+    if ((flags & ~kKeepFlags) || !keep_group_ok(flags)) return HRC_ERR_UNSUPPORTED;
     const bool half = (flags & HRC_FLAG_HALF_INTERVALS) != 0;
-    Layout L = make_layout(log2_size, false, forward_group(log2_size, flags), half);
+    const bool keep = (flags & HRC_FLAG_KEEP_PYRAMID) != 0;
+    // with KEEP: the reverse's layout, every level the reverse reads kept
+    Layout L = make_layout(log2_size, keep, forward_group(log2_size, flags), half);
     if (workspace_bytes < L.total) return HRC_ERR_WORKSPACE;
     if (!ctx) return HRC_ERR_INVALID_ARG;
     DeviceGuard g(ctx->device);
@@ -440,7 +454,7 @@ hrc_status hrc_forward(hrc_context *ctx, int log2_size, const float *emission,
     SolveBuffers b{emission, sigma_t, fluence, nullptr, nullptr, nullptr,
                    (flags & HRC_FLAG_BLUR) ? 1 : 0, ctx->has_env ? ctx->env : nullptr,
                    half ? 1 : 0};
-    int np = build_solve_phases(w, b, false, nullptr, ph, kMaxPhases);
+    int np = build_solve_phases(w, b, keep, nullptr, ph, kMaxPhases);
     return run_phases(ph, np, s);
 }
 
@@ -478,8 +492,9 @@ hrc_status hrc_backward(hrc_context *ctx, int log2_size, const float *emission,
     if (!aligned16(emission) || !aligned16(sigma_t) || !aligned16(grad_fluence) ||
         !aligned16(grad_emission) || !aligned16(grad_sigma_t) || !aligned16(workspace))
         return HRC_ERR_INVALID_ARG;
-    if (flags & ~kForwardFlags) return HRC_ERR_UNSUPPORTED;
+    if (flags & ~kReuseFlags) return HRC_ERR_UNSUPPORTED;
     const bool half = (flags & HRC_FLAG_HALF_INTERVALS) != 0;
+    const bool reuse = (flags & HRC_FLAG_REUSE_PYRAMID) != 0;
     Layout L = make_layout(log2_size, true, 4, half);
     if (workspace_bytes < L.total) return HRC_ERR_WORKSPACE;
     if (!ctx) return HRC_ERR_INVALID_ARG;
@@ -495,7 +510,7 @@ hrc_status hrc_backward(hrc_context *ctx, int log2_size, const float *emission,
     SolveBuffers b{emission, sigma_t, nullptr, grad_fluence, grad_emission, grad_sigma_t,
                    (flags & HRC_FLAG_BLUR) ? 1 : 0, ctx->has_env ? ctx->env : nullptr,
                    half ? 1 : 0};
-    int np = build_solve_phases(w, b, true, nullptr, ph, kMaxPhases);
+    int np = build_solve_phases(w, b, true, nullptr, ph, kMaxPhases, !reuse);
     return run_phases(ph, np, s);
 }
 

@@ -181,8 +181,11 @@ struct SolveBuffers {
 // Opacity threshold of the cross blur (Eq. 21): |alpha_nb - alpha| above it ignores
 // the neighbour.
 constexpr float kBlurThreshold = 0.5f;
+// keep_all_r: the reverse's layout, every level kept (forward down to R_1).
+// recompute = false (with keep_all_r and a gradient): only the reverse, on
+// the levels a kept forward left in the workspace.
 int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, const int *U,
-                       Phase *out, int max_out);
+                       Phase *out, int max_out, bool recompute = true);
 // The passes of one RGB forward (all four quadrants at once): eps is [3][S][S],
 // F is [3][S][S]; with blur, each plane is blurred by the one-channel pass.
 int build_rgb_forward_phases(const Ws &w, const SolveBuffers &b, Phase *out, int max_out);

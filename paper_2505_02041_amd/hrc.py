@@ -113,16 +113,37 @@ class Context:
     def release_workspaces(self) -> None:
         self._ws.clear()
 
+    def reserve(self, N: int, flags: int = 0) -> torch.Tensor:
+        """A fresh (uncached) workspace of the backward's size: the reserve space
+        a forward with ``HRC_FLAG_KEEP_PYRAMID`` fills and a backward with
+        ``HRC_FLAG_REUSE_PYRAMID`` reads."""
+        _, b = hrc_workspace_bytes(N, flags & _lib.HRC_FLAG_HALF_INTERVALS)
+        return torch.empty(b, dtype=torch.uint8, device=torch.device("cuda", self.device))
+
+    def _workspace_arg(self, ws: torch.Tensor) -> torch.Tensor:
+        if ws.dtype != torch.uint8 or not ws.is_cuda or not ws.is_contiguous():
+            raise ValueError("reserve must be a contiguous uint8 CUDA tensor")
+        self._check_device(ws)
+        return ws
+
     # -- entry points --------------------------------------------------------
     def hrc_forward(self, emission: torch.Tensor, sigma_t: torch.Tensor,
-                    out: Optional[torch.Tensor] = None, flags: int = 0) -> torch.Tensor:
+                    out: Optional[torch.Tensor] = None, flags: int = 0,
+                    reserve: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """With ``HRC_FLAG_KEEP_PYRAMID`` in flags, ``reserve`` (from ``reserve()``)
+        is the workspace and keeps what the reverse reads."""
         _check_field(emission, "emission")
         self._check_device(emission)
         N = _log2_size(emission)
         if out is None:
             out = torch.empty_like(emission)
         _check_like(emission, sigma_t=sigma_t, out=out)
-        ws = self.workspace(N, False, flags)
+        if flags & _lib.HRC_FLAG_KEEP_PYRAMID:
+            if reserve is None:
+                raise ValueError("HRC_FLAG_KEEP_PYRAMID needs a reserve tensor")
+            ws = self._workspace_arg(reserve)
+        else:
+            ws = self.workspace(N, False, flags)
         check(_lib.load().hrc_forward(self._ptr, N, emission.data_ptr(), sigma_t.data_ptr(),
                                       out.data_ptr(), ws.data_ptr(), ws.numel(),
                                       _stream_handle(emission.device), flags), "hrc_forward")
@@ -143,14 +164,22 @@ class Context:
         return out
 
     def hrc_backward(self, emission: torch.Tensor, sigma_t: torch.Tensor,
-                     grad_fluence: torch.Tensor, flags: int = 0):
+                     grad_fluence: torch.Tensor, flags: int = 0,
+                     reserve: Optional[torch.Tensor] = None):
+        """With ``HRC_FLAG_REUSE_PYRAMID`` in flags, ``reserve`` is the workspace a
+        forward with ``HRC_FLAG_KEEP_PYRAMID`` filled on the same inputs."""
         _check_field(emission, "emission")
         self._check_device(emission)
         N = _log2_size(emission)
         _check_like(emission, sigma_t=sigma_t, grad_fluence=grad_fluence)
         ge = torch.empty_like(emission)
         gs = torch.empty_like(emission)
-        ws = self.workspace(N, True, flags)
+        if flags & _lib.HRC_FLAG_REUSE_PYRAMID:
+            if reserve is None:
+                raise ValueError("HRC_FLAG_REUSE_PYRAMID needs the kept forward's reserve tensor")
+            ws = self._workspace_arg(reserve)
+        else:
+            ws = self.workspace(N, True, flags)
         check(_lib.load().hrc_backward(self._ptr, N, emission.data_ptr(), sigma_t.data_ptr(),
                                        grad_fluence.data_ptr(), ge.data_ptr(), gs.data_ptr(),
                                        ws.data_ptr(), ws.numel(),
@@ -305,16 +334,25 @@ def default_context(device: Optional[int] = None) -> Context:
 
 class HRCFunction(torch.autograd.Function):
     """F = HRC(emission, sigma_t) with the hand-written adjoint as backward.
-    Nothing but the inputs is saved: the backward recomputes the forward
-    intervals and cascades inside ``hrc_backward``."""
+    When a gradient is needed the forward keeps the interval pyramid and the
+    cascade levels in a reserve tensor (``HRC_FLAG_KEEP_PYRAMID``: the
+    backward's workspace size, held until the graph is freed) and the backward
+    reads them instead of recomputing them (``HRC_FLAG_REUSE_PYRAMID``);
+    ``keep=False`` saves only the inputs and lets ``hrc_backward`` recompute."""
 
     @staticmethod
-    def forward(ctx, emission, sigma_t, blur=False):
+    def forward(ctx, emission, sigma_t, blur=False, keep=True):
         emission = emission.contiguous()
         sigma_t = sigma_t.contiguous()
         c = default_context(emission.device.index)
         ctx.flags = _lib.HRC_FLAG_BLUR if blur else 0
-        F = c.hrc_forward(emission, sigma_t, flags=ctx.flags)
+        ctx.reserve = None
+        if keep and (ctx.needs_input_grad[0] or ctx.needs_input_grad[1]):
+            ctx.reserve = c.reserve(_log2_size(emission), ctx.flags)
+            F = c.hrc_forward(emission, sigma_t, flags=ctx.flags | _lib.HRC_FLAG_KEEP_PYRAMID,
+                              reserve=ctx.reserve)
+        else:
+            F = c.hrc_forward(emission, sigma_t, flags=ctx.flags)
         ctx.save_for_backward(emission, sigma_t)
         return F
 
@@ -322,14 +360,22 @@ class HRCFunction(torch.autograd.Function):
     def backward(ctx, grad_F):
         emission, sigma_t = ctx.saved_tensors
         c = default_context(emission.device.index)
-        ge, gs = c.hrc_backward(emission, sigma_t, grad_F.contiguous(), flags=ctx.flags)
-        return ge, gs, None
+        if ctx.reserve is not None:
+            ge, gs = c.hrc_backward(emission, sigma_t, grad_F.contiguous(),
+                                    flags=ctx.flags | _lib.HRC_FLAG_REUSE_PYRAMID,
+                                    reserve=ctx.reserve)
+        else:
+            ge, gs = c.hrc_backward(emission, sigma_t, grad_F.contiguous(), flags=ctx.flags)
+        return ge, gs, None, None
 
 
-def fluence(emission: torch.Tensor, sigma_t: torch.Tensor, blur: bool = False) -> torch.Tensor:
+def fluence(emission: torch.Tensor, sigma_t: torch.Tensor, blur: bool = False,
+            keep: bool = True) -> torch.Tensor:
     """Per-pixel fluence of a square power-of-two scene (differentiable); with
-    ``blur`` the cross blur of Eq. 21 follows the gather."""
-    return HRCFunction.apply(emission, sigma_t, blur)
+    ``blur`` the cross blur of Eq. 21 follows the gather.  ``keep=False``
+    trades the reverse's recomputation for not holding the reserve tensor
+    between forward and backward."""
+    return HRCFunction.apply(emission, sigma_t, blur, keep)
 
 
 class RGBFunction(torch.autograd.Function):

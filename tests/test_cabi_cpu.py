@@ -116,6 +116,50 @@ def test_half_intervals_where_taken():
     assert lib.hrc_batch_plan(None, sc, 1, H, None, ctypes.byref(out)) == HRC_ERR_UNSUPPORTED
 
 
+def test_keep_and_reuse_flags_where_taken():
+    """HRC_FLAG_KEEP_PYRAMID: the forward's workspace becomes the backward's
+    (with or without 16-bit intervals), all four quadrants at once;
+    HRC_FLAG_REUSE_PYRAMID only on the backward; every other call rejects both
+    before touching the device."""
+    lib = _lib.load()
+    buf = (ctypes.c_float * 1024)()
+    p = ctypes.addressof(buf)
+    K, R = _lib.HRC_FLAG_KEEP_PYRAMID, _lib.HRC_FLAG_REUSE_PYRAMID
+    H = _lib.HRC_FLAG_HALF_INTERVALS
+    for extra in (0, H):
+        st, f, b = _ws(5, extra)
+        stk, fk, bk = _ws(5, extra | K)
+        assert st == stk == HRC_OK and fk == bk == b and f < b
+        assert _ws(5, extra | R)[1:] == (f, b)
+        # the kept forward needs the backward's size
+        assert lib.hrc_forward(None, 5, p, p, p, p, b - 1, None, extra | K) == HRC_ERR_WORKSPACE
+        assert lib.hrc_forward(None, 5, p, p, p, p, b, None, extra | K) == HRC_ERR_INVALID_ARG
+        assert lib.hrc_backward(None, 5, p, p, p, p, p, p, b - 1, None, extra | R) == \
+            HRC_ERR_WORKSPACE
+        assert lib.hrc_backward(None, 5, p, p, p, p, p, p, b, None, extra | R) == \
+            HRC_ERR_INVALID_ARG
+    st, f, b = _ws(5)
+    # quadrant groups other than four, and the flags on the wrong call
+    for g in (_lib.HRC_FLAG_QUADRANTS_1, _lib.HRC_FLAG_QUADRANTS_2):
+        assert _ws(5, K | g)[0] == HRC_ERR_UNSUPPORTED
+        assert lib.hrc_forward(None, 5, p, p, p, p, b, None, K | g) == HRC_ERR_UNSUPPORTED
+    assert lib.hrc_forward(None, 5, p, p, p, p, b, None, K | _lib.HRC_FLAG_QUADRANTS_4) == \
+        HRC_ERR_INVALID_ARG
+    assert lib.hrc_forward(None, 5, p, p, p, p, b, None, R) == HRC_ERR_UNSUPPORTED
+    assert lib.hrc_backward(None, 5, p, p, p, p, p, p, b, None, K) == HRC_ERR_UNSUPPORTED
+    assert lib.hrc_forward_static(None, 5, p, p, p, None, K) == HRC_ERR_UNSUPPORTED
+    fr, br = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.hrc_workspace_bytes_rgb(5, K, ctypes.byref(fr), ctypes.byref(br)) == \
+        HRC_ERR_UNSUPPORTED
+    assert lib.hrc_forward_rgb(None, 5, p, p, p, p, 1 << 30, None, K) == HRC_ERR_UNSUPPORTED
+    assert lib.hrc_backward_rgb(None, 5, p, p, p, p, p, p, 1 << 30, None, R) == \
+        HRC_ERR_UNSUPPORTED
+    fb = ctypes.c_size_t(0)
+    for flag in (K, R):
+        assert lib.hrc_multibounce_workspace_bytes(5, 3, flag, ctypes.byref(fb), None) == \
+            HRC_ERR_UNSUPPORTED
+
+
 @pytest.mark.parametrize("N", [0, 2, 13, -1])
 def test_bad_sizes_are_rejected(N):
     assert _ws(N)[0] == HRC_ERR_SHAPE

@@ -150,6 +150,56 @@ def test_autograd_function_matches_direct_calls(ctx):
     assert torch.equal(e_t.grad, ge) and torch.equal(s_t.grad, gs)
 
 
+@pytest.mark.parametrize("S,flags,env", [(8, 0, False), (64, 0x2, False), (64, 0x4, False),
+                                          (256, 0x6, False), (128, 0, True), (1024, 0, False)],
+                         ids=["8", "64-blur", "64-half", "256-blur-half", "128-env", "1024"])
+def test_kept_forward_and_reused_backward_equal_the_plain_calls(ctx, S, flags, env):
+    """HRC_FLAG_KEEP_PYRAMID / HRC_FLAG_REUSE_PYRAMID: the kept forward's
+    fluence and the reused reverse's gradients are bitwise those of the plain
+    calls; a second reverse on the same reserve (another dLoss/dF) too, since a
+    reverse leaves the kept levels intact."""
+    from paper_2505_02041_amd import _lib
+    log(f"keep/reuse S={S} flags {flags:#x} env {env}")
+    if S == 1024:
+        sc = config3()
+        eps, sig = sc.eps, sc.sigma
+        dF = np.random.default_rng(5).normal(size=(S, S)).astype(np.float32)
+    else:
+        eps, sig, dF = _random_scene(S, 40 + S)
+    dF2 = np.random.default_rng(S + 1).normal(size=(S, S)).astype(np.float32)
+    if env:
+        ctx.set_environment([0.5 + 0.25 * k for k in range(12)])
+    try:
+        e, s, g, g2 = to_dev(eps), to_dev(sig), to_dev(dF), to_dev(dF2)
+        res = ctx.reserve(int(np.log2(S)), flags)
+        Fk = ctx.hrc_forward(e, s, flags=flags | _lib.HRC_FLAG_KEEP_PYRAMID, reserve=res)
+        gk = ctx.hrc_backward(e, s, g, flags=flags | _lib.HRC_FLAG_REUSE_PYRAMID, reserve=res)
+        gk2 = ctx.hrc_backward(e, s, g2, flags=flags | _lib.HRC_FLAG_REUSE_PYRAMID, reserve=res)
+        F = ctx.hrc_forward(e, s, flags=flags)
+        gp = ctx.hrc_backward(e, s, g, flags=flags)
+        gp2 = ctx.hrc_backward(e, s, g2, flags=flags)
+        torch.cuda.synchronize()
+    finally:
+        if env:
+            ctx.set_environment(None)
+    assert torch.equal(Fk, F)
+    for a, b in zip(gk + gk2, gp + gp2):
+        assert torch.equal(a, b)
+
+
+def test_autograd_without_keep_equals_with_keep(ctx):
+    from paper_2505_02041_amd import fluence
+    eps, sig, dF = _random_scene(128, 9)
+    grads = []
+    for keep in (True, False):
+        e_t, s_t = to_dev(eps).requires_grad_(), to_dev(sig).requires_grad_()
+        F = fluence(e_t, s_t, keep=keep)
+        F.backward(to_dev(dF))
+        grads.append((F.detach(), e_t.grad, s_t.grad))
+    for a, b in zip(*grads):
+        assert torch.equal(a, b)
+
+
 def test_backward_signs(ctx):
     """With dF >= 0 the emission gradient is >= 0 and the attenuation gradient
     is <= 0 (every term of F grows with emission and shrinks with attenuation)."""
