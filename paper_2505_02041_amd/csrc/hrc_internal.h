@@ -88,6 +88,7 @@ struct DownArgs {
     const float *env;        // environment table (nullable)
     int q0;                  // absolute quadrant of the group's first solve
     int half;                // T levels stored as 16-bit (L, T) pairs
+    int blk = 0;             // log2 of the direction block of the row order (0: column-major)
 };
 // The tail of the forward: levels 1 and 0 of the merge down, the gather and
 // the sum over quadrants, from R_2 of the group's quadrants q0 .. q0+nq-1.

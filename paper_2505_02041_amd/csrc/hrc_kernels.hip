@@ -480,8 +480,19 @@ __device__ void body_merge_down(const DownArgs &a, unsigned tile, int U, int tid
         const int y0 = (int)(idx & (S / (2 * P) - 1)) * 2 * P;
         const unsigned row = (unsigned)(idx >> (N - (P == 2 ? 2 : 1)));
         const int q = row >> N;
-        const unsigned r = row & (S - 1);
-        const int x = r >> n, ii = r & ((1 << n) - 1);
+        int x, ii;
+        if (a.blk) {
+            // rows in blocks of 2^blk directions, every probe column of a
+            // block together: the columns that read the same R_{n+1} and T
+            // rows run side by side on one XCD
+            const unsigned rr = row & (S - 1), lb = a.blk, lx = N - n;
+            x = (int)((rr >> lb) & ((1u << lx) - 1));
+            ii = (int)(((rr >> (lb + lx)) << lb) | (rr & ((1u << lb) - 1)));
+        } else {
+            x = (int)((row & (S - 1)) >> n);
+            ii = (int)(row & ((1u << n) - 1));
+        }
+        const unsigned r = ((unsigned)x << n) | (unsigned)ii;
         const float *Rq = a.Rn1 + q * SS;
         const float *envq = a.env ? a.env + (size_t)(a.q0 + q) * kConeTable : nullptr;
         float acc0[P], acc1[P];
