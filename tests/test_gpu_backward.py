@@ -10,7 +10,7 @@ import torch
 
 from oracle import hrc as oracle
 from oracle import hrc_vjp
-from scenes import config1, config3, config4
+from scenes import config1, config3, config4, scene_like_512
 
 pytestmark = pytest.mark.gpu
 
@@ -61,6 +61,29 @@ def test_backward_benchmark_scene_matches_oracle_reverse(ctx):
     assert_grad_close(ge, re, "d eps 1024")
     assert_grad_close(gs, rs, "d sigma 1024")
     ctx.release_workspaces()
+
+
+def test_backward_2048_matches_oracle_reverse(ctx):
+    """2048x2048 (N = 11) with the benchmark scene's recipe scaled with the
+    area, through the reuse pair (kept forward, reused reverse): d eps and
+    d sigma element by element against the oracle's reverse (about a minute
+    on one host core)."""
+    from paper_2505_02041_amd import _lib
+    log("backward 2048x2048 vs oracle reverse")
+    S = 2048
+    sc = scene_like_512(S, 32, 512, 1024, 128)
+    dF = np.random.default_rng(7).normal(size=(S, S)).astype(np.float32)
+    e, s, g = to_dev(sc.eps), to_dev(sc.sigma), to_dev(dF)
+    res = ctx.reserve(11)
+    ctx.hrc_forward(e, s, flags=_lib.HRC_FLAG_KEEP_PYRAMID, reserve=res)
+    ge, gs = ctx.hrc_backward(e, s, g, flags=_lib.HRC_FLAG_REUSE_PYRAMID, reserve=res)
+    torch.cuda.synchronize()
+    ge, gs = ge.cpu().numpy(), gs.cpu().numpy()
+    del res, e, s, g
+    ctx.release_workspaces()
+    re, rs = hrc_vjp.fluence_vjp(sc.eps, sc.sigma, dF)
+    assert_grad_close(ge, re, "d eps 2048")
+    assert_grad_close(gs, rs, "d sigma 2048")
 
 
 def test_backward_config1(ctx):

@@ -7,7 +7,7 @@ import pytest
 import torch
 
 from oracle import hrc as oracle
-from scenes import config1, config2, config3
+from scenes import config1, config2, config3, scene_like_512
 
 pytestmark = pytest.mark.gpu
 
@@ -58,6 +58,18 @@ def test_forward_config3_1024(ctx):
     log("forward 1024x1024 disks128_boxes256_lines32_fog")
     sc = config3()
     assert_forward_close(_run(ctx, sc.eps, sc.sigma), oracle.fluence(sc.eps, sc.sigma), "1024")
+
+
+@pytest.mark.parametrize("S", [2048, 4096])
+def test_forward_largest_sizes_match_oracle(ctx, S):
+    """The two largest grids, every pixel against the oracle: the benchmark
+    scene's recipe with disks, boxes and lines scaled with the area (the
+    oracle takes some 20-90 s here)."""
+    k = (S // 1024) ** 2
+    log(f"forward {S}x{S} scene vs oracle")
+    sc = scene_like_512(S, 30 + S // 1024, 128 * k, 256 * k, 32 * k)
+    assert_forward_close(_run(ctx, sc.eps, sc.sigma), oracle.fluence(sc.eps, sc.sigma), f"{S}")
+    ctx.release_workspaces()
 
 
 def test_forward_zero_emission_is_exactly_zero(ctx):
