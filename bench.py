@@ -37,6 +37,9 @@ def parse():
                     help="with --only-forward: the 16-bit interval storage (for profiling)")
     ap.add_argument("--only-backward", action="store_true",
                     help="run hrc_backward only, --steps times (for profiler runs)")
+    ap.add_argument("--kept", action="store_true",
+                    help="with --only-backward: one forward keeping the pyramid, then the "
+                         "backward reusing it (HRC_FLAG_KEEP_PYRAMID / _REUSE_PYRAMID)")
     return ap.parse_args()
 
 
@@ -157,10 +160,16 @@ def main():
         return (time.perf_counter() - t0) / steps
 
     if args.only_backward:
-        for _ in range(args.warmup + args.steps):
-            ctx.hrc_backward(eps, sig, dF)
+        if args.kept:
+            res = ctx.reserve(N)
+            ctx.hrc_forward(eps, sig, F, flags=_lib.HRC_FLAG_KEEP_PYRAMID, reserve=res)
+            for _ in range(args.warmup + args.steps):
+                ctx.hrc_backward(eps, sig, dF, flags=_lib.HRC_FLAG_REUSE_PYRAMID, reserve=res)
+        else:
+            for _ in range(args.warmup + args.steps):
+                ctx.hrc_backward(eps, sig, dF)
         torch.cuda.synchronize()
-        print(json.dumps({"backward_steps": args.steps}))
+        print(json.dumps({"backward_steps": args.steps, "kept": args.kept}))
         return
 
     # ---- forward: the metric ------------------------------------------------
