@@ -141,11 +141,28 @@ static int pick_u(const int *U, int kind) { return U ? (U[kind] > 0 ? U[kind] : 
 // The passes of one solve in execution order (Algorithm 1 for the four
 // quadrants at once, then, with gradients, its reverse).  R levels either all
 // kept (R(n) = R_n, needed by the reverse) or alternating in two buffers.
+// Tile order of the elementwise passes from 1024^2 up: blocks of tiles dealt
+// round robin to the XCDs (log2 of the block; 0 below, where the contiguous
+// eighths were as fast or faster).  Measured against contiguous eighths: the
+// forward 2-7% and the reverse 3-9% faster at 1024^2 .. 4096^2; the same
+// results, since only the order of the tiles changes.
+static int tile_order(int N, int kind) {
+    if (N < 10) return 0;
+    switch (kind) {
+        case PH_UP: return 7;
+        case PH_DOWN: return 9;
+        case PH_DOWN_ADJ:
+        case PH_DT: return N - 6;
+        default: return 0;
+    }
+}
+
 int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, const int *U,
                        Phase *out, int max_out, bool recompute) {
     const int N = w.L.N;
     int np = 0;
-    auto add = [&](const Phase &p) {
+    auto add = [&](Phase p) {
+        p.xblk = tile_order(N, p.kind);
         if (np < max_out) out[np] = p;
         ++np;
     };

@@ -154,6 +154,7 @@ enum PhaseKind {
 struct Phase {
     int kind = 0;
     int U = 1;
+    int xblk = 0;  // log2 of the tile blocks dealt round-robin to the XCDs (0: contiguous eighths)
     union A {
         SeedArgs seed;
         UpArgs up;

@@ -52,6 +52,19 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb) {
     return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
 }
 
+// The same with the tiles dealt to the XCDs in blocks of 2^lb, round robin
+// (the last partial round split as above), so that the XCDs work on nearby
+// addresses at any time instead of addresses an eighth of the pass apart.
+__device__ __forceinline__ unsigned xcd_tile_blk(unsigned b, unsigned nb, unsigned lb) {
+    if (lb == 0) return xcd_tile(b, nb);
+    const unsigned xcd = b & 7u, local = b >> 3;
+    const unsigned full = nb >> (3 + lb);
+    if (local < (full << lb))
+        return ((((local >> lb) << 3) + xcd) << lb) + (local & ((1u << lb) - 1));
+    const unsigned rem = nb - (full << (3 + lb));
+    return (full << (3 + lb)) + xcd_tile(xcd + 8u * (local - (full << lb)), rem);
+}
+
 // <L, T> of a chord of length ell through a uniform pixel (Eq. 2-4):
 // T = exp(-tau), L = eps*ell*(1 - exp(-tau))/tau, tau = sig*ell.
 //
@@ -1845,7 +1858,7 @@ __device__ __forceinline__ void run_phase(const Phase &p, unsigned tile, char *l
 
 #define HRC_ELEMENTWISE_KERNEL(name, body, field)                                  \
     __global__ __launch_bounds__(256) void name(Phase p) {                         \
-        body(p.a.field, xcd_tile(blockIdx.x, gridDim.x), p.U, ltid());             \
+        body(p.a.field, xcd_tile_blk(blockIdx.x, gridDim.x, p.xblk), p.U, ltid()); \
     }
 HRC_ELEMENTWISE_KERNEL(hrc_merge_up, body_merge_up<float2>, up)
 HRC_ELEMENTWISE_KERNEL(hrc_merge_down, body_merge_down<float2>, down)
