@@ -1901,16 +1901,16 @@ __global__ __launch_bounds__(256) void hrc_seed_rgb_f16(Phase p) {
     body_seed_rgb<16, half4_t>(p.a.seed, xcd_tile(blockIdx.x, gridDim.x), lds, ltid());
 }
 __global__ __launch_bounds__(256) void hrc_merge_up_rgb(Phase p) {
-    body_merge_up_rgb<float4>(p.a.up, xcd_tile(blockIdx.x, gridDim.x), p.U, ltid());
+    body_merge_up_rgb<float4>(p.a.up, xcd_tile_blk(blockIdx.x, gridDim.x, p.xblk), p.U, ltid());
 }
 __global__ __launch_bounds__(256) void hrc_merge_up_rgb_f16(Phase p) {
-    body_merge_up_rgb<half4_t>(p.a.up, xcd_tile(blockIdx.x, gridDim.x), p.U, ltid());
+    body_merge_up_rgb<half4_t>(p.a.up, xcd_tile_blk(blockIdx.x, gridDim.x, p.xblk), p.U, ltid());
 }
 __global__ __launch_bounds__(256) void hrc_merge_down_rgb(Phase p) {
-    body_merge_down_rgb<float4>(p.a.down, xcd_tile(blockIdx.x, gridDim.x), p.U, ltid());
+    body_merge_down_rgb<float4>(p.a.down, xcd_tile_blk(blockIdx.x, gridDim.x, p.xblk), p.U, ltid());
 }
 __global__ __launch_bounds__(256) void hrc_merge_down_rgb_f16(Phase p) {
-    body_merge_down_rgb<half4_t>(p.a.down, xcd_tile(blockIdx.x, gridDim.x), p.U, ltid());
+    body_merge_down_rgb<half4_t>(p.a.down, xcd_tile_blk(blockIdx.x, gridDim.x, p.xblk), p.U, ltid());
 }
 __global__ __launch_bounds__(256) void hrc_tail_rgb(Phase p) {
     __shared__ __align__(16) char lds[TailTileRgb<16>::lds];
