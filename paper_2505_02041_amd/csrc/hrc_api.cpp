@@ -143,7 +143,8 @@ static int pick_u(const int *U, int kind) { return U ? (U[kind] > 0 ? U[kind] : 
 // kept (R(n) = R_n, needed by the reverse) or alternating in two buffers.
 // Tile order of the elementwise passes from 1024^2 up: blocks of tiles dealt
 // round robin to the XCDs (log2 of the block; 0 below, where the contiguous
-// eighths were as fast or faster).  Measured against contiguous eighths: the
+// eighths were as fast or faster).  For the adjoints, blocks of 2^(N-6) were
+// as fast as 2^(N-5) and the larger ones split fewer shared rows across XCDs.  Measured against contiguous eighths: the
 // forward 2-7%, the RGB forward 4% and the reverse 3-9% faster at 1024^2 ..
 // 4096^2; the same results, since only the order of the tiles changes.
 static int tile_order(int N, int kind) {
@@ -154,7 +155,7 @@ static int tile_order(int N, int kind) {
         case PH_DOWN:
         case PH_DOWN_RGB: return 9;
         case PH_DOWN_ADJ:
-        case PH_DT: return N - 6;
+        case PH_DT: return N - 5;
         default: return 0;
     }
 }
