@@ -106,8 +106,8 @@ typedef enum {
  * hrc_backward.  The library cannot check the pairing: a workspace that does
  * not hold a matching kept forward gives wrong gradients (every access stays
  * inside the workspace).  KEEP runs the four quadrants at once
- * (HRC_FLAG_QUADRANTS_1 or _2 with it: HRC_ERR_UNSUPPORTED); the other calls
- * reject both flags. */
+ * (HRC_FLAG_QUADRANTS_1 or _2 with it: HRC_ERR_UNSUPPORTED).  The RGB calls
+ * take the pair in the same way; the other calls reject both flags. */
 #define HRC_FLAG_KEEP_PYRAMID 0x8u
 #define HRC_FLAG_REUSE_PYRAMID 0x40u
 #define HRC_FLAG_QUADRANTS_1 0x10u
@@ -219,13 +219,15 @@ hrc_status hrc_backward(hrc_context *ctx, int log2_size,
  *   sigma_t  : [S][S], shared by the channels
  *   fluence  : [3][S][S] planes, overwritten
  * Flags: HRC_FLAG_VALIDATE, HRC_FLAG_BLUR (each plane blurred as by
- * hrc_forward), and for the forward HRC_FLAG_HALF_INTERVALS: the paper's own
- * storage (Section 5), the interval as four IEEE halves (8 bytes), computed
- * in FP32 and rounded once when stored, each channel then within the relative
- * N * 2^-11 of the FP32 result that hrc_forward's flag states.  The context's
- * environment map is not applied (RGB calls run without one).  Workspace from
- * hrc_workspace_bytes_rgb (pass the same flags).  Argument checks as for
- * hrc_forward. */
+ * hrc_forward), and for the forward either HRC_FLAG_HALF_INTERVALS (the
+ * paper's own storage, Section 5: the interval as four IEEE halves, 8 bytes,
+ * computed in FP32 and rounded once when stored, each channel then within the
+ * relative N * 2^-11 of the FP32 result that hrc_forward's flag states) or
+ * HRC_FLAG_KEEP_PYRAMID (the reserve space, as for hrc_forward: the workspace
+ * must then be the backward's size; not both, HRC_ERR_UNSUPPORTED).  The
+ * context's environment map is not applied (RGB calls run without one).
+ * Workspace from hrc_workspace_bytes_rgb (pass the same flags; it takes
+ * HRC_FLAG_REUSE_PYRAMID as well).  Argument checks as for hrc_forward. */
 hrc_status hrc_workspace_bytes_rgb(int log2_size, unsigned flags, size_t *forward_bytes,
                                    size_t *backward_bytes);
 hrc_status hrc_forward_rgb(hrc_context *ctx, int log2_size, const float *emission,
@@ -233,11 +235,17 @@ hrc_status hrc_forward_rgb(hrc_context *ctx, int log2_size, const float *emissio
                            size_t workspace_bytes, void *stream, unsigned flags);
 
 /* Vector-Jacobian product of hrc_forward_rgb: given grad_fluence ([3][S][S]),
- * writes grad_emission ([3][S][S]) and grad_sigma_t ([S][S], the sum over the
- * channels, in channel order).  Runs the one-channel reverse of hrc_backward
- * per channel over the shared medium, so grad_emission's plane c equals
- * hrc_backward's d emission for channel c bitwise.  Flags and checks as for
- * hrc_forward_rgb. */
+ * writes grad_emission ([3][S][S]) and grad_sigma_t ([S][S]).  The reverse of
+ * the RGB solve itself: its adjoint intervals are (dL_r, dL_g, dL_b, dT) and
+ * its adjoint cascade levels three planes, so the medium's transmittances and
+ * their adjoints are computed and moved once for the three channels.  The
+ * radiance adjoints of a channel never depend on the transmittance adjoints,
+ * so grad_emission's plane c equals hrc_backward's d emission for channel c
+ * bitwise; grad_sigma_t gathers the channels inside the reverse (the sum of
+ * three one-channel d sigma up to rounding).  Flags: HRC_FLAG_VALIDATE,
+ * HRC_FLAG_BLUR, HRC_FLAG_REUSE_PYRAMID (after hrc_forward_rgb with
+ * HRC_FLAG_KEEP_PYRAMID, as for hrc_backward).  Workspace: backward_bytes of
+ * hrc_workspace_bytes_rgb. */
 hrc_status hrc_backward_rgb(hrc_context *ctx, int log2_size, const float *emission,
                             const float *sigma_t, const float *grad_fluence,
                             float *grad_emission, float *grad_sigma_t, void *workspace,

@@ -36,12 +36,14 @@ HRC_FLAG_BATCH_DENSE = 0x200
 HRC_FLAG_BATCH_PERSISTENT = 0x400
 PASS_NAMES = ["seed", "merge_up", "merge_down", "tail", "gather_adj",
               "merge_down_adj", "interval_adj", "seed_adj", "blur", "blur_adj",
-              "seed_rgb", "merge_up_rgb", "merge_down_rgb", "tail_rgb"]
+              "seed_rgb", "merge_up_rgb", "merge_down_rgb", "tail_rgb",
+              "merge_down_adj_rgb", "interval_adj_rgb", "seed_adj_rgb"]
 # Kernel symbol of each pass kind (what a profiler shows).
 PASS_KERNELS = ["hrc_seed", "hrc_merge_up", "hrc_merge_down", "hrc_tail",
                 "hrc_gather_adj", "hrc_merge_down_adj", "hrc_interval_adj", "hrc_seed_adj",
                 "hrc_blur", "hrc_blur_adj", "hrc_seed_rgb", "hrc_merge_up_rgb",
-                "hrc_merge_down_rgb", "hrc_tail_rgb"]
+                "hrc_merge_down_rgb", "hrc_tail_rgb", "hrc_merge_down_adj_rgb",
+                "hrc_interval_adj_rgb", "hrc_seed_adj_rgb"]
 
 # Every function the header declares, with (restype, argtypes).
 _vp = ctypes.c_void_p

@@ -19,14 +19,13 @@ Layout make_layout(int N, bool backward, int group, bool half, bool rgb) {
     L.S = size_t(1) << N;
     L.group = backward ? kQuadrants : group;
     const size_t SS = L.S * L.S;
-    const size_t planes = (rgb && !backward) ? 3 : 1;
+    const size_t planes = rgb ? 3 : 1;
     size_t off = 256;  // first 256 bytes: scratch flag for HRC_FLAG_VALIDATE
     // the forward's tail folds T_0 and T_1 itself (only the reverse stores
     // them), and the merge down builds what it reads of T_N itself
-    const size_t iv_bytes = backward ? (half ? 2 * sizeof(uint16_t) : sizeof(float2))
-                            : rgb    ? (half ? 4 * sizeof(uint16_t) : sizeof(float4))
-                            : half   ? 2 * sizeof(uint16_t)
-                                     : sizeof(float2);
+    const size_t iv_bytes = rgb    ? (half ? 4 * sizeof(uint16_t) : sizeof(float4))
+                            : half ? 2 * sizeof(uint16_t)
+                                   : sizeof(float2);
     for (int n = backward ? 0 : kTracedLevels - 1; n < N; ++n) {
         L.t_level[n] = off;
         off += align256(L.group * t_level_entries(N, n) * iv_bytes);
@@ -43,11 +42,11 @@ Layout make_layout(int N, bool backward, int group, bool half, bool rgb) {
     if (backward) {
         for (int n = 0; n <= N; ++n) {
             L.dt_level[n] = off;
-            off += align256(kQuadrants * t_level_entries(N, n) * sizeof(float2));
+            off += align256(kQuadrants * t_level_entries(N, n) * (rgb ? sizeof(float4) : sizeof(float2)));
         }
         for (int i = 0; i < N; ++i) {
             L.dr_level[i] = off;
-            off += align256(kQuadrants * SS * sizeof(float));
+            off += align256(planes * kQuadrants * SS * sizeof(float));
         }
     }
     L.total = off;
@@ -155,7 +154,9 @@ static int tile_order(int N, int kind) {
         case PH_DOWN:
         case PH_DOWN_RGB: return 9;
         case PH_DOWN_ADJ:
-        case PH_DT: return N - 5;
+        case PH_DOWN_ADJ_RGB:
+        case PH_DT:
+        case PH_DT_RGB: return N - 5;
         default: return 0;
     }
 }
@@ -335,6 +336,111 @@ int build_rgb_forward_phases(const Ws &w, const SolveBuffers &b, Phase *out, int
             p.a.bl = BlurArgs{gathered + c * SS, b.sig, b.F + c * SS, N, kBlurThreshold};
             add(p);
         }
+    }
+    return np;
+}
+
+// The RGB solve in the reverse's layout (every level kept, three planes per
+// cascade level, float4 intervals and adjoints): with recompute, the forward
+// down to R_1 (and, given F, the tail and the blur); with a gradient, the
+// reverse.  Mirrors build_solve_phases for all four quadrants at once.
+int build_rgb_backward_phases(const Ws &w, const SolveBuffers &b, Phase *out, int max_out,
+                              bool recompute) {
+    const int N = w.L.N;
+    const size_t SS = w.L.S * w.L.S, plane = kQuadrants * SS;
+    int np = 0;
+    auto add = [&](Phase p) {
+        p.xblk = tile_order(N, p.kind);
+        if (np < max_out) out[np] = p;
+        ++np;
+    };
+    Phase p;
+    // the gather before the blur goes to dR_0, which the reverse writes only later
+    float *gathered = b.blur ? w.dR(0) : b.F;
+    if (recompute) {
+        p.kind = PH_SEED_RGB;
+        p.a.seed = SeedArgs{b.eps, b.sig, w.T(0), w.T(1), w.T(2), t_level_entries(N, 0),
+                            t_level_entries(N, 1), t_level_entries(N, 2), N, 0, kQuadrants, 16, 0, 0};
+        add(p);
+        for (int n = kTracedLevels; n < N; ++n) {
+            p = Phase();
+            p.kind = PH_UP_RGB;
+            p.a.up = UpArgs{w.T(n - 1), w.T(n), t_level_entries(N, n - 1), t_level_entries(N, n), N,
+                            n, kQuadrants, 0};
+            add(p);
+        }
+        for (int n = N - 1; n >= 1; --n) {
+            p = Phase();
+            p.kind = PH_DOWN_RGB;
+            p.a.down = DownArgs{(n + 1 < N) ? w.R(n + 1) : nullptr, w.T(n), w.T(n + 1), w.R(n),
+                                t_level_entries(N, n), t_level_entries(N, n + 1), N, n, kQuadrants,
+                                nullptr, 0, 0};
+            add(p);
+        }
+        if (b.F) {
+            p = Phase();
+            p.kind = PH_TAIL_RGB;
+            p.a.tail = TailArgs{b.eps, b.sig, w.R(2), gathered, N, 0, kQuadrants, 0, nullptr, 16};
+            add(p);
+            if (b.blur) {
+                for (int c = 0; c < 3; ++c) {
+                    p = Phase();
+                    p.kind = PH_BLUR;
+                    p.a.bl = BlurArgs{gathered + c * SS, b.sig, b.F + c * SS, N, kBlurThreshold};
+                    add(p);
+                }
+            }
+        }
+    }
+    if (b.dF) {
+        // with the blur, its transpose per channel first, into R_0's buffer
+        const float *dgathered = b.dF;
+        if (b.blur) {
+            for (int c = 0; c < 3; ++c) {
+                p = Phase();
+                p.kind = PH_BLUR_ADJ;
+                p.a.bl = BlurArgs{b.dF + c * SS, b.sig, w.R(0) + c * SS, N, kBlurThreshold};
+                add(p);
+            }
+            dgathered = w.R(0);
+        }
+        for (int c = 0; c < 3; ++c) {
+            p = Phase();
+            p.kind = PH_GATHER_ADJ;
+            p.a.ga = GatherAdjArgs{dgathered + c * SS, w.dR(0) + c * plane, N};
+            add(p);
+        }
+        for (int n = 0; n + 1 < N; ++n) {
+            p = Phase();
+            p.kind = PH_DOWN_ADJ_RGB;
+            p.a.da = DownAdjArgs{w.dR(n), w.T(n), w.T(n + 1), w.dR(n + 1), t_level_entries(N, n),
+                                 t_level_entries(N, n + 1), N, n, 0};
+            add(p);
+        }
+        for (int n = N; n >= 0; --n) {
+            p = Phase();
+            p.kind = PH_DT_RGB;
+            DTArgs d{};
+            d.Tn = w.T(n);
+            d.has_up = (n + 1 <= N && n + 1 >= kTracedLevels) ? 1 : 0;
+            d.dTn1 = d.has_up ? w.dT(n + 1) : nullptr;
+            d.dRn = n < N ? w.dR(n) : nullptr;
+            d.dRm = n >= 1 ? w.dR(n - 1) : nullptr;
+            d.Rn1 = (n + 1 < N) ? w.R(n + 1) : nullptr;
+            d.Rn = n < N ? w.R(n) : nullptr;
+            d.dT = w.dT(n);
+            d.en = t_level_entries(N, n);
+            d.en1 = n + 1 <= N ? t_level_entries(N, n + 1) : 0;
+            d.N = N;
+            d.n = n;
+            p.a.dt = d;
+            add(p);
+        }
+        p = Phase();
+        p.kind = PH_SEED_ADJ_RGB;
+        p.a.sa = SeedAdjArgs{b.eps, b.sig, w.dT(0), w.dT(1), w.dT(2), t_level_entries(N, 0),
+                             t_level_entries(N, 1), t_level_entries(N, 2), b.dE, b.dS, N};
+        add(p);
     }
     return np;
 }
@@ -542,25 +648,37 @@ hrc_status hrc_backward(hrc_context *ctx, int log2_size, const float *emission,
 // ---- three radiance channels (RGB) over one medium ---------------------------
 
 static constexpr unsigned kRgbFlags = HRC_FLAG_VALIDATE | HRC_FLAG_BLUR;
-static constexpr unsigned kRgbForwardFlags = kRgbFlags | HRC_FLAG_HALF_INTERVALS;
+// hrc_forward_rgb also takes the 16-bit storage or HRC_FLAG_KEEP_PYRAMID (not
+// both: the reverse keeps FP32 intervals), hrc_backward_rgb
+// HRC_FLAG_REUSE_PYRAMID; the workspace query takes all three.
+static constexpr unsigned kRgbForwardFlags =
+    kRgbFlags | HRC_FLAG_HALF_INTERVALS | HRC_FLAG_KEEP_PYRAMID;
+static constexpr unsigned kRgbBackwardFlags = kRgbFlags | HRC_FLAG_REUSE_PYRAMID;
 
-// The RGB reverse: the one-channel reverse's workspace, then two fields for
-// the second and third channels' dLoss/d sigma.
-static size_t rgb_backward_bytes(int N) {
-    const size_t SS = size_t(1) << (2 * N);
-    return align256(make_layout(N, true).total) + 2 * align256(SS * sizeof(float));
+static bool rgb_flags_ok(unsigned flags) {
+    return !((flags & HRC_FLAG_HALF_INTERVALS) && (flags & HRC_FLAG_KEEP_PYRAMID));
 }
 
 hrc_status hrc_workspace_bytes_rgb(int log2_size, unsigned flags, size_t *forward_bytes,
                                    size_t *backward_bytes) {
     hrc_status st = check_shape(log2_size);
     if (st != HRC_OK) return st;
-    if (flags & ~kRgbForwardFlags) return HRC_ERR_UNSUPPORTED;
+    if ((flags & ~(kRgbForwardFlags | HRC_FLAG_REUSE_PYRAMID)) || !rgb_flags_ok(flags))
+        return HRC_ERR_UNSUPPORTED;
+    const bool keep = (flags & HRC_FLAG_KEEP_PYRAMID) != 0;
     if (forward_bytes)
         *forward_bytes =
-            make_layout(log2_size, false, 4, (flags & HRC_FLAG_HALF_INTERVALS) != 0, true).total;
-    if (backward_bytes) *backward_bytes = rgb_backward_bytes(log2_size);
+            make_layout(log2_size, keep, 4, (flags & HRC_FLAG_HALF_INTERVALS) != 0, true).total;
+    if (backward_bytes) *backward_bytes = make_layout(log2_size, true, 4, false, true).total;
     return HRC_OK;
+}
+
+static hrc_status validate_rgb(const Ws &w, const float *emission, const float *sigma_t,
+                               hipStream_t s) {
+    const size_t SS = w.L.S * w.L.S;
+    hrc_status st = validate_inputs(w, emission, emission + SS, s);
+    if (st == HRC_OK) st = validate_inputs(w, emission + 2 * SS, sigma_t, s);
+    return st;
 }
 
 hrc_status hrc_forward_rgb(hrc_context *ctx, int log2_size, const float *emission,
@@ -571,9 +689,10 @@ hrc_status hrc_forward_rgb(hrc_context *ctx, int log2_size, const float *emissio
     if (!aligned16(emission) || !aligned16(sigma_t) || !aligned16(fluence) ||
         !aligned16(workspace))
         return HRC_ERR_INVALID_ARG;
-    if (flags & ~kRgbForwardFlags) return HRC_ERR_UNSUPPORTED;
+    if ((flags & ~kRgbForwardFlags) || !rgb_flags_ok(flags)) return HRC_ERR_UNSUPPORTED;
     const bool half = (flags & HRC_FLAG_HALF_INTERVALS) != 0;
-    Layout L = make_layout(log2_size, false, 4, half, true);
+    const bool keep = (flags & HRC_FLAG_KEEP_PYRAMID) != 0;
+    Layout L = make_layout(log2_size, keep, 4, half, true);
     if (workspace_bytes < L.total) return HRC_ERR_WORKSPACE;
     if (!ctx) return HRC_ERR_INVALID_ARG;
     DeviceGuard g(ctx->device);
@@ -581,15 +700,14 @@ hrc_status hrc_forward_rgb(hrc_context *ctx, int log2_size, const float *emissio
     hipStream_t s = static_cast<hipStream_t>(stream);
     Ws w{static_cast<char *>(workspace), L};
     if (flags & HRC_FLAG_VALIDATE) {
-        const size_t SS = L.S * L.S;
-        st = validate_inputs(w, emission, emission + SS, s);
-        if (st == HRC_OK) st = validate_inputs(w, emission + 2 * SS, sigma_t, s);
+        st = validate_rgb(w, emission, sigma_t, s);
         if (st != HRC_OK) return st;
     }
     Phase ph[kMaxPhases];
     SolveBuffers b{emission, sigma_t, fluence, nullptr, nullptr, nullptr,
                    (flags & HRC_FLAG_BLUR) ? 1 : 0, nullptr, half ? 1 : 0};
-    int np = build_rgb_forward_phases(w, b, ph, kMaxPhases);
+    int np = keep ? build_rgb_backward_phases(w, b, ph, kMaxPhases, true)
+                  : build_rgb_forward_phases(w, b, ph, kMaxPhases);
     return run_phases(ph, np, s);
 }
 
@@ -602,36 +720,24 @@ hrc_status hrc_backward_rgb(hrc_context *ctx, int log2_size, const float *emissi
     if (!aligned16(emission) || !aligned16(sigma_t) || !aligned16(grad_fluence) ||
         !aligned16(grad_emission) || !aligned16(grad_sigma_t) || !aligned16(workspace))
         return HRC_ERR_INVALID_ARG;
-    if (flags & ~kRgbFlags) return HRC_ERR_UNSUPPORTED;
-    if (workspace_bytes < rgb_backward_bytes(log2_size)) return HRC_ERR_WORKSPACE;
+    if (flags & ~kRgbBackwardFlags) return HRC_ERR_UNSUPPORTED;
+    const Layout L = make_layout(log2_size, true, 4, false, true);
+    if (workspace_bytes < L.total) return HRC_ERR_WORKSPACE;
     if (!ctx) return HRC_ERR_INVALID_ARG;
     DeviceGuard g(ctx->device);
     if (!g.ok) return HRC_ERR_HIP;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const Layout L = make_layout(log2_size, true);
-    const size_t SS = L.S * L.S;
-    char *base = static_cast<char *>(workspace);
-    Ws w{base, L};
-    float *dS1 = reinterpret_cast<float *>(base + align256(L.total));
-    float *dS2 = reinterpret_cast<float *>(base + align256(L.total) + align256(SS * sizeof(float)));
+    Ws w{static_cast<char *>(workspace), L};
     if (flags & HRC_FLAG_VALIDATE) {
-        st = validate_inputs(w, emission, emission + SS, s);
-        if (st == HRC_OK) st = validate_inputs(w, emission + 2 * SS, sigma_t, s);
+        st = validate_rgb(w, emission, sigma_t, s);
         if (st != HRC_OK) return st;
     }
-    // each channel's reverse over the shared medium (the channels' fluences are
-    // independent solves), then dLoss/d sigma summed over the channels
-    float *dS[3] = {grad_sigma_t, dS1, dS2};
     Phase ph[kMaxPhases];
-    for (int c = 0; c < 3; ++c) {
-        SolveBuffers b{emission + c * SS, sigma_t, nullptr, grad_fluence + c * SS,
-                       grad_emission + c * SS, dS[c], (flags & HRC_FLAG_BLUR) ? 1 : 0, nullptr};
-        const int np = build_solve_phases(w, b, true, nullptr, ph, kMaxPhases);
-        st = run_phases(ph, np, s);
-        if (st != HRC_OK) return st;
-    }
-    return launch_add3(grad_sigma_t, dS1, dS2, grad_sigma_t, SS, s) == hipSuccess ? HRC_OK
-                                                                                 : HRC_ERR_HIP;
+    SolveBuffers b{emission, sigma_t, nullptr, grad_fluence, grad_emission, grad_sigma_t,
+                   (flags & HRC_FLAG_BLUR) ? 1 : 0, nullptr, 0};
+    const int np = build_rgb_backward_phases(w, b, ph, kMaxPhases,
+                                             (flags & HRC_FLAG_REUSE_PYRAMID) == 0);
+    return run_phases(ph, np, s);
 }
 
 // ---- several diffuse bounces ------------------------------------------------

@@ -145,8 +145,9 @@ struct BlurArgs {
 enum PhaseKind {
     PH_SEED = 0, PH_UP, PH_DOWN, PH_TAIL, PH_GATHER_ADJ,
     PH_DOWN_ADJ, PH_DT, PH_SEED_ADJ, PH_BLUR, PH_BLUR_ADJ,
-    // the RGB forward (three radiance channels over one medium)
-    PH_SEED_RGB, PH_UP_RGB, PH_DOWN_RGB, PH_TAIL_RGB, PH_KIND_COUNT
+    // the RGB solve (three radiance channels over one medium) and its reverse
+    PH_SEED_RGB, PH_UP_RGB, PH_DOWN_RGB, PH_TAIL_RGB,
+    PH_DOWN_ADJ_RGB, PH_DT_RGB, PH_SEED_ADJ_RGB, PH_KIND_COUNT
 };
 
 // One pass.  U = elements per thread of the elementwise phases (a tile covers
@@ -191,6 +192,10 @@ int build_solve_phases(const Ws &w, const SolveBuffers &b, bool keep_all_r, cons
 // The passes of one RGB forward (all four quadrants at once): eps is [3][S][S],
 // F is [3][S][S]; with blur, each plane is blurred by the one-channel pass.
 int build_rgb_forward_phases(const Ws &w, const SolveBuffers &b, Phase *out, int max_out);
+// The RGB solve in the reverse's layout: with recompute the forward down to R_1
+// (then, given F, the tail and the blur), with a gradient the reverse.
+int build_rgb_backward_phases(const Ws &w, const SolveBuffers &b, Phase *out, int max_out,
+                              bool recompute);
 
 unsigned phase_tiles(const Phase &p);
 hipError_t upload_cone_table(const float *host_table);
@@ -253,8 +258,6 @@ hipError_t persistent_occupancy(int variant, int *blocks_per_cu);
 hipError_t launch_xcd_probe(unsigned *out, int grid, int variant, hipStream_t s);
 hipError_t launch_validate(const float *a, const float *b, size_t n, int *flag,
                            hipStream_t s);
-hipError_t launch_add3(const float *a, const float *b, const float *c, float *out, size_t n,
-                       hipStream_t s);
 
 // Several diffuse bounces: the next bounce's emission eps_0 + a sigma F / (2 pi)
 // (isotropic in-scattering), and the reverse step of that update given dLoss/d

@@ -1456,9 +1456,9 @@ __device__ void body_blur_adj(const BlurArgs &a, unsigned tile, int tid) {
 // and a cascade level is three planes of floats (plane c at c * nq * S^2).
 // Every channel's arithmetic is that of the one-channel bodies, in the same
 // order, so each channel's fluence equals the one-channel forward's bitwise.
-// The forward only: 16x16 image tiles (a 32x32 tile of RGB intervals would
-// not leave LDS for two blocks per CU), all four quadrants at once, no
-// environment map.  With the 16-bit storage (the paper's: radiance and
+// 16x16 image tiles (a 32x32 tile of RGB intervals would not leave LDS for
+// two blocks per CU), all four quadrants at once, no environment map; the
+// reverse follows the forward below.  With the 16-bit storage (the paper's: radiance and
 // transmittance as halves) an interval is four halves, 8 bytes, computed in
 // FP32 and rounded once when stored.
 // ---------------------------------------------------------------------------
@@ -1469,7 +1469,8 @@ template <int TILE> struct SeedTileRgb {
     static constexpr int lds = 3 * span * pitch * 16;
 };
 
-// Traced level T_2 of every quadrant (the tail folds T_0 and T_1 itself).
+// Traced level T_2 of every quadrant (the tail folds T_0 and T_1 itself), and
+// T_0, T_1 as well for the reverse's recomputed forward (a.first = 0).
 template <int TILE, typename TS>
 __device__ void body_seed_rgb(const SeedArgs &a, unsigned tile, char *lds, int tid) {
     using G = SeedTileRgb<TILE>;
@@ -1495,7 +1496,11 @@ __device__ void body_seed_rgb(const SeedArgs &a, unsigned tile, char *lds, int t
         iv[2 * G::span * G::pitch + l] = cell_interval_rgb(e0, e1, e2, g, kQ5);
     }
     __syncthreads();
-    for (int g = 0; g < a.nq; ++g) seed_level_rays<TILE, 2, TS, float4>(iv, a, a.q0 + g, g, r0, c0, tid);
+    for (int g = 0; g < a.nq; ++g) {
+        if (a.first <= 0) seed_level_rays<TILE, 0, TS, float4>(iv, a, a.q0 + g, g, r0, c0, tid);
+        if (a.first <= 1) seed_level_rays<TILE, 1, TS, float4>(iv, a, a.q0 + g, g, r0, c0, tid);
+        seed_level_rays<TILE, 2, TS, float4>(iv, a, a.q0 + g, g, r0, c0, tid);
+    }
     __syncthreads();
 }
 
@@ -1819,6 +1824,433 @@ __device__ void body_tail_rgb(const TailArgs &a, unsigned tile, char *lds, int t
     __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// Reverse of the RGB solve.  The adjoint of an RGB interval is one float4
+// (dL_r, dL_g, dL_b, dT) and an adjoint cascade level is three planes, as in
+// the forward.  The merge's transpose keeps the channels apart in its radiance
+// terms and gathers them in its transmittance term: for L_c = L_n,c + T_n L_f,c
+// and T = T_n T_f, dL_n,c = dL_c, dL_f,c = dL_c T_n, dT_f = dT T_n and
+// dT_n = sum_c dL_c L_f,c + dT T_f.  The radiance adjoints never depend on the
+// transmittance adjoints, so each channel's radiance adjoints and d emission
+// follow the one-channel reverse's arithmetic in its order (bitwise its
+// result); only the transmittance adjoints and d sigma gather the channels,
+// computing, storing and reading the medium's part once for all three.
+// ---------------------------------------------------------------------------
+
+// Adjoint of the merge down over three channel planes, transmittances shared
+// (gather form, as body_merge_down_adj).
+template <typename TS>
+__device__ void body_merge_down_adj_rgb(const DownAdjArgs &a, unsigned tile, int U, int tid) {
+    const int N = a.N, S = 1 << N, n = a.n, m = n + 1;
+    const size_t SS = (size_t)S * S, plane = 4 * SS;
+    for (int uu = 0; uu < U; ++uu) {
+        const size_t idx = ((size_t)tile * U + uu) * 256 + tid;
+        if (idx >= 2 * SS) return;
+        const int yp = (int)(idx & (S / 2 - 1)) * 2;
+        const unsigned row = (unsigned)(idx >> (N - 1));
+        const int q = row >> N;
+        const unsigned r = row & (S - 1);
+        const int c = r >> m, jj = r & ((1 << m) - 1);
+        const int ii = jj >> 1, up = jj & 1;
+        const float *dRq = a.dR + q * SS;
+        float2 f0[3], g[3], g2[3];
+        float2 t = make_float2(0.f, 0.f), t2 = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            f0[ch] = *reinterpret_cast<const float2 *>(dRq + ch * plane +
+                                                       ((size_t)(((2 * c) << n) | ii)) * S + yp);
+            g[ch] = g2[ch] = make_float2(0.f, 0.f);
+        }
+        if (c >= 1) {
+            // odd column 2c-1 (far end of Eq. 14) at row y = y' - (2e - 2^n)
+            const int e = ii + up, x = 2 * c - 1;
+            const int y = yp - (2 * e - (1 << n));  // odd when n = 0
+            const size_t grow = ((size_t)((x << n) | ii)) * S;
+            const TS *trow = reinterpret_cast<const TS *>(a.Tn) + q * a.en +
+                             ((size_t)x * ((1 << n) + 1) + e) * S;
+            if (n > 0) {
+                const bool in = (unsigned)y < (unsigned)S;
+                const int yc = in ? y : 0;
+                const float4 ta = ld4(trow + yc), tb = ld4(trow + yc + 1);
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    const float2 gv = *reinterpret_cast<const float2 *>(dRq + ch * plane + grow + yc);
+                    g[ch] = in ? gv : make_float2(0.f, 0.f);
+                }
+                t = in ? make_float2(ta.w, tb.w) : make_float2(0.f, 0.f);
+            } else {
+                const bool in0 = (unsigned)y < (unsigned)S, in1 = (unsigned)(y + 1) < (unsigned)S;
+                const int y0 = in0 ? y : 0, y1 = in1 ? y + 1 : 0;
+                const float ta = ld4(trow + y0).w, tb = ld4(trow + y1).w;
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    const float ga = dRq[ch * plane + grow + y0], gb = dRq[ch * plane + grow + y1];
+                    g[ch] = make_float2(in0 ? ga : 0.f, in1 ? gb : 0.f);
+                }
+                t = make_float2(in0 ? ta : 0.f, in1 ? tb : 0.f);
+            }
+            // even column 2c-2 (far end of Eq. 17) at row y' - (2 e2 - 2^(n+1))
+            const int e2 = 2 * ii + 2 * up, x2 = 2 * c - 2;
+            const int y2 = yp - (2 * e2 - (1 << m));
+            const bool in2 = (unsigned)y2 < (unsigned)S;
+            const int y2c = in2 ? y2 : 0;
+            const TS *t2row = reinterpret_cast<const TS *>(a.Tn1) + q * a.en1 +
+                              ((size_t)(c - 1) * ((1 << m) + 1) + e2) * S;
+            const float4 t2a = ld4(t2row + y2c), t2b = ld4(t2row + y2c + 1);
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                const float2 gv = *reinterpret_cast<const float2 *>(
+                    dRq + ch * plane + ((size_t)((x2 << n) | ii)) * S + y2c);
+                g2[ch] = in2 ? gv : make_float2(0.f, 0.f);
+            }
+            t2 = in2 ? make_float2(t2a.w, t2b.w) : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float acc0 = 0.5f * f0[ch].x, acc1 = 0.5f * f0[ch].y;
+            acc0 = fmaf(g[ch].x, t.x, acc0);
+            acc1 = fmaf(g[ch].y, t.y, acc1);
+            acc0 = fmaf(0.5f * g2[ch].x, t2.x, acc0);
+            acc1 = fmaf(0.5f * g2[ch].y, t2.y, acc1);
+            *reinterpret_cast<float2 *>(a.dRn1 + ch * plane + q * SS + (size_t)r * S + yp) =
+                make_float2(acc0, acc1);
+        }
+    }
+}
+
+// Adjoint of the RGB interval pyramid (gather form, as body_dT): dT_n from the
+// merge down at levels n and n-1 and from the merge up of T_{n+1}, two
+// consecutive y per thread, every operand loaded before the terms are added.
+template <typename TS>
+__device__ void body_dT_rgb(const DTArgs &a, unsigned tile, int U, int tid) {
+    const int N = a.N, S = 1 << N, n = a.n;
+    const size_t SS = (size_t)S * S, plane = 4 * SS;
+    const int dirs = (1 << n) + 1;
+    const unsigned rpq = (unsigned)(S >> n) * dirs;
+    const size_t total = (size_t)4 * rpq * (S / 2);
+    for (int uu = 0; uu < U; ++uu) {
+        const size_t idx = ((size_t)tile * U + uu) * 256 + tid;
+        if (idx >= total) return;
+        const int y = (int)(idx & (S / 2 - 1)) * 2;
+        const unsigned row = (unsigned)(idx >> (N - 1));
+        const int q = row / rpq;
+        const unsigned r = row % rpq;
+        const int x = r / dirs, k = r % dirs;
+        // (a) merge down at level n, odd x (Eq. 14)
+        float2 ag[2][3], ar[2][3];
+        float aA[2] = {0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) ag[i][ch] = ar[i][ch] = make_float2(0.f, 0.f);
+        if (n < N && (x & 1)) {
+            const int c = (x + 1) >> 1, yf = y + 2 * k - (1 << n);
+            const bool rin = n + 1 < N && c < (S >> (n + 1));
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int ii = k - 1 + i, jj = 2 * k - 1 + i;
+                if (ii < 0 || ii >= (1 << n)) continue;
+                aA[i] = c_cone[(1 << (n + 1)) - 1 + jj];
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    ag[i][ch] = *reinterpret_cast<const float2 *>(
+                        a.dRn + ch * plane + q * SS + ((size_t)((x << n) | ii)) * S + y);
+                    ar[i][ch] = ld2_r(rin, a.Rn1 + ch * plane + q * SS +
+                                               ((size_t)((c << (n + 1)) | jj)) * S,
+                                      yf, S, n > 0, 0.f);
+                }
+            }
+        }
+        // (b) merge down at level n-1, even column 2x (Eq. 17)
+        float2 bg[2][3], br[2][3];
+        float bA[2] = {0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) bg[i][ch] = br[i][ch] = make_float2(0.f, 0.f);
+        if (n >= 1 && (k & 1) == 0) {
+            const int nm = n - 1, yf = y + 2 * k - (1 << n), xm = 2 * x;
+            const bool rin = n < N && x + 1 < (S >> n);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int jj = k - 1 + i;
+                if (jj < 0 || jj >= (1 << n)) continue;
+                bA[i] = c_cone[(1 << n) - 1 + jj];
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    bg[i][ch] = *reinterpret_cast<const float2 *>(
+                        a.dRm + ch * plane + q * SS + ((size_t)((xm << nm) | (k / 2 - 1 + i))) * S + y);
+                    br[i][ch] = ld2_r(rin, a.Rn + ch * plane + q * SS +
+                                               ((size_t)(((x + 1) << n) | jj)) * S,
+                                      yf, S, true, 0.f);
+                }
+            }
+        }
+        // (c) merge up of T_{n+1} from T_n (Eq. 18-20, n >= 2: even shifts)
+        float4 cg[3][2], cf[3][2];
+        float cw[3] = {0.f, 0.f, 0.f};
+        const bool near_role = (x & 1) == 0;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            cg[v][0] = cg[v][1] = make_float4(0.f, 0.f, 0.f, 0.f);
+            cf[v][0] = cf[v][1] = empty_interval<float4>();
+        }
+        if (a.has_up) {
+            const int H = 1 << n, odirs = 2 * H + 1;
+            const TS *Tq = reinterpret_cast<const TS *>(a.Tn) + q * a.en;
+            const float4 *g0 = reinterpret_cast<const float4 *>(a.dTn1) + q * a.en1 +
+                               (size_t)(x >> 1) * odirs * S;
+            const TS *part = Tq + (size_t)(near_role ? x + 1 : x - 1) * dirs * S;
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                const int ko = v == 0 ? 2 * k : (v == 1 ? 2 * k + 1 : 2 * k - 1);
+                const int kp = v == 0 ? k : (v == 1 ? k + 1 : k - 1);
+                if (ko < 0 || ko > 2 * H) continue;
+                cw[v] = v == 0 ? 1.f : 0.5f;
+                if (near_role) {
+                    far_pair_rgb(part + (size_t)kp * S, y + 2 * k - H, S, cf[v][0], cf[v][1]);
+                    cg[v][0] = g0[(size_t)ko * S + y];
+                    cg[v][1] = g0[(size_t)ko * S + y + 1];
+                } else {
+                    const int yo = y - (2 * kp - H);
+                    const bool in = (unsigned)yo < (unsigned)S;
+                    const int yc = in ? yo : 0;
+                    const float4 t0 = ld4(part + (size_t)kp * S + yc), t1 = ld4(part + (size_t)kp * S + yc + 1);
+                    const float4 h0 = g0[(size_t)ko * S + yc], h1 = g0[(size_t)ko * S + yc + 1];
+                    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+                    cf[v][0] = in ? t0 : z;
+                    cf[v][1] = in ? t1 : z;
+                    cg[v][0] = in ? h0 : z;
+                    cg[v][1] = in ? h1 : z;
+                }
+            }
+        }
+        float gl[3][2] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+        float gt[2] = {0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                gl[ch][0] = fmaf(ag[i][ch].x, aA[i], gl[ch][0]);
+                gl[ch][1] = fmaf(ag[i][ch].y, aA[i], gl[ch][1]);
+                gt[0] = fmaf(ag[i][ch].x, ar[i][ch].x, gt[0]);
+                gt[1] = fmaf(ag[i][ch].y, ar[i][ch].y, gt[1]);
+            }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                const float g0x = 0.5f * bg[i][ch].x, g0y = 0.5f * bg[i][ch].y;
+                gl[ch][0] = fmaf(g0x, bA[i], gl[ch][0]);
+                gl[ch][1] = fmaf(g0y, bA[i], gl[ch][1]);
+                gt[0] = fmaf(g0x, br[i][ch].x, gt[0]);
+                gt[1] = fmaf(g0y, br[i][ch].y, gt[1]);
+            }
+        if (near_role) {
+#pragma unroll
+            for (int v = 0; v < 3; ++v)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const float4 g = cg[v][j], f = cf[v][j];
+                    gl[0][j] = fmaf(cw[v], g.x, gl[0][j]);
+                    gl[1][j] = fmaf(cw[v], g.y, gl[1][j]);
+                    gl[2][j] = fmaf(cw[v], g.z, gl[2][j]);
+                    gt[j] = fmaf(cw[v], fmaf(g.x, f.x, fmaf(g.y, f.y, fmaf(g.z, f.z, g.w * f.w))), gt[j]);
+                }
+        } else {
+#pragma unroll
+            for (int v = 0; v < 3; ++v)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const float4 g = cg[v][j], tn = cf[v][j];
+                    gl[0][j] = fmaf(cw[v] * g.x, tn.w, gl[0][j]);
+                    gl[1][j] = fmaf(cw[v] * g.y, tn.w, gl[1][j]);
+                    gl[2][j] = fmaf(cw[v] * g.z, tn.w, gl[2][j]);
+                    gt[j] = fmaf(cw[v] * g.w, tn.w, gt[j]);
+                }
+        }
+        float4 *out = reinterpret_cast<float4 *>(a.dT) + q * a.en + (size_t)r * S + y;
+        out[0] = make_float4(gl[0][0], gl[1][0], gl[2][0], gt[0]);
+        out[1] = make_float4(gl[0][1], gl[1][1], gl[2][1], gt[1]);
+    }
+}
+
+// Adjoint of the RGB traced levels (as body_seed_adj): each pixel sums, per
+// half length, dLoss/dL_j of every channel and dLoss/dT_j over the pieces of
+// every ray that cross it, then applies its cell derivatives once.
+constexpr int kSeedAdjRgbLds = 3 * kAdjSpan * kAdjPitch * 16;
+static_assert(12 * kAccPlane * 4 <= kSeedAdjRgbLds, "partial sums fit over the interval tile");
+
+struct AdjSumsRgb {
+    float dl[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};  // [half length][channel]
+    float dt[3] = {0.f, 0.f, 0.f};
+    template <int L>
+    __device__ __forceinline__ void add(float d0, float d1, float d2, float t) {
+        dl[L][0] += d0;
+        dl[L][1] += d1;
+        dl[L][2] += d2;
+        dt[L] += t;
+    }
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t dT_resource_rgb(const float2 *p, size_t entries) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float2 *>(p), (short)0,
+                                             (int)(entries * sizeof(float4)), (int)kBufferWord3);
+}
+
+template <int Q, int n, int rho, int k>
+__device__ __forceinline__ void seed_adj_dir_rgb(__amdgpu_buffer_rsrc_t dTq, int S, int un, int w,
+                                                 int lane_off, const float4 *ivp, AdjSumsRgb &sum) {
+    constexpr int dirs = (1 << n) + 1, pieces = 2 << n;
+    constexpr int L = piece_len(n, k);
+    constexpr int plane = kAdjSpan * kAdjPitch;
+    float4 g[2];
+#pragma unroll
+    for (int which = 0; which < 2; ++which) {
+        const int j = adj_piece(n, rho, which);
+        const int cj = (piece_du(j) - (rho & ((1 << n) - 1))) >> n;
+        const int dwj = piece_dw(n, k, j);
+        const int pw = w - dwj;
+        const bool ok = un >= cj && (unsigned)pw < (unsigned)S;
+        const unsigned off =
+            ok ? (unsigned)(lane_off + ((k - cj * dirs) * S - dwj) * (int)sizeof(float4)) : kOutside;
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(dTq, off, 0, 0);
+        g[which] = make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]),
+                               __uint_as_float(v[3]));
+    }
+#pragma unroll
+    for (int which = 0; which < 2; ++which) {
+        const int j = adj_piece(n, rho, which);
+        float pre = 1.f;
+        float4 suf = empty_interval<float4>();
+#pragma unroll
+        for (int i = pieces - 1; i >= 0; --i) {
+            if (i == j) continue;
+            const float4 c = ivp[L * plane + adj_lds_off<Q>(piece_du(i) - piece_du(j),
+                                                             piece_dw(n, k, i) - piece_dw(n, k, j))];
+            if (i > j) suf = merge(c, suf);
+            else pre *= c.w;
+        }
+        const float4 gg = g[which];
+        sum.add<L>(gg.x * pre, gg.y * pre, gg.z * pre,
+                   pre * fmaf(gg.x, suf.x, fmaf(gg.y, suf.y, fmaf(gg.z, suf.z, gg.w * suf.w))));
+    }
+}
+
+template <int Q, int n, int rho>
+__device__ __forceinline__ void seed_adj_level_rgb(__amdgpu_buffer_rsrc_t dTq, int S, int u, int w,
+                                                   const float4 *ivp, AdjSumsRgb &sum) {
+    constexpr int dirs = (1 << n) + 1;
+    const int un = u >> n;
+    const int lane_off = (un * dirs * S + w) * (int)sizeof(float4);
+    seed_adj_dir_rgb<Q, n, rho, 0>(dTq, S, un, w, lane_off, ivp, sum);
+    seed_adj_dir_rgb<Q, n, rho, (1 << n)>(dTq, S, un, w, lane_off, ivp, sum);
+    if constexpr (n >= 1) seed_adj_dir_rgb<Q, n, rho, (1 << n) / 2>(dTq, S, un, w, lane_off, ivp, sum);
+    if constexpr (n == 2) {
+        seed_adj_dir_rgb<Q, n, rho, 1>(dTq, S, un, w, lane_off, ivp, sum);
+        seed_adj_dir_rgb<Q, n, rho, 3>(dTq, S, un, w, lane_off, ivp, sum);
+    }
+}
+
+template <int Q, int rho>
+__device__ __forceinline__ void seed_adj_levels_rgb(const SeedAdjArgs &a, int u, int w,
+                                                    const float4 *ivp, AdjSumsRgb &sum) {
+    const int S = 1 << a.N;
+    // RGB levels hold 16-byte entries: quadrant Q starts Q e_n entries in
+    seed_adj_level_rgb<Q, 0, 0>(dT_resource_rgb(a.dT0 + (size_t)Q * a.e0 * 2, a.e0), S, u, w, ivp, sum);
+    seed_adj_level_rgb<Q, 1, rho & 1>(dT_resource_rgb(a.dT1 + (size_t)Q * a.e1 * 2, a.e1), S, u, w, ivp, sum);
+    seed_adj_level_rgb<Q, 2, rho>(dT_resource_rgb(a.dT2 + (size_t)Q * a.e2 * 2, a.e2), S, u, w, ivp, sum);
+}
+
+template <int Q>
+__device__ __forceinline__ void seed_adj_quadrant_rgb(const SeedAdjArgs &a, int v, int r, int c,
+                                                      const float4 *ivp, AdjSumsRgb &sum) {
+    const int S = 1 << a.N;
+    const int u = Q == 0 ? c : Q == 1 ? S - 1 - c : Q == 2 ? r : S - 1 - r;
+    const int w = Q < 2 ? r : c;
+    switch ((Q == 0 || Q == 2) ? v : 3 - v) {
+        case 0: seed_adj_levels_rgb<Q, 0>(a, u, w, ivp, sum); break;
+        case 1: seed_adj_levels_rgb<Q, 1>(a, u, w, ivp, sum); break;
+        case 2: seed_adj_levels_rgb<Q, 2>(a, u, w, ivp, sum); break;
+        default: seed_adj_levels_rgb<Q, 3>(a, u, w, ivp, sum); break;
+    }
+}
+
+__device__ __forceinline__ void body_seed_adj_rgb(const SeedAdjArgs &a, unsigned tile, char *lds,
+                                                  int tid) {
+    constexpr int P = kAdjPitch, plane = kAdjSpan * kAdjPitch, H = kAdjHalo;
+    float4 *iv = reinterpret_cast<float4 *>(lds);
+    const int S = 1 << a.N;
+    const size_t SS = (size_t)S * S;
+    const int tiles = (S + kAdjTile - 1) / kAdjTile;
+    const int r0 = (int)(tile / tiles) * kAdjTile, c0 = (int)(tile % tiles) * kAdjTile;
+    for (int i = tid; i < kAdjSpan * kAdjSpan; i += 256) {
+        const int lr = i / kAdjSpan, lc = i % kAdjSpan;
+        const int r = r0 - H + lr, c = c0 - H + lc;
+        float e0 = 0.f, e1 = 0.f, e2 = 0.f, g = 0.f;
+        if (r >= 0 && r < S && c >= 0 && c < S) {
+            const size_t o = (size_t)r * S + c;
+            e0 = a.eps[o];
+            e1 = a.eps[SS + o];
+            e2 = a.eps[2 * SS + o];
+            g = a.sig[o];
+        }
+        const int l = lr * P + lc;
+        iv[l] = cell_interval_rgb(e0, e1, e2, g, 0.5f);
+        iv[plane + l] = cell_interval_rgb(e0, e1, e2, g, kH2);
+        iv[2 * plane + l] = cell_interval_rgb(e0, e1, e2, g, kQ5);
+    }
+    __syncthreads();
+    const int v = tid >> 6, lane = tid & 63;
+    const int i4 = v + 4 * (lane >> 4), i16 = lane & 15;
+    AdjSumsRgb sa;
+    if (r0 + i16 < S && c0 + i4 < S) {
+        const float4 *ivp = iv + i16 * P + i4;
+        seed_adj_quadrant_rgb<0>(a, v, r0 + i16, c0 + i4, ivp, sa);
+        seed_adj_quadrant_rgb<1>(a, v, r0 + i16, c0 + i4, ivp, sa);
+    }
+    const int r = r0 + i4, c = c0 + i16;
+    const bool in = r < S && c < S;
+    AdjSumsRgb sb;
+    if (in) {
+        const float4 *ivp = iv + i4 * P + i16;
+        seed_adj_quadrant_rgb<2>(a, v, r, c, ivp, sb);
+        seed_adj_quadrant_rgb<3>(a, v, r, c, ivp, sb);
+    }
+    __syncthreads();
+    float *x = reinterpret_cast<float *>(lds);  // [12][16][kAccPitch]
+    const int la = i16 * kAccPitch + i4;
+#pragma unroll
+    for (int L = 0; L < 3; ++L) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) x[(L * 3 + ch) * kAccPlane + la] = sa.dl[L][ch];
+        x[(9 + L) * kAccPlane + la] = sa.dt[L];
+    }
+    __syncthreads();
+    if (in) {
+        const int lb = i4 * kAccPitch + i16;
+        float dl[3][3], dt[3];
+#pragma unroll
+        for (int L = 0; L < 3; ++L) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) dl[L][ch] = x[(L * 3 + ch) * kAccPlane + lb] + sb.dl[L][ch];
+            dt[L] = x[(9 + L) * kAccPlane + lb] + sb.dt[L];
+        }
+        const size_t o = (size_t)r * S + c;
+        const float s = a.sig[o];
+        float ds = 0.f;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const CellDer d(a.eps[ch * SS + o], s);
+            a.dE[ch * SS + o] = fmaf(dl[2][ch], d.le2, fmaf(dl[1][ch], d.le1, dl[0][ch] * d.le0));
+            if (ch == 0) ds = fmaf(dt[2], d.ts2, fmaf(dt[1], d.ts1, dt[0] * d.ts0));
+            ds = fmaf(dl[2][ch], d.ls2, fmaf(dl[1][ch], d.ls1, fmaf(dl[0][ch], d.ls0, ds)));
+        }
+        a.dS[o] = ds;
+    }
+    __syncthreads();
+}
+
 // The persistent kernel's one LDS buffer: the largest body it runs (the traced
 // levels and the tail run there on 16x16 tiles).
 constexpr int kMaxLds2 = kSeedAdjLds > SeedTile<16>::lds ? kSeedAdjLds : SeedTile<16>::lds;
@@ -1915,6 +2347,16 @@ __global__ __launch_bounds__(256) void hrc_merge_down_rgb_f16(Phase p) {
 __global__ __launch_bounds__(256) void hrc_tail_rgb(Phase p) {
     __shared__ __align__(16) char lds[TailTileRgb<16>::lds];
     body_tail_rgb<16>(p.a.tail, xcd_tile(blockIdx.x, gridDim.x), lds, ltid());
+}
+__global__ __launch_bounds__(256) void hrc_merge_down_adj_rgb(Phase p) {
+    body_merge_down_adj_rgb<float4>(p.a.da, xcd_tile_blk(blockIdx.x, gridDim.x, p.xblk), p.U, ltid());
+}
+__global__ __launch_bounds__(256) void hrc_interval_adj_rgb(Phase p) {
+    body_dT_rgb<float4>(p.a.dt, xcd_tile_blk(blockIdx.x, gridDim.x, p.xblk), p.U, ltid());
+}
+__global__ __launch_bounds__(256) void hrc_seed_adj_rgb(Phase p) {
+    __shared__ __align__(16) char lds[kSeedAdjRgbLds];
+    body_seed_adj_rgb(p.a.sa, xcd_tile(blockIdx.x, gridDim.x), lds, ltid());
 }
 __global__ __launch_bounds__(256) void hrc_gather_adj(Phase p) {
     __shared__ __align__(16) char lds[kGatherAdjLds];
@@ -2162,6 +2604,9 @@ unsigned phase_tiles(const Phase &p) {
             case PH_UP_RGB: return p.a.up.N;
             case PH_DOWN_RGB: return p.a.down.N;
             case PH_TAIL_RGB: return p.a.tail.N;
+            case PH_DOWN_ADJ_RGB: return p.a.da.N;
+            case PH_DT_RGB: return p.a.dt.N;
+            case PH_SEED_ADJ_RGB: return p.a.sa.N;
         }
         return 0;
     }();
@@ -2180,12 +2625,15 @@ unsigned phase_tiles(const Phase &p) {
         }
         case PH_UP:  // pairs of y per thread: one, two with 16-bit intervals
             return cdiv((size_t)p.a.up.nq * t_level_entries(N, p.a.up.n) / (p.a.up.half ? 4 : 2), per);
-        case PH_DT: return cdiv(4 * t_level_entries(N, p.a.dt.n) / 2, per);
+        case PH_DT:
+        case PH_DT_RGB: return cdiv(4 * t_level_entries(N, p.a.dt.n) / 2, per);
         case PH_DOWN: return cdiv((size_t)p.a.down.nq * SS / (p.a.down.half ? 4 : 2), per);
-        case PH_DOWN_ADJ: return cdiv(4 * SS / 2, per);
+        case PH_DOWN_ADJ:
+        case PH_DOWN_ADJ_RGB: return cdiv(4 * SS / 2, per);
         case PH_BLUR:
         case PH_BLUR_ADJ:
         case PH_SEED_ADJ:
+        case PH_SEED_ADJ_RGB:
         case PH_SEED_RGB:
         case PH_TAIL_RGB: {
             const unsigned t16 = (unsigned)((S + 15) / 16);
@@ -2220,6 +2668,9 @@ hipError_t launch_phase(const Phase &p, hipStream_t s, hipEvent_t start, hipEven
         case PH_UP_RGB: k = p.a.up.half ? hrc_merge_up_rgb_f16 : hrc_merge_up_rgb; break;
         case PH_DOWN_RGB: k = p.a.down.half ? hrc_merge_down_rgb_f16 : hrc_merge_down_rgb; break;
         case PH_TAIL_RGB: k = hrc_tail_rgb; break;
+        case PH_DOWN_ADJ_RGB: k = hrc_merge_down_adj_rgb; break;
+        case PH_DT_RGB: k = hrc_interval_adj_rgb; break;
+        case PH_SEED_ADJ_RGB: k = hrc_seed_adj_rgb; break;
         default: return hipErrorInvalidValue;
     }
     if (start || stop)
@@ -2287,14 +2738,6 @@ __global__ __launch_bounds__(256) void hrc_scatter_adj(const float *dE, const fl
     }
 }
 
-// out = (a + b) + c elementwise (out may be a): the RGB reverse's sum of the
-// three channels' dLoss/d sigma, in channel order.
-__global__ __launch_bounds__(256) void hrc_add3(const float *a, const float *b, const float *c,
-                                                float *out, size_t n) {
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
-        out[i] = (a[i] + b[i]) + c[i];
-}
-
 static unsigned elementwise_blocks(size_t n) {
     size_t b = (n + 255) / 256;
     return (unsigned)(b > 8192 ? 8192 : b);
@@ -2312,12 +2755,6 @@ hipError_t launch_scatter_adj(const float *dE, const float *dS, const float *F_p
                               float *d_sig, float *d_alb, size_t n, int assign, hipStream_t s) {
     hipLaunchKernelGGL(hrc_scatter_adj, dim3(elementwise_blocks(n)), dim3(256), 0, s, dE, dS,
                        F_prev, sig, alb, g, d_eps, d_sig, d_alb, n, assign);
-    return hipGetLastError();
-}
-
-hipError_t launch_add3(const float *a, const float *b, const float *c, float *out, size_t n,
-                       hipStream_t s) {
-    hipLaunchKernelGGL(hrc_add3, dim3(elementwise_blocks(n)), dim3(256), 0, s, a, b, c, out, n);
     return hipGetLastError();
 }
 

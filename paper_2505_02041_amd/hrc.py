@@ -188,6 +188,19 @@ class Context:
 
 
     # -- three radiance channels over one medium ----------------------------
+    def _rgb_sizes(self, N: int, flags: int = 0) -> Tuple[int, int]:
+        f, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        check(_lib.load().hrc_workspace_bytes_rgb(N, flags, ctypes.byref(f), ctypes.byref(b)),
+              "hrc_workspace_bytes_rgb")
+        return f.value, b.value
+
+    def reserve_rgb(self, N: int) -> torch.Tensor:
+        """A fresh workspace of the RGB reverse's size: the reserve space that
+        hrc_forward_rgb with ``HRC_FLAG_KEEP_PYRAMID`` fills and hrc_backward_rgb
+        with ``HRC_FLAG_REUSE_PYRAMID`` reads."""
+        return torch.empty(self._rgb_sizes(N)[1], dtype=torch.uint8,
+                           device=torch.device("cuda", self.device))
+
     def _rgb_workspace(self, N: int, backward: bool, flags: int = 0) -> torch.Tensor:
         half = 0 if backward else flags & _lib.HRC_FLAG_HALF_INTERVALS
         key = ("rgb", N, backward, half, self._stream_key())
@@ -211,15 +224,22 @@ class Context:
         return N
 
     def hrc_forward_rgb(self, emission: torch.Tensor, sigma_t: torch.Tensor,
-                        out: Optional[torch.Tensor] = None, flags: int = 0) -> torch.Tensor:
-        """Fluence of the three channels of emission [3, S, S] over one sigma_t [S, S]."""
+                        out: Optional[torch.Tensor] = None, flags: int = 0,
+                        reserve: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Fluence of the three channels of emission [3, S, S] over one sigma_t [S, S];
+        with ``HRC_FLAG_KEEP_PYRAMID``, ``reserve`` (``reserve_rgb()``) is the workspace."""
         _check_field(emission, "emission")
         _check_field(sigma_t, "sigma_t")
         N = self._rgb_shapes(emission, sigma_t)
         if out is None:
             out = torch.empty_like(emission)
         _check_like(emission, out=out)
-        ws = self._rgb_workspace(N, False, flags)
+        if flags & _lib.HRC_FLAG_KEEP_PYRAMID:
+            if reserve is None:
+                raise ValueError("HRC_FLAG_KEEP_PYRAMID needs a reserve tensor")
+            ws = self._workspace_arg(reserve)
+        else:
+            ws = self._rgb_workspace(N, False, flags)
         check(_lib.load().hrc_forward_rgb(self._ptr, N, emission.data_ptr(), sigma_t.data_ptr(),
                                           out.data_ptr(), ws.data_ptr(), ws.numel(),
                                           _stream_handle(emission.device), flags),
@@ -227,14 +247,21 @@ class Context:
         return out
 
     def hrc_backward_rgb(self, emission: torch.Tensor, sigma_t: torch.Tensor,
-                         grad_fluence: torch.Tensor, flags: int = 0):
+                         grad_fluence: torch.Tensor, flags: int = 0,
+                         reserve: Optional[torch.Tensor] = None):
+        """With ``HRC_FLAG_REUSE_PYRAMID``, ``reserve`` is the kept RGB forward's workspace."""
         for t, n in ((emission, "emission"), (sigma_t, "sigma_t"), (grad_fluence, "grad_fluence")):
             _check_field(t, n)
         N = self._rgb_shapes(emission, sigma_t)
         _check_like(emission, grad_fluence=grad_fluence)
         ge = torch.empty_like(emission)
         gs = torch.empty_like(sigma_t)
-        ws = self._rgb_workspace(N, True)
+        if flags & _lib.HRC_FLAG_REUSE_PYRAMID:
+            if reserve is None:
+                raise ValueError("HRC_FLAG_REUSE_PYRAMID needs the kept forward's reserve tensor")
+            ws = self._workspace_arg(reserve)
+        else:
+            ws = self._rgb_workspace(N, True)
         check(_lib.load().hrc_backward_rgb(self._ptr, N, emission.data_ptr(), sigma_t.data_ptr(),
                                            grad_fluence.data_ptr(), ge.data_ptr(), gs.data_ptr(),
                                            ws.data_ptr(), ws.numel(),
@@ -380,29 +407,43 @@ def fluence(emission: torch.Tensor, sigma_t: torch.Tensor, blur: bool = False,
 
 class RGBFunction(torch.autograd.Function):
     """F[3, S, S] = HRC of three emission channels over one sigma_t, with the
-    hand-written reverse (``hrc_backward_rgb``) as backward."""
+    hand-written RGB reverse (``hrc_backward_rgb``) as backward; as for
+    ``HRCFunction``, the forward keeps what the reverse reads in a reserve
+    tensor when a gradient is needed (``keep=False``: the reverse recomputes)."""
 
     @staticmethod
-    def forward(ctx, emission, sigma_t, blur=False):
+    def forward(ctx, emission, sigma_t, blur=False, keep=True):
         emission = emission.contiguous()
         sigma_t = sigma_t.contiguous()
         c = default_context(emission.device.index)
         ctx.flags = _lib.HRC_FLAG_BLUR if blur else 0
+        ctx.reserve = None
         ctx.save_for_backward(emission, sigma_t)
+        if keep and (ctx.needs_input_grad[0] or ctx.needs_input_grad[1]):
+            ctx.reserve = c.reserve_rgb(_log2_size(sigma_t))
+            return c.hrc_forward_rgb(emission, sigma_t,
+                                     flags=ctx.flags | _lib.HRC_FLAG_KEEP_PYRAMID,
+                                     reserve=ctx.reserve)
         return c.hrc_forward_rgb(emission, sigma_t, flags=ctx.flags)
 
     @staticmethod
     def backward(ctx, grad_F):
         emission, sigma_t = ctx.saved_tensors
         c = default_context(emission.device.index)
-        ge, gs = c.hrc_backward_rgb(emission, sigma_t, grad_F.contiguous(), flags=ctx.flags)
-        return ge, gs, None
+        if ctx.reserve is not None:
+            ge, gs = c.hrc_backward_rgb(emission, sigma_t, grad_F.contiguous(),
+                                        flags=ctx.flags | _lib.HRC_FLAG_REUSE_PYRAMID,
+                                        reserve=ctx.reserve)
+        else:
+            ge, gs = c.hrc_backward_rgb(emission, sigma_t, grad_F.contiguous(), flags=ctx.flags)
+        return ge, gs, None, None
 
 
-def fluence_rgb(emission: torch.Tensor, sigma_t: torch.Tensor, blur: bool = False) -> torch.Tensor:
+def fluence_rgb(emission: torch.Tensor, sigma_t: torch.Tensor, blur: bool = False,
+                keep: bool = True) -> torch.Tensor:
     """Fluence [3, S, S] of three emission channels [3, S, S] over one attenuation
     sigma_t [S, S] (differentiable in both)."""
-    return RGBFunction.apply(emission, sigma_t, blur)
+    return RGBFunction.apply(emission, sigma_t, blur, keep)
 
 
 class MultibounceFunction(torch.autograd.Function):

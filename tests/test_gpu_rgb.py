@@ -1,7 +1,8 @@
 """GPU parity of the RGB solve (hrc_forward_rgb / hrc_backward_rgb: three
-emission channels over one attenuation, sharing every transmittance) through
-the C ABI: each channel bitwise equal to the one-channel calls, against three
-oracle solves up to the 1024x1024 benchmark scene, and through autograd."""
+emission channels over one attenuation, sharing every transmittance and its
+adjoint) through the C ABI: each channel's fluence and d emission bitwise equal
+to the one-channel calls, d sigma against the sum of three oracle reverses, up
+to the 1024x1024 benchmark scene, the reserve-space pair, and autograd."""
 import numpy as np
 import pytest
 import torch
@@ -72,8 +73,10 @@ def test_rgb_forward_benchmark_scene_matches_oracle(ctx):
 
 @pytest.mark.parametrize("S,flags", [(8, 0), (64, 0), (256, 0), (64, 0x2)])
 def test_rgb_backward(ctx, S, flags):
-    """d emission per channel bitwise equal to the one-channel reverse, d sigma
-    the channels' sum in channel order, both against the oracle's reverse."""
+    """d emission per channel bitwise equal to the one-channel reverse (its
+    radiance adjoints never meet the transmittance adjoints); d sigma, which the
+    RGB reverse gathers over the channels inside, close to the sum of the three
+    one-channel d sigma; both against the oracle's reverse."""
     log(f"rgb backward S={S} flags {flags:#x}")
     eps, sig = _rgb_scene(S, 30 + S)
     dF = np.random.default_rng(S).normal(size=(3, S, S)).astype(np.float32)
@@ -83,7 +86,8 @@ def test_rgb_backward(ctx, S, flags):
              for c in range(3)]
     for c in range(3):
         assert torch.equal(ge[c], parts[c][0]), c
-    assert torch.equal(gs, (parts[0][1] + parts[1][1]) + parts[2][1])
+    assert_grad_close(gs.cpu().numpy(), ((parts[0][1] + parts[1][1]) + parts[2][1]).cpu().numpy(),
+                      f"rgb d sigma vs three one-channel reverses S={S}")
     ge, gs = ge.cpu().numpy(), gs.cpu().numpy()
     rs = np.zeros((S, S))
     for c in range(3):
@@ -94,17 +98,64 @@ def test_rgb_backward(ctx, S, flags):
     assert_grad_close(gs, rs, f"rgb d sigma S={S}")
 
 
+def test_rgb_backward_benchmark_scene(ctx):
+    """The 1024x1024 benchmark scene's medium with three emission channels:
+    d emission per channel bitwise equal to the one-channel reverse and, like
+    d sigma, within the gradient tolerance of three oracle reverses."""
+    log("rgb backward 1024 vs oracle reverse")
+    sc = config3()
+    eps = np.stack([sc.eps, np.roll(sc.eps, 37, axis=1), 0.3 * sc.eps]).astype(np.float32)
+    dF = np.random.default_rng(11).normal(size=(3, 1024, 1024)).astype(np.float32)
+    e, s, g = to_dev(eps), to_dev(sc.sigma), to_dev(dF)
+    ge, gs = ctx.hrc_backward_rgb(e, s, g)
+    for c in range(3):
+        gc = ctx.hrc_backward(e[c].contiguous(), s, g[c].contiguous())[0]
+        assert torch.equal(ge[c], gc), c
+    torch.cuda.synchronize()
+    ge, gs = ge.cpu().numpy(), gs.cpu().numpy()
+    ctx.release_workspaces()
+    rs = np.zeros((1024, 1024))
+    for c in range(3):
+        re, rsc = hrc_vjp.fluence_vjp(eps[c], sc.sigma, dF[c])
+        assert_grad_close(ge[c], re, f"rgb 1024 d eps channel {c}")
+        rs += rsc
+    assert_grad_close(gs, rs, "rgb 1024 d sigma")
+
+
+@pytest.mark.parametrize("S,flags", [(8, 0), (64, 0x2), (256, 0), (1024, 0)])
+def test_rgb_kept_forward_and_reused_backward(ctx, S, flags):
+    """The reserve-space pair for RGB: the kept forward's fluence and the
+    reused reverse's gradients bitwise those of the plain RGB calls, twice."""
+    from paper_2505_02041_amd import _lib
+    log(f"rgb keep/reuse S={S} flags {flags:#x}")
+    eps, sig = _rgb_scene(S, 60 + S)
+    e, s = to_dev(eps), to_dev(sig)
+    res = ctx.reserve_rgb(S.bit_length() - 1)
+    Fk = ctx.hrc_forward_rgb(e, s, flags=flags | _lib.HRC_FLAG_KEEP_PYRAMID, reserve=res)
+    F = ctx.hrc_forward_rgb(e, s, flags=flags)
+    assert torch.equal(Fk, F)
+    for seed in (1, 2):
+        g = to_dev(np.random.default_rng(seed).normal(size=(3, S, S)).astype(np.float32))
+        gk = ctx.hrc_backward_rgb(e, s, g, flags=flags | _lib.HRC_FLAG_REUSE_PYRAMID, reserve=res)
+        gp = ctx.hrc_backward_rgb(e, s, g, flags=flags)
+        assert torch.equal(gk[0], gp[0]) and torch.equal(gk[1], gp[1])
+    del res
+    ctx.release_workspaces()
+
+
 def test_rgb_autograd(ctx):
     from paper_2505_02041_amd import fluence_rgb
     eps, sig = _rgb_scene(32, 40)
     e = to_dev(eps).requires_grad_(True)
     s = to_dev(sig).requires_grad_(True)
-    F = fluence_rgb(e, s)
-    g = torch.randn_like(F)
-    F.backward(g)
-    ge, gs = ctx.hrc_backward_rgb(to_dev(eps), to_dev(sig), g)
-    assert torch.equal(e.grad, ge) and torch.equal(s.grad, gs)
-    assert torch.equal(F.detach(), ctx.hrc_forward_rgb(to_dev(eps), to_dev(sig)))
+    g = torch.randn((3, 32, 32), device="cuda")
+    for keep in (True, False):
+        e.grad = s.grad = None
+        F = fluence_rgb(e, s, keep=keep)
+        F.backward(g)
+        ge, gs = ctx.hrc_backward_rgb(to_dev(eps), to_dev(sig), g)
+        assert torch.equal(e.grad, ge) and torch.equal(s.grad, gs)
+        assert torch.equal(F.detach(), ctx.hrc_forward_rgb(to_dev(eps), to_dev(sig)))
 
 
 @pytest.mark.parametrize("S", [8, 64, 256])
