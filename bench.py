@@ -247,7 +247,26 @@ def main():
     rgb_s = timed(lambda: ctx.hrc_forward_rgb(eps3, sig, F3), args.steps, 3)
     rgb_half_s = timed(lambda: ctx.hrc_forward_rgb(eps3, sig, F3, flags=_lib.HRC_FLAG_HALF_INTERVALS),
                        args.steps, 3)
-    del eps3, F3
+    # the RGB reverse (transmittance adjoints shared by the channels) beside
+    # three one-channel reverses, plain and through the reserve space
+    log("rgb forward+backward")
+    g3 = torch.from_numpy(np.random.default_rng(3).normal(size=(3, S, S)).astype(np.float32)).to(dev)
+    KP, RP = _lib.HRC_FLAG_KEEP_PYRAMID, _lib.HRC_FLAG_REUSE_PYRAMID
+    rb_reps = max(5, args.steps // 5)
+    rgb_bwd_s = timed(lambda: ctx.hrc_backward_rgb(eps3, sig, g3), rb_reps, 2)
+    ch = [(eps3[c].contiguous(), g3[c].contiguous()) for c in range(3)]
+    three_bwd_s = timed(lambda: [ctx.hrc_backward(e_, sig, g_) for e_, g_ in ch], rb_reps, 2)
+    res3 = ctx.reserve_rgb(N)
+    rgb_kept_s = timed(lambda: (ctx.hrc_forward_rgb(eps3, sig, F3, flags=KP, reserve=res3),
+                                ctx.hrc_backward_rgb(eps3, sig, g3, flags=RP, reserve=res3)),
+                       rb_reps, 2)
+    reserve3_bytes = res3.numel()
+    del res3
+    res1 = ctx.reserve(N)
+    three_kept_s = timed(lambda: [(ctx.hrc_forward(e_, sig, F, flags=KP, reserve=res1),
+                                   ctx.hrc_backward(e_, sig, g_, flags=RP, reserve=res1))
+                                  for e_, g_ in ch], rb_reps, 2)
+    del res1, ch, g3, eps3, F3
     ctx.release_workspaces()
     # ---- the allocation-free forward (hrc_forward_static: the library's own
     # device scratch) beside hrc_forward at 512^2, its largest grid -------------
@@ -337,6 +356,14 @@ def main():
                     "one_channel_model_bytes": step_bytes,
                     "model_GBps": forward_bytes_rgb(N) / rgb_s / 1e9,
                     "speedup_vs_three_calls": 3 * fwd_s / rgb_s,
+                    "backward": {"ms": rgb_bwd_s * 1e3, "three_one_channel_ms": three_bwd_s * 1e3,
+                                 "speedup_vs_three": three_bwd_s / rgb_bwd_s,
+                                 "fwd_bwd_kept_ms": rgb_kept_s * 1e3,
+                                 "three_one_channel_fwd_bwd_kept_ms": three_kept_s * 1e3,
+                                 "reserve_GB": reserve3_bytes / 1e9,
+                                 "note": "hrc_backward_rgb (adjoint intervals (dL_r, dL_g, dL_b, dT): "
+                                         "the medium's adjoints shared) beside three hrc_backward calls; "
+                                         "and the reserve-space pairs (kept forward, reused reverse)"},
                     "half_intervals": {"ms": rgb_half_s * 1e3, "ms_per_channel": rgb_half_s * 1e3 / 3,
                                        "model_bytes_per_channel": forward_bytes_rgb(N, 8) / 3,
                                        "model_GBps": forward_bytes_rgb(N, 8) / rgb_half_s / 1e9,
