@@ -29,11 +29,11 @@ def _scene(S, seed):
     return eps, sig, alb
 
 
-@pytest.mark.parametrize("S,K", [(8, 2), (64, 3), (128, 4)])
+@pytest.mark.parametrize("S,K", [(8, 2), (64, 3), (128, 4), (1024, 3)])
 def test_multibounce_forward_matches_oracle(ctx, S, K):
     log(f"multibounce forward S={S} K={K}")
-    if S == 128:
-        sc = scene_like_512(S, 51, 6, 10)
+    if S >= 128:
+        sc = scene_like_512(S, 51, max(6, S // 16), max(10, S // 8))
         eps, sig = sc.eps, sc.sigma
         alb = np.full((S, S), 0.7, np.float32)
     else:
@@ -44,10 +44,15 @@ def test_multibounce_forward_matches_oracle(ctx, S, K):
                          f"bounces S={S} K={K}")
 
 
-@pytest.mark.parametrize("S,K", [(8, 1), (16, 3), (64, 2), (256, 3)])
+@pytest.mark.parametrize("S,K", [(8, 1), (16, 3), (64, 2), (256, 3), (512, 2)])
 def test_multibounce_backward_matches_oracle(ctx, S, K):
     log(f"multibounce backward S={S} K={K}")
-    eps, sig, alb = _scene(S, 100 + S + K)
+    if S == 512:
+        sc = scene_like_512(S, 52, 32, 64)
+        eps, sig = sc.eps, sc.sigma
+        alb = np.random.default_rng(9).uniform(0, 0.9, (S, S)).astype(np.float32)
+    else:
+        eps, sig, alb = _scene(S, 100 + S + K)
     dF = np.random.default_rng(S).normal(size=(S, S)).astype(np.float32)
     ge, gs, ga = ctx.hrc_multibounce_backward(to_dev(eps), to_dev(sig), to_dev(alb), K,
                                               to_dev(dF))
