@@ -390,20 +390,25 @@ size_t hrc_batch_workspace_bytes(const hrc_batch *batch);
 hrc_status hrc_batch_describe(const hrc_batch *batch, int *variant, int *grid,
                               int *target_tiles, int *chunk, int *direct_scenes);
 
-/* The queue layout the autotuner chose: the persistent kernel's queues, 1 if
- * each serves one XCD (0: one queue for the whole device), and the workspace
- * slots per queue (0: one per scene).  Any output pointer may be NULL.  Pure
- * host function; HRC_ERR_INVALID_ARG for a NULL batch. */
-hrc_status hrc_batch_queues(const hrc_batch *batch, int *queues, int *xcd_local, int *slots);
+/* The layout the autotuner chose: the persistent kernel's queues, 1 if each
+ * serves one XCD (0: one queue for the whole device), the workspace slots per
+ * queue (0: one per scene), and the graph branches the scenes that run as
+ * kernels of their own are split over (1, 2 or 4: each branch has a workspace
+ * of its own, and the branches' passes overlap, so that one branch fills the
+ * GPU where another drains and ramps at a kernel boundary).  Any output
+ * pointer may be NULL.  Pure host function; HRC_ERR_INVALID_ARG for a NULL
+ * batch. */
+hrc_status hrc_batch_queues(const hrc_batch *batch, int *queues, int *xcd_local, int *slots,
+                            int *branches);
 
 /* Every candidate the autotuner timed, in the order timed: *count receives
- * their number; for the first min(max, count), desc[7 i .. 7 i + 6] receives
+ * their number; for the first min(max, count), desc[8 i .. 8 i + 7] receives
  * (log2 size from which scenes ran as kernels of their own, 0 for none;
  * queues; 1 if one queue per XCD; workspace slots per queue, 0 for one per
- * scene; kernel variant; target tiles per pass; claim chunk) and ms[i] the
- * whole batch's time in milliseconds.  Pure host function;
- * HRC_ERR_INVALID_ARG for a NULL batch or count, a negative max, or NULL
- * arrays with max > 0. */
+ * scene; kernel variant; target tiles per pass; claim chunk; graph branches of
+ * the direct scenes) and ms[i] the whole batch's time in milliseconds.  Pure
+ * host function; HRC_ERR_INVALID_ARG for a NULL batch or count, a negative
+ * max, or NULL arrays with max > 0. */
 hrc_status hrc_batch_candidates(const hrc_batch *batch, int max, int *count, int *desc,
                                 float *ms);
 

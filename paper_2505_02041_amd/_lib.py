@@ -107,6 +107,7 @@ SIGNATURES = {
     "hrc_batch_debug_waits": (ctypes.c_int, [_vp, ctypes.c_uint]),
     "hrc_batch_queues": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int),
                                         ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_int),
                                         ctypes.POINTER(ctypes.c_int)]),
     "hrc_batch_candidates": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                             ctypes.POINTER(ctypes.c_int),

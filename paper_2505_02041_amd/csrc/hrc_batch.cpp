@@ -35,12 +35,13 @@ struct hrc_batch {
     int queues = 0;                // queues of the persistent kernel
     int xcd_local = 0;             // one queue per XCD
     int slots = 0;                 // workspace slots per queue (0: one per scene)
+    int branches = 1;              // graph branches the direct scenes run in
     std::vector<int> cand_desc;    // every timed candidate: kCandFields ints each
     std::vector<float> cand_ms;    // and its time
 };
 
 // Fields of a timed candidate as hrc_batch_candidates reports them.
-constexpr int kCandFields = 7;
+constexpr int kCandFields = 8;
 
 namespace {
 
@@ -161,7 +162,8 @@ struct Arrangement {
     int slots = 0;                      // workspace slots per queue; 0 = one per scene
     int target = 0;                     // tiles per phase
     int quarters = kMaxQuarters;        // tiles per group (per block of the kernel variant)
-    std::vector<Phase> direct;          // direct scenes' passes in order
+    int branches = 1;                   // graph branches the direct scenes run in
+    std::vector<Phase> direct[kMaxBranches];  // each branch's direct passes, in order
     std::vector<Phase> phases;          // the persistent kernel's passes
     std::vector<unsigned> seg_start;
     std::vector<int> seg_phase, seg_step;
@@ -193,7 +195,7 @@ double scene_cost(const hrc_scene &sc) {
 // Step t of a queue holds, for every scene of the queue in order, its passes
 // of step t.
 void arrange(Arrangement &ar, const hrc_scene *scenes, int count, char *base) {
-    ar.direct.clear();
+    for (auto &d : ar.direct) d.clear();
     ar.phases.clear();
     ar.phase_scene.clear();
     ar.seg_start.clear();
@@ -215,18 +217,36 @@ void arrange(Arrangement &ar, const hrc_scene *scenes, int count, char *base) {
         if (persistent)
             for (Phase &p : out) size_tiles(p, ar.target);
     };
-    // direct scenes, in the caller's order, in one shared workspace
-    size_t direct_bytes = 0;
+    // direct scenes, in the caller's order, in one shared workspace per branch
+    // (with two branches: largest first, each to the lighter branch)
     std::vector<int> pers, direct;
     for (int i = 0; i < count; ++i) {
-        if (scenes[i].log2_size >= ar.min_direct) {
-            direct.push_back(i);
-            direct_bytes = std::max(direct_bytes, align256(lay[i].total));
-        } else {
-            pers.push_back(i);
-        }
+        if (scenes[i].log2_size >= ar.min_direct) direct.push_back(i);
+        else pers.push_back(i);
     }
     ar.n_direct = (int)direct.size();
+    const int nbr = std::max(1, std::min({ar.branches, kMaxBranches, (int)direct.size()}));
+    std::vector<int> branch_of(count, 0);
+    if (nbr > 1) {
+        std::vector<int> order = direct;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return scene_cost(scenes[a]) > scene_cost(scenes[b]);
+        });
+        double load[kMaxBranches] = {};
+        for (int i : order) {
+            const int bb = (int)(std::min_element(load, load + nbr) - load);
+            branch_of[i] = bb;
+            load[bb] += scene_cost(scenes[i]);
+        }
+    }
+    size_t branch_off[kMaxBranches + 1] = {};
+    {
+        size_t branch_bytes[kMaxBranches] = {};
+        for (int i : direct)
+            branch_bytes[branch_of[i]] = std::max(branch_bytes[branch_of[i]], align256(lay[i].total));
+        for (int bb = 0; bb < kMaxBranches; ++bb) branch_off[bb + 1] = branch_off[bb] + branch_bytes[bb];
+    }
+    const size_t direct_bytes = branch_off[kMaxBranches];
     // persistent scenes: largest first, each to the least-loaded queue
     std::stable_sort(pers.begin(), pers.end(), [&](int a, int b) {
         return scene_cost(scenes[a]) > scene_cost(scenes[b]);
@@ -262,8 +282,8 @@ void arrange(Arrangement &ar, const hrc_scene *scenes, int count, char *base) {
     if (!base) return;  // sizes only
     std::vector<Phase> chain;
     for (int i : direct) {
-        solve(i, base, false, chain);
-        ar.direct.insert(ar.direct.end(), chain.begin(), chain.end());
+        solve(i, base + branch_off[branch_of[i]], false, chain);
+        ar.direct[branch_of[i]].insert(ar.direct[branch_of[i]].end(), chain.begin(), chain.end());
     }
     // per queue: each scene's steps, offset past the previous scene of its slot
     int total_steps = 0, seg = 0;
@@ -434,8 +454,25 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
         return HRC_ERR_HIP;
     }
 
-    hipStream_t cap = nullptr;
-    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+    // the capture stream, one more stream per extra graph branch, and the
+    // events that fork the branches from it and join them again
+    hipStream_t cap = nullptr, side[kMaxBranches] = {};
+    hipEvent_t fork = nullptr, join[kMaxBranches] = {};
+    auto free_streams = [&]() {
+        if (cap) (void)hipStreamDestroy(cap);
+        if (fork) (void)hipEventDestroy(fork);
+        for (int i = 1; i < kMaxBranches; ++i) {
+            if (side[i]) (void)hipStreamDestroy(side[i]);
+            if (join[i]) (void)hipEventDestroy(join[i]);
+        }
+    };
+    bool streams_ok = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess &&
+                      hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 1; streams_ok && i < kMaxBranches; ++i)
+        streams_ok = hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking) == hipSuccess &&
+                     hipEventCreateWithFlags(&join[i], hipEventDisableTiming) == hipSuccess;
+    if (!streams_ok) {
+        free_streams();
         free_batch(b);
         return HRC_ERR_HIP;
     }
@@ -485,8 +522,25 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
     };
     // one batch: the direct scenes' passes in order, then the persistent kernel
     auto run = [&]() -> bool {
-        for (const Phase &p : ar.direct)
+        // branches 1.. fork from the stream and join it again before the
+        // persistent kernel; branch 0 runs on the stream itself
+        bool forked = false;
+        for (int i = 1; i < kMaxBranches; ++i) {
+            if (ar.direct[i].empty()) continue;
+            if (!forked && hipEventRecord(fork, cap) != hipSuccess) return false;
+            forked = true;
+            if (hipStreamWaitEvent(side[i], fork, 0) != hipSuccess) return false;
+            for (const Phase &p : ar.direct[i])
+                if (launch_phase(p, side[i]) != hipSuccess) return false;
+        }
+        for (const Phase &p : ar.direct[0])
             if (launch_phase(p, cap) != hipSuccess) return false;
+        for (int i = 1; i < kMaxBranches; ++i) {
+            if (ar.direct[i].empty()) continue;
+            if (hipEventRecord(join[i], side[i]) != hipSuccess ||
+                hipStreamWaitEvent(cap, join[i], 0) != hipSuccess)
+                return false;
+        }
         if (ar.phases.empty()) return true;
         return launch_persistent(tables, b->sched, grids[variant], variant, cap) == hipSuccess;
     };
@@ -501,6 +555,7 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
     struct Cand {
         int min_direct, xcd, slots, variant, mult;
         unsigned chunk;
+        int branches = 1;
     };
     std::vector<int> min_directs{HRC_MAX_LOG2 + 1};  // none direct
     if (!(flags & HRC_FLAG_BATCH_PERSISTENT)) {
@@ -530,6 +585,7 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
         xcd_local = c.xcd > 0;
         ar = Arrangement();
         ar.min_direct = c.min_direct;
+        ar.branches = c.branches;
         ar.nqueues = xcd_local ? c.xcd : 1;
         ar.slots = c.slots;
         ar.quarters = persistent_quarters(variant);
@@ -559,10 +615,11 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
         }
         const int desc[kCandFields] = {c.min_direct <= HRC_MAX_LOG2 ? c.min_direct : 0,
                                        ar.nqueues, xcd_local ? 1 : 0, c.slots, c.variant,
-                                       ar.target, (int)c.chunk};
+                                       ar.target, (int)c.chunk, c.branches};
         b->cand_desc.insert(b->cand_desc.end(), desc, desc + kCandFields);
         b->cand_ms.push_back(ms);
-        if (ms < best_ms) {
+        // more graph branches (a workspace more each) must win by 1%
+        if (c.branches > best.branches ? ms < 0.99f * best_ms : ms < best_ms) {
             best_ms = ms;
             best = c;
         }
@@ -596,6 +653,20 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
                 if (!(mult == stage1.mult && ch == stage1.chunk))
                     time_one(Cand{stage1.min_direct, stage1.xcd, stage1.slots, stage1.variant, mult,
                                   ch});
+    // stage 3: the direct scenes in 2 or 4 graph branches (each with a
+    // workspace of its own), so that one branch's passes fill the GPU where
+    // another's drain and ramp at a kernel boundary
+    {
+        int n_direct = 0;
+        for (int i = 0; i < count; ++i) n_direct += scenes[i].log2_size >= best.min_direct ? 1 : 0;
+        const Cand stage2 = best;
+        for (int br : {2, 4})
+            if (br <= n_direct) {
+                Cand c = stage2;
+                c.branches = br;
+                time_one(c);
+            }
+    }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
 
@@ -603,6 +674,7 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
     if (fine) {
         ar = Arrangement();
         ar.min_direct = best.min_direct;
+        ar.branches = best.branches;
         ar.nqueues = best.xcd > 0 ? best.xcd : 1;
         ar.slots = best.slots;
         ar.quarters = persistent_quarters(best.variant);
@@ -629,6 +701,7 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
     b->queues = ar.nqueues;
     b->xcd_local = best.xcd > 0 ? 1 : 0;
     b->slots = best.slots;
+    b->branches = ar.direct[1].empty() ? 1 : best.branches;
 
     // ---- capture one launch in a graph ---------------------------------
     if (fine) fine = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
@@ -637,7 +710,7 @@ hrc_status hrc_batch_plan(hrc_context *ctx, const hrc_scene *scenes, int count, 
         fine = (hipStreamEndCapture(cap, &b->graph) == hipSuccess) && launched;
     }
     if (fine) fine = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess;
-    (void)hipStreamDestroy(cap);
+    free_streams();
     if (!fine) {
         free_batch(b);
         return timed_out ? HRC_ERR_TIMEOUT : HRC_ERR_HIP;
@@ -697,11 +770,13 @@ hrc_status hrc_batch_describe(const hrc_batch *batch, int *variant, int *grid,
     return HRC_OK;
 }
 
-hrc_status hrc_batch_queues(const hrc_batch *batch, int *queues, int *xcd_local, int *slots) {
+hrc_status hrc_batch_queues(const hrc_batch *batch, int *queues, int *xcd_local, int *slots,
+                            int *branches) {
     if (!batch) return HRC_ERR_INVALID_ARG;
     if (queues) *queues = batch->queues;
     if (xcd_local) *xcd_local = batch->xcd_local;
     if (slots) *slots = batch->slots;
+    if (branches) *branches = batch->branches;
     return HRC_OK;
 }
 

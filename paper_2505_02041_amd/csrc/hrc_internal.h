@@ -217,6 +217,7 @@ hipError_t launch_phase(const Phase &p, hipStream_t s, hipEvent_t start = nullpt
 // groups of that many consecutive tiles of one phase (phases padded with empty
 // tiles to whole groups).
 constexpr int kMaxQuarters = 4;
+constexpr int kMaxBranches = 4;  // graph branches of a batch's direct scenes
 constexpr int kMaxQueues = 16;
 struct BatchTables {
     const Phase *phases;

@@ -531,12 +531,12 @@ class Batch:
         check(_lib.load().hrc_batch_describe(self._ptr, ctypes.byref(v), ctypes.byref(g),
                                              ctypes.byref(t), ctypes.byref(c), ctypes.byref(d)),
               "hrc_batch_describe")
-        nq, xl, sl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        nq, xl, sl, br = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         check(_lib.load().hrc_batch_queues(self._ptr, ctypes.byref(nq), ctypes.byref(xl),
-                                           ctypes.byref(sl)), "hrc_batch_queues")
+                                           ctypes.byref(sl), ctypes.byref(br)), "hrc_batch_queues")
         return {"variant": v.value, "grid": g.value, "target_tiles": t.value,
                 "chunk_groups": c.value, "direct_scenes": d.value, "queues": nq.value,
-                "xcd_local": xl.value, "slots_per_queue": sl.value}
+                "xcd_local": xl.value, "slots_per_queue": sl.value, "direct_branches": br.value}
 
     def candidates(self) -> List[dict]:
         """Every candidate the autotuner timed (``hrc_batch_candidates``)."""
@@ -544,13 +544,14 @@ class Batch:
         check(_lib.load().hrc_batch_candidates(self._ptr, 0, ctypes.byref(n), None, None),
               "hrc_batch_candidates")
         cap = n.value
-        desc = (ctypes.c_int * (7 * max(cap, 1)))()
+        F = 8  # fields per candidate
+        desc = (ctypes.c_int * (F * max(cap, 1)))()
         ms = (ctypes.c_float * max(cap, 1))()
         check(_lib.load().hrc_batch_candidates(self._ptr, cap, ctypes.byref(n), desc, ms),
               "hrc_batch_candidates")
         keys = ("direct_from_log2", "queues", "xcd_local", "slots_per_queue", "variant",
-                "target_tiles", "chunk_groups")
-        return [dict(zip(keys, desc[7 * i:7 * i + 7]), ms=ms[i]) for i in range(cap)]
+                "target_tiles", "chunk_groups", "direct_branches")
+        return [dict(zip(keys, desc[F * i:F * i + F]), ms=ms[i]) for i in range(cap)]
 
     def __del__(self):
         ptr = getattr(self, "_ptr", None)

@@ -91,6 +91,21 @@ static void check_arrangement(const Arrangement &ar, const std::vector<hrc_scene
             CHECK(ar.step_items[ar.q_step[q] + t] == per_step[t]);
     }
     for (int v : seen) CHECK(v == 1);
+    // graph branches of the direct scenes run side by side: no buffer that one
+    // branch writes is touched by another
+    for (int x = 0; x < kMaxBranches; ++x)
+        for (int y = x + 1; y < kMaxBranches; ++y)
+            for (const Phase &p : ar.direct[x])
+                for (const Phase &q : ar.direct[y]) {
+                    Access a, b;
+                    phase_access(p, a.rd, a.wr);
+                    phase_access(q, b.rd, b.wr);
+                    CHECK(!conflict(a, b));
+                }
+    int direct_passes = 0;
+    for (int x = 0; x < kMaxBranches; ++x) direct_passes += (int)ar.direct[x].size();
+    if (ar.n_direct > 0) CHECK(direct_passes > 0);
+    if (ar.branches == 1) for (int x = 1; x < kMaxBranches; ++x) CHECK(ar.direct[x].empty());
     // within a scene, a pass that depends on an earlier one runs in a later step
     for (size_t a = 0; a < np; ++a)
         for (size_t b = a + 1; b < np && ar.phase_scene[b] == ar.phase_scene[a]; ++b)
@@ -210,11 +225,14 @@ int main() {
     int arrangements = 0;
     for (int nq : {1, 8})
         for (int slots : {0, 1, 2})
-            for (int md : {HRC_MAX_LOG2 + 1, 10})
+            for (int md : {HRC_MAX_LOG2 + 1, 10, 9})
                 for (int quarters : {1, 4})
-                    for (int target : {64, 2048}) {
+                    for (int target : {64, 2048})
+                        for (int branches : {1, 2, 4}) {
+                        if (md > HRC_MAX_LOG2 && branches > 1) continue;
                         Arrangement ar;
                         ar.min_direct = md;
+                        ar.branches = branches;
                         ar.nqueues = nq;
                         ar.slots = slots;
                         ar.quarters = quarters;
