@@ -340,11 +340,13 @@ typedef struct hrc_batch hrc_batch;
  * scenes of a queue share a few workspace slots, the scenes of one slot
  * running one after another.  Optionally the scenes from a size up run first,
  * pass by pass, as kernels of their own in the same graph (a pass of a large
- * scene fills the GPU by itself).  The autotuner picks that size (possibly
- * none), the queue layout (per XCD, or one queue for the whole device whose
- * steps then synchronise through an L2 write-back), the slots per queue, the
- * kernel variant, the tile sizes and the claim chunk, timing each candidate
- * batch on a stream of its own, on the caller's buffers.  The scene pointers are
+ * scene fills the GPU by itself), split over 1, 2 or 4 graph branches with a
+ * workspace each whose passes overlap.  The autotuner picks that size
+ * (possibly none), the queue layout (per XCD, or one queue for the whole
+ * device whose steps then synchronise through an L2 write-back), the slots per
+ * queue, the kernel variant, the tile sizes, the claim chunk and the branches,
+ * timing each candidate batch on a stream of its own, on the caller's
+ * buffers.  The scene pointers are
  * baked in: later launches read and write the same buffers; no scene's
  * outputs may overlap another scene's inputs or outputs.  flags: 0, or
  * HRC_FLAG_BATCH_FULL or HRC_FLAG_BATCH_DENSE, each optionally with
