@@ -219,13 +219,13 @@ hrc_status hrc_backward(hrc_context *ctx, int log2_size,
  *   sigma_t  : [S][S], shared by the channels
  *   fluence  : [3][S][S] planes, overwritten
  * Flags: HRC_FLAG_VALIDATE, HRC_FLAG_BLUR (each plane blurred as by
- * hrc_forward), and for the forward either HRC_FLAG_HALF_INTERVALS (the
- * paper's own storage, Section 5: the interval as four IEEE halves, 8 bytes,
- * computed in FP32 and rounded once when stored, each channel then within the
- * relative N * 2^-11 of the FP32 result that hrc_forward's flag states) or
- * HRC_FLAG_KEEP_PYRAMID (the reserve space, as for hrc_forward: the workspace
- * must then be the backward's size; not both, HRC_ERR_UNSUPPORTED).  The
- * context's environment map is not applied (RGB calls run without one).
+ * hrc_forward), HRC_FLAG_HALF_INTERVALS (the paper's own storage, Section 5:
+ * the interval as four IEEE halves, 8 bytes, computed in FP32 and rounded once
+ * when stored, each channel then within the relative N * 2^-11 of the FP32
+ * result that hrc_forward's flag states) and HRC_FLAG_KEEP_PYRAMID (the
+ * reserve space, as for hrc_forward: the workspace must then be the
+ * backward's size for the same storage).  The context's environment map is
+ * not applied (RGB calls run without one).
  * Workspace from hrc_workspace_bytes_rgb (pass the same flags; it takes
  * HRC_FLAG_REUSE_PYRAMID as well).  Argument checks as for hrc_forward. */
 hrc_status hrc_workspace_bytes_rgb(int log2_size, unsigned flags, size_t *forward_bytes,
@@ -243,9 +243,12 @@ hrc_status hrc_forward_rgb(hrc_context *ctx, int log2_size, const float *emissio
  * so grad_emission's plane c equals hrc_backward's d emission for channel c
  * bitwise; grad_sigma_t gathers the channels inside the reverse (the sum of
  * three one-channel d sigma up to rounding).  Flags: HRC_FLAG_VALIDATE,
- * HRC_FLAG_BLUR, HRC_FLAG_REUSE_PYRAMID (after hrc_forward_rgb with
- * HRC_FLAG_KEEP_PYRAMID, as for hrc_backward).  Workspace: backward_bytes of
- * hrc_workspace_bytes_rgb. */
+ * HRC_FLAG_BLUR, HRC_FLAG_HALF_INTERVALS (the recomputed pyramid stored as
+ * halves, every adjoint FP32: each gradient element within N * 2^-11 times
+ * the same gradient taken with abs(grad_fluence), as hrc_backward states),
+ * HRC_FLAG_REUSE_PYRAMID (after hrc_forward_rgb with HRC_FLAG_KEEP_PYRAMID and
+ * the same storage, as for hrc_backward).  Workspace: backward_bytes of
+ * hrc_workspace_bytes_rgb for the same flags. */
 hrc_status hrc_backward_rgb(hrc_context *ctx, int log2_size, const float *emission,
                             const float *sigma_t, const float *grad_fluence,
                             float *grad_emission, float *grad_sigma_t, void *workspace,

@@ -360,13 +360,14 @@ int build_rgb_backward_phases(const Ws &w, const SolveBuffers &b, Phase *out, in
     if (recompute) {
         p.kind = PH_SEED_RGB;
         p.a.seed = SeedArgs{b.eps, b.sig, w.T(0), w.T(1), w.T(2), t_level_entries(N, 0),
-                            t_level_entries(N, 1), t_level_entries(N, 2), N, 0, kQuadrants, 16, 0, 0};
+                            t_level_entries(N, 1), t_level_entries(N, 2), N, 0, kQuadrants, 16, 0,
+                            b.half};
         add(p);
         for (int n = kTracedLevels; n < N; ++n) {
             p = Phase();
             p.kind = PH_UP_RGB;
             p.a.up = UpArgs{w.T(n - 1), w.T(n), t_level_entries(N, n - 1), t_level_entries(N, n), N,
-                            n, kQuadrants, 0};
+                            n, kQuadrants, b.half};
             add(p);
         }
         for (int n = N - 1; n >= 1; --n) {
@@ -374,7 +375,7 @@ int build_rgb_backward_phases(const Ws &w, const SolveBuffers &b, Phase *out, in
             p.kind = PH_DOWN_RGB;
             p.a.down = DownArgs{(n + 1 < N) ? w.R(n + 1) : nullptr, w.T(n), w.T(n + 1), w.R(n),
                                 t_level_entries(N, n), t_level_entries(N, n + 1), N, n, kQuadrants,
-                                nullptr, 0, 0};
+                                nullptr, 0, b.half};
             add(p);
         }
         if (b.F) {
@@ -414,7 +415,7 @@ int build_rgb_backward_phases(const Ws &w, const SolveBuffers &b, Phase *out, in
             p = Phase();
             p.kind = PH_DOWN_ADJ_RGB;
             p.a.da = DownAdjArgs{w.dR(n), w.T(n), w.T(n + 1), w.dR(n + 1), t_level_entries(N, n),
-                                 t_level_entries(N, n + 1), N, n, 0};
+                                 t_level_entries(N, n + 1), N, n, b.half};
             add(p);
         }
         for (int n = N; n >= 0; --n) {
@@ -433,6 +434,7 @@ int build_rgb_backward_phases(const Ws &w, const SolveBuffers &b, Phase *out, in
             d.en1 = n + 1 <= N ? t_level_entries(N, n + 1) : 0;
             d.N = N;
             d.n = n;
+            d.half = b.half;
             p.a.dt = d;
             add(p);
         }
@@ -647,29 +649,21 @@ hrc_status hrc_backward(hrc_context *ctx, int log2_size, const float *emission,
 
 // ---- three radiance channels (RGB) over one medium ---------------------------
 
-static constexpr unsigned kRgbFlags = HRC_FLAG_VALIDATE | HRC_FLAG_BLUR;
-// hrc_forward_rgb also takes the 16-bit storage or HRC_FLAG_KEEP_PYRAMID (not
-// both: the reverse keeps FP32 intervals), hrc_backward_rgb
-// HRC_FLAG_REUSE_PYRAMID; the workspace query takes all three.
-static constexpr unsigned kRgbForwardFlags =
-    kRgbFlags | HRC_FLAG_HALF_INTERVALS | HRC_FLAG_KEEP_PYRAMID;
+static constexpr unsigned kRgbFlags = HRC_FLAG_VALIDATE | HRC_FLAG_BLUR | HRC_FLAG_HALF_INTERVALS;
+// hrc_forward_rgb also takes HRC_FLAG_KEEP_PYRAMID, hrc_backward_rgb
+// HRC_FLAG_REUSE_PYRAMID; the workspace query takes both.
+static constexpr unsigned kRgbForwardFlags = kRgbFlags | HRC_FLAG_KEEP_PYRAMID;
 static constexpr unsigned kRgbBackwardFlags = kRgbFlags | HRC_FLAG_REUSE_PYRAMID;
-
-static bool rgb_flags_ok(unsigned flags) {
-    return !((flags & HRC_FLAG_HALF_INTERVALS) && (flags & HRC_FLAG_KEEP_PYRAMID));
-}
 
 hrc_status hrc_workspace_bytes_rgb(int log2_size, unsigned flags, size_t *forward_bytes,
                                    size_t *backward_bytes) {
     hrc_status st = check_shape(log2_size);
     if (st != HRC_OK) return st;
-    if ((flags & ~(kRgbForwardFlags | HRC_FLAG_REUSE_PYRAMID)) || !rgb_flags_ok(flags))
-        return HRC_ERR_UNSUPPORTED;
+    if (flags & ~(kRgbForwardFlags | HRC_FLAG_REUSE_PYRAMID)) return HRC_ERR_UNSUPPORTED;
     const bool keep = (flags & HRC_FLAG_KEEP_PYRAMID) != 0;
-    if (forward_bytes)
-        *forward_bytes =
-            make_layout(log2_size, keep, 4, (flags & HRC_FLAG_HALF_INTERVALS) != 0, true).total;
-    if (backward_bytes) *backward_bytes = make_layout(log2_size, true, 4, false, true).total;
+    const bool half = (flags & HRC_FLAG_HALF_INTERVALS) != 0;
+    if (forward_bytes) *forward_bytes = make_layout(log2_size, keep, 4, half, true).total;
+    if (backward_bytes) *backward_bytes = make_layout(log2_size, true, 4, half, true).total;
     return HRC_OK;
 }
 
@@ -689,7 +683,7 @@ hrc_status hrc_forward_rgb(hrc_context *ctx, int log2_size, const float *emissio
     if (!aligned16(emission) || !aligned16(sigma_t) || !aligned16(fluence) ||
         !aligned16(workspace))
         return HRC_ERR_INVALID_ARG;
-    if ((flags & ~kRgbForwardFlags) || !rgb_flags_ok(flags)) return HRC_ERR_UNSUPPORTED;
+    if (flags & ~kRgbForwardFlags) return HRC_ERR_UNSUPPORTED;
     const bool half = (flags & HRC_FLAG_HALF_INTERVALS) != 0;
     const bool keep = (flags & HRC_FLAG_KEEP_PYRAMID) != 0;
     Layout L = make_layout(log2_size, keep, 4, half, true);
@@ -721,7 +715,8 @@ hrc_status hrc_backward_rgb(hrc_context *ctx, int log2_size, const float *emissi
         !aligned16(grad_emission) || !aligned16(grad_sigma_t) || !aligned16(workspace))
         return HRC_ERR_INVALID_ARG;
     if (flags & ~kRgbBackwardFlags) return HRC_ERR_UNSUPPORTED;
-    const Layout L = make_layout(log2_size, true, 4, false, true);
+    const bool half = (flags & HRC_FLAG_HALF_INTERVALS) != 0;
+    const Layout L = make_layout(log2_size, true, 4, half, true);
     if (workspace_bytes < L.total) return HRC_ERR_WORKSPACE;
     if (!ctx) return HRC_ERR_INVALID_ARG;
     DeviceGuard g(ctx->device);
@@ -734,7 +729,7 @@ hrc_status hrc_backward_rgb(hrc_context *ctx, int log2_size, const float *emissi
     }
     Phase ph[kMaxPhases];
     SolveBuffers b{emission, sigma_t, nullptr, grad_fluence, grad_emission, grad_sigma_t,
-                   (flags & HRC_FLAG_BLUR) ? 1 : 0, nullptr, 0};
+                   (flags & HRC_FLAG_BLUR) ? 1 : 0, nullptr, half ? 1 : 0};
     const int np = build_rgb_backward_phases(w, b, ph, kMaxPhases,
                                              (flags & HRC_FLAG_REUSE_PYRAMID) == 0);
     return run_phases(ph, np, s);

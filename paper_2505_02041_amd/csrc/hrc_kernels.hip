@@ -2354,6 +2354,12 @@ __global__ __launch_bounds__(256) void hrc_merge_down_adj_rgb(Phase p) {
 __global__ __launch_bounds__(256) void hrc_interval_adj_rgb(Phase p) {
     body_dT_rgb<float4>(p.a.dt, xcd_tile_blk(blockIdx.x, gridDim.x, p.xblk), p.U, ltid());
 }
+__global__ __launch_bounds__(256) void hrc_merge_down_adj_rgb_f16(Phase p) {
+    body_merge_down_adj_rgb<half4_t>(p.a.da, xcd_tile_blk(blockIdx.x, gridDim.x, p.xblk), p.U, ltid());
+}
+__global__ __launch_bounds__(256) void hrc_interval_adj_rgb_f16(Phase p) {
+    body_dT_rgb<half4_t>(p.a.dt, xcd_tile_blk(blockIdx.x, gridDim.x, p.xblk), p.U, ltid());
+}
 __global__ __launch_bounds__(256) void hrc_seed_adj_rgb(Phase p) {
     __shared__ __align__(16) char lds[kSeedAdjRgbLds];
     body_seed_adj_rgb(p.a.sa, xcd_tile(blockIdx.x, gridDim.x), lds, ltid());
@@ -2668,8 +2674,8 @@ hipError_t launch_phase(const Phase &p, hipStream_t s, hipEvent_t start, hipEven
         case PH_UP_RGB: k = p.a.up.half ? hrc_merge_up_rgb_f16 : hrc_merge_up_rgb; break;
         case PH_DOWN_RGB: k = p.a.down.half ? hrc_merge_down_rgb_f16 : hrc_merge_down_rgb; break;
         case PH_TAIL_RGB: k = hrc_tail_rgb; break;
-        case PH_DOWN_ADJ_RGB: k = hrc_merge_down_adj_rgb; break;
-        case PH_DT_RGB: k = hrc_interval_adj_rgb; break;
+        case PH_DOWN_ADJ_RGB: k = p.a.da.half ? hrc_merge_down_adj_rgb_f16 : hrc_merge_down_adj_rgb; break;
+        case PH_DT_RGB: k = p.a.dt.half ? hrc_interval_adj_rgb_f16 : hrc_interval_adj_rgb; break;
         case PH_SEED_ADJ_RGB: k = hrc_seed_adj_rgb; break;
         default: return hipErrorInvalidValue;
     }

@@ -194,15 +194,17 @@ class Context:
               "hrc_workspace_bytes_rgb")
         return f.value, b.value
 
-    def reserve_rgb(self, N: int) -> torch.Tensor:
-        """A fresh workspace of the RGB reverse's size: the reserve space that
-        hrc_forward_rgb with ``HRC_FLAG_KEEP_PYRAMID`` fills and hrc_backward_rgb
-        with ``HRC_FLAG_REUSE_PYRAMID`` reads."""
-        return torch.empty(self._rgb_sizes(N)[1], dtype=torch.uint8,
+    def reserve_rgb(self, N: int, flags: int = 0) -> torch.Tensor:
+        """A fresh workspace of the RGB reverse's size (for the interval storage
+        in ``flags``): the reserve space that hrc_forward_rgb with
+        ``HRC_FLAG_KEEP_PYRAMID`` fills and hrc_backward_rgb with
+        ``HRC_FLAG_REUSE_PYRAMID`` reads."""
+        half = flags & _lib.HRC_FLAG_HALF_INTERVALS
+        return torch.empty(self._rgb_sizes(N, half)[1], dtype=torch.uint8,
                            device=torch.device("cuda", self.device))
 
     def _rgb_workspace(self, N: int, backward: bool, flags: int = 0) -> torch.Tensor:
-        half = 0 if backward else flags & _lib.HRC_FLAG_HALF_INTERVALS
+        half = flags & _lib.HRC_FLAG_HALF_INTERVALS
         key = ("rgb", N, backward, half, self._stream_key())
         ws = self._ws.get(key)
         if ws is None:
@@ -261,7 +263,7 @@ class Context:
                 raise ValueError("HRC_FLAG_REUSE_PYRAMID needs the kept forward's reserve tensor")
             ws = self._workspace_arg(reserve)
         else:
-            ws = self._rgb_workspace(N, True)
+            ws = self._rgb_workspace(N, True, flags)
         check(_lib.load().hrc_backward_rgb(self._ptr, N, emission.data_ptr(), sigma_t.data_ptr(),
                                            grad_fluence.data_ptr(), ge.data_ptr(), gs.data_ptr(),
                                            ws.data_ptr(), ws.numel(),
@@ -420,7 +422,7 @@ class RGBFunction(torch.autograd.Function):
         ctx.reserve = None
         ctx.save_for_backward(emission, sigma_t)
         if keep and (ctx.needs_input_grad[0] or ctx.needs_input_grad[1]):
-            ctx.reserve = c.reserve_rgb(_log2_size(sigma_t))
+            ctx.reserve = c.reserve_rgb(_log2_size(sigma_t), ctx.flags)
             return c.hrc_forward_rgb(emission, sigma_t,
                                      flags=ctx.flags | _lib.HRC_FLAG_KEEP_PYRAMID,
                                      reserve=ctx.reserve)

@@ -77,3 +77,19 @@ def to_dev(a):
 def log(msg):
     print(msg, flush=True)
     sys.stdout.flush()
+
+
+def assert_half_grad(g16, g_ref, g_abs, N, what):
+    """Each gradient element within N 2^-11 times the same gradient taken with
+    abs(dLoss/dF) (every term of a gradient is a fluence term with one factor
+    differentiated: one sign per field, and at most N roundings on its path),
+    plus the FP32 reverse's own tolerance."""
+    g16 = np.asarray(g16, np.float64)
+    err = np.abs(g16 - g_ref)
+    bound = N * 2.0 ** -11 * np.abs(g_abs) + 1e-4 * np.abs(g_ref).max()
+    bad = err > bound
+    if bad.any():
+        i = np.unravel_index(np.argmax(err / np.maximum(bound, 1e-300)), err.shape)
+        raise AssertionError(f"{what}: {bad.sum()} of {bad.size} outside the 16-bit reverse "
+                             f"bound; worst at {i}: gpu {g16[i]!r} ref {g_ref[i]!r} "
+                             f"abs-gradient {g_abs[i]!r}")

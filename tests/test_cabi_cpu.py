@@ -148,21 +148,27 @@ def test_keep_and_reuse_flags_where_taken():
     assert lib.hrc_forward(None, 5, p, p, p, p, b, None, R) == HRC_ERR_UNSUPPORTED
     assert lib.hrc_backward(None, 5, p, p, p, p, p, p, b, None, K) == HRC_ERR_UNSUPPORTED
     assert lib.hrc_forward_static(None, 5, p, p, p, None, K) == HRC_ERR_UNSUPPORTED
-    # the RGB calls: the kept forward takes the RGB reverse's workspace, not
-    # together with the 16-bit storage
+    # the RGB calls: the kept forward takes the RGB reverse's workspace (smaller
+    # with the 16-bit storage)
     fr, br = ctypes.c_size_t(0), ctypes.c_size_t(0)
     frk, brk = ctypes.c_size_t(0), ctypes.c_size_t(0)
     assert lib.hrc_workspace_bytes_rgb(5, 0, ctypes.byref(fr), ctypes.byref(br)) == HRC_OK
     assert lib.hrc_workspace_bytes_rgb(5, K, ctypes.byref(frk), ctypes.byref(brk)) == HRC_OK
     assert frk.value == brk.value == br.value and fr.value < br.value
-    assert lib.hrc_workspace_bytes_rgb(5, K | H, ctypes.byref(frk), None) == HRC_ERR_UNSUPPORTED
-    assert lib.hrc_forward_rgb(None, 5, p, p, p, p, br.value, None, K | H) == HRC_ERR_UNSUPPORTED
+    frh, brh = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.hrc_workspace_bytes_rgb(5, K | H, ctypes.byref(frh), ctypes.byref(brh)) == HRC_OK
+    assert frh.value == brh.value < br.value
+    assert lib.hrc_forward_rgb(None, 5, p, p, p, p, brh.value, None, K | H) == HRC_ERR_INVALID_ARG
+    assert lib.hrc_backward_rgb(None, 5, p, p, p, p, p, p, brh.value - 1, None, H) == \
+        HRC_ERR_WORKSPACE
     assert lib.hrc_forward_rgb(None, 5, p, p, p, p, br.value - 1, None, K) == HRC_ERR_WORKSPACE
     assert lib.hrc_forward_rgb(None, 5, p, p, p, p, br.value, None, K) == HRC_ERR_INVALID_ARG
     assert lib.hrc_forward_rgb(None, 5, p, p, p, p, br.value, None, R) == HRC_ERR_UNSUPPORTED
     assert lib.hrc_backward_rgb(None, 5, p, p, p, p, p, p, br.value, None, R) == HRC_ERR_INVALID_ARG
     assert lib.hrc_backward_rgb(None, 5, p, p, p, p, p, p, br.value, None, K) == HRC_ERR_UNSUPPORTED
-    assert lib.hrc_backward_rgb(None, 5, p, p, p, p, p, p, br.value, None, H) == HRC_ERR_UNSUPPORTED
+    assert lib.hrc_backward_rgb(None, 5, p, p, p, p, p, p, br.value, None, H) == HRC_ERR_INVALID_ARG
+    assert lib.hrc_backward_rgb(None, 5, p, p, p, p, p, p, br.value, None, 0x10) == \
+        HRC_ERR_UNSUPPORTED
     fb = ctypes.c_size_t(0)
     for flag in (K, R):
         assert lib.hrc_multibounce_workspace_bytes(5, 3, flag, ctypes.byref(fb), None) == \

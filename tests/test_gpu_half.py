@@ -12,7 +12,7 @@ from scenes import config1, config2, config3
 
 pytestmark = pytest.mark.gpu
 
-from gpu_common import assert_forward_close, assert_half_close, log, to_dev  # noqa: E402
+from gpu_common import assert_forward_close, assert_half_close, assert_half_grad, log, to_dev  # noqa: E402
 
 HALF = 0x4
 
@@ -98,22 +98,6 @@ def test_fp32_path_unchanged_by_the_option(ctx):
 
 # ---- the reverse with the 16-bit storage ------------------------------------
 
-def _assert_half_grad(g16, g_ref, g_abs, N, what):
-    """Each gradient element within N 2^-11 times the same gradient taken with
-    abs(dLoss/dF) (every term of a gradient is a fluence term with one factor
-    differentiated: one sign per field, and at most N roundings on its path),
-    plus the FP32 reverse's own tolerance."""
-    g16 = np.asarray(g16, np.float64)
-    err = np.abs(g16 - g_ref)
-    bound = N * 2.0 ** -11 * np.abs(g_abs) + 1e-4 * np.abs(g_ref).max()
-    bad = err > bound
-    if bad.any():
-        i = np.unravel_index(np.argmax(err / np.maximum(bound, 1e-300)), err.shape)
-        raise AssertionError(f"{what}: {bad.sum()} of {bad.size} outside the 16-bit reverse "
-                             f"bound; worst at {i}: gpu {g16[i]!r} ref {g_ref[i]!r} "
-                             f"abs-gradient {g_abs[i]!r}")
-
-
 @pytest.mark.parametrize("case", ["random8", "random64", "config1", "random256", "config3"])
 def test_half_backward_within_derived_bound(ctx, case):
     """hrc_backward with HRC_FLAG_HALF_INTERVALS against the oracle's FP64
@@ -136,8 +120,8 @@ def test_half_backward_within_derived_bound(ctx, case):
     torch.cuda.synchronize()
     re, rs = hrc_vjp.fluence_vjp(eps, sig, dF)
     ae, as_ = hrc_vjp.fluence_vjp(eps, sig, np.abs(dF))
-    _assert_half_grad(ge.cpu().numpy(), re, ae, N, f"d eps {case}")
-    _assert_half_grad(gs.cpu().numpy(), rs, as_, N, f"d sigma {case}")
+    assert_half_grad(ge.cpu().numpy(), re, ae, N, f"d eps {case}")
+    assert_half_grad(gs.cpu().numpy(), rs, as_, N, f"d sigma {case}")
     # the storage does round (the check is not vacuous)
     ge32, _ = ctx.hrc_backward(to_dev(eps), to_dev(sig), to_dev(dF))
     assert not torch.equal(ge, ge32) or S <= 8

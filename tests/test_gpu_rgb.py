@@ -14,8 +14,8 @@ from scenes import config3, scene_like_512
 
 pytestmark = pytest.mark.gpu
 
-from gpu_common import (assert_forward_close, assert_grad_close, assert_half_close, log,  # noqa: E402
-                        to_dev)
+from gpu_common import (assert_forward_close, assert_grad_close, assert_half_close,  # noqa: E402
+                        assert_half_grad, log, to_dev)
 
 
 @pytest.fixture(scope="module")
@@ -184,6 +184,48 @@ def test_rgb_half_storage_benchmark_scene(ctx):
     ctx.release_workspaces()
 
 
+@pytest.mark.parametrize("S", [64, 256, 1024])
+def test_rgb_half_backward(ctx, S):
+    """The RGB reverse with the paper's 16-bit storage: d emission per channel
+    bitwise equal to the one-channel 16-bit reverse (the same values rounded at
+    the same points); both gradients within N 2^-11 times the gradient of
+    abs(dLoss/dF) of three oracle reverses, as the one-channel 16-bit reverse;
+    the reserve-space pair bitwise equal to the plain call."""
+    from paper_2505_02041_amd import _lib
+    log(f"rgb 16-bit reverse S={S}")
+    H = _lib.HRC_FLAG_HALF_INTERVALS
+    if S == 1024:
+        sc = config3()
+        eps = np.stack([sc.eps, np.roll(sc.eps, 37, axis=1), 0.3 * sc.eps]).astype(np.float32)
+        sig = sc.sigma
+    else:
+        eps, sig = _rgb_scene(S, 80 + S)
+    N = S.bit_length() - 1
+    dF = np.random.default_rng(S + 3).normal(size=(3, S, S)).astype(np.float32)
+    e, s, g = to_dev(eps), to_dev(sig), to_dev(dF)
+    ge, gs = ctx.hrc_backward_rgb(e, s, g, flags=H)
+    for c in range(3):
+        assert torch.equal(ge[c], ctx.hrc_backward(e[c].contiguous(), s, g[c].contiguous(),
+                                                   flags=H)[0]), c
+    res = ctx.reserve_rgb(N, H)
+    ctx.hrc_forward_rgb(e, s, flags=H | _lib.HRC_FLAG_KEEP_PYRAMID, reserve=res)
+    gk = ctx.hrc_backward_rgb(e, s, g, flags=H | _lib.HRC_FLAG_REUSE_PYRAMID, reserve=res)
+    assert torch.equal(gk[0], ge) and torch.equal(gk[1], gs)
+    torch.cuda.synchronize()
+    ge, gs = ge.cpu().numpy(), gs.cpu().numpy()
+    del res
+    ctx.release_workspaces()
+    rs = np.zeros((S, S))
+    as_ = np.zeros((S, S))
+    for c in range(3):
+        re, rsc = hrc_vjp.fluence_vjp(eps[c], sig, dF[c])
+        ae, asc = hrc_vjp.fluence_vjp(eps[c], sig, np.abs(dF[c]))
+        assert_half_grad(ge[c], re, ae, N, f"rgb 16-bit d eps channel {c} S={S}")
+        rs += rsc
+        as_ += asc
+    assert_half_grad(gs, rs, as_, N, f"rgb 16-bit d sigma S={S}")
+
+
 def test_rgb_rejects_bad_arguments(ctx):
     from paper_2505_02041_amd._lib import HRCError
     z = torch.zeros((3, 16, 16), device="cuda")
@@ -191,6 +233,6 @@ def test_rgb_rejects_bad_arguments(ctx):
     with pytest.raises(HRCError):
         ctx.hrc_forward_rgb(z, s, flags=0x10)  # no quadrant grouping for RGB
     with pytest.raises(HRCError):
-        ctx.hrc_backward_rgb(z, s, z, flags=0x4)  # the reverse stays FP32
+        ctx.hrc_backward_rgb(z, s, z, flags=0x10)  # no quadrant grouping for RGB
     with pytest.raises(ValueError):
         ctx.hrc_forward_rgb(z[:2].contiguous(), s)
