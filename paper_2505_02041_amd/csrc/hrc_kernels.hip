@@ -477,6 +477,102 @@ __device__ __forceinline__ void r_quad(const float *Rq, int N, int m, int c, int
     }
 }
 
+// Interval pair at a shifted row position yf of a row, or <0, 1> twice
+// outside [0, S): a clamped address and a select, so the lookup has no branch.
+__device__ __forceinline__ float4 far_pair_sel(const float2 *row, int yf, int S) {
+    const bool in = (unsigned)yf < (unsigned)S;
+    const float4 v = ld_pair(row + (in ? yf : 0));
+    return in ? v : make_float4(0.f, 1.f, 0.f, 1.f);
+}
+
+// R_{n+1} pair at (c, jj) and rows (y, y+1), y even, or the environment's
+// fluence e outside the grid (column c past the last, or y outside [0, S)):
+// a clamped address and a select.
+__device__ __forceinline__ float2 r_pair_sel(const float *Rq, int N, int m, int c, int jj, int y,
+                                             float e) {
+    const int S = 1 << N;
+    const bool in = c < (S >> m) && (unsigned)y < (unsigned)S;
+    const float2 v = *reinterpret_cast<const float2 *>(
+        Rq + ((size_t)(((in ? c : 0) << m) | jj)) * S + (in ? y : 0));
+    return in ? v : make_float2(e, e);
+}
+
+// One pair of rows (y, y+1) of R_n at probe column x, cone pair ii (cones
+// jj = 2 ii, 2 ii + 1), FP32 intervals.  Every operand, the cone weights
+// included, is loaded before any is used, so a wave waits for memory once;
+// TOP (n + 1 = N) builds the doubled edges of T_N from T_{N-1} and reads the
+// environment for R_N; without ENV the fluence from beyond the grid is 0 (a
+// constant, so the lookups outside the grid stay selects, not branches).  The
+// arithmetic, and its order, is that of Eq. 14 (odd x) and Eq. 15-17 (even x).
+template <bool TOP, bool ENV>
+__device__ __forceinline__ float2 merge_down_pair(const DownArgs &a, int q, int x, int ii, int y) {
+    const int N = a.N, S = 1 << N, n = a.n, m = n + 1;
+    const float *Rq = a.Rn1 + q * (size_t)S * S;
+    const int jb = (1 << m) - 1 + 2 * ii;  // cone table index of cone 2 ii at level m
+    const float A0 = c_cone[jb], A1 = c_cone[jb + 1];
+    float E0 = 0.f, E1 = 0.f;
+    if (ENV) {
+        const float *ep = a.env + (size_t)(a.q0 + q) * kConeTable + jb;
+        E0 = ep[0];
+        E1 = ep[1];
+    }
+    float acc0 = 0.f, acc1 = 0.f;
+    if (x & 1) {
+        // Eq. 14: the half-cone's outer edge (T_n of this column, directions
+        // ii and ii + 1) to the level n+1 probe c.
+        const float2 *Tx = a.Tn + q * a.en + (size_t)x * ((1 << n) + 1) * S;
+        const int c = (x + 1) >> 1;
+        const int yr = y + 2 * ii - (1 << n);
+        const float4 t0 = ld_pair(Tx + (size_t)ii * S + y);
+        const float4 t1 = ld_pair(Tx + (size_t)(ii + 1) * S + y);
+        float2 f0 = make_float2(E0, E0), f1 = make_float2(E1, E1);
+        if (!TOP) {
+            f0 = r_pair_sel(Rq, N, m, c, 2 * ii, yr, E0);
+            f1 = r_pair_sel(Rq, N, m, c, 2 * ii + 1, yr + 2, E1);
+        }
+        acc0 += fmaf(t0.y, f0.x, A0 * t0.x);
+        acc1 += fmaf(t0.w, f0.y, A0 * t0.z);
+        acc0 += fmaf(t1.y, f1.x, A1 * t1.x);
+        acc1 += fmaf(t1.w, f1.y, A1 * t1.z);
+    } else {
+        // Eq. 15-17: the co-located probe c averaged with the doubled edge
+        // T_{n+1}(c, e2), e2 = 2 ii and 2 ii + 2, to probe c + 1.
+        const int c = x >> 1;
+        float4 t0, t1;
+        if (TOP) {
+            // T_N(c, e2) as the merge up builds an even direction (Eq. 18):
+            // T_{N-1}(2c, e2/2) at row y, then T_{N-1}(2c+1, e2/2) at row
+            // y + e2 - 2^n.
+            const float2 *Tnear = a.Tn + q * a.en + (size_t)(2 * c) * ((1 << n) + 1) * S;
+            const float2 *Tfar = Tnear + (size_t)((1 << n) + 1) * S;
+            const float4 nv0 = ld_pair(Tnear + (size_t)ii * S + y);
+            const float4 nv1 = ld_pair(Tnear + (size_t)(ii + 1) * S + y);
+            const float4 fv0 = far_pair_sel(Tfar + (size_t)ii * S, y + 2 * ii - (1 << n), S);
+            const float4 fv1 = far_pair_sel(Tfar + (size_t)(ii + 1) * S, y + 2 * ii + 2 - (1 << n), S);
+            t0 = pair(merge(lo(nv0), lo(fv0)), merge(hi(nv0), hi(fv0)));
+            t1 = pair(merge(lo(nv1), lo(fv1)), merge(hi(nv1), hi(fv1)));
+        } else {
+            const float2 *Tx = a.Tn1 + q * a.en1 + (size_t)c * ((1 << m) + 1) * S;
+            t0 = ld_pair(Tx + (size_t)(2 * ii) * S + y);
+            t1 = ld_pair(Tx + (size_t)(2 * ii + 2) * S + y);
+        }
+        float2 r00 = make_float2(E0, E0), r01 = make_float2(E1, E1);
+        float2 r10 = r00, r11 = r01;
+        if (!TOP) {
+            const int yf = y + 4 * ii - (1 << m);
+            r00 = r_pair_sel(Rq, N, m, c, 2 * ii, y, E0);
+            r01 = r_pair_sel(Rq, N, m, c, 2 * ii + 1, y, E1);
+            r10 = r_pair_sel(Rq, N, m, c + 1, 2 * ii, yf, E0);
+            r11 = r_pair_sel(Rq, N, m, c + 1, 2 * ii + 1, yf + 4, E1);
+        }
+        acc0 += 0.5f * (r00.x + fmaf(t0.y, r10.x, A0 * t0.x));
+        acc1 += 0.5f * (r00.y + fmaf(t0.w, r10.y, A0 * t0.z));
+        acc0 += 0.5f * (r01.x + fmaf(t1.y, r11.x, A1 * t1.x));
+        acc1 += 0.5f * (r01.y + fmaf(t1.w, r11.y, A1 * t1.z));
+    }
+    return make_float2(acc0, acc1);
+}
+
 // Merge down: R_n from R_{n+1}, T_n, T_{n+1} (Eq. 14-17), for n >= 1 (levels 1
 // and 0 of the forward are the tail's, and the reverse reads R_1 at the
 // lowest), so every row shift is even and each lookup is a pair.
@@ -506,44 +602,38 @@ __device__ void body_merge_down(const DownArgs &a, unsigned tile, int U, int tid
             ii = (int)(row & ((1u << n) - 1));
         }
         const unsigned r = ((unsigned)x << n) | (unsigned)ii;
+        float *out = a.R + q * SS + (size_t)r * S + y0;
+        if constexpr (P == 1) {
+            float2 v;
+            if (a.env)
+                v = m == N ? merge_down_pair<true, true>(a, q, x, ii, y0)
+                           : merge_down_pair<false, true>(a, q, x, ii, y0);
+            else
+                v = m == N ? merge_down_pair<true, false>(a, q, x, ii, y0)
+                           : merge_down_pair<false, false>(a, q, x, ii, y0);
+            *reinterpret_cast<float2 *>(out) = v;
+        } else {
+        // 16-bit intervals: rows y0 .. y0+3 per thread, each T row one quad.
         const float *Rq = a.Rn1 + q * SS;
         const float *envq = a.env ? a.env + (size_t)(a.q0 + q) * kConeTable : nullptr;
-        float acc0[P], acc1[P];
-#pragma unroll
-        for (int j = 0; j < P; ++j) acc0[j] = acc1[j] = 0.f;
+        float acc0[2] = {0.f, 0.f}, acc1[2] = {0.f, 0.f};
         if (x & 1) {
             // Eq. 14: trace the half-cone's outer edge to the level n+1 probe.
             const TS *Tx = reinterpret_cast<const TS *>(a.Tn) + q * a.en + (size_t)x * ((1 << n) + 1) * S;
             const int c = (x + 1) >> 1;
-            if constexpr (P == 2) {
 #pragma unroll
-                for (int up = 0; up < 2; ++up) {
-                    const int e = ii + up, jj = 2 * ii + up;
-                    const float A = c_cone[(1 << m) - 1 + jj];
-                    float4 t[2];
-                    float2 rf[2];
-                    ld_quad(Tx + (size_t)e * S + y0, t[0], t[1]);
-                    r_quad(Rq, N, m, c, jj, y0 + 2 * e - (1 << n), envq, rf[0], rf[1]);
+            for (int up = 0; up < 2; ++up) {
+                const int e = ii + up, jj = 2 * ii + up;
+                const float A = c_cone[(1 << m) - 1 + jj];
+                float4 t[2];
+                float2 rf[2];
+                ld_quad(Tx + (size_t)e * S + y0, t[0], t[1]);
+                r_quad(Rq, N, m, c, jj, y0 + 2 * e - (1 << n), envq, rf[0], rf[1]);
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        acc0[j] += fmaf(t[j].y, rf[j].x, A * t[j].x);
-                        acc1[j] += fmaf(t[j].w, rf[j].y, A * t[j].z);
-                    }
+                for (int j = 0; j < 2; ++j) {
+                    acc0[j] += fmaf(t[j].y, rf[j].x, A * t[j].x);
+                    acc1[j] += fmaf(t[j].w, rf[j].y, A * t[j].z);
                 }
-            } else {
-#pragma unroll
-            for (int j = 0; j < P; ++j) {
-                const int y = y0 + 2 * j;
-#pragma unroll
-                for (int up = 0; up < 2; ++up) {
-                    const int e = ii + up, jj = 2 * ii + up;
-                    const float A = c_cone[(1 << m) - 1 + jj];
-                    const float4 t = ld_pair(Tx + (size_t)e * S + y);
-                    const float2 rf = r_pair(Rq, N, m, c, jj, y + 2 * e - (1 << n), envq);
-                    acc0[j] += fmaf(t.y, rf.x, A * t.x);
-                    acc1[j] += fmaf(t.w, rf.y, A * t.z);
-                }
-            }
             }
         } else {
             // Eq. 15-17: average the co-located probe with the doubled-edge trace.
@@ -555,62 +645,33 @@ __device__ void body_merge_down(const DownArgs &a, unsigned tile, int U, int tid
             const TS *Tx = reinterpret_cast<const TS *>(a.Tn1) + q * a.en1 + (size_t)c * ((1 << m) + 1) * S;
             const TS *Tnear = reinterpret_cast<const TS *>(a.Tn) + q * a.en + (size_t)(2 * c) * ((1 << n) + 1) * S;
             const TS *Tfar = Tnear + (size_t)((1 << n) + 1) * S;
-            if constexpr (P == 2) {
 #pragma unroll
-                for (int up = 0; up < 2; ++up) {
-                    const int e2 = 2 * ii + 2 * up, jj = 2 * ii + up;
-                    const float A = c_cone[(1 << m) - 1 + jj];
-                    float4 t[2];
-                    if (top) {
-                        const int kk = e2 >> 1;
-                        float4 nv[2], fv[2];
-                        ld_quad(Tnear + (size_t)kk * S + y0, nv[0], nv[1]);
-                        far_quad(Tfar + (size_t)kk * S, y0 + e2 - (1 << n), S, fv[0], fv[1]);
+            for (int up = 0; up < 2; ++up) {
+                const int e2 = 2 * ii + 2 * up, jj = 2 * ii + up;
+                const float A = c_cone[(1 << m) - 1 + jj];
+                float4 t[2];
+                if (top) {
+                    const int kk = e2 >> 1;
+                    float4 nv[2], fv[2];
+                    ld_quad(Tnear + (size_t)kk * S + y0, nv[0], nv[1]);
+                    far_quad(Tfar + (size_t)kk * S, y0 + e2 - (1 << n), S, fv[0], fv[1]);
 #pragma unroll
-                        for (int j = 0; j < 2; ++j)
-                            t[j] = pair(merge(lo(nv[j]), lo(fv[j])), merge(hi(nv[j]), hi(fv[j])));
-                    } else {
-                        ld_quad(Tx + (size_t)e2 * S + y0, t[0], t[1]);
-                    }
-                    float2 r0[2], r1[2];
-                    r_quad(Rq, N, m, c, jj, y0, envq, r0[0], r0[1]);
-                    r_quad(Rq, N, m, c + 1, jj, y0 + 2 * e2 - (1 << m), envq, r1[0], r1[1]);
-#pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        acc0[j] += 0.5f * (r0[j].x + fmaf(t[j].y, r1[j].x, A * t[j].x));
-                        acc1[j] += 0.5f * (r0[j].y + fmaf(t[j].w, r1[j].y, A * t[j].z));
-                    }
+                    for (int j = 0; j < 2; ++j)
+                        t[j] = pair(merge(lo(nv[j]), lo(fv[j])), merge(hi(nv[j]), hi(fv[j])));
+                } else {
+                    ld_quad(Tx + (size_t)e2 * S + y0, t[0], t[1]);
                 }
-            } else {
+                float2 r0[2], r1[2];
+                r_quad(Rq, N, m, c, jj, y0, envq, r0[0], r0[1]);
+                r_quad(Rq, N, m, c + 1, jj, y0 + 2 * e2 - (1 << m), envq, r1[0], r1[1]);
 #pragma unroll
-            for (int j = 0; j < P; ++j) {
-                const int y = y0 + 2 * j;
-#pragma unroll
-                for (int up = 0; up < 2; ++up) {
-                    const int e2 = 2 * ii + 2 * up, jj = 2 * ii + up;
-                    const float A = c_cone[(1 << m) - 1 + jj];
-                    float4 t;
-                    if (top) {
-                        const int kk = e2 >> 1;
-                        const float4 nv = ld_pair(Tnear + (size_t)kk * S + y);
-                        const float4 fv = far_pair(Tfar + (size_t)kk * S, y + e2 - (1 << n), S);
-                        t = pair(merge(lo(nv), lo(fv)), merge(hi(nv), hi(fv)));
-                    } else {
-                        t = ld_pair(Tx + (size_t)e2 * S + y);
-                    }
-                    const float2 r0 = r_pair(Rq, N, m, c, jj, y, envq);
-                    const float2 r1 = r_pair(Rq, N, m, c + 1, jj, y + 2 * e2 - (1 << m), envq);
-                    acc0[j] += 0.5f * (r0.x + fmaf(t.y, r1.x, A * t.x));
-                    acc1[j] += 0.5f * (r0.y + fmaf(t.w, r1.y, A * t.z));
+                for (int j = 0; j < 2; ++j) {
+                    acc0[j] += 0.5f * (r0[j].x + fmaf(t[j].y, r1[j].x, A * t[j].x));
+                    acc1[j] += 0.5f * (r0[j].y + fmaf(t[j].w, r1[j].y, A * t[j].z));
                 }
-            }
             }
         }
-        float *out = a.R + q * SS + (size_t)r * S + y0;
-        if constexpr (P == 2) {
-            *reinterpret_cast<float4 *>(out) = make_float4(acc0[0], acc1[0], acc0[1], acc1[1]);
-        } else {
-            *reinterpret_cast<float2 *>(out) = make_float2(acc0[0], acc1[0]);
+        *reinterpret_cast<float4 *>(out) = make_float4(acc0[0], acc1[0], acc0[1], acc1[1]);
         }
     }
 }
