@@ -163,6 +163,15 @@ __device__ __forceinline__ _Float16 to_half(float v) {
     asm volatile("" : "+v"(v));
     return (_Float16)v;
 }
+// A loaded operand pinned in a register at the point where every load of a
+// pass has been issued.  Loads under conditions uniform over the wave would
+// otherwise draw the arithmetic that uses them into each conditional block,
+// and each block would then wait for its own loads: the pins keep the loads
+// of all the blocks in flight together, so the wave waits for memory once.
+__device__ __forceinline__ void pin(float &v) { asm volatile("" : "+v"(v)); }
+__device__ __forceinline__ void pin(float2 &v) { pin(v.x); pin(v.y); }
+__device__ __forceinline__ void pin(float4 &v) { pin(v.x); pin(v.y); pin(v.z); pin(v.w); }
+
 __device__ __forceinline__ float4 ld_pair(const half2_t *p) {
     const half4_t v = *reinterpret_cast<const half4_t *>(p);
     return make_float4((float)v.x, (float)v.y, (float)v.z, (float)v.w);
@@ -479,7 +488,8 @@ __device__ __forceinline__ void r_quad(const float *Rq, int N, int m, int c, int
 
 // Interval pair at a shifted row position yf of a row, or <0, 1> twice
 // outside [0, S): a clamped address and a select, so the lookup has no branch.
-__device__ __forceinline__ float4 far_pair_sel(const float2 *row, int yf, int S) {
+template <typename TS>
+__device__ __forceinline__ float4 far_pair_sel(const TS *row, int yf, int S) {
     const bool in = (unsigned)yf < (unsigned)S;
     const float4 v = ld_pair(row + (in ? yf : 0));
     return in ? v : make_float4(0.f, 1.f, 0.f, 1.f);
@@ -1030,8 +1040,10 @@ __device__ void body_merge_down_adj(const DownAdjArgs &a, unsigned tile, int U, 
 // so that a wave waits for memory once rather than once per source: the
 // conditions on x and k are uniform over the wave, absent terms load nothing
 // and add zero, and reads outside the grid take a clamped address and a select.
-template <typename TS>
-__device__ void body_dT(const DTArgs &a, unsigned tile, int U, int tid) {
+// Without ENV the fluence from beyond the grid is the constant 0, which keeps
+// those selects from turning into branches that wait on the environment table.
+template <typename TS, bool ENV>
+__device__ void body_dT_t(const DTArgs &a, unsigned tile, int U, int tid) {
     const int N = a.N, S = 1 << N, n = a.n;
     const size_t SS = (size_t)S * S;
     const int dirs = (1 << n) + 1;
@@ -1045,7 +1057,7 @@ __device__ void body_dT(const DTArgs &a, unsigned tile, int U, int tid) {
         const int q = row / rpq;
         const unsigned r = row % rpq;
         const int x = r / dirs, k = r % dirs;
-        const float *envq = a.env ? a.env + (size_t)q * kConeTable : nullptr;
+        const float *envq = ENV ? a.env + (size_t)q * kConeTable : nullptr;
         // (a) merge down at level n, odd x (Eq. 14): T_n(p, k) is the edge of
         //     cone k (lower half, jj = 2k) and of cone k-1 (upper half, jj = 2k-1):
         //     term i = 0 reads R_n row (x, k-1) and cone 2k-1 of R_{n+1}, i = 1
@@ -1098,6 +1110,8 @@ __device__ void body_dT(const DTArgs &a, unsigned tile, int U, int tid) {
         //     near role (x even): the far partner kb = k, k+1, k-1 at row y + 2k - H;
         //     far role (x odd): the near partner ka = k, k+1, k-1, each from
         //     output row y - (2 ka - H).
+        //     Both roles load one partner interval pair and one dT_{n+1} pair
+        //     per output; the role only moves the rows and the fill.
         float4 cg[3], cf[3];
         float cw[3] = {0.f, 0.f, 0.f};
         const bool near_role = (x & 1) == 0;
@@ -1107,26 +1121,30 @@ __device__ void body_dT(const DTArgs &a, unsigned tile, int U, int tid) {
             const TS *Tq = reinterpret_cast<const TS *>(a.Tn) + q * a.en;
             const float2 *g0 = a.dTn1 + q * a.en1 + (size_t)(x >> 1) * odirs * S;
             const TS *part = Tq + (size_t)(near_role ? x + 1 : x - 1) * dirs * S;
+            bool act[3], in[3];
 #pragma unroll
             for (int v = 0; v < 3; ++v) {
                 const int ko = v == 0 ? 2 * k : (v == 1 ? 2 * k + 1 : 2 * k - 1);
                 const int kp = v == 0 ? k : (v == 1 ? k + 1 : k - 1);
-                cg[v] = make_float4(0.f, 0.f, 0.f, 0.f);
-                cf[v] = make_float4(0.f, 1.f, 0.f, 1.f);
-                if (ko < 0 || ko > 2 * H) continue;
-                cw[v] = v == 0 ? 1.f : 0.5f;
-                if (near_role) {
-                    cf[v] = far_pair(part + (size_t)kp * S, y + 2 * k - H, S);
-                    cg[v] = ld_pair(g0 + (size_t)ko * S + y);
-                } else {
-                    const int yo = y - (2 * kp - H);
-                    const bool in = (unsigned)yo < (unsigned)S;
-                    const int yc = in ? yo : 0;
-                    const float4 tn = ld_pair(part + (size_t)kp * S + yc);
-                    const float4 g = ld_pair(g0 + (size_t)ko * S + yc);
-                    cf[v] = in ? tn : make_float4(0.f, 0.f, 0.f, 0.f);
-                    cg[v] = in ? g : make_float4(0.f, 0.f, 0.f, 0.f);
+                const int yo = near_role ? y + 2 * k - H : y - (2 * kp - H);
+                act[v] = ko >= 0 && ko <= 2 * H;
+                in[v] = (unsigned)yo < (unsigned)S;
+                const int yc = in[v] ? yo : 0;
+                cf[v] = cg[v] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (act[v]) {
+                    cf[v] = ld_pair(part + (size_t)kp * S + yc);
+                    cg[v] = ld_pair(g0 + (size_t)ko * S + (near_role ? y : yc));
                 }
+            }
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                pin(cf[v]);
+                pin(cg[v]);
+                const float4 fill = near_role ? make_float4(0.f, 1.f, 0.f, 1.f)
+                                              : make_float4(0.f, 0.f, 0.f, 0.f);
+                cw[v] = act[v] ? (v == 0 ? 1.f : 0.5f) : 0.f;
+                cf[v] = act[v] ? (in[v] ? cf[v] : fill) : make_float4(0.f, 1.f, 0.f, 1.f);
+                cg[v] = act[v] && (in[v] || near_role) ? cg[v] : make_float4(0.f, 0.f, 0.f, 0.f);
             }
         } else {
 #pragma unroll
@@ -1134,6 +1152,11 @@ __device__ void body_dT(const DTArgs &a, unsigned tile, int U, int tid) {
                 cg[v] = make_float4(0.f, 0.f, 0.f, 0.f);
                 cf[v] = make_float4(0.f, 1.f, 0.f, 1.f);
             }
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            pin(ag[i]); pin(ar[i]); pin(aA[i]);
+            pin(bg[i]); pin(br[i]); pin(bA[i]);
         }
         float gl0 = 0.f, gt0 = 0.f, gl1 = 0.f, gt1 = 0.f;
 #pragma unroll
@@ -1169,6 +1192,14 @@ __device__ void body_dT(const DTArgs &a, unsigned tile, int U, int tid) {
         *reinterpret_cast<float4 *>(a.dT + q * a.en + (size_t)r * S + y) =
             make_float4(gl0, gt0, gl1, gt1);
     }
+}
+
+template <typename TS>
+__device__ void body_dT(const DTArgs &a, unsigned tile, int U, int tid) {
+    if (a.env)
+        body_dT_t<TS, true>(a, tile, U, tid);
+    else
+        body_dT_t<TS, false>(a, tile, U, tid);
 }
 
 // phi'(tau) for phi(tau) = (1 - exp(-tau))/tau: a Taylor series near 0, where
