@@ -915,24 +915,34 @@ __device__ void body_gather_adj(const GatherAdjArgs &a, unsigned tile, char *lds
     const int tx = tid & 31, ty = tid >> 5;
     // Every thread reaches both barriers whatever its tile (tiles of other
     // passes may share the block); tiles past the four quadrants store nothing.
+    // The four loads of a thread are issued before any is used: positions
+    // without a source read a clamped address and take 0 by a select.
     if (q == 2 || q == 3) {
+        float v[4];
+#pragma unroll
         for (int i = 0; i < 4; ++i) {
-            int x = tX * 32 + ty + 8 * i, y = tY * 32 + tx;
-            if (x < S && y < S) {
-                float v = 0.f;
-                if (x >= 1) v = a.dF[(size_t)frame_row(q, x - 1, S) * S + y];
-                a.dR0[q * SS + (size_t)x * S + y] = v;
-            }
+            const int x = tX * 32 + ty + 8 * i, y = tY * 32 + tx;
+            const bool src = x >= 1 && x < S && y < S;
+            v[i] = a.dF[(size_t)frame_row(q, src ? x - 1 : 0, S) * S + (src ? y : 0)];
+            v[i] = src ? v[i] : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int x = tX * 32 + ty + 8 * i, y = tY * 32 + tx;
+            if (x < S && y < S) a.dR0[q * SS + (size_t)x * S + y] = v[i];
         }
     } else if (q < 2) {
         // +-x: frame (u, w) is image (w, u or S-1-u): read image rows w = y.
+        float v[4];
+#pragma unroll
         for (int i = 0; i < 4; ++i) {
-            int yl = ty + 8 * i;
-            int y = tY * 32 + yl, x = tX * 32 + tx;
-            float v = 0.f;
-            if (x < S && y < S && x >= 1) v = a.dF[(size_t)y * S + frame_row(q, x - 1, S)];
-            ga_tile[yl][tx] = v;
+            const int y = tY * 32 + ty + 8 * i, x = tX * 32 + tx;
+            const bool src = x >= 1 && x < S && y < S;
+            v[i] = a.dF[(size_t)(src ? y : 0) * S + frame_row(q, src ? x - 1 : 0, S)];
+            v[i] = src ? v[i] : 0.f;
         }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ga_tile[ty + 8 * i][tx] = v[i];
     }
     __syncthreads();
     if (q < 2) {
@@ -1657,15 +1667,114 @@ __device__ void body_merge_up_rgb(const UpArgs &a, unsigned tile, int U, int tid
     }
 }
 
-// R_m of one quadrant's channel plane at (c, jj) for rows y, y+1 (y even);
-// 0 outside the grid and for R_N.
-__device__ __forceinline__ float2 r_pair0(const float *Rq, int N, int m, int c, int jj, int y) {
-    const int S = 1 << N;
-    if (m >= N || c >= (S >> m) || y < 0 || y >= S) return make_float2(0.f, 0.f);
-    return *reinterpret_cast<const float2 *>(Rq + ((size_t)((c << m) | jj)) * S + y);
+__device__ __forceinline__ float chan(float4 v, int c) { return c == 0 ? v.x : c == 1 ? v.y : v.z; }
+
+// Two consecutive RGB intervals at a shifted row position yf (even), or two
+// empty intervals outside [0, S): a clamped address and a select.
+template <typename TS>
+__device__ __forceinline__ void far_pair_rgb_sel(const TS *row, int yf, int S, float4 &a, float4 &b) {
+    const bool in = (unsigned)yf < (unsigned)S;
+    const int yc = in ? yf : 0;
+    const float4 va = ld4(row + yc), vb = ld4(row + yc + 1);
+    a = in ? va : empty_interval<float4>();
+    b = in ? vb : empty_interval<float4>();
 }
 
-__device__ __forceinline__ float chan(float4 v, int c) { return c == 0 ? v.x : c == 1 ? v.y : v.z; }
+// One pair of rows (y, y+1) of the three R_n planes at probe column x, cone
+// pair ii (cones 2 ii and 2 ii + 1).  As the one-channel merge down, every
+// operand is loaded before any is used, and TOP (n + 1 = N) builds the doubled
+// edges of T_N from T_{N-1} and reads R_N = 0.  Per channel, the arithmetic
+// and its order are those of Eq. 14 (odd x) and Eq. 15-17 (even x).
+template <typename TS, bool TOP>
+__device__ __forceinline__ void merge_down_rgb_pair(const DownArgs &a, int q, int x, int ii, int y,
+                                                    float2 res[3]) {
+    const int N = a.N, S = 1 << N, n = a.n, m = n + 1;
+    const size_t SS = (size_t)S * S;
+    const size_t plane = (size_t)a.nq * SS;
+    const int jb = (1 << m) - 1 + 2 * ii;
+    const float A[2] = {c_cone[jb], c_cone[jb + 1]};
+    float acc0[3] = {0.f, 0.f, 0.f}, acc1[3] = {0.f, 0.f, 0.f};
+    if (x & 1) {
+        // Eq. 14: directions ii + up of this column to probe c of level n+1.
+        const TS *Tx = reinterpret_cast<const TS *>(a.Tn) + q * a.en + (size_t)x * ((1 << n) + 1) * S;
+        const int c = (x + 1) >> 1;
+        const int yr = y + 2 * ii - (1 << n);
+        float4 t0[2], t1[2];
+        float2 rf[2][3];
+#pragma unroll
+        for (int up = 0; up < 2; ++up) {
+            t0[up] = ld4(Tx + (size_t)(ii + up) * S + y);
+            t1[up] = ld4(Tx + (size_t)(ii + up) * S + y + 1);
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch)
+                rf[up][ch] = TOP ? make_float2(0.f, 0.f)
+                                 : r_pair_sel(a.Rn1 + ch * plane + q * SS, N, m, c, 2 * ii + up,
+                                              yr + 2 * up, 0.f);
+        }
+#pragma unroll
+        for (int up = 0; up < 2; ++up) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                acc0[ch] += fmaf(t0[up].w, rf[up][ch].x, A[up] * chan(t0[up], ch));
+                acc1[ch] += fmaf(t1[up].w, rf[up][ch].y, A[up] * chan(t1[up], ch));
+            }
+        }
+    } else {
+        // Eq. 15-17: probe c averaged with the doubled edge T_{n+1}(c, e2),
+        // e2 = 2 ii + 2 up, to probe c + 1; at n = N-1 that edge is built here
+        // as the merge up builds an even direction (Eq. 18).
+        const int c = x >> 1;
+        float4 t0[2], t1[2];
+        if (TOP) {
+            const TS *Tnear = reinterpret_cast<const TS *>(a.Tn) + q * a.en +
+                              (size_t)(2 * c) * ((1 << n) + 1) * S;
+            const TS *Tfar = Tnear + (size_t)((1 << n) + 1) * S;
+            float4 n0[2], n1[2], f0[2], f1[2];
+#pragma unroll
+            for (int up = 0; up < 2; ++up) {
+                n0[up] = ld4(Tnear + (size_t)(ii + up) * S + y);
+                n1[up] = ld4(Tnear + (size_t)(ii + up) * S + y + 1);
+                far_pair_rgb_sel(Tfar + (size_t)(ii + up) * S, y + 2 * ii + 2 * up - (1 << n), S,
+                                 f0[up], f1[up]);
+            }
+#pragma unroll
+            for (int up = 0; up < 2; ++up) {
+                t0[up] = merge(n0[up], f0[up]);
+                t1[up] = merge(n1[up], f1[up]);
+            }
+        } else {
+            const TS *Tx = reinterpret_cast<const TS *>(a.Tn1) + q * a.en1 +
+                           (size_t)c * ((1 << m) + 1) * S;
+#pragma unroll
+            for (int up = 0; up < 2; ++up) {
+                t0[up] = ld4(Tx + (size_t)(2 * ii + 2 * up) * S + y);
+                t1[up] = ld4(Tx + (size_t)(2 * ii + 2 * up) * S + y + 1);
+            }
+        }
+        float2 ra[2][3], rb[2][3];
+#pragma unroll
+        for (int up = 0; up < 2; ++up) {
+            const int yf = y + 4 * ii + 4 * up - (1 << m);
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                const float *Rq = a.Rn1 + ch * plane + q * SS;
+                ra[up][ch] = TOP ? make_float2(0.f, 0.f) : r_pair_sel(Rq, N, m, c, 2 * ii + up, y, 0.f);
+                rb[up][ch] = TOP ? make_float2(0.f, 0.f)
+                                 : r_pair_sel(Rq, N, m, c + 1, 2 * ii + up, yf, 0.f);
+            }
+        }
+#pragma unroll
+        for (int up = 0; up < 2; ++up) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                acc0[ch] += 0.5f * (ra[up][ch].x + fmaf(t0[up].w, rb[up][ch].x, A[up] * chan(t0[up], ch)));
+                acc1[ch] += 0.5f * (ra[up][ch].y + fmaf(t1[up].w, rb[up][ch].y, A[up] * chan(t1[up], ch)));
+            }
+        }
+    }
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) res[ch] = make_float2(acc0[ch], acc1[ch]);
+}
 
 // Merge down (Eq. 14-17) of RGB intervals into three planes, n >= 1, two
 // consecutive y per thread.
@@ -1675,7 +1784,6 @@ __device__ void body_merge_down_rgb(const DownArgs &a, unsigned tile, int U, int
     const size_t SS = (size_t)S * S;
     const size_t plane = (size_t)a.nq * SS;
     const size_t total = (size_t)a.nq * (SS / 2);
-    const int m = n + 1;
     for (int uu = 0; uu < U; ++uu) {
         const size_t idx = ((size_t)tile * U + uu) * 256 + tid;
         if (idx >= total) return;
@@ -1684,64 +1792,14 @@ __device__ void body_merge_down_rgb(const DownArgs &a, unsigned tile, int U, int
         const int q = row >> N;
         const unsigned r = row & (S - 1);
         const int x = r >> n, ii = r & ((1 << n) - 1);
-        float acc0[3] = {0.f, 0.f, 0.f}, acc1[3] = {0.f, 0.f, 0.f};
-        if (x & 1) {
-            // Eq. 14
-            const TS *Tx = reinterpret_cast<const TS *>(a.Tn) + q * a.en +
-                           (size_t)x * ((1 << n) + 1) * S;
-            const int c = (x + 1) >> 1;
-#pragma unroll
-            for (int up = 0; up < 2; ++up) {
-                const int e = ii + up, jj = 2 * ii + up;
-                const float A = c_cone[(1 << m) - 1 + jj];
-                const float4 t0 = ld4(Tx + (size_t)e * S + y), t1 = ld4(Tx + (size_t)e * S + y + 1);
-#pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-                    const float2 rf = r_pair0(a.Rn1 + ch * plane + q * SS, N, m, c, jj,
-                                              y + 2 * e - (1 << n));
-                    acc0[ch] += fmaf(t0.w, rf.x, A * chan(t0, ch));
-                    acc1[ch] += fmaf(t1.w, rf.y, A * chan(t1, ch));
-                }
-            }
-        } else {
-            // Eq. 15-17, with T_N built here at n = N-1 (Eq. 18, even direction)
-            const int c = x >> 1;
-            const bool top = m == N;
-            const TS *Tx = reinterpret_cast<const TS *>(a.Tn1) + q * a.en1 +
-                           (size_t)c * ((1 << m) + 1) * S;
-            const TS *Tnear = reinterpret_cast<const TS *>(a.Tn) + q * a.en +
-                              (size_t)(2 * c) * ((1 << n) + 1) * S;
-            const TS *Tfar = Tnear + (size_t)((1 << n) + 1) * S;
-#pragma unroll
-            for (int up = 0; up < 2; ++up) {
-                const int e2 = 2 * ii + 2 * up, jj = 2 * ii + up;
-                const float A = c_cone[(1 << m) - 1 + jj];
-                float4 t0, t1;
-                if (top) {
-                    const int kk = e2 >> 1;
-                    const float4 n0 = ld4(Tnear + (size_t)kk * S + y), n1 = ld4(Tnear + (size_t)kk * S + y + 1);
-                    float4 f0, f1;
-                    far_pair_rgb(Tfar + (size_t)kk * S, y + e2 - (1 << n), S, f0, f1);
-                    t0 = merge(n0, f0);
-                    t1 = merge(n1, f1);
-                } else {
-                    t0 = ld4(Tx + (size_t)e2 * S + y);
-                    t1 = ld4(Tx + (size_t)e2 * S + y + 1);
-                }
-#pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-                    const float *Rq = a.Rn1 + ch * plane + q * SS;
-                    const float2 ra = r_pair0(Rq, N, m, c, jj, y);
-                    const float2 rb = r_pair0(Rq, N, m, c + 1, jj, y + 2 * e2 - (1 << m));
-                    acc0[ch] += 0.5f * (ra.x + fmaf(t0.w, rb.x, A * chan(t0, ch)));
-                    acc1[ch] += 0.5f * (ra.y + fmaf(t1.w, rb.y, A * chan(t1, ch)));
-                }
-            }
-        }
+        float2 res[3];
+        if (n + 1 == N)
+            merge_down_rgb_pair<TS, true>(a, q, x, ii, y, res);
+        else
+            merge_down_rgb_pair<TS, false>(a, q, x, ii, y, res);
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch)
-            *reinterpret_cast<float2 *>(a.R + ch * plane + q * SS + (size_t)r * S + y) =
-                make_float2(acc0[ch], acc1[ch]);
+            *reinterpret_cast<float2 *>(a.R + ch * plane + q * SS + (size_t)r * S + y) = res[ch];
     }
 }
 
