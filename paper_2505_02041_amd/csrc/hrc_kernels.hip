@@ -495,15 +495,17 @@ __device__ __forceinline__ float4 far_pair_sel(const TS *row, int yf, int S) {
     return in ? v : make_float4(0.f, 1.f, 0.f, 1.f);
 }
 
-// R_{n+1} pair at (c, jj) and rows (y, y+1), y even, or the environment's
-// fluence e outside the grid (column c past the last, or y outside [0, S)):
-// a clamped address and a select.
-__device__ __forceinline__ float2 r_pair_sel(const float *Rq, int N, int m, int c, int jj, int y,
-                                             float e) {
+// R_{n+1} pair at (c, jj) and rows (y, y+1), y even, of the quadrant whose
+// level starts at element rq, or the environment's fluence e outside the grid
+// (column c past the last, or y outside [0, S)): a clamped address and a
+// select.  Element offsets are 32-bit: a level of four quadrants holds at
+// most 2^26 entries (S <= 4096), three channel planes of it 3 x 2^26.
+__device__ __forceinline__ float2 r_pair_sel(const float *R, unsigned rq, int N, int m, int c,
+                                             int jj, int y, float e) {
     const int S = 1 << N;
     const bool in = c < (S >> m) && (unsigned)y < (unsigned)S;
-    const float2 v = *reinterpret_cast<const float2 *>(
-        Rq + ((size_t)(((in ? c : 0) << m) | jj)) * S + (in ? y : 0));
+    const unsigned at = rq + ((unsigned)(((in ? c : 0) << m) | jj) << N) + (unsigned)(in ? y : 0);
+    const float2 v = *reinterpret_cast<const float2 *>(R + at);
     return in ? v : make_float2(e, e);
 }
 
@@ -512,12 +514,14 @@ __device__ __forceinline__ float2 r_pair_sel(const float *Rq, int N, int m, int 
 // included, is loaded before any is used, so a wave waits for memory once;
 // TOP (n + 1 = N) builds the doubled edges of T_N from T_{N-1} and reads the
 // environment for R_N; without ENV the fluence from beyond the grid is 0 (a
-// constant, so the lookups outside the grid stay selects, not branches).  The
-// arithmetic, and its order, is that of Eq. 14 (odd x) and Eq. 15-17 (even x).
+// constant, so the lookups outside the grid stay selects, not branches).
+// Addresses are 32-bit element offsets from the level's base (a T level of
+// four quadrants holds fewer than 2^27 entries).  The arithmetic, and its
+// order, is that of Eq. 14 (odd x) and Eq. 15-17 (even x).
 template <bool TOP, bool ENV>
 __device__ __forceinline__ float2 merge_down_pair(const DownArgs &a, int q, int x, int ii, int y) {
     const int N = a.N, S = 1 << N, n = a.n, m = n + 1;
-    const float *Rq = a.Rn1 + q * (size_t)S * S;
+    const unsigned rq = (unsigned)q << (2 * N);
     const int jb = (1 << m) - 1 + 2 * ii;  // cone table index of cone 2 ii at level m
     const float A0 = c_cone[jb], A1 = c_cone[jb + 1];
     float E0 = 0.f, E1 = 0.f;
@@ -530,15 +534,16 @@ __device__ __forceinline__ float2 merge_down_pair(const DownArgs &a, int q, int 
     if (x & 1) {
         // Eq. 14: the half-cone's outer edge (T_n of this column, directions
         // ii and ii + 1) to the level n+1 probe c.
-        const float2 *Tx = a.Tn + q * a.en + (size_t)x * ((1 << n) + 1) * S;
+        const unsigned tx = (unsigned)q * (unsigned)a.en + ((unsigned)x * ((1u << n) + 1) << N) +
+                            ((unsigned)ii << N) + (unsigned)y;
         const int c = (x + 1) >> 1;
         const int yr = y + 2 * ii - (1 << n);
-        const float4 t0 = ld_pair(Tx + (size_t)ii * S + y);
-        const float4 t1 = ld_pair(Tx + (size_t)(ii + 1) * S + y);
+        const float4 t0 = ld_pair(a.Tn + tx);
+        const float4 t1 = ld_pair(a.Tn + tx + S);
         float2 f0 = make_float2(E0, E0), f1 = make_float2(E1, E1);
         if (!TOP) {
-            f0 = r_pair_sel(Rq, N, m, c, 2 * ii, yr, E0);
-            f1 = r_pair_sel(Rq, N, m, c, 2 * ii + 1, yr + 2, E1);
+            f0 = r_pair_sel(a.Rn1, rq, N, m, c, 2 * ii, yr, E0);
+            f1 = r_pair_sel(a.Rn1, rq, N, m, c, 2 * ii + 1, yr + 2, E1);
         }
         acc0 += fmaf(t0.y, f0.x, A0 * t0.x);
         acc1 += fmaf(t0.w, f0.y, A0 * t0.z);
@@ -553,27 +558,31 @@ __device__ __forceinline__ float2 merge_down_pair(const DownArgs &a, int q, int 
             // T_N(c, e2) as the merge up builds an even direction (Eq. 18):
             // T_{N-1}(2c, e2/2) at row y, then T_{N-1}(2c+1, e2/2) at row
             // y + e2 - 2^n.
-            const float2 *Tnear = a.Tn + q * a.en + (size_t)(2 * c) * ((1 << n) + 1) * S;
-            const float2 *Tfar = Tnear + (size_t)((1 << n) + 1) * S;
-            const float4 nv0 = ld_pair(Tnear + (size_t)ii * S + y);
-            const float4 nv1 = ld_pair(Tnear + (size_t)(ii + 1) * S + y);
-            const float4 fv0 = far_pair_sel(Tfar + (size_t)ii * S, y + 2 * ii - (1 << n), S);
-            const float4 fv1 = far_pair_sel(Tfar + (size_t)(ii + 1) * S, y + 2 * ii + 2 - (1 << n), S);
+            const unsigned dn = (1u << n) + 1;
+            const unsigned tn = (unsigned)q * (unsigned)a.en + ((unsigned)(2 * c) * dn << N) +
+                                ((unsigned)ii << N);
+            const float2 *Tnear = a.Tn + tn;
+            const float2 *Tfar = Tnear + (dn << N);
+            const float4 nv0 = ld_pair(Tnear + y);
+            const float4 nv1 = ld_pair(Tnear + S + y);
+            const float4 fv0 = far_pair_sel(Tfar, y + 2 * ii - (1 << n), S);
+            const float4 fv1 = far_pair_sel(Tfar + S, y + 2 * ii + 2 - (1 << n), S);
             t0 = pair(merge(lo(nv0), lo(fv0)), merge(hi(nv0), hi(fv0)));
             t1 = pair(merge(lo(nv1), lo(fv1)), merge(hi(nv1), hi(fv1)));
         } else {
-            const float2 *Tx = a.Tn1 + q * a.en1 + (size_t)c * ((1 << m) + 1) * S;
-            t0 = ld_pair(Tx + (size_t)(2 * ii) * S + y);
-            t1 = ld_pair(Tx + (size_t)(2 * ii + 2) * S + y);
+            const unsigned tx = (unsigned)q * (unsigned)a.en1 + ((unsigned)c * ((1u << m) + 1) << N) +
+                                ((unsigned)(2 * ii) << N) + (unsigned)y;
+            t0 = ld_pair(a.Tn1 + tx);
+            t1 = ld_pair(a.Tn1 + tx + 2 * S);
         }
         float2 r00 = make_float2(E0, E0), r01 = make_float2(E1, E1);
         float2 r10 = r00, r11 = r01;
         if (!TOP) {
             const int yf = y + 4 * ii - (1 << m);
-            r00 = r_pair_sel(Rq, N, m, c, 2 * ii, y, E0);
-            r01 = r_pair_sel(Rq, N, m, c, 2 * ii + 1, y, E1);
-            r10 = r_pair_sel(Rq, N, m, c + 1, 2 * ii, yf, E0);
-            r11 = r_pair_sel(Rq, N, m, c + 1, 2 * ii + 1, yf + 4, E1);
+            r00 = r_pair_sel(a.Rn1, rq, N, m, c, 2 * ii, y, E0);
+            r01 = r_pair_sel(a.Rn1, rq, N, m, c, 2 * ii + 1, y, E1);
+            r10 = r_pair_sel(a.Rn1, rq, N, m, c + 1, 2 * ii, yf, E0);
+            r11 = r_pair_sel(a.Rn1, rq, N, m, c + 1, 2 * ii + 1, yf + 4, E1);
         }
         acc0 += 0.5f * (r00.x + fmaf(t0.y, r10.x, A0 * t0.x));
         acc1 += 0.5f * (r00.y + fmaf(t0.w, r10.y, A0 * t0.z));
@@ -1708,7 +1717,7 @@ __device__ __forceinline__ void merge_down_rgb_pair(const DownArgs &a, int q, in
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch)
                 rf[up][ch] = TOP ? make_float2(0.f, 0.f)
-                                 : r_pair_sel(a.Rn1 + ch * plane + q * SS, N, m, c, 2 * ii + up,
+                                 : r_pair_sel(a.Rn1, (unsigned)(ch * plane + q * SS), N, m, c, 2 * ii + up,
                                               yr + 2 * up, 0.f);
         }
 #pragma unroll
@@ -1757,10 +1766,11 @@ __device__ __forceinline__ void merge_down_rgb_pair(const DownArgs &a, int q, in
             const int yf = y + 4 * ii + 4 * up - (1 << m);
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
-                const float *Rq = a.Rn1 + ch * plane + q * SS;
-                ra[up][ch] = TOP ? make_float2(0.f, 0.f) : r_pair_sel(Rq, N, m, c, 2 * ii + up, y, 0.f);
+                const unsigned rq = (unsigned)(ch * plane + q * SS);
+                ra[up][ch] = TOP ? make_float2(0.f, 0.f)
+                                 : r_pair_sel(a.Rn1, rq, N, m, c, 2 * ii + up, y, 0.f);
                 rb[up][ch] = TOP ? make_float2(0.f, 0.f)
-                                 : r_pair_sel(Rq, N, m, c + 1, 2 * ii + up, yf, 0.f);
+                                 : r_pair_sel(a.Rn1, rq, N, m, c + 1, 2 * ii + up, yf, 0.f);
             }
         }
 #pragma unroll
