@@ -203,11 +203,16 @@ __device__ __forceinline__ float4 far_pair(const TS *row, int yf, int S) {
 // Four consecutive 16-bit intervals (two pairs) at y, y a multiple of 4: one
 // 16-byte load.
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
-__device__ __forceinline__ void ld_quad(const half2_t *p, float4 &a, float4 &b) {
-    const half8_t v = *reinterpret_cast<const half8_t *>(p);
+__device__ __forceinline__ void cvt_quad(half8_t v, float4 &a, float4 &b) {
     a = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
     b = make_float4((float)v[4], (float)v[5], (float)v[6], (float)v[7]);
 }
+__device__ __forceinline__ void ld_quad(const half2_t *p, float4 &a, float4 &b) {
+    cvt_quad(*reinterpret_cast<const half8_t *>(p), a, b);
+}
+// Raw 16-bit loads pinned as they are, before their conversion (see pin).
+__device__ __forceinline__ void pin(half8_t &v) { asm volatile("" : "+v"(v)); }
+__device__ __forceinline__ void pin(half4_t &v) { asm volatile("" : "+v"(v)); }
 __device__ __forceinline__ void st_quad(half2_t *p, float4 a, float4 b) {
     half8_t h;
     h[0] = to_half(a.x); h[1] = to_half(a.y); h[2] = to_half(a.z); h[3] = to_half(a.w);
@@ -458,36 +463,6 @@ __device__ void body_merge_up(const UpArgs &a, unsigned tile, int U, int tid) {
     }
 }
 
-// R_m of one quadrant at (c, jj) for the row pair (y, y+1), y even; outside the
-// grid, and for R_N, the environment's fluence (0 without one).
-__device__ __forceinline__ float2 r_pair(const float *Rq, int N, int m, int c, int jj, int y,
-                                         const float *envq) {
-    const int S = 1 << N;
-    if (m >= N || c >= (S >> m) || y < 0 || y >= S) {
-        const float e = env_fluence(envq, m, jj);
-        return make_float2(e, e);
-    }
-    return *reinterpret_cast<const float2 *>(Rq + ((size_t)((c << m) | jj)) * S + y);
-}
-
-// The same for rows y .. y+3 (y even): one 16-byte load when y is a multiple of
-// 4 (uniform over the wave, as in far_quad) and the four lie in the grid, else
-// two pair lookups.
-__device__ __forceinline__ void r_quad(const float *Rq, int N, int m, int c, int jj, int y,
-                                       const float *envq, float2 &a, float2 &b) {
-    const int S = 1 << N;
-    if ((y & 3) == 0 && m < N && c < (S >> m) && y >= 0 && y < S) {
-        const float4 v = *reinterpret_cast<const float4 *>(Rq + ((size_t)((c << m) | jj)) * S + y);
-        a = make_float2(v.x, v.y);
-        b = make_float2(v.z, v.w);
-    } else {
-        a = r_pair(Rq, N, m, c, jj, y, envq);
-        b = r_pair(Rq, N, m, c, jj, y + 2, envq);
-    }
-}
-
-// Interval pair at a shifted row position yf of a row, or <0, 1> twice
-// outside [0, S): a clamped address and a select, so the lookup has no branch.
 template <typename TS>
 __device__ __forceinline__ float4 far_pair_sel(const TS *row, int yf, int S) {
     const bool in = (unsigned)yf < (unsigned)S;
@@ -592,6 +567,136 @@ __device__ __forceinline__ float2 merge_down_pair(const DownArgs &a, int q, int 
     return make_float2(acc0, acc1);
 }
 
+// R_{n+1} at (c, jj) for rows y .. y+3, y a multiple of 4 (so the four are in
+// or out of the grid together), or the environment's fluence e outside it: a
+// clamped address and a select.
+__device__ __forceinline__ float4 r_quad_sel(const float *R, unsigned rq, int N, int m, int c,
+                                             int jj, int y, float e) {
+    const int S = 1 << N;
+    const bool in = c < (S >> m) && (unsigned)y < (unsigned)S;
+    const unsigned at = rq + ((unsigned)(((in ? c : 0) << m) | jj) << N) + (unsigned)(in ? y : 0);
+    const float4 v = *reinterpret_cast<const float4 *>(R + at);
+    return in ? v : make_float4(e, e, e, e);
+}
+
+// The 16-bit form of merge_down_pair: rows y .. y+3 (y a multiple of 4) of
+// R_n, each T row read as one quad of intervals, and every operand loaded
+// before any is used.  Lookups whose row shift is only even (Eq. 14, and the
+// far end of T_N's doubled edges) take two pairs, each with its own select.
+template <bool TOP, bool ENV>
+__device__ __forceinline__ float4 merge_down_quad(const DownArgs &a, int q, int x, int ii, int y) {
+    const int N = a.N, S = 1 << N, n = a.n, m = n + 1;
+    const unsigned rq = (unsigned)q << (2 * N);
+    const half2_t *Tn = reinterpret_cast<const half2_t *>(a.Tn);
+    const half2_t *Tn1 = reinterpret_cast<const half2_t *>(a.Tn1);
+    const int jb = (1 << m) - 1 + 2 * ii;
+    const float A[2] = {c_cone[jb], c_cone[jb + 1]};
+    float E[2] = {0.f, 0.f};
+    if (ENV) {
+        const float *ep = a.env + (size_t)(a.q0 + q) * kConeTable + jb;
+        E[0] = ep[0];
+        E[1] = ep[1];
+    }
+    float acc0[2] = {0.f, 0.f}, acc1[2] = {0.f, 0.f};
+    if (x & 1) {
+        // Eq. 14
+        const unsigned tx = (unsigned)q * (unsigned)a.en + ((unsigned)x * ((1u << n) + 1) << N) +
+                            ((unsigned)ii << N) + (unsigned)y;
+        const int c = (x + 1) >> 1;
+        const int yr = y + 2 * ii - (1 << n);
+        half8_t h[2];
+        float2 rf[2][2];
+#pragma unroll
+        for (int up = 0; up < 2; ++up) {
+            h[up] = *reinterpret_cast<const half8_t *>(Tn + tx + up * S);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                rf[up][j] = TOP ? make_float2(E[up], E[up])
+                                : r_pair_sel(a.Rn1, rq, N, m, c, 2 * ii + up, yr + 2 * up + 2 * j, E[up]);
+        }
+#pragma unroll
+        for (int up = 0; up < 2; ++up) {
+            pin(h[up]);
+            float4 t[2];
+            cvt_quad(h[up], t[0], t[1]);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                acc0[j] += fmaf(t[j].y, rf[up][j].x, A[up] * t[j].x);
+                acc1[j] += fmaf(t[j].w, rf[up][j].y, A[up] * t[j].z);
+            }
+        }
+    } else {
+        // Eq. 15-17
+        const int c = x >> 1;
+        float4 t[2][2];
+        if (TOP) {
+            const unsigned dn = (1u << n) + 1;
+            const unsigned tn = (unsigned)q * (unsigned)a.en + ((unsigned)(2 * c) * dn << N) +
+                                ((unsigned)ii << N);
+            half8_t hn[2];
+            half4_t hf[2][2];
+            bool in[2][2];
+#pragma unroll
+            for (int up = 0; up < 2; ++up) {
+                const half2_t *near = Tn + tn + up * S, *far = near + (dn << N);
+                const int yf = y + 2 * ii + 2 * up - (1 << n);
+                hn[up] = *reinterpret_cast<const half8_t *>(near + y);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    in[up][j] = (unsigned)(yf + 2 * j) < (unsigned)S;
+                    hf[up][j] = *reinterpret_cast<const half4_t *>(far + (in[up][j] ? yf + 2 * j : 0));
+                }
+            }
+#pragma unroll
+            for (int up = 0; up < 2; ++up) {
+                pin(hn[up]);
+                float4 nv[2];
+                cvt_quad(hn[up], nv[0], nv[1]);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    pin(hf[up][j]);
+                    const half4_t v = hf[up][j];
+                    const float4 fv = in[up][j] ? make_float4((float)v.x, (float)v.y, (float)v.z, (float)v.w)
+                                                : make_float4(0.f, 1.f, 0.f, 1.f);
+                    t[up][j] = pair(merge(lo(nv[j]), lo(fv)), merge(hi(nv[j]), hi(fv)));
+                }
+            }
+        } else {
+            const unsigned tx = (unsigned)q * (unsigned)a.en1 + ((unsigned)c * ((1u << m) + 1) << N) +
+                                ((unsigned)(2 * ii) << N) + (unsigned)y;
+            half8_t h[2];
+#pragma unroll
+            for (int up = 0; up < 2; ++up) h[up] = *reinterpret_cast<const half8_t *>(Tn1 + tx + 2 * up * S);
+#pragma unroll
+            for (int up = 0; up < 2; ++up) {
+                pin(h[up]);
+                cvt_quad(h[up], t[up][0], t[up][1]);
+            }
+        }
+        float4 r0[2], r1[2];
+#pragma unroll
+        for (int up = 0; up < 2; ++up) {
+            const float e = E[up];
+            r0[up] = r1[up] = make_float4(e, e, e, e);
+            if (!TOP) {
+                r0[up] = r_quad_sel(a.Rn1, rq, N, m, c, 2 * ii + up, y, e);
+                r1[up] = r_quad_sel(a.Rn1, rq, N, m, c + 1, 2 * ii + up, y + 4 * ii + 4 * up - (1 << m), e);
+            }
+        }
+#pragma unroll
+        for (int up = 0; up < 2; ++up) {
+            const float2 ra[2] = {make_float2(r0[up].x, r0[up].y), make_float2(r0[up].z, r0[up].w)};
+            const float2 rb[2] = {make_float2(r1[up].x, r1[up].y), make_float2(r1[up].z, r1[up].w)};
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                acc0[j] += 0.5f * (ra[j].x + fmaf(t[up][j].y, rb[j].x, A[up] * t[up][j].x));
+                acc1[j] += 0.5f * (ra[j].y + fmaf(t[up][j].w, rb[j].y, A[up] * t[up][j].z));
+            }
+        }
+    }
+    return make_float4(acc0[0], acc1[0], acc0[1], acc1[1]);
+}
+
 // Merge down: R_n from R_{n+1}, T_n, T_{n+1} (Eq. 14-17), for n >= 1 (levels 1
 // and 0 of the forward are the tail's, and the reverse reads R_1 at the
 // lowest), so every row shift is even and each lookup is a pair.
@@ -632,65 +737,15 @@ __device__ void body_merge_down(const DownArgs &a, unsigned tile, int U, int tid
                            : merge_down_pair<false, false>(a, q, x, ii, y0);
             *reinterpret_cast<float2 *>(out) = v;
         } else {
-        // 16-bit intervals: rows y0 .. y0+3 per thread, each T row one quad.
-        const float *Rq = a.Rn1 + q * SS;
-        const float *envq = a.env ? a.env + (size_t)(a.q0 + q) * kConeTable : nullptr;
-        float acc0[2] = {0.f, 0.f}, acc1[2] = {0.f, 0.f};
-        if (x & 1) {
-            // Eq. 14: trace the half-cone's outer edge to the level n+1 probe.
-            const TS *Tx = reinterpret_cast<const TS *>(a.Tn) + q * a.en + (size_t)x * ((1 << n) + 1) * S;
-            const int c = (x + 1) >> 1;
-#pragma unroll
-            for (int up = 0; up < 2; ++up) {
-                const int e = ii + up, jj = 2 * ii + up;
-                const float A = c_cone[(1 << m) - 1 + jj];
-                float4 t[2];
-                float2 rf[2];
-                ld_quad(Tx + (size_t)e * S + y0, t[0], t[1]);
-                r_quad(Rq, N, m, c, jj, y0 + 2 * e - (1 << n), envq, rf[0], rf[1]);
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    acc0[j] += fmaf(t[j].y, rf[j].x, A * t[j].x);
-                    acc1[j] += fmaf(t[j].w, rf[j].y, A * t[j].z);
-                }
-            }
-        } else {
-            // Eq. 15-17: average the co-located probe with the doubled-edge trace.
-            // At n = N-1 the doubled edge T_N(c, e2) is built here, as the merge
-            // up would (Eq. 18, even direction): T_{N-1}(2c, e2/2) at row y,
-            // then T_{N-1}(2c+1, e2/2) at row y + e2 - 2^n.
-            const int c = x >> 1;
-            const bool top = m == N;
-            const TS *Tx = reinterpret_cast<const TS *>(a.Tn1) + q * a.en1 + (size_t)c * ((1 << m) + 1) * S;
-            const TS *Tnear = reinterpret_cast<const TS *>(a.Tn) + q * a.en + (size_t)(2 * c) * ((1 << n) + 1) * S;
-            const TS *Tfar = Tnear + (size_t)((1 << n) + 1) * S;
-#pragma unroll
-            for (int up = 0; up < 2; ++up) {
-                const int e2 = 2 * ii + 2 * up, jj = 2 * ii + up;
-                const float A = c_cone[(1 << m) - 1 + jj];
-                float4 t[2];
-                if (top) {
-                    const int kk = e2 >> 1;
-                    float4 nv[2], fv[2];
-                    ld_quad(Tnear + (size_t)kk * S + y0, nv[0], nv[1]);
-                    far_quad(Tfar + (size_t)kk * S, y0 + e2 - (1 << n), S, fv[0], fv[1]);
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        t[j] = pair(merge(lo(nv[j]), lo(fv[j])), merge(hi(nv[j]), hi(fv[j])));
-                } else {
-                    ld_quad(Tx + (size_t)e2 * S + y0, t[0], t[1]);
-                }
-                float2 r0[2], r1[2];
-                r_quad(Rq, N, m, c, jj, y0, envq, r0[0], r0[1]);
-                r_quad(Rq, N, m, c + 1, jj, y0 + 2 * e2 - (1 << m), envq, r1[0], r1[1]);
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    acc0[j] += 0.5f * (r0[j].x + fmaf(t[j].y, r1[j].x, A * t[j].x));
-                    acc1[j] += 0.5f * (r0[j].y + fmaf(t[j].w, r1[j].y, A * t[j].z));
-                }
-            }
-        }
-        *reinterpret_cast<float4 *>(out) = make_float4(acc0[0], acc1[0], acc0[1], acc1[1]);
+            // 16-bit intervals: rows y0 .. y0+3 per thread, each T row one quad.
+            float4 v;
+            if (a.env)
+                v = m == N ? merge_down_quad<true, true>(a, q, x, ii, y0)
+                           : merge_down_quad<false, true>(a, q, x, ii, y0);
+            else
+                v = m == N ? merge_down_quad<true, false>(a, q, x, ii, y0)
+                           : merge_down_quad<false, false>(a, q, x, ii, y0);
+            *reinterpret_cast<float4 *>(out) = v;
         }
     }
 }
