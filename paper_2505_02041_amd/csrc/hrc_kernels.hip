@@ -213,6 +213,35 @@ __device__ __forceinline__ void ld_quad(const half2_t *p, float4 &a, float4 &b) 
 // Raw 16-bit loads pinned as they are, before their conversion (see pin).
 __device__ __forceinline__ void pin(half8_t &v) { asm volatile("" : "+v"(v)); }
 __device__ __forceinline__ void pin(half4_t &v) { asm volatile("" : "+v"(v)); }
+// A far row's two interval pairs at yf and yf + 2 (yf even) as raw halves,
+// outside [0, S) from a clamped address, with the flags that select <0, 1>
+// for them once converted.
+__device__ __forceinline__ void far_pairs_raw(const half2_t *row, int yf, int S, half4_t h[2],
+                                              bool in[2]) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        in[j] = (unsigned)(yf + 2 * j) < (unsigned)S;
+        h[j] = *reinterpret_cast<const half4_t *>(row + (in[j] ? yf + 2 * j : 0));
+    }
+}
+// An interval pair as stored (FP32, or four halves), loaded without its
+// conversion, so that it can be pinned before it is used.
+template <typename TS> struct PairRaw;
+template <> struct PairRaw<float2> { using type = float4; };
+template <> struct PairRaw<half2_t> { using type = half4_t; };
+template <typename TS> __device__ __forceinline__ typename PairRaw<TS>::type raw_zero() {
+    return typename PairRaw<TS>::type{0, 0, 0, 0};
+}
+__device__ __forceinline__ float4 ld_pair_raw(const float2 *p) { return *reinterpret_cast<const float4 *>(p); }
+__device__ __forceinline__ half4_t ld_pair_raw(const half2_t *p) { return *reinterpret_cast<const half4_t *>(p); }
+__device__ __forceinline__ float4 cvt_pair(float4 v) { return v; }
+__device__ __forceinline__ float4 cvt_pair(half4_t v) {
+    return make_float4((float)v.x, (float)v.y, (float)v.z, (float)v.w);
+}
+__device__ __forceinline__ float4 far_pair_cvt(half4_t v, bool in) {
+    return in ? make_float4((float)v.x, (float)v.y, (float)v.z, (float)v.w)
+              : make_float4(0.f, 1.f, 0.f, 1.f);
+}
 __device__ __forceinline__ void st_quad(half2_t *p, float4 a, float4 b) {
     half8_t h;
     h[0] = to_half(a.x); h[1] = to_half(a.y); h[2] = to_half(a.z); h[3] = to_half(a.w);
@@ -406,26 +435,48 @@ __device__ void body_merge_up(const UpArgs &a, unsigned tile, int U, int tid) {
         const TS *far = near + (size_t)pdirs * S;
         float4 res[P];
         if constexpr (P == 2) {
-            // 16-bit intervals: each row read as one quad (two pairs) per thread
+            // 16-bit intervals: each near row read as one quad (two pairs) per
+            // thread, each far row as two pairs (its shift is only even); the
+            // raw halves are all loaded, and pinned, before any is converted
             if ((k & 1) == 0) {
                 const int kk = k >> 1;
-                float4 nv[2], fv[2];
-                ld_quad(near + (size_t)kk * S + y0, nv[0], nv[1]);
-                far_quad(far + (size_t)kk * S, y0 + 2 * kk - h, S, fv[0], fv[1]);
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    res[j] = pair(merge(lo(nv[j]), lo(fv[j])), merge(hi(nv[j]), hi(fv[j])));
-            } else {
-                const int ka = (k + 1) >> 1, kb = (k - 1) >> 1;
-                float4 na[2], nb[2], fa[2], fb[2];
-                ld_quad(near + (size_t)ka * S + y0, na[0], na[1]);
-                ld_quad(near + (size_t)kb * S + y0, nb[0], nb[1]);
-                far_quad(far + (size_t)kb * S, y0 + 2 * ka - h, S, fa[0], fa[1]);
-                far_quad(far + (size_t)ka * S, y0 + 2 * kb - h, S, fb[0], fb[1]);
+                half8_t hn = *reinterpret_cast<const half8_t *>(near + (size_t)kk * S + y0);
+                half4_t hf[2];
+                bool in[2];
+                far_pairs_raw(far + (size_t)kk * S, y0 + 2 * kk - h, S, hf, in);
+                pin(hn);
+                pin(hf[0]);
+                pin(hf[1]);
+                float4 nv[2];
+                cvt_quad(hn, nv[0], nv[1]);
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
-                    const float2 p0 = merge(lo(na[j]), lo(fa[j])), m0 = merge(lo(nb[j]), lo(fb[j]));
-                    const float2 p1 = merge(hi(na[j]), hi(fa[j])), m1 = merge(hi(nb[j]), hi(fb[j]));
+                    const float4 fv = far_pair_cvt(hf[j], in[j]);
+                    res[j] = pair(merge(lo(nv[j]), lo(fv)), merge(hi(nv[j]), hi(fv)));
+                }
+            } else {
+                const int ka = (k + 1) >> 1, kb = (k - 1) >> 1;
+                half8_t hna = *reinterpret_cast<const half8_t *>(near + (size_t)ka * S + y0);
+                half8_t hnb = *reinterpret_cast<const half8_t *>(near + (size_t)kb * S + y0);
+                half4_t hfa[2], hfb[2];
+                bool ina[2], inb[2];
+                far_pairs_raw(far + (size_t)kb * S, y0 + 2 * ka - h, S, hfa, ina);
+                far_pairs_raw(far + (size_t)ka * S, y0 + 2 * kb - h, S, hfb, inb);
+                pin(hna);
+                pin(hnb);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    pin(hfa[j]);
+                    pin(hfb[j]);
+                }
+                float4 na[2], nb[2];
+                cvt_quad(hna, na[0], na[1]);
+                cvt_quad(hnb, nb[0], nb[1]);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const float4 fa = far_pair_cvt(hfa[j], ina[j]), fb = far_pair_cvt(hfb[j], inb[j]);
+                    const float2 p0 = merge(lo(na[j]), lo(fa)), m0 = merge(lo(nb[j]), lo(fb));
+                    const float2 p1 = merge(hi(na[j]), hi(fa)), m1 = merge(hi(nb[j]), hi(fb));
                     res[j] = make_float4(0.5f * (p0.x + m0.x), 0.5f * (p0.y + m0.y),
                                          0.5f * (p1.x + m1.x), 0.5f * (p1.y + m1.y));
                 }
@@ -1196,6 +1247,7 @@ __device__ void body_dT_t(const DTArgs &a, unsigned tile, int U, int tid) {
             const float2 *g0 = a.dTn1 + q * a.en1 + (size_t)(x >> 1) * odirs * S;
             const TS *part = Tq + (size_t)(near_role ? x + 1 : x - 1) * dirs * S;
             bool act[3], in[3];
+            typename PairRaw<TS>::type cr[3];
 #pragma unroll
             for (int v = 0; v < 3; ++v) {
                 const int ko = v == 0 ? 2 * k : (v == 1 ? 2 * k + 1 : 2 * k - 1);
@@ -1204,16 +1256,18 @@ __device__ void body_dT_t(const DTArgs &a, unsigned tile, int U, int tid) {
                 act[v] = ko >= 0 && ko <= 2 * H;
                 in[v] = (unsigned)yo < (unsigned)S;
                 const int yc = in[v] ? yo : 0;
-                cf[v] = cg[v] = make_float4(0.f, 0.f, 0.f, 0.f);
+                cr[v] = raw_zero<TS>();
+                cg[v] = make_float4(0.f, 0.f, 0.f, 0.f);
                 if (act[v]) {
-                    cf[v] = ld_pair(part + (size_t)kp * S + yc);
+                    cr[v] = ld_pair_raw(part + (size_t)kp * S + yc);
                     cg[v] = ld_pair(g0 + (size_t)ko * S + (near_role ? y : yc));
                 }
             }
 #pragma unroll
             for (int v = 0; v < 3; ++v) {
-                pin(cf[v]);
+                pin(cr[v]);
                 pin(cg[v]);
+                cf[v] = cvt_pair(cr[v]);
                 const float4 fill = near_role ? make_float4(0.f, 1.f, 0.f, 1.f)
                                               : make_float4(0.f, 0.f, 0.f, 0.f);
                 cw[v] = act[v] ? (v == 0 ? 1.f : 0.5f) : 0.f;
