@@ -1089,6 +1089,20 @@ __device__ __forceinline__ float2 ld2_r(bool in, const float *row, int y, int S,
     return make_float2(ok0 ? a0 : fill, ok1 ? a1 : fill);
 }
 
+// ld2_r for the row that starts at element `row` of `base` (32-bit offsets).
+__device__ __forceinline__ float2 ld2_r_at(bool in, const float *base, unsigned row, int y, int S,
+                                           bool even, float fill) {
+    if (!in) return make_float2(fill, fill);
+    if (even) {
+        const bool ok = (unsigned)y < (unsigned)S;
+        const float2 v = *reinterpret_cast<const float2 *>(base + (row + (unsigned)(ok ? y : 0)));
+        return ok ? v : make_float2(fill, fill);
+    }
+    const bool ok0 = (unsigned)y < (unsigned)S, ok1 = (unsigned)(y + 1) < (unsigned)S;
+    const float a0 = base[row + (unsigned)(ok0 ? y : 0)], a1 = base[row + (unsigned)(ok1 ? y + 1 : 0)];
+    return make_float2(ok0 ? a0 : fill, ok1 ? a1 : fill);
+}
+
 // Adjoint of the merge down: dR_{n+1} from dR_n (gather form).  Each R_{n+1}
 // entry (c, jj, y') is read by at most three R_n entries: the odd column 2c-1
 // (far end of Eq. 14), the even column 2c (F^0 of Eq. 16) and the even column
@@ -1159,6 +1173,17 @@ __device__ void body_merge_down_adj(const DownAdjArgs &a, unsigned tile, int U, 
     }
 }
 
+// floor(r / d) for a row index r = x d + k of a level (d = 2^n + 1 directions,
+// 0 <= k < d, x below 2^12, so r below 2^14): the single-precision estimate
+// is within one of x, and one correction each way makes it exact, in a few
+// instructions where an integer division takes some thirty.
+__device__ __forceinline__ unsigned div_rows(unsigned r, unsigned d) {
+    unsigned x = (unsigned)((float)r * __builtin_amdgcn_rcpf((float)d));
+    x = x * d > r ? x - 1 : x;
+    x = (x + 1) * d <= r ? x + 1 : x;
+    return x;
+}
+
 // Adjoint of the interval pyramid: dT_n (gather form) from the merge down at
 // levels n and n-1 and from the merge up of T_{n+1}.  Two consecutive y per
 // thread.  Every operand is loaded first and the terms are added afterwards,
@@ -1170,7 +1195,6 @@ __device__ void body_merge_down_adj(const DownAdjArgs &a, unsigned tile, int U, 
 template <typename TS, bool ENV>
 __device__ void body_dT_t(const DTArgs &a, unsigned tile, int U, int tid) {
     const int N = a.N, S = 1 << N, n = a.n;
-    const size_t SS = (size_t)S * S;
     const int dirs = (1 << n) + 1;
     const unsigned rpq = (unsigned)(S >> n) * dirs;
     const size_t total = (size_t)4 * rpq * (S / 2);
@@ -1179,10 +1203,13 @@ __device__ void body_dT_t(const DTArgs &a, unsigned tile, int U, int tid) {
         if (idx >= total) return;
         const int y = (int)(idx & (S / 2 - 1)) * 2;
         const unsigned row = (unsigned)(idx >> (N - 1));
-        const int q = row / rpq;
-        const unsigned r = row % rpq;
-        const int x = r / dirs, k = r % dirs;
+        const int q = (row >= rpq) + (row >= 2 * rpq) + (row >= 3 * rpq);
+        const unsigned r = row - (unsigned)q * rpq;
+        const int x = (int)div_rows(r, (unsigned)dirs), k = (int)(r - (unsigned)x * dirs);
         const float *envq = ENV ? a.env + (size_t)q * kConeTable : nullptr;
+        // element offsets within each level are 32-bit (a level of four
+        // quadrants holds fewer than 2^28 entries)
+        const unsigned qS = (unsigned)q << (2 * N);
         // (a) merge down at level n, odd x (Eq. 14): T_n(p, k) is the edge of
         //     cone k (lower half, jj = 2k) and of cone k-1 (upper half, jj = 2k-1):
         //     term i = 0 reads R_n row (x, k-1) and cone 2k-1 of R_{n+1}, i = 1
@@ -1191,18 +1218,17 @@ __device__ void body_dT_t(const DTArgs &a, unsigned tile, int U, int tid) {
         float2 ar[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
         float aA[2] = {0.f, 0.f};
         if (n < N && (x & 1)) {
-            const float *dRq = a.dRn + q * SS;
-            const float *Rq = a.Rn1 + q * SS;
             const int c = (x + 1) >> 1, yf = y + 2 * k - (1 << n);  // odd when n = 0
             const bool rin = n + 1 < N && c < (S >> (n + 1));
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 const int ii = k - 1 + i, jj = 2 * k - 1 + i;
                 if (ii < 0 || ii >= (1 << n)) continue;
-                ag[i] = *reinterpret_cast<const float2 *>(dRq + ((size_t)((x << n) | ii)) * S + y);
+                ag[i] = *reinterpret_cast<const float2 *>(
+                    a.dRn + (qS + ((unsigned)((x << n) | ii) << N) + (unsigned)y));
                 aA[i] = c_cone[(1 << (n + 1)) - 1 + jj];
-                ar[i] = ld2_r(rin, Rq + ((size_t)((c << (n + 1)) | jj)) * S, yf, S, n > 0,
-                              env_fluence(envq, n + 1, jj));
+                ar[i] = ld2_r_at(rin, a.Rn1, qS + ((unsigned)((c << (n + 1)) | jj) << N), yf, S,
+                                 n > 0, env_fluence(envq, n + 1, jj));
             }
         }
         // (b) merge down at level n-1, even column 2x (Eq. 17): T_n(p, k), k even,
@@ -1214,8 +1240,6 @@ __device__ void body_dT_t(const DTArgs &a, unsigned tile, int U, int tid) {
         float bA[2] = {0.f, 0.f};
         if (n >= 1 && (k & 1) == 0) {
             const int nm = n - 1;
-            const float *dRq = a.dRm + q * SS;
-            const float *Rq = a.Rn + q * SS;
             const int yf = y + 2 * k - (1 << n);
             const int xm = 2 * x;
             const bool rin = n < N && x + 1 < (S >> n);
@@ -1224,10 +1248,10 @@ __device__ void body_dT_t(const DTArgs &a, unsigned tile, int U, int tid) {
                 const int jj = k - 1 + i;
                 if (jj < 0 || jj >= (1 << n)) continue;
                 bg[i] = *reinterpret_cast<const float2 *>(
-                    dRq + ((size_t)((xm << nm) | (k / 2 - 1 + i))) * S + y);
+                    a.dRm + (qS + ((unsigned)((xm << nm) | (k / 2 - 1 + i)) << N) + (unsigned)y));
                 bA[i] = c_cone[(1 << n) - 1 + jj];
-                br[i] = ld2_r(rin, Rq + ((size_t)(((x + 1) << n) | jj)) * S, yf, S, true,
-                              env_fluence(envq, n, jj));
+                br[i] = ld2_r_at(rin, a.Rn, qS + ((unsigned)(((x + 1) << n) | jj) << N), yf, S, true,
+                                 env_fluence(envq, n, jj));
             }
         }
         // (c) merge up of T_{n+1} from T_n (Eq. 18-20), H = 2^n (n >= 2: even
@@ -1243,9 +1267,10 @@ __device__ void body_dT_t(const DTArgs &a, unsigned tile, int U, int tid) {
         if (a.has_up) {
             const int H = 1 << n;
             const int odirs = 2 * H + 1;
-            const TS *Tq = reinterpret_cast<const TS *>(a.Tn) + q * a.en;
-            const float2 *g0 = a.dTn1 + q * a.en1 + (size_t)(x >> 1) * odirs * S;
-            const TS *part = Tq + (size_t)(near_role ? x + 1 : x - 1) * dirs * S;
+            const TS *Tn = reinterpret_cast<const TS *>(a.Tn);
+            const unsigned g0 = (unsigned)q * (unsigned)a.en1 + ((unsigned)((x >> 1) * odirs) << N);
+            const unsigned part = (unsigned)q * (unsigned)a.en +
+                                  ((unsigned)((near_role ? x + 1 : x - 1) * dirs) << N);
             bool act[3], in[3];
             typename PairRaw<TS>::type cr[3];
 #pragma unroll
@@ -1259,8 +1284,8 @@ __device__ void body_dT_t(const DTArgs &a, unsigned tile, int U, int tid) {
                 cr[v] = raw_zero<TS>();
                 cg[v] = make_float4(0.f, 0.f, 0.f, 0.f);
                 if (act[v]) {
-                    cr[v] = ld_pair_raw(part + (size_t)kp * S + yc);
-                    cg[v] = ld_pair(g0 + (size_t)ko * S + (near_role ? y : yc));
+                    cr[v] = ld_pair_raw(Tn + (part + ((unsigned)kp << N) + (unsigned)yc));
+                    cg[v] = ld_pair(a.dTn1 + (g0 + ((unsigned)ko << N) + (unsigned)(near_role ? y : yc)));
                 }
             }
 #pragma unroll
@@ -1317,7 +1342,7 @@ __device__ void body_dT_t(const DTArgs &a, unsigned tile, int U, int tid) {
                 gt1 = fmaf(cw[v] * g.w, tn.w, gt1);
             }
         }
-        *reinterpret_cast<float4 *>(a.dT + q * a.en + (size_t)r * S + y) =
+        *reinterpret_cast<float4 *>(a.dT + ((unsigned)q * (unsigned)a.en + (r << N) + (unsigned)y)) =
             make_float4(gl0, gt0, gl1, gt1);
     }
 }
