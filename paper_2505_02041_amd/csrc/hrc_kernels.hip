@@ -410,6 +410,17 @@ __device__ void body_seed(const SeedArgs &a, unsigned tile, char *lds, int tid) 
 // has 16 bytes of each row in flight).
 template <typename TS> constexpr int merge_pairs() { return sizeof(TS) == 4 ? 2 : 1; }
 
+// floor(r / d) for a row index r = x d + k of a level (d = 2^n + 1 directions,
+// 0 <= k < d, x below 2^12, so r below 2^14): the single-precision estimate
+// is within one of x, and one correction each way makes it exact, in a few
+// instructions where an integer division takes some thirty.
+__device__ __forceinline__ unsigned div_rows(unsigned r, unsigned d) {
+    unsigned x = (unsigned)((float)r * __builtin_amdgcn_rcpf((float)d));
+    x = x * d > r ? x - 1 : x;
+    x = (x + 1) * d <= r ? x + 1 : x;
+    return x;
+}
+
 // Merge up: T_n from T_{n-1} (Section 4.1, Eq. 18-20), for n < N.  The top
 // level is never stored: the merge down reads T_N only through the even
 // directions of its one column (the doubled edges of Eq. 15-17), and builds
@@ -427,12 +438,15 @@ __device__ void body_merge_up(const UpArgs &a, unsigned tile, int U, int tid) {
         if (idx >= total) return;
         const int y0 = (int)(idx & (S / (2 * P) - 1)) * 2 * P;
         const unsigned row = (unsigned)(idx >> (N - (P == 2 ? 2 : 1)));
-        const int q = row / rpq;
-        const unsigned rk = row % rpq;
-        const int x = rk / dirs, k = rk % dirs;
-        const unsigned r = (unsigned)x * dirs + k;  // output row (x, k)
-        const TS *near = reinterpret_cast<const TS *>(a.Tp) + q * a.ep + (size_t)(2 * x) * pdirs * S;
-        const TS *far = near + (size_t)pdirs * S;
+        const int q = (row >= rpq) + (row >= 2 * rpq) + (row >= 3 * rpq);
+        const unsigned rk = row - (unsigned)q * rpq;
+        const int x = (int)div_rows(rk, (unsigned)dirs), k = (int)(rk - (unsigned)x * dirs);
+        const unsigned r = rk;  // output row (x, k)
+        // 32-bit element offsets (a level of four quadrants holds fewer than
+        // 2^28 entries)
+        const TS *near = reinterpret_cast<const TS *>(a.Tp) +
+                         ((unsigned)q * (unsigned)a.ep + ((unsigned)(2 * x) * pdirs << N));
+        const TS *far = near + ((unsigned)pdirs << N);
         float4 res[P];
         if constexpr (P == 2) {
             // 16-bit intervals: each near row read as one quad (two pairs) per
@@ -505,7 +519,7 @@ __device__ void body_merge_up(const UpArgs &a, unsigned tile, int U, int tid) {
             }
         }
         }
-        TS *out = reinterpret_cast<TS *>(a.T) + q * a.e + (size_t)r * S + y0;
+        TS *out = reinterpret_cast<TS *>(a.T) + ((unsigned)q * (unsigned)a.e + (r << N) + (unsigned)y0);
         if constexpr (P == 2) {
             st_quad(out, res[0], res[1]);
         } else {
@@ -1120,12 +1134,12 @@ __device__ void body_merge_down_adj(const DownAdjArgs &a, unsigned tile, int U, 
         const unsigned r = row & (S - 1);
         const int c = r >> m, jj = r & ((1 << m) - 1);
         const int ii = jj >> 1, up = jj & 1;
-        const float *dRq = a.dR + q * SS;
+        const unsigned qS = (unsigned)q << (2 * N);  // 32-bit element offsets
         // Every operand is loaded before any is used (one memory wait per
         // wave); c >= 1 and n > 0 are uniform over the wave, and rows outside
         // the grid take a clamped address and a select.
         const float2 f0 = *reinterpret_cast<const float2 *>(
-            dRq + ((size_t)(((2 * c) << n) | ii)) * S + yp);
+            a.dR + (qS + ((unsigned)(((2 * c) << n) | ii) << N) + (unsigned)yp));
         float2 g = make_float2(0.f, 0.f), t = make_float2(0.f, 0.f);
         float2 g2 = make_float2(0.f, 0.f), t2 = make_float2(0.f, 0.f);
         if (c >= 1) {
@@ -1133,9 +1147,9 @@ __device__ void body_merge_down_adj(const DownAdjArgs &a, unsigned tile, int U, 
             const int e = ii + up;
             const int x = 2 * c - 1;
             const int y = yp - (2 * e - (1 << n));  // odd when n = 0
-            const float *grow = dRq + ((size_t)((x << n) | ii)) * S;
-            const TS *trow = reinterpret_cast<const TS *>(a.Tn) + q * a.en +
-                             ((size_t)x * ((1 << n) + 1) + e) * S;
+            const float *grow = a.dR + (qS + ((unsigned)((x << n) | ii) << N));
+            const TS *trow = reinterpret_cast<const TS *>(a.Tn) +
+                             ((unsigned)q * (unsigned)a.en + ((unsigned)(x * ((1 << n) + 1) + e) << N));
             if (n > 0) {
                 const bool in = (unsigned)y < (unsigned)S;
                 const int yc = in ? y : 0;
@@ -1158,9 +1172,10 @@ __device__ void body_merge_down_adj(const DownAdjArgs &a, unsigned tile, int U, 
             const bool in2 = (unsigned)y2 < (unsigned)S;
             const int y2c = in2 ? y2 : 0;
             const float2 g2v = *reinterpret_cast<const float2 *>(
-                dRq + ((size_t)((x2 << n) | ii)) * S + y2c);
-            const float4 t2v = ld_pair(reinterpret_cast<const TS *>(a.Tn1) + q * a.en1 +
-                                       ((size_t)(c - 1) * ((1 << m) + 1) + e2) * S + y2c);
+                a.dR + (qS + ((unsigned)((x2 << n) | ii) << N) + (unsigned)y2c));
+            const float4 t2v = ld_pair(reinterpret_cast<const TS *>(a.Tn1) +
+                                       ((unsigned)q * (unsigned)a.en1 +
+                                        ((unsigned)((c - 1) * ((1 << m) + 1) + e2) << N) + (unsigned)y2c));
             g2 = in2 ? g2v : make_float2(0.f, 0.f);
             t2 = in2 ? make_float2(t2v.y, t2v.w) : make_float2(0.f, 0.f);
         }
@@ -1169,19 +1184,8 @@ __device__ void body_merge_down_adj(const DownAdjArgs &a, unsigned tile, int U, 
         acc1 = fmaf(g.y, t.y, acc1);
         acc0 = fmaf(0.5f * g2.x, t2.x, acc0);
         acc1 = fmaf(0.5f * g2.y, t2.y, acc1);
-        *reinterpret_cast<float2 *>(a.dRn1 + q * SS + (size_t)r * S + yp) = make_float2(acc0, acc1);
+        *reinterpret_cast<float2 *>(a.dRn1 + (qS + (r << N) + (unsigned)yp)) = make_float2(acc0, acc1);
     }
-}
-
-// floor(r / d) for a row index r = x d + k of a level (d = 2^n + 1 directions,
-// 0 <= k < d, x below 2^12, so r below 2^14): the single-precision estimate
-// is within one of x, and one correction each way makes it exact, in a few
-// instructions where an integer division takes some thirty.
-__device__ __forceinline__ unsigned div_rows(unsigned r, unsigned d) {
-    unsigned x = (unsigned)((float)r * __builtin_amdgcn_rcpf((float)d));
-    x = x * d > r ? x - 1 : x;
-    x = (x + 1) * d <= r ? x + 1 : x;
-    return x;
 }
 
 // Adjoint of the interval pyramid: dT_n (gather form) from the merge down at
