@@ -1197,10 +1197,160 @@ __device__ void body_merge_down_adj(const DownAdjArgs &a, unsigned tile, int U, 
 // Without ENV the fluence from beyond the grid is the constant 0, which keeps
 // those selects from turning into branches that wait on the environment table.
 template <typename TS, bool ENV>
+__device__ __forceinline__ void dT_output(const DTArgs &a, int q, int x, int k, int y) {
+    const int N = a.N, S = 1 << N, n = a.n;
+    const int dirs = (1 << n) + 1;
+    const unsigned r = (unsigned)(x * dirs + k);
+    const float *envq = ENV ? a.env + (size_t)q * kConeTable : nullptr;
+    // element offsets within each level are 32-bit (a level of four
+    // quadrants holds fewer than 2^28 entries)
+    const unsigned qS = (unsigned)q << (2 * N);
+    // (a) merge down at level n, odd x (Eq. 14): T_n(p, k) is the edge of
+    //     cone k (lower half, jj = 2k) and of cone k-1 (upper half, jj = 2k-1):
+    //     term i = 0 reads R_n row (x, k-1) and cone 2k-1 of R_{n+1}, i = 1
+    //     row (x, k) and cone 2k.
+    float2 ag[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+    float2 ar[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+    float aA[2] = {0.f, 0.f};
+    if (n < N && (x & 1)) {
+        const int c = (x + 1) >> 1, yf = y + 2 * k - (1 << n);  // odd when n = 0
+        const bool rin = n + 1 < N && c < (S >> (n + 1));
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int ii = k - 1 + i, jj = 2 * k - 1 + i;
+            if (ii < 0 || ii >= (1 << n)) continue;
+            ag[i] = *reinterpret_cast<const float2 *>(
+                a.dRn + (qS + ((unsigned)((x << n) | ii) << N) + (unsigned)y));
+            aA[i] = c_cone[(1 << (n + 1)) - 1 + jj];
+            ar[i] = ld2_r_at(rin, a.Rn1, qS + ((unsigned)((c << (n + 1)) | jj) << N), yf, S,
+                             n > 0, env_fluence(envq, n + 1, jj));
+        }
+    }
+    // (b) merge down at level n-1, even column 2x (Eq. 17): T_n(p, k), k even,
+    //     is the doubled edge of cone k/2 (jj = k) and of cone k/2-1 (jj = k-1):
+    //     term i = 0 reads dR_{n-1} row (2x, k/2-1) and cone k-1 of R_n at
+    //     column x+1, i = 1 row (2x, k/2) and cone k.
+    float2 bg[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+    float2 br[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+    float bA[2] = {0.f, 0.f};
+    if (n >= 1 && (k & 1) == 0) {
+        const int nm = n - 1;
+        const int yf = y + 2 * k - (1 << n);
+        const int xm = 2 * x;
+        const bool rin = n < N && x + 1 < (S >> n);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int jj = k - 1 + i;
+            if (jj < 0 || jj >= (1 << n)) continue;
+            bg[i] = *reinterpret_cast<const float2 *>(
+                a.dRm + (qS + ((unsigned)((xm << nm) | (k / 2 - 1 + i)) << N) + (unsigned)y));
+            bA[i] = c_cone[(1 << n) - 1 + jj];
+            br[i] = ld2_r_at(rin, a.Rn, qS + ((unsigned)(((x + 1) << n) | jj) << N), yf, S, true,
+                             env_fluence(envq, n, jj));
+        }
+    }
+    // (c) merge up of T_{n+1} from T_n (Eq. 18-20), H = 2^n (n >= 2: even
+    //     shifts).  Outputs ko = 2k (weight 1), 2k+1 and 2k-1 (weight 1/2):
+    //     near role (x even): the far partner kb = k, k+1, k-1 at row y + 2k - H;
+    //     far role (x odd): the near partner ka = k, k+1, k-1, each from
+    //     output row y - (2 ka - H).
+    //     Both roles load one partner interval pair and one dT_{n+1} pair
+    //     per output; the role only moves the rows and the fill.
+    float4 cg[3], cf[3];
+    float cw[3] = {0.f, 0.f, 0.f};
+    const bool near_role = (x & 1) == 0;
+    if (a.has_up) {
+        const int H = 1 << n;
+        const int odirs = 2 * H + 1;
+        const TS *Tn = reinterpret_cast<const TS *>(a.Tn);
+        const unsigned g0 = (unsigned)q * (unsigned)a.en1 + ((unsigned)((x >> 1) * odirs) << N);
+        const unsigned part = (unsigned)q * (unsigned)a.en +
+                              ((unsigned)((near_role ? x + 1 : x - 1) * dirs) << N);
+        bool act[3], in[3];
+        typename PairRaw<TS>::type cr[3];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            const int ko = v == 0 ? 2 * k : (v == 1 ? 2 * k + 1 : 2 * k - 1);
+            const int kp = v == 0 ? k : (v == 1 ? k + 1 : k - 1);
+            const int yo = near_role ? y + 2 * k - H : y - (2 * kp - H);
+            act[v] = ko >= 0 && ko <= 2 * H;
+            in[v] = (unsigned)yo < (unsigned)S;
+            const int yc = in[v] ? yo : 0;
+            cr[v] = raw_zero<TS>();
+            cg[v] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (act[v]) {
+                cr[v] = ld_pair_raw(Tn + (part + ((unsigned)kp << N) + (unsigned)yc));
+                cg[v] = ld_pair(a.dTn1 + (g0 + ((unsigned)ko << N) + (unsigned)(near_role ? y : yc)));
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            pin(cr[v]);
+            pin(cg[v]);
+            cf[v] = cvt_pair(cr[v]);
+            const float4 fill = near_role ? make_float4(0.f, 1.f, 0.f, 1.f)
+                                          : make_float4(0.f, 0.f, 0.f, 0.f);
+            cw[v] = act[v] ? (v == 0 ? 1.f : 0.5f) : 0.f;
+            cf[v] = act[v] ? (in[v] ? cf[v] : fill) : make_float4(0.f, 1.f, 0.f, 1.f);
+            cg[v] = act[v] && (in[v] || near_role) ? cg[v] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            cg[v] = make_float4(0.f, 0.f, 0.f, 0.f);
+            cf[v] = make_float4(0.f, 1.f, 0.f, 1.f);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        pin(ag[i]); pin(ar[i]); pin(aA[i]);
+        pin(bg[i]); pin(br[i]); pin(bA[i]);
+    }
+    float gl0 = 0.f, gt0 = 0.f, gl1 = 0.f, gt1 = 0.f;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        gl0 = fmaf(ag[i].x, aA[i], gl0); gl1 = fmaf(ag[i].y, aA[i], gl1);
+        gt0 = fmaf(ag[i].x, ar[i].x, gt0); gt1 = fmaf(ag[i].y, ar[i].y, gt1);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const float g0x = 0.5f * bg[i].x, g0y = 0.5f * bg[i].y;
+        gl0 = fmaf(g0x, bA[i], gl0); gl1 = fmaf(g0y, bA[i], gl1);
+        gt0 = fmaf(g0x, br[i].x, gt0); gt1 = fmaf(g0y, br[i].y, gt1);
+    }
+    if (near_role) {
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            const float4 g = cg[v], f = cf[v];
+            gl0 = fmaf(cw[v], g.x, gl0);
+            gt0 = fmaf(cw[v], fmaf(g.x, f.x, g.y * f.y), gt0);
+            gl1 = fmaf(cw[v], g.z, gl1);
+            gt1 = fmaf(cw[v], fmaf(g.z, f.z, g.w * f.w), gt1);
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            const float4 g = cg[v], tn = cf[v];
+            gl0 = fmaf(cw[v] * g.x, tn.y, gl0);
+            gt0 = fmaf(cw[v] * g.y, tn.y, gt0);
+            gl1 = fmaf(cw[v] * g.z, tn.w, gl1);
+            gt1 = fmaf(cw[v] * g.w, tn.w, gt1);
+        }
+    }
+    *reinterpret_cast<float4 *>(a.dT + ((unsigned)q * (unsigned)a.en + (r << N) + (unsigned)y)) =
+        make_float4(gl0, gt0, gl1, gt1);
+}
+
+template <typename TS, bool ENV>
 __device__ void body_dT_t(const DTArgs &a, unsigned tile, int U, int tid) {
     const int N = a.N, S = 1 << N, n = a.n;
     const int dirs = (1 << n) + 1;
-    const unsigned rpq = (unsigned)(S >> n) * dirs;
+    // at the two lowest levels a thread takes the same (k, y) of both probe
+    // columns 2c and 2c+1, which read the same dT_{n+1} rows of column c
+    // (measured at 1024^2: 3-14% faster there, 1-2 us slower per level above)
+    const bool pairs = n <= 1 && n < N;
+    const unsigned cols = pairs ? (unsigned)(S >> n) / 2 : (unsigned)(S >> n);
+    const unsigned rpq = cols * dirs;
     const size_t total = (size_t)4 * rpq * (S / 2);
     for (int uu = 0; uu < U; ++uu) {
         const size_t idx = ((size_t)tile * U + uu) * 256 + tid;
@@ -1208,146 +1358,14 @@ __device__ void body_dT_t(const DTArgs &a, unsigned tile, int U, int tid) {
         const int y = (int)(idx & (S / 2 - 1)) * 2;
         const unsigned row = (unsigned)(idx >> (N - 1));
         const int q = (row >= rpq) + (row >= 2 * rpq) + (row >= 3 * rpq);
-        const unsigned r = row - (unsigned)q * rpq;
-        const int x = (int)div_rows(r, (unsigned)dirs), k = (int)(r - (unsigned)x * dirs);
-        const float *envq = ENV ? a.env + (size_t)q * kConeTable : nullptr;
-        // element offsets within each level are 32-bit (a level of four
-        // quadrants holds fewer than 2^28 entries)
-        const unsigned qS = (unsigned)q << (2 * N);
-        // (a) merge down at level n, odd x (Eq. 14): T_n(p, k) is the edge of
-        //     cone k (lower half, jj = 2k) and of cone k-1 (upper half, jj = 2k-1):
-        //     term i = 0 reads R_n row (x, k-1) and cone 2k-1 of R_{n+1}, i = 1
-        //     row (x, k) and cone 2k.
-        float2 ag[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
-        float2 ar[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
-        float aA[2] = {0.f, 0.f};
-        if (n < N && (x & 1)) {
-            const int c = (x + 1) >> 1, yf = y + 2 * k - (1 << n);  // odd when n = 0
-            const bool rin = n + 1 < N && c < (S >> (n + 1));
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int ii = k - 1 + i, jj = 2 * k - 1 + i;
-                if (ii < 0 || ii >= (1 << n)) continue;
-                ag[i] = *reinterpret_cast<const float2 *>(
-                    a.dRn + (qS + ((unsigned)((x << n) | ii) << N) + (unsigned)y));
-                aA[i] = c_cone[(1 << (n + 1)) - 1 + jj];
-                ar[i] = ld2_r_at(rin, a.Rn1, qS + ((unsigned)((c << (n + 1)) | jj) << N), yf, S,
-                                 n > 0, env_fluence(envq, n + 1, jj));
-            }
-        }
-        // (b) merge down at level n-1, even column 2x (Eq. 17): T_n(p, k), k even,
-        //     is the doubled edge of cone k/2 (jj = k) and of cone k/2-1 (jj = k-1):
-        //     term i = 0 reads dR_{n-1} row (2x, k/2-1) and cone k-1 of R_n at
-        //     column x+1, i = 1 row (2x, k/2) and cone k.
-        float2 bg[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
-        float2 br[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
-        float bA[2] = {0.f, 0.f};
-        if (n >= 1 && (k & 1) == 0) {
-            const int nm = n - 1;
-            const int yf = y + 2 * k - (1 << n);
-            const int xm = 2 * x;
-            const bool rin = n < N && x + 1 < (S >> n);
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int jj = k - 1 + i;
-                if (jj < 0 || jj >= (1 << n)) continue;
-                bg[i] = *reinterpret_cast<const float2 *>(
-                    a.dRm + (qS + ((unsigned)((xm << nm) | (k / 2 - 1 + i)) << N) + (unsigned)y));
-                bA[i] = c_cone[(1 << n) - 1 + jj];
-                br[i] = ld2_r_at(rin, a.Rn, qS + ((unsigned)(((x + 1) << n) | jj) << N), yf, S, true,
-                                 env_fluence(envq, n, jj));
-            }
-        }
-        // (c) merge up of T_{n+1} from T_n (Eq. 18-20), H = 2^n (n >= 2: even
-        //     shifts).  Outputs ko = 2k (weight 1), 2k+1 and 2k-1 (weight 1/2):
-        //     near role (x even): the far partner kb = k, k+1, k-1 at row y + 2k - H;
-        //     far role (x odd): the near partner ka = k, k+1, k-1, each from
-        //     output row y - (2 ka - H).
-        //     Both roles load one partner interval pair and one dT_{n+1} pair
-        //     per output; the role only moves the rows and the fill.
-        float4 cg[3], cf[3];
-        float cw[3] = {0.f, 0.f, 0.f};
-        const bool near_role = (x & 1) == 0;
-        if (a.has_up) {
-            const int H = 1 << n;
-            const int odirs = 2 * H + 1;
-            const TS *Tn = reinterpret_cast<const TS *>(a.Tn);
-            const unsigned g0 = (unsigned)q * (unsigned)a.en1 + ((unsigned)((x >> 1) * odirs) << N);
-            const unsigned part = (unsigned)q * (unsigned)a.en +
-                                  ((unsigned)((near_role ? x + 1 : x - 1) * dirs) << N);
-            bool act[3], in[3];
-            typename PairRaw<TS>::type cr[3];
-#pragma unroll
-            for (int v = 0; v < 3; ++v) {
-                const int ko = v == 0 ? 2 * k : (v == 1 ? 2 * k + 1 : 2 * k - 1);
-                const int kp = v == 0 ? k : (v == 1 ? k + 1 : k - 1);
-                const int yo = near_role ? y + 2 * k - H : y - (2 * kp - H);
-                act[v] = ko >= 0 && ko <= 2 * H;
-                in[v] = (unsigned)yo < (unsigned)S;
-                const int yc = in[v] ? yo : 0;
-                cr[v] = raw_zero<TS>();
-                cg[v] = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (act[v]) {
-                    cr[v] = ld_pair_raw(Tn + (part + ((unsigned)kp << N) + (unsigned)yc));
-                    cg[v] = ld_pair(a.dTn1 + (g0 + ((unsigned)ko << N) + (unsigned)(near_role ? y : yc)));
-                }
-            }
-#pragma unroll
-            for (int v = 0; v < 3; ++v) {
-                pin(cr[v]);
-                pin(cg[v]);
-                cf[v] = cvt_pair(cr[v]);
-                const float4 fill = near_role ? make_float4(0.f, 1.f, 0.f, 1.f)
-                                              : make_float4(0.f, 0.f, 0.f, 0.f);
-                cw[v] = act[v] ? (v == 0 ? 1.f : 0.5f) : 0.f;
-                cf[v] = act[v] ? (in[v] ? cf[v] : fill) : make_float4(0.f, 1.f, 0.f, 1.f);
-                cg[v] = act[v] && (in[v] || near_role) ? cg[v] : make_float4(0.f, 0.f, 0.f, 0.f);
-            }
+        const unsigned rc = row - (unsigned)q * rpq;
+        const int c = (int)div_rows(rc, (unsigned)dirs), k = (int)(rc - (unsigned)c * dirs);
+        if (pairs) {
+            dT_output<TS, ENV>(a, q, 2 * c, k, y);
+            dT_output<TS, ENV>(a, q, 2 * c + 1, k, y);
         } else {
-#pragma unroll
-            for (int v = 0; v < 3; ++v) {
-                cg[v] = make_float4(0.f, 0.f, 0.f, 0.f);
-                cf[v] = make_float4(0.f, 1.f, 0.f, 1.f);
-            }
+            dT_output<TS, ENV>(a, q, c, k, y);
         }
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            pin(ag[i]); pin(ar[i]); pin(aA[i]);
-            pin(bg[i]); pin(br[i]); pin(bA[i]);
-        }
-        float gl0 = 0.f, gt0 = 0.f, gl1 = 0.f, gt1 = 0.f;
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            gl0 = fmaf(ag[i].x, aA[i], gl0); gl1 = fmaf(ag[i].y, aA[i], gl1);
-            gt0 = fmaf(ag[i].x, ar[i].x, gt0); gt1 = fmaf(ag[i].y, ar[i].y, gt1);
-        }
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const float g0x = 0.5f * bg[i].x, g0y = 0.5f * bg[i].y;
-            gl0 = fmaf(g0x, bA[i], gl0); gl1 = fmaf(g0y, bA[i], gl1);
-            gt0 = fmaf(g0x, br[i].x, gt0); gt1 = fmaf(g0y, br[i].y, gt1);
-        }
-        if (near_role) {
-#pragma unroll
-            for (int v = 0; v < 3; ++v) {
-                const float4 g = cg[v], f = cf[v];
-                gl0 = fmaf(cw[v], g.x, gl0);
-                gt0 = fmaf(cw[v], fmaf(g.x, f.x, g.y * f.y), gt0);
-                gl1 = fmaf(cw[v], g.z, gl1);
-                gt1 = fmaf(cw[v], fmaf(g.z, f.z, g.w * f.w), gt1);
-            }
-        } else {
-#pragma unroll
-            for (int v = 0; v < 3; ++v) {
-                const float4 g = cg[v], tn = cf[v];
-                gl0 = fmaf(cw[v] * g.x, tn.y, gl0);
-                gt0 = fmaf(cw[v] * g.y, tn.y, gt0);
-                gl1 = fmaf(cw[v] * g.z, tn.w, gl1);
-                gt1 = fmaf(cw[v] * g.w, tn.w, gt1);
-            }
-        }
-        *reinterpret_cast<float4 *>(a.dT + ((unsigned)q * (unsigned)a.en + (r << N) + (unsigned)y)) =
-            make_float4(gl0, gt0, gl1, gt1);
     }
 }
 
@@ -2929,7 +2947,8 @@ unsigned phase_tiles(const Phase &p) {
         }
         case PH_UP:  // pairs of y per thread: one, two with 16-bit intervals
             return cdiv((size_t)p.a.up.nq * t_level_entries(N, p.a.up.n) / (p.a.up.half ? 4 : 2), per);
-        case PH_DT:
+        case PH_DT:  // two probe columns per thread at levels 0 and 1
+            return cdiv(4 * t_level_entries(N, p.a.dt.n) / (p.a.dt.n <= 1 && p.a.dt.n < N ? 4 : 2), per);
         case PH_DT_RGB: return cdiv(4 * t_level_entries(N, p.a.dt.n) / 2, per);
         case PH_DOWN: return cdiv((size_t)p.a.down.nq * SS / (p.a.down.half ? 4 : 2), per);
         case PH_DOWN_ADJ:
