@@ -1084,26 +1084,13 @@ __device__ void body_gather_adj(const GatherAdjArgs &a, unsigned tile, char *lds
     __syncthreads();
 }
 
-// R at (row, y) and (row, y+1) when the row lies in the grid (`in`, uniform
+// R at (row, y) and (row, y+1), the row starting at element `row` of `base`
+// (32-bit offsets), when the row lies in the grid (`in`, uniform
 // over the wave); rows y outside [0, S) and every element of a row outside the
 // grid read `fill` (the environment's fluence for the cone, or 0).  With
 // `even` (every shift but those of level 0) y is even and the two form one
 // aligned pair.  Rows outside [0, S) load a clamped address and are replaced
 // by a select, so the lookup has no per-lane branch.
-__device__ __forceinline__ float2 ld2_r(bool in, const float *row, int y, int S, bool even,
-                                        float fill) {
-    if (!in) return make_float2(fill, fill);
-    if (even) {
-        const bool ok = (unsigned)y < (unsigned)S;
-        const float2 v = *reinterpret_cast<const float2 *>(row + (ok ? y : 0));
-        return ok ? v : make_float2(fill, fill);
-    }
-    const bool ok0 = (unsigned)y < (unsigned)S, ok1 = (unsigned)(y + 1) < (unsigned)S;
-    const float a0 = row[ok0 ? y : 0], a1 = row[ok1 ? y + 1 : 0];
-    return make_float2(ok0 ? a0 : fill, ok1 ? a1 : fill);
-}
-
-// ld2_r for the row that starts at element `row` of `base` (32-bit offsets).
 __device__ __forceinline__ float2 ld2_r_at(bool in, const float *base, unsigned row, int y, int S,
                                            bool even, float fill) {
     if (!in) return make_float2(fill, fill);
@@ -1801,13 +1788,13 @@ __device__ void body_merge_up_rgb(const UpArgs &a, unsigned tile, int U, int tid
         if (idx >= total) return;
         const int y = (int)(idx & (S / 2 - 1)) * 2;
         const unsigned row = (unsigned)(idx >> (N - 1));
-        const int q = row / rpq;
-        const unsigned rk = row % rpq;
-        const int x = rk / dirs, k = rk % dirs;
-        const unsigned r = (unsigned)x * dirs + k;
-        const TS *near =
-            reinterpret_cast<const TS *>(a.Tp) + q * a.ep + (size_t)(2 * x) * pdirs * S;
-        const TS *far = near + (size_t)pdirs * S;
+        const int q = (row >= rpq) + (row >= 2 * rpq) + (row >= 3 * rpq);
+        const unsigned rk = row - (unsigned)q * rpq;
+        const int x = (int)div_rows(rk, (unsigned)dirs), k = (int)(rk - (unsigned)x * dirs);
+        const unsigned r = rk;
+        const TS *near = reinterpret_cast<const TS *>(a.Tp) +
+                         ((unsigned)q * (unsigned)a.ep + ((unsigned)(2 * x) * pdirs << N));
+        const TS *far = near + ((unsigned)pdirs << N);
         float4 o0, o1;
         if ((k & 1) == 0) {
             const int kk = k >> 1;
@@ -2249,9 +2236,9 @@ __device__ void body_dT_rgb(const DTArgs &a, unsigned tile, int U, int tid) {
         if (idx >= total) return;
         const int y = (int)(idx & (S / 2 - 1)) * 2;
         const unsigned row = (unsigned)(idx >> (N - 1));
-        const int q = row / rpq;
-        const unsigned r = row % rpq;
-        const int x = r / dirs, k = r % dirs;
+        const int q = (row >= rpq) + (row >= 2 * rpq) + (row >= 3 * rpq);
+        const unsigned r = row - (unsigned)q * rpq;
+        const int x = (int)div_rows(r, (unsigned)dirs), k = (int)(r - (unsigned)x * dirs);
         // (a) merge down at level n, odd x (Eq. 14)
         float2 ag[2][3], ar[2][3];
         float aA[2] = {0.f, 0.f};
@@ -2270,9 +2257,11 @@ __device__ void body_dT_rgb(const DTArgs &a, unsigned tile, int U, int tid) {
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch) {
                     ag[i][ch] = *reinterpret_cast<const float2 *>(
-                        a.dRn + ch * plane + q * SS + ((size_t)((x << n) | ii)) * S + y);
-                    ar[i][ch] = ld2_r(rin, a.Rn1 + ch * plane + q * SS +
-                                               ((size_t)((c << (n + 1)) | jj)) * S,
+                        a.dRn + ((unsigned)(ch * plane + q * SS) + ((unsigned)((x << n) | ii) << N) +
+                                 (unsigned)y));
+                    ar[i][ch] = ld2_r_at(rin, a.Rn1,
+                                         (unsigned)(ch * plane + q * SS) +
+                                             ((unsigned)((c << (n + 1)) | jj) << N),
                                       yf, S, n > 0, 0.f);
                 }
             }
@@ -2295,9 +2284,11 @@ __device__ void body_dT_rgb(const DTArgs &a, unsigned tile, int U, int tid) {
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch) {
                     bg[i][ch] = *reinterpret_cast<const float2 *>(
-                        a.dRm + ch * plane + q * SS + ((size_t)((xm << nm) | (k / 2 - 1 + i))) * S + y);
-                    br[i][ch] = ld2_r(rin, a.Rn + ch * plane + q * SS +
-                                               ((size_t)(((x + 1) << n) | jj)) * S,
+                        a.dRm + ((unsigned)(ch * plane + q * SS) +
+                                 ((unsigned)((xm << nm) | (k / 2 - 1 + i)) << N) + (unsigned)y));
+                    br[i][ch] = ld2_r_at(rin, a.Rn,
+                                         (unsigned)(ch * plane + q * SS) +
+                                             ((unsigned)(((x + 1) << n) | jj) << N),
                                       yf, S, true, 0.f);
                 }
             }
@@ -2313,10 +2304,11 @@ __device__ void body_dT_rgb(const DTArgs &a, unsigned tile, int U, int tid) {
         }
         if (a.has_up) {
             const int H = 1 << n, odirs = 2 * H + 1;
-            const TS *Tq = reinterpret_cast<const TS *>(a.Tn) + q * a.en;
-            const float4 *g0 = reinterpret_cast<const float4 *>(a.dTn1) + q * a.en1 +
-                               (size_t)(x >> 1) * odirs * S;
-            const TS *part = Tq + (size_t)(near_role ? x + 1 : x - 1) * dirs * S;
+            // 32-bit element offsets (a level holds fewer than 2^28 entries)
+            const float4 *g0 = reinterpret_cast<const float4 *>(a.dTn1) +
+                               ((unsigned)q * (unsigned)a.en1 + ((unsigned)((x >> 1) * odirs) << N));
+            const TS *part = reinterpret_cast<const TS *>(a.Tn) +
+                             ((unsigned)q * (unsigned)a.en + ((unsigned)((near_role ? x + 1 : x - 1) * dirs) << N));
 #pragma unroll
             for (int v = 0; v < 3; ++v) {
                 const int ko = v == 0 ? 2 * k : (v == 1 ? 2 * k + 1 : 2 * k - 1);
