@@ -320,6 +320,22 @@ def main():
                   "GBps": v[1] / (v[0] * 1e-3) / 1e9} for k, v in per.items()}
     step_bytes = forward_bytes(N)
     kernel_name = _lib.PASS_KERNELS[_lib.PASS_NAMES.index(dom)]
+    # ---- the same for hrc_backward (the recomputed forward, then the reverse):
+    # per pass, kernel time and algorithmic bytes over that time ---------------
+    log("per-pass kernel timing of the backward")
+    bper = {}
+    breps = max(3, args.steps // 10)
+    for _ in range(breps):
+        for name, n, ms in ctx.hrc_profile_solve(eps, sig, dF):
+            # the backward's traced-levels pass stores all three levels
+            nb = pass_bytes("seed_all" if name == "seed" else name, N, n)
+            tot_ms, tot_b, cnt = bper.get(name, (0.0, 0.0, 0))
+            bper[name] = (tot_ms + ms, tot_b + nb, cnt + 1)
+    backward_passes = {k: {"launches_per_call": v[2] // breps, "ms_per_call": v[0] / breps,
+                           "us_per_launch": v[0] / v[2] * 1e3,
+                           "GBps": v[1] / (v[0] * 1e-3) / 1e9,
+                           "frac_of_hbm_peak": v[1] / (v[0] * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+                       for k, v in bper.items()}
     # ---- the same forward replayed from a HIP graph (ten solves captured in
     # one graph): the time between the passes is the GPU's drain and ramp at
     # each kernel boundary, which a graph keeps ---------------------------------
@@ -431,6 +447,7 @@ def main():
             "algorithmic_bytes_per_launch": bytes_per_launch,
         },
         "passes": passes,
+        "backward_passes": backward_passes,
         "graph_replay": {"ms_per_forward": graph_s * 1e3 if graph_s else None,
                          "direct_ms": fwd_s * 1e3,
                          "kernel_sum_ms": kernel_sum_ms, "bitwise_equal": graph_bitwise,
