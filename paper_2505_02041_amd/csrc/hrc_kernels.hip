@@ -200,15 +200,12 @@ __device__ __forceinline__ float4 far_pair(const TS *row, int yf, int S) {
     return (yf >= 0 && yf < S) ? ld_pair(row + yf) : make_float4(0.f, 1.f, 0.f, 1.f);
 }
 
-// Four consecutive 16-bit intervals (two pairs) at y, y a multiple of 4: one
-// 16-byte load.
+// Four consecutive 16-bit intervals (two pairs) at y, y a multiple of 4, as
+// one 16-byte load, and their conversion to two FP32 pairs.
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ void cvt_quad(half8_t v, float4 &a, float4 &b) {
     a = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
     b = make_float4((float)v[4], (float)v[5], (float)v[6], (float)v[7]);
-}
-__device__ __forceinline__ void ld_quad(const half2_t *p, float4 &a, float4 &b) {
-    cvt_quad(*reinterpret_cast<const half8_t *>(p), a, b);
 }
 // Raw 16-bit loads pinned as they are, before their conversion (see pin).
 __device__ __forceinline__ void pin(half8_t &v) { asm volatile("" : "+v"(v)); }
@@ -264,24 +261,6 @@ __device__ __forceinline__ void st_iv(half4_t *p, float4 v) {
     h.z = to_half(v.z);
     h.w = to_half(v.w);
     *p = h;
-}
-
-// The same at a shifted row position yf (even): one 16-byte load when yf is a
-// multiple of 4 (it is, or is not, for the whole wave: threads start at
-// multiples of 4 and the shift is uniform), else two 8-byte pair loads; rows
-// outside [0, S) read <0, 1> (S and aligned yf are multiples of 4, so an
-// aligned quad is wholly in or out).
-__device__ __forceinline__ void far_quad(const half2_t *row, int yf, int S, float4 &a, float4 &b) {
-    if ((yf & 3) == 0) {
-        if (yf >= 0 && yf < S) {
-            ld_quad(row + yf, a, b);
-        } else {
-            a = b = make_float4(0.f, 1.f, 0.f, 1.f);
-        }
-    } else {
-        a = far_pair(row, yf, S);
-        b = far_pair(row, yf + 2, S);
-    }
 }
 
 // Traced levels T_0, T_1, T_2 (Algorithm 1, first loop), for all four
