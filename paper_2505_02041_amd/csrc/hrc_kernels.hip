@@ -362,18 +362,37 @@ __device__ void body_seed(const SeedArgs &a, unsigned tile, char *lds, int tid) 
     const int S = 1 << a.N;
     const int tiles = (S + TILE - 1) / TILE;
     const int r0 = (int)(tile / tiles) * TILE, c0 = (int)(tile % tiles) * TILE;
-    for (int i = tid; i < G::span * G::span; i += 256) {
+    // the fields of the tile and its halo: every load of the thread first
+    // (cells outside the grid from a clamped address, then 0), then the
+    // intervals, so the block waits for memory once
+    constexpr int cells = G::span * G::span, NI = (cells + 255) / 256;
+    float ev[NI], gv[NI];
+    bool inside[NI];
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int i = tid + 256 * it;
         const int lr = i / G::span, lc = i % G::span;
         const int r = r0 - kSeedHalo + lr, c = c0 - kSeedHalo + lc;
-        float e = 0.f, g = 0.f;
-        if (r >= 0 && r < S && c >= 0 && c < S) {
-            e = a.eps[(size_t)r * S + c];
-            g = a.sig[(size_t)r * S + c];
+        inside[it] = i < cells && (unsigned)r < (unsigned)S && (unsigned)c < (unsigned)S;
+        const unsigned o = inside[it] ? (unsigned)(r * S + c) : 0u;
+        ev[it] = a.eps[o];
+        gv[it] = a.sig[o];
+    }
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        pin(ev[it]);
+        pin(gv[it]);
+    }
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int i = tid + 256 * it;
+        if (i < cells) {
+            const float e = inside[it] ? ev[it] : 0.f, g = inside[it] ? gv[it] : 0.f;
+            const int l = (i / G::span) * G::pitch + i % G::span;
+            iv[l] = cell_interval(e, g, 0.5f);
+            iv[G::span * G::pitch + l] = cell_interval(e, g, kH2);
+            iv[2 * G::span * G::pitch + l] = cell_interval(e, g, kQ5);
         }
-        const int l = lr * G::pitch + lc;
-        iv[l] = cell_interval(e, g, 0.5f);
-        iv[G::span * G::pitch + l] = cell_interval(e, g, kH2);
-        iv[2 * G::span * G::pitch + l] = cell_interval(e, g, kQ5);
     }
     __syncthreads();
     for (int g = 0; g < a.nq; ++g) {
@@ -1554,19 +1573,36 @@ __device__ __forceinline__ void body_seed_adj(const SeedAdjArgs &a, unsigned til
     const int S = 1 << a.N;
     const int tiles = (S + kAdjTile - 1) / kAdjTile;
     const int r0 = (int)(tile / tiles) * kAdjTile, c0 = (int)(tile % tiles) * kAdjTile;
-    // the tile and its halo as three half-length intervals per cell
-    for (int i = tid; i < kAdjSpan * kAdjSpan; i += 256) {
-        const int lr = i / kAdjSpan, lc = i % kAdjSpan;
-        const int r = r0 - H + lr, c = c0 - H + lc;
-        float e = 0.f, g = 0.f;
-        if (r >= 0 && r < S && c >= 0 && c < S) {
-            e = a.eps[(size_t)r * S + c];
-            g = a.sig[(size_t)r * S + c];
+    // the tile and its halo as three half-length intervals per cell: every
+    // load of the thread first (cells outside the grid from a clamped address,
+    // then 0), so the block waits for memory once
+    constexpr int cells = kAdjSpan * kAdjSpan, NI = (cells + 255) / 256;
+    float ev[NI], gv[NI];
+    bool inside[NI];
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int i = tid + 256 * it;
+        const int r = r0 - H + i / kAdjSpan, c = c0 - H + i % kAdjSpan;
+        inside[it] = i < cells && (unsigned)r < (unsigned)S && (unsigned)c < (unsigned)S;
+        const unsigned o = inside[it] ? (unsigned)(r * S + c) : 0u;
+        ev[it] = a.eps[o];
+        gv[it] = a.sig[o];
+    }
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        pin(ev[it]);
+        pin(gv[it]);
+    }
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int i = tid + 256 * it;
+        if (i < cells) {
+            const float e = inside[it] ? ev[it] : 0.f, g = inside[it] ? gv[it] : 0.f;
+            const int l = (i / kAdjSpan) * P + i % kAdjSpan;
+            iv[l] = cell_interval(e, g, 0.5f);
+            iv[plane + l] = cell_interval(e, g, kH2);
+            iv[2 * plane + l] = cell_interval(e, g, kQ5);
         }
-        const int l = lr * P + lc;
-        iv[l] = cell_interval(e, g, 0.5f);
-        iv[plane + l] = cell_interval(e, g, kH2);
-        iv[2 * plane + l] = cell_interval(e, g, kQ5);
     }
     __syncthreads();
     const int v = tid >> 6, lane = tid & 63;
@@ -1712,21 +1748,40 @@ __device__ void body_seed_rgb(const SeedArgs &a, unsigned tile, char *lds, int t
     const size_t SS = (size_t)S * S;
     const int tiles = (S + TILE - 1) / TILE;
     const int r0 = (int)(tile / tiles) * TILE, c0 = (int)(tile % tiles) * TILE;
-    for (int i = tid; i < G::span * G::span; i += 256) {
-        const int lr = i / G::span, lc = i % G::span;
-        const int r = r0 - kSeedHalo + lr, c = c0 - kSeedHalo + lc;
-        float e0 = 0.f, e1 = 0.f, e2 = 0.f, g = 0.f;
-        if (r >= 0 && r < S && c >= 0 && c < S) {
-            const size_t o = (size_t)r * S + c;
-            e0 = a.eps[o];
-            e1 = a.eps[SS + o];
-            e2 = a.eps[2 * SS + o];
-            g = a.sig[o];
+    // every field load of the thread first, then the intervals (as body_seed)
+    constexpr int cells = G::span * G::span, NI = (cells + 255) / 256;
+    float ev[NI][3], gv[NI];
+    bool inside[NI];
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int i = tid + 256 * it;
+        const int r = r0 - kSeedHalo + i / G::span, c = c0 - kSeedHalo + i % G::span;
+        inside[it] = i < cells && (unsigned)r < (unsigned)S && (unsigned)c < (unsigned)S;
+        const size_t o = inside[it] ? (size_t)r * S + c : 0;
+        ev[it][0] = a.eps[o];
+        ev[it][1] = a.eps[SS + o];
+        ev[it][2] = a.eps[2 * SS + o];
+        gv[it] = a.sig[o];
+    }
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        pin(ev[it][0]);
+        pin(ev[it][1]);
+        pin(ev[it][2]);
+        pin(gv[it]);
+    }
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int i = tid + 256 * it;
+        if (i < cells) {
+            const bool in = inside[it];
+            const float e0 = in ? ev[it][0] : 0.f, e1 = in ? ev[it][1] : 0.f;
+            const float e2 = in ? ev[it][2] : 0.f, g = in ? gv[it] : 0.f;
+            const int l = (i / G::span) * G::pitch + i % G::span;
+            iv[l] = cell_interval_rgb(e0, e1, e2, g, 0.5f);
+            iv[G::span * G::pitch + l] = cell_interval_rgb(e0, e1, e2, g, kH2);
+            iv[2 * G::span * G::pitch + l] = cell_interval_rgb(e0, e1, e2, g, kQ5);
         }
-        const int l = lr * G::pitch + lc;
-        iv[l] = cell_interval_rgb(e0, e1, e2, g, 0.5f);
-        iv[G::span * G::pitch + l] = cell_interval_rgb(e0, e1, e2, g, kH2);
-        iv[2 * G::span * G::pitch + l] = cell_interval_rgb(e0, e1, e2, g, kQ5);
     }
     __syncthreads();
     for (int g = 0; g < a.nq; ++g) {
