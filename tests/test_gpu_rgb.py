@@ -122,6 +122,34 @@ def test_rgb_backward_benchmark_scene(ctx):
     assert_grad_close(gs, rs, "rgb 1024 d sigma")
 
 
+def test_rgb_largest_grid_equals_one_channel_calls(ctx):
+    """At 4096x4096, the largest grid, where the element offsets into the
+    channel planes and the interval levels are largest: each channel's fluence
+    and d emission bitwise those of the one-channel calls, d sigma within the
+    gradient tolerance of the sum of the three one-channel d sigma."""
+    S = 4096
+    log("rgb forward and backward S=4096 vs one-channel calls")
+    g = torch.Generator(device="cuda").manual_seed(S)
+    sig = torch.rand((S, S), device="cuda", generator=g) * 0.5
+    eps = torch.rand((3, S, S), device="cuda", generator=g) * (
+        torch.rand((3, S, S), device="cuda", generator=g) < 0.05)
+    dF = torch.randn((3, S, S), device="cuda", generator=g)
+    F = ctx.hrc_forward_rgb(eps, sig)
+    for c in range(3):
+        assert torch.equal(F[c], ctx.hrc_forward(eps[c].contiguous(), sig)), c
+    del F
+    ge, gs = ctx.hrc_backward_rgb(eps, sig, dF)
+    gs_sum = torch.zeros_like(sig)
+    for c in range(3):
+        pe, ps = ctx.hrc_backward(eps[c].contiguous(), sig, dF[c].contiguous())
+        assert torch.equal(ge[c], pe), c
+        gs_sum += ps
+    torch.cuda.synchronize()
+    assert_grad_close(gs.cpu().numpy(), gs_sum.cpu().numpy(), "rgb d sigma S=4096")
+    del ge, gs, gs_sum
+    ctx.release_workspaces()
+
+
 @pytest.mark.parametrize("S,flags", [(8, 0), (64, 0x2), (256, 0), (1024, 0)])
 def test_rgb_kept_forward_and_reused_backward(ctx, S, flags):
     """The reserve-space pair for RGB: the kept forward's fluence and the
